@@ -1,0 +1,216 @@
+"""Definitional CPU oracle (test infrastructure).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The GPU library does not use it and shares no code with
+it. The arithmetic lives in ``oracle.c`` (plain C, built with gcc); this module
+only marshals numpy arrays.
+
+Functions (each follows a definition of arXiv 2409.00613):
+  expand      double-strand string list P0, rc(P0), P1, rc(P1), ... (Sec. 2.5)
+  bwt         BWT by sorting every suffix of the sentinel-terminated list (Sec. 2.1)
+  verify      inverse-BWT check of a candidate BWT (LF relation, Sec. 2.1)
+  count       SA interval [lo, hi) by scanning every suffix (Sec. 2.3)
+  Text.interval / Text.smem
+              SA interval by binary search; SMEMs by their definition (Sec. 2.6)
+  insertion_ranks
+              l(x) of each new suffix: number of existing-index suffixes below
+              it (the quantity Algorithm 1 accumulates)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-std=c99",
+                               "-Wall", "-Wextra", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_expand.argtypes = [_u8p, _i64p, ctypes.c_int64, ctypes.c_int, _u8p, _i64p]
+    lib.orc_expand.restype = ctypes.c_int
+    lib.orc_bwt.argtypes = [_u8p, _i64p, ctypes.c_int64, ctypes.c_int, _u8p, _i64p]
+    lib.orc_bwt.restype = ctypes.c_int
+    lib.orc_verify.argtypes = [_u8p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64, ctypes.c_int]
+    lib.orc_verify.restype = ctypes.c_int64
+    lib.orc_count.argtypes = [_u8p, _i64p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64,
+                              ctypes.c_int, _i64p, _i64p]
+    lib.orc_count.restype = ctypes.c_int
+    lib.orc_text_new.argtypes = [_u8p, _i64p, ctypes.c_int64]
+    lib.orc_text_new.restype = ctypes.c_void_p
+    lib.orc_text_free.argtypes = [ctypes.c_void_p]
+    lib.orc_text_free.restype = None
+    lib.orc_sa_interval.argtypes = [ctypes.c_void_p, _i64p, _u8p, ctypes.c_int64, _i64p, _i64p]
+    lib.orc_sa_interval.restype = ctypes.c_int
+    lib.orc_smem.argtypes = [ctypes.c_void_p, _i64p, _u8p, ctypes.c_int64, ctypes.c_int64,
+                             ctypes.c_int64, _i64p, ctypes.c_int64]
+    lib.orc_smem.restype = ctypes.c_int64
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def _threads(nthreads):
+    return int(nthreads) if nthreads else max(1, min(os.cpu_count() or 1, 16))
+
+
+def expand(data: np.ndarray, lens: np.ndarray, both: bool = True):
+    """Encode ASCII strings ($=0 A=1 C=2 G=3 T=4 N=5) and, when ``both``, follow
+    each string by its reverse complement. Returns (codes, lens)."""
+    lib = _load()
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    lens = np.ascontiguousarray(lens, dtype=np.int64)
+    k = 2 if both else 1
+    codes = np.empty(max(1, k * int(lens.sum())), dtype=np.uint8)
+    out_lens = np.empty(max(1, k * lens.shape[0]), dtype=np.int64)
+    rc = lib.orc_expand(_p(data, _u8p), _p(lens, _i64p), lens.shape[0], int(both),
+                        _p(codes, _u8p), _p(out_lens, _i64p))
+    if rc == -1:
+        raise ValueError("byte outside ACGTNacgtn")
+    if rc == -2:
+        raise ValueError("empty string")
+    return codes[:k * int(lens.sum())], out_lens[:k * lens.shape[0]]
+
+
+def encode(data: np.ndarray, lens: np.ndarray):
+    """Encode strings without reverse complements (used for queries)."""
+    return expand(data, lens, both=False)
+
+
+def bwt(codes: np.ndarray, lens: np.ndarray, nthreads: int | None = None, want_sa: bool = False):
+    """BWT (codes 0..5) of the ordered list; optionally also its suffix array."""
+    lib = _load()
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    lens = np.ascontiguousarray(lens, dtype=np.int64)
+    n = int(lens.sum()) + lens.shape[0]
+    B = np.empty(max(n, 1), dtype=np.uint8)
+    S = np.empty(max(n, 1), dtype=np.int64) if want_sa else None
+    cod = codes if codes.size else np.zeros(1, np.uint8)
+    rc = lib.orc_bwt(_p(cod, _u8p), _p(lens, _i64p), lens.shape[0], _threads(nthreads),
+                     _p(B, _u8p), _p(S, _i64p) if want_sa else None)
+    if rc != 0:
+        raise MemoryError("oracle bwt: allocation failed")
+    if want_sa:
+        return B[:n], S[:n]
+    return B[:n]
+
+
+def verify(B: np.ndarray, codes: np.ndarray, lens: np.ndarray, nthreads: int | None = None) -> int:
+    """0 if B is the BWT of the list; otherwise a nonzero diagnostic
+    (-1 wrong length, -2 wrong symbol counts, j+1 string j not recovered)."""
+    lib = _load()
+    B = np.ascontiguousarray(B, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    lens = np.ascontiguousarray(lens, dtype=np.int64)
+    cod = codes if codes.size else np.zeros(1, np.uint8)
+    b = B if B.size else np.zeros(1, np.uint8)
+    return int(lib.orc_verify(_p(b, _u8p), B.shape[0], _p(cod, _u8p), _p(lens, _i64p),
+                              lens.shape[0], _threads(nthreads)))
+
+
+def count(codes: np.ndarray, lens: np.ndarray, qcodes: np.ndarray, qlens: np.ndarray,
+          nthreads: int | None = None):
+    """Brute-force SA intervals (lo, hi) of each query."""
+    lib = _load()
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    lens = np.ascontiguousarray(lens, dtype=np.int64)
+    qcodes = np.ascontiguousarray(qcodes, dtype=np.uint8)
+    qlens = np.ascontiguousarray(qlens, dtype=np.int64)
+    nq = qlens.shape[0]
+    lo = np.zeros(max(nq, 1), dtype=np.int64)
+    hi = np.zeros(max(nq, 1), dtype=np.int64)
+    q = qcodes if qcodes.size else np.zeros(1, np.uint8)
+    cod = codes if codes.size else np.zeros(1, np.uint8)
+    rc = lib.orc_count(_p(cod, _u8p), _p(lens, _i64p), lens.shape[0], _p(q, _u8p),
+                       _p(qlens, _i64p), nq, _threads(nthreads), _p(lo, _i64p), _p(hi, _i64p))
+    if rc != 0:
+        raise MemoryError("oracle count: allocation failed")
+    return lo[:nq], hi[:nq]
+
+
+class Text:
+    """The concatenated text of a list plus its suffix array (by the oracle's
+    own sort), for interval and SMEM queries."""
+
+    def __init__(self, codes: np.ndarray, lens: np.ndarray, nthreads: int | None = None):
+        lib = _load()
+        self.codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        self.lens = np.ascontiguousarray(lens, dtype=np.int64)
+        self.B, self.S = bwt(self.codes, self.lens, nthreads, want_sa=True)
+        self.n = int(self.S.shape[0])
+        cod = self.codes if self.codes.size else np.zeros(1, np.uint8)
+        self._keep = cod
+        self._h = lib.orc_text_new(_p(cod, _u8p), _p(self.lens, _i64p), self.lens.shape[0])
+        if not self._h:
+            raise MemoryError("oracle text: allocation failed")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_text_free(h)
+            self._h = None
+
+    def interval(self, P: np.ndarray):
+        P = np.ascontiguousarray(P, dtype=np.uint8)
+        lo = np.zeros(1, np.int64)
+        hi = np.zeros(1, np.int64)
+        pp = P if P.size else np.zeros(1, np.uint8)
+        _lib.orc_sa_interval(self._h, _p(self.S, _i64p), _p(pp, _u8p), P.shape[0],
+                             _p(lo, _i64p), _p(hi, _i64p))
+        return int(lo[0]), int(hi[0])
+
+    def smem(self, P: np.ndarray, min_len: int, min_occ: int = 1) -> np.ndarray:
+        """SMEMs as an (k, 5) int64 array: start, end, occ, lo, lo_rc."""
+        P = np.ascontiguousarray(P, dtype=np.uint8)
+        pp = P if P.size else np.zeros(1, np.uint8)
+        cap = max(16, P.shape[0] // 8)
+        while True:
+            out = np.zeros((cap, 5), dtype=np.int64)
+            k = _lib.orc_smem(self._h, _p(self.S, _i64p), _p(pp, _u8p), P.shape[0],
+                              int(min_len), int(min_occ), _p(out, _i64p), cap)
+            if k < 0:
+                raise MemoryError("oracle smem: allocation failed")
+            if k <= cap:
+                return out[:k]
+            cap = int(k)
+
+
+def insertion_ranks(S: np.ndarray, lens: np.ndarray, m1: int) -> np.ndarray:
+    """From the suffix array S of the list (existing strings 0..m1-1 followed
+    by new strings), return l(x) for every position x of the new strings'
+    part of the text (sentinels included): the number of suffixes of the
+    existing strings that are smaller than x."""
+    lens = np.asarray(lens, dtype=np.int64)
+    n1 = int(lens[:m1].sum()) + m1
+    n = int(S.shape[0])
+    is_new = S >= n1
+    rows_old_before = np.cumsum(~is_new) - (~is_new)   # old suffixes strictly before each row
+    l = np.empty(n - n1, dtype=np.int64)
+    l[S[is_new] - n1] = rows_old_before[is_new]
+    return l

@@ -1,0 +1,546 @@
+/*
+ * Definitional CPU oracle for multi-string BWT construction, SA-interval
+ * counting and SMEM finding (Li, "BWT construction and search at the terabase
+ * scale", arXiv 2409.00613).
+ *
+ * THIS IS TEST INFRASTRUCTURE. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg call it. The GPU library never links, loads or
+ * calls anything here, and nothing here shares code with the GPU library.
+ *
+ * Every routine computes the plain definition, slowly:
+ *   - orc_expand       double-strand string list (Sec. 2.5, the DS concatenation)
+ *   - orc_bwt          suffix array by comparison sort of every suffix of the
+ *                      sentinel-terminated concatenation, then B[i] = T[S(i)-1]
+ *                      (Sec. 2.1; the m+5 integer alphabet of Sec. 2.2)
+ *   - orc_verify       inverse BWT: LF-walk every string back out of a candidate
+ *                      BWT (the LF relation of Sec. 2.1 / Table 1)
+ *   - orc_count        SA interval [lo, hi) of a pattern by scanning every
+ *                      suffix (Sec. 2.3 definition of lo/occ/hi)
+ *   - orc_sa_interval  the same interval by binary search over a sorted SA
+ *   - orc_smem         SMEMs of length >= min_len occurring >= min_occ times,
+ *                      from the definition of Sec. 2.6 (see the function)
+ *
+ * Symbol codes: $=0 A=1 C=2 G=3 T=4 N=5 (the order $ < A < C < G < T < N of
+ * Sec. 2.2). All positions and counts are int64.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_THREADS 256
+
+/* ------------------------------------------------------------------------ */
+/* Alphabet                                                                   */
+/* ------------------------------------------------------------------------ */
+
+static int orc_code_of(uint8_t ch)
+{
+    switch (ch) {
+    case 'A': case 'a': return 1;
+    case 'C': case 'c': return 2;
+    case 'G': case 'g': return 3;
+    case 'T': case 't': return 4;
+    case 'N': case 'n': return 5;
+    default: return -1;
+    }
+}
+
+/* Watson-Crick complement on codes (Sec. 2.5): $->$, A<->T, C<->G, N->N. */
+static uint8_t orc_comp(uint8_t c)
+{
+    static const uint8_t tab[6] = {0, 4, 3, 2, 1, 5};
+    return tab[c];
+}
+
+/*
+ * Encode ASCII strings and expand them to the ordered list
+ * P0, rc(P0), P1, rc(P1), ... when both != 0 (Sec. 2.5), or P0, P1, ...
+ * otherwise. codes receives the concatenated strands without sentinels,
+ * lens_out one length per strand. Returns 0, or -1 on a byte outside
+ * ACGTNacgtn, or -2 on a string of length 0.
+ */
+int orc_expand(const uint8_t *seq, const int64_t *lens, int64_t m_in, int both,
+               uint8_t *codes, int64_t *lens_out)
+{
+    int64_t in = 0, out = 0, s = 0;
+    for (int64_t j = 0; j < m_in; ++j) {
+        int64_t L = lens[j];
+        if (L <= 0) return -2;
+        for (int64_t t = 0; t < L; ++t) {
+            int c = orc_code_of(seq[in + t]);
+            if (c < 0) return -1;
+            codes[out + t] = (uint8_t)c;
+        }
+        lens_out[s++] = L;
+        if (both) {
+            for (int64_t t = 0; t < L; ++t)
+                codes[out + L + t] = orc_comp(codes[out + L - 1 - t]);
+            lens_out[s++] = L;
+            out += 2 * L;
+        } else {
+            out += L;
+        }
+        in += L;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The concatenated text T over the m+5 integer alphabet (Sec. 2.2)           */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * T = P_0 $_0 P_1 $_1 ... P_{m-1} $_{m-1} with $_0 < ... < $_{m-1} < A < C < G
+ * < T < N. Encoded as int32: sentinel $_j -> j, base code c (1..5) -> m-1+c.
+ * Two distinct suffixes always differ at or before the first sentinel either
+ * reaches, because sentinel values are unique.
+ */
+static int32_t *orc_make_text(const uint8_t *codes, const int64_t *lens, int64_t m,
+                              int64_t *n_out)
+{
+    int64_t n = 0;
+    for (int64_t j = 0; j < m; ++j) n += lens[j] + 1;
+    int32_t *T = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!T) return NULL;
+    int64_t p = 0, q = 0;
+    for (int64_t j = 0; j < m; ++j) {
+        for (int64_t t = 0; t < lens[j]; ++t) T[p++] = (int32_t)(m - 1 + codes[q++]);
+        T[p++] = (int32_t)j;
+    }
+    *n_out = n;
+    return T;
+}
+
+static int orc_cmp_suffix(const int32_t *T, int64_t a, int64_t b)
+{
+    if (a == b) return 0;
+    for (;;) {
+        int32_t x = T[a], y = T[b];
+        if (x != y) return x < y ? -1 : 1;
+        ++a;
+        ++b;
+    }
+}
+
+/* top-down merge sort of suffix start positions */
+static void orc_msort(const int32_t *T, int64_t *a, int64_t *tmp, int64_t n)
+{
+    if (n < 2) return;
+    if (n <= 16) {
+        for (int64_t i = 1; i < n; ++i) {
+            int64_t v = a[i], j = i;
+            while (j > 0 && orc_cmp_suffix(T, a[j - 1], v) > 0) { a[j] = a[j - 1]; --j; }
+            a[j] = v;
+        }
+        return;
+    }
+    int64_t h = n / 2;
+    orc_msort(T, a, tmp, h);
+    orc_msort(T, a + h, tmp + h, n - h);
+    int64_t i = 0, j = h, k = 0;
+    while (i < h && j < n) tmp[k++] = (orc_cmp_suffix(T, a[j], a[i]) < 0) ? a[j++] : a[i++];
+    while (i < h) tmp[k++] = a[i++];
+    while (j < n) tmp[k++] = a[j++];
+    memcpy(a, tmp, (size_t)n * sizeof(int64_t));
+}
+
+typedef struct {
+    const int32_t *T;
+    int64_t *a, *tmp;
+    int64_t n;
+} orc_sort_job;
+
+static void *orc_sort_worker(void *p)
+{
+    orc_sort_job *jb = (orc_sort_job *)p;
+    orc_msort(jb->T, jb->a, jb->tmp, jb->n);
+    return NULL;
+}
+
+typedef struct {
+    const int32_t *T;
+    const int64_t *src;
+    int64_t *dst;
+    int64_t a0, a1, b1; /* merge src[a0,a1) with src[a1,b1) into dst[a0,b1) */
+} orc_merge_job;
+
+static void *orc_merge_worker(void *p)
+{
+    orc_merge_job *jb = (orc_merge_job *)p;
+    int64_t i = jb->a0, j = jb->a1, k = jb->a0;
+    while (i < jb->a1 && j < jb->b1)
+        jb->dst[k++] = (orc_cmp_suffix(jb->T, jb->src[j], jb->src[i]) < 0) ? jb->src[j++] : jb->src[i++];
+    while (i < jb->a1) jb->dst[k++] = jb->src[i++];
+    while (j < jb->b1) jb->dst[k++] = jb->src[j++];
+    return NULL;
+}
+
+/* Sort every suffix start of T (the suffix array S of Sec. 2.1). */
+static int orc_suffix_sort(const int32_t *T, int64_t n, int nthreads, int64_t *S)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > ORC_MAX_THREADS) nthreads = ORC_MAX_THREADS;
+    if (n < (int64_t)nthreads * 1024) nthreads = 1;
+    int64_t *tmp = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!tmp) return -1;
+    for (int64_t i = 0; i < n; ++i) S[i] = i;
+    int64_t bounds[ORC_MAX_THREADS + 1];
+    for (int t = 0; t <= nthreads; ++t) bounds[t] = n * t / nthreads;
+    pthread_t th[ORC_MAX_THREADS];
+    orc_sort_job jobs[ORC_MAX_THREADS];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].T = T;
+        jobs[t].a = S + bounds[t];
+        jobs[t].tmp = tmp + bounds[t];
+        jobs[t].n = bounds[t + 1] - bounds[t];
+        pthread_create(&th[t], NULL, orc_sort_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    /* pairwise merge rounds of the sorted runs */
+    int runs = nthreads;
+    int64_t *src = S, *dst = tmp;
+    while (runs > 1) {
+        orc_merge_job mj[ORC_MAX_THREADS];
+        int nj = 0, nr = 0;
+        int64_t nb[ORC_MAX_THREADS + 1];
+        for (int r = 0; r < runs; r += 2) {
+            if (r + 1 < runs) {
+                mj[nj].T = T; mj[nj].src = src; mj[nj].dst = dst;
+                mj[nj].a0 = bounds[r]; mj[nj].a1 = bounds[r + 1]; mj[nj].b1 = bounds[r + 2];
+                pthread_create(&th[nj], NULL, orc_merge_worker, &mj[nj]);
+                ++nj;
+            } else {
+                memcpy(dst + bounds[r], src + bounds[r],
+                       (size_t)(bounds[r + 1] - bounds[r]) * sizeof(int64_t));
+            }
+            nb[nr++] = bounds[r];
+        }
+        for (int t = 0; t < nj; ++t) pthread_join(th[t], NULL);
+        nb[nr] = n;
+        for (int r = 0; r <= nr; ++r) bounds[r] = nb[r];
+        runs = nr;
+        int64_t *sw = src; src = dst; dst = sw;
+    }
+    if (src != S) memcpy(S, src, (size_t)n * sizeof(int64_t));
+    free(tmp);
+    return 0;
+}
+
+/*
+ * BWT of the ordered list (Sec. 2.1): sort all n = sum(L_j + 1) suffixes of T
+ * and output B[i] = T[S(i) - 1] with T[-1] = T[n-1]; every sentinel prints as
+ * code 0. If S_out is not NULL it receives the suffix array (positions in T).
+ * Returns 0, or -1 on allocation failure.
+ */
+int orc_bwt(const uint8_t *codes, const int64_t *lens, int64_t m, int nthreads,
+            uint8_t *B, int64_t *S_out)
+{
+    int64_t n = 0;
+    int32_t *T = orc_make_text(codes, lens, m, &n);
+    if (!T) return -1;
+    int64_t *S = S_out ? S_out : (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!S) { free(T); return -1; }
+    if (orc_suffix_sort(T, n, nthreads, S) != 0) {
+        if (!S_out) free(S);
+        free(T);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t p = S[i] == 0 ? n - 1 : S[i] - 1;
+        int32_t v = T[p];
+        B[i] = (v < m) ? 0 : (uint8_t)(v - (m - 1));
+    }
+    if (!S_out) free(S);
+    free(T);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inverse-BWT verifier                                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const uint8_t *B;
+    const int64_t *occ; /* counts of each code before every 64th position */
+    const int64_t *C;
+    const uint8_t *codes;
+    const int64_t *lens, *start; /* start offset of each string in codes */
+    int64_t m;
+    int64_t j0, j1;
+    int64_t bad; /* first failing string + 1, or 0 */
+} orc_walk_job;
+
+static int64_t orc_rank(const uint8_t *B, const int64_t *occ, int c, int64_t k)
+{
+    int64_t b = k >> 6, r = occ[b * 6 + c];
+    for (int64_t i = b << 6; i < k; ++i) r += (B[i] == c);
+    return r;
+}
+
+static void *orc_walk_worker(void *p)
+{
+    orc_walk_job *jb = (orc_walk_job *)p;
+    jb->bad = 0;
+    for (int64_t j = jb->j0; j < jb->j1; ++j) {
+        /* row j holds the sentinel-only suffix of string j; its BWT symbol is
+         * the string's last base, and LF walks the string right to left */
+        int64_t k = j;
+        const uint8_t *Q = jb->codes + jb->start[j];
+        for (int64_t t = jb->lens[j] - 1; t >= 0; --t) {
+            int c = jb->B[k];
+            if (c != Q[t]) { jb->bad = j + 1; return NULL; }
+            k = jb->C[c] + orc_rank(jb->B, jb->occ, c, k);
+        }
+        if (jb->B[k] != 0) { jb->bad = j + 1; return NULL; }
+    }
+    return NULL;
+}
+
+/*
+ * Check that candidate codes B (length n) are the BWT of the list (codes,
+ * lens, m). Returns 0 when every string is recovered by LF walks from rows
+ * 0..m-1 and the symbol counts match; -1 when n is wrong; -2 when symbol
+ * counts differ; -3 on allocation failure; j+1 when string j is not recovered.
+ */
+int64_t orc_verify(const uint8_t *B, int64_t n, const uint8_t *codes, const int64_t *lens,
+                   int64_t m, int nthreads)
+{
+    int64_t want = 0;
+    int64_t cnt[6] = {0, 0, 0, 0, 0, 0}, got[6] = {0, 0, 0, 0, 0, 0};
+    int64_t q = 0;
+    for (int64_t j = 0; j < m; ++j) {
+        want += lens[j] + 1;
+        for (int64_t t = 0; t < lens[j]; ++t) cnt[codes[q++]]++;
+    }
+    cnt[0] = m;
+    if (want != n) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (B[i] > 5) return -2;
+        got[B[i]]++;
+    }
+    for (int c = 0; c < 6; ++c)
+        if (got[c] != cnt[c]) return -2;
+    int64_t C[6];
+    C[0] = 0;
+    for (int c = 1; c < 6; ++c) C[c] = C[c - 1] + cnt[c - 1];
+    int64_t nb = (n >> 6) + 1;
+    int64_t *occ = (int64_t *)malloc((size_t)nb * 6 * sizeof(int64_t));
+    int64_t *start = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!occ || !start) { free(occ); free(start); return -3; }
+    int64_t run[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        if ((i & 63) == 0) memcpy(occ + (i >> 6) * 6, run, sizeof(run));
+        run[B[i]]++;
+    }
+    if ((n & 63) == 0) memcpy(occ + (n >> 6) * 6, run, sizeof(run));
+    q = 0;
+    for (int64_t j = 0; j < m; ++j) { start[j] = q; q += lens[j]; }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > ORC_MAX_THREADS) nthreads = ORC_MAX_THREADS;
+    pthread_t th[ORC_MAX_THREADS];
+    orc_walk_job jobs[ORC_MAX_THREADS];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].B = B; jobs[t].occ = occ; jobs[t].C = C; jobs[t].codes = codes;
+        jobs[t].lens = lens; jobs[t].start = start; jobs[t].m = m;
+        jobs[t].j0 = m * t / nthreads; jobs[t].j1 = m * (t + 1) / nthreads;
+        pthread_create(&th[t], NULL, orc_walk_worker, &jobs[t]);
+    }
+    int64_t bad = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        pthread_join(th[t], NULL);
+        if (jobs[t].bad && (!bad || jobs[t].bad < bad)) bad = jobs[t].bad;
+    }
+    free(occ);
+    free(start);
+    return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SA intervals                                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Compare the suffix of T starting at g with the pattern P (codes 1..5):
+ * -1 if the suffix is smaller than P and P is not its prefix, 0 if P is a
+ * prefix of the suffix, +1 if the suffix is larger. A sentinel is smaller
+ * than every base.
+ */
+static int orc_cmp_pattern(const int32_t *T, int64_t m, int64_t g, const uint8_t *P, int64_t len)
+{
+    for (int64_t d = 0; d < len; ++d) {
+        int32_t v = T[g + d];
+        if (v < m) return -1;
+        int c = (int)(v - (m - 1));
+        if (c != P[d]) return c < P[d] ? -1 : 1;
+    }
+    return 0;
+}
+
+typedef struct {
+    const int32_t *T;
+    int64_t n, m;
+    const uint8_t *q;
+    const int64_t *qoff, *qlens;
+    int64_t i0, i1;
+    int64_t *lo, *hi;
+} orc_count_job;
+
+static void *orc_count_worker(void *p)
+{
+    orc_count_job *jb = (orc_count_job *)p;
+    for (int64_t i = jb->i0; i < jb->i1; ++i) {
+        const uint8_t *P = jb->q + jb->qoff[i];
+        int64_t len = jb->qlens[i], lo = 0, occ = 0;
+        for (int64_t g = 0; g < jb->n; ++g) {
+            int r = orc_cmp_pattern(jb->T, jb->m, g, P, len);
+            if (r < 0) ++lo;
+            else if (r == 0) ++occ;
+        }
+        jb->lo[i] = lo;
+        jb->hi[i] = lo + occ;
+    }
+    return NULL;
+}
+
+/*
+ * SA interval of each query by brute force (Sec. 2.3): lo = number of
+ * suffixes smaller than P, occ = number of suffixes with prefix P, hi = lo +
+ * occ. Query codes are 1..5 concatenated; an empty query gives [0, n).
+ */
+int orc_count(const uint8_t *codes, const int64_t *lens, int64_t m, const uint8_t *qcodes,
+              const int64_t *qlens, int64_t nq, int nthreads, int64_t *lo, int64_t *hi)
+{
+    int64_t n = 0;
+    int32_t *T = orc_make_text(codes, lens, m, &n);
+    int64_t *qoff = (int64_t *)malloc((size_t)(nq > 0 ? nq : 1) * sizeof(int64_t));
+    if (!T || !qoff) { free(T); free(qoff); return -1; }
+    int64_t s = 0;
+    for (int64_t i = 0; i < nq; ++i) { qoff[i] = s; s += qlens[i]; }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > ORC_MAX_THREADS) nthreads = ORC_MAX_THREADS;
+    pthread_t th[ORC_MAX_THREADS];
+    orc_count_job jobs[ORC_MAX_THREADS];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].T = T; jobs[t].n = n; jobs[t].m = m; jobs[t].q = qcodes;
+        jobs[t].qoff = qoff; jobs[t].qlens = qlens;
+        jobs[t].i0 = nq * t / nthreads; jobs[t].i1 = nq * (t + 1) / nthreads;
+        jobs[t].lo = lo; jobs[t].hi = hi;
+        pthread_create(&th[t], NULL, orc_count_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    free(qoff);
+    free(T);
+    return 0;
+}
+
+/* [lo, hi) of P by binary search over the sorted suffix array S of T. */
+static void orc_interval(const int32_t *T, int64_t n, int64_t m, const int64_t *S,
+                         const uint8_t *P, int64_t len, int64_t *lo, int64_t *hi)
+{
+    int64_t a = 0, b = n;
+    while (a < b) { /* first row whose suffix is not below P */
+        int64_t mid = a + (b - a) / 2;
+        if (orc_cmp_pattern(T, m, S[mid], P, len) < 0) a = mid + 1; else b = mid;
+    }
+    *lo = a;
+    b = n;
+    while (a < b) { /* first row whose suffix is above P */
+        int64_t mid = a + (b - a) / 2;
+        if (orc_cmp_pattern(T, m, S[mid], P, len) <= 0) a = mid + 1; else b = mid;
+    }
+    *hi = a;
+}
+
+typedef struct {
+    int32_t *T;
+    int64_t n, m;
+} orc_text;
+
+/* Build the integer text once so that interval and SMEM calls can reuse it. */
+void *orc_text_new(const uint8_t *codes, const int64_t *lens, int64_t m)
+{
+    orc_text *x = (orc_text *)malloc(sizeof(orc_text));
+    if (!x) return NULL;
+    x->T = orc_make_text(codes, lens, m, &x->n);
+    x->m = m;
+    if (!x->T) { free(x); return NULL; }
+    return x;
+}
+
+void orc_text_free(void *h)
+{
+    orc_text *x = (orc_text *)h;
+    if (!x) return;
+    free(x->T);
+    free(x);
+}
+
+int orc_sa_interval(void *h, const int64_t *S, const uint8_t *P, int64_t len, int64_t *lo,
+                    int64_t *hi)
+{
+    orc_text *x = (orc_text *)h;
+    orc_interval(x->T, x->n, x->m, S, P, len, lo, hi);
+    return 0;
+}
+
+/*
+ * SMEMs of P no shorter than min_len that occur at least min_occ times
+ * (Sec. 2.6, with the min-occurrence generalisation cited there).
+ *
+ * Definition used: let e(i) be the largest e <= |P| with occ(P[i,e)) >=
+ * min_occ (e(i) = i when even P[i] is too rare). occ only falls as a
+ * substring grows, so e(.) is non-decreasing, and the exact matches that no
+ * other match on P contains are exactly [i, e(i)) with i = 0 or e(i) >
+ * e(i-1), whenever that interval is non-empty. The ones of length >= min_len
+ * are reported, in increasing i, as five int64 each: start, end,
+ * occ(P[start,end)), lo(P[start,end)), lo(rc(P[start,end))).
+ *
+ * S is the suffix array of the text (from orc_bwt). Returns the number of
+ * SMEMs found; only the first cap are written.
+ */
+int64_t orc_smem(void *h, const int64_t *S, const uint8_t *P, int64_t len, int64_t min_len,
+                 int64_t min_occ, int64_t *out, int64_t cap)
+{
+    orc_text *x = (orc_text *)h;
+    int64_t found = 0, eprev = -1;
+    uint8_t *rc = (uint8_t *)malloc((size_t)(len > 0 ? len : 1));
+    if (!rc) return -1;
+    for (int64_t i = 0; i < len; ++i) {
+        int64_t e = eprev > i ? eprev : i;
+        int64_t lo, hi;
+        /* e(i) >= e(i-1): P[i, e(i-1)) is inside P[i-1, e(i-1)) */
+        if (e > i) {
+            orc_interval(x->T, x->n, x->m, S, P + i, e - i, &lo, &hi);
+        } else {
+            lo = 0;
+            hi = x->n;
+        }
+        if (hi - lo < min_occ) {
+            /* only possible when e == i and the whole text is too small */
+            eprev = e;
+            continue;
+        }
+        while (e < len) {
+            int64_t lo2, hi2;
+            orc_interval(x->T, x->n, x->m, S, P + i, e + 1 - i, &lo2, &hi2);
+            if (hi2 - lo2 < min_occ) break;
+            lo = lo2;
+            hi = hi2;
+            ++e;
+        }
+        if ((i == 0 || e > eprev) && e - i >= min_len && e > i) {
+            if (found < cap) {
+                int64_t L = e - i, klo, khi;
+                for (int64_t t = 0; t < L; ++t) rc[t] = orc_comp(P[e - 1 - t]);
+                orc_interval(x->T, x->n, x->m, S, rc, L, &klo, &khi);
+                int64_t *o = out + found * 5;
+                o[0] = i; o[1] = e; o[2] = hi - lo; o[3] = lo; o[4] = klo;
+            }
+            ++found;
+        }
+        eprev = e;
+    }
+    free(rc);
+    return found;
+}

@@ -1,0 +1,403 @@
+"""Pins for the CPU oracle: checks it against hand-worked values, the paper's
+worked example, textbook routines, invariants and brute force on tiny inputs.
+
+None of these tests needs a GPU. The brute-force helpers here are written
+independently of ``oracle/oracle.c`` (pure Python over explicit tuples), so a
+mistake in the oracle's sentinel order, symbol order, complement, interval
+bounds or SMEM filter fails at least one of them.
+"""
+import itertools
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+SYM = "$ACGTN"
+CODE = {c: i for i, c in enumerate(SYM)}
+COMP = {"A": "T", "C": "G", "G": "C", "T": "A", "N": "N"}
+
+
+def _rc(s):
+    return "".join(COMP[c] for c in reversed(s))
+
+
+def _codes(strands):
+    """Concatenate already-expanded strands into (codes, lens) directly."""
+    data = np.array([CODE[c] for s in strands for c in s], dtype=np.uint8)
+    lens = np.array([len(s) for s in strands], dtype=np.int64)
+    return data, lens
+
+
+def _bwt_str(B):
+    return "".join(SYM[int(c)] for c in B)
+
+
+# --- independent brute force (pure Python) --------------------------------
+
+def _suffixes(strands):
+    """Every suffix as a tuple of (kind, value): sentinel j -> (0, j), base c ->
+    (1, rank of c in ACGTN). Returns list of (tuple, string index, offset)."""
+    out = []
+    for j, s in enumerate(strands):
+        full = [(1, "ACGTN".index(c)) for c in s] + [(0, j)]
+        for t in range(len(s) + 1):
+            out.append((tuple(full[t:]), j, t))
+    return out
+
+
+def _brute_bwt(strands):
+    suf = sorted(_suffixes(strands))
+    m = len(strands)
+    res = []
+    for _, j, t in suf:
+        if t == 0:
+            res.append("$")          # preceded by the previous sentinel (T[-1] = T[n-1])
+        else:
+            res.append(strands[j][t - 1])
+    assert len(res) == sum(len(s) + 1 for s in strands) and res.count("$") == m
+    return "".join(res)
+
+
+def _rotation_bwt(s):
+    """Textbook Burrows-Wheeler transform of one string: sort every rotation of
+    s + '$' ('$' smallest) and take the last column."""
+    order = {c: i for i, c in enumerate("$ACGTN")}
+    t = s + "$"
+    rots = sorted((t[i:] + t[:i] for i in range(len(t))),
+                  key=lambda r: [order[c] for c in r])
+    return "".join(r[-1] for r in rots)
+
+
+def _lf_decode(B, m):
+    """Recover every string from a multi-string BWT by LF walks (Retrieve)."""
+    cnt = {c: B.count(c) for c in SYM}
+    C, acc = {}, 0
+    for c in SYM:
+        C[c] = acc
+        acc += cnt[c]
+    out = []
+    for j in range(m):
+        k, s = j, []
+        while B[k] != "$":
+            a = B[k]
+            s.append(a)
+            k = C[a] + B[:k].count(a)
+        out.append("".join(reversed(s)))
+    return out
+
+
+def _brute_interval(strands, P):
+    key = [(1, "ACGTN".index(c)) for c in P]
+    suf = sorted(x[0] for x in _suffixes(strands))
+    lo = sum(1 for s in suf if list(s[:len(key)]) < key and list(s[:len(key)]) != key)
+    occ = sum(1 for s in suf if list(s[:len(key)]) == key)
+    return lo, lo + occ
+
+
+def _brute_smem(strands, P, min_len):
+    """SMEMs from the MEM-containment definition (Sec. 2.6): enumerate every
+    maximal exact match (text offset, pattern offset, length) over all strands,
+    keep pattern intervals not contained in another MEM's interval."""
+    mems = set()
+    for s in strands:
+        for t in range(len(s)):
+            for p in range(len(P)):
+                if s[t] != P[p]:
+                    continue
+                if t > 0 and p > 0 and s[t - 1] == P[p - 1]:
+                    continue  # extendable to the left
+                L = 0
+                while t + L < len(s) and p + L < len(P) and s[t + L] == P[p + L]:
+                    L += 1
+                mems.add((p, p + L))
+    smems = [iv for iv in mems
+             if not any(o != iv and o[0] <= iv[0] and iv[1] <= o[1] for o in mems)]
+    smems = sorted(iv for iv in smems if iv[1] - iv[0] >= min_len)
+    res = []
+    for a, b in smems:
+        sub = P[a:b]
+        occ = sum(1 for s in strands for t in range(len(s) - len(sub) + 1) if s[t:t + len(sub)] == sub)
+        res.append((a, b, occ))
+    return res
+
+
+def _read_table(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append([x.strip() for x in line.split("|")])
+    return rows
+
+
+# --- expansion --------------------------------------------------------------
+
+def test_expand_order_and_complement():
+    data = np.frombuffer(b"ACGTNacg", dtype=np.uint8)
+    codes, lens = oracle.expand(data, np.array([5, 3]))
+    assert list(lens) == [5, 5, 3, 3]
+    got = _bwt_str(codes)
+    assert got == "ACGTN" + "NACGT" + "ACG" + "CGT"
+
+
+def test_expand_rejects_bad_bytes_and_empty():
+    with pytest.raises(ValueError):
+        oracle.expand(np.frombuffer(b"ACXT", dtype=np.uint8), np.array([4]))
+    with pytest.raises(ValueError):
+        oracle.expand(np.frombuffer(b"ACGT", dtype=np.uint8), np.array([0, 4]))
+
+
+# --- BWT --------------------------------------------------------------------
+
+def test_bwt_hand_worked():
+    for strands, want, _ in _read_table("bwt_hand.txt"):
+        codes, lens = _codes(strands.split(","))
+        B = oracle.bwt(codes, lens, nthreads=1)
+        assert _bwt_str(B) == want, strands
+
+
+def test_bwt_double_strand_hand_worked_from_expand():
+    codes, lens = oracle.expand(np.frombuffer(b"AC", dtype=np.uint8), np.array([2]))
+    assert _bwt_str(oracle.bwt(codes, lens)) == "CT$A$G"
+    codes, lens = oracle.expand(np.frombuffer(b"AN", dtype=np.uint8), np.array([2]))
+    assert _bwt_str(oracle.bwt(codes, lens)) == "NT$NA$"
+
+
+def test_bwt_single_string_is_textbook_rotation_sort():
+    rnd = random.Random(7)
+    for _ in range(300):
+        s = "".join(rnd.choice("ACGTN" if rnd.random() < 0.3 else "ACGT")
+                    for _ in range(rnd.randint(1, 40)))
+        codes, lens = _codes([s])
+        assert _bwt_str(oracle.bwt(codes, lens, nthreads=1)) == _rotation_bwt(s), s
+
+
+def test_bwt_exhaustive_tiny_lists():
+    """Every list of 1-2 strings of length 1-3 over ACGT (and a sample of
+    3-string lists with N) against the pure-Python suffix sort."""
+    words = ["".join(w) for L in (1, 2, 3) for w in itertools.product("ACGT", repeat=L)]
+    lists = [[w] for w in words] + [[a, b] for a in words for b in words]
+    rnd = random.Random(11)
+    for _ in range(1500):
+        lists.append(["".join(rnd.choice("ACGTN") for _ in range(rnd.randint(1, 3)))
+                      for _ in range(3)])
+    for strands in lists:
+        codes, lens = _codes(strands)
+        B = _bwt_str(oracle.bwt(codes, lens, nthreads=1))
+        assert B == _brute_bwt(strands), strands
+
+
+def test_bwt_random_lists_brute_and_lf_decode():
+    rnd = random.Random(3)
+    for _ in range(200):
+        raw = ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 12)))
+               for _ in range(rnd.randint(1, 5))]
+        strands = [x for s in raw for x in (s, _rc(s))]
+        codes, lens = _codes(strands)
+        B = _bwt_str(oracle.bwt(codes, lens, nthreads=2))
+        assert B == _brute_bwt(strands)
+        assert _lf_decode(B, len(strands)) == strands
+
+
+def test_bwt_parallel_sort_matches_serial():
+    rnd = random.Random(5)
+    strands = ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(50, 400))) for _ in range(40)]
+    strands += strands[:10]  # exact duplicates: ties broken only by sentinels
+    codes, lens = _codes(strands)
+    assert np.array_equal(oracle.bwt(codes, lens, nthreads=1), oracle.bwt(codes, lens, nthreads=7))
+
+
+def test_bwt_symbol_counts_and_sentinel_rows():
+    rnd = random.Random(9)
+    strands = ["".join(rnd.choice("ACGTN") for _ in range(rnd.randint(1, 30))) for _ in range(25)]
+    codes, lens = _codes(strands)
+    B = oracle.bwt(codes, lens)
+    assert int((B == 0).sum()) == len(strands)
+    for c in range(1, 6):
+        assert int((B == c).sum()) == int((codes == c).sum())
+    # row j < m holds the suffix $_j, so B[j] is the last symbol of string j
+    for j, s in enumerate(strands):
+        assert SYM[B[j]] == s[-1]
+
+
+# --- inverse-BWT verifier ---------------------------------------------------
+
+def test_verify_accepts_true_bwt_and_rejects_every_transposition():
+    rnd = random.Random(13)
+    for _ in range(60):
+        strands = ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 6)))
+                   for _ in range(rnd.randint(1, 4))]
+        codes, lens = _codes(strands)
+        B = oracle.bwt(codes, lens)
+        assert oracle.verify(B, codes, lens) == 0
+        n = B.shape[0]
+        for i in range(n):
+            for j in range(i + 1, n):
+                if B[i] != B[j]:
+                    X = B.copy()
+                    X[i], X[j] = X[j], X[i]
+                    assert oracle.verify(X, codes, lens) != 0, (strands, i, j)
+
+
+def test_verify_rejects_wrong_length_and_counts():
+    codes, lens = _codes(["ACGT", "GG"])
+    B = oracle.bwt(codes, lens)
+    assert oracle.verify(B[:-1], codes, lens) == -1
+    X = B.copy()
+    X[X != 0] = 1
+    assert oracle.verify(X, codes, lens) == -2
+
+
+# --- counts -----------------------------------------------------------------
+
+def test_count_hand_worked():
+    for strands, pat, lo, hi in _read_table("count_hand.txt"):
+        codes, lens = _codes(strands.split(","))
+        P = "" if pat == "-" else pat
+        q = np.array([CODE[c] for c in P], dtype=np.uint8)
+        glo, ghi = oracle.count(codes, lens, q, np.array([len(P)]))
+        assert (int(glo[0]), int(ghi[0])) == (int(lo), int(hi)), (strands, pat)
+
+
+def test_count_brute_force_and_strand_symmetry():
+    rnd = random.Random(17)
+    raw = ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(5, 25))) for _ in range(6)]
+    strands = [x for s in raw for x in (s, _rc(s))]
+    codes, lens = _codes(strands)
+    pats = [s[a:a + L] for s in raw for a in range(0, len(s) - 3, 3) for L in (1, 2, 4)]
+    pats += ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 5))) for _ in range(40)]
+    qc = np.array([CODE[c] for p in pats for c in p], dtype=np.uint8)
+    ql = np.array([len(p) for p in pats], dtype=np.int64)
+    lo, hi = oracle.count(codes, lens, qc, ql, nthreads=3)
+    text = oracle.Text(codes, lens)
+    for i, p in enumerate(pats):
+        assert (lo[i], hi[i]) == _brute_interval(strands, p), p
+        assert text.interval(np.array([CODE[c] for c in p], np.uint8)) == (lo[i], hi[i])
+    # occ(P) = occ(rc P) on a double-strand list (Sec. 2.5)
+    rcq = np.array([CODE[c] for p in pats for c in _rc(p)], dtype=np.uint8)
+    lo2, hi2 = oracle.count(codes, lens, rcq, ql)
+    assert np.array_equal(hi - lo, hi2 - lo2)
+
+
+# --- SMEMs ------------------------------------------------------------------
+
+def _smem_fixture():
+    d = {}
+    with open(os.path.join(GOLD, "smem_paper_example.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                k, *v = line.split()
+                d[k] = v
+    return d
+
+
+@pytest.mark.parametrize("both", [False, True])
+def test_smem_paper_example(both):
+    fx = _smem_fixture()
+    T, P = fx["text"][0], fx["pattern"][0]
+    a, b, toff = map(int, fx["smem"])
+    assert T[toff:toff + (b - a)] == P[a:b]
+    strands = [T, _rc(T)] if both else [T]
+    codes, lens = _codes(strands)
+    text = oracle.Text(codes, lens)
+    q = np.array([CODE[c] for c in P], np.uint8)
+    for min_len in (1, 2, 3, 4):
+        got = text.smem(q, min_len, 1)
+        assert [tuple(r[:2]) for r in got] == [(a, b)]
+        assert got[0][2] == 1
+    na, nb, _ = map(int, fx["not_smem"])
+    assert all(tuple(r[:2]) != (na, nb) for r in text.smem(q, 1, 1))
+    assert len(text.smem(q, 5, 1)) == 0
+
+
+def test_smem_brute_force_mem_containment():
+    rnd = random.Random(23)
+    for trial in range(120):
+        raw = ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(3, 14)))
+               for _ in range(rnd.randint(1, 3))]
+        strands = [x for s in raw for x in (s, _rc(s))]
+        codes, lens = _codes(strands)
+        text = oracle.Text(codes, lens)
+        src = rnd.choice(raw)
+        P = "".join(c if rnd.random() > 0.2 else rnd.choice("ACGT") for c in src)
+        P += "".join(rnd.choice("ACGT") for _ in range(rnd.randint(0, 4)))
+        q = np.array([CODE[c] for c in P], np.uint8)
+        for min_len in (1, 2, 3):
+            got = [tuple(int(x) for x in r[:3]) for r in text.smem(q, min_len, 1)]
+            assert got == _brute_smem(strands, P, min_len), (strands, P, min_len)
+
+
+def test_smem_intervals_and_bi_interval_symmetry():
+    rnd = random.Random(29)
+    raw = ["".join(rnd.choice("ACGT") for _ in range(60)) for _ in range(4)]
+    strands = [x for s in raw for x in (s, _rc(s))]
+    codes, lens = _codes(strands)
+    text = oracle.Text(codes, lens)
+    P = raw[1][5:40] + "T" + raw[2][10:50]
+    q = np.array([CODE[c] for c in P], np.uint8)
+    rows = text.smem(q, 5, 1)
+    assert len(rows) >= 2
+    for a, b, occ, k, krc in rows:
+        sub = P[a:b]
+        lo, hi = _brute_interval(strands, sub)
+        lo2, hi2 = _brute_interval(strands, _rc(sub))
+        # (k, k', s) is the bi-interval of P[a,b); swapping gives rc's (Sec. 2.5)
+        assert (k, occ, krc) == (lo, hi - lo, lo2) and hi2 - lo2 == occ
+
+
+def test_smem_min_occ():
+    """With min_occ > 1 each reported match occurs that often and cannot be
+    extended on either side without falling below it."""
+    rnd = random.Random(31)
+    raw = ["".join(rnd.choice("ACGT") for _ in range(40)) for _ in range(3)]
+    raw.append(raw[0][:25] + "".join(rnd.choice("ACGT") for _ in range(15)))
+    strands = [x for s in raw for x in (s, _rc(s))]
+    codes, lens = _codes(strands)
+    text = oracle.Text(codes, lens)
+    P = raw[0]
+    q = np.array([CODE[c] for c in P], np.uint8)
+    for smin in (1, 2, 3):
+        rows = text.smem(q, 1, smin)
+        for a, b, occ, _, _ in rows:
+            assert occ >= smin
+            if b < len(P):
+                lo, hi = _brute_interval(strands, P[a:b + 1])
+                assert hi - lo < smin
+            if a > 0:
+                lo, hi = _brute_interval(strands, P[a - 1:b])
+                assert hi - lo < smin
+
+
+# --- insertion ranks ----------------------------------------------------------
+
+def test_insertion_ranks_brute_force():
+    rnd = random.Random(37)
+    for _ in range(40):
+        old = [x for s in ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 8)))
+                           for _ in range(rnd.randint(1, 3))] for x in (s, _rc(s))]
+        new = [x for s in ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 8)))
+                           for _ in range(rnd.randint(1, 3))] for x in (s, _rc(s))]
+        codes, lens = _codes(old + new)
+        _, S = oracle.bwt(codes, lens, want_sa=True)
+        l = oracle.insertion_ranks(S, lens, len(old))
+        old_suf = [x[0] for x in _suffixes(old)]
+        allsuf = _suffixes(old + new)
+        k = 0
+        for j in range(len(old), len(old) + len(new)):
+            for t in range(len(new[j - len(old)]) + 1):
+                x = [s for s in allsuf if s[1] == j and s[2] == t][0][0]
+                # old sentinels are $0..$(m1-1) in both lists, so tuples compare directly
+                assert l[k] == sum(1 for y in old_suf if y < x)
+                k += 1
+        # a new sentinel suffix is above exactly the m1 old sentinels (Algorithm 1 starts l at m1)
+        off = 0
+        for s in new:
+            off += len(s)
+            assert l[off] == len(old)
+            off += 1
