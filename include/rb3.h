@@ -1,0 +1,174 @@
+/*
+ * rb3.h - C ABI of the MI355X (gfx950) multi-string BWT library.
+ *
+ * The library keeps a multi-string Burrows-Wheeler transform of DNA strings
+ * resident in device memory, merges new strings into it, and answers
+ * backward-search counts and SMEM queries on it. The operations follow
+ * H. Li, "BWT construction and search at the terabase scale" (arXiv
+ * 2409.00613):
+ *   - the BWT of an ordered string list with sentinels ordered by string
+ *     index (Sec. 2.1), stored with both strands by default (Sec. 2.5);
+ *   - merging new strings into an existing BWT (Sec. 2.2, Algorithm 1);
+ *   - SA-interval counting by backward search (Sec. 2.3);
+ *   - SMEM finding over SA bi-intervals (Sec. 2.5-2.6, Algorithms 3-4).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns int: RB3_OK (0) on success, a negative RB3_E*
+ *     code otherwise. rb3_strerror() gives a message; for RB3_EDEVICE the
+ *     message includes the HIP error of the failing call (thread-local).
+ *     Nothing throws across the ABI.
+ *   - Input strings are passed as ONE buffer of concatenated bytes plus a
+ *     host array of int64 lengths. Bytes are ACGTN in either case; any other
+ *     byte, and any string of length 0, gives RB3_EINVAL. The buffer lives in
+ *     host memory (mem = RB3_MEM_HOST) or in device memory of the index's
+ *     device (mem = RB3_MEM_DEVICE); the lengths are always host memory.
+ *   - Symbol codes, where codes cross the ABI: $=0 A=1 C=2 G=3 T=4 N=5, the
+ *     order $ < A < C < G < T < N of Sec. 2.2.
+ *   - All positions and counts are int64.
+ *   - The caller owns every buffer it passes; the library reads inputs and
+ *     writes outputs only during the call. The library owns rb3_index objects
+ *     until rb3_index_free().
+ *   - Calls are synchronous: they enqueue work on the index's stream and
+ *     return after it has completed.
+ *   - Read-only calls (count, smem, info, export, clone) on one index may run
+ *     concurrently from several host threads; rb3_merge needs exclusive
+ *     access to its index.
+ */
+#ifndef RB3_H
+#define RB3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RB3_OK = 0,
+    RB3_EINVAL = -1,   /* bad argument: NULL, bad byte, empty string, bad size */
+    RB3_ENOMEM = -2,   /* device or host allocation failed */
+    RB3_EDEVICE = -3,  /* a HIP runtime call or kernel failed */
+    RB3_ENOSPC = -4,   /* caller output buffer too small (sizes are reported) */
+    RB3_ELIMIT = -5    /* input beyond a documented size limit */
+};
+
+enum { RB3_MEM_HOST = 0, RB3_MEM_DEVICE = 1 };
+
+/* Device-resident index: the BWT as 3-bit symbols in 64-byte blocks of 128
+ * symbols with occurrence checkpoints, superblock counts and C[]. */
+typedef struct rb3_index rb3_index;
+
+/* Device allocator hooks. dev_alloc returns NULL on failure. */
+typedef void *(*rb3_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*rb3_free_fn)(void *ptr, void *ctx);
+
+typedef struct rb3_opts {
+    int32_t both_strands;  /* 1 (default): each input string P is followed by
+                              its reverse complement, giving the list P0, rc(P0),
+                              P1, rc(P1), ... of Sec. 2.5. 0: strings as given. */
+    int32_t device;        /* HIP device ordinal (default 0) */
+    void *stream;          /* hipStream_t for all work; NULL: a stream the
+                              library creates for this index */
+    rb3_alloc_fn dev_alloc; /* NULL: hipMalloc/hipFree */
+    rb3_free_fn dev_free;
+    void *alloc_ctx;
+    int64_t chunk_len;     /* LF-chain chunk length for merges; 0 = default */
+} rb3_opts;
+
+/* Fill *o with the defaults above. */
+void rb3_opts_init(rb3_opts *o);
+
+/*
+ * rb3_build: the BWT of the ordered list expand(strings) (Sec. 2.1; with
+ * both_strands, the double-strand list of Sec. 2.5). Equivalent to merging
+ * the strings into an empty index.
+ *   seq, lens, n_seqs, mem: the input strings (see conventions).
+ *   *out receives a new index on success and is untouched on error.
+ */
+int rb3_build(const rb3_opts *o, const uint8_t *seq, const int64_t *lens, int64_t n_seqs,
+              int32_t mem, rb3_index **out);
+
+/*
+ * rb3_merge: idx := BWT(list(idx) ++ expand(strings)) (Sec. 2.2, Algorithm 1).
+ * Every sentinel already in idx orders before every new sentinel, and new
+ * strings keep their input order. Per batch the number of new symbols
+ * (sum of lengths plus one sentinel per strand) must be below 2^32 - 2^20
+ * (RB3_ELIMIT otherwise). On error idx is unchanged.
+ */
+int rb3_merge(rb3_index *idx, const uint8_t *seq, const int64_t *lens, int64_t n_seqs,
+              int32_t mem);
+
+/*
+ * rb3_count: SA interval [lo, hi) of each query by backward search
+ * (Sec. 2.3): lo = number of suffixes smaller than the query, hi - lo =
+ * number of occurrences. Queries are NOT reverse complemented. An empty
+ * query gives [0, n). lo and hi are host arrays of n_q entries.
+ */
+int rb3_count(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q,
+              int32_t mem, int64_t *lo, int64_t *hi);
+
+/* One SMEM: query interval [start, end), its occurrence count occ, and its
+ * SA bi-interval starts k = lo(P[start,end)), krc = lo(rc(P[start,end)))
+ * (Sec. 2.5). */
+typedef struct rb3_smem_t {
+    int64_t start, end, occ, k, krc;
+    int32_t qid;
+    int32_t pad;
+} rb3_smem_t;
+
+/*
+ * rb3_smem: SMEMs of each query no shorter than min_len that occur at least
+ * min_occ times (Sec. 2.6, Algorithm 4 over the extensions of Algorithm 3).
+ * Results for query i are out[out_off[i] .. out_off[i+1]) in increasing
+ * start. out (host, out_cap entries) and out_off (host, n_q + 1 entries)
+ * are caller buffers. If out_cap is too small the call returns RB3_ENOSPC
+ * with out_off filled, so the caller can size a retry. min_len >= 1 and
+ * min_occ >= 1, else RB3_EINVAL. The index must hold both strands.
+ */
+int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q,
+             int32_t mem, int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap,
+             int64_t *out_off);
+
+/* Size of the BWT n, number of sentinels m, and C[c] = number of symbols
+ * smaller than c (Table 1) for c = 0..5. Any output pointer may be NULL. */
+int rb3_info(const rb3_index *idx, int64_t *n, int64_t *m, int64_t C[6]);
+
+/* Write the BWT as n symbol codes into codes (host, n bytes). */
+int rb3_export(const rb3_index *idx, uint8_t *codes);
+
+/* Build an index from n BWT symbol codes (host or device per mem). Codes
+ * must be 0..5 and include at least one 0; otherwise RB3_EINVAL. The codes
+ * are taken as given: the call does not check that they form a BWT. */
+int rb3_import(const rb3_opts *o, const uint8_t *codes, int64_t n, int32_t mem,
+               rb3_index **out);
+
+/* Deep copy of an index on the same device and stream. */
+int rb3_clone(const rb3_index *src, rb3_index **out);
+
+void rb3_index_free(rb3_index *idx);
+
+const char *rb3_strerror(int err);
+
+/*
+ * Kernel timing. While enabled, every kernel the library launches is
+ * bracketed by HIP events on the stream it runs on. rb3_prof_read
+ * synchronizes those events and reports, per kernel name, the number of
+ * launches and the summed GPU time in milliseconds. Names are copied into
+ * names[i*32 .. i*32+31] (NUL-terminated). *n_out receives the number of
+ * distinct kernels (entries beyond cap are not written).
+ */
+int rb3_prof_enable(int on);
+int rb3_prof_reset(void);
+int rb3_prof_read(char *names, int64_t *launches, double *ms, int64_t cap, int64_t *n_out);
+
+/* Last merge statistics: per-stage counters useful for throughput accounting
+ * (suffixes inserted, rank steps, tie rounds, ...). keys receives up to cap
+ * 32-byte names, vals their values. */
+int rb3_merge_stats(const rb3_index *idx, char *keys, int64_t *vals, int64_t cap, int64_t *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RB3_H */

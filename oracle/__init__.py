@@ -50,7 +50,7 @@ def _load():
     if not os.path.exists(_LIB_PATH):
         build(force=True)
     lib = ctypes.CDLL(_LIB_PATH)
-    lib.orc_expand.argtypes = [_u8p, _i64p, ctypes.c_int64, ctypes.c_int, _u8p, _i64p]
+    lib.orc_expand.argtypes = [_u8p, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _u8p, _i64p]
     lib.orc_expand.restype = ctypes.c_int
     lib.orc_bwt.argtypes = [_u8p, _i64p, ctypes.c_int64, ctypes.c_int, _u8p, _i64p]
     lib.orc_bwt.restype = ctypes.c_int
@@ -80,7 +80,7 @@ def _threads(nthreads):
     return int(nthreads) if nthreads else max(1, min(os.cpu_count() or 1, 16))
 
 
-def expand(data: np.ndarray, lens: np.ndarray, both: bool = True):
+def expand(data: np.ndarray, lens: np.ndarray, both: bool = True, allow_empty: bool = False):
     """Encode ASCII strings ($=0 A=1 C=2 G=3 T=4 N=5) and, when ``both``, follow
     each string by its reverse complement. Returns (codes, lens)."""
     lib = _load()
@@ -89,7 +89,8 @@ def expand(data: np.ndarray, lens: np.ndarray, both: bool = True):
     k = 2 if both else 1
     codes = np.empty(max(1, k * int(lens.sum())), dtype=np.uint8)
     out_lens = np.empty(max(1, k * lens.shape[0]), dtype=np.int64)
-    rc = lib.orc_expand(_p(data, _u8p), _p(lens, _i64p), lens.shape[0], int(both),
+    dat = data if data.size else np.zeros(1, np.uint8)
+    rc = lib.orc_expand(_p(dat, _u8p), _p(lens, _i64p), lens.shape[0], int(both), int(allow_empty),
                         _p(codes, _u8p), _p(out_lens, _i64p))
     if rc == -1:
         raise ValueError("byte outside ACGTNacgtn")
@@ -99,8 +100,8 @@ def expand(data: np.ndarray, lens: np.ndarray, both: bool = True):
 
 
 def encode(data: np.ndarray, lens: np.ndarray):
-    """Encode strings without reverse complements (used for queries)."""
-    return expand(data, lens, both=False)
+    """Encode patterns without reverse complements; empty patterns allowed."""
+    return expand(data, lens, both=False, allow_empty=True)
 
 
 def bwt(codes: np.ndarray, lens: np.ndarray, nthreads: int | None = None, want_sa: bool = False):

@@ -58,15 +58,16 @@ static uint8_t orc_comp(uint8_t c)
  * P0, rc(P0), P1, rc(P1), ... when both != 0 (Sec. 2.5), or P0, P1, ...
  * otherwise. codes receives the concatenated strands without sentinels,
  * lens_out one length per strand. Returns 0, or -1 on a byte outside
- * ACGTNacgtn, or -2 on a string of length 0.
+ * ACGTNacgtn, or -2 on a string of length 0 unless allow_empty (patterns
+ * may be empty; strings of the text may not).
  */
 int orc_expand(const uint8_t *seq, const int64_t *lens, int64_t m_in, int both,
-               uint8_t *codes, int64_t *lens_out)
+               int allow_empty, uint8_t *codes, int64_t *lens_out)
 {
     int64_t in = 0, out = 0, s = 0;
     for (int64_t j = 0; j < m_in; ++j) {
         int64_t L = lens[j];
-        if (L <= 0) return -2;
+        if (L < 0 || (L == 0 && !allow_empty)) return -2;
         for (int64_t t = 0; t < L; ++t) {
             int c = orc_code_of(seq[in + t]);
             if (c < 0) return -1;

@@ -1,0 +1,589 @@
+// C ABI of the library (see include/rb3.h): argument checks, host/device
+// staging, ownership, error reporting and kernel-time profiling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rb3_internal.h"
+
+struct rb3_index {
+    rb3::IndexData d;
+};
+
+namespace rb3 {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+static thread_local int g_err_code = 0;
+
+void set_error(int code, const std::string &msg) {
+    g_err_code = code;
+    g_err = msg;
+}
+
+static int fail(int code, const char *msg) {
+    set_error(code, msg);
+    return code;
+}
+
+int check_launch(const char *name) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(RB3_EDEVICE, std::string("launch of ") + name + ": " + hipGetErrorString(e));
+        return RB3_EDEVICE;
+    }
+    return RB3_OK;
+}
+
+// ---------------------------------------------------------------------------
+// memory
+// ---------------------------------------------------------------------------
+void *Ctx::dmalloc(size_t bytes) {
+    if (alloc) return alloc(bytes, alloc_ctx);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void Ctx::free_now(void *p) {
+    if (!p) return;
+    if (free_fn) free_fn(p, alloc_ctx);
+    else (void)hipFree(p);
+}
+
+int Ctx::flush() {
+    hipError_t e = hipStreamSynchronize(stream);
+    for (void *p : deferred) free_now(p);
+    deferred.clear();
+    if (e != hipSuccess) {
+        set_error(RB3_EDEVICE, std::string("stream synchronize: ") + hipGetErrorString(e));
+        return RB3_EDEVICE;
+    }
+    return RB3_OK;
+}
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+struct Agg {
+    int64_t launches = 0;
+    double ms = 0;
+};
+std::map<std::string, Agg> g_prof_agg;
+
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void prof_drain_locked() {
+    for (auto &r : g_prof_pending) {
+        float ms = 0;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            Agg &g = g_prof_agg[r.name];
+            g.launches += 1;
+            g.ms += ms;
+        }
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof_pending.clear();
+}
+}  // namespace
+
+ProfScope::ProfScope(const char *nm, hipStream_t s) : name(nm), stream(s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    hipEvent_t e = prof_event();
+    if (e && hipEventRecord(e, s) == hipSuccess) ev0 = e;
+}
+
+ProfScope::~ProfScope() {
+    if (!ev0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t e = prof_event();
+    if (e && hipEventRecord(e, stream) == hipSuccess) {
+        g_prof_pending.push_back({name, (hipEvent_t)ev0, e});
+        if (g_prof_pending.size() > 4096) prof_drain_locked();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+static int ctx_from_opts(const rb3_opts *o, Ctx &c) {
+    rb3_opts d;
+    rb3_opts_init(&d);
+    if (!o) o = &d;
+    c.device = o->device;
+    c.alloc = o->dev_alloc;
+    c.free_fn = o->dev_free;
+    c.alloc_ctx = o->alloc_ctx;
+    c.chunk_len = o->chunk_len;
+    c.both = o->both_strands ? 1 : 0;
+    if ((c.alloc == nullptr) != (c.free_fn == nullptr)) return fail(RB3_EINVAL, "dev_alloc and dev_free must be given together");
+    RB3_HIP(hipSetDevice(c.device));
+    if (o->stream) {
+        c.stream = (hipStream_t)o->stream;
+        c.own_stream = false;
+    } else {
+        RB3_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+        c.own_stream = true;
+    }
+    return RB3_OK;
+}
+
+// A per-call working context: the index's configuration with its own list
+// of deferred frees.
+static Ctx call_ctx(const IndexData &d) {
+    Ctx c;
+    c.device = d.ctx.device;
+    c.stream = d.ctx.stream;
+    c.own_stream = false;
+    c.alloc = d.ctx.alloc;
+    c.free_fn = d.ctx.free_fn;
+    c.alloc_ctx = d.ctx.alloc_ctx;
+    c.chunk_len = d.ctx.chunk_len;
+    c.both = d.ctx.both;
+    return c;
+}
+
+// Finish a call: drain the stream, release temporaries, keep the first error.
+static int finish(Ctx &c, int rc) {
+    int r2 = c.flush();
+    return rc != RB3_OK ? rc : r2;
+}
+
+static int check_strings(const uint8_t *seq, const int64_t *lens, int64_t n, int32_t mem, bool allow_empty,
+                         int64_t *total) {
+    if (n < 0 || (n > 0 && !lens)) return fail(RB3_EINVAL, "lengths array is NULL or count negative");
+    if (mem != RB3_MEM_HOST && mem != RB3_MEM_DEVICE) return fail(RB3_EINVAL, "mem must be RB3_MEM_HOST or RB3_MEM_DEVICE");
+    int64_t t = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (lens[j] < 0 || (!allow_empty && lens[j] == 0)) return fail(RB3_EINVAL, "string of length 0 (or negative)");
+        t += lens[j];
+    }
+    if (t > 0 && !seq) return fail(RB3_EINVAL, "sequence buffer is NULL");
+    *total = t;
+    return RB3_OK;
+}
+
+// Device copy of a caller buffer (or the buffer itself when already there).
+static int stage(Ctx &c, const uint8_t *p, int64_t bytes, int32_t mem, DBuf &hold, const uint8_t **dptr) {
+    if (mem == RB3_MEM_DEVICE) {
+        *dptr = p;
+        return RB3_OK;
+    }
+    RB3_ALLOC(hold, &c, bytes > 0 ? bytes : 1);
+    if (bytes > 0) RB3_HIP(hipMemcpyAsync(hold.p, p, bytes, hipMemcpyHostToDevice, c.stream));
+    *dptr = hold.as<uint8_t>();
+    return RB3_OK;
+}
+
+static int read_flag(Ctx &c, const int32_t *d_flag, int32_t *out) {
+    RB3_HIP(hipMemcpyAsync(out, d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipStreamSynchronize(c.stream));
+    return RB3_OK;
+}
+
+static int init_empty(Ctx &c, IndexData &d) {
+    // zero symbols: one padding block (code 7 everywhere) and one superblock
+    d.n = 0;
+    d.m = 0;
+    for (int i = 0; i < 6; ++i) d.C[i] = 0;
+    DBuf blk, sb;
+    RB3_ALLOC(blk, &c, 64);
+    RB3_ALLOC(sb, &c, SB_STRIDE * sizeof(int64_t));
+    RB3_HIP(hipMemsetAsync(blk.p, 0xFF, 48, c.stream));
+    RB3_HIP(hipMemsetAsync((uint8_t *)blk.p + 48, 0, 16, c.stream));
+    RB3_HIP(hipMemsetAsync(sb.p, 0, SB_STRIDE * sizeof(int64_t), c.stream));
+    d.blk = blk.as<uint4>();
+    d.sb = sb.as<int64_t>();
+    blk.release();
+    sb.release();
+    return RB3_OK;
+}
+
+// Merge expanded strings into d (strong guarantee: d unchanged on error).
+static int do_merge(Ctx &c, IndexData &d, const uint8_t *seq, const int64_t *lens, int64_t n_seqs, int32_t mem) {
+    int64_t total = 0;
+    RB3_TRY(check_strings(seq, lens, n_seqs, mem, false, &total));
+    if (n_seqs == 0) return RB3_OK;
+    const int k = d.ctx.both ? 2 : 1;
+    const int64_t m2 = k * n_seqs;
+    const int64_t n2 = k * (total + n_seqs);
+    const int64_t limit = (int64_t)UINT32_MAX - (1ll << 20);
+    if (n2 >= limit) return fail(RB3_ELIMIT, "batch too large: new symbols must stay below 2^32 - 2^20");
+    if (d.m + m2 >= (int64_t)INT32_MAX) return fail(RB3_ELIMIT, "too many strings");
+    DBuf hold, Q, err;
+    const uint8_t *d_seq = nullptr;
+    RB3_TRY(stage(c, seq, total, mem, hold, &d_seq));
+    RB3_ALLOC(Q, &c, n2);
+    RB3_ALLOC(err, &c, sizeof(int32_t));
+    RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
+    RB3_TRY(encode_strands(c, d_seq, lens, n_seqs, d.ctx.both, Q.as<uint8_t>(), n2, err.as<int32_t>()));
+    int32_t bad = 0;
+    RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
+    if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in the input strings");
+    hold.reset();
+    std::vector<int64_t> slens(m2);
+    for (int64_t j = 0; j < n_seqs; ++j)
+        for (int s = 0; s < k; ++s) slens[j * k + s] = lens[j];
+    uint4 *nb = nullptr;
+    int64_t *nsb = nullptr;
+    int64_t C[6];
+    MergeStats st;
+    RB3_TRY(merge_into(c, d, Q.as<uint8_t>(), slens.data(), m2, n2, &nb, &nsb, C, st));
+    c.dfree(d.blk);
+    c.dfree(d.sb);
+    d.blk = nb;
+    d.sb = nsb;
+    d.n += n2;
+    d.m += m2;
+    for (int i = 0; i < 6; ++i) d.C[i] = C[i];
+    d.last = st;
+    return RB3_OK;
+}
+
+}  // namespace rb3
+
+using namespace rb3;
+
+extern "C" {
+
+void rb3_opts_init(rb3_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->both_strands = 1;
+    o->device = 0;
+}
+
+const char *rb3_strerror(int err) {
+    if (err != RB3_OK && err == g_err_code && !g_err.empty()) return g_err.c_str();
+    switch (err) {
+    case RB3_OK: return "ok";
+    case RB3_EINVAL: return "invalid argument";
+    case RB3_ENOMEM: return "out of memory";
+    case RB3_EDEVICE: return "device error";
+    case RB3_ENOSPC: return "output buffer too small";
+    case RB3_ELIMIT: return "size limit exceeded";
+    default: return "unknown error";
+    }
+}
+
+int rb3_build(const rb3_opts *o, const uint8_t *seq, const int64_t *lens, int64_t n_seqs, int32_t mem,
+              rb3_index **out) {
+    if (!out) return fail(RB3_EINVAL, "out is NULL");
+    if (n_seqs < 1) return fail(RB3_EINVAL, "rb3_build needs at least one string");
+    int64_t total = 0;
+    RB3_TRY(check_strings(seq, lens, n_seqs, mem, false, &total));
+    rb3_index *ix = new (std::nothrow) rb3_index();
+    if (!ix) return fail(RB3_ENOMEM, "host allocation failed");
+    int rc = ctx_from_opts(o, ix->d.ctx);
+    if (rc != RB3_OK) {
+        delete ix;
+        return rc;
+    }
+    Ctx c = call_ctx(ix->d);
+    rc = init_empty(c, ix->d);
+    if (rc == RB3_OK) rc = do_merge(c, ix->d, seq, lens, n_seqs, mem);
+    rc = finish(c, rc);
+    if (rc != RB3_OK) {
+        rb3_index_free(ix);
+        return rc;
+    }
+    *out = ix;
+    return RB3_OK;
+}
+
+int rb3_merge(rb3_index *idx, const uint8_t *seq, const int64_t *lens, int64_t n_seqs, int32_t mem) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    Ctx c = call_ctx(idx->d);
+    int rc = do_merge(c, idx->d, seq, lens, n_seqs, mem);
+    return finish(c, rc);
+}
+
+int rb3_count(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
+              int64_t *lo, int64_t *hi) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    if (n_q > 0 && (!lo || !hi)) return fail(RB3_EINVAL, "output arrays are NULL");
+    int64_t total = 0;
+    RB3_TRY(check_strings(q, qlens, n_q, mem, true, &total));
+    if (n_q == 0) return RB3_OK;
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    Ctx c = call_ctx(idx->d);
+    int rc = [&]() -> int {
+        DBuf hold, codes, err, off, dlo, dhi;
+        const uint8_t *d_q = nullptr;
+        RB3_TRY(stage(c, q, total, mem, hold, &d_q));
+        RB3_ALLOC(codes, &c, total > 0 ? total : 1);
+        RB3_ALLOC(err, &c, sizeof(int32_t));
+        RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
+        RB3_TRY(encode_plain(c, d_q, qlens, n_q, codes.as<uint8_t>(), total, err.as<int32_t>()));
+        std::vector<int64_t> hoff(n_q + 1);
+        hoff[0] = 0;
+        for (int64_t i = 0; i < n_q; ++i) hoff[i + 1] = hoff[i] + qlens[i];
+        RB3_ALLOC(off, &c, (n_q + 1) * sizeof(int64_t));
+        RB3_ALLOC(dlo, &c, n_q * sizeof(int64_t));
+        RB3_ALLOC(dhi, &c, n_q * sizeof(int64_t));
+        RB3_HIP(hipMemcpyAsync(off.p, hoff.data(), (n_q + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+        int32_t bad = 0;
+        RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
+        if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in a query");
+        RB3_TRY(count_queries(c, idx->d.dev(), codes.as<uint8_t>(), off.as<int64_t>(), n_q, dlo.as<int64_t>(),
+                              dhi.as<int64_t>()));
+        RB3_HIP(hipMemcpyAsync(lo, dlo.p, n_q * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+        RB3_HIP(hipMemcpyAsync(hi, dhi.p, n_q * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+        return RB3_OK;
+    }();
+    return finish(c, rc);
+}
+
+int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
+             int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    if (!out_off) return fail(RB3_EINVAL, "out_off is NULL");
+    if (min_len < 1 || min_occ < 1) return fail(RB3_EINVAL, "min_len and min_occ must be >= 1");
+    if (out_cap < 0 || (out_cap > 0 && !out)) return fail(RB3_EINVAL, "bad output buffer");
+    if (!idx->d.ctx.both) return fail(RB3_EINVAL, "SMEM finding needs an index of both strands");
+    if (n_q >= (int64_t)INT32_MAX) return fail(RB3_ELIMIT, "too many queries");
+    int64_t total = 0;
+    RB3_TRY(check_strings(q, qlens, n_q, mem, true, &total));
+    out_off[0] = 0;
+    if (n_q == 0) return RB3_OK;
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    Ctx c = call_ctx(idx->d);
+    int rc = [&]() -> int {
+        DBuf hold, codes, err, off, tmp, ordered, cnt, coff, tot;
+        const uint8_t *d_q = nullptr;
+        RB3_TRY(stage(c, q, total, mem, hold, &d_q));
+        RB3_ALLOC(codes, &c, total > 0 ? total : 1);
+        RB3_ALLOC(err, &c, sizeof(int32_t));
+        RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
+        RB3_TRY(encode_plain(c, d_q, qlens, n_q, codes.as<uint8_t>(), total, err.as<int32_t>()));
+        std::vector<int64_t> hoff(n_q + 1);
+        hoff[0] = 0;
+        for (int64_t i = 0; i < n_q; ++i) hoff[i + 1] = hoff[i] + qlens[i];
+        RB3_ALLOC(off, &c, (n_q + 1) * sizeof(int64_t));
+        RB3_HIP(hipMemcpyAsync(off.p, hoff.data(), (n_q + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+        int32_t bad = 0;
+        RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
+        if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in a query");
+        int64_t cap = out_cap;
+        RB3_ALLOC(tmp, &c, (cap > 0 ? cap : 1) * sizeof(rb3_smem_t));
+        RB3_ALLOC(ordered, &c, (cap > 0 ? cap : 1) * sizeof(rb3_smem_t));
+        RB3_ALLOC(cnt, &c, (n_q + 1) * sizeof(uint32_t));
+        RB3_ALLOC(coff, &c, (n_q + 1) * sizeof(uint32_t));
+        RB3_ALLOC(tot, &c, sizeof(unsigned long long));
+        RB3_HIP(hipMemsetAsync(cnt.p, 0, (n_q + 1) * sizeof(uint32_t), c.stream));
+        int64_t found = 0;
+        RB3_TRY(smem_run(c, idx->d.dev(), codes.as<uint8_t>(), off.as<int64_t>(), n_q, min_len, min_occ, cap,
+                         tmp.as<rb3_smem_t>(), ordered.as<rb3_smem_t>(), cnt.as<uint32_t>(), coff.as<uint32_t>(),
+                         tot.as<unsigned long long>(), &found));
+        std::vector<uint32_t> hco(n_q + 1);
+        RB3_HIP(hipMemcpyAsync(hco.data(), coff.p, (n_q + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+        if (found <= cap && found > 0)
+            RB3_HIP(hipMemcpyAsync(out, ordered.p, found * sizeof(rb3_smem_t), hipMemcpyDeviceToHost, c.stream));
+        RB3_HIP(hipStreamSynchronize(c.stream));
+        for (int64_t i = 0; i <= n_q; ++i) out_off[i] = hco[i];
+        if (found > cap) return fail(RB3_ENOSPC, "SMEM output buffer too small; out_off holds the sizes");
+        return RB3_OK;
+    }();
+    return finish(c, rc);
+}
+
+int rb3_info(const rb3_index *idx, int64_t *n, int64_t *m, int64_t C[6]) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    if (n) *n = idx->d.n;
+    if (m) *m = idx->d.m;
+    if (C)
+        for (int i = 0; i < 6; ++i) C[i] = idx->d.C[i];
+    return RB3_OK;
+}
+
+int rb3_export(const rb3_index *idx, uint8_t *codes) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    if (idx->d.n == 0) return RB3_OK;
+    if (!codes) return fail(RB3_EINVAL, "codes is NULL");
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    Ctx c = call_ctx(idx->d);
+    int rc = [&]() -> int {
+        DBuf dc;
+        RB3_ALLOC(dc, &c, idx->d.n);
+        RB3_TRY(unpack_codes(c, idx->d.dev(), dc.as<uint8_t>()));
+        RB3_HIP(hipMemcpyAsync(codes, dc.p, idx->d.n, hipMemcpyDeviceToHost, c.stream));
+        return RB3_OK;
+    }();
+    return finish(c, rc);
+}
+
+int rb3_import(const rb3_opts *o, const uint8_t *codes, int64_t n, int32_t mem, rb3_index **out) {
+    if (!out) return fail(RB3_EINVAL, "out is NULL");
+    if (n < 1 || !codes) return fail(RB3_EINVAL, "need at least one code");
+    if (mem != RB3_MEM_HOST && mem != RB3_MEM_DEVICE) return fail(RB3_EINVAL, "bad mem");
+    rb3_index *ix = new (std::nothrow) rb3_index();
+    if (!ix) return fail(RB3_ENOMEM, "host allocation failed");
+    int rc = ctx_from_opts(o, ix->d.ctx);
+    if (rc != RB3_OK) {
+        delete ix;
+        return rc;
+    }
+    Ctx c = call_ctx(ix->d);
+    rc = [&]() -> int {
+        DBuf hold, err, blk, sb;
+        const uint8_t *d_codes = nullptr;
+        RB3_TRY(stage(c, codes, n, mem, hold, &d_codes));
+        RB3_ALLOC(err, &c, sizeof(int32_t));
+        RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
+        RB3_TRY(check_codes(c, d_codes, n, err.as<int32_t>()));
+        int32_t bad = 0;
+        RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
+        if (bad) return fail(RB3_EINVAL, "code outside 0..5");
+        RB3_ALLOC(blk, &c, num_blocks(n) * 64);
+        RB3_ALLOC(sb, &c, num_superblocks(n) * SB_STRIDE * sizeof(int64_t));
+        RB3_TRY(pack_codes(c, d_codes, n, blk.as<uint4>()));
+        int64_t C[6], cnt[6];
+        RB3_TRY(build_checkpoints(c, blk.as<uint4>(), n, sb.as<int64_t>(), C, cnt));
+        if (cnt[0] < 1) return fail(RB3_EINVAL, "no sentinel ($) in the codes");
+        ix->d.n = n;
+        ix->d.m = cnt[0];
+        for (int i = 0; i < 6; ++i) ix->d.C[i] = C[i];
+        ix->d.blk = (uint4 *)blk.release();
+        ix->d.sb = (int64_t *)sb.release();
+        return RB3_OK;
+    }();
+    rc = finish(c, rc);
+    if (rc != RB3_OK) {
+        rb3_index_free(ix);
+        return rc;
+    }
+    *out = ix;
+    return RB3_OK;
+}
+
+int rb3_clone(const rb3_index *src, rb3_index **out) {
+    if (!src || !out) return fail(RB3_EINVAL, "NULL argument");
+    RB3_HIP(hipSetDevice(src->d.ctx.device));
+    rb3_index *ix = new (std::nothrow) rb3_index();
+    if (!ix) return fail(RB3_ENOMEM, "host allocation failed");
+    ix->d.ctx = call_ctx(src->d);
+    ix->d.ctx.own_stream = false;
+    Ctx c = call_ctx(src->d);
+    int rc = [&]() -> int {
+        DBuf blk, sb;
+        size_t bb = num_blocks(src->d.n) * 64, sbb = num_superblocks(src->d.n) * SB_STRIDE * sizeof(int64_t);
+        RB3_ALLOC(blk, &c, bb);
+        RB3_ALLOC(sb, &c, sbb);
+        RB3_HIP(hipMemcpyAsync(blk.p, src->d.blk, bb, hipMemcpyDeviceToDevice, c.stream));
+        RB3_HIP(hipMemcpyAsync(sb.p, src->d.sb, sbb, hipMemcpyDeviceToDevice, c.stream));
+        ix->d.n = src->d.n;
+        ix->d.m = src->d.m;
+        for (int i = 0; i < 6; ++i) ix->d.C[i] = src->d.C[i];
+        ix->d.blk = (uint4 *)blk.release();
+        ix->d.sb = (int64_t *)sb.release();
+        return RB3_OK;
+    }();
+    rc = finish(c, rc);
+    if (rc != RB3_OK) {
+        rb3_index_free(ix);
+        return rc;
+    }
+    *out = ix;
+    return RB3_OK;
+}
+
+void rb3_index_free(rb3_index *idx) {
+    if (!idx) return;
+    (void)hipSetDevice(idx->d.ctx.device);
+    if (idx->d.ctx.stream) (void)hipStreamSynchronize(idx->d.ctx.stream);
+    Ctx c = call_ctx(idx->d);
+    c.free_now(idx->d.blk);
+    c.free_now(idx->d.sb);
+    if (idx->d.ctx.own_stream && idx->d.ctx.stream) (void)hipStreamDestroy(idx->d.ctx.stream);
+    delete idx;
+}
+
+int rb3_prof_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return RB3_OK;
+}
+
+int rb3_prof_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain_locked();
+    g_prof_agg.clear();
+    return RB3_OK;
+}
+
+int rb3_prof_read(char *names, int64_t *launches, double *ms, int64_t cap, int64_t *n_out) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain_locked();
+    int64_t i = 0;
+    for (auto &kv : g_prof_agg) {
+        if (i < cap) {
+            if (names) {
+                std::memset(names + i * 32, 0, 32);
+                std::strncpy(names + i * 32, kv.first.c_str(), 31);
+            }
+            if (launches) launches[i] = kv.second.launches;
+            if (ms) ms[i] = kv.second.ms;
+        }
+        ++i;
+    }
+    if (n_out) *n_out = i;
+    return RB3_OK;
+}
+
+int rb3_merge_stats(const rb3_index *idx, char *keys, int64_t *vals, int64_t cap, int64_t *n_out) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    const MergeStats &s = idx->d.last;
+    std::vector<std::pair<const char *, int64_t>> kv = {
+        {"n1", s.n1}, {"m1", s.m1}, {"n2", s.n2}, {"m2", s.m2},
+        {"chunks", s.chunks}, {"chunk_len", s.chunk_len}, {"chain_steps", s.chain_steps},
+        {"fixup_steps", s.fixup_steps}, {"fixup_passes", s.fixup_passes}, {"key_syms", s.key_syms},
+        {"sort_bits", s.sort_bits}, {"tied_records", s.tied_records}, {"tie_rounds", s.tie_rounds},
+        {"tie_work", s.tie_work}, {"max_group", s.max_group}};
+    int64_t i = 0;
+    for (auto &p : kv) {
+        if (i < cap) {
+            if (keys) {
+                std::memset(keys + i * 32, 0, 32);
+                std::strncpy(keys + i * 32, p.first, 31);
+            }
+            if (vals) vals[i] = p.second;
+        }
+        ++i;
+    }
+    if (n_out) *n_out = i;
+    return RB3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,621 @@
+// Merging new strings into a device-resident BWT (Sec. 2.2, Algorithm 1).
+//
+// Algorithm 1 walks each new string right to left, keeping l = the number of
+// suffixes of the existing BWT B1 that are smaller than the current suffix
+// (l starts at m1 for the sentinel, then l <- pi_B1(a, l)), and adds the row
+// of the suffix among the new suffixes, which it reads from the partial BWT
+// B2 of the batch. Here:
+//
+//   1. LF chains (k_chain, k_fixup). The walk is cut into chunks so that
+//      thousands of lanes run at once. A chunk whose right end is not the
+//      sentinel starts from the closed range [m1, n1] of possible l values
+//      and maps both ends through the monotone l -> pi(a, l); once they meet,
+//      the value is exact whatever the true start was. The positions walked
+//      before that are replayed by a fix-up pass from the right neighbour's
+//      exact value.
+//   2. Order among the new suffixes without building B2. For new suffixes x,
+//      y: l(x) < l(y) implies x < y, and when l(x) = l(y) the order is the
+//      plain string order. So the new suffixes are radix-sorted by the key
+//      (l, first w symbols) and the remaining ties are broken by prefix
+//      doubling on the sequence of those keys (k_gather / k_rerank).
+//      Sentinel suffixes are unique and sort by strand index.
+//   3. Interleave (k_interleave): the s-th new suffix in sorted order lands
+//      on merged row l_s + s, its BWT symbol being the symbol before it; the
+//      B1 rows fill the remaining rows in order. Checkpoints are rebuilt.
+#include "rb3_internal.h"
+
+namespace rb3 {
+
+struct Chunk {
+    int64_t p0;    // position in Q of the chunk's first symbol
+    int32_t len;   // symbols in the chunk
+    int32_t last;  // 1 if the chunk ends at the strand's sentinel
+};
+
+// Sort key of a new suffix at position p:
+//   (l - m1) << lshift | packed(Q[p..p+w)) << 3 | emit
+// where packed holds w codes, the first in the most significant place, with
+// zeros after the strand's sentinel, and emit = Q[p-1] is the suffix's BWT
+// symbol (0 = $ at a strand start). Bits 0..2 are carried but not sorted on.
+// A key whose lowest packed code is 0 contains its sentinel: such suffixes
+// are unique and ordered by position.
+__device__ __forceinline__ uint64_t make_key(int64_t lrel, uint64_t packed, uint32_t emit, int lshift) {
+    return ((uint64_t)lrel << lshift) | (packed << 3) | (uint64_t)emit;
+}
+
+__device__ __forceinline__ uint64_t pack_ahead(const uint8_t *__restrict__ Q, int64_t p, int w) {
+    uint64_t packed = 0;
+    for (int t = 0; t < w; ++t) {
+        uint32_t c = Q[p + t];
+        if (!c) break;
+        packed |= (uint64_t)c << (3 * (w - 1 - t));
+    }
+    return packed;
+}
+
+__global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
+                        int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K,
+                        int32_t *__restrict__ unres, int32_t *__restrict__ ready,
+                        unsigned long long *__restrict__ stats) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nch) return;
+    Chunk c = ch[i];
+    const int lshift = 3 + 3 * w, wsh = 3 * (w - 1);
+    int64_t p1 = c.p0 + c.len;
+    uint64_t packed = 0;
+    bool point;
+    int64_t l = m1, lo = m1, hi = ix.n;
+    if (c.last) {
+        point = true;
+        K[p1] = (uint64_t)Q[p1 - 1];  // sentinel suffix: l = m1, no symbols
+    } else {
+        point = false;
+        packed = pack_ahead(Q, p1, w);
+    }
+    int32_t unresolved = 0;
+    int64_t wide = 0;
+    for (int64_t p = p1 - 1; p >= c.p0; --p) {
+        uint32_t a = Q[p];
+        uint32_t emit = p > 0 ? Q[p - 1] : 0u;
+        packed = ((uint64_t)a << wsh) | (packed >> 3);
+        if (point) {
+            l = pi_sym(ix, (int)a, l);
+            K[p] = make_key(l - m1, packed, emit, lshift);
+        } else {
+            int64_t bl = lo >> BLK_SHIFT, bh = hi >> BLK_SHIFT;
+            Block B = load_block(ix.blk, bl);
+            int64_t nlo = pi_from_block(ix, B, (int)a, lo);
+            int64_t nhi;
+            if (bh == bl) {
+                nhi = pi_from_block(ix, B, (int)a, hi);
+            } else {
+                nhi = pi_sym(ix, (int)a, hi);
+                ++wide;
+            }
+            lo = nlo;
+            hi = nhi;
+            if (lo == hi) {
+                point = true;
+                l = lo;
+                K[p] = make_key(l - m1, packed, emit, lshift);
+            } else {
+                ++unresolved;
+            }
+        }
+    }
+    unres[i] = unresolved;
+    ready[i] = point ? 1 : 0;
+    if (unresolved) atomicAdd(&stats[0], (unsigned long long)unresolved);
+    if (wide) atomicAdd(&stats[1], (unsigned long long)wide);
+}
+
+__global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
+                        int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K,
+                        int32_t *__restrict__ unres, const int32_t *__restrict__ ready_in,
+                        int32_t *__restrict__ ready_out, int32_t *__restrict__ pending) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nch) return;
+    int32_t u = unres[i];
+    if (u == 0) return;
+    // an unresolved chunk is never the last of its strand, so i+1 is its
+    // right neighbour; its first position must already be exact
+    if (!ready_in[i + 1]) {
+        atomicAdd(pending, 1);
+        return;
+    }
+    Chunk c = ch[i];
+    const int lshift = 3 + 3 * w, wsh = 3 * (w - 1);
+    int64_t p1 = c.p0 + c.len;
+    int64_t l = (int64_t)(K[p1] >> lshift) + m1;
+    uint64_t packed = pack_ahead(Q, p1, w);
+    for (int64_t p = p1 - 1; p >= p1 - u; --p) {
+        uint32_t a = Q[p];
+        uint32_t emit = p > 0 ? Q[p - 1] : 0u;
+        packed = ((uint64_t)a << wsh) | (packed >> 3);
+        l = pi_sym(ix, (int)a, l);
+        K[p] = make_key(l - m1, packed, emit, lshift);
+    }
+    unres[i] = 0;
+    if (u == c.len) ready_out[i] = 1;
+}
+
+// Keys for a merge into an empty index: every l is 0.
+__global__ void k_build_keys(const uint8_t *__restrict__ Q, int64_t n2, int w, uint64_t *__restrict__ K) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n2;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t packed = pack_ahead(Q, p, w);
+        uint32_t emit = p > 0 ? Q[p - 1] : 0u;
+        K[p] = (packed << 3) | emit;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tie resolution
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool starts_group(const uint64_t *__restrict__ SK, int64_t s) {
+    if (s == 0) return true;
+    uint64_t k = SK[s] >> 3;
+    if ((k & 7) == 0) return true;  // contains its sentinel: unique
+    return k != (SK[s - 1] >> 3);
+}
+
+__global__ void k_head_flags(const uint64_t *__restrict__ SK, int64_t n, uint32_t *__restrict__ hv) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x)
+        hv[s] = starts_group(SK, s) ? (uint32_t)s : 0u;
+}
+
+// R[pos] = group head; tied[s] = 1 when the group has two or more members.
+__global__ void k_rank_init(const uint64_t *__restrict__ SK, const uint32_t *__restrict__ SV,
+                            const uint32_t *__restrict__ head, int64_t n, uint32_t *__restrict__ R,
+                            uint32_t *__restrict__ tied) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = head[s];
+        R[SV[s]] = h;
+        bool single = (h == (uint32_t)s) && (s + 1 == n || starts_group(SK, s + 1));
+        tied[s] = single ? 0u : 1u;
+    }
+}
+
+__global__ void k_active_init(const uint64_t *__restrict__ SK, const uint32_t *__restrict__ SV,
+                              const uint32_t *__restrict__ head, const uint32_t *__restrict__ tied,
+                              const uint32_t *__restrict__ idx, int64_t n, uint32_t *__restrict__ apos,
+                              uint32_t *__restrict__ ahead, uint32_t *__restrict__ ags,
+                              uint32_t *__restrict__ agsz, uint32_t *__restrict__ maxg) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        if (!tied[s]) continue;
+        uint32_t i = idx[s], h = head[s];
+        uint32_t gs = idx[h];
+        apos[i] = SV[s];
+        ahead[i] = h;
+        ags[i] = gs;
+        if (s + 1 == n || starts_group(SK, s + 1)) {
+            uint32_t sz = (uint32_t)(s - h + 1);
+            agsz[gs] = sz;
+            atomicMax(maxg, sz);
+        }
+    }
+}
+
+__global__ void k_gather(const uint32_t *__restrict__ apos, int64_t A, const uint32_t *__restrict__ R,
+                         int64_t h, int64_t n2, uint32_t *__restrict__ key2, int32_t *__restrict__ guard) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t q = (int64_t)apos[i] + h;
+        if (q < n2) {
+            key2[i] = R[q];
+        } else {
+            key2[i] = 0;
+            atomicOr(guard, GUARD_GATHER);
+        }
+    }
+}
+
+// Refine each group by the rank h positions further on. Groups are
+// contiguous in the active list and small, so every member counts the keys
+// of its group directly.
+__global__ void k_rerank(const uint32_t *__restrict__ apos, const uint32_t *__restrict__ ahead,
+                         const uint32_t *__restrict__ ags, const uint32_t *__restrict__ agsz,
+                         const uint32_t *__restrict__ key2, int64_t A, uint32_t *__restrict__ R,
+                         uint32_t *__restrict__ tpos, uint32_t *__restrict__ thead,
+                         uint32_t *__restrict__ tkeep, uint32_t *__restrict__ tsub,
+                         uint32_t *__restrict__ teq, int32_t *__restrict__ guard) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t gs = ags[i];
+        if ((int64_t)gs >= A) {
+            atomicOr(guard, GUARD_RERANK);
+            continue;
+        }
+        uint32_t sz = agsz[gs], mine = key2[i];
+        if ((int64_t)gs + sz > A || (uint32_t)i < gs || (uint32_t)i >= gs + sz) {
+            atomicOr(guard, GUARD_RERANK);
+            continue;
+        }
+        uint32_t lt = 0, eq = 0, eqb = 0;
+        for (uint32_t j = gs; j < gs + sz; ++j) {
+            uint32_t kj = key2[j];
+            lt += kj < mine;
+            eq += kj == mine;
+            eqb += (kj == mine) & (j < (uint32_t)i);
+        }
+        uint32_t nh = ahead[i] + lt;
+        R[apos[i]] = nh;
+        uint32_t sidx = gs + lt + eqb;
+        tpos[sidx] = apos[i];
+        thead[sidx] = nh;
+        tkeep[sidx] = eq >= 2 ? 1u : 0u;
+        tsub[sidx] = eqb;
+        teq[sidx] = eq;
+    }
+}
+
+__global__ void k_compact(const uint32_t *__restrict__ tpos, const uint32_t *__restrict__ thead,
+                          const uint32_t *__restrict__ tkeep, const uint32_t *__restrict__ tsub,
+                          const uint32_t *__restrict__ teq, const uint32_t *__restrict__ nidx, int64_t A,
+                          uint32_t *__restrict__ apos, uint32_t *__restrict__ ahead,
+                          uint32_t *__restrict__ ags, uint32_t *__restrict__ agsz,
+                          int32_t *__restrict__ guard) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < A;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        if (!tkeep[s]) continue;
+        uint32_t ni = nidx[s];
+        if ((int64_t)ni >= A || tsub[s] > ni) {
+            atomicOr(guard, GUARD_COMPACT);
+            continue;
+        }
+        apos[ni] = tpos[s];
+        ahead[ni] = thead[s];
+        ags[ni] = ni - tsub[s];
+        if (tsub[s] == 0) agsz[ni] = teq[s];
+    }
+}
+
+// Move tied records to their final rows: SK[R[pos]] = K[pos].
+__global__ void k_place(const uint32_t *__restrict__ SV, const uint32_t *__restrict__ R,
+                        const uint64_t *__restrict__ K, int64_t n, uint64_t *__restrict__ SK,
+                        int32_t *__restrict__ guard) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t p = SV[s];
+        if ((int64_t)p >= n) {
+            atomicOr(guard, GUARD_PLACE);
+            continue;
+        }
+        uint32_t r = R[p];
+        if ((int64_t)r >= n) {
+            atomicOr(guard, GUARD_PLACE);
+            continue;
+        }
+        if (r != (uint32_t)s) SK[r] = K[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Interleave
+// ---------------------------------------------------------------------------
+
+__global__ void k_block_count(const uint64_t *__restrict__ SK, int64_t n2, int64_t m1, int lshift,
+                              uint32_t *__restrict__ cnt) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n2;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        int64_t M = (int64_t)(SK[s] >> lshift) + m1 + s;
+        atomicAdd(&cnt[M >> BLK_SHIFT], 1u);
+    }
+}
+
+__device__ __forceinline__ uint32_t b1_symbol(const uint64_t *__restrict__ words, int64_t i) {
+    int64_t b = i >> BLK_SHIFT;
+    int r = (int)(i & 127);
+    int w = r >> 6, bit = r & 63;
+    const uint64_t *q = words + b * 8;
+    return (uint32_t)((q[w] >> bit) & 1u) | (uint32_t)(((q[2 + w] >> bit) & 1u) << 1) |
+           (uint32_t)(((q[4 + w] >> bit) & 1u) << 2);
+}
+
+__global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__ b1words,
+                                                    const uint64_t *__restrict__ SK,
+                                                    const uint32_t *__restrict__ bs, int64_t nout,
+                                                    int64_t nblk_out, int64_t n1, int64_t m1, int lshift,
+                                                    uint4 *__restrict__ out, int32_t *__restrict__ guard) {
+    __shared__ uint8_t slot[4][128];
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t b = wave; b < nblk_out; b += nwaves) {
+        int64_t P0 = b << BLK_SHIFT;
+        uint32_t s0 = bs[b], s1 = bs[b + 1];
+        int64_t i0 = P0 - (int64_t)s0;
+        slot[wv][lane] = 0;
+        slot[wv][lane + 64] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t k = s0 + lane; k < s1; k += 64) {
+            uint64_t key = SK[k];
+            int64_t M = (int64_t)(key >> lshift) + m1 + k;
+            if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | (uint32_t)(key & 7));
+            else atomicOr(guard, GUARD_INTERLEAVE);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        uint32_t e0 = slot[wv][lane], e1 = slot[wv][lane + 64];
+        uint64_t nm0 = __ballot(e0 & 0x80u), nm1 = __ballot(e1 & 0x80u);
+        uint32_t c0 = 7, c1 = 7;
+        if (P0 + lane < nout) {
+            if (e0 & 0x80u) {
+                c0 = e0 & 7u;
+            } else {
+                int64_t i = i0 + lane - __popcll(nm0 & low_mask(lane));
+                if (i >= 0 && i < n1) c0 = b1_symbol(b1words, i);
+                else atomicOr(guard, GUARD_INTERLEAVE);
+            }
+        }
+        if (P0 + 64 + lane < nout) {
+            if (e1 & 0x80u) {
+                c1 = e1 & 7u;
+            } else {
+                int64_t i = i0 + 64 + lane - __popcll(nm0) - __popcll(nm1 & low_mask(lane));
+                if (i >= 0 && i < n1) c1 = b1_symbol(b1words, i);
+                else atomicOr(guard, GUARD_INTERLEAVE);
+            }
+        }
+        uint64_t a0 = __ballot(c0 & 1), a1 = __ballot(c0 & 2), a2 = __ballot(c0 & 4);
+        uint64_t d0 = __ballot(c1 & 1), d1 = __ballot(c1 & 2), d2 = __ballot(c1 & 4);
+        uint32_t cnt = 0;
+        if (lane < 6)
+            cnt = __popcll(plane_match(a0, a1, a2, lane)) + __popcll(plane_match(d0, d1, d2, lane));
+        uint32_t lo = 0, hi = 0;
+        for (int s = 0; s < 6; ++s) {
+            uint32_t v = __shfl(cnt, s);
+            if (s < 4) lo |= v << (8 * s);
+            else hi |= v << (8 * (s - 4));
+        }
+        uint4 *dst = out + (b << 2);
+        if (lane == 0) dst[0] = make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)d0, (uint32_t)(d0 >> 32));
+        if (lane == 1) dst[1] = make_uint4((uint32_t)a1, (uint32_t)(a1 >> 32), (uint32_t)d1, (uint32_t)(d1 >> 32));
+        if (lane == 2) dst[2] = make_uint4((uint32_t)a2, (uint32_t)(a2 >> 32), (uint32_t)d2, (uint32_t)(d2 >> 32));
+        if (lane == 3) dst[3] = make_uint4(lo, hi, 0u, 0u);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+static int bits_for(int64_t v) {  // bits to hold values 0..v
+    int b = 0;
+    while (b < 63 && (v >> b) != 0) ++b;
+    return b;
+}
+
+int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_lens, int64_t m2,
+               int64_t n2, uint4 **new_blk, int64_t **new_sb, int64_t new_C[6], MergeStats &st) {
+    const DevIndex b1 = ix.dev();
+    const int64_t n1 = ix.n, m1 = ix.m;
+    const int w = n1 == 0 ? 20 : 1;
+    const int lbits = n1 == 0 ? 0 : bits_for(n1 - m1);
+    const int lshift = 3 + 3 * w;
+    const int hi_bit = lshift + lbits;
+    st = MergeStats();
+    st.n1 = n1;
+    st.m1 = m1;
+    st.n2 = n2;
+    st.m2 = m2;
+    st.key_syms = w;
+    st.sort_bits = hi_bit - 3;
+    if (hi_bit > 64) {
+        set_error(RB3_ELIMIT, "index too large for the merge key");
+        return RB3_ELIMIT;
+    }
+
+    DBuf K, stats, guardb;
+    RB3_ALLOC(K, &c, n2 * sizeof(uint64_t));
+    RB3_ALLOC(guardb, &c, sizeof(int32_t));
+    RB3_HIP(hipMemsetAsync(guardb.p, 0, sizeof(int32_t), c.stream));
+    int32_t *guard = guardb.as<int32_t>();
+    RB3_ALLOC(stats, &c, 4 * sizeof(unsigned long long));
+    RB3_HIP(hipMemsetAsync(stats.p, 0, 4 * sizeof(unsigned long long), c.stream));
+
+    // ---- 1. insertion ranks ----
+    if (n1 > 0) {
+        int64_t CL = c.chunk_len > 0 ? c.chunk_len : 4096;
+        if (CL > (1 << 30)) CL = 1 << 30;
+        std::vector<Chunk> chunks;
+        int64_t off = 0;
+        for (int64_t s = 0; s < m2; ++s) {
+            int64_t L = strand_lens[s];
+            for (int64_t t0 = 0; t0 < L; t0 += CL) {
+                int64_t t1 = t0 + CL < L ? t0 + CL : L;
+                Chunk ck;
+                ck.p0 = off + t0;
+                ck.len = (int32_t)(t1 - t0);
+                ck.last = t1 == L ? 1 : 0;
+                chunks.push_back(ck);
+            }
+            off += L + 1;
+        }
+        int64_t nch = (int64_t)chunks.size();
+        st.chunks = nch;
+        st.chunk_len = CL;
+        st.chain_steps = n2 - m2;
+        DBuf d_ch, unres, readyA, readyB, pend;
+        RB3_ALLOC(d_ch, &c, nch * sizeof(Chunk));
+        RB3_ALLOC(unres, &c, nch * sizeof(int32_t));
+        RB3_ALLOC(readyA, &c, (nch + 1) * sizeof(int32_t));
+        RB3_ALLOC(readyB, &c, (nch + 1) * sizeof(int32_t));
+        RB3_ALLOC(pend, &c, sizeof(int32_t));
+        RB3_HIP(hipMemcpyAsync(d_ch.p, chunks.data(), nch * sizeof(Chunk), hipMemcpyHostToDevice, c.stream));
+        RB3_HIP(hipMemsetAsync(readyA.p, 0, (nch + 1) * sizeof(int32_t), c.stream));
+        RB3_LAUNCH("chain", k_chain, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
+                   d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(),
+                   readyA.as<int32_t>(), stats.as<unsigned long long>());
+        unsigned long long hs[4];
+        RB3_HIP(hipMemcpyAsync(hs, stats.p, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
+        RB3_HIP(hipStreamSynchronize(c.stream));
+        st.fixup_steps = (int64_t)hs[0];
+        st.chain_steps += (int64_t)hs[1];
+        int32_t *rin = readyA.as<int32_t>(), *rout = readyB.as<int32_t>();
+        int64_t passes = 0;
+        if (hs[0] > 0) {
+            for (;;) {
+                RB3_HIP(hipMemcpyAsync(rout, rin, (nch + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                       c.stream));
+                RB3_HIP(hipMemsetAsync(pend.p, 0, sizeof(int32_t), c.stream));
+                RB3_LAUNCH("chain_fixup", k_fixup, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
+                           b1, d_Q, d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(),
+                           rin, rout, pend.as<int32_t>());
+                int32_t hp = 0;
+                RB3_HIP(hipMemcpyAsync(&hp, pend.p, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+                RB3_HIP(hipStreamSynchronize(c.stream));
+                ++passes;
+                std::swap(rin, rout);
+                if (hp == 0) break;
+                if (passes > nch + 1) {
+                    set_error(RB3_EDEVICE, "chain fix-up did not converge");
+                    return RB3_EDEVICE;
+                }
+            }
+        }
+        st.fixup_passes = passes;
+    } else {
+        RB3_LAUNCH("build_keys", k_build_keys, grid_for(n2, 256 * 4), dim3(256), 0, c.stream, d_Q, n2, w,
+                   K.as<uint64_t>());
+    }
+
+    // ---- 2. order of the new suffixes ----
+    DBuf ka, va, kb, vb;
+    RB3_ALLOC(ka, &c, n2 * sizeof(uint64_t));
+    RB3_ALLOC(kb, &c, n2 * sizeof(uint64_t));
+    RB3_ALLOC(va, &c, n2 * sizeof(uint32_t));
+    RB3_ALLOC(vb, &c, n2 * sizeof(uint32_t));
+    uint64_t *SK = nullptr;
+    uint32_t *SV = nullptr;
+    RB3_TRY(radix_sort(c, K.as<uint64_t>(), nullptr, ka.as<uint64_t>(), va.as<uint32_t>(), kb.as<uint64_t>(),
+                       vb.as<uint32_t>(), n2, 3, hi_bit, true, &SK, &SV, guard));
+    // free the other buffer pair early
+    if (SK == ka.as<uint64_t>()) {
+        kb.reset();
+        vb.reset();
+    } else {
+        ka.reset();
+        va.reset();
+    }
+
+    {
+        DBuf head, tied, idx, R, cnt;
+        RB3_ALLOC(head, &c, n2 * sizeof(uint32_t));
+        RB3_ALLOC(tied, &c, n2 * sizeof(uint32_t));
+        RB3_ALLOC(idx, &c, n2 * sizeof(uint32_t));
+        RB3_ALLOC(R, &c, n2 * sizeof(uint32_t));
+        RB3_ALLOC(cnt, &c, 4 * sizeof(uint32_t));
+        RB3_HIP(hipMemsetAsync(cnt.p, 0, 4 * sizeof(uint32_t), c.stream));
+        dim3 g = grid_for(n2, 256 * 8);
+        RB3_LAUNCH("tie_flags", k_head_flags, g, dim3(256), 0, c.stream, SK, n2, head.as<uint32_t>());
+        RB3_TRY(scan_u32(c, head.as<uint32_t>(), head.as<uint32_t>(), n2, true, true, nullptr));
+        RB3_LAUNCH("tie_rank_init", k_rank_init, g, dim3(256), 0, c.stream, SK, SV, head.as<uint32_t>(), n2,
+                   R.as<uint32_t>(), tied.as<uint32_t>());
+        uint32_t *d_tot = cnt.as<uint32_t>();
+        RB3_TRY(scan_u32(c, tied.as<uint32_t>(), idx.as<uint32_t>(), n2, false, false, d_tot));
+        uint32_t h_cnt[4];
+        RB3_HIP(hipMemcpyAsync(h_cnt, cnt.p, sizeof(h_cnt), hipMemcpyDeviceToHost, c.stream));
+        RB3_HIP(hipStreamSynchronize(c.stream));
+        int64_t A = h_cnt[0];
+        st.tied_records = A;
+        if (A > 0) {
+            DBuf apos[2], ahead[2], ags[2], agsz[2], key2, tpos, thead, tkeep, tsub, teq, nidx;
+            for (int q = 0; q < 2; ++q) {
+                RB3_ALLOC(apos[q], &c, A * sizeof(uint32_t));
+                RB3_ALLOC(ahead[q], &c, A * sizeof(uint32_t));
+                RB3_ALLOC(ags[q], &c, A * sizeof(uint32_t));
+                RB3_ALLOC(agsz[q], &c, A * sizeof(uint32_t));
+            }
+            RB3_ALLOC(key2, &c, A * sizeof(uint32_t));
+            RB3_ALLOC(tpos, &c, A * sizeof(uint32_t));
+            RB3_ALLOC(thead, &c, A * sizeof(uint32_t));
+            RB3_ALLOC(tkeep, &c, A * sizeof(uint32_t));
+            RB3_ALLOC(tsub, &c, A * sizeof(uint32_t));
+            RB3_ALLOC(teq, &c, A * sizeof(uint32_t));
+            RB3_ALLOC(nidx, &c, A * sizeof(uint32_t));
+            RB3_LAUNCH("tie_active_init", k_active_init, g, dim3(256), 0, c.stream, SK, SV, head.as<uint32_t>(),
+                       tied.as<uint32_t>(), idx.as<uint32_t>(), n2, apos[0].as<uint32_t>(),
+                       ahead[0].as<uint32_t>(), ags[0].as<uint32_t>(), agsz[0].as<uint32_t>(), d_tot + 1);
+            RB3_HIP(hipMemcpyAsync(h_cnt, cnt.p, sizeof(h_cnt), hipMemcpyDeviceToHost, c.stream));
+            RB3_HIP(hipStreamSynchronize(c.stream));
+            st.max_group = h_cnt[1];
+            if (h_cnt[1] > 65536) {
+                set_error(RB3_ELIMIT, "a group of more than 65536 new suffixes shares its sort key "
+                                      "(highly repetitive batch)");
+                return RB3_ELIMIT;
+            }
+            head.reset();
+            tied.reset();
+            idx.reset();
+            int cur = 0;
+            int64_t h = w;
+            int rounds = 0;
+            while (A > 0) {
+                dim3 ga = grid_for(A, 256 * 4);
+                RB3_LAUNCH("tie_gather", k_gather, ga, dim3(256), 0, c.stream, apos[cur].as<uint32_t>(), A,
+                           R.as<uint32_t>(), h, n2, key2.as<uint32_t>(), guard);
+                RB3_LAUNCH("tie_rerank", k_rerank, ga, dim3(256), 0, c.stream, apos[cur].as<uint32_t>(),
+                           ahead[cur].as<uint32_t>(), ags[cur].as<uint32_t>(), agsz[cur].as<uint32_t>(),
+                           key2.as<uint32_t>(), A, R.as<uint32_t>(), tpos.as<uint32_t>(),
+                           thead.as<uint32_t>(), tkeep.as<uint32_t>(), tsub.as<uint32_t>(), teq.as<uint32_t>(), guard);
+                RB3_TRY(scan_u32(c, tkeep.as<uint32_t>(), nidx.as<uint32_t>(), A, false, false, d_tot));
+                int nx = cur ^ 1;
+                RB3_LAUNCH("tie_compact", k_compact, ga, dim3(256), 0, c.stream, tpos.as<uint32_t>(),
+                           thead.as<uint32_t>(), tkeep.as<uint32_t>(), tsub.as<uint32_t>(), teq.as<uint32_t>(),
+                           nidx.as<uint32_t>(), A, apos[nx].as<uint32_t>(), ahead[nx].as<uint32_t>(),
+                           ags[nx].as<uint32_t>(), agsz[nx].as<uint32_t>(), guard);
+                RB3_HIP(hipMemcpyAsync(h_cnt, cnt.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+                RB3_HIP(hipStreamSynchronize(c.stream));
+                st.tie_work += A;
+                A = h_cnt[0];
+                cur = nx;
+                h *= 2;
+                ++rounds;
+                if (rounds > 48) {
+                    set_error(RB3_EDEVICE, "tie resolution did not terminate");
+                    return RB3_EDEVICE;
+                }
+            }
+            st.tie_rounds = rounds;
+            RB3_LAUNCH("tie_place", k_place, g, dim3(256), 0, c.stream, SV, R.as<uint32_t>(), K.as<uint64_t>(),
+                       n2, SK, guard);
+        }
+    }
+
+    // ---- 3. interleave into the merged BWT ----
+    const int64_t nout = n1 + n2;
+    const int64_t nblk_out = num_blocks(nout);
+    DBuf bcnt, out_blk, out_sb;
+    RB3_ALLOC(bcnt, &c, (nblk_out + 1) * sizeof(uint32_t));
+    RB3_HIP(hipMemsetAsync(bcnt.p, 0, (nblk_out + 1) * sizeof(uint32_t), c.stream));
+    RB3_LAUNCH("merge_block_count", k_block_count, grid_for(n2, 256 * 8), dim3(256), 0, c.stream, SK, n2, m1,
+               lshift, bcnt.as<uint32_t>());
+    RB3_TRY(scan_u32(c, bcnt.as<uint32_t>(), bcnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
+    RB3_ALLOC(out_blk, &c, nblk_out * 64);
+    RB3_ALLOC(out_sb, &c, num_superblocks(nout) * SB_STRIDE * sizeof(int64_t));
+    RB3_LAUNCH("interleave", k_interleave, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream,
+               (const uint64_t *)b1.blk, SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
+               out_blk.as<uint4>(), guard);
+    int64_t counts[6];
+    RB3_TRY(build_checkpoints(c, out_blk.as<uint4>(), nout, out_sb.as<int64_t>(), new_C, counts));
+    int32_t hg = 0;
+    RB3_HIP(hipMemcpyAsync(&hg, guard, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipStreamSynchronize(c.stream));
+    if (hg) {
+        set_error(RB3_EDEVICE, "merge: internal consistency guard tripped (mask " + std::to_string(hg) + ")");
+        return RB3_EDEVICE;
+    }
+    if (counts[0] != m1 + m2) {
+        set_error(RB3_EDEVICE, "merged BWT has the wrong number of sentinels");
+        return RB3_EDEVICE;
+    }
+    *new_blk = (uint4 *)out_blk.release();
+    *new_sb = (int64_t *)out_sb.release();
+    return RB3_OK;
+}
+
+}  // namespace rb3

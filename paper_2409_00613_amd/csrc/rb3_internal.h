@@ -1,0 +1,340 @@
+// Internal definitions shared by the HIP kernels and the host side of the
+// library. gfx950 (CDNA4) only: wave64, 64-byte index blocks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "rb3.h"
+
+namespace rb3 {
+
+// ---------------------------------------------------------------------------
+// Index layout in HBM
+// ---------------------------------------------------------------------------
+//
+// The BWT B[0..n) of codes $=0 A=1 C=2 G=3 T=4 N=5 is cut into blocks of 128
+// symbols. Block b is 64 bytes = 4 x uint4:
+//   q[0], q[1], q[2] : bit planes 0, 1, 2 of the 128 codes. As two uint64
+//                      words (lo = symbols 0..63, hi = 64..127), bit r of a
+//                      word is symbol r.
+//   q[3]             : occurrence checkpoint. The number of A, C, G, T, N in
+//                      B[S, 128 b), where S is the start of b's superblock,
+//                      as 24-bit fields at bit offsets 0, 24, 48, 72, 96 of
+//                      the 128-bit word (lo 64 bits first).
+// A superblock covers 2^24 symbols (2^17 blocks); its table entry holds eight
+// int64: entry[c] = C[c] + (occurrences of c before the superblock) for
+// c = 0..5, so C + rank is one add away. Positions past n hold code 7, which
+// matches no symbol. There are n/128 + 1 blocks, so a rank at k = n reads a
+// real block.
+//
+// One rank therefore touches one 64-byte block plus one superblock entry
+// (a table of n/2^24 * 64 bytes that stays in cache).
+constexpr int BLK_SHIFT = 7;
+constexpr int64_t BLK_SYMS = 128;
+constexpr int SB_SHIFT = 24;
+constexpr int SB_BLK_SHIFT = SB_SHIFT - BLK_SHIFT;  // blocks per superblock = 2^17
+constexpr int SB_STRIDE = 8;
+constexpr uint32_t CNT_MASK = 0xFFFFFFu;
+
+// Blocks per scan segment when checkpoints are rebuilt (divides 2^17).
+constexpr int SEG_BLKS = 1024;
+
+struct DevIndex {
+    const uint4 *blk;   // nblk * 4
+    const int64_t *sb;  // nsb * SB_STRIDE
+    int64_t n;          // BWT length (symbols, sentinels included)
+    int64_t m;          // sentinels
+    int64_t C[8];       // C[0..5], C[6] = n
+};
+
+__host__ __device__ inline int64_t num_blocks(int64_t n) { return (n >> BLK_SHIFT) + 1; }
+__host__ __device__ inline int64_t num_superblocks(int64_t n) { return (n >> SB_SHIFT) + 1; }
+
+__device__ __forceinline__ uint64_t u64_lo(const uint4 &q) {
+    return (uint64_t)q.x | ((uint64_t)q.y << 32);
+}
+__device__ __forceinline__ uint64_t u64_hi(const uint4 &q) {
+    return (uint64_t)q.z | ((uint64_t)q.w << 32);
+}
+
+// Bits of a plane word pair where the code equals sym (0..7).
+__device__ __forceinline__ uint64_t plane_match(uint64_t p0, uint64_t p1, uint64_t p2, int sym) {
+    uint64_t a = (sym & 1) ? p0 : ~p0;
+    uint64_t b = (sym & 2) ? p1 : ~p1;
+    uint64_t c = (sym & 4) ? p2 : ~p2;
+    return a & b & c;
+}
+
+__device__ __forceinline__ uint64_t low_mask(int o) {  // bits [0, o), o in [0, 64]
+    return o >= 64 ? ~0ull : ((1ull << o) - 1ull);
+}
+
+// 24-bit checkpoint field f (0..4 for A..N) of q[3].
+__device__ __forceinline__ uint32_t ckpt_field(const uint4 &q3, int f) {
+    uint64_t c0 = u64_lo(q3), c1 = u64_hi(q3);
+    uint64_t v;
+    switch (f) {
+    case 0: v = c0; break;
+    case 1: v = c0 >> 24; break;
+    case 2: v = (c0 >> 48) | (c1 << 16); break;
+    case 3: v = c1 >> 8; break;
+    default: v = c1 >> 32; break;
+    }
+    return (uint32_t)(v & CNT_MASK);
+}
+
+__device__ __forceinline__ uint4 pack_ckpt(const uint32_t c[5]) {
+    uint64_t c0 = (uint64_t)c[0] | ((uint64_t)c[1] << 24) | ((uint64_t)c[2] << 48);
+    uint64_t c1 = ((uint64_t)c[2] >> 16) | ((uint64_t)c[3] << 8) | ((uint64_t)c[4] << 32);
+    return make_uint4((uint32_t)c0, (uint32_t)(c0 >> 32), (uint32_t)c1, (uint32_t)(c1 >> 32));
+}
+
+struct Block {
+    uint4 q0, q1, q2, q3;
+};
+
+__device__ __forceinline__ Block load_block(const uint4 *blk, int64_t b) {
+    const uint4 *p = blk + (b << 2);
+    Block r;
+    r.q0 = p[0];
+    r.q1 = p[1];
+    r.q2 = p[2];
+    r.q3 = p[3];
+    return r;
+}
+
+// Occurrences of sym in the first o symbols of the block (o in [0, 128]).
+__device__ __forceinline__ int inblock_count(const Block &B, int sym, int o) {
+    uint64_t lo = plane_match(u64_lo(B.q0), u64_lo(B.q1), u64_lo(B.q2), sym);
+    if (o <= 64) return __popcll(lo & low_mask(o));
+    uint64_t hi = plane_match(u64_hi(B.q0), u64_hi(B.q1), u64_hi(B.q2), sym);
+    return __popcll(lo) + __popcll(hi & low_mask(o - 64));
+}
+
+// pi_B(a, k) = C(a) + rank_B(a, k) for a in 1..5 (Table 1), given the block
+// holding position k.
+__device__ __forceinline__ int64_t pi_from_block(const DevIndex &ix, const Block &B, int a,
+                                                 int64_t k) {
+    int o = (int)(k & (BLK_SYMS - 1));
+    return ix.sb[(k >> SB_SHIFT) * SB_STRIDE + a] + (int64_t)ckpt_field(B.q3, a - 1) +
+           inblock_count(B, a, o);
+}
+
+__device__ __forceinline__ int64_t pi_sym(const DevIndex &ix, int a, int64_t k) {
+    Block B = load_block(ix.blk, k >> BLK_SHIFT);
+    return pi_from_block(ix, B, a, k);
+}
+
+// pi_B(c, k) for every c in 0..5. rank($, k) is k minus the other ranks.
+__device__ __forceinline__ void pi_all(const DevIndex &ix, int64_t k, int64_t out[6]) {
+    Block B = load_block(ix.blk, k >> BLK_SHIFT);
+    int o = (int)(k & (BLK_SYMS - 1));
+    const int64_t *s = ix.sb + (k >> SB_SHIFT) * SB_STRIDE;
+    uint64_t l0 = u64_lo(B.q0), l1 = u64_lo(B.q1), l2 = u64_lo(B.q2);
+    uint64_t h0 = u64_hi(B.q0), h1 = u64_hi(B.q1), h2 = u64_hi(B.q2);
+    uint64_t mlo = low_mask(o < 64 ? o : 64);
+    uint64_t mhi = o > 64 ? low_mask(o - 64) : 0ull;
+    int64_t others = 0;
+    for (int a = 1; a <= 5; ++a) {
+        int cnt = __popcll(plane_match(l0, l1, l2, a) & mlo) + __popcll(plane_match(h0, h1, h2, a) & mhi);
+        out[a] = s[a] + (int64_t)ckpt_field(B.q3, a - 1) + cnt;
+        others += out[a] - ix.C[a];
+    }
+    out[0] = k - others;  // C[0] = 0
+}
+
+// ---------------------------------------------------------------------------
+// Host-side context
+// ---------------------------------------------------------------------------
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    rb3_alloc_fn alloc = nullptr;
+    rb3_free_fn free_fn = nullptr;
+    void *alloc_ctx = nullptr;
+    int64_t chunk_len = 0;
+    int32_t both = 1;
+    // Frees are deferred until flush(), called after the stream has drained,
+    // so that a caching allocator never hands out memory a queued kernel
+    // still uses.
+    std::vector<void *> deferred;
+
+    void *dmalloc(size_t bytes);
+    void dfree(void *p) { if (p) deferred.push_back(p); }
+    void free_now(void *p);
+    int flush();  // synchronize the stream, then release deferred buffers
+};
+
+// RAII device buffer owned through a Ctx.
+struct DBuf {
+    Ctx *ctx = nullptr;
+    void *p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { reset(); }
+    void reset() {
+        if (p && ctx) ctx->dfree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // returns false on allocation failure
+    bool alloc(Ctx *c, size_t nbytes) {
+        reset();
+        ctx = c;
+        bytes = nbytes;
+        p = c->dmalloc(nbytes ? nbytes : 16);
+        return p != nullptr;
+    }
+    void *release() {
+        void *r = p;
+        p = nullptr;
+        return r;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+// Consistency guards: kernels that index through computed positions check
+// them and set a bit here instead of touching memory out of range.
+enum {
+    GUARD_SORT = 1,
+    GUARD_GATHER = 2,
+    GUARD_RERANK = 4,
+    GUARD_COMPACT = 8,
+    GUARD_INTERLEAVE = 16,
+    GUARD_PLACE = 32
+};
+
+// Error state: thread-local message for rb3_strerror.
+void set_error(int code, const std::string &msg);
+
+// A failed HIP call: record and return RB3_EDEVICE.
+#define RB3_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t _e = (call);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            ::rb3::set_error(RB3_EDEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
+            return RB3_EDEVICE;                                                        \
+        }                                                                              \
+    } while (0)
+
+#define RB3_TRY(expr)          \
+    do {                       \
+        int _r = (expr);       \
+        if (_r != RB3_OK) return _r; \
+    } while (0)
+
+#define RB3_ALLOC(buf, ctx, nbytes)                                                    \
+    do {                                                                               \
+        if (!(buf).alloc((ctx), (nbytes))) {                                           \
+            ::rb3::set_error(RB3_ENOMEM, "device allocation failed (" #buf ")");       \
+            return RB3_ENOMEM;                                                         \
+        }                                                                              \
+    } while (0)
+
+// Kernel-launch profiling (events around launches when enabled).
+struct ProfScope {
+    const char *name;
+    hipStream_t stream;
+    void *ev0 = nullptr;
+    ProfScope(const char *nm, hipStream_t s);
+    ~ProfScope();
+};
+
+int check_launch(const char *name);
+
+#define RB3_LAUNCH(name, kernel, grid, block, shmem, stream, ...)                      \
+    do {                                                                               \
+        ::rb3::ProfScope _ps(name, stream);                                            \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);           \
+        RB3_TRY(::rb3::check_launch(name));                                            \
+    } while (0)
+
+// Grid for a grid-stride loop over `work` items with `per_block` items/block.
+inline dim3 grid_for(int64_t work, int64_t per_block, int64_t cap = 1 << 20) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return dim3((unsigned)g);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers implemented in the .hip files
+// ---------------------------------------------------------------------------
+
+// index.hip
+int encode_strands(Ctx &c, const uint8_t *d_seq, const int64_t *lens, int64_t n_in, int32_t both,
+                   uint8_t *d_Q, int64_t n_out, int32_t *d_err);
+int encode_plain(Ctx &c, const uint8_t *d_seq, const int64_t *lens, int64_t n_in, uint8_t *d_codes,
+                 int64_t total, int32_t *d_err);
+int pack_codes(Ctx &c, const uint8_t *d_codes, int64_t n, uint4 *d_blk);
+int build_checkpoints(Ctx &c, uint4 *d_blk, int64_t n, int64_t *d_sb, int64_t C_out[6],
+                      int64_t counts_out[6]);
+int unpack_codes(Ctx &c, const DevIndex &ix, uint8_t *d_codes);
+int check_codes(Ctx &c, const uint8_t *d_codes, int64_t n, int32_t *d_err);
+
+// scan.hip
+int scan_u32(Ctx &c, const uint32_t *d_in, uint32_t *d_out, int64_t n, bool inclusive,
+             bool max_op, uint32_t *d_total);
+
+// sort.hip: stable LSD radix sort of (key, value) by key bits [lo_bit, hi_bit).
+// If vals_in is null the values are the input indices. Result lands in
+// (*k_res, *v_res), one of the two buffer pairs.
+// The input pair (k_in, v_in) is left untouched.
+int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *v_a, uint64_t *k_b,
+               uint32_t *v_b, int64_t n, int lo_bit, int hi_bit, bool iota_vals, uint64_t **k_res,
+               uint32_t **v_res, int32_t *d_guard);
+
+// merge.hip
+struct MergeStats {
+    int64_t n1 = 0, m1 = 0, n2 = 0, m2 = 0;
+    int64_t chunks = 0, chunk_len = 0;
+    int64_t chain_steps = 0;      // rank steps in the chain phase (point + interval)
+    int64_t fixup_steps = 0;      // rank steps replayed by fix-up passes
+    int64_t fixup_passes = 0;
+    int64_t key_syms = 0;         // symbols per initial sort key
+    int64_t sort_bits = 0;
+    int64_t tied_records = 0;     // records in non-singleton groups after the sort
+    int64_t tie_rounds = 0;
+    int64_t tie_work = 0;         // sum over rounds of active records
+    int64_t max_group = 0;
+};
+
+struct IndexData {
+    Ctx ctx;
+    int64_t n = 0, m = 0;
+    int64_t C[6] = {0, 0, 0, 0, 0, 0};
+    uint4 *blk = nullptr;  // owned
+    int64_t *sb = nullptr; // owned
+    MergeStats last;
+    DevIndex dev() const {
+        DevIndex d;
+        d.blk = blk;
+        d.sb = sb;
+        d.n = n;
+        d.m = m;
+        for (int i = 0; i < 6; ++i) d.C[i] = C[i];
+        d.C[6] = n;
+        d.C[7] = 0;
+        return d;
+    }
+};
+
+int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_lens, int64_t m2,
+               int64_t n2, uint4 **new_blk, int64_t **new_sb, int64_t new_C[6], MergeStats &st);
+
+// query.hip
+int count_queries(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *d_qoff,
+                  int64_t nq, int64_t *d_lo, int64_t *d_hi);
+int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *d_qoff, int64_t nq,
+             int32_t min_len, int64_t min_occ, int64_t cap, rb3_smem_t *d_tmp, rb3_smem_t *d_out,
+             uint32_t *d_cnt, uint32_t *d_off, unsigned long long *d_total, int64_t *h_total);
+
+}  // namespace rb3

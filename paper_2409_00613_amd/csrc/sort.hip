@@ -1,0 +1,152 @@
+// Stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit digits.
+//
+// Per pass: (1) per-tile digit histograms in LDS, (2) one exclusive scan of
+// the digit-major histogram table, (3) a stable scatter. In the scatter each
+// wave owns a contiguous run of 1024 keys of the tile and ranks keys with
+// equal digits inside a 64-key step by matching the digit with 8 ballots, so
+// no cross-wave synchronisation is needed inside the scatter loop.
+#include "rb3_internal.h"
+
+namespace rb3 {
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_STEPS = 16;                       // 64-key steps per wave
+constexpr int RS_WAVE_KEYS = 64 * RS_STEPS;        // 1024
+constexpr int RS_TILE = RS_WAVES * RS_WAVE_KEYS;   // 4096
+
+__global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t dmask,
+                          uint32_t *__restrict__ H, int64_t ntiles) {
+    __shared__ uint32_t h[RS_WAVES][256];
+    int tid = threadIdx.x, wave = tid >> 6;
+    for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int i = 0; i < RS_TILE / RS_THREADS; ++i) {
+        int64_t idx = base + (int64_t)i * RS_THREADS + tid;
+        if (idx < n) atomicAdd(&h[wave][(uint32_t)(keys[idx] >> shift) & dmask], 1u);
+    }
+    __syncthreads();
+    for (int d = tid; d < 256; d += RS_THREADS)
+        H[(int64_t)d * ntiles + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    // number of set bits of mask below this lane
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                             int iota, int64_t n, int shift, uint32_t dmask, int dbits,
+                             const uint32_t *__restrict__ O, int64_t ntiles, uint64_t *__restrict__ kout,
+                             uint32_t *__restrict__ vout, int32_t *__restrict__ guard) {
+    __shared__ uint32_t wbase[RS_WAVES][256];
+    int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&wbase[0][0])[i] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)wave * RS_WAVE_KEYS;
+    uint64_t k[RS_STEPS];
+    uint32_t v[RS_STEPS];
+    for (int j = 0; j < RS_STEPS; ++j) {
+        int64_t idx = base + j * 64 + lane;
+        if (idx < n) {
+            k[j] = kin[idx];
+            v[j] = iota ? (uint32_t)idx : vin[idx];
+            atomicAdd(&wbase[wave][(uint32_t)(k[j] >> shift) & dmask], 1u);
+        } else {
+            k[j] = 0;
+            v[j] = 0;
+        }
+    }
+    __syncthreads();
+    // per digit: global offset of this tile, then the waves in order
+    for (int d = tid; d < 256; d += RS_THREADS) {
+        uint32_t run = O[(int64_t)d * ntiles + blockIdx.x];
+        for (int w = 0; w < RS_WAVES; ++w) {
+            uint32_t t = wbase[w][d];
+            wbase[w][d] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < RS_STEPS; ++j) {
+        int64_t idx = base + j * 64 + lane;
+        bool valid = idx < n;
+        uint32_t d = (uint32_t)(k[j] >> shift) & dmask;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < dbits; ++b) {
+            uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        uint32_t r = lane_rank(peers);
+        uint32_t pos = 0;
+        if (valid) pos = wbase[wave][d] + r;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (valid) {
+            if ((int64_t)pos < n) {
+                kout[pos] = k[j];
+                vout[pos] = v[j];
+            } else {
+                atomicOr(guard, 1);
+            }
+            if (r == 0) wbase[wave][d] = pos + (uint32_t)__popcll(peers);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *v_a, uint64_t *k_b,
+               uint32_t *v_b, int64_t n, int lo_bit, int hi_bit, bool iota_vals, uint64_t **k_res,
+               uint32_t **v_res, int32_t *d_guard) {
+    if (n >= (int64_t)UINT32_MAX) {
+        set_error(RB3_ELIMIT, "radix sort: too many records");
+        return RB3_ELIMIT;
+    }
+    int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    DBuf H;
+    RB3_ALLOC(H, &c, 256 * (ntiles > 0 ? ntiles : 1) * sizeof(uint32_t));
+    const uint64_t *src_k = k_in;
+    const uint32_t *src_v = v_in;
+    bool iota = iota_vals;
+    uint64_t *dk = k_a;
+    uint32_t *dv = v_a;
+    if (hi_bit <= lo_bit || n == 0) {
+        // nothing to sort: copy through
+        RB3_HIP(hipMemcpyAsync(k_a, k_in, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, c.stream));
+        if (iota) {
+            set_error(RB3_EINVAL, "radix sort: empty key range with implicit values");
+            return RB3_EINVAL;
+        }
+        RB3_HIP(hipMemcpyAsync(v_a, v_in, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, c.stream));
+        *k_res = k_a;
+        *v_res = v_a;
+        return RB3_OK;
+    }
+    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
+        int dbits = hi_bit - shift < 8 ? hi_bit - shift : 8;
+        uint32_t dmask = (1u << dbits) - 1u;
+        RB3_LAUNCH("sort_hist", k_rs_hist, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, c.stream, src_k, n,
+                   shift, dmask, H.as<uint32_t>(), ntiles);
+        RB3_TRY(scan_u32(c, H.as<uint32_t>(), H.as<uint32_t>(), 256 * ntiles, false, false, nullptr));
+        RB3_LAUNCH("sort_scatter", k_rs_scatter, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, c.stream,
+                   src_k, src_v, (int)iota, n, shift, dmask, dbits, H.as<uint32_t>(), ntiles, dk, dv, d_guard);
+        src_k = dk;
+        src_v = dv;
+        iota = false;
+        if (dk == k_a) {
+            dk = k_b;
+            dv = v_b;
+        } else {
+            dk = k_a;
+            dv = v_a;
+        }
+    }
+    *k_res = (uint64_t *)src_k;
+    *v_res = (uint32_t *)src_v;
+    return RB3_OK;
+}
+
+}  // namespace rb3

@@ -1,0 +1,329 @@
+"""Thin Python binding of librb3.so (the C ABI of include/rb3.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. The binding refuses to work without the built library; there is no
+CPU fallback. Names follow the C ABI (rb3_build, rb3_merge, rb3_count,
+rb3_smem, ...); ``Index`` wraps the opaque handle.
+
+Strings are passed as one concatenated uint8 buffer plus int64 lengths. The
+buffer may be a numpy array (host memory) or a torch tensor on the GPU
+(device memory, RB3_MEM_DEVICE); lengths are always host arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librb3.so")
+
+RB3_OK, RB3_EINVAL, RB3_ENOMEM, RB3_EDEVICE, RB3_ENOSPC, RB3_ELIMIT = 0, -1, -2, -3, -4, -5
+RB3_MEM_HOST, RB3_MEM_DEVICE = 0, 1
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("both_strands", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p), ("chunk_len", ctypes.c_int64)]
+
+
+class SmemRec(ctypes.Structure):
+    _fields_ = [("start", ctypes.c_int64), ("end", ctypes.c_int64), ("occ", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("krc", ctypes.c_int64), ("qid", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+SMEM_DTYPE = np.dtype([("start", np.int64), ("end", np.int64), ("occ", np.int64), ("k", np.int64),
+                       ("krc", np.int64), ("qid", np.int32), ("pad", np.int32)])
+assert SMEM_DTYPE.itemsize == ctypes.sizeof(SmemRec) == 48
+
+# Every function declared in include/rb3.h.
+EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_info",
+           "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
+           "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats"]
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class RB3Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rb3 error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load librb3.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2409_00613_amd.build` (hipcc, gfx950)")
+    # torch carries its own HIP runtime under the same soname; load it first
+    # so that the library binds to that one copy and shares its device
+    # memory and streams (two runtimes in one process do not see each other)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    L.rb3_opts_init.argtypes = [ctypes.POINTER(Opts)]
+    L.rb3_opts_init.restype = None
+    L.rb3_build.argtypes = [ctypes.POINTER(Opts), _vp, _i64p, _i64, _i32, ctypes.POINTER(_vp)]
+    L.rb3_merge.argtypes = [_vp, _vp, _i64p, _i64, _i32]
+    L.rb3_count.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p]
+    L.rb3_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, ctypes.POINTER(SmemRec), _i64, _i64p]
+    L.rb3_info.argtypes = [_vp, _i64p, _i64p, _i64p]
+    L.rb3_export.argtypes = [_vp, _vp]
+    L.rb3_import.argtypes = [ctypes.POINTER(Opts), _vp, _i64, _i32, ctypes.POINTER(_vp)]
+    L.rb3_clone.argtypes = [_vp, ctypes.POINTER(_vp)]
+    L.rb3_index_free.argtypes = [_vp]
+    L.rb3_index_free.restype = None
+    L.rb3_strerror.argtypes = [ctypes.c_int]
+    L.rb3_strerror.restype = ctypes.c_char_p
+    L.rb3_prof_enable.argtypes = [ctypes.c_int]
+    L.rb3_prof_reset.argtypes = []
+    L.rb3_prof_read.argtypes = [ctypes.c_char_p, _i64p, ctypes.POINTER(ctypes.c_double), _i64, _i64p]
+    L.rb3_merge_stats.argtypes = [_vp, ctypes.c_char_p, _i64p, _i64, _i64p]
+    for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_info", "rb3_export",
+                 "rb3_import", "rb3_clone", "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read",
+                 "rb3_merge_stats"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != RB3_OK:
+        raise RB3Error(rc, lib().rb3_strerror(rc).decode())
+
+
+def _buffer(x):
+    """(pointer, nbytes, mem, keepalive) of a uint8 host array or GPU tensor."""
+    if hasattr(x, "is_cuda") and hasattr(x, "data_ptr"):
+        if x.is_cuda:
+            if x.element_size() != 1 or not x.is_contiguous():
+                raise ValueError("device buffer must be a contiguous uint8 tensor")
+            # the library may run on its own stream: make the producer's
+            # writes visible first
+            import torch
+            torch.cuda.current_stream(x.device).synchronize()
+            return x.data_ptr(), x.numel(), RB3_MEM_DEVICE, x
+        x = x.numpy()
+    if isinstance(x, (bytes, bytearray)):
+        x = np.frombuffer(x, dtype=np.uint8)
+    a = np.ascontiguousarray(x, dtype=np.uint8)
+    return (a.ctypes.data if a.size else None), a.size, RB3_MEM_HOST, a
+
+
+def _lens(lens):
+    a = np.ascontiguousarray(np.asarray(lens, dtype=np.int64))
+    return a, a.ctypes.data_as(_i64p)
+
+
+class TorchAllocator:
+    """Device allocator hooks backed by torch's caching allocator."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+
+        def _alloc(nbytes, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:
+                return None
+
+        def _free(ptr, ctx):
+            if ptr:
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc_fn = _ALLOC_FN(_alloc)
+        self.free_fn = _FREE_FN(_free)
+
+
+def make_opts(both_strands: bool = True, device: int = 0, stream=None, allocator: TorchAllocator | None = None,
+              chunk_len: int = 0) -> Opts:
+    o = Opts()
+    lib().rb3_opts_init(ctypes.byref(o))
+    o.both_strands = 1 if both_strands else 0
+    o.device = device
+    if stream is not None:
+        o.stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    elif allocator is not None:
+        o.stream = allocator.stream.cuda_stream
+    if allocator is not None:
+        o.dev_alloc = allocator.alloc_fn
+        o.dev_free = allocator.free_fn
+    o.chunk_len = int(chunk_len)
+    return o
+
+
+class Index:
+    """An rb3_index handle (device-resident BWT)."""
+
+    def __init__(self, handle, keep=()):
+        self._h = ctypes.c_void_p(handle)
+        self._keep = list(keep)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().rb3_index_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # --- calls ---------------------------------------------------------------
+    def merge(self, seq, lens):
+        return rb3_merge(self, seq, lens)
+
+    def count(self, q, qlens):
+        return rb3_count(self, q, qlens)
+
+    def smem(self, q, qlens, min_len: int, min_occ: int = 1, cap: int | None = None):
+        return rb3_smem(self, q, qlens, min_len, min_occ, cap)
+
+    def info(self):
+        return rb3_info(self)
+
+    def export(self) -> np.ndarray:
+        return rb3_export(self)
+
+    def clone(self) -> "Index":
+        return rb3_clone(self)
+
+    def merge_stats(self) -> dict:
+        return rb3_merge_stats(self)
+
+
+def rb3_build(seq, lens, both_strands: bool = True, device: int = 0, stream=None,
+              allocator: TorchAllocator | None = None, chunk_len: int = 0) -> Index:
+    o = make_opts(both_strands, device, stream, allocator, chunk_len)
+    ptr, _, mem, keep = _buffer(seq)
+    la, lp = _lens(lens)
+    h = ctypes.c_void_p()
+    _check(lib().rb3_build(ctypes.byref(o), ptr, lp, la.shape[0], mem, ctypes.byref(h)))
+    return Index(h.value, keep=[o, allocator])
+
+
+def rb3_merge(idx: Index, seq, lens) -> None:
+    ptr, _, mem, keep = _buffer(seq)
+    la, lp = _lens(lens)
+    _check(lib().rb3_merge(idx.handle, ptr, lp, la.shape[0], mem))
+
+
+def rb3_count(idx: Index, q, qlens):
+    ptr, _, mem, keep = _buffer(q)
+    la, lp = _lens(qlens)
+    n = la.shape[0]
+    lo = np.zeros(max(n, 1), np.int64)
+    hi = np.zeros(max(n, 1), np.int64)
+    _check(lib().rb3_count(idx.handle, ptr, lp, n, mem, lo.ctypes.data_as(_i64p), hi.ctypes.data_as(_i64p)))
+    return lo[:n], hi[:n]
+
+
+def rb3_smem(idx: Index, q, qlens, min_len: int, min_occ: int = 1, cap: int | None = None):
+    """Returns (records, offsets): records is a structured array (SMEM_DTYPE);
+    query i owns records[offsets[i]:offsets[i+1]]."""
+    ptr, _, mem, keep = _buffer(q)
+    la, lp = _lens(qlens)
+    n = la.shape[0]
+    if cap is None:
+        cap = max(1024, int(la.sum()) // 16 + 16 * n)
+    while True:
+        out = np.zeros(max(cap, 1), dtype=SMEM_DTYPE)
+        off = np.zeros(n + 1, np.int64)
+        rc = lib().rb3_smem(idx.handle, ptr, lp, n, mem, int(min_len), int(min_occ),
+                            out.ctypes.data_as(ctypes.POINTER(SmemRec)), cap, off.ctypes.data_as(_i64p))
+        if rc == RB3_ENOSPC:
+            cap = int(off[-1])
+            continue
+        _check(rc)
+        return out[:off[-1]], off
+
+
+def rb3_info(idx: Index):
+    n = ctypes.c_int64()
+    m = ctypes.c_int64()
+    C = (ctypes.c_int64 * 6)()
+    _check(lib().rb3_info(idx.handle, ctypes.byref(n), ctypes.byref(m), C))
+    return n.value, m.value, list(C)
+
+
+def rb3_export(idx: Index) -> np.ndarray:
+    n, _, _ = rb3_info(idx)
+    out = np.zeros(max(n, 1), np.uint8)
+    _check(lib().rb3_export(idx.handle, out.ctypes.data))
+    return out[:n]
+
+
+def rb3_import(codes, both_strands: bool = True, device: int = 0, stream=None,
+               allocator: TorchAllocator | None = None) -> Index:
+    o = make_opts(both_strands, device, stream, allocator)
+    ptr, nbytes, mem, keep = _buffer(codes)
+    h = ctypes.c_void_p()
+    _check(lib().rb3_import(ctypes.byref(o), ptr, nbytes, mem, ctypes.byref(h)))
+    return Index(h.value, keep=[o, allocator])
+
+
+def rb3_clone(idx: Index) -> Index:
+    h = ctypes.c_void_p()
+    _check(lib().rb3_clone(idx.handle, ctypes.byref(h)))
+    return Index(h.value, keep=list(idx._keep))
+
+
+def rb3_merge_stats(idx: Index) -> dict:
+    cap = 64
+    keys = ctypes.create_string_buffer(32 * cap)
+    vals = np.zeros(cap, np.int64)
+    n = ctypes.c_int64()
+    _check(lib().rb3_merge_stats(idx.handle, keys, vals.ctypes.data_as(_i64p), cap, ctypes.byref(n)))
+    raw = keys.raw
+    return {raw[i * 32:(i + 1) * 32].split(b"\0")[0].decode(): int(vals[i]) for i in range(min(n.value, cap))}
+
+
+def rb3_prof_enable(on: bool = True):
+    _check(lib().rb3_prof_enable(1 if on else 0))
+
+
+def rb3_prof_reset():
+    _check(lib().rb3_prof_reset())
+
+
+def rb3_prof_read() -> dict:
+    """{kernel name: (launches, total ms)} since the last reset."""
+    cap = 256
+    names = ctypes.create_string_buffer(32 * cap)
+    launches = np.zeros(cap, np.int64)
+    ms = np.zeros(cap, np.float64)
+    n = ctypes.c_int64()
+    _check(lib().rb3_prof_read(names, launches.ctypes.data_as(_i64p),
+                               ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap, ctypes.byref(n)))
+    raw = names.raw
+    return {raw[i * 32:(i + 1) * 32].split(b"\0")[0].decode(): (int(launches[i]), float(ms[i]))
+            for i in range(min(n.value, cap))}
