@@ -295,15 +295,609 @@ __global__ void k_place(const uint32_t *__restrict__ SV, const uint32_t *__restr
 }
 
 // ---------------------------------------------------------------------------
+// Tie resolution by symbol-aware refinement
+// ---------------------------------------------------------------------------
+//
+// The suffixes of one tied group occupy consecutive rows of the merged BWT,
+// and the rows only record each suffix's BWT symbol (bits 0..2 of its key).
+// So the order inside a group matters only between members whose symbols
+// differ. k_tie_groups lists the groups whose symbols are not all equal;
+// k_tie_walk sorts each of them by comparing the keys of the following
+// positions, depth by depth (the definition of suffix order on the key
+// sequence), and stops refining a subgroup as soon as its symbols agree.
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t t = __shfl_xor(v, o);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+// Each workgroup scans a contiguous range of the sorted keys; group starts
+// in the range measure their group, and the groups whose members carry
+// different symbols are appended, by size class (2 members, 3..8, more),
+// to three lists with one atomic per class per workgroup. Each list entry
+// is (first sorted index, member count).
+constexpr int TG_THREADS = 256;
+constexpr int TG_ITEMS = 8;
+constexpr int TG_CLASSES = 3;
+
+__device__ __forceinline__ int group_class(uint32_t k) { return k == 2 ? 0 : (k <= 8 ? 1 : 2); }
+
+__global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__restrict__ SK, int64_t n,
+                                                           uint32_t *__restrict__ l0, uint32_t *__restrict__ l1,
+                                                           uint32_t *__restrict__ l2,
+                                                           uint32_t *__restrict__ gstat,
+                                                           unsigned long long *__restrict__ tied) {
+    __shared__ uint32_t wcnt[TG_CLASSES][TG_THREADS / 64];
+    __shared__ uint64_t wtied[TG_THREADS / 64];
+    __shared__ uint32_t wmax[TG_THREADS / 64];
+    __shared__ uint32_t base_slot[TG_CLASSES];
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t *lists[TG_CLASSES] = {l0, l1, l2};
+    const int64_t per_block = (int64_t)TG_THREADS * TG_ITEMS;
+    for (int64_t blk0 = blockIdx.x * per_block; blk0 < n; blk0 += (int64_t)gridDim.x * per_block) {
+        uint32_t my_s[TG_ITEMS], my_k[TG_ITEMS];
+        uint32_t nmine = 0, kmax = 0;
+        uint32_t ncls[TG_CLASSES] = {0, 0, 0};
+        uint64_t ntied = 0;
+        for (int it = 0; it < TG_ITEMS; ++it) {
+            int64_t s = blk0 + (int64_t)it * TG_THREADS + threadIdx.x;
+            if (s >= n || !starts_group(SK, s)) continue;
+            uint64_t key = SK[s] >> 3;
+            if ((key & 7) == 0) continue;
+            uint32_t e0 = (uint32_t)(SK[s] & 7);
+            bool uni = true;
+            int64_t t = s + 1;
+            while (t < n && (SK[t] >> 3) == key) {
+                uni &= (uint32_t)(SK[t] & 7) == e0;
+                ++t;
+            }
+            int64_t k = t - s;
+            if (k < 2) continue;
+            ntied += (uint64_t)k;
+            if (!uni) {
+                uint32_t kk = (uint32_t)(k > 0xFFFFFFFFll ? 0xFFFFFFFFll : k);
+                my_s[nmine] = (uint32_t)s;
+                my_k[nmine] = kk;
+                ++nmine;
+                ncls[group_class(kk)] += 1;
+                kmax = kk > kmax ? kk : kmax;
+            }
+        }
+        uint32_t incl[TG_CLASSES];
+        for (int c = 0; c < TG_CLASSES; ++c) {
+            incl[c] = ncls[c];
+            for (int d = 1; d < 64; d <<= 1) {
+                uint32_t t = __shfl_up(incl[c], d);
+                if (lane >= d) incl[c] += t;
+            }
+        }
+        uint64_t wt = wave_sum_u64(ntied);
+        uint32_t wm = wave_max_u32(kmax);
+        if (lane == 63)
+            for (int c = 0; c < TG_CLASSES; ++c) wcnt[c][wv] = incl[c];
+        if (lane == 0) {
+            wtied[wv] = wt;
+            wmax[wv] = wm;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t mx = 0;
+            uint64_t tt = 0;
+            for (int w = 0; w < TG_THREADS / 64; ++w) {
+                tt += wtied[w];
+                mx = wmax[w] > mx ? wmax[w] : mx;
+            }
+            for (int c = 0; c < TG_CLASSES; ++c) {
+                uint32_t tot = 0;
+                for (int w = 0; w < TG_THREADS / 64; ++w) tot += wcnt[c][w];
+                base_slot[c] = tot ? atomicAdd(&gstat[c], tot) : 0u;
+            }
+            if (tt) atomicAdd(tied, (unsigned long long)tt);
+            if (mx) atomicMax(&gstat[3], mx);
+        }
+        __syncthreads();
+        uint32_t pre[TG_CLASSES];
+        for (int c = 0; c < TG_CLASSES; ++c) {
+            pre[c] = base_slot[c] + incl[c] - ncls[c];
+            for (int w = 0; w < wv; ++w) pre[c] += wcnt[c][w];
+        }
+        for (uint32_t i = 0; i < nmine; ++i) {
+            int c = group_class(my_k[i]);
+            uint32_t slot = pre[c]++;
+            lists[c][2 * (int64_t)slot] = my_s[i];
+            lists[c][2 * (int64_t)slot + 1] = my_k[i];
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int WALK_MAXK = 64;
+constexpr int WALK_DEPTHS = 16;
+
+
+constexpr int SMALL_MAXK = 8;
+constexpr int SMALL_DEPTHS = 4;
+constexpr int LANES_WG = 256;
+constexpr int LANES_MAX_DEPTH = 128;
+
+// Groups of 2..8 members, one lane per group, persistent: a lane that has
+// ordered its group takes the next one from a shared queue (one atomic per
+// wave refill), so no lane idles while a neighbour walks a deep group. The
+// queue is the pair list (entries 0..np) followed by the 3..8 list. Members
+// are held in registers; every loop over them is unrolled.
+__global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restrict__ K, int64_t n2,
+                                                        const uint32_t *__restrict__ SV,
+                                                        const uint32_t *__restrict__ plist, int64_t np,
+                                                        const uint32_t *__restrict__ slist, int64_t ns,
+                                                        uint32_t *__restrict__ qhead,
+                                                        uint32_t *__restrict__ dlist, uint32_t *__restrict__ dcount,
+                                                        uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
+                                                        unsigned long long *__restrict__ reads) {
+    const int lane = threadIdx.x & 63;
+    const int64_t total = np + ns;
+    uint64_t steps = 0;
+    uint32_t maxdepth = 0;
+    bool busy = false, exhausted = false;
+    uint32_t gs = 0;
+    int k = 0;
+    int64_t d0 = 1;
+    uint32_t pos[SMALL_MAXK], e[SMALL_MAXK], o[SMALL_MAXK], sub[SMALL_MAXK];
+    bool act[SMALL_MAXK];
+#pragma unroll
+    for (int i = 0; i < SMALL_MAXK; ++i) {
+        pos[i] = e[i] = o[i] = sub[i] = 0;
+        act[i] = false;
+    }
+    for (;;) {
+        uint64_t idle = __ballot(!busy);
+        if (idle && !exhausted) {
+            uint32_t nidle = (uint32_t)__popcll(idle);
+            uint32_t base = 0;
+            if (lane == __ffsll((unsigned long long)idle) - 1) base = atomicAdd(qhead, nidle);
+            base = __shfl(base, __ffsll((unsigned long long)idle) - 1);
+            if ((int64_t)base + nidle >= total) exhausted = true;
+            if (!busy) {
+                int64_t slot = (int64_t)base + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+                if (slot < total) {
+                    const uint32_t *ent = slot < np ? plist + 2 * slot : slist + 2 * (slot - np);
+                    gs = ent[0];
+                    k = (int)ent[1];
+                    if (k > SMALL_MAXK) {
+                        atomicOr(guard, GUARD_RERANK);
+                    } else {
+                        busy = true;
+                        d0 = 1;
+#pragma unroll
+                        for (int i = 0; i < SMALL_MAXK; ++i) {
+                            pos[i] = i < k ? SV[gs + i] : 0u;
+                            o[i] = (uint32_t)i;
+                            sub[i] = 0;
+                            act[i] = i < k;
+                        }
+#pragma unroll
+                        for (int i = 0; i < SMALL_MAXK; ++i) e[i] = i < k ? (uint32_t)(K[pos[i]] & 7) : 0u;
+                    }
+                }
+            }
+        }
+        if (__ballot(busy) == 0) break;
+        if (!busy) continue;
+        // one batch of depths for this lane's group
+        uint64_t kv[SMALL_MAXK][SMALL_DEPTHS];
+#pragma unroll
+        for (int i = 0; i < SMALL_MAXK; ++i)
+#pragma unroll
+            for (int t = 0; t < SMALL_DEPTHS; ++t) {
+                int64_t q = (int64_t)pos[i] + d0 + t;
+                kv[i][t] = (act[i] && q < n2) ? K[q] : ~0ull;
+            }
+        bool any = true;
+#pragma unroll
+        for (int t = 0; t < SMALL_DEPTHS; ++t) {
+            if (!any) break;
+            uint64_t c[SMALL_MAXK];
+            uint32_t tb[SMALL_MAXK];
+#pragma unroll
+            for (int i = 0; i < SMALL_MAXK; ++i) {
+                c[i] = kv[i][t] >> 3;
+                tb[i] = 0;
+                if (act[i]) {
+                    ++steps;
+                    if (kv[i][t] == ~0ull) {
+                        atomicOr(guard, GUARD_RERANK);
+                        act[i] = false;
+                    } else if ((c[i] & 7) == 0) {
+                        // a key holding its sentinel is unique: position order
+                        tb[i] = pos[i] + (uint32_t)(d0 + t);
+                    }
+                }
+            }
+            bool split = false;
+#pragma unroll
+            for (int i = 0; i < SMALL_MAXK; ++i)
+#pragma unroll
+                for (int j = i + 1; j < SMALL_MAXK; ++j)
+                    split |= act[i] && act[j] && sub[i] == sub[j] && (c[i] != c[j] || tb[i] != tb[j]);
+            if (!split) continue;
+            uint32_t no[SMALL_MAXK], nsb[SMALL_MAXK];
+#pragma unroll
+            for (int i = 0; i < SMALL_MAXK; ++i) {
+                uint32_t less = 0, eqb = 0;
+#pragma unroll
+                for (int j = 0; j < SMALL_MAXK; ++j) {
+                    bool same = act[i] && act[j] && sub[j] == sub[i];
+                    bool lt_ = c[j] < c[i] || (c[j] == c[i] && tb[j] < tb[i]);
+                    bool eq_ = c[j] == c[i] && tb[j] == tb[i];
+                    less += (same && lt_) ? 1u : 0u;
+                    eqb += (same && eq_ && o[j] < o[i]) ? 1u : 0u;
+                }
+                no[i] = act[i] ? sub[i] + less + eqb : o[i];
+                nsb[i] = act[i] ? sub[i] + less : sub[i];
+            }
+            bool nact[SMALL_MAXK];
+            any = false;
+#pragma unroll
+            for (int i = 0; i < SMALL_MAXK; ++i) {
+                uint32_t cnt = 0;
+                bool uni = true;
+#pragma unroll
+                for (int j = 0; j < SMALL_MAXK; ++j) {
+                    bool same = act[j] && nsb[j] == nsb[i];
+                    cnt += same ? 1u : 0u;
+                    uni &= !same || e[j] == e[i];
+                }
+                nact[i] = act[i] && cnt >= 2 && !uni;
+                any |= nact[i];
+            }
+#pragma unroll
+            for (int i = 0; i < SMALL_MAXK; ++i) {
+                o[i] = no[i];
+                sub[i] = nsb[i];
+                act[i] = nact[i];
+            }
+        }
+        d0 += SMALL_DEPTHS;
+        if (!any) {
+#pragma unroll
+            for (int i = 0; i < SMALL_MAXK; ++i)
+                if (i < k) SK[gs + o[i]] = K[pos[i]];
+            busy = false;
+            maxdepth = (uint32_t)d0 > maxdepth ? (uint32_t)d0 : maxdepth;
+        }
+        // a group still mixed after LANES_MAX_DEPTH goes to the deep walk
+        bool evict = busy && d0 > LANES_MAX_DEPTH;
+        uint64_t em = __ballot(evict);
+        if (em) {
+            int first = __ffsll((unsigned long long)em) - 1;
+            uint32_t b = 0;
+            if (lane == first) b = atomicAdd(dcount, (uint32_t)__popcll(em));
+            b = __shfl(b, first);
+            if (evict) {
+                uint32_t slot = b + __builtin_amdgcn_mbcnt_hi((uint32_t)(em >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)em, 0u));
+                dlist[2 * (int64_t)slot] = gs;
+                dlist[2 * (int64_t)slot + 1] = (uint32_t)k;
+                busy = false;
+            }
+        }
+    }
+    uint64_t tot = wave_sum_u64(steps);
+    uint32_t md = wave_max_u32(maxdepth);
+    if (lane == 0 && tot) atomicAdd(reads, (unsigned long long)tot);
+    if (lane == 0 && md) atomicMax((unsigned long long *)reads + 1, (unsigned long long)md);
+}
+
+
+constexpr int DEEP_DPL = 4;  // depths per lane per window
+
+// Groups of 2..8 members whose order needs deep comparisons, one wave each.
+// Lane (m, t) = (lane / W, lane % W) loads depths d0 + 4t .. d0 + 4t + 3 of
+// member m, W = 64 / (k rounded up to a power of two), so one round trip
+// covers 4W depths. The wave finds the first depth where some subgroup
+// splits, applies the same refinement as k_tie_lanes there (all lanes keep
+// the same copy of the members' state), and goes on from the next depth.
+__global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K, int64_t n2,
+                                                  const uint32_t *__restrict__ SV,
+                                                  const uint32_t *__restrict__ dlist,
+                                                  const uint32_t *__restrict__ dcount,
+                                                  uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
+                                                  unsigned long long *__restrict__ reads) {
+    const int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t nd = *dcount;
+    uint64_t steps = 0;
+    uint32_t maxdepth = 0;
+    for (int64_t g = wave; g < nd; g += nwaves) {
+        const uint32_t gs = dlist[2 * g];
+        const int k = (int)dlist[2 * g + 1];
+        if (k < 2 || k > SMALL_MAXK) {
+            if (lane == 0) atomicOr(guard, GUARD_RERANK);
+            continue;
+        }
+        const int kp = k <= 2 ? 2 : (k <= 4 ? 4 : 8);
+        const int W = 64 / kp;
+        const int mi = lane / W, ti = lane % W;
+        uint32_t pos[SMALL_MAXK], e[SMALL_MAXK], o[SMALL_MAXK], sub[SMALL_MAXK], lead[SMALL_MAXK];
+        bool act[SMALL_MAXK];
+#pragma unroll
+        for (int i = 0; i < SMALL_MAXK; ++i) {
+            pos[i] = i < k ? SV[gs + i] : 0u;
+            o[i] = (uint32_t)i;
+            sub[i] = 0;
+            lead[i] = 0;
+            act[i] = i < k;
+        }
+#pragma unroll
+        for (int i = 0; i < SMALL_MAXK; ++i) e[i] = i < k ? (uint32_t)(K[pos[i]] & 7) : 0u;
+        uint32_t mypos = 0;
+        bool myact = false;
+#pragma unroll
+        for (int i = 0; i < SMALL_MAXK; ++i)
+            if (i == mi) {
+                mypos = pos[i];
+                myact = act[i];
+            }
+        bool any = true;
+        int64_t d0 = 1;
+        const int WIN = W * DEEP_DPL;
+        while (any) {
+            uint64_t kv[DEEP_DPL];
+#pragma unroll
+            for (int j = 0; j < DEEP_DPL; ++j) {
+                int64_t q = (int64_t)mypos + d0 + ti * DEEP_DPL + j;
+                kv[j] = (mi < k && myact && q < n2) ? K[q] : ~0ull;
+            }
+            int u0 = 0;  // first depth of the window not yet processed
+            while (any && u0 < WIN) {
+                // my member's leader, and the first depth >= u0 where I differ from it
+                uint32_t my_lead = 0, my_sub = 0;
+                bool my_act = false;
+#pragma unroll
+                for (int i = 0; i < SMALL_MAXK; ++i)
+                    if (i == mi) {
+                        my_lead = lead[i];
+                        my_act = act[i];
+                        my_sub = sub[i];
+                    }
+                (void)my_sub;
+                int first = WIN;
+#pragma unroll
+                for (int j = 0; j < DEEP_DPL; ++j) {
+                    uint64_t lk = __shfl(kv[j], (int)my_lead * W + ti);
+                    int u = ti * DEEP_DPL + j;
+                    uint64_t c = kv[j] >> 3;
+                    bool sent = (c & 7) == 0;
+                    bool differ = mi < k && my_act && u >= u0 &&
+                                  (kv[j] == ~0ull || (c != (lk >> 3)) || (sent && (uint32_t)mi != my_lead));
+                    if (differ && u < first) first = u;
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    int t = __shfl_xor(first, off);
+                    first = t < first ? t : first;
+                }
+                if (first >= WIN) break;
+                // refine at depth u = first using every member's key there
+                const int u = first;
+                const int src_t = u / DEEP_DPL, src_j = u % DEEP_DPL;
+                uint64_t c[SMALL_MAXK];
+                uint32_t tb[SMALL_MAXK];
+#pragma unroll
+                for (int i = 0; i < SMALL_MAXK; ++i) {
+                    uint64_t v = 0;
+#pragma unroll
+                    for (int j = 0; j < DEEP_DPL; ++j) {
+                        uint64_t x = __shfl(kv[j], (i < kp ? i : 0) * W + src_t);
+                        if (j == src_j) v = x;
+                    }
+                    c[i] = v >> 3;
+                    tb[i] = 0;
+                    if (act[i]) {
+                        if (v == ~0ull) {
+                            if (lane == 0) atomicOr(guard, GUARD_RERANK);
+                            act[i] = false;
+                        } else if ((c[i] & 7) == 0) {
+                            tb[i] = pos[i] + (uint32_t)(d0 + u);
+                        }
+                    }
+                }
+                uint32_t no[SMALL_MAXK], nsb[SMALL_MAXK];
+#pragma unroll
+                for (int i = 0; i < SMALL_MAXK; ++i) {
+                    uint32_t less = 0, eqb = 0;
+#pragma unroll
+                    for (int j = 0; j < SMALL_MAXK; ++j) {
+                        bool same = act[i] && act[j] && sub[j] == sub[i];
+                        bool lt_ = c[j] < c[i] || (c[j] == c[i] && tb[j] < tb[i]);
+                        bool eq_ = c[j] == c[i] && tb[j] == tb[i];
+                        less += (same && lt_) ? 1u : 0u;
+                        eqb += (same && eq_ && o[j] < o[i]) ? 1u : 0u;
+                    }
+                    no[i] = act[i] ? sub[i] + less + eqb : o[i];
+                    nsb[i] = act[i] ? sub[i] + less : sub[i];
+                }
+                bool nact[SMALL_MAXK];
+                uint32_t nlead[SMALL_MAXK];
+                any = false;
+#pragma unroll
+                for (int i = 0; i < SMALL_MAXK; ++i) {
+                    uint32_t cnt = 0, ld = lead[i];
+                    bool uni = true;
+#pragma unroll
+                    for (int j = 0; j < SMALL_MAXK; ++j) {
+                        bool same = act[j] && nsb[j] == nsb[i];
+                        cnt += same ? 1u : 0u;
+                        uni &= !same || e[j] == e[i];
+                        if (same && no[j] == nsb[i]) ld = (uint32_t)j;
+                    }
+                    nact[i] = act[i] && cnt >= 2 && !uni;
+                    nlead[i] = ld;
+                    any |= nact[i];
+                }
+#pragma unroll
+                for (int i = 0; i < SMALL_MAXK; ++i) {
+                    o[i] = no[i];
+                    sub[i] = nsb[i];
+                    act[i] = nact[i];
+                    lead[i] = nlead[i];
+                }
+                u0 = u + 1;
+            }
+            uint32_t na = 0;
+#pragma unroll
+            for (int i = 0; i < SMALL_MAXK; ++i) na += act[i] ? 1u : 0u;
+            steps += (uint64_t)na * WIN;
+#pragma unroll
+            for (int i = 0; i < SMALL_MAXK; ++i)
+                if (i == mi) myact = act[i];
+            d0 += WIN;
+        }
+        maxdepth = (uint32_t)d0 > maxdepth ? (uint32_t)d0 : maxdepth;
+        if (lane < k) {
+            uint32_t oo = 0, pp = 0;
+#pragma unroll
+            for (int i = 0; i < SMALL_MAXK; ++i)
+                if (i == lane) {
+                    oo = o[i];
+                    pp = pos[i];
+                }
+            SK[gs + oo] = K[pp];
+        }
+    }
+    if (lane == 0 && steps) atomicAdd(reads, (unsigned long long)steps);
+    if (lane == 0 && maxdepth) atomicMax(reads + 1, (unsigned long long)maxdepth);
+}
+
+// One wave per listed group of at most 64 members; lane i holds member i.
+__global__ void __launch_bounds__(256) k_tie_walk(const uint64_t *__restrict__ K, int64_t n2,
+                                                  const uint32_t *__restrict__ SV,
+                                                  const uint32_t *__restrict__ glist, int64_t ng,
+                                                  uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
+                                                  unsigned long long *__restrict__ reads) {
+    int lane = threadIdx.x & 63;
+    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t g = wave; g < ng; g += nwaves) {
+        uint32_t gs = glist[2 * g], k = glist[2 * g + 1];
+        if (k > WALK_MAXK) {
+            if (lane == 0) atomicOr(guard, GUARD_RERANK);
+            continue;
+        }
+        bool member = (uint32_t)lane < k;
+        uint32_t p = member ? SV[gs + lane] : 0u;
+        uint64_t kp = member ? K[p] : 0ull;
+        uint32_t e = (uint32_t)(kp & 7);
+        uint32_t o = (uint32_t)lane;  // position in the current order
+        uint32_t sub = 0;             // order index where my subgroup starts
+        uint32_t lead = 0;            // lane holding the first member of my subgroup
+        bool active = member;         // my subgroup still mixes symbols
+        uint64_t steps = 0;
+        for (int64_t d0 = 1;; d0 += WALK_DEPTHS) {
+            if (__ballot(active) == 0) break;
+            uint64_t kv[WALK_DEPTHS];
+            for (int t = 0; t < WALK_DEPTHS; ++t) {
+                int64_t q = (int64_t)p + d0 + t;
+                kv[t] = (active && q < n2) ? K[q] : ~0ull;
+            }
+            for (int t = 0; t < WALK_DEPTHS; ++t) {
+                uint64_t amask = __ballot(active);
+                if (amask == 0) break;
+                int64_t q = (int64_t)p + d0 + t;
+                uint64_t kk = 0;
+                uint32_t tb = 0;
+                if (active) {
+                    ++steps;
+                    if (kv[t] == ~0ull) {
+                        atomicOr(guard, GUARD_RERANK);
+                        active = false;
+                    } else {
+                        kk = kv[t] >> 3;
+                        // a key holding its sentinel is unique; such keys order by
+                        // position, which follows the strand order
+                        if ((kk & 7) == 0) tb = (uint32_t)q;
+                    }
+                }
+                uint64_t lk = __shfl(kk, (int)lead);
+                uint32_t lt = __shfl(tb, (int)lead);
+                bool differ = active && (kk != lk || tb != lt);
+                if (__ballot(differ) == 0) continue;
+                // some subgroup splits: stable re-sort inside every active subgroup
+                uint32_t less = 0, eqb = 0;
+                for (int j = 0; j < (int)k; ++j) {
+                    uint64_t kj = __shfl(kk, j);
+                    uint32_t tj = __shfl(tb, j);
+                    uint32_t sj = __shfl(sub, j);
+                    uint32_t oj = __shfl(o, j);
+                    bool aj = (amask >> j) & 1ull;
+                    if (active && aj && sj == sub) {
+                        bool lt_ = kj < kk || (kj == kk && tj < tb);
+                        bool eq_ = kj == kk && tj == tb;
+                        less += lt_ ? 1u : 0u;
+                        eqb += (eq_ && oj < o) ? 1u : 0u;
+                    }
+                }
+                if (active) {
+                    o = sub + less + eqb;
+                    sub = sub + less;
+                }
+                uint32_t cnt = 0, nlead = lead;
+                bool uni = true;
+                for (int j = 0; j < (int)k; ++j) {
+                    uint32_t sj = __shfl(sub, j);
+                    uint32_t oj = __shfl(o, j);
+                    uint32_t ej = __shfl(e, j);
+                    bool aj = (amask >> j) & 1ull;
+                    if (active && aj && sj == sub) {
+                        ++cnt;
+                        uni &= ej == e;
+                        if (oj == sub) nlead = (uint32_t)j;
+                    }
+                }
+                if (active) {
+                    lead = nlead;
+                    active = cnt >= 2 && !uni;
+                }
+            }
+        }
+        if (member) SK[gs + o] = kp;
+        uint64_t tot = wave_sum_u64(steps);
+        if (lane == 0 && tot) atomicAdd(reads, (unsigned long long)tot);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Interleave
 // ---------------------------------------------------------------------------
 
+// Number of new suffixes landing in each 128-row output block. Consecutive
+// sorted entries land in non-decreasing blocks, so each wave adds one count
+// per run of equal blocks instead of one per entry.
 __global__ void k_block_count(const uint64_t *__restrict__ SK, int64_t n2, int64_t m1, int lshift,
                               uint32_t *__restrict__ cnt) {
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n2;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        int64_t M = (int64_t)(SK[s] >> lshift) + m1 + s;
-        atomicAdd(&cnt[M >> BLK_SHIFT], 1u);
+    int lane = threadIdx.x & 63;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t base0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63);
+    for (int64_t base = base0; base < n2; base += stride) {
+        int64_t s = base + lane;
+        bool valid = s < n2;
+        int64_t b = valid ? (((int64_t)(SK[s] >> lshift) + m1 + s) >> BLK_SHIFT) : -1;
+        int64_t bprev = __shfl_up(b, 1);
+        bool head = valid && (lane == 0 || b != bprev);
+        uint64_t heads = __ballot(head);
+        uint64_t vmask = __ballot(valid);
+        if (head) {
+            uint64_t above = heads & ~low_mask(lane + 1);
+            int next = above ? __ffsll((unsigned long long)above) - 1 : 64 - __clzll((long long)vmask);
+            atomicAdd(&cnt[b], (uint32_t)(next - lane));
+        }
     }
 }
 
@@ -502,7 +1096,69 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         va.reset();
     }
 
+    // Groups whose members carry different BWT symbols need an order; the
+    // symbol walk handles groups of up to WALK_MAXK members, prefix doubling
+    // (which orders every tie) handles the rest.
+    bool need_doubling = false;
     {
+        DBuf lpair, lsmall, lbig, gstat, gtied;
+        RB3_ALLOC(lpair, &c, (n2 / 2 + 1) * 2 * sizeof(uint32_t));
+        RB3_ALLOC(lsmall, &c, (n2 / 3 + 1) * 2 * sizeof(uint32_t));
+        RB3_ALLOC(lbig, &c, (n2 / 9 + 1) * 2 * sizeof(uint32_t));
+        RB3_ALLOC(gstat, &c, 4 * sizeof(uint32_t));
+        RB3_ALLOC(gtied, &c, 4 * sizeof(unsigned long long));
+        DBuf gdeep;
+        RB3_ALLOC(gdeep, &c, 2 * sizeof(unsigned long long));
+        RB3_HIP(hipMemsetAsync(gdeep.p, 0, 2 * sizeof(unsigned long long), c.stream));
+        RB3_HIP(hipMemsetAsync(gstat.p, 0, 4 * sizeof(uint32_t), c.stream));
+        RB3_HIP(hipMemsetAsync(gtied.p, 0, 4 * sizeof(unsigned long long), c.stream));
+        RB3_LAUNCH("tie_groups", k_tie_groups, grid_for(n2, TG_THREADS * TG_ITEMS), dim3(TG_THREADS), 0,
+                   c.stream, SK, n2, lpair.as<uint32_t>(), lsmall.as<uint32_t>(), lbig.as<uint32_t>(),
+                   gstat.as<uint32_t>(), gtied.as<unsigned long long>());
+        uint32_t hs2[4];
+        unsigned long long ht[4];
+        RB3_HIP(hipMemcpyAsync(hs2, gstat.p, sizeof(hs2), hipMemcpyDeviceToHost, c.stream));
+        RB3_HIP(hipMemcpyAsync(ht, gtied.p, sizeof(ht), hipMemcpyDeviceToHost, c.stream));
+        RB3_HIP(hipStreamSynchronize(c.stream));
+        st.tied_records = (int64_t)ht[0];
+        st.tie_pairs = hs2[0];
+        st.tie_groups = (int64_t)hs2[0] + hs2[1] + hs2[2];
+        st.max_group = hs2[3];
+        if (hs2[3] > (uint32_t)WALK_MAXK) {
+            need_doubling = true;
+        } else if (st.tie_groups > 0) {
+            if (hs2[0] + hs2[1] > 0) {
+                DBuf qh, dl;
+                int64_t nq = (int64_t)hs2[0] + hs2[1];
+                RB3_ALLOC(qh, &c, 2 * sizeof(uint32_t));
+                RB3_ALLOC(dl, &c, nq * 2 * sizeof(uint32_t));
+                RB3_HIP(hipMemsetAsync(qh.p, 0, 2 * sizeof(uint32_t), c.stream));
+                // persistent: enough waves to fill the chip, no more than the work
+                int64_t wgs = (nq + LANES_WG - 1) / LANES_WG;
+                if (wgs > 2048) wgs = 2048;
+                RB3_LAUNCH("tie_lanes", k_tie_lanes, dim3((unsigned)wgs), dim3(LANES_WG), 0, c.stream,
+                           K.as<uint64_t>(), n2, SV, lpair.as<uint32_t>(), (int64_t)hs2[0], lsmall.as<uint32_t>(),
+                           (int64_t)hs2[1], qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, guard,
+                           gtied.as<unsigned long long>() + 1);
+                // the deep list's length stays on the device: a fixed grid loops over it
+                RB3_LAUNCH("tie_deep", k_tie_deep, dim3(1024), dim3(256), 0, c.stream, K.as<uint64_t>(), n2, SV,
+                           dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, guard, gdeep.as<unsigned long long>());
+            }
+            if (hs2[2] > 0)
+                RB3_LAUNCH("tie_walk", k_tie_walk, grid_for(hs2[2], 4, 1 << 20), dim3(256), 0, c.stream,
+                           K.as<uint64_t>(), n2, SV, lbig.as<uint32_t>(), (int64_t)hs2[2], SK, guard,
+                           gtied.as<unsigned long long>() + 3);
+            unsigned long long hd[2];
+            RB3_HIP(hipMemcpyAsync(ht, gtied.p, sizeof(ht), hipMemcpyDeviceToHost, c.stream));
+            RB3_HIP(hipMemcpyAsync(hd, gdeep.p, sizeof(hd), hipMemcpyDeviceToHost, c.stream));
+            RB3_HIP(hipStreamSynchronize(c.stream));
+            st.tie_small_reads = (int64_t)ht[1];
+            st.tie_max_depth = (int64_t)(ht[2] > hd[1] ? ht[2] : hd[1]);
+            st.tie_deep_reads = (int64_t)hd[0];
+            st.tie_work = (int64_t)ht[3];
+        }
+    }
+    if (need_doubling) {
         DBuf head, tied, idx, R, cnt;
         RB3_ALLOC(head, &c, n2 * sizeof(uint32_t));
         RB3_ALLOC(tied, &c, n2 * sizeof(uint32_t));
@@ -521,7 +1177,8 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_HIP(hipMemcpyAsync(h_cnt, cnt.p, sizeof(h_cnt), hipMemcpyDeviceToHost, c.stream));
         RB3_HIP(hipStreamSynchronize(c.stream));
         int64_t A = h_cnt[0];
-        st.tied_records = A;
+        st.tie_doubling = 1;
+        st.tie_work = 0;
         if (A > 0) {
             DBuf apos[2], ahead[2], ags[2], agsz[2], key2, tpos, thead, tkeep, tsub, teq, nidx;
             for (int q = 0; q < 2; ++q) {
@@ -542,7 +1199,6 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                        ahead[0].as<uint32_t>(), ags[0].as<uint32_t>(), agsz[0].as<uint32_t>(), d_tot + 1);
             RB3_HIP(hipMemcpyAsync(h_cnt, cnt.p, sizeof(h_cnt), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipStreamSynchronize(c.stream));
-            st.max_group = h_cnt[1];
             if (h_cnt[1] > 65536) {
                 set_error(RB3_ELIMIT, "a group of more than 65536 new suffixes shares its sort key "
                                       "(highly repetitive batch)");

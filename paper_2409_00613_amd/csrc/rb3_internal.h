@@ -302,9 +302,16 @@ struct MergeStats {
     int64_t key_syms = 0;         // symbols per initial sort key
     int64_t sort_bits = 0;
     int64_t tied_records = 0;     // records in non-singleton groups after the sort
-    int64_t tie_rounds = 0;
-    int64_t tie_work = 0;         // sum over rounds of active records
-    int64_t max_group = 0;
+    int64_t tie_groups = 0;       // tied groups whose members carry different symbols
+    int64_t tie_pairs = 0;        // ... of which have two members
+    int64_t tie_small_reads = 0;  // key reads refining groups of 2..8
+    int64_t tie_max_depth = 0;    // deepest comparison those needed
+    int64_t tie_deep_reads = 0;   // key reads of groups handed to the deep walk
+    int64_t max_group = 0;        // largest such group
+    int64_t tie_doubling = 0;     // 1 if prefix doubling ordered the ties
+    int64_t tie_rounds = 0;       // doubling rounds
+    int64_t tie_work = 0;         // key reads of the symbol walk over groups of 9+,
+                                  // or active records summed over doubling rounds
 };
 
 struct IndexData {

@@ -155,7 +155,8 @@ def test_merge_pangenome_small():
     codes, lens = _expand(w.b1 + w.new)
     got = idx.export()
     assert np.array_equal(got, oracle.bwt(codes, lens))
-    assert st["tied_records"] > 0 and st["tie_rounds"] > 0 and st["fixup_steps"] > 0
+    assert st["tied_records"] > 0 and st["tie_groups"] > 0 and st["fixup_steps"] > 0
+    assert st["tie_work"] + st["tie_small_reads"] > 0
     idx.close()
 
 
@@ -279,3 +280,30 @@ def test_smem_small_capacity_reports_sizes(tiny):
     small, off2 = idx.smem(q.data, q.lens, 5, 1, cap=3)  # retried internally after ENOSPC
     assert np.array_equal(off, off2) and np.array_equal(full, small)
     idx.close()
+
+
+@pytest.mark.parametrize("copies", [6, 40, 70])
+def test_large_mixed_symbol_groups(copies):
+    """Many new strings sharing a long suffix after different first bases:
+    one tied group per position of the shared part, with mixed BWT symbols
+    right after the differing base. 70 copies exceed the symbol walk's group
+    limit and take the prefix-doubling path."""
+    say(f"case: {copies} strings with a shared 300-base tail")
+    rnd = random.Random(copies)
+    tail = "".join(rnd.choice("ACGT") for _ in range(300))
+    strs = ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 3))) + tail for _ in range(copies)]
+    old = synth.pack([("".join(rnd.choice("ACGT") for _ in range(150)) + tail[:100]).encode()])
+    new = synth.pack([s.encode() for s in strs])
+    for start in ("empty", "index"):
+        if start == "empty":
+            idx = rb3.rb3_build(new.data, new.lens)
+            codes, lens = _expand(new)
+        else:
+            idx = rb3.rb3_build(old.data, old.lens)
+            idx.merge(new.data, new.lens)
+            codes, lens = _expand(old + new)
+        assert np.array_equal(idx.export(), oracle.bwt(codes, lens)), start
+        st = idx.merge_stats()
+        assert st["tie_groups"] > 0
+        assert st["tie_doubling"] == (1 if st["max_group"] > 64 else 0)
+        idx.close()
