@@ -53,6 +53,41 @@ __device__ __forceinline__ uint64_t pack_ahead(const uint8_t *__restrict__ Q, in
     return packed;
 }
 
+
+// Keys of consecutive positions, walked downwards, collected in an 8-entry
+// register window: slot j holds the key of position p + j, where p is the
+// last position pushed. Flushing at a multiple of 8 with all slots valid
+// writes one whole 64-byte line; otherwise only the valid slots are stored.
+struct KeyWindow {
+    uint64_t b[8];
+    uint32_t vm;  // bit j: slot j holds a key to store
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b[j] = 0;
+        vm = 0;
+    }
+    __device__ __forceinline__ void push(uint64_t key, bool valid) {
+#pragma unroll
+        for (int j = 7; j > 0; --j) b[j] = b[j - 1];
+        b[0] = key;
+        vm = ((vm << 1) | (valid ? 1u : 0u)) & 0xFFu;
+    }
+    __device__ __forceinline__ void flush(uint64_t *__restrict__ K, int64_t p) {
+        if (vm == 0xFFu && (p & 7) == 0) {
+            uint4 *dst = (uint4 *)(K + p);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                dst[j] = make_uint4((uint32_t)b[2 * j], (uint32_t)(b[2 * j] >> 32), (uint32_t)b[2 * j + 1],
+                                    (uint32_t)(b[2 * j + 1] >> 32));
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if ((vm >> j) & 1u) K[p + j] = b[j];
+        }
+        vm = 0;
+    }
+};
+
 __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
                         int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K,
                         int32_t *__restrict__ unres, int32_t *__restrict__ ready,
@@ -74,13 +109,15 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     }
     int32_t unresolved = 0;
     int64_t wide = 0;
+    KeyWindow win;
+    win.init();
     for (int64_t p = p1 - 1; p >= c.p0; --p) {
         uint32_t a = Q[p];
         uint32_t emit = p > 0 ? Q[p - 1] : 0u;
         packed = ((uint64_t)a << wsh) | (packed >> 3);
         if (point) {
             l = pi_sym(ix, (int)a, l);
-            K[p] = make_key(l - m1, packed, emit, lshift);
+            win.push(make_key(l - m1, packed, emit, lshift), true);
         } else {
             int64_t bl = lo >> BLK_SHIFT, bh = hi >> BLK_SHIFT;
             Block B = load_block(ix.blk, bl);
@@ -97,11 +134,13 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
             if (lo == hi) {
                 point = true;
                 l = lo;
-                K[p] = make_key(l - m1, packed, emit, lshift);
+                win.push(make_key(l - m1, packed, emit, lshift), true);
             } else {
                 ++unresolved;
+                win.push(0, false);
             }
         }
+        if ((p & 7) == 0 || p == c.p0) win.flush(K, p);
     }
     unres[i] = unresolved;
     ready[i] = point ? 1 : 0;
@@ -128,12 +167,15 @@ __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     int64_t p1 = c.p0 + c.len;
     int64_t l = (int64_t)(K[p1] >> lshift) + m1;
     uint64_t packed = pack_ahead(Q, p1, w);
+    KeyWindow win;
+    win.init();
     for (int64_t p = p1 - 1; p >= p1 - u; --p) {
         uint32_t a = Q[p];
         uint32_t emit = p > 0 ? Q[p - 1] : 0u;
         packed = ((uint64_t)a << wsh) | (packed >> 3);
         l = pi_sym(ix, (int)a, l);
-        K[p] = make_key(l - m1, packed, emit, lshift);
+        win.push(make_key(l - m1, packed, emit, lshift), true);
+        if ((p & 7) == 0 || p == p1 - u) win.flush(K, p);
     }
     unres[i] = 0;
     if (u == c.len) ready_out[i] = 1;

@@ -37,18 +37,35 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                             int iota, int64_t n, int shift, uint32_t dmask, int dbits,
-                             const uint32_t *__restrict__ O, int64_t ntiles, uint64_t *__restrict__ kout,
-                             uint32_t *__restrict__ vout, int32_t *__restrict__ guard) {
-    __shared__ uint32_t wbase[RS_WAVES][256];
-    int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&wbase[0][0])[i] = 0;
+// Scatter of one tile. The tile's keys are first ranked stably inside the
+// tile and staged in LDS in digit order; then the workgroup writes them out
+// with consecutive threads on consecutive output positions, so each digit's
+// run leaves as whole lines instead of scattered 8- and 4-byte stores.
+constexpr int SC_THREADS = 512;
+constexpr int SC_WAVES = SC_THREADS / 64;
+constexpr int SC_STEPS = RS_TILE / SC_THREADS;  // 64-key steps per wave
+
+__global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__restrict__ kin,
+                                                           const uint32_t *__restrict__ vin, int iota,
+                                                           int64_t n, int shift, uint32_t dmask, int dbits,
+                                                           const uint32_t *__restrict__ O, int64_t ntiles,
+                                                           uint64_t *__restrict__ kout,
+                                                           uint32_t *__restrict__ vout,
+                                                           int32_t *__restrict__ guard) {
+    __shared__ uint64_t sk[RS_TILE];
+    __shared__ uint32_t sv[RS_TILE];
+    __shared__ uint32_t wbase[SC_WAVES][256];
+    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t wsum[SC_WAVES];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < SC_WAVES * 256; i += SC_THREADS) (&wbase[0][0])[i] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)wave * RS_WAVE_KEYS;
-    uint64_t k[RS_STEPS];
-    uint32_t v[RS_STEPS];
-    for (int j = 0; j < RS_STEPS; ++j) {
+    const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t base = tile0 + (int64_t)wave * (64 * SC_STEPS);
+    uint64_t k[SC_STEPS];
+    uint32_t v[SC_STEPS];
+#pragma unroll
+    for (int j = 0; j < SC_STEPS; ++j) {
         int64_t idx = base + j * 64 + lane;
         if (idx < n) {
             k[j] = kin[idx];
@@ -60,17 +77,37 @@ __global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *_
         }
     }
     __syncthreads();
-    // per digit: global offset of this tile, then the waves in order
-    for (int d = tid; d < 256; d += RS_THREADS) {
-        uint32_t run = O[(int64_t)d * ntiles + blockIdx.x];
-        for (int w = 0; w < RS_WAVES; ++w) {
-            uint32_t t = wbase[w][d];
-            wbase[w][d] = run;
-            run += t;
+    // digit totals of the tile, their exclusive prefix (tile-local digit
+    // starts), and per (wave, digit) local bases
+    uint32_t tot = 0, cnt[SC_WAVES];
+    if (tid < 256) {
+#pragma unroll
+        for (int w = 0; w < SC_WAVES; ++w) {
+            cnt[w] = wbase[w][tid];
+            tot += cnt[w];
+        }
+    }
+    uint32_t inc = tot;
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(inc, d);
+        if (lane >= d) inc += t;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    if (tid < 256) {
+        uint32_t pre = inc - tot;
+        for (int w = 0; w < wave; ++w) pre += wsum[w];
+        gbase[tid] = O[(int64_t)tid * ntiles + blockIdx.x] - pre;
+        uint32_t run = pre;
+#pragma unroll
+        for (int w = 0; w < SC_WAVES; ++w) {
+            wbase[w][tid] = run;
+            run += cnt[w];
         }
     }
     __syncthreads();
-    for (int j = 0; j < RS_STEPS; ++j) {
+#pragma unroll
+    for (int j = 0; j < SC_STEPS; ++j) {
         int64_t idx = base + j * 64 + lane;
         bool valid = idx < n;
         uint32_t d = (uint32_t)(k[j] >> shift) & dmask;
@@ -85,16 +122,25 @@ __global__ void k_rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *_
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (valid) {
-            if ((int64_t)pos < n) {
-                kout[pos] = k[j];
-                vout[pos] = v[j];
-            } else {
-                atomicOr(guard, 1);
-            }
+            sk[pos] = k[j];
+            sv[pos] = v[j];
             if (r == 0) wbase[wave][d] = pos + (uint32_t)__popcll(peers);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    const int64_t tn = n - tile0 < RS_TILE ? n - tile0 : RS_TILE;
+    for (int i = tid; i < tn; i += SC_THREADS) {
+        uint64_t key = sk[i];
+        uint32_t d = (uint32_t)(key >> shift) & dmask;
+        uint32_t gpos = gbase[d] + (uint32_t)i;
+        if ((int64_t)gpos < n) {
+            kout[gpos] = key;
+            vout[gpos] = sv[i];
+        } else {
+            atomicOr(guard, 1);
+        }
     }
 }
 
@@ -131,7 +177,7 @@ int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *
         RB3_LAUNCH("sort_hist", k_rs_hist, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, c.stream, src_k, n,
                    shift, dmask, H.as<uint32_t>(), ntiles);
         RB3_TRY(scan_u32(c, H.as<uint32_t>(), H.as<uint32_t>(), 256 * ntiles, false, false, nullptr));
-        RB3_LAUNCH("sort_scatter", k_rs_scatter, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, c.stream,
+        RB3_LAUNCH("sort_scatter", k_rs_scatter, dim3((unsigned)ntiles), dim3(SC_THREADS), 0, c.stream,
                    src_k, src_v, (int)iota, n, shift, dmask, dbits, H.as<uint32_t>(), ntiles, dk, dv, d_guard);
         src_k = dk;
         src_v = dv;
