@@ -143,7 +143,9 @@ int rb3_export(const rb3_index *idx, uint8_t *codes);
 int rb3_import(const rb3_opts *o, const uint8_t *codes, int64_t n, int32_t mem,
                rb3_index **out);
 
-/* Deep copy of an index on the same device and stream. */
+/* Deep copy of an index on the same device. The copy uses the caller's
+ * stream if the source was given one; otherwise it gets a stream of its own,
+ * so either index may be freed first. The call returns after the copy. */
 int rb3_clone(const rb3_index *src, rb3_index **out);
 
 void rb3_index_free(rb3_index *idx);

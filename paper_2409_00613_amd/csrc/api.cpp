@@ -495,6 +495,17 @@ int rb3_clone(const rb3_index *src, rb3_index **out) {
     if (!ix) return fail(RB3_ENOMEM, "host allocation failed");
     ix->d.ctx = call_ctx(src->d);
     ix->d.ctx.own_stream = false;
+    if (src->d.ctx.own_stream) {
+        // the source's stream dies with the source: the copy gets its own
+        hipStream_t s2 = nullptr;
+        if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
+            delete ix;
+            return fail(RB3_EDEVICE, "hipStreamCreateWithFlags failed");
+        }
+        // the copy below runs on the source's stream; the new stream starts after it
+        ix->d.ctx.stream = s2;
+        ix->d.ctx.own_stream = true;
+    }
     Ctx c = call_ctx(src->d);
     int rc = [&]() -> int {
         DBuf blk, sb;

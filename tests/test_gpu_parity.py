@@ -307,3 +307,18 @@ def test_large_mixed_symbol_groups(copies):
         assert st["tie_groups"] > 0
         assert st["tie_doubling"] == (1 if st["max_group"] > 64 else 0)
         idx.close()
+
+
+def test_clone_outlives_source(tiny):
+    say("case: a clone stays usable after its source is freed")
+    src = rb3.rb3_build(tiny.b1.data, tiny.b1.lens)
+    cp = src.clone()
+    src.close()
+    cp.merge(tiny.new.data, tiny.new.lens)
+    lo, hi = cp.count(tiny.queries.data, tiny.queries.lens)
+    codes, lens = _expand(tiny.b1 + tiny.new)
+    assert np.array_equal(cp.export(), oracle.bwt(codes, lens))
+    qc, ql = oracle.encode(tiny.queries.data, tiny.queries.lens)
+    olo, ohi = oracle.count(codes, lens, qc, ql)
+    assert np.array_equal(lo, olo) and np.array_equal(hi, ohi)
+    cp.close()
