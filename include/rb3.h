@@ -130,6 +130,10 @@ int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64
              int32_t mem, int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap,
              int64_t *out_off);
 
+/* Work done by the calling thread's last successful rb3_smem call: the
+ * number of bi-interval extensions (each reads rank-all at two positions). */
+int rb3_last_smem_stats(int64_t *extensions);
+
 /* Size of the BWT n, number of sentinels m, and C[c] = number of symbols
  * smaller than c (Table 1) for c = 0..5. Any output pointer may be NULL. */
 int rb3_info(const rb3_index *idx, int64_t *n, int64_t *m, int64_t C[6]);

@@ -21,6 +21,8 @@ namespace rb3 {
 // errors
 // ---------------------------------------------------------------------------
 static thread_local std::string g_err;
+// extensions performed by the last rb3_smem call of this thread
+static thread_local int64_t g_last_smem_exts = 0;
 static thread_local int g_err_code = 0;
 
 void set_error(int code, const std::string &msg) {
@@ -381,42 +383,36 @@ int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64
     RB3_HIP(hipSetDevice(idx->d.ctx.device));
     Ctx c = call_ctx(idx->d);
     int rc = [&]() -> int {
-        DBuf hold, codes, err, off, tmp, ordered, cnt, coff, tot;
+        DBuf hold, codes, err, ordered, coff;
         const uint8_t *d_q = nullptr;
         RB3_TRY(stage(c, q, total, mem, hold, &d_q));
         RB3_ALLOC(codes, &c, total > 0 ? total : 1);
         RB3_ALLOC(err, &c, sizeof(int32_t));
         RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
         RB3_TRY(encode_plain(c, d_q, qlens, n_q, codes.as<uint8_t>(), total, err.as<int32_t>()));
-        std::vector<int64_t> hoff(n_q + 1);
-        hoff[0] = 0;
-        for (int64_t i = 0; i < n_q; ++i) hoff[i + 1] = hoff[i] + qlens[i];
-        RB3_ALLOC(off, &c, (n_q + 1) * sizeof(int64_t));
-        RB3_HIP(hipMemcpyAsync(off.p, hoff.data(), (n_q + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
         int32_t bad = 0;
         RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
         if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in a query");
-        int64_t cap = out_cap;
-        RB3_ALLOC(tmp, &c, (cap > 0 ? cap : 1) * sizeof(rb3_smem_t));
-        RB3_ALLOC(ordered, &c, (cap > 0 ? cap : 1) * sizeof(rb3_smem_t));
-        RB3_ALLOC(cnt, &c, (n_q + 1) * sizeof(uint32_t));
-        RB3_ALLOC(coff, &c, (n_q + 1) * sizeof(uint32_t));
-        RB3_ALLOC(tot, &c, sizeof(unsigned long long));
-        RB3_HIP(hipMemsetAsync(cnt.p, 0, (n_q + 1) * sizeof(uint32_t), c.stream));
-        int64_t found = 0;
-        RB3_TRY(smem_run(c, idx->d.dev(), codes.as<uint8_t>(), off.as<int64_t>(), n_q, min_len, min_occ, cap,
-                         tmp.as<rb3_smem_t>(), ordered.as<rb3_smem_t>(), cnt.as<uint32_t>(), coff.as<uint32_t>(),
-                         tot.as<unsigned long long>(), &found));
-        std::vector<uint32_t> hco(n_q + 1);
-        RB3_HIP(hipMemcpyAsync(hco.data(), coff.p, (n_q + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
-        if (found <= cap && found > 0)
-            RB3_HIP(hipMemcpyAsync(out, ordered.p, found * sizeof(rb3_smem_t), hipMemcpyDeviceToHost, c.stream));
+        RB3_ALLOC(ordered, &c, (out_cap > 0 ? out_cap : 1) * sizeof(rb3_smem_t));
+        RB3_ALLOC(coff, &c, (n_q + 1) * sizeof(int64_t));
+        int64_t kept = 0, exts = 0;
+        RB3_TRY(smem_run(c, idx->d.dev(), codes.as<uint8_t>(), qlens, n_q, min_len, min_occ, out_cap,
+                         ordered.as<rb3_smem_t>(), coff.as<int64_t>(), &kept, &exts));
+        RB3_HIP(hipMemcpyAsync(out_off, coff.p, (n_q + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+        if (kept <= out_cap && kept > 0)
+            RB3_HIP(hipMemcpyAsync(out, ordered.p, kept * sizeof(rb3_smem_t), hipMemcpyDeviceToHost, c.stream));
         RB3_HIP(hipStreamSynchronize(c.stream));
-        for (int64_t i = 0; i <= n_q; ++i) out_off[i] = hco[i];
-        if (found > cap) return fail(RB3_ENOSPC, "SMEM output buffer too small; out_off holds the sizes");
+        g_last_smem_exts = exts;
+        if (kept > out_cap) return fail(RB3_ENOSPC, "SMEM output buffer too small; out_off holds the sizes");
         return RB3_OK;
     }();
     return finish(c, rc);
+}
+
+int rb3_last_smem_stats(int64_t *extensions) {
+    if (!extensions) return fail(RB3_EINVAL, "extensions is NULL");
+    *extensions = g_last_smem_exts;
+    return RB3_OK;
 }
 
 int rb3_info(const rb3_index *idx, int64_t *n, int64_t *m, int64_t C[6]) {

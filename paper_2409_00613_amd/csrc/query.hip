@@ -3,6 +3,8 @@
 // double-strand BWT (Sec. 2.5, Algorithm 3).
 #include "rb3_internal.h"
 
+#include <vector>
+
 namespace rb3 {
 
 // [lo, hi) of each query. The search runs over the whole query even after
@@ -98,89 +100,307 @@ __device__ __forceinline__ void emit_smem(rb3_smem_t *out, int64_t cap, unsigned
     }
 }
 
-// Algorithm 4, one query per lane. Readings where the printed algorithm is
-// silent: the interval reported with [i, e) is the one before the failing
-// forward extension; if the forward loop reaches the end of P, e = |P| and
-// the search stops; when the second backward loop finishes without a
-// failure the next start is i + 1.
-__global__ void k_smem(DevIndex ix, const uint8_t *__restrict__ q, const int64_t *__restrict__ qoff,
-                       int64_t nq, int32_t ell, int64_t smin, rb3_smem_t *__restrict__ out, int64_t cap,
-                       unsigned long long *__restrict__ total, uint32_t *__restrict__ cnt) {
-    int64_t qi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (qi >= nq) return;
-    const uint8_t *P = q + qoff[qi];
-    const int64_t L = qoff[qi + 1] - qoff[qi];
-    int32_t found = 0;
-    int64_t i = 0;
+// ---------------------------------------------------------------------------
+// Algorithm 4 over query segments
+// ---------------------------------------------------------------------------
+//
+// A query is cut into segments of SMEM_SEG positions. Algorithm 4 is run
+// from each segment's first position and stops once its start passes the
+// segment's end (forward extensions still read past it). Started at an
+// arbitrary position c, the algorithm reports exactly the SMEMs of length
+// >= min_len whose start is at least c, except that its very first report
+// may be [c, e(c)) although e(c) <= e(c-1): that one is contained in an
+// earlier SMEM, which an earlier segment reported, so it is dropped when its
+// end does not exceed the largest end reported by the earlier segments of
+// the query (k_smem_fix).
+//
+// Readings where the printed algorithm is silent: the interval reported with
+// [i, e) is the one before the failing forward extension; if the forward
+// loop reaches the end of P, e = |P| and the search stops; when the second
+// backward loop finishes without a failure the next start is i + 1.
+
+struct Seg {
+    int64_t qoff;  // offset of the query's codes
+    int32_t qlen;  // query length
+    int32_t qid;
+    int32_t c0, c1;  // segment [c0, c1) of the query
+};
+
+enum { PH_START = 0, PH_BACK1 = 1, PH_FWD = 2, PH_BACK2 = 3 };
+
+constexpr int SMEM_WG = 256;
+
+// One lane per segment, persistent. Each turn of the loop every busy lane
+// performs one extension (two rank-all block reads); a lane that finishes
+// its segment takes the next one from a shared queue.
+__global__ void __launch_bounds__(SMEM_WG) k_smem_seg(DevIndex ix, const uint8_t *__restrict__ q,
+                                                      const Seg *__restrict__ segs, int64_t nseg, int32_t ell,
+                                                      int64_t smin, uint32_t *__restrict__ qhead,
+                                                      rb3_smem_t *__restrict__ tmp, int64_t cap,
+                                                      unsigned long long *__restrict__ total,
+                                                      uint32_t *__restrict__ segcnt, int64_t *__restrict__ segfirst,
+                                                      int64_t *__restrict__ seglast,
+                                                      unsigned long long *__restrict__ exts) {
+    const int lane = threadIdx.x & 63;
     const BiInt empty = {0, 0, ix.n};
-    while (i < L) {
-        if (i + ell > L) break;
-        BiInt x = empty;
-        int64_t next = -1;
-        for (int64_t j = i + ell - 1; j >= i; --j) {
-            x = backward_ext(ix, x, P[j]);
-            if (x.s < smin) {
-                next = j + 1;
-                break;
+    bool busy = false, exhausted = false;
+    int64_t g = 0;
+    const uint8_t *P = q;
+    int64_t L = 0, c1 = 0, i = 0, j = 0;
+    int phase = PH_START;
+    BiInt x = empty;
+    uint32_t nrec = 0;
+    int64_t first_end = -1, last_end = -1;
+    uint64_t nexts = 0;
+    for (;;) {
+        uint64_t idle = __ballot(!busy);
+        if (idle && !exhausted) {
+            int first = __ffsll((unsigned long long)idle) - 1;
+            uint32_t nidle = (uint32_t)__popcll(idle);
+            uint32_t base = 0;
+            if (lane == first) base = atomicAdd(qhead, nidle);
+            base = __shfl(base, first);
+            if ((int64_t)base + nidle >= nseg) exhausted = true;
+            if (!busy) {
+                int64_t slot = (int64_t)base + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+                if (slot < nseg) {
+                    Seg sg = segs[slot];
+                    g = slot;
+                    P = q + sg.qoff;
+                    L = sg.qlen;
+                    i = sg.c0;
+                    c1 = sg.c1;
+                    phase = PH_START;
+                    nrec = 0;
+                    first_end = last_end = -1;
+                    busy = true;
+                }
             }
         }
-        if (next >= 0) {
-            i = next;
-            continue;
-        }
-        int64_t j = i + ell;
-        for (; j < L; ++j) {
-            BiInt y = forward_ext(ix, x, P[j]);
-            if (y.s < smin) break;
-            x = y;
-        }
-        int64_t e = j;
-        emit_smem(out, cap, total, qi, found, i, e, x);
-        ++found;
-        if (e >= L) break;
-        x = empty;
-        next = i + 1;
-        for (j = e; j >= i + 1; --j) {
-            x = backward_ext(ix, x, P[j]);
-            if (x.s < smin) {
-                next = j + 1;
-                break;
+        if (__ballot(busy) == 0) break;
+        bool emit = false, done = false;
+        int64_t em_start = 0, em_end = 0;
+        BiInt em_x = empty;
+        if (busy) {
+            if (phase == PH_START) {
+                if (i >= c1 || i + ell > L) {
+                    done = true;
+                } else {
+                    x = empty;
+                    j = i + ell - 1;
+                    phase = PH_BACK1;
+                }
+            }
+            if (!done) {
+                if (phase == PH_BACK1) {
+                    x = backward_ext(ix, x, P[j]);
+                    ++nexts;
+                    if (x.s < smin) {
+                        i = j + 1;
+                        phase = PH_START;
+                    } else if (j == i) {
+                        j = i + ell;
+                        phase = PH_FWD;
+                    } else {
+                        --j;
+                    }
+                } else if (phase == PH_FWD) {
+                    bool stop;
+                    BiInt y = x;
+                    if (j >= L) {
+                        stop = true;
+                    } else {
+                        y = forward_ext(ix, x, P[j]);
+                        ++nexts;
+                        stop = y.s < smin;
+                    }
+                    if (stop) {
+                        emit = true;
+                        em_start = i;
+                        em_end = j;
+                        em_x = x;
+                        if (j >= L) {
+                            done = true;  // an SMEM reaching the end: no later start can add one
+                        } else {
+                            x = empty;
+                            phase = PH_BACK2;  // j stays at e
+                        }
+                    } else {
+                        x = y;
+                        ++j;
+                    }
+                } else if (phase == PH_BACK2) {
+                    x = backward_ext(ix, x, P[j]);
+                    ++nexts;
+                    if (x.s < smin) {
+                        i = j + 1;
+                        phase = PH_START;
+                    } else if (j == i + 1) {
+                        i = i + 1;
+                        phase = PH_START;
+                    } else {
+                        --j;
+                    }
+                }
             }
         }
-        i = next;
+        uint64_t em = __ballot(emit);
+        if (em) {
+            int first = __ffsll((unsigned long long)em) - 1;
+            unsigned long long base = 0;
+            if (lane == first) base = atomicAdd(total, (unsigned long long)__popcll(em));
+            base = __shfl(base, first);
+            if (emit) {
+                unsigned long long slot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(em >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)em, 0u));
+                if ((int64_t)slot < cap) {
+                    rb3_smem_t r;
+                    r.start = em_start;
+                    r.end = em_end;
+                    r.occ = em_x.s;
+                    r.k = em_x.k;
+                    r.krc = em_x.kr;
+                    r.qid = (int32_t)g;  // segment; k_smem_order restores the query id
+                    r.pad = (int32_t)nrec;
+                    tmp[slot] = r;
+                }
+                if (nrec == 0) first_end = em_end;
+                last_end = em_end;
+                ++nrec;
+            }
+        }
+        if (done) {
+            segcnt[g] = nrec;
+            segfirst[g] = first_end;
+            seglast[g] = last_end;
+            busy = false;
+        }
     }
-    cnt[qi] = (uint32_t)found;
+    uint64_t t = nexts;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0 && t) atomicAdd(exts, (unsigned long long)t);
 }
 
-// Put the records of each query in order: out[off[qid] + seq].
-__global__ void k_smem_order(const rb3_smem_t *__restrict__ tmp, int64_t total,
-                             const uint32_t *__restrict__ off, rb3_smem_t *__restrict__ out) {
+// Per segment: whether its first report is contained in an SMEM of an
+// earlier segment of the same query, and how many reports it keeps.
+__global__ void k_smem_fix(const Seg *__restrict__ segs, int64_t nseg, const uint32_t *__restrict__ segcnt,
+                           const int64_t *__restrict__ segfirst, const int64_t *__restrict__ seglast,
+                           uint32_t *__restrict__ drop, uint32_t *__restrict__ kept) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nseg;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t d = 0;
+        if (segcnt[g] > 0) {
+            int64_t maxend = -1;
+            for (int64_t h = g - 1; h >= 0 && segs[h].qid == segs[g].qid; --h)
+                maxend = seglast[h] > maxend ? seglast[h] : maxend;
+            d = segfirst[g] <= maxend ? 1u : 0u;
+        }
+        drop[g] = d;
+        kept[g] = segcnt[g] - d;
+    }
+}
+
+// Query offsets: out_off[q] = offset of the first segment at or after the
+// query's first one (segments of a query are consecutive).
+__global__ void k_smem_qoff(const int64_t *__restrict__ qseg, int64_t nq, const uint32_t *__restrict__ segoff,
+                            int64_t *__restrict__ out_off) {
+    for (int64_t qq = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; qq <= nq;
+         qq += (int64_t)gridDim.x * blockDim.x)
+        out_off[qq] = segoff[qseg[qq]];
+}
+
+// Put the kept reports in order: segment order, then report order.
+__global__ void k_smem_order(const rb3_smem_t *__restrict__ tmp, int64_t total, const Seg *__restrict__ segs,
+                             const uint32_t *__restrict__ segoff, const uint32_t *__restrict__ drop,
+                             rb3_smem_t *__restrict__ out) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < total;
          r += (int64_t)gridDim.x * blockDim.x) {
         rb3_smem_t x = tmp[r];
-        int64_t pos = (int64_t)off[x.qid] + x.pad;
+        int64_t g = x.qid;
+        uint32_t d = drop[g];
+        if (d && x.pad == 0) continue;
+        int64_t pos = (int64_t)segoff[g] + x.pad - d;
+        x.qid = segs[g].qid;
         x.pad = 0;
         out[pos] = x;
     }
 }
 
-// Full SMEM call: unordered records into tmp (capacity cap), per-query counts,
-// offsets, ordered copy into out. Returns the total in *h_total.
-int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *d_qoff, int64_t nq,
-             int32_t min_len, int64_t min_occ, int64_t cap, rb3_smem_t *d_tmp, rb3_smem_t *d_out,
-             uint32_t *d_cnt, uint32_t *d_off, unsigned long long *d_total, int64_t *h_total) {
-    RB3_HIP(hipMemsetAsync(d_total, 0, sizeof(unsigned long long), c.stream));
-    if (nq > 0)
-        RB3_LAUNCH("smem", k_smem, grid_for(nq, 64, 1 << 30), dim3(64), 0, c.stream, ix, d_q, d_qoff, nq,
-                   min_len, min_occ, d_tmp, cap, d_total, d_cnt);
-    unsigned long long tot = 0;
-    RB3_HIP(hipMemcpyAsync(&tot, d_total, sizeof(tot), hipMemcpyDeviceToHost, c.stream));
-    RB3_TRY(scan_u32(c, d_cnt, d_off, nq + 1, false, false, nullptr));
+int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlens, int64_t nq, int32_t min_len,
+             int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
+             int64_t *h_exts) {
+    // segment table
+    std::vector<Seg> segs;
+    std::vector<int64_t> qseg(nq + 1);
+    int64_t off = 0;
+    for (int64_t qq = 0; qq < nq; ++qq) {
+        qseg[qq] = (int64_t)segs.size();
+        int64_t L = qlens[qq];
+        if (L >= min_len) {
+            for (int64_t c0 = 0; c0 < L; c0 += SMEM_SEG) {
+                Seg sg;
+                sg.qoff = off;
+                sg.qlen = (int32_t)L;
+                sg.qid = (int32_t)qq;
+                sg.c0 = (int32_t)c0;
+                sg.c1 = (int32_t)(c0 + SMEM_SEG < L ? c0 + SMEM_SEG : L);
+                segs.push_back(sg);
+            }
+        }
+        off += L;
+    }
+    int64_t nseg = (int64_t)segs.size();
+    qseg[nq] = nseg;
+    // every segment drops at most one report, so out_cap + nseg raw reports
+    // hold all kept ones whenever they fit in out_cap
+    const int64_t cap = out_cap + nseg;
+    DBuf d_segs, d_qseg, qh, tot, cnt, first, last, drop, kept, segoff, ext, tmpb;
+    RB3_ALLOC(tmpb, &c, (cap > 0 ? cap : 1) * sizeof(rb3_smem_t));
+    rb3_smem_t *d_tmp = tmpb.as<rb3_smem_t>();
+    RB3_ALLOC(d_segs, &c, (nseg > 0 ? nseg : 1) * sizeof(Seg));
+    RB3_ALLOC(d_qseg, &c, (nq + 1) * sizeof(int64_t));
+    RB3_ALLOC(qh, &c, sizeof(uint32_t));
+    RB3_ALLOC(tot, &c, sizeof(unsigned long long));
+    RB3_ALLOC(ext, &c, sizeof(unsigned long long));
+    RB3_ALLOC(cnt, &c, (nseg + 1) * sizeof(uint32_t));
+    RB3_ALLOC(first, &c, (nseg + 1) * sizeof(int64_t));
+    RB3_ALLOC(last, &c, (nseg + 1) * sizeof(int64_t));
+    RB3_ALLOC(drop, &c, (nseg + 1) * sizeof(uint32_t));
+    RB3_ALLOC(kept, &c, (nseg + 1) * sizeof(uint32_t));
+    RB3_ALLOC(segoff, &c, (nseg + 1) * sizeof(uint32_t));
+    if (nseg > 0)
+        RB3_HIP(hipMemcpyAsync(d_segs.p, segs.data(), nseg * sizeof(Seg), hipMemcpyHostToDevice, c.stream));
+    RB3_HIP(hipMemcpyAsync(d_qseg.p, qseg.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+    RB3_HIP(hipMemsetAsync(qh.p, 0, sizeof(uint32_t), c.stream));
+    RB3_HIP(hipMemsetAsync(tot.p, 0, sizeof(unsigned long long), c.stream));
+    RB3_HIP(hipMemsetAsync(ext.p, 0, sizeof(unsigned long long), c.stream));
+    RB3_HIP(hipMemsetAsync(kept.p, 0, (nseg + 1) * sizeof(uint32_t), c.stream));
+    if (nseg > 0) {
+        int64_t wgs = (nseg + SMEM_WG - 1) / SMEM_WG;
+        if (wgs > 2048) wgs = 2048;
+        RB3_LAUNCH("smem", k_smem_seg, dim3((unsigned)wgs), dim3(SMEM_WG), 0, c.stream, ix, d_q,
+                   d_segs.as<Seg>(), nseg, min_len, min_occ, qh.as<uint32_t>(), d_tmp, cap,
+                   tot.as<unsigned long long>(), cnt.as<uint32_t>(), first.as<int64_t>(), last.as<int64_t>(),
+                   ext.as<unsigned long long>());
+        RB3_LAUNCH("smem_fix", k_smem_fix, grid_for(nseg, 256, 1 << 20), dim3(256), 0, c.stream,
+                   d_segs.as<Seg>(), nseg, cnt.as<uint32_t>(), first.as<int64_t>(), last.as<int64_t>(),
+                   drop.as<uint32_t>(), kept.as<uint32_t>());
+    }
+    RB3_TRY(scan_u32(c, kept.as<uint32_t>(), segoff.as<uint32_t>(), nseg + 1, false, false, nullptr));
+    RB3_LAUNCH("smem_qoff", k_smem_qoff, grid_for(nq + 1, 256, 1 << 20), dim3(256), 0, c.stream,
+               d_qseg.as<int64_t>(), nq, segoff.as<uint32_t>(), d_out_off);
+    unsigned long long htot = 0, hext = 0;
+    int64_t hkept = 0;
+    RB3_HIP(hipMemcpyAsync(&htot, tot.p, sizeof(htot), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipMemcpyAsync(&hext, ext.p, sizeof(hext), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipMemcpyAsync(&hkept, d_out_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
     RB3_HIP(hipStreamSynchronize(c.stream));
-    *h_total = (int64_t)tot;
-    if ((int64_t)tot <= cap && tot > 0)
-        RB3_LAUNCH("smem_order", k_smem_order, grid_for((int64_t)tot, 256 * 4), dim3(256), 0, c.stream, d_tmp,
-                   (int64_t)tot, d_off, d_out);
+    *h_kept = hkept;
+    *h_exts = (int64_t)hext;
+    if ((int64_t)htot <= cap && hkept <= out_cap && htot > 0)
+        RB3_LAUNCH("smem_order", k_smem_order, grid_for((int64_t)htot, 256 * 4), dim3(256), 0, c.stream, d_tmp,
+                   (int64_t)htot, d_segs.as<Seg>(), segoff.as<uint32_t>(), drop.as<uint32_t>(), d_out);
     return RB3_OK;
 }
 

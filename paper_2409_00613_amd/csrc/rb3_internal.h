@@ -340,8 +340,14 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
 // query.hip
 int count_queries(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *d_qoff,
                   int64_t nq, int64_t *d_lo, int64_t *d_hi);
-int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *d_qoff, int64_t nq,
-             int32_t min_len, int64_t min_occ, int64_t cap, rb3_smem_t *d_tmp, rb3_smem_t *d_out,
-             uint32_t *d_cnt, uint32_t *d_off, unsigned long long *d_total, int64_t *h_total);
+// Query positions per SMEM segment.
+constexpr int64_t SMEM_SEG = 1024;
+// SMEMs of nq queries (codes at d_q, host lengths qlens). d_out_off
+// (device, nq + 1) receives the per-query offsets; when all *h_kept reports
+// fit in out_cap they are written in order to d_out. *h_exts: bi-interval
+// extensions performed.
+int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlens, int64_t nq, int32_t min_len,
+             int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
+             int64_t *h_exts);
 
 }  // namespace rb3

@@ -43,7 +43,7 @@ SMEM_DTYPE = np.dtype([("start", np.int64), ("end", np.int64), ("occ", np.int64)
 assert SMEM_DTYPE.itemsize == ctypes.sizeof(SmemRec) == 48
 
 # Every function declared in include/rb3.h.
-EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_info",
+EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats", "rb3_info",
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
            "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats"]
 
@@ -83,6 +83,7 @@ def lib():
     L.rb3_count.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p]
     L.rb3_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, ctypes.POINTER(SmemRec), _i64, _i64p]
     L.rb3_info.argtypes = [_vp, _i64p, _i64p, _i64p]
+    L.rb3_last_smem_stats.argtypes = [_i64p]
     L.rb3_export.argtypes = [_vp, _vp]
     L.rb3_import.argtypes = [ctypes.POINTER(Opts), _vp, _i64, _i32, ctypes.POINTER(_vp)]
     L.rb3_clone.argtypes = [_vp, ctypes.POINTER(_vp)]
@@ -94,7 +95,7 @@ def lib():
     L.rb3_prof_reset.argtypes = []
     L.rb3_prof_read.argtypes = [ctypes.c_char_p, _i64p, ctypes.POINTER(ctypes.c_double), _i64, _i64p]
     L.rb3_merge_stats.argtypes = [_vp, ctypes.c_char_p, _i64p, _i64, _i64p]
-    for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_info", "rb3_export",
+    for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats", "rb3_info", "rb3_export",
                  "rb3_import", "rb3_clone", "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read",
                  "rb3_merge_stats"):
         getattr(L, name).restype = ctypes.c_int
@@ -265,6 +266,13 @@ def rb3_smem(idx: Index, q, qlens, min_len: int, min_occ: int = 1, cap: int | No
             continue
         _check(rc)
         return out[:off[-1]], off
+
+
+def rb3_last_smem_stats() -> dict:
+    """Work of this thread's last rb3_smem call."""
+    e = ctypes.c_int64()
+    _check(lib().rb3_last_smem_stats(ctypes.byref(e)))
+    return {"extensions": e.value}
 
 
 def rb3_info(idx: Index):

@@ -322,3 +322,31 @@ def test_clone_outlives_source(tiny):
     olo, ohi = oracle.count(codes, lens, qc, ql)
     assert np.array_equal(lo, olo) and np.array_equal(hi, ohi)
     cp.close()
+
+
+@pytest.mark.parametrize("min_len,min_occ", [(31, 1), (51, 1), (19, 3)])
+def test_smem_long_queries_across_segments(min_len, min_occ):
+    """Queries of several kilobases are cut into segments inside the library;
+    exact excerpts give one SMEM spanning every segment."""
+    say(f"case: long SMEM queries, min_len={min_len} min_occ={min_occ}")
+    w = synth.config_serving(genome_len=40_000, n_index=5, n_unseen=2, n_queries=12, log_lo=3.3, log_hi=4.3)
+    hap = w.index.get(2)
+    extra = synth.pack([hap[1000:9000], hap[20000:23100] + b"ACGTTGCA" + hap[23100:27000]])
+    qs = w.queries + extra
+    idx = rb3.rb3_build(w.index.data, w.index.lens)
+    recs, off = idx.smem(qs.data, qs.lens, min_len, min_occ)
+    codes, lens = _expand(w.index)
+    text = oracle.Text(codes, lens)
+    qc, ql = oracle.encode(qs.data, qs.lens)
+    qoff = np.concatenate([[0], np.cumsum(ql)])
+    for i in range(qs.n):
+        exp = text.smem(qc[qoff[i]:qoff[i + 1]], min_len, min_occ)
+        r = recs[off[i]:off[i + 1]]
+        got = np.stack([r["start"], r["end"], r["occ"], r["k"], r["krc"]], 1) if len(r) else np.zeros((0, 5), np.int64)
+        assert np.array_equal(got, exp), i
+    # the exact 8 kb excerpt is one SMEM covering the whole query
+    r = recs[off[qs.n - 2]:off[qs.n - 1]]
+    if min_occ == 1:
+        assert len(r) == 1 and r["start"][0] == 0 and r["end"][0] == 8000
+    assert rb3.rb3_last_smem_stats()["extensions"] > 0
+    idx.close()
