@@ -157,6 +157,57 @@ void rb3_index_free(rb3_index *idx);
 const char *rb3_strerror(int err);
 
 /*
+ * Continuous-batching query server over one index.
+ *
+ * Requests (count or SMEM queries, one string each) are submitted from any
+ * thread and answered asynchronously. Worker threads, each with its own HIP
+ * stream and device memory pool, take every pending request up to the batch
+ * limits whenever they are free, so requests that arrive while earlier
+ * batches are on the GPU are admitted as soon as a worker and the device
+ * memory budget allow, and batches overlap on the device. Results are the
+ * same as those of rb3_count / rb3_smem on the same queries, whatever the
+ * batching. The index must stay alive and must not be merged while a server
+ * uses it.
+ */
+typedef struct rb3_server rb3_server;
+
+enum { RB3_REQ_COUNT = 0, RB3_REQ_SMEM = 1 };
+
+typedef struct rb3_server_opts {
+    int32_t workers;            /* batches in flight at once (streams); default 4 */
+    int32_t pad;
+    int64_t max_batch_queries;  /* default 4096 */
+    int64_t max_batch_bases;    /* query bases per batch; default 8 Mi */
+    int64_t mem_budget;         /* device bytes for requests in flight; default 4 GiB */
+} rb3_server_opts;
+
+typedef struct rb3_result {
+    uint64_t ticket;
+    int32_t kind;               /* RB3_REQ_COUNT or RB3_REQ_SMEM */
+    int32_t status;             /* RB3_OK or the error of its batch */
+    int64_t lo, hi;             /* count: SA interval */
+    int64_t smem_off, n_smem;   /* SMEM: records recs[smem_off .. smem_off + n_smem) of the poll */
+} rb3_result;
+
+void rb3_server_opts_init(rb3_server_opts *so);
+int rb3_server_create(const rb3_index *idx, const rb3_server_opts *so, rb3_server **out);
+/* Queue one request; the query is copied. min_len / min_occ are used by SMEM
+ * requests (>= 1). Invalid bytes give RB3_EINVAL at submission. */
+int rb3_server_submit(rb3_server *s, int32_t kind, const uint8_t *q, int64_t len, int32_t min_len,
+                      int64_t min_occ, uint64_t *ticket);
+/* Move finished results into res (res_cap entries) and their SMEM records into
+ * recs (rec_cap entries). Waits up to wait_ms for a first result when none is
+ * ready. RB3_ENOSPC (with *n_recs = records needed) when the next result does
+ * not fit in an empty record buffer. */
+int rb3_server_poll(rb3_server *s, int32_t wait_ms, rb3_result *res, int64_t res_cap, rb3_smem_t *recs,
+                    int64_t rec_cap, int64_t *n_res, int64_t *n_recs);
+/* Queue length, batches in flight, batches run, requests served, largest batch. */
+int rb3_server_stats(rb3_server *s, int64_t *queued, int64_t *inflight, int64_t *batches, int64_t *served,
+                     int64_t *max_batch);
+/* Stops the workers after their current batches; unpolled results are dropped. */
+void rb3_server_free(rb3_server *s);
+
+/*
  * Kernel timing. While enabled, every kernel the library launches is
  * bracketed by HIP events on the stream it runs on. rb3_prof_read
  * synchronizes those events and reports, per kernel name, the number of

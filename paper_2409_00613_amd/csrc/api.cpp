@@ -273,6 +273,63 @@ static int do_merge(Ctx &c, IndexData &d, const uint8_t *seq, const int64_t *len
     return RB3_OK;
 }
 
+
+int run_count(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
+              int32_t mem, int64_t *lo, int64_t *hi) {
+    DBuf hold, codes, err, off, dlo, dhi;
+    const uint8_t *d_q = nullptr;
+    RB3_TRY(stage(c, q, total, mem, hold, &d_q));
+    RB3_ALLOC(codes, &c, total > 0 ? total : 1);
+    RB3_ALLOC(err, &c, sizeof(int32_t));
+    RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
+    RB3_TRY(encode_plain(c, d_q, qlens, n_q, codes.as<uint8_t>(), total, err.as<int32_t>()));
+    std::vector<int64_t> hoff(n_q + 1);
+    hoff[0] = 0;
+    for (int64_t i = 0; i < n_q; ++i) hoff[i + 1] = hoff[i] + qlens[i];
+    RB3_ALLOC(off, &c, (n_q + 1) * sizeof(int64_t));
+    RB3_ALLOC(dlo, &c, n_q * sizeof(int64_t));
+    RB3_ALLOC(dhi, &c, n_q * sizeof(int64_t));
+    RB3_HIP(hipMemcpyAsync(off.p, hoff.data(), (n_q + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+    int32_t bad = 0;
+    RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
+    if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in a query");
+    RB3_TRY(count_queries(c, ix, codes.as<uint8_t>(), off.as<int64_t>(), n_q, dlo.as<int64_t>(), dhi.as<int64_t>()));
+    RB3_HIP(hipMemcpyAsync(lo, dlo.p, n_q * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipMemcpyAsync(hi, dhi.p, n_q * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipStreamSynchronize(c.stream));
+    return RB3_OK;
+}
+
+int run_smem(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
+             int32_t mem, int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off,
+             int64_t *exts) {
+    DBuf hold, codes, err, ordered, coff;
+    const uint8_t *d_q = nullptr;
+    RB3_TRY(stage(c, q, total, mem, hold, &d_q));
+    RB3_ALLOC(codes, &c, total > 0 ? total : 1);
+    RB3_ALLOC(err, &c, sizeof(int32_t));
+    RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
+    RB3_TRY(encode_plain(c, d_q, qlens, n_q, codes.as<uint8_t>(), total, err.as<int32_t>()));
+    int32_t bad = 0;
+    RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
+    if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in a query");
+    RB3_ALLOC(ordered, &c, (out_cap > 0 ? out_cap : 1) * sizeof(rb3_smem_t));
+    RB3_ALLOC(coff, &c, (n_q + 1) * sizeof(int64_t));
+    int64_t kept = 0;
+    RB3_TRY(smem_run(c, ix, codes.as<uint8_t>(), qlens, n_q, min_len, min_occ, out_cap, ordered.as<rb3_smem_t>(),
+                     coff.as<int64_t>(), &kept, exts));
+    RB3_HIP(hipMemcpyAsync(out_off, coff.p, (n_q + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    if (kept <= out_cap && kept > 0)
+        RB3_HIP(hipMemcpyAsync(out, ordered.p, kept * sizeof(rb3_smem_t), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipStreamSynchronize(c.stream));
+    if (kept > out_cap) return fail(RB3_ENOSPC, "SMEM output buffer too small; out_off holds the sizes");
+    return RB3_OK;
+}
+
+const DevIndex index_dev(const rb3_index *idx) { return idx->d.dev(); }
+int index_device(const rb3_index *idx) { return idx->d.ctx.device; }
+int32_t index_both(const rb3_index *idx) { return idx->d.ctx.both; }
+
 }  // namespace rb3
 
 using namespace rb3;
@@ -341,30 +398,7 @@ int rb3_count(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int6
     if (n_q == 0) return RB3_OK;
     RB3_HIP(hipSetDevice(idx->d.ctx.device));
     Ctx c = call_ctx(idx->d);
-    int rc = [&]() -> int {
-        DBuf hold, codes, err, off, dlo, dhi;
-        const uint8_t *d_q = nullptr;
-        RB3_TRY(stage(c, q, total, mem, hold, &d_q));
-        RB3_ALLOC(codes, &c, total > 0 ? total : 1);
-        RB3_ALLOC(err, &c, sizeof(int32_t));
-        RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
-        RB3_TRY(encode_plain(c, d_q, qlens, n_q, codes.as<uint8_t>(), total, err.as<int32_t>()));
-        std::vector<int64_t> hoff(n_q + 1);
-        hoff[0] = 0;
-        for (int64_t i = 0; i < n_q; ++i) hoff[i + 1] = hoff[i] + qlens[i];
-        RB3_ALLOC(off, &c, (n_q + 1) * sizeof(int64_t));
-        RB3_ALLOC(dlo, &c, n_q * sizeof(int64_t));
-        RB3_ALLOC(dhi, &c, n_q * sizeof(int64_t));
-        RB3_HIP(hipMemcpyAsync(off.p, hoff.data(), (n_q + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
-        int32_t bad = 0;
-        RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
-        if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in a query");
-        RB3_TRY(count_queries(c, idx->d.dev(), codes.as<uint8_t>(), off.as<int64_t>(), n_q, dlo.as<int64_t>(),
-                              dhi.as<int64_t>()));
-        RB3_HIP(hipMemcpyAsync(lo, dlo.p, n_q * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
-        RB3_HIP(hipMemcpyAsync(hi, dhi.p, n_q * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
-        return RB3_OK;
-    }();
+    int rc = run_count(c, idx->d.dev(), q, qlens, n_q, total, mem, lo, hi);
     return finish(c, rc);
 }
 
@@ -382,30 +416,9 @@ int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64
     if (n_q == 0) return RB3_OK;
     RB3_HIP(hipSetDevice(idx->d.ctx.device));
     Ctx c = call_ctx(idx->d);
-    int rc = [&]() -> int {
-        DBuf hold, codes, err, ordered, coff;
-        const uint8_t *d_q = nullptr;
-        RB3_TRY(stage(c, q, total, mem, hold, &d_q));
-        RB3_ALLOC(codes, &c, total > 0 ? total : 1);
-        RB3_ALLOC(err, &c, sizeof(int32_t));
-        RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
-        RB3_TRY(encode_plain(c, d_q, qlens, n_q, codes.as<uint8_t>(), total, err.as<int32_t>()));
-        int32_t bad = 0;
-        RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
-        if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in a query");
-        RB3_ALLOC(ordered, &c, (out_cap > 0 ? out_cap : 1) * sizeof(rb3_smem_t));
-        RB3_ALLOC(coff, &c, (n_q + 1) * sizeof(int64_t));
-        int64_t kept = 0, exts = 0;
-        RB3_TRY(smem_run(c, idx->d.dev(), codes.as<uint8_t>(), qlens, n_q, min_len, min_occ, out_cap,
-                         ordered.as<rb3_smem_t>(), coff.as<int64_t>(), &kept, &exts));
-        RB3_HIP(hipMemcpyAsync(out_off, coff.p, (n_q + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
-        if (kept <= out_cap && kept > 0)
-            RB3_HIP(hipMemcpyAsync(out, ordered.p, kept * sizeof(rb3_smem_t), hipMemcpyDeviceToHost, c.stream));
-        RB3_HIP(hipStreamSynchronize(c.stream));
-        g_last_smem_exts = exts;
-        if (kept > out_cap) return fail(RB3_ENOSPC, "SMEM output buffer too small; out_off holds the sizes");
-        return RB3_OK;
-    }();
+    int64_t exts = 0;
+    int rc = run_smem(c, idx->d.dev(), q, qlens, n_q, total, mem, min_len, min_occ, out, out_cap, out_off, &exts);
+    if (rc == RB3_OK) g_last_smem_exts = exts;
     return finish(c, rc);
 }
 

@@ -350,4 +350,15 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
              int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
              int64_t *h_exts);
 
+// api.cpp: one synchronous count / SMEM call on a context's stream (the
+// caller flushes the context afterwards). total = sum of qlens.
+int run_count(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
+              int32_t mem, int64_t *lo, int64_t *hi);
+int run_smem(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
+             int32_t mem, int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off,
+             int64_t *exts);
+const DevIndex index_dev(const rb3_index *idx);
+int index_device(const rb3_index *idx);
+int32_t index_both(const rb3_index *idx);
+
 }  // namespace rb3

@@ -45,7 +45,22 @@ assert SMEM_DTYPE.itemsize == ctypes.sizeof(SmemRec) == 48
 # Every function declared in include/rb3.h.
 EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats", "rb3_info",
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
-           "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats"]
+           "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats",
+           "rb3_server_opts_init", "rb3_server_create", "rb3_server_submit", "rb3_server_poll",
+           "rb3_server_stats", "rb3_server_free"]
+
+RB3_REQ_COUNT, RB3_REQ_SMEM = 0, 1
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("pad", ctypes.c_int32), ("max_batch_queries", ctypes.c_int64),
+                ("max_batch_bases", ctypes.c_int64), ("mem_budget", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("kind", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("lo", ctypes.c_int64), ("hi", ctypes.c_int64), ("smem_off", ctypes.c_int64),
+                ("n_smem", ctypes.c_int64)]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -95,6 +110,17 @@ def lib():
     L.rb3_prof_reset.argtypes = []
     L.rb3_prof_read.argtypes = [ctypes.c_char_p, _i64p, ctypes.POINTER(ctypes.c_double), _i64, _i64p]
     L.rb3_merge_stats.argtypes = [_vp, ctypes.c_char_p, _i64p, _i64, _i64p]
+    L.rb3_server_opts_init.argtypes = [ctypes.POINTER(ServerOpts)]
+    L.rb3_server_opts_init.restype = None
+    L.rb3_server_create.argtypes = [_vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
+    L.rb3_server_submit.argtypes = [_vp, _i32, _vp, _i64, _i32, _i64, ctypes.POINTER(ctypes.c_uint64)]
+    L.rb3_server_poll.argtypes = [_vp, _i32, ctypes.POINTER(Result), _i64, ctypes.POINTER(SmemRec), _i64,
+                                  _i64p, _i64p]
+    L.rb3_server_stats.argtypes = [_vp, _i64p, _i64p, _i64p, _i64p, _i64p]
+    L.rb3_server_free.argtypes = [_vp]
+    L.rb3_server_free.restype = None
+    for name in ("rb3_server_create", "rb3_server_submit", "rb3_server_poll", "rb3_server_stats"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats", "rb3_info", "rb3_export",
                  "rb3_import", "rb3_clone", "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read",
                  "rb3_merge_stats"):
@@ -335,3 +361,74 @@ def rb3_prof_read() -> dict:
     raw = names.raw
     return {raw[i * 32:(i + 1) * 32].split(b"\0")[0].decode(): (int(launches[i]), float(ms[i]))
             for i in range(min(n.value, cap))}
+
+
+class Server:
+    """rb3_server: continuous-batching count / SMEM service over an Index."""
+
+    def __init__(self, idx: Index, workers: int = 4, max_batch_queries: int = 4096,
+                 max_batch_bases: int = 8 << 20, mem_budget: int = 4 << 30):
+        L = lib()
+        so = ServerOpts()
+        L.rb3_server_opts_init(ctypes.byref(so))
+        so.workers = workers
+        so.max_batch_queries = max_batch_queries
+        so.max_batch_bases = max_batch_bases
+        so.mem_budget = mem_budget
+        h = ctypes.c_void_p()
+        _check(L.rb3_server_create(idx.handle, ctypes.byref(so), ctypes.byref(h)))
+        self._h = h
+        self._idx = idx  # keep the index alive
+        self._res = (Result * 4096)()
+        self._cap = 1 << 16
+        self._recs = np.zeros(self._cap, dtype=SMEM_DTYPE)
+
+    def submit(self, kind: int, q: bytes, min_len: int = 0, min_occ: int = 1) -> int:
+        t = ctypes.c_uint64()
+        buf = np.frombuffer(q, dtype=np.uint8) if len(q) else np.zeros(1, np.uint8)
+        _check(lib().rb3_server_submit(self._h, kind, buf.ctypes.data, len(q), int(min_len), int(min_occ),
+                                       ctypes.byref(t)))
+        return t.value
+
+    def poll(self, wait_ms: int = 0) -> list:
+        """Finished results: dicts with ticket, kind, status, and lo/hi
+        (count) or records (SMEM, structured array)."""
+        out = []
+        while True:
+            nr = ctypes.c_int64()
+            nk = ctypes.c_int64()
+            rc = lib().rb3_server_poll(self._h, int(wait_ms), self._res, len(self._res),
+                                       self._recs.ctypes.data_as(ctypes.POINTER(SmemRec)), self._cap,
+                                       ctypes.byref(nr), ctypes.byref(nk))
+            if rc == RB3_ENOSPC:
+                self._cap = max(2 * self._cap, int(nk.value))
+                self._recs = np.zeros(self._cap, dtype=SMEM_DTYPE)
+                continue
+            _check(rc)
+            for i in range(nr.value):
+                r = self._res[i]
+                d = {"ticket": int(r.ticket), "kind": int(r.kind), "status": int(r.status)}
+                if r.kind == RB3_REQ_COUNT:
+                    d["lo"], d["hi"] = int(r.lo), int(r.hi)
+                else:
+                    d["records"] = self._recs[r.smem_off:r.smem_off + r.n_smem].copy()
+                out.append(d)
+            if nr.value < len(self._res):
+                return out
+            wait_ms = 0
+
+    def stats(self) -> dict:
+        v = [ctypes.c_int64() for _ in range(5)]
+        _check(lib().rb3_server_stats(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["queued", "inflight", "batches", "served", "max_batch"], [x.value for x in v]))
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().rb3_server_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
