@@ -114,6 +114,86 @@ def cpu_baseline(sample_len: int, threads: int):
                       f"{dt:.2f} s"}
 
 
+def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, rates: list[float],
+               served_queries: int, min_len: int = 31, steps: int = 2):
+    """SMEM finding on a serving-shaped workload: closed-loop batched
+    throughput, the plain one-query-per-call form, and served latency under
+    Poisson arrivals at fractions of the batched saturation rate."""
+    import synth
+    from paper_2409_00613_amd import rb3
+    t = time.perf_counter()
+    w = synth.config_serving(genome_len=genome, n_index=n_index, n_unseen=8, n_queries=n_queries)
+    log(f"serving workload: {n_index} haplotypes of ~{genome} bases, {n_queries} queries "
+        f"({w.queries.total} bases) in {time.perf_counter() - t:.1f} s")
+    t = time.perf_counter()
+    # batches of 32 haplotypes keep every merge below the per-batch size limit
+    idx = rb3.rb3_build(w.index.slice(0, min(32, n_index)).data, w.index.slice(0, min(32, n_index)).lens)
+    for a in range(32, n_index, 32):
+        part = w.index.slice(a, min(a + 32, n_index))
+        idx.merge(part.data, part.lens)
+        log(f"  merged haplotypes {a}..{min(a + 32, n_index) - 1}")
+    n, m, _ = idx.info()
+    log(f"query index: n={n} in {time.perf_counter() - t:.1f} s")
+    bases = w.queries.total
+    import torch
+    qdev = torch.from_numpy(w.queries.data).cuda()  # queries resident in HBM before timing
+    torch.cuda.synchronize()
+    idx.smem(qdev, w.queries.lens, min_len)  # warm-up
+    rb3.rb3_prof_reset()
+    rb3.rb3_prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        recs, off = idx.smem(qdev, w.queries.lens, min_len)
+    t1 = time.perf_counter()
+    rb3.rb3_prof_enable(False)
+    prof = rb3.rb3_prof_read()
+    exts = rb3.rb3_last_smem_stats()["extensions"]
+    batched = bases * steps / (t1 - t0)
+    qps = n_queries * steps / (t1 - t0)
+    k_ms = prof.get("smem", (0, 0.0))[1] / steps
+    roof = None
+    if k_ms > 0:
+        ab = exts * 2 * BLOCK_BYTES
+        ach = ab / (k_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": "smem", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes_per_launch": ab,
+                "avg_launch_ms": k_ms, "extensions_per_base": round(exts / bases, 3)}
+    log(f"SMEM batched: {batched / 1e9:.3f} G bases/s, {qps:.0f} queries/s, {len(recs)} SMEMs, "
+        f"{exts} extensions, smem kernel {k_ms:.2f} ms")
+    # plain form: one query per call
+    k = min(plain_queries, n_queries)
+    pq = w.queries.slice(0, k)
+    t0 = time.perf_counter()
+    for i in range(k):
+        one = pq.slice(i, i + 1)
+        idx.smem(one.data, one.lens, min_len)
+    t1 = time.perf_counter()
+    plain = pq.total / (t1 - t0)
+    log(f"SMEM plain (one query per call, {k} queries): {plain / 1e9:.4f} G bases/s")
+    served = []
+    srv = rb3.Server(idx, workers=4)
+    m_served = min(served_queries, n_queries)
+    sq = w.queries.slice(0, m_served)
+    for frac in rates:
+        lam = frac * qps
+        arr = synth.poisson_arrivals(m_served, lam)
+        lat, wall = srv.replay(rb3.RB3_REQ_SMEM, sq.data, sq.lens, arr, min_len, 1)
+        served.append({"load": frac, "qps": round(lam, 1), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                       "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                       "bases_per_s": round(sq.total / wall, 1), "queries": m_served})
+        log(f"SMEM served at {frac:.2f} x saturation ({lam:.0f} q/s): p50 {served[-1]['p50_ms']} ms, "
+            f"p99 {served[-1]['p99_ms']} ms")
+    st = srv.stats()
+    srv.close()
+    idx.close()
+    return {"metric": "SMEM query bases/s", "value": round(batched, 1), "unit": "bases/s",
+            "plain_one_query_per_call": round(plain, 1), "served": served, "server": st,
+            "config": {"workload": "serving", "genome_len": genome, "haplotypes_indexed": n_index,
+                       "both_strands": True, "n": n, "queries": n_queries, "query_bases": bases,
+                       "min_len": min_len, "min_occ": 1, "query_lengths": "log-uniform 100-100000"},
+            "roofline": roof}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +204,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=40_000,
                     help="haplotype prefix length for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-smem", action="store_true", help="skip the SMEM serving measurement")
+    ap.add_argument("--workload", default="pangenome_merge", choices=["pangenome_merge", "serving"],
+                    help="serving: the full serving configuration (320 haplotypes) only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (three times) and exit; "
                          "used to scale hardware byte counters")
@@ -152,6 +235,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "serving":
+        res = smem_bench(10_000_000, 320, 10_000, 500, [0.25, 0.5, 0.8], 10_000)
+        res.update({"n_gpus": 1, "steps": 2, "warmup": 1, "higher_is_better": True, "scaling": "weak",
+                    "vs_baseline": None, "dtype": "int64", "data": "synthetic"})
+        print(json.dumps(res), flush=True)
+        return
     workload = "pangenome_merge"
     t = time.perf_counter()
     w = synth.config_pangenome(genome_len=args.genome)
@@ -221,6 +310,11 @@ def main():
         cpu = cpu_baseline(args.cpu_sample, threads)
         log(f"oracle: {cpu['value']:.3g} suffixes/s ({cpu['sample']})")
 
+    smem = None
+    if not args.no_smem:
+        b1.close()
+        smem = smem_bench(10_000_000, 32, 2000, 200, [0.5], 2000)
+
     out = {
         "metric": "BWT-merge suffixes inserted/s",
         "value": round(value, 1),
@@ -239,6 +333,7 @@ def main():
                    "n_merged": n_out, "chunk_len": st["chunk_len"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "smem": smem,
         "merge_stats": st,
         "kernels": kernels,
         "source_hash": src_hash,

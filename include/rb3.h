@@ -204,6 +204,15 @@ int rb3_server_poll(rb3_server *s, int32_t wait_ms, rb3_result *res, int64_t res
 /* Queue length, batches in flight, batches run, requests served, largest batch. */
 int rb3_server_stats(rb3_server *s, int64_t *queued, int64_t *inflight, int64_t *batches, int64_t *served,
                      int64_t *max_batch);
+/* Open-loop request driver for latency measurement: submits query i (kind,
+ * min_len, min_occ shared) at arrival_s[i] seconds after the call starts
+ * (arrival times non-decreasing), polls from a second thread, and writes
+ * latency_s[i] = time from the arrival to the result. *wall_s (may be NULL)
+ * receives the time until the last result. The results themselves are
+ * discarded. The call returns after every accepted request is answered. */
+int rb3_server_replay(rb3_server *s, int32_t kind, const uint8_t *q, const int64_t *qlens, int64_t n,
+                      int32_t min_len, int64_t min_occ, const double *arrival_s, double *latency_s,
+                      double *wall_s);
 /* Stops the workers after their current batches; unpolled results are dropped. */
 void rb3_server_free(rb3_server *s);
 

@@ -330,7 +330,13 @@ __global__ void k_smem_order(const rb3_smem_t *__restrict__ tmp, int64_t total, 
 int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlens, int64_t nq, int32_t min_len,
              int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
              int64_t *h_exts) {
-    // segment table
+    // segment table: segments short enough that the batch fills the GPU
+    // with lanes (each segment repeats about one SMEM's worth of work at its
+    // start, so not shorter than SMEM_SEG_MIN)
+    int64_t bases = 0;
+    for (int64_t qq = 0; qq < nq; ++qq) bases += qlens[qq];
+    int64_t S = bases / SMEM_TARGET_SEGS;
+    S = S < SMEM_SEG_MIN ? SMEM_SEG_MIN : (S > SMEM_SEG ? SMEM_SEG : S);
     std::vector<Seg> segs;
     std::vector<int64_t> qseg(nq + 1);
     int64_t off = 0;
@@ -338,13 +344,13 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
         qseg[qq] = (int64_t)segs.size();
         int64_t L = qlens[qq];
         if (L >= min_len) {
-            for (int64_t c0 = 0; c0 < L; c0 += SMEM_SEG) {
+            for (int64_t c0 = 0; c0 < L; c0 += S) {
                 Seg sg;
                 sg.qoff = off;
                 sg.qlen = (int32_t)L;
                 sg.qid = (int32_t)qq;
                 sg.c0 = (int32_t)c0;
-                sg.c1 = (int32_t)(c0 + SMEM_SEG < L ? c0 + SMEM_SEG : L);
+                sg.c1 = (int32_t)(c0 + S < L ? c0 + S : L);
                 segs.push_back(sg);
             }
         }

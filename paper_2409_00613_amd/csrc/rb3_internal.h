@@ -340,8 +340,11 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
 // query.hip
 int count_queries(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *d_qoff,
                   int64_t nq, int64_t *d_lo, int64_t *d_hi);
-// Query positions per SMEM segment.
-constexpr int64_t SMEM_SEG = 1024;
+// Query positions per SMEM segment: the batch's bases over
+// SMEM_TARGET_SEGS, within [SMEM_SEG_MIN, SMEM_SEG].
+constexpr int64_t SMEM_SEG = 4096;
+constexpr int64_t SMEM_SEG_MIN = 128;
+constexpr int64_t SMEM_TARGET_SEGS = 131072;
 // SMEMs of nq queries (codes at d_q, host lengths qlens). d_out_off
 // (device, nq + 1) receives the per-query offsets; when all *h_kept reports
 // fit in out_cap they are written in order to d_out. *h_exts: bi-interval

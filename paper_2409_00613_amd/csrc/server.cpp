@@ -10,6 +10,7 @@
 // rb3_count / rb3_smem.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -363,6 +364,68 @@ int rb3_server_stats(rb3_server *s, int64_t *queued, int64_t *inflight, int64_t 
     if (batches) *batches = s->batches;
     if (served) *served = s->served;
     if (max_batch) *max_batch = s->max_batch;
+    return RB3_OK;
+}
+
+int rb3_server_replay(rb3_server *s, int32_t kind, const uint8_t *q, const int64_t *qlens, int64_t n,
+                      int32_t min_len, int64_t min_occ, const double *arrival_s, double *latency_s,
+                      double *wall_s) {
+    if (!s || n < 0 || (n > 0 && (!qlens || !arrival_s || !latency_s))) {
+        set_error(RB3_EINVAL, "bad argument");
+        return RB3_EINVAL;
+    }
+    using clk = std::chrono::steady_clock;
+    std::vector<int64_t> off(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + qlens[i];
+    std::map<uint64_t, int64_t> who;
+    std::mutex wmu;
+    std::vector<int32_t> status(n, RB3_OK);
+    std::atomic<int64_t> expected(n);  // results still to come; lowered by failed submissions
+    const auto t0 = clk::now();
+    auto since = [&](clk::time_point t) { return std::chrono::duration<double>(t - t0).count(); };
+    std::thread poller([&] {
+        std::vector<rb3_result> res(1024);
+        std::vector<rb3_smem_t> recs(1 << 16);
+        int64_t got = 0;
+        while (got < expected.load()) {
+            int64_t nr = 0, nk = 0;
+            int rc = rb3_server_poll(s, 20, res.data(), (int64_t)res.size(), recs.data(), (int64_t)recs.size(), &nr,
+                                     &nk);
+            if (rc == RB3_ENOSPC) {
+                recs.resize((size_t)nk * 2);
+                continue;
+            }
+            double now = since(clk::now());
+            std::lock_guard<std::mutex> lk(wmu);
+            for (int64_t k = 0; k < nr; ++k) {
+                auto it = who.find(res[k].ticket);
+                if (it == who.end()) continue;  // a result of another client's request
+                latency_s[it->second] = now - arrival_s[it->second];
+                status[it->second] = res[k].status;
+                ++got;
+            }
+        }
+    });
+    for (int64_t i = 0; i < n; ++i) {
+        while (since(clk::now()) < arrival_s[i]) std::this_thread::yield();
+        uint64_t t = 0;
+        std::lock_guard<std::mutex> lk(wmu);
+        int rc = rb3_server_submit(s, kind, q + off[i], qlens[i], min_len, min_occ, &t);
+        if (rc != RB3_OK) {
+            latency_s[i] = -1;
+            status[i] = rc;
+            expected.fetch_sub(1);
+        } else {
+            who[t] = i;
+        }
+    }
+    poller.join();
+    if (wall_s) *wall_s = since(clk::now());
+    for (int64_t i = 0; i < n; ++i)
+        if (status[i] != RB3_OK) {
+            set_error(status[i], "a request failed");
+            return status[i];
+        }
     return RB3_OK;
 }
 

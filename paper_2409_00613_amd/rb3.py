@@ -47,7 +47,7 @@ EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
            "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats",
            "rb3_server_opts_init", "rb3_server_create", "rb3_server_submit", "rb3_server_poll",
-           "rb3_server_stats", "rb3_server_free"]
+           "rb3_server_stats", "rb3_server_replay", "rb3_server_free"]
 
 RB3_REQ_COUNT, RB3_REQ_SMEM = 0, 1
 
@@ -117,9 +117,12 @@ def lib():
     L.rb3_server_poll.argtypes = [_vp, _i32, ctypes.POINTER(Result), _i64, ctypes.POINTER(SmemRec), _i64,
                                   _i64p, _i64p]
     L.rb3_server_stats.argtypes = [_vp, _i64p, _i64p, _i64p, _i64p, _i64p]
+    _dp = ctypes.POINTER(ctypes.c_double)
+    L.rb3_server_replay.argtypes = [_vp, _i32, _vp, _i64p, _i64, _i32, _i64, _dp, _dp, _dp]
     L.rb3_server_free.argtypes = [_vp]
     L.rb3_server_free.restype = None
-    for name in ("rb3_server_create", "rb3_server_submit", "rb3_server_poll", "rb3_server_stats"):
+    for name in ("rb3_server_create", "rb3_server_submit", "rb3_server_poll", "rb3_server_stats",
+                 "rb3_server_replay"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats", "rb3_info", "rb3_export",
                  "rb3_import", "rb3_clone", "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read",
@@ -416,6 +419,20 @@ class Server:
             if nr.value < len(self._res):
                 return out
             wait_ms = 0
+
+    def replay(self, kind: int, data, lens, arrival_s, min_len: int = 0, min_occ: int = 1):
+        """Open-loop run: query i is submitted at arrival_s[i]; returns
+        (latencies in seconds, wall time)."""
+        d = np.ascontiguousarray(data, dtype=np.uint8)
+        la, lp = _lens(lens)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        lat = np.zeros(max(1, la.shape[0]), np.float64)
+        wall = ctypes.c_double()
+        _dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().rb3_server_replay(self._h, kind, d.ctypes.data if d.size else None, lp, la.shape[0],
+                                       int(min_len), int(min_occ), arr.ctypes.data_as(_dp),
+                                       lat.ctypes.data_as(_dp), ctypes.byref(wall)))
+        return lat[:la.shape[0]], wall.value
 
     def stats(self) -> dict:
         v = [ctypes.c_int64() for _ in range(5)]
