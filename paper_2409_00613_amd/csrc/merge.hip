@@ -73,16 +73,16 @@ struct KeyWindow {
         vm = ((vm << 1) | (valid ? 1u : 0u)) & 0xFFu;
     }
     __device__ __forceinline__ void flush(uint64_t *__restrict__ K, int64_t p) {
+        // the keys are streamed out: non-temporal stores keep them from
+        // displacing the index in the caches
         if (vm == 0xFFu && (p & 7) == 0) {
-            uint4 *dst = (uint4 *)(K + p);
+            uint64_t *dst = K + p;
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                dst[j] = make_uint4((uint32_t)b[2 * j], (uint32_t)(b[2 * j] >> 32), (uint32_t)b[2 * j + 1],
-                                    (uint32_t)(b[2 * j + 1] >> 32));
+            for (int j = 0; j < 8; ++j) __builtin_nontemporal_store(b[j], dst + j);
         } else {
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                if ((vm >> j) & 1u) K[p + j] = b[j];
+                if ((vm >> j) & 1u) __builtin_nontemporal_store(b[j], K + p + j);
         }
         vm = 0;
     }
@@ -360,14 +360,18 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
-// Each workgroup scans a contiguous range of the sorted keys; group starts
-// in the range measure their group, and the groups whose members carry
-// different symbols are appended, by size class (2 members, 3..8, more),
-// to three lists with one atomic per class per workgroup. Each list entry
-// is (first sorted index, member count).
+// Tied groups, found with coalesced reads: each wave looks at 64 consecutive
+// sorted keys (one per lane). Group starts come from a ballot; a group that
+// starts and ends inside the window has its size from the next start and
+// its mixed-symbol test from a ballot of members whose BWT symbol differs
+// from their group leader's. Only the group reaching past the window's end
+// is measured with a serial scan. Groups whose members carry different
+// symbols are collected per workgroup in LDS, by size class (2 members,
+// 3..8, more), and flushed to three global lists of (first sorted index,
+// member count) with one atomic per class per flush.
 constexpr int TG_THREADS = 256;
-constexpr int TG_ITEMS = 8;
 constexpr int TG_CLASSES = 3;
+constexpr int TG_LCAP = 1024;  // LDS list capacity per class
 
 __device__ __forceinline__ int group_class(uint32_t k) { return k == 2 ? 0 : (k <= 8 ? 1 : 2); }
 
@@ -376,87 +380,107 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
                                                            uint32_t *__restrict__ l2,
                                                            uint32_t *__restrict__ gstat,
                                                            unsigned long long *__restrict__ tied) {
-    __shared__ uint32_t wcnt[TG_CLASSES][TG_THREADS / 64];
-    __shared__ uint64_t wtied[TG_THREADS / 64];
-    __shared__ uint32_t wmax[TG_THREADS / 64];
-    __shared__ uint32_t base_slot[TG_CLASSES];
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ uint32_t lst[TG_CLASSES][TG_LCAP][2];
+    __shared__ uint32_t lcnt[TG_CLASSES];
+    __shared__ uint32_t lbase[TG_CLASSES];
+    __shared__ unsigned long long wt[TG_THREADS / 64];
+    __shared__ uint32_t wm[TG_THREADS / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     uint32_t *lists[TG_CLASSES] = {l0, l1, l2};
-    const int64_t per_block = (int64_t)TG_THREADS * TG_ITEMS;
-    for (int64_t blk0 = blockIdx.x * per_block; blk0 < n; blk0 += (int64_t)gridDim.x * per_block) {
-        uint32_t my_s[TG_ITEMS], my_k[TG_ITEMS];
-        uint32_t nmine = 0, kmax = 0;
-        uint32_t ncls[TG_CLASSES] = {0, 0, 0};
-        uint64_t ntied = 0;
-        for (int it = 0; it < TG_ITEMS; ++it) {
-            int64_t s = blk0 + (int64_t)it * TG_THREADS + threadIdx.x;
-            if (s >= n || !starts_group(SK, s)) continue;
-            uint64_t key = SK[s] >> 3;
-            if ((key & 7) == 0) continue;
-            uint32_t e0 = (uint32_t)(SK[s] & 7);
-            bool uni = true;
-            int64_t t = s + 1;
-            while (t < n && (SK[t] >> 3) == key) {
-                uni &= (uint32_t)(SK[t] & 7) == e0;
-                ++t;
-            }
-            int64_t k = t - s;
-            if (k < 2) continue;
-            ntied += (uint64_t)k;
-            if (!uni) {
-                uint32_t kk = (uint32_t)(k > 0xFFFFFFFFll ? 0xFFFFFFFFll : k);
-                my_s[nmine] = (uint32_t)s;
-                my_k[nmine] = kk;
-                ++nmine;
-                ncls[group_class(kk)] += 1;
-                kmax = kk > kmax ? kk : kmax;
+    if (threadIdx.x < TG_CLASSES) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t ntied = 0;
+    uint32_t kmax = 0;
+    const int64_t ntiles = (n + TG_THREADS - 1) / TG_THREADS;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t w0 = tile * TG_THREADS + (int64_t)wv * 64;
+        const int64_t s = w0 + lane;
+        const bool in = s < n;
+        const uint64_t v = in ? SK[s] : ~0ull;
+        const uint64_t key = v >> 3;
+        const uint32_t e = (uint32_t)(v & 7);
+        uint64_t prevkey = __shfl_up(key, 1);
+        if (lane == 0) prevkey = (s > 0 && in) ? (SK[s - 1] >> 3) : ~0ull;
+        // a key holding its sentinel is unique: always a group of its own
+        const bool sent = (key & 7) == 0;
+        const bool start = in && (s == 0 || sent || key != prevkey);
+        const uint64_t smask = __ballot(start);
+        const uint64_t inmask = __ballot(in);
+        // leader of my group inside the window (lane of the last start at or below me)
+        const uint64_t below = smask & low_mask(lane + 1);
+        const int lead = below ? 63 - __clzll((long long)below) : -1;
+        const uint32_t le = __shfl(e, lead < 0 ? 0 : lead);
+        const bool mism = in && lead >= 0 && e != le;
+        const uint64_t mmask = __ballot(mism);
+        // the window's last group may run past its end: the whole wave
+        // extends it with coalesced 64-key reads of the following windows
+        const int last_in = inmask ? 63 - __clzll((long long)inmask) : -1;
+        const int ls = smask ? 63 - __clzll((long long)smask) : -1;
+        const uint64_t xkey = __shfl(key, ls < 0 ? 0 : ls);
+        const uint32_t xe = __shfl(e, ls < 0 ? 0 : ls);
+        int64_t ext = 0;
+        bool xuni = true;
+        if (ls >= 0 && last_in == 63 && (xkey & 7) != 0) {
+            for (int64_t t = w0 + 64; t < n; t += 64) {
+                const int64_t u = t + lane;
+                const uint64_t uv = u < n ? SK[u] : ~0ull;
+                const uint64_t mm = __ballot((uv >> 3) == xkey);
+                const int run = ~mm ? __ffsll((unsigned long long)~mm) - 1 : 64;
+                if (__ballot(lane < run && (uint32_t)(uv & 7) != xe)) xuni = false;
+                ext += run;
+                if (run < 64) break;
             }
         }
-        uint32_t incl[TG_CLASSES];
+        if (start && !sent) {
+            const uint64_t above = smask & ~low_mask(lane + 1);
+            const int ns = above ? __ffsll((unsigned long long)above) - 1 : last_in + 1;
+            const int64_t k = (ns - lane) + (above ? 0 : ext);
+            const bool uni = (mmask & low_mask(ns) & ~low_mask(lane)) == 0 && (above || xuni);
+            if (k >= 2) {
+                ntied += (uint64_t)k;
+                if (!uni) {
+                    uint32_t kk = (uint32_t)(k > 0xFFFFFFFFll ? 0xFFFFFFFFll : k);
+                    int c = group_class(kk);
+                    uint32_t slot = atomicAdd(&lcnt[c], 1u);
+                    lst[c][slot][0] = (uint32_t)s;
+                    lst[c][slot][1] = kk;
+                    kmax = kk > kmax ? kk : kmax;
+                }
+            }
+        }
+        __syncthreads();
+        // flush a class list when the next tile could overflow it (a tile adds at most TG_THREADS / 2)
+        const bool last_tile = tile + gridDim.x >= ntiles;
         for (int c = 0; c < TG_CLASSES; ++c) {
-            incl[c] = ncls[c];
-            for (int d = 1; d < 64; d <<= 1) {
-                uint32_t t = __shfl_up(incl[c], d);
-                if (lane >= d) incl[c] += t;
+            uint32_t cnt = lcnt[c];
+            if (cnt == 0 || (!last_tile && cnt + TG_THREADS / 2 <= TG_LCAP)) continue;
+            if (threadIdx.x == 0) lbase[c] = atomicAdd(&gstat[c], cnt);
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < cnt; i += TG_THREADS) {
+                lists[c][2 * (int64_t)(lbase[c] + i)] = lst[c][i][0];
+                lists[c][2 * (int64_t)(lbase[c] + i) + 1] = lst[c][i][1];
             }
+            __syncthreads();
+            if (threadIdx.x == 0) lcnt[c] = 0;
+            __syncthreads();
         }
-        uint64_t wt = wave_sum_u64(ntied);
-        uint32_t wm = wave_max_u32(kmax);
-        if (lane == 63)
-            for (int c = 0; c < TG_CLASSES; ++c) wcnt[c][wv] = incl[c];
-        if (lane == 0) {
-            wtied[wv] = wt;
-            wmax[wv] = wm;
+    }
+    const uint64_t t = wave_sum_u64(ntied);
+    const uint32_t m = wave_max_u32(kmax);
+    if (lane == 0) {
+        wt[wv] = t;
+        wm[wv] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tt = 0;
+        uint32_t mm = 0;
+        for (int w = 0; w < TG_THREADS / 64; ++w) {
+            tt += wt[w];
+            mm = wm[w] > mm ? wm[w] : mm;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t mx = 0;
-            uint64_t tt = 0;
-            for (int w = 0; w < TG_THREADS / 64; ++w) {
-                tt += wtied[w];
-                mx = wmax[w] > mx ? wmax[w] : mx;
-            }
-            for (int c = 0; c < TG_CLASSES; ++c) {
-                uint32_t tot = 0;
-                for (int w = 0; w < TG_THREADS / 64; ++w) tot += wcnt[c][w];
-                base_slot[c] = tot ? atomicAdd(&gstat[c], tot) : 0u;
-            }
-            if (tt) atomicAdd(tied, (unsigned long long)tt);
-            if (mx) atomicMax(&gstat[3], mx);
-        }
-        __syncthreads();
-        uint32_t pre[TG_CLASSES];
-        for (int c = 0; c < TG_CLASSES; ++c) {
-            pre[c] = base_slot[c] + incl[c] - ncls[c];
-            for (int w = 0; w < wv; ++w) pre[c] += wcnt[c][w];
-        }
-        for (uint32_t i = 0; i < nmine; ++i) {
-            int c = group_class(my_k[i]);
-            uint32_t slot = pre[c]++;
-            lists[c][2 * (int64_t)slot] = my_s[i];
-            lists[c][2 * (int64_t)slot + 1] = my_k[i];
-        }
-        __syncthreads();
+        if (tt) atomicAdd(tied, tt);
+        if (mm) atomicMax(&gstat[3], mm);
     }
 }
 
@@ -1154,7 +1178,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_HIP(hipMemsetAsync(gdeep.p, 0, 2 * sizeof(unsigned long long), c.stream));
         RB3_HIP(hipMemsetAsync(gstat.p, 0, 4 * sizeof(uint32_t), c.stream));
         RB3_HIP(hipMemsetAsync(gtied.p, 0, 4 * sizeof(unsigned long long), c.stream));
-        RB3_LAUNCH("tie_groups", k_tie_groups, grid_for(n2, TG_THREADS * TG_ITEMS), dim3(TG_THREADS), 0,
+        RB3_LAUNCH("tie_groups", k_tie_groups, grid_for(n2, TG_THREADS * 64, 2048), dim3(TG_THREADS), 0,
                    c.stream, SK, n2, lpair.as<uint32_t>(), lsmall.as<uint32_t>(), lbig.as<uint32_t>(),
                    gstat.as<uint32_t>(), gtied.as<unsigned long long>());
         uint32_t hs2[4];
