@@ -8,7 +8,8 @@ only marshals numpy arrays.
 Functions (each follows a definition of arXiv 2409.00613):
   expand      double-strand string list P0, rc(P0), P1, rc(P1), ... (Sec. 2.5)
   bwt         BWT by sorting every suffix of the sentinel-terminated list (Sec. 2.1)
-  verify      inverse-BWT check of a candidate BWT (LF relation, Sec. 2.1)
+  verify      inverse-BWT check of a candidate BWT (LF relation, Sec. 2.1);
+              Verifier does the same check in parts for very large lists
   count       SA interval [lo, hi) by scanning every suffix (Sec. 2.3)
   Text.interval / Text.smem
               SA interval by binary search; SMEMs by their definition (Sec. 2.6)
@@ -56,6 +57,12 @@ def _load():
     lib.orc_bwt.restype = ctypes.c_int
     lib.orc_verify.argtypes = [_u8p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64, ctypes.c_int]
     lib.orc_verify.restype = ctypes.c_int64
+    lib.orc_verifier_new.argtypes = [_u8p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64, _i64p]
+    lib.orc_verifier_new.restype = ctypes.c_void_p
+    lib.orc_verifier_walk.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+    lib.orc_verifier_walk.restype = ctypes.c_int64
+    lib.orc_verifier_free.argtypes = [ctypes.c_void_p]
+    lib.orc_verifier_free.restype = None
     lib.orc_count.argtypes = [_u8p, _i64p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64,
                               ctypes.c_int, _i64p, _i64p]
     lib.orc_count.restype = ctypes.c_int
@@ -133,6 +140,41 @@ def verify(B: np.ndarray, codes: np.ndarray, lens: np.ndarray, nthreads: int | N
     b = B if B.size else np.zeros(1, np.uint8)
     return int(lib.orc_verify(_p(b, _u8p), B.shape[0], _p(cod, _u8p), _p(lens, _i64p),
                               lens.shape[0], _threads(nthreads)))
+
+
+class Verifier:
+    """The inverse-BWT check in parts: the constructor checks the length and
+    the symbol counts (``status`` 0, or -1 / -2 as for verify); walk(j0, j1)
+    checks strings [j0, j1) and returns 0 or the first failing j + 1. The
+    list passes when status is 0 and every string of [0, m) walks cleanly.
+    The arrays are kept referenced for the verifier's lifetime."""
+
+    def __init__(self, B: np.ndarray, codes: np.ndarray, lens: np.ndarray):
+        lib = _load()
+        self.B = np.ascontiguousarray(B, dtype=np.uint8)
+        self.codes = np.ascontiguousarray(codes, dtype=np.uint8)
+        self.lens = np.ascontiguousarray(lens, dtype=np.int64)
+        self.m = self.lens.shape[0]
+        b = self.B if self.B.size else np.zeros(1, np.uint8)
+        cod = self.codes if self.codes.size else np.zeros(1, np.uint8)
+        self._keep = (b, cod)
+        st = ctypes.c_int64(0)
+        self._h = lib.orc_verifier_new(_p(b, _u8p), self.B.shape[0], _p(cod, _u8p), _p(self.lens, _i64p),
+                                       self.m, ctypes.byref(st))
+        self.status = int(st.value)
+
+    def walk(self, j0: int, j1: int, nthreads: int | None = None) -> int:
+        if not self._h:
+            raise RuntimeError("verifier was not created (status %d)" % self.status)
+        return int(_load().orc_verifier_walk(self._h, j0, j1, _threads(nthreads)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().orc_verifier_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def count(codes: np.ndarray, lens: np.ndarray, qcodes: np.ndarray, qlens: np.ndarray,

@@ -13,7 +13,9 @@
  *                      sentinel-terminated concatenation, then B[i] = T[S(i)-1]
  *                      (Sec. 2.1; the m+5 integer alphabet of Sec. 2.2)
  *   - orc_verify       inverse BWT: LF-walk every string back out of a candidate
- *                      BWT (the LF relation of Sec. 2.1 / Table 1)
+ *                      BWT (the LF relation of Sec. 2.1 / Table 1); also in
+ *                      parts (orc_verifier_new / _walk / _free) for lists too
+ *                      large to walk in one call
  *   - orc_count        SA interval [lo, hi) of a pattern by scanning every
  *                      suffix (Sec. 2.3 definition of lo/occ/hi)
  *   - orc_sa_interval  the same interval by binary search over a sorted SA
@@ -299,13 +301,37 @@ static void *orc_walk_worker(void *p)
 }
 
 /*
- * Check that candidate codes B (length n) are the BWT of the list (codes,
- * lens, m). Returns 0 when every string is recovered by LF walks from rows
- * 0..m-1 and the symbol counts match; -1 when n is wrong; -2 when symbol
- * counts differ; -3 on allocation failure; j+1 when string j is not recovered.
+ * The verifier in two parts, so that a very large list can be walked a few
+ * strings at a time: orc_verifier_new checks the length and the symbol
+ * counts and builds C and the occurrence table (it keeps pointers to B,
+ * codes and lens, which must outlive it); orc_verifier_walk LF-walks strings
+ * [j0, j1). The list passes when the counts pass and every string in
+ * [0, m) is walked without failure.
  */
-int64_t orc_verify(const uint8_t *B, int64_t n, const uint8_t *codes, const int64_t *lens,
-                   int64_t m, int nthreads)
+typedef struct {
+    const uint8_t *B;
+    int64_t n;
+    const uint8_t *codes;
+    const int64_t *lens;
+    int64_t m;
+    int64_t C[6];
+    int64_t *occ;
+    int64_t *start;
+} orc_verifier;
+
+void orc_verifier_free(void *h)
+{
+    orc_verifier *v = (orc_verifier *)h;
+    if (!v) return;
+    free(v->occ);
+    free(v->start);
+    free(v);
+}
+
+/* *status: 0 ok, -1 wrong n, -2 symbol counts differ, -3 allocation failure
+ * (the handle is NULL unless *status is 0). */
+void *orc_verifier_new(const uint8_t *B, int64_t n, const uint8_t *codes, const int64_t *lens,
+                       int64_t m, int64_t *status)
 {
     int64_t want = 0;
     int64_t cnt[6] = {0, 0, 0, 0, 0, 0}, got[6] = {0, 0, 0, 0, 0, 0};
@@ -315,36 +341,51 @@ int64_t orc_verify(const uint8_t *B, int64_t n, const uint8_t *codes, const int6
         for (int64_t t = 0; t < lens[j]; ++t) cnt[codes[q++]]++;
     }
     cnt[0] = m;
-    if (want != n) return -1;
+    if (want != n) { *status = -1; return NULL; }
     for (int64_t i = 0; i < n; ++i) {
-        if (B[i] > 5) return -2;
+        if (B[i] > 5) { *status = -2; return NULL; }
         got[B[i]]++;
     }
     for (int c = 0; c < 6; ++c)
-        if (got[c] != cnt[c]) return -2;
-    int64_t C[6];
-    C[0] = 0;
-    for (int c = 1; c < 6; ++c) C[c] = C[c - 1] + cnt[c - 1];
+        if (got[c] != cnt[c]) { *status = -2; return NULL; }
+    orc_verifier *v = (orc_verifier *)calloc(1, sizeof(orc_verifier));
+    if (!v) { *status = -3; return NULL; }
+    v->B = B; v->n = n; v->codes = codes; v->lens = lens; v->m = m;
+    v->C[0] = 0;
+    for (int c = 1; c < 6; ++c) v->C[c] = v->C[c - 1] + cnt[c - 1];
     int64_t nb = (n >> 6) + 1;
-    int64_t *occ = (int64_t *)malloc((size_t)nb * 6 * sizeof(int64_t));
-    int64_t *start = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
-    if (!occ || !start) { free(occ); free(start); return -3; }
+    v->occ = (int64_t *)malloc((size_t)nb * 6 * sizeof(int64_t));
+    v->start = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!v->occ || !v->start) { orc_verifier_free(v); *status = -3; return NULL; }
     int64_t run[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = 0; i < n; ++i) {
-        if ((i & 63) == 0) memcpy(occ + (i >> 6) * 6, run, sizeof(run));
+        if ((i & 63) == 0) memcpy(v->occ + (i >> 6) * 6, run, sizeof(run));
         run[B[i]]++;
     }
-    if ((n & 63) == 0) memcpy(occ + (n >> 6) * 6, run, sizeof(run));
+    if ((n & 63) == 0) memcpy(v->occ + (n >> 6) * 6, run, sizeof(run));
     q = 0;
-    for (int64_t j = 0; j < m; ++j) { start[j] = q; q += lens[j]; }
+    for (int64_t j = 0; j < m; ++j) { v->start[j] = q; q += lens[j]; }
+    *status = 0;
+    return v;
+}
+
+/* 0 when strings [j0, j1) are all recovered, else the first failing j + 1. */
+int64_t orc_verifier_walk(void *h, int64_t j0, int64_t j1, int nthreads)
+{
+    orc_verifier *v = (orc_verifier *)h;
+    if (j0 < 0) j0 = 0;
+    if (j1 > v->m) j1 = v->m;
+    if (j1 <= j0) return 0;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > ORC_MAX_THREADS) nthreads = ORC_MAX_THREADS;
+    if (nthreads > j1 - j0) nthreads = (int)(j1 - j0);
     pthread_t th[ORC_MAX_THREADS];
     orc_walk_job jobs[ORC_MAX_THREADS];
+    const int64_t k = j1 - j0;
     for (int t = 0; t < nthreads; ++t) {
-        jobs[t].B = B; jobs[t].occ = occ; jobs[t].C = C; jobs[t].codes = codes;
-        jobs[t].lens = lens; jobs[t].start = start; jobs[t].m = m;
-        jobs[t].j0 = m * t / nthreads; jobs[t].j1 = m * (t + 1) / nthreads;
+        jobs[t].B = v->B; jobs[t].occ = v->occ; jobs[t].C = v->C; jobs[t].codes = v->codes;
+        jobs[t].lens = v->lens; jobs[t].start = v->start; jobs[t].m = v->m;
+        jobs[t].j0 = j0 + k * t / nthreads; jobs[t].j1 = j0 + k * (t + 1) / nthreads;
         pthread_create(&th[t], NULL, orc_walk_worker, &jobs[t]);
     }
     int64_t bad = 0;
@@ -352,8 +393,23 @@ int64_t orc_verify(const uint8_t *B, int64_t n, const uint8_t *codes, const int6
         pthread_join(th[t], NULL);
         if (jobs[t].bad && (!bad || jobs[t].bad < bad)) bad = jobs[t].bad;
     }
-    free(occ);
-    free(start);
+    return bad;
+}
+
+/*
+ * Check that candidate codes B (length n) are the BWT of the list (codes,
+ * lens, m). Returns 0 when every string is recovered by LF walks from rows
+ * 0..m-1 and the symbol counts match; -1 when n is wrong; -2 when symbol
+ * counts differ; -3 on allocation failure; j+1 when string j is not recovered.
+ */
+int64_t orc_verify(const uint8_t *B, int64_t n, const uint8_t *codes, const int64_t *lens,
+                   int64_t m, int nthreads)
+{
+    int64_t status = 0;
+    void *h = orc_verifier_new(B, n, codes, lens, m, &status);
+    if (!h) return status;
+    int64_t bad = orc_verifier_walk(h, 0, m, nthreads);
+    orc_verifier_free(h);
     return bad;
 }
 

@@ -244,6 +244,37 @@ def test_verify_accepts_true_bwt_and_rejects_every_transposition():
                     assert oracle.verify(X, codes, lens) != 0, (strands, i, j)
 
 
+def test_verifier_in_parts_agrees_with_verify():
+    # walking the strings one at a time reports the same first failing
+    # string as the one-call check, on the true BWT and on every transposition
+    rnd = random.Random(17)
+    for _ in range(25):
+        strands = ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 5)))
+                   for _ in range(rnd.randint(1, 4))]
+        codes, lens = _codes(strands)
+        B = oracle.bwt(codes, lens)
+        n = B.shape[0]
+        cases = [B]
+        for i in range(n):
+            for j in range(i + 1, n):
+                if B[i] != B[j]:
+                    X = B.copy()
+                    X[i], X[j] = X[j], X[i]
+                    cases.append(X)
+        for X in cases:
+            want = oracle.verify(X, codes, lens)
+            v = oracle.Verifier(X, codes, lens)
+            if v.status != 0:
+                assert v.status == want
+                continue
+            bad = [r for r in (v.walk(j, j + 1) for j in range(lens.shape[0])) if r]
+            got = min(bad) if bad else 0
+            assert got == want and v.walk(0, lens.shape[0], nthreads=3) == want
+            v.close()
+    v = oracle.Verifier(B[:-1], codes, lens)
+    assert v.status == -1
+
+
 def test_verify_rejects_wrong_length_and_counts():
     codes, lens = _codes(["ACGT", "GG"])
     B = oracle.bwt(codes, lens)
