@@ -194,6 +194,168 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
             "roofline": roof}
 
 
+def timed_merges(b1, new, steps: int, warmup: int):
+    """Merge a device-resident batch into a fresh copy of b1, warmup + steps
+    times; the timed region covers the steps only (copy + merge each)."""
+    import torch
+    from paper_2409_00613_amd import rb3
+    new_dev = torch.from_numpy(new.data).cuda()
+    new_lens = new.lens.copy()
+    torch.cuda.synchronize()
+
+    def step():
+        idx = b1.clone()
+        idx.merge(new_dev, new_lens)
+        return idx
+
+    for i in range(warmup):
+        step().close()
+        log(f"warmup {i + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    rb3.rb3_prof_reset()
+    rb3.rb3_prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for i in range(steps):
+        if last is not None:
+            last.close()
+        last = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rb3.rb3_prof_enable(False)
+    prof = rb3.rb3_prof_read()
+    st = last.merge_stats()
+    n_out, _, _ = last.info()
+    last.close()
+    del new_dev
+    log(f"timed {steps} steps in {t1 - t0:.3f} s")
+    for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        log(f"  {k:24s} launches={v[0]:6d}  ms/step={v[1] / steps:9.3f}")
+    return {"ms": (t1 - t0) / steps * 1e3, "prof": prof, "stats": st, "n_out": n_out}
+
+
+def roofline_of(prof: dict, st: dict, steps: int, workload: str, src_hash: str):
+    """Roofline entry for the kernel with the largest total time."""
+    if not prof:
+        return None
+    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    dom_ms_total = prof[dom][1]
+    launches = prof[dom][0]
+    ab = algorithmic_bytes(dom, st, steps)
+    if ab is None or dom_ms_total <= 0:
+        return None
+    achieved = ab / (dom_ms_total / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic(dom, workload, src_hash), "algorithmic_bytes_per_launch": ab / launches,
+            "avg_launch_ms": dom_ms_total / launches}
+
+
+def plain_vs_batched(b1_strings, new, chunk: int, k: int):
+    """The same merge of the first k new strings in the batched form (one
+    LF-chain launch over every chunk) and in the plain form (one launch per
+    string); both results must be identical."""
+    import torch
+    from paper_2409_00613_amd import rb3
+    sub = new.slice(0, min(k, new.n))
+    sub_dev = torch.from_numpy(sub.data).cuda()
+    out = {}
+    exports = {}
+    for form, per_string in (("batched", False), ("plain", True)):
+        b1 = rb3.rb3_build(b1_strings.data, b1_strings.lens, chunk_len=chunk, launch_per_string=per_string)
+        for rep in range(2):  # the first is a warm-up
+            idx = b1.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            idx.merge(sub_dev, sub.lens)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if rep == 1:
+                exports[form] = idx.export()
+            idx.close()
+        st_n2 = 2 * (sub.total + sub.n)
+        out[form] = {"ms": round(dt * 1e3, 3), "suffixes_per_s": round(st_n2 / dt, 1)}
+        b1.close()
+        log(f"{form} form, {sub.n} strings ({st_n2} new suffixes): {dt * 1e3:.1f} ms")
+    assert np.array_equal(exports["batched"], exports["plain"]), "plain and batched forms disagree"
+    out["strings"] = sub.n
+    out["strands"] = 2 * sub.n
+    out["new_suffixes"] = 2 * (sub.total + sub.n)
+    out["batched_over_plain"] = round(out["plain"]["ms"] / out["batched"]["ms"], 2)
+    out["identical"] = True
+    return out
+
+
+def incremental_bench(args):
+    """Large incremental build: 100 haplotypes of a 100 Mb genome with
+    segmental duplications, merged 10 at a time (the first batch is a build
+    into an empty index). Each batch is uploaded to the device before its
+    merge is timed."""
+    import torch
+    import synth
+    from paper_2409_00613_amd import rb3
+    t = time.perf_counter()
+    inc = synth.config_incremental()
+    log(f"base genome with duplications: {inc.base.shape[0]} bases in {time.perf_counter() - t:.1f} s")
+    alloc = rb3.TorchAllocator(0)
+    per = inc.n_hap // args.batches
+    idx = None
+    batches = []
+    total_new = 0
+    total_s = 0.0
+    rb3.rb3_prof_reset()
+    rb3.rb3_prof_enable(True)
+    torch.cuda.reset_peak_stats()
+    dev_free_min = None
+    for b in range(args.batches):
+        t = time.perf_counter()
+        batch = inc.batch(b * per, per)
+        gen_s = time.perf_counter() - t
+        bdev = torch.from_numpy(batch.data).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if idx is None:
+            idx = rb3.rb3_build(bdev, batch.lens, allocator=alloc)
+        else:
+            idx.merge(bdev, batch.lens)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        free, tot = torch.cuda.mem_get_info()
+        dev_free_min = free if dev_free_min is None else min(dev_free_min, free)
+        del bdev
+        st = idx.merge_stats()
+        n, m, _ = idx.info()
+        new_suffixes = st["n2"]
+        total_new += new_suffixes
+        total_s += dt
+        batches.append({"batch": b, "n1": st["n1"], "n2": new_suffixes, "n": n, "ms": round(dt * 1e3, 1),
+                        "suffixes_per_s": round(new_suffixes / dt, 1), "tie_max_depth": st["tie_max_depth"],
+                        "max_group": st["max_group"], "tie_doubling": st["tie_doubling"]})
+        log(f"batch {b}: {per} haplotypes generated in {gen_s:.1f} s; {new_suffixes} new suffixes merged "
+            f"into n1={st['n1']} in {dt * 1e3:.1f} ms ({new_suffixes / dt / 1e9:.2f} G/s); n={n}")
+    rb3.rb3_prof_enable(False)
+    prof = rb3.rb3_prof_read()
+    peak_alloc = torch.cuda.max_memory_allocated()
+    kernels = {k: {"launches": v[0], "ms_total": v[1]} for k, v in prof.items()}
+    for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:12]:
+        log(f"  {k:24s} launches={v[0]:6d}  ms total={v[1]:9.1f}")
+    if idx is not None:
+        n, m, _ = idx.info()
+        idx.close()
+    return {"metric": "BWT-merge suffixes inserted/s", "value": round(total_new / total_s, 1),
+            "unit": "suffixes/s", "n_gpus": 1, "steps": args.batches, "warmup": 0,
+            "ms_per_step": round(total_s / args.batches * 1e3, 1), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": "incremental", "genome_len": int(inc.base.shape[0]),
+                       "haplotypes": inc.n_hap, "batches": args.batches, "haplotypes_per_batch": per,
+                       "both_strands": True, "segmental_duplications": "0.1% of the base, 1-50 kb, half inverted",
+                       "n_final": n},
+            "batches": batches, "total_merge_s": round(total_s, 2),
+            "peak_hbm_allocated_bytes": int(peak_alloc), "device_free_min_bytes": int(dev_free_min),
+            "kernels": kernels, "source_hash": kernel_source_hash()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,8 +367,17 @@ def main():
                     help="haplotype prefix length for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-smem", action="store_true", help="skip the SMEM serving measurement")
-    ap.add_argument("--workload", default="pangenome_merge", choices=["pangenome_merge", "serving"],
-                    help="serving: the full serving configuration (320 haplotypes) only")
+    ap.add_argument("--workload", default="pangenome_merge",
+                    choices=["pangenome_merge", "uneven_merge", "incremental", "serving"],
+                    help="pangenome_merge: 32 haplotypes into 32 (default); uneven_merge: 10,000 "
+                         "log-normal contigs and 2 chromosomes into the same index, plus the plain "
+                         "one-launch-per-string form on a sample; incremental: 100 haplotypes of a "
+                         "100 Mb genome merged in 10 batches; serving: the full serving configuration "
+                         "(320 haplotypes) only")
+    ap.add_argument("--plain-strings", type=int, default=200,
+                    help="uneven_merge: input strings in the plain-vs-batched sample")
+    ap.add_argument("--batches", type=int, default=10, help="incremental: number of batches")
+
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (three times) and exit; "
                          "used to scale hardware byte counters")
@@ -241,67 +412,37 @@ def main():
                     "vs_baseline": None, "dtype": "int64", "data": "synthetic"})
         print(json.dumps(res), flush=True)
         return
-    workload = "pangenome_merge"
+    if args.workload == "incremental":
+        res = incremental_bench(args)
+        print(json.dumps(res), flush=True)
+        return
+    workload = args.workload
     t = time.perf_counter()
     w = synth.config_pangenome(genome_len=args.genome)
-    log(f"generated {w.b1.n}+{w.new.n} haplotypes of ~{args.genome} bases in {time.perf_counter() - t:.1f} s")
+    b1_strings, new_strings = w.b1, w.new
+    if workload == "uneven_merge":
+        u = synth.config_uneven(genome_len=args.genome)
+        b1_strings, new_strings = u.b1, u.new
+    log(f"generated {b1_strings.n} indexed + {new_strings.n} new strings ({new_strings.total} new bases) "
+        f"in {time.perf_counter() - t:.1f} s")
 
     alloc = rb3.TorchAllocator(0)
     t = time.perf_counter()
-    b1 = rb3.rb3_build(w.b1.data, w.b1.lens, allocator=alloc, chunk_len=args.chunk)
+    b1 = rb3.rb3_build(b1_strings.data, b1_strings.lens, allocator=alloc, chunk_len=args.chunk)
     torch.cuda.synchronize()
     n1, m1, _ = b1.info()
     log(f"built existing index: n1={n1} m1={m1} in {time.perf_counter() - t:.1f} s")
-    new_dev = torch.from_numpy(w.new.data).cuda()
-    new_lens = w.new.lens.copy()
-    torch.cuda.synchronize()
-
-    def step():
-        idx = b1.clone()
-        idx.merge(new_dev, new_lens)
-        return idx
-
-    for i in range(args.warmup):
-        step().close()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    rb3.rb3_prof_reset()
-    rb3.rb3_prof_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    last = None
-    for i in range(args.steps):
-        if last is not None:
-            last.close()
-        last = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rb3.rb3_prof_enable(False)
-    prof = rb3.rb3_prof_read()
-    st = last.merge_stats()
-    n_out, m_out, _ = last.info()
-    last.close()
-    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
-
-    ms = (t1 - t0) / args.steps * 1e3
+    r = timed_merges(b1, new_strings, args.steps, args.warmup)
+    st, ms, prof, n_out = r["stats"], r["ms"], r["prof"], r["n_out"]
     n2 = st["n2"]
     value = n2 / (ms / 1e3)
     kernels = {k: {"launches": v[0], "ms_per_step": v[1] / args.steps} for k, v in prof.items()}
-    for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1]):
-        log(f"  {k:24s} launches={v[0]:6d}  ms/step={v[1] / args.steps:9.3f}")
-    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
-    dom_ms_total = prof[dom][1]
-    launches = prof[dom][0]
-    ab = algorithmic_bytes(dom, st, args.steps)
     src_hash = kernel_source_hash()
-    roofline = None
-    if ab is not None and dom_ms_total > 0:
-        achieved = ab / (dom_ms_total / 1e3) / 1e9
-        traffic = read_traffic(dom, workload, src_hash)
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "algorithmic_bytes_per_launch": ab / launches,
-                    "avg_launch_ms": dom_ms_total / launches}
+    roofline = roofline_of(prof, st, args.steps, workload, src_hash)
+
+    plain = None
+    if workload == "uneven_merge":
+        plain = plain_vs_batched(b1_strings, new_strings, args.chunk, args.plain_strings)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -328,12 +469,13 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": workload, "genome_len": args.genome, "haplotypes_indexed": w.b1.n,
-                   "haplotypes_merged": w.new.n, "both_strands": True, "n1": n1, "n2": n2,
+        "config": {"workload": workload, "genome_len": args.genome, "strings_indexed": b1_strings.n,
+                   "strings_merged": new_strings.n, "both_strands": True, "n1": n1, "n2": n2,
                    "n_merged": n_out, "chunk_len": st["chunk_len"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "smem": smem,
+        "plain_vs_batched": plain,
         "merge_stats": st,
         "kernels": kernels,
         "source_hash": src_hash,

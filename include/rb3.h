@@ -74,6 +74,12 @@ typedef struct rb3_opts {
     rb3_free_fn dev_free;
     void *alloc_ctx;
     int64_t chunk_len;     /* LF-chain chunk length for merges; 0 = default */
+    int32_t launch_per_string; /* 0 (default): one launch of the LF-chain
+                              kernel covers every chunk of every new string
+                              of a merge. 1: the plain form, one launch per
+                              new string (over that string's chunks); same
+                              result, for measuring what batching gains. */
+    int32_t reserved;      /* must be 0 */
 } rb3_opts;
 
 /* Fill *o with the defaults above. */

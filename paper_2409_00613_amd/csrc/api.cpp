@@ -148,8 +148,10 @@ static int ctx_from_opts(const rb3_opts *o, Ctx &c) {
     c.free_fn = o->dev_free;
     c.alloc_ctx = o->alloc_ctx;
     c.chunk_len = o->chunk_len;
+    c.launch_per_string = o->launch_per_string ? 1 : 0;
     c.both = o->both_strands ? 1 : 0;
     if ((c.alloc == nullptr) != (c.free_fn == nullptr)) return fail(RB3_EINVAL, "dev_alloc and dev_free must be given together");
+    if (o->reserved != 0) return fail(RB3_EINVAL, "rb3_opts.reserved must be 0");
     RB3_HIP(hipSetDevice(c.device));
     if (o->stream) {
         c.stream = (hipStream_t)o->stream;
@@ -172,6 +174,7 @@ static Ctx call_ctx(const IndexData &d) {
     c.free_fn = d.ctx.free_fn;
     c.alloc_ctx = d.ctx.alloc_ctx;
     c.chunk_len = d.ctx.chunk_len;
+    c.launch_per_string = d.ctx.launch_per_string;
     c.both = d.ctx.both;
     return c;
 }
@@ -246,7 +249,9 @@ static int do_merge(Ctx &c, IndexData &d, const uint8_t *seq, const int64_t *len
     DBuf hold, Q, err;
     const uint8_t *d_seq = nullptr;
     RB3_TRY(stage(c, seq, total, mem, hold, &d_seq));
-    RB3_ALLOC(Q, &c, n2);
+    // the tie kernels read whole 8-byte words: 16 zero bytes follow the codes
+    RB3_ALLOC(Q, &c, n2 + 16);
+    RB3_HIP(hipMemsetAsync(Q.as<uint8_t>() + n2, 0, 16, c.stream));
     RB3_ALLOC(err, &c, sizeof(int32_t));
     RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
     RB3_TRY(encode_strands(c, d_seq, lens, n_seqs, d.ctx.both, Q.as<uint8_t>(), n2, err.as<int32_t>()));
@@ -591,7 +596,17 @@ int rb3_merge_stats(const rb3_index *idx, char *keys, int64_t *vals, int64_t cap
         {"fixup_steps", s.fixup_steps}, {"fixup_passes", s.fixup_passes}, {"key_syms", s.key_syms},
         {"sort_bits", s.sort_bits}, {"tied_records", s.tied_records}, {"tie_groups", s.tie_groups}, {"tie_pairs", s.tie_pairs}, {"tie_small_reads", s.tie_small_reads}, {"tie_max_depth", s.tie_max_depth}, {"tie_deep_reads", s.tie_deep_reads},
         {"max_group", s.max_group}, {"tie_doubling", s.tie_doubling}, {"tie_rounds", s.tie_rounds},
-        {"tie_work", s.tie_work}};
+        {"tie_work", s.tie_work}, {"tie_block_reads", s.tie_block_reads}};
+    static const char *hist_names[32] = {
+        "groups_log2_0", "groups_log2_1", "groups_log2_2", "groups_log2_3", "groups_log2_4",
+        "groups_log2_5", "groups_log2_6", "groups_log2_7", "groups_log2_8", "groups_log2_9",
+        "groups_log2_10", "groups_log2_11", "groups_log2_12", "groups_log2_13", "groups_log2_14",
+        "groups_log2_15", "groups_log2_16", "groups_log2_17", "groups_log2_18", "groups_log2_19",
+        "groups_log2_20", "groups_log2_21", "groups_log2_22", "groups_log2_23", "groups_log2_24",
+        "groups_log2_25", "groups_log2_26", "groups_log2_27", "groups_log2_28", "groups_log2_29",
+        "groups_log2_30", "groups_log2_31"};
+    for (int b = 1; b < 32; ++b)
+        if (s.group_hist[b]) kv.push_back({hist_names[b], (int64_t)s.group_hist[b]});
     int64_t i = 0;
     for (auto &p : kv) {
         if (i < cap) {

@@ -365,29 +365,37 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // starts and ends inside the window has its size from the next start and
 // its mixed-symbol test from a ballot of members whose BWT symbol differs
 // from their group leader's. Only the group reaching past the window's end
-// is measured with a serial scan. Groups whose members carry different
-// symbols are collected per workgroup in LDS, by size class (2 members,
-// 3..8, more), and flushed to three global lists of (first sorted index,
-// member count) with one atomic per class per flush.
+// is extended by the whole wave. Groups whose members carry different
+// symbols are collected per workgroup in LDS, by size class, and flushed to
+// one global list of (first sorted index, member count) per class with one
+// atomic per class per flush.
 constexpr int TG_THREADS = 256;
-constexpr int TG_CLASSES = 3;
-constexpr int TG_LCAP = 1024;  // LDS list capacity per class
+constexpr int TG_CLASSES = 6;
+constexpr int TG_LCAP = 512;  // LDS list capacity per class
+// class upper bounds: 2 | 3..8 | 9..64 | 65..128 | 129..256 | 257..8192
+constexpr uint32_t TG_BOUND[TG_CLASSES] = {2, 8, 64, 128, 256, 8192};
 
-__device__ __forceinline__ int group_class(uint32_t k) { return k == 2 ? 0 : (k <= 8 ? 1 : 2); }
+__device__ __forceinline__ int group_class(uint32_t k) {
+    return k == 2 ? 0 : (k <= 8 ? 1 : (k <= 64 ? 2 : (k <= 128 ? 3 : (k <= 256 ? 4 : 5))));
+}
+
+struct TieLists {
+    uint32_t *l[TG_CLASSES];
+};
 
 __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__restrict__ SK, int64_t n,
-                                                           uint32_t *__restrict__ l0, uint32_t *__restrict__ l1,
-                                                           uint32_t *__restrict__ l2,
-                                                           uint32_t *__restrict__ gstat,
-                                                           unsigned long long *__restrict__ tied) {
+                                                           TieLists lists, uint32_t *__restrict__ gstat,
+                                                           unsigned long long *__restrict__ tied,
+                                                           uint32_t *__restrict__ ghist) {
     __shared__ uint32_t lst[TG_CLASSES][TG_LCAP][2];
+    __shared__ uint32_t hist[32];
     __shared__ uint32_t lcnt[TG_CLASSES];
     __shared__ uint32_t lbase[TG_CLASSES];
     __shared__ unsigned long long wt[TG_THREADS / 64];
     __shared__ uint32_t wm[TG_THREADS / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t *lists[TG_CLASSES] = {l0, l1, l2};
     if (threadIdx.x < TG_CLASSES) lcnt[threadIdx.x] = 0;
+    if (threadIdx.x < 32) hist[threadIdx.x] = 0;
     __syncthreads();
     uint64_t ntied = 0;
     uint32_t kmax = 0;
@@ -444,6 +452,7 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
                     uint32_t slot = atomicAdd(&lcnt[c], 1u);
                     lst[c][slot][0] = (uint32_t)s;
                     lst[c][slot][1] = kk;
+                    atomicAdd(&hist[31 - __clz(kk)], 1u);
                     kmax = kk > kmax ? kk : kmax;
                 }
             }
@@ -457,8 +466,8 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
             if (threadIdx.x == 0) lbase[c] = atomicAdd(&gstat[c], cnt);
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < cnt; i += TG_THREADS) {
-                lists[c][2 * (int64_t)(lbase[c] + i)] = lst[c][i][0];
-                lists[c][2 * (int64_t)(lbase[c] + i) + 1] = lst[c][i][1];
+                lists.l[c][2 * (int64_t)(lbase[c] + i)] = lst[c][i][0];
+                lists.l[c][2 * (int64_t)(lbase[c] + i) + 1] = lst[c][i][1];
             }
             __syncthreads();
             if (threadIdx.x == 0) lcnt[c] = 0;
@@ -480,25 +489,56 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
             mm = wm[w] > mm ? wm[w] : mm;
         }
         if (tt) atomicAdd(tied, tt);
-        if (mm) atomicMax(&gstat[3], mm);
+        if (mm) atomicMax(&gstat[TG_CLASSES], mm);
     }
+    if (threadIdx.x < 32 && hist[threadIdx.x]) atomicAdd(&ghist[threadIdx.x], hist[threadIdx.x]);
 }
 
+// Eight symbols of the new strands starting at position q of Q, the first in
+// the most significant byte, so that unsigned order is lexicographic order.
+// Bytes after a sentinel (code 0) belong to the next strand and are cleared.
+// Q holds 16 readable bytes past its last symbol.
+__device__ __forceinline__ uint64_t load_chunk(const uint8_t *__restrict__ Q, int64_t q) {
+    const uint64_t *w = (const uint64_t *)(Q + (q & ~(int64_t)7));
+    const int sh = (int)(q & 7) * 8;
+    uint64_t v = w[0];
+    if (sh) v = (v >> sh) | (w[1] << (64 - sh));
+    v = __builtin_bswap64(v);
+    // codes are below 0x80: a byte is zero iff adding 0x7F leaves its top bit clear
+    const uint64_t t = (v & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full;
+    const uint64_t z = ~(t | v) & 0x8080808080808080ull;
+    if (z) v &= ~0ull << (56 - (__clzll((long long)z) & ~7));
+    return v;
+}
+
+// A chunk holds a sentinel iff it has a zero byte (symbol codes are 1..5).
+__device__ __forceinline__ bool chunk_has_sentinel(uint64_t v) {
+    const uint64_t t = (v & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full;
+    return (~(t | v) & 0x8080808080808080ull) != 0;
+}
+
+// The tie kernels below compare suffixes that share their sort key, i.e.
+// their insertion rank l and first symbol. Their order is then plain string
+// order from the second symbol on, which they read eight symbols at a time
+// (one chunk). Two chunks that are equal and hold a sentinel belong to
+// suffixes reaching their strands' ends together: strand order, which is
+// position order in Q, decides.
 constexpr int WALK_MAXK = 64;
-constexpr int WALK_DEPTHS = 16;
+constexpr int WALK_DEPTHS = 16;  // chunks per member per load round
 
 
 constexpr int SMALL_MAXK = 8;
 constexpr int SMALL_DEPTHS = 4;
 constexpr int LANES_WG = 256;
-constexpr int LANES_MAX_DEPTH = 128;
+constexpr int LANES_MAX_DEPTH = 1024;  // symbols
 
 // Groups of 2..8 members, one lane per group, persistent: a lane that has
 // ordered its group takes the next one from a shared queue (one atomic per
 // wave refill), so no lane idles while a neighbour walks a deep group. The
 // queue is the pair list (entries 0..np) followed by the 3..8 list. Members
 // are held in registers; every loop over them is unrolled.
-__global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restrict__ K, int64_t n2,
+__global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restrict__ K,
+                                                        const uint8_t *__restrict__ Q, int64_t n2,
                                                         const uint32_t *__restrict__ SV,
                                                         const uint32_t *__restrict__ plist, int64_t np,
                                                         const uint32_t *__restrict__ slist, int64_t ns,
@@ -562,8 +602,8 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restri
         for (int i = 0; i < SMALL_MAXK; ++i)
 #pragma unroll
             for (int t = 0; t < SMALL_DEPTHS; ++t) {
-                int64_t q = (int64_t)pos[i] + d0 + t;
-                kv[i][t] = (act[i] && q < n2) ? K[q] : ~0ull;
+                int64_t q = (int64_t)pos[i] + d0 + 8 * t;
+                kv[i][t] = (act[i] && q < n2) ? load_chunk(Q, q) : ~0ull;
             }
         bool any = true;
 #pragma unroll
@@ -573,16 +613,15 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restri
             uint32_t tb[SMALL_MAXK];
 #pragma unroll
             for (int i = 0; i < SMALL_MAXK; ++i) {
-                c[i] = kv[i][t] >> 3;
+                c[i] = kv[i][t];
                 tb[i] = 0;
                 if (act[i]) {
                     ++steps;
                     if (kv[i][t] == ~0ull) {
                         atomicOr(guard, GUARD_RERANK);
                         act[i] = false;
-                    } else if ((c[i] & 7) == 0) {
-                        // a key holding its sentinel is unique: position order
-                        tb[i] = pos[i] + (uint32_t)(d0 + t);
+                    } else if (chunk_has_sentinel(c[i])) {
+                        tb[i] = pos[i];  // strand order
                     }
                 }
             }
@@ -630,7 +669,7 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restri
                 act[i] = nact[i];
             }
         }
-        d0 += SMALL_DEPTHS;
+        d0 += 8 * SMALL_DEPTHS;
         if (!any) {
 #pragma unroll
             for (int i = 0; i < SMALL_MAXK; ++i)
@@ -670,7 +709,8 @@ constexpr int DEEP_DPL = 4;  // depths per lane per window
 // covers 4W depths. The wave finds the first depth where some subgroup
 // splits, applies the same refinement as k_tie_lanes there (all lanes keep
 // the same copy of the members' state), and goes on from the next depth.
-__global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K, int64_t n2,
+__global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K,
+                                                  const uint8_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ dlist,
                                                   const uint32_t *__restrict__ dcount,
@@ -719,8 +759,8 @@ __global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K
             uint64_t kv[DEEP_DPL];
 #pragma unroll
             for (int j = 0; j < DEEP_DPL; ++j) {
-                int64_t q = (int64_t)mypos + d0 + ti * DEEP_DPL + j;
-                kv[j] = (mi < k && myact && q < n2) ? K[q] : ~0ull;
+                int64_t q = (int64_t)mypos + d0 + 8 * (ti * DEEP_DPL + j);
+                kv[j] = (mi < k && myact && q < n2) ? load_chunk(Q, q) : ~0ull;
             }
             int u0 = 0;  // first depth of the window not yet processed
             while (any && u0 < WIN) {
@@ -740,10 +780,10 @@ __global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K
                 for (int j = 0; j < DEEP_DPL; ++j) {
                     uint64_t lk = __shfl(kv[j], (int)my_lead * W + ti);
                     int u = ti * DEEP_DPL + j;
-                    uint64_t c = kv[j] >> 3;
-                    bool sent = (c & 7) == 0;
+                    uint64_t c = kv[j];
+                    bool sent = chunk_has_sentinel(c);
                     bool differ = mi < k && my_act && u >= u0 &&
-                                  (kv[j] == ~0ull || (c != (lk >> 3)) || (sent && (uint32_t)mi != my_lead));
+                                  (kv[j] == ~0ull || c != lk || (sent && (uint32_t)mi != my_lead));
                     if (differ && u < first) first = u;
                 }
                 for (int off = 32; off > 0; off >>= 1) {
@@ -764,14 +804,14 @@ __global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K
                         uint64_t x = __shfl(kv[j], (i < kp ? i : 0) * W + src_t);
                         if (j == src_j) v = x;
                     }
-                    c[i] = v >> 3;
+                    c[i] = v;
                     tb[i] = 0;
                     if (act[i]) {
                         if (v == ~0ull) {
                             if (lane == 0) atomicOr(guard, GUARD_RERANK);
                             act[i] = false;
-                        } else if ((c[i] & 7) == 0) {
-                            tb[i] = pos[i] + (uint32_t)(d0 + u);
+                        } else if (chunk_has_sentinel(c[i])) {
+                            tb[i] = pos[i];
                         }
                     }
                 }
@@ -824,7 +864,7 @@ __global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K
 #pragma unroll
             for (int i = 0; i < SMALL_MAXK; ++i)
                 if (i == mi) myact = act[i];
-            d0 += WIN;
+            d0 += 8 * WIN;
         }
         maxdepth = (uint32_t)d0 > maxdepth ? (uint32_t)d0 : maxdepth;
         if (lane < k) {
@@ -842,101 +882,268 @@ __global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K
     if (lane == 0 && maxdepth) atomicMax(reads + 1, (unsigned long long)maxdepth);
 }
 
-// One wave per listed group of at most 64 members; lane i holds member i.
-__global__ void __launch_bounds__(256) k_tie_walk(const uint64_t *__restrict__ K, int64_t n2,
+__device__ __forceinline__ uint32_t lane_read(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ uint64_t lane_read64(uint64_t v, int l) {
+    return (uint64_t)lane_read((uint32_t)v, l) | ((uint64_t)lane_read((uint32_t)(v >> 32), l) << 32);
+}
+
+// One wave per listed group of 9..64 members; lane i holds member i for the
+// whole walk, with its place o in the group's current order, the first
+// place of its subgroup and the lane of one subgroup member (its lead),
+// whose chunk it compares with at each depth. When some subgroup splits,
+// the wave visits the classes of equal (subgroup, chunk) among the members
+// still mixed, one class per step, with ballots and lane reads only: a
+// class's members take consecutive places after the members of their
+// subgroup with smaller chunks. The order inside a class is not kept (its
+// members are still tied), so lane order is used there.
+__global__ void __launch_bounds__(256) k_tie_walk(const uint64_t *__restrict__ K,
+                                                  const uint8_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ glist, int64_t ng,
                                                   uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
                                                   unsigned long long *__restrict__ reads) {
-    int lane = threadIdx.x & 63;
-    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = low_mask(lane);
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    uint64_t steps = 0;
     for (int64_t g = wave; g < ng; g += nwaves) {
-        uint32_t gs = glist[2 * g], k = glist[2 * g + 1];
-        if (k > WALK_MAXK) {
+        const uint32_t gs = glist[2 * g], k = glist[2 * g + 1];
+        if (k < 2 || k > WALK_MAXK || (int64_t)gs + k > n2) {
             if (lane == 0) atomicOr(guard, GUARD_RERANK);
             continue;
         }
-        bool member = (uint32_t)lane < k;
-        uint32_t p = member ? SV[gs + lane] : 0u;
-        uint64_t kp = member ? K[p] : 0ull;
-        uint32_t e = (uint32_t)(kp & 7);
-        uint32_t o = (uint32_t)lane;  // position in the current order
-        uint32_t sub = 0;             // order index where my subgroup starts
-        uint32_t lead = 0;            // lane holding the first member of my subgroup
-        bool active = member;         // my subgroup still mixes symbols
-        uint64_t steps = 0;
-        for (int64_t d0 = 1;; d0 += WALK_DEPTHS) {
+        const bool member = (uint32_t)lane < k;
+        const uint32_t p = member ? SV[gs + lane] : 0u;
+        const uint64_t kp = member ? K[p] : 0ull;
+        const uint32_t e = (uint32_t)(kp & 7);
+        uint32_t o = (uint32_t)lane, sub = 0, lead = 0;
+        bool active = member;
+        for (int64_t d0 = 1;; d0 += 8 * WALK_DEPTHS) {
             if (__ballot(active) == 0) break;
             uint64_t kv[WALK_DEPTHS];
             for (int t = 0; t < WALK_DEPTHS; ++t) {
-                int64_t q = (int64_t)p + d0 + t;
-                kv[t] = (active && q < n2) ? K[q] : ~0ull;
+                const int64_t q = (int64_t)p + d0 + 8 * t;
+                kv[t] = (active && q < n2) ? load_chunk(Q, q) : ~0ull;
             }
             for (int t = 0; t < WALK_DEPTHS; ++t) {
-                uint64_t amask = __ballot(active);
-                if (amask == 0) break;
-                int64_t q = (int64_t)p + d0 + t;
+                if (__ballot(active) == 0) break;
                 uint64_t kk = 0;
-                uint32_t tb = 0;
+                bool sent = false;
                 if (active) {
                     ++steps;
-                    if (kv[t] == ~0ull) {
-                        atomicOr(guard, GUARD_RERANK);
-                        active = false;
-                    } else {
-                        kk = kv[t] >> 3;
-                        // a key holding its sentinel is unique; such keys order by
-                        // position, which follows the strand order
-                        if ((kk & 7) == 0) tb = (uint32_t)q;
-                    }
+                    kk = kv[t];
+                    if (kk == ~0ull) atomicOr(guard, GUARD_RERANK);
+                    sent = chunk_has_sentinel(kk);
                 }
-                uint64_t lk = __shfl(kk, (int)lead);
-                uint32_t lt = __shfl(tb, (int)lead);
-                bool differ = active && (kk != lk || tb != lt);
+                const uint64_t lk = __shfl(kk, (int)lead);
+                const bool differ = active && (kk != lk || (sent && (uint32_t)lane != lead));
                 if (__ballot(differ) == 0) continue;
-                // some subgroup splits: stable re-sort inside every active subgroup
-                uint32_t less = 0, eqb = 0;
-                for (int j = 0; j < (int)k; ++j) {
-                    uint64_t kj = __shfl(kk, j);
-                    uint32_t tj = __shfl(tb, j);
-                    uint32_t sj = __shfl(sub, j);
-                    uint32_t oj = __shfl(o, j);
-                    bool aj = (amask >> j) & 1ull;
-                    if (active && aj && sj == sub) {
-                        bool lt_ = kj < kk || (kj == kk && tj < tb);
-                        bool eq_ = kj == kk && tj == tb;
-                        less += lt_ ? 1u : 0u;
-                        eqb += (eq_ && oj < o) ? 1u : 0u;
+                uint64_t rem = __ballot(active);
+                uint32_t no = o, nsub = sub, nlead = lead;
+                bool nact = active;
+                while (rem) {
+                    const int L = __ffsll((unsigned long long)rem) - 1;
+                    const uint32_t subL = lane_read(sub, L);
+                    const uint64_t kL = lane_read64(kk, L);
+                    const bool sL = lane_read(sent ? 1u : 0u, L) != 0;
+                    const uint32_t pL = lane_read(p, L);
+                    const uint32_t eL = lane_read(e, L);
+                    const bool same = active && sub == subL;
+                    // a chunk holding its sentinel is a class of its own, ordered by strand
+                    const uint64_t m = sL ? (1ull << L) : __ballot(same && !sent && kk == kL);
+                    const uint64_t lt = __ballot(same && (kk < kL || (kk == kL && sent && p < pL)));
+                    const uint32_t base = subL + (uint32_t)__popcll(lt);
+                    const bool uni = (__ballot(e == eL) & m) == m;
+                    if ((m >> lane) & 1ull) {
+                        no = base + (uint32_t)__popcll(m & below);
+                        nsub = base;
+                        nlead = (uint32_t)L;
+                        nact = __popcll(m) >= 2 && !uni;
                     }
+                    rem &= ~m;
                 }
-                if (active) {
-                    o = sub + less + eqb;
-                    sub = sub + less;
-                }
-                uint32_t cnt = 0, nlead = lead;
-                bool uni = true;
-                for (int j = 0; j < (int)k; ++j) {
-                    uint32_t sj = __shfl(sub, j);
-                    uint32_t oj = __shfl(o, j);
-                    uint32_t ej = __shfl(e, j);
-                    bool aj = (amask >> j) & 1ull;
-                    if (active && aj && sj == sub) {
-                        ++cnt;
-                        uni &= ej == e;
-                        if (oj == sub) nlead = (uint32_t)j;
-                    }
-                }
-                if (active) {
-                    lead = nlead;
-                    active = cnt >= 2 && !uni;
-                }
+                o = no;
+                sub = nsub;
+                lead = nlead;
+                active = nact;
             }
         }
         if (member) SK[gs + o] = kp;
-        uint64_t tot = wave_sum_u64(steps);
-        if (lane == 0 && tot) atomicAdd(reads, (unsigned long long)tot);
     }
+    const uint64_t tot = wave_sum_u64(steps);
+    if (lane == 0 && tot) atomicAdd(reads, (unsigned long long)tot);
+}
+
+// Groups of more than 64 members (up to T * MPT), one workgroup each. The
+// members' state lives in LDS, indexed by each member's place in the
+// group's current order; a subgroup is a run of places [S, S + size) whose
+// members are known equal so far. Every round loads DEPTHS chunks of each
+// member of a still-mixed subgroup; at each depth the workgroup checks whether
+// some subgroup splits, and if so ranks every member inside its subgroup
+// (stable, by chunk, sentinel chunks by strand order), moves the members to
+// their new places, measures the new subgroups and keeps only those whose
+// members carry different symbols. A split moves members, so the round ends
+// there and the next one loads from the following depth.
+template <int T, int MPT, int DEPTHS>
+__global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ K, const uint8_t *__restrict__ Q,
+                                                 int64_t n2, const uint32_t *__restrict__ SV,
+                                                 const uint32_t *__restrict__ glist, int64_t ng,
+                                                 uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
+                                                 unsigned long long *__restrict__ stat) {
+    constexpr int MAXK = T * MPT;
+    static_assert(MAXK <= 65535, "places must fit 16 bits");
+    __shared__ uint64_t sc[MAXK];   // chunk at the current depth
+    __shared__ uint32_t spos[MAXK]; // position of the member in Q
+    __shared__ uint16_t ssub[MAXK]; // first place of the member's subgroup
+    __shared__ uint16_t ssz[MAXK];  // subgroup size, kept at its first place
+    __shared__ uint8_t se[MAXK];    // the member's BWT symbol
+    __shared__ uint8_t sact[MAXK];  // the member's subgroup still mixes symbols
+    __shared__ uint8_t snew[MAXK];  // per new subgroup: still mixed
+    const int tid = threadIdx.x;
+    uint64_t reads = 0;
+    int64_t maxd = 0;
+    for (int64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+        const uint32_t gs = glist[2 * g];
+        const int k = (int)glist[2 * g + 1];
+        if (k < 2 || k > MAXK || (int64_t)gs + k > n2) {
+            if (tid == 0) atomicOr(guard, GUARD_RERANK);
+            continue;
+        }
+        for (int o = tid; o < k; o += T) {
+            uint32_t p = SV[gs + o];
+            spos[o] = p;
+            se[o] = (uint8_t)(K[p] & 7);
+            ssub[o] = 0;
+            sact[o] = 1;
+        }
+        if (tid == 0) ssz[0] = (uint16_t)k;
+        __syncthreads();
+        int64_t d0 = 1;
+        for (;;) {
+            uint64_t kv[MPT][DEPTHS];
+#pragma unroll
+            for (int j = 0; j < MPT; ++j) {
+                const int o = tid + j * T;
+                const bool a = o < k && sact[o];
+                const int64_t p = o < k ? (int64_t)spos[o] : 0;
+#pragma unroll
+                for (int t = 0; t < DEPTHS; ++t) {
+                    const int64_t q = p + d0 + 8 * t;
+                    kv[j][t] = a ? (q < n2 ? load_chunk(Q, q) : ~0ull) : 0ull;
+                    reads += a ? 1u : 0u;
+                }
+            }
+            int used = DEPTHS;
+            bool any = true;
+            for (int t = 0; t < DEPTHS; ++t) {
+#pragma unroll
+                for (int j = 0; j < MPT; ++j) {
+                    const int o = tid + j * T;
+                    if (o < k && sact[o]) {
+                        if (kv[j][t] == ~0ull) atomicOr(guard, GUARD_RERANK);
+                        sc[o] = kv[j][t];
+                    }
+                }
+                __syncthreads();
+                int sp = 0;
+#pragma unroll
+                for (int j = 0; j < MPT; ++j) {
+                    const int o = tid + j * T;
+                    if (o < k && sact[o]) {
+                        const int S = ssub[o];
+                        const uint64_t v = sc[o];
+                        sp |= (v != sc[S] || (o != S && chunk_has_sentinel(v))) ? 1 : 0;
+                    }
+                }
+                if (!__syncthreads_or(sp)) continue;
+                // rank every member of a mixed subgroup inside it
+                uint32_t r_no[MPT], r_sub[MPT], r_pos[MPT];
+                uint8_t r_e[MPT], r_a[MPT];
+#pragma unroll
+                for (int j = 0; j < MPT; ++j) {
+                    const int o = tid + j * T;
+                    r_no[j] = r_sub[j] = r_pos[j] = 0;
+                    r_e[j] = r_a[j] = 0;
+                    if (o < k) {
+                        r_pos[j] = spos[o];
+                        r_e[j] = se[o];
+                        r_a[j] = sact[o];
+                        const int S = ssub[o];
+                        if (r_a[j]) {
+                            const int size = ssz[S];
+                            const uint64_t v = sc[o];
+                            const bool sv = chunk_has_sentinel(v);
+                            uint32_t less = 0, eqb = 0;
+                            for (int x = S; x < S + size; ++x) {
+                                const uint64_t w = sc[x];
+                                less += (w < v || (w == v && sv && spos[x] < r_pos[j])) ? 1u : 0u;
+                                eqb += (w == v && !sv && x < o) ? 1u : 0u;
+                            }
+                            r_no[j] = (uint32_t)S + less + eqb;
+                            r_sub[j] = (uint32_t)S + less;
+                        } else {
+                            r_no[j] = (uint32_t)o;
+                            r_sub[j] = (uint32_t)S;
+                        }
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < MPT; ++j) {
+                    const int o = tid + j * T;
+                    if (o < k) {
+                        const uint32_t no = r_no[j];
+                        spos[no] = r_pos[j];
+                        se[no] = r_e[j];
+                        ssub[no] = (uint16_t)r_sub[j];
+                        sact[no] = r_a[j];
+                    }
+                }
+                __syncthreads();
+                // the first member of each new subgroup measures it
+#pragma unroll
+                for (int j = 0; j < MPT; ++j) {
+                    const int o = tid + j * T;
+                    if (o < k && sact[o] && ssub[o] == o) {
+                        const uint8_t e0 = se[o];
+                        bool uni = true;
+                        int x = o + 1;
+                        while (x < k && ssub[x] == o) {
+                            uni &= se[x] == e0;
+                            ++x;
+                        }
+                        ssz[o] = (uint16_t)(x - o);
+                        snew[o] = (x - o >= 2 && !uni) ? 1 : 0;
+                    }
+                }
+                __syncthreads();
+                int anyact = 0;
+#pragma unroll
+                for (int j = 0; j < MPT; ++j) {
+                    const int o = tid + j * T;
+                    if (o < k && sact[o]) {
+                        const uint8_t a = snew[ssub[o]];
+                        sact[o] = a;
+                        anyact |= a;
+                    }
+                }
+                any = __syncthreads_or(anyact) != 0;
+                used = t + 1;
+                break;
+            }
+            if (!any) break;
+            d0 += 8 * used;
+        }
+        maxd = d0 > maxd ? d0 : maxd;
+        for (int o = tid; o < k; o += T) SK[gs + o] = K[spos[o]];
+        __syncthreads();
+    }
+    const uint64_t tot = wave_sum_u64(reads);
+    if ((tid & 63) == 0 && tot) atomicAdd(&stat[0], (unsigned long long)tot);
+    if (tid == 0 && maxd) atomicMax(&stat[1], (unsigned long long)maxd);
 }
 
 // ---------------------------------------------------------------------------
@@ -1082,9 +1289,11 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         int64_t CL = c.chunk_len > 0 ? c.chunk_len : 4096;
         if (CL > (1 << 30)) CL = 1 << 30;
         std::vector<Chunk> chunks;
+        std::vector<int64_t> first_chunk;  // per strand, for the one-launch-per-string form
         int64_t off = 0;
         for (int64_t s = 0; s < m2; ++s) {
             int64_t L = strand_lens[s];
+            first_chunk.push_back((int64_t)chunks.size());
             for (int64_t t0 = 0; t0 < L; t0 += CL) {
                 int64_t t1 = t0 + CL < L ? t0 + CL : L;
                 Chunk ck;
@@ -1107,9 +1316,21 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_ALLOC(pend, &c, sizeof(int32_t));
         RB3_HIP(hipMemcpyAsync(d_ch.p, chunks.data(), nch * sizeof(Chunk), hipMemcpyHostToDevice, c.stream));
         RB3_HIP(hipMemsetAsync(readyA.p, 0, (nch + 1) * sizeof(int32_t), c.stream));
-        RB3_LAUNCH("chain", k_chain, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
-                   d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(),
-                   readyA.as<int32_t>(), stats.as<unsigned long long>());
+        if (c.launch_per_string) {
+            // the plain form: each new string's chunks in a launch of their own
+            first_chunk.push_back(nch);
+            for (int64_t s = 0; s < m2; ++s) {
+                const int64_t f = first_chunk[s], k = first_chunk[s + 1] - f;
+                if (k == 0) continue;
+                RB3_LAUNCH("chain", k_chain, grid_for(k, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
+                           d_ch.as<Chunk>() + f, k, m1, w, K.as<uint64_t>(), unres.as<int32_t>() + f,
+                           readyA.as<int32_t>() + f, stats.as<unsigned long long>());
+            }
+        } else {
+            RB3_LAUNCH("chain", k_chain, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
+                       d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(),
+                       readyA.as<int32_t>(), stats.as<unsigned long long>());
+        }
         unsigned long long hs[4];
         RB3_HIP(hipMemcpyAsync(hs, stats.p, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
         RB3_HIP(hipStreamSynchronize(c.stream));
@@ -1167,32 +1388,41 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     // (which orders every tie) handles the rest.
     bool need_doubling = false;
     {
-        DBuf lpair, lsmall, lbig, gstat, gtied;
-        RB3_ALLOC(lpair, &c, (n2 / 2 + 1) * 2 * sizeof(uint32_t));
-        RB3_ALLOC(lsmall, &c, (n2 / 3 + 1) * 2 * sizeof(uint32_t));
-        RB3_ALLOC(lbig, &c, (n2 / 9 + 1) * 2 * sizeof(uint32_t));
-        RB3_ALLOC(gstat, &c, 4 * sizeof(uint32_t));
+        DBuf lists[TG_CLASSES], gstat, gtied, ghist, gdeep, gblk;
+        TieLists tl;
+        for (int q = 0; q < TG_CLASSES; ++q) {
+            // a class-q group has more than TG_BOUND[q-1] members
+            const int64_t minsz = q == 0 ? 2 : (int64_t)TG_BOUND[q - 1] + 1;
+            RB3_ALLOC(lists[q], &c, (n2 / minsz + 1) * 2 * sizeof(uint32_t));
+            tl.l[q] = lists[q].as<uint32_t>();
+        }
+        RB3_ALLOC(ghist, &c, 32 * sizeof(uint32_t));
+        RB3_ALLOC(gstat, &c, 8 * sizeof(uint32_t));
         RB3_ALLOC(gtied, &c, 4 * sizeof(unsigned long long));
-        DBuf gdeep;
         RB3_ALLOC(gdeep, &c, 2 * sizeof(unsigned long long));
-        RB3_HIP(hipMemsetAsync(gdeep.p, 0, 2 * sizeof(unsigned long long), c.stream));
-        RB3_HIP(hipMemsetAsync(gstat.p, 0, 4 * sizeof(uint32_t), c.stream));
+        RB3_ALLOC(gblk, &c, 2 * sizeof(unsigned long long));
+        RB3_HIP(hipMemsetAsync(ghist.p, 0, 32 * sizeof(uint32_t), c.stream));
+        RB3_HIP(hipMemsetAsync(gstat.p, 0, 8 * sizeof(uint32_t), c.stream));
         RB3_HIP(hipMemsetAsync(gtied.p, 0, 4 * sizeof(unsigned long long), c.stream));
+        RB3_HIP(hipMemsetAsync(gdeep.p, 0, 2 * sizeof(unsigned long long), c.stream));
+        RB3_HIP(hipMemsetAsync(gblk.p, 0, 2 * sizeof(unsigned long long), c.stream));
         RB3_LAUNCH("tie_groups", k_tie_groups, grid_for(n2, TG_THREADS * 64, 2048), dim3(TG_THREADS), 0,
-                   c.stream, SK, n2, lpair.as<uint32_t>(), lsmall.as<uint32_t>(), lbig.as<uint32_t>(),
-                   gstat.as<uint32_t>(), gtied.as<unsigned long long>());
-        uint32_t hs2[4];
+                   c.stream, SK, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>());
+        uint32_t hs2[8];
         unsigned long long ht[4];
+        RB3_HIP(hipMemcpyAsync(st.group_hist, ghist.p, sizeof(st.group_hist), hipMemcpyDeviceToHost, c.stream));
         RB3_HIP(hipMemcpyAsync(hs2, gstat.p, sizeof(hs2), hipMemcpyDeviceToHost, c.stream));
         RB3_HIP(hipMemcpyAsync(ht, gtied.p, sizeof(ht), hipMemcpyDeviceToHost, c.stream));
         RB3_HIP(hipStreamSynchronize(c.stream));
         st.tied_records = (int64_t)ht[0];
         st.tie_pairs = hs2[0];
-        st.tie_groups = (int64_t)hs2[0] + hs2[1] + hs2[2];
-        st.max_group = hs2[3];
-        if (hs2[3] > (uint32_t)WALK_MAXK) {
+        st.tie_groups = 0;
+        for (int q = 0; q < TG_CLASSES; ++q) st.tie_groups += hs2[q];
+        st.max_group = hs2[TG_CLASSES];
+        if (hs2[TG_CLASSES] > TG_BOUND[TG_CLASSES - 1]) {
             need_doubling = true;
         } else if (st.tie_groups > 0) {
+            const uint8_t *Qc = d_Q;
             if (hs2[0] + hs2[1] > 0) {
                 DBuf qh, dl;
                 int64_t nq = (int64_t)hs2[0] + hs2[1];
@@ -1203,25 +1433,41 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 int64_t wgs = (nq + LANES_WG - 1) / LANES_WG;
                 if (wgs > 2048) wgs = 2048;
                 RB3_LAUNCH("tie_lanes", k_tie_lanes, dim3((unsigned)wgs), dim3(LANES_WG), 0, c.stream,
-                           K.as<uint64_t>(), n2, SV, lpair.as<uint32_t>(), (int64_t)hs2[0], lsmall.as<uint32_t>(),
-                           (int64_t)hs2[1], qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, guard,
+                           K.as<uint64_t>(), Qc, n2, SV, tl.l[0], (int64_t)hs2[0], tl.l[1], (int64_t)hs2[1],
+                           qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, guard,
                            gtied.as<unsigned long long>() + 1);
                 // the deep list's length stays on the device: a fixed grid loops over it
-                RB3_LAUNCH("tie_deep", k_tie_deep, dim3(1024), dim3(256), 0, c.stream, K.as<uint64_t>(), n2, SV,
+                RB3_LAUNCH("tie_deep", k_tie_deep, dim3(1024), dim3(256), 0, c.stream, K.as<uint64_t>(), Qc, n2, SV,
                            dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, guard, gdeep.as<unsigned long long>());
             }
             if (hs2[2] > 0)
                 RB3_LAUNCH("tie_walk", k_tie_walk, grid_for(hs2[2], 4, 1 << 20), dim3(256), 0, c.stream,
-                           K.as<uint64_t>(), n2, SV, lbig.as<uint32_t>(), (int64_t)hs2[2], SK, guard,
+                           K.as<uint64_t>(), Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, guard,
                            gtied.as<unsigned long long>() + 3);
-            unsigned long long hd[2];
+            if (hs2[3] > 0)
+                RB3_LAUNCH("tie_block128", (k_tie_block<128, 1, 4>), grid_for(hs2[3], 1, 8192), dim3(128), 0,
+                           c.stream, K.as<uint64_t>(), Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, guard,
+                           gblk.as<unsigned long long>());
+            if (hs2[4] > 0)
+                RB3_LAUNCH("tie_block256", (k_tie_block<256, 1, 4>), grid_for(hs2[4], 1, 4096), dim3(256), 0,
+                           c.stream, K.as<uint64_t>(), Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, guard,
+                           gblk.as<unsigned long long>());
+            if (hs2[5] > 0)
+                RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
+                           c.stream, K.as<uint64_t>(), Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, guard,
+                           gblk.as<unsigned long long>());
+            unsigned long long hd[2], hb[2];
             RB3_HIP(hipMemcpyAsync(ht, gtied.p, sizeof(ht), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipMemcpyAsync(hd, gdeep.p, sizeof(hd), hipMemcpyDeviceToHost, c.stream));
+            RB3_HIP(hipMemcpyAsync(hb, gblk.p, sizeof(hb), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipStreamSynchronize(c.stream));
             st.tie_small_reads = (int64_t)ht[1];
-            st.tie_max_depth = (int64_t)(ht[2] > hd[1] ? ht[2] : hd[1]);
+            unsigned long long md = ht[2] > hd[1] ? ht[2] : hd[1];
+            md = md > hb[1] ? md : hb[1];
+            st.tie_max_depth = (int64_t)md;
             st.tie_deep_reads = (int64_t)hd[0];
             st.tie_work = (int64_t)ht[3];
+            st.tie_block_reads = (int64_t)hb[0];
         }
     }
     if (need_doubling) {

@@ -159,6 +159,7 @@ struct Ctx {
     rb3_free_fn free_fn = nullptr;
     void *alloc_ctx = nullptr;
     int64_t chunk_len = 0;
+    int32_t launch_per_string = 0;
     int32_t both = 1;
     // Frees are deferred until flush(), called after the stream has drained,
     // so that a caching allocator never hands out memory a queued kernel
@@ -295,6 +296,7 @@ int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *
 // merge.hip
 struct MergeStats {
     int64_t n1 = 0, m1 = 0, n2 = 0, m2 = 0;
+    uint32_t group_hist[32] = {};  // mixed-symbol tied groups by floor(log2(size))
     int64_t chunks = 0, chunk_len = 0;
     int64_t chain_steps = 0;      // rank steps in the chain phase (point + interval)
     int64_t fixup_steps = 0;      // rank steps replayed by fix-up passes
@@ -304,6 +306,7 @@ struct MergeStats {
     int64_t tied_records = 0;     // records in non-singleton groups after the sort
     int64_t tie_groups = 0;       // tied groups whose members carry different symbols
     int64_t tie_pairs = 0;        // ... of which have two members
+    int64_t tie_block_reads = 0;  // chunk reads refining groups of more than 64
     int64_t tie_small_reads = 0;  // key reads refining groups of 2..8
     int64_t tie_max_depth = 0;    // deepest comparison those needed
     int64_t tie_deep_reads = 0;   // key reads of groups handed to the deep walk
@@ -334,6 +337,8 @@ struct IndexData {
     }
 };
 
+// d_Q: the n2 codes of the m2 new strands, each followed by its sentinel
+// (code 0), then 16 zero bytes of padding.
 int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_lens, int64_t m2,
                int64_t n2, uint4 **new_blk, int64_t **new_sb, int64_t new_C[6], MergeStats &st);
 

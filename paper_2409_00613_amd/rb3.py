@@ -29,7 +29,8 @@ _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class Opts(ctypes.Structure):
     _fields_ = [("both_strands", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN),
-                ("alloc_ctx", ctypes.c_void_p), ("chunk_len", ctypes.c_int64)]
+                ("alloc_ctx", ctypes.c_void_p), ("chunk_len", ctypes.c_int64),
+                ("launch_per_string", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SmemRec(ctypes.Structure):
@@ -184,7 +185,7 @@ class TorchAllocator:
 
 
 def make_opts(both_strands: bool = True, device: int = 0, stream=None, allocator: TorchAllocator | None = None,
-              chunk_len: int = 0) -> Opts:
+              chunk_len: int = 0, launch_per_string: bool = False) -> Opts:
     o = Opts()
     lib().rb3_opts_init(ctypes.byref(o))
     o.both_strands = 1 if both_strands else 0
@@ -197,6 +198,7 @@ def make_opts(both_strands: bool = True, device: int = 0, stream=None, allocator
         o.dev_alloc = allocator.alloc_fn
         o.dev_free = allocator.free_fn
     o.chunk_len = int(chunk_len)
+    o.launch_per_string = 1 if launch_per_string else 0
     return o
 
 
@@ -252,8 +254,9 @@ class Index:
 
 
 def rb3_build(seq, lens, both_strands: bool = True, device: int = 0, stream=None,
-              allocator: TorchAllocator | None = None, chunk_len: int = 0) -> Index:
-    o = make_opts(both_strands, device, stream, allocator, chunk_len)
+              allocator: TorchAllocator | None = None, chunk_len: int = 0,
+              launch_per_string: bool = False) -> Index:
+    o = make_opts(both_strands, device, stream, allocator, chunk_len, launch_per_string)
     ptr, _, mem, keep = _buffer(seq)
     la, lp = _lens(lens)
     h = ctypes.c_void_p()

@@ -250,9 +250,11 @@ def config_uneven(seed: int = SEED + 3, genome_len: int = 4_000_000, n_b1: int =
     """Batched uneven merge: the existing index is the pangenome index; the new
     batch is ``n_contigs`` log-normal-length excerpts of haplotypes (each with
     fresh SNPs) plus ``n_chrom`` chromosome-like haplotypes of a second base
-    genome."""
+    genome. Log-lengths are normal around ln(median) with sigma chosen so that
+    +-3 sigma spans [median / 100, median * 100] (1.535 for the defaults, mean
+    about 30 kb), redrawn outside [len_lo, len_hi]."""
     haps = pangenome_haplotypes(SEED + 2, genome_len, n_src)
-    sigma = math.log(median) / 3.0
+    sigma = math.log(100.0) / 3.0
     contigs = []
     for c in range(n_contigs):
         g = rng(seed, STREAM_CONTIG + c)
@@ -308,12 +310,27 @@ def poisson_arrivals(n: int, rate_per_s: float, seed: int = SEED + 4) -> np.ndar
     return np.cumsum(g.exponential(1.0 / rate_per_s, n))
 
 
+class IncrementalWorkload:
+    """Large incremental build: a base genome with segmental duplications and
+    inversions, and ``n_hap`` haplotypes of it, drawn on demand (haplotype h
+    always from its own stream) so that batches need not all be in memory."""
+
+    def __init__(self, seed: int, genome_len: int, n_hap: int, dup_frac: float, dup_lo: int,
+                 dup_hi: int):
+        self.seed = seed
+        self.n_hap = n_hap
+        base = random_genome(genome_len, rng(seed, STREAM_BASE))
+        self.base = segmental_duplications(base, dup_frac, dup_lo, dup_hi, rng(seed, STREAM_BASE + 7))
+
+    def haplotype(self, h: int) -> np.ndarray:
+        return haplotype(self.base, 1e-3, 1e-4, rng(self.seed, STREAM_HAP + h))
+
+    def batch(self, first: int, count: int) -> Strings:
+        return pack([self.haplotype(h) for h in range(first, first + count)])
+
+
 def config_incremental(seed: int = SEED + 5, genome_len: int = 100_000_000,
                        n_hap: int = 100, dup_frac: float = 0.001, dup_lo: int = 1000,
-                       dup_hi: int = 50_000) -> tuple[np.ndarray, list[np.ndarray]]:
-    """Large incremental build: a base genome with segmental duplications and
-    inversions, then ``n_hap`` haplotypes of it (returned lazily as a list)."""
-    base = random_genome(genome_len, rng(seed, STREAM_BASE))
-    base = segmental_duplications(base, dup_frac, dup_lo, dup_hi, rng(seed, STREAM_BASE + 7))
-    haps = [haplotype(base, 1e-3, 1e-4, rng(seed, STREAM_HAP + h)) for h in range(n_hap)]
-    return base, haps
+                       dup_hi: int = 50_000) -> IncrementalWorkload:
+    """Large incremental build (see IncrementalWorkload); merged in batches."""
+    return IncrementalWorkload(seed, genome_len, n_hap, dup_frac, dup_lo, dup_hi)

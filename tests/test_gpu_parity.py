@@ -282,16 +282,25 @@ def test_smem_small_capacity_reports_sizes(tiny):
     idx.close()
 
 
-@pytest.mark.parametrize("copies", [6, 40, 70])
-def test_large_mixed_symbol_groups(copies):
-    """Many new strings sharing a long suffix after different first bases:
+@pytest.mark.parametrize("copies,tail_len,muts", [(6, 300, 0), (40, 300, 0), (70, 300, 0), (70, 300, 2),
+                                                  (200, 300, 2), (1000, 200, 3), (9000, 40, 0)])
+def test_large_mixed_symbol_groups(copies, tail_len, muts):
+    """Many new strings sharing a long tail after different first bases:
     one tied group per position of the shared part, with mixed BWT symbols
-    right after the differing base. 70 copies exceed the symbol walk's group
-    limit and take the prefix-doubling path."""
-    say(f"case: {copies} strings with a shared 300-base tail")
-    rnd = random.Random(copies)
-    tail = "".join(rnd.choice("ACGT") for _ in range(300))
-    strs = ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 3))) + tail for _ in range(copies)]
+    right after the differing base. Up to ``muts`` substitutions per copy
+    make the big groups split at many depths. The group sizes cover every
+    tie kernel: a wave per group (up to 64 members), a workgroup per group
+    (65..128, 129..256, 257..8192), and prefix doubling (more than 8192)."""
+    say(f"case: {copies} strings with a shared {tail_len}-base tail, {muts} substitutions each")
+    rnd = random.Random(copies * 7 + muts)
+    tail = "".join(rnd.choice("ACGT") for _ in range(tail_len))
+    strs = []
+    for _ in range(copies):
+        t = list(tail)
+        for _ in range(rnd.randint(0, muts)):
+            i = rnd.randrange(tail_len)
+            t[i] = rnd.choice("ACGT")
+        strs.append("".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 3))) + "".join(t))
     old = synth.pack([("".join(rnd.choice("ACGT") for _ in range(150)) + tail[:100]).encode()])
     new = synth.pack([s.encode() for s in strs])
     for start in ("empty", "index"):
@@ -305,7 +314,7 @@ def test_large_mixed_symbol_groups(copies):
         assert np.array_equal(idx.export(), oracle.bwt(codes, lens)), start
         st = idx.merge_stats()
         assert st["tie_groups"] > 0
-        assert st["tie_doubling"] == (1 if st["max_group"] > 64 else 0)
+        assert st["tie_doubling"] == (1 if st["max_group"] > 8192 else 0)
         idx.close()
 
 
