@@ -524,7 +524,7 @@ __device__ __forceinline__ bool chunk_has_sentinel(uint64_t v) {
 // suffixes reaching their strands' ends together: strand order, which is
 // position order in Q, decides.
 constexpr int WALK_MAXK = 64;
-constexpr int WALK_DEPTHS = 16;  // chunks per member per load round
+constexpr int WALK_DEPTHS = 4;  // chunks per member per load round
 
 
 constexpr int SMALL_MAXK = 8;
@@ -537,8 +537,7 @@ constexpr int LANES_MAX_DEPTH = 1024;  // symbols
 // wave refill), so no lane idles while a neighbour walks a deep group. The
 // queue is the pair list (entries 0..np) followed by the 3..8 list. Members
 // are held in registers; every loop over them is unrolled.
-__global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restrict__ K,
-                                                        const uint8_t *__restrict__ Q, int64_t n2,
+__global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restrict__ Q, int64_t n2,
                                                         const uint32_t *__restrict__ SV,
                                                         const uint32_t *__restrict__ plist, int64_t np,
                                                         const uint32_t *__restrict__ slist, int64_t ns,
@@ -555,6 +554,7 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restri
     int k = 0;
     int64_t d0 = 1;
     uint32_t pos[SMALL_MAXK], e[SMALL_MAXK], o[SMALL_MAXK], sub[SMALL_MAXK];
+    uint64_t gkey = 0;  // the group's common key bits (all but the symbol)
     bool act[SMALL_MAXK];
 #pragma unroll
     for (int i = 0; i < SMALL_MAXK; ++i) {
@@ -589,7 +589,8 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restri
                             act[i] = i < k;
                         }
 #pragma unroll
-                        for (int i = 0; i < SMALL_MAXK; ++i) e[i] = i < k ? (uint32_t)(K[pos[i]] & 7) : 0u;
+                        for (int i = 0; i < SMALL_MAXK; ++i) e[i] = i < k ? (uint32_t)(SK[gs + i] & 7) : 0u;
+                        gkey = SK[gs] & ~7ull;
                     }
                 }
             }
@@ -673,7 +674,7 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restri
         if (!any) {
 #pragma unroll
             for (int i = 0; i < SMALL_MAXK; ++i)
-                if (i < k) SK[gs + o[i]] = K[pos[i]];
+                if (i < k) SK[gs + o[i]] = gkey | e[i];
             busy = false;
             maxdepth = (uint32_t)d0 > maxdepth ? (uint32_t)d0 : maxdepth;
         }
@@ -709,8 +710,7 @@ constexpr int DEEP_DPL = 4;  // depths per lane per window
 // covers 4W depths. The wave finds the first depth where some subgroup
 // splits, applies the same refinement as k_tie_lanes there (all lanes keep
 // the same copy of the members' state), and goes on from the next depth.
-__global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K,
-                                                  const uint8_t *__restrict__ Q, int64_t n2,
+__global__ void __launch_bounds__(256) k_tie_deep(const uint8_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ dlist,
                                                   const uint32_t *__restrict__ dcount,
@@ -743,7 +743,8 @@ __global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K
             act[i] = i < k;
         }
 #pragma unroll
-        for (int i = 0; i < SMALL_MAXK; ++i) e[i] = i < k ? (uint32_t)(K[pos[i]] & 7) : 0u;
+        for (int i = 0; i < SMALL_MAXK; ++i) e[i] = i < k ? (uint32_t)(SK[gs + i] & 7) : 0u;
+        const uint64_t gkey = SK[gs] & ~7ull;
         uint32_t mypos = 0;
         bool myact = false;
 #pragma unroll
@@ -868,14 +869,14 @@ __global__ void __launch_bounds__(256) k_tie_deep(const uint64_t *__restrict__ K
         }
         maxdepth = (uint32_t)d0 > maxdepth ? (uint32_t)d0 : maxdepth;
         if (lane < k) {
-            uint32_t oo = 0, pp = 0;
+            uint32_t oo = 0, ee = 0;
 #pragma unroll
             for (int i = 0; i < SMALL_MAXK; ++i)
                 if (i == lane) {
                     oo = o[i];
-                    pp = pos[i];
+                    ee = e[i];
                 }
-            SK[gs + oo] = K[pp];
+            SK[gs + oo] = gkey | ee;
         }
     }
     if (lane == 0 && steps) atomicAdd(reads, (unsigned long long)steps);
@@ -889,89 +890,189 @@ __device__ __forceinline__ uint64_t lane_read64(uint64_t v, int l) {
     return (uint64_t)lane_read((uint32_t)v, l) | ((uint64_t)lane_read((uint32_t)(v >> 32), l) << 32);
 }
 
-// One wave per listed group of 9..64 members; lane i holds member i for the
-// whole walk, with its place o in the group's current order, the first
-// place of its subgroup and the lane of one subgroup member (its lead),
-// whose chunk it compares with at each depth. When some subgroup splits,
+// One wave per listed group of up to 64 * MPL members; member i lives in
+// lane i % 64, slot i / 64, for the whole walk, with its place o in the
+// group's current order and the first place of its subgroup. At each depth
 // the wave visits the classes of equal (subgroup, chunk) among the members
-// still mixed, one class per step, with ballots and lane reads only: a
-// class's members take consecutive places after the members of their
-// subgroup with smaller chunks. The order inside a class is not kept (its
-// members are still tied), so lane order is used there.
-__global__ void __launch_bounds__(256) k_tie_walk(const uint64_t *__restrict__ K,
-                                                  const uint8_t *__restrict__ Q, int64_t n2,
+// of still-mixed subgroups, one class per step, with ballots and lane reads
+// only (no LDS): a class that is its whole subgroup changes nothing; a
+// class of a subgroup that splits takes consecutive places after the
+// members of its subgroup with smaller chunks, and stays mixed if its
+// members' symbols differ. The order inside a class is not kept (its
+// members are still tied), so member order is used there.
+//
+// Members of a group share their sort key except for its symbol bits, so
+// the symbols come from the group's run of sorted keys (coalesced). The next
+// group's members are fetched while the current one is walked.
+template <int MPL>
+__global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ glist, int64_t ng,
                                                   uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
                                                   unsigned long long *__restrict__ reads) {
+    constexpr uint32_t MAXK = 64 * MPL;
     const int lane = threadIdx.x & 63;
     const uint64_t below = low_mask(lane);
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     uint64_t steps = 0;
+    uint32_t f_gs = 0, f_k = 0, f_p[MPL];
+    uint64_t f_key[MPL];
+    auto fetch = [&](int64_t g) {
+        f_gs = glist[2 * g];
+        f_k = glist[2 * g + 1];
+        const bool ok = f_k >= 2 && f_k <= MAXK && (int64_t)f_gs + f_k <= n2;
+#pragma unroll
+        for (int s = 0; s < MPL; ++s) {
+            const uint32_t i = (uint32_t)(s * 64 + lane);
+            const bool m = ok && i < f_k;
+            f_p[s] = m ? SV[f_gs + i] : 0u;
+            f_key[s] = m ? SK[f_gs + i] : 0ull;
+        }
+    };
+#pragma unroll
+    for (int s = 0; s < MPL; ++s) {
+        f_p[s] = 0;
+        f_key[s] = 0;
+    }
+    if (wave < ng) fetch(wave);
     for (int64_t g = wave; g < ng; g += nwaves) {
-        const uint32_t gs = glist[2 * g], k = glist[2 * g + 1];
-        if (k < 2 || k > WALK_MAXK || (int64_t)gs + k > n2) {
+        const uint32_t gs = f_gs, k = f_k;
+        uint32_t p[MPL], e[MPL], o[MPL], sub[MPL];
+        uint64_t key[MPL];
+        bool act[MPL];
+#pragma unroll
+        for (int s = 0; s < MPL; ++s) {
+            p[s] = f_p[s];
+            key[s] = f_key[s];
+        }
+        if (g + nwaves < ng) fetch(g + nwaves);
+        if (k < 2 || k > MAXK || (int64_t)gs + k > n2) {
             if (lane == 0) atomicOr(guard, GUARD_RERANK);
             continue;
         }
-        const bool member = (uint32_t)lane < k;
-        const uint32_t p = member ? SV[gs + lane] : 0u;
-        const uint64_t kp = member ? K[p] : 0ull;
-        const uint32_t e = (uint32_t)(kp & 7);
-        uint32_t o = (uint32_t)lane, sub = 0, lead = 0;
-        bool active = member;
+#pragma unroll
+        for (int s = 0; s < MPL; ++s) {
+            const uint32_t i = (uint32_t)(s * 64 + lane);
+            e[s] = (uint32_t)(key[s] & 7);
+            o[s] = i;
+            sub[s] = 0;
+            act[s] = i < k;
+        }
         for (int64_t d0 = 1;; d0 += 8 * WALK_DEPTHS) {
-            if (__ballot(active) == 0) break;
-            uint64_t kv[WALK_DEPTHS];
-            for (int t = 0; t < WALK_DEPTHS; ++t) {
-                const int64_t q = (int64_t)p + d0 + 8 * t;
-                kv[t] = (active && q < n2) ? load_chunk(Q, q) : ~0ull;
-            }
-            for (int t = 0; t < WALK_DEPTHS; ++t) {
-                if (__ballot(active) == 0) break;
-                uint64_t kk = 0;
-                bool sent = false;
-                if (active) {
-                    ++steps;
-                    kk = kv[t];
-                    if (kk == ~0ull) atomicOr(guard, GUARD_RERANK);
-                    sent = chunk_has_sentinel(kk);
+            bool any = false;
+#pragma unroll
+            for (int s = 0; s < MPL; ++s) any |= __ballot(act[s]) != 0;
+            if (!any) break;
+            uint64_t kv[MPL][WALK_DEPTHS];
+#pragma unroll
+            for (int s = 0; s < MPL; ++s)
+#pragma unroll
+                for (int t = 0; t < WALK_DEPTHS; ++t) {
+                    const int64_t q = (int64_t)p[s] + d0 + 8 * t;
+                    kv[s][t] = (act[s] && q < n2) ? load_chunk(Q, q) : ~0ull;
                 }
-                const uint64_t lk = __shfl(kk, (int)lead);
-                const bool differ = active && (kk != lk || (sent && (uint32_t)lane != lead));
-                if (__ballot(differ) == 0) continue;
-                uint64_t rem = __ballot(active);
-                uint32_t no = o, nsub = sub, nlead = lead;
-                bool nact = active;
-                while (rem) {
-                    const int L = __ffsll((unsigned long long)rem) - 1;
-                    const uint32_t subL = lane_read(sub, L);
-                    const uint64_t kL = lane_read64(kk, L);
-                    const bool sL = lane_read(sent ? 1u : 0u, L) != 0;
-                    const uint32_t pL = lane_read(p, L);
-                    const uint32_t eL = lane_read(e, L);
-                    const bool same = active && sub == subL;
-                    // a chunk holding its sentinel is a class of its own, ordered by strand
-                    const uint64_t m = sL ? (1ull << L) : __ballot(same && !sent && kk == kL);
-                    const uint64_t lt = __ballot(same && (kk < kL || (kk == kL && sent && p < pL)));
-                    const uint32_t base = subL + (uint32_t)__popcll(lt);
-                    const bool uni = (__ballot(e == eL) & m) == m;
-                    if ((m >> lane) & 1ull) {
-                        no = base + (uint32_t)__popcll(m & below);
-                        nsub = base;
-                        nlead = (uint32_t)L;
-                        nact = __popcll(m) >= 2 && !uni;
+#pragma unroll
+            for (int t = 0; t < WALK_DEPTHS; ++t) {
+                uint64_t rem[MPL], kk[MPL];
+                bool sent[MPL];
+                bool left = false;
+#pragma unroll
+                for (int s = 0; s < MPL; ++s) {
+                    kk[s] = act[s] ? kv[s][t] : 0ull;
+                    if (act[s]) {
+                        ++steps;
+                        if (kk[s] == ~0ull) atomicOr(guard, GUARD_RERANK);
                     }
-                    rem &= ~m;
+                    sent[s] = act[s] && chunk_has_sentinel(kk[s]);
+                    rem[s] = __ballot(act[s]);
+                    left |= rem[s] != 0;
                 }
-                o = no;
-                sub = nsub;
-                lead = nlead;
-                active = nact;
+                if (!left) break;
+                uint32_t no[MPL], nsub[MPL];
+                bool nact[MPL];
+#pragma unroll
+                for (int s = 0; s < MPL; ++s) {
+                    no[s] = o[s];
+                    nsub[s] = sub[s];
+                    nact[s] = act[s];
+                }
+                for (;;) {
+                    int sl = -1;
+#pragma unroll
+                    for (int s = MPL - 1; s >= 0; --s)
+                        if (rem[s]) sl = s;
+                    if (sl < 0) break;
+                    uint64_t remL = rem[0];
+                    uint32_t subR = sub[0], sentR = sent[0] ? 1u : 0u;
+                    uint64_t kR = kk[0];
+#pragma unroll
+                    for (int s = 1; s < MPL; ++s)
+                        if (sl == s) {
+                            remL = rem[s];
+                            subR = sub[s];
+                            sentR = sent[s] ? 1u : 0u;
+                            kR = kk[s];
+                        }
+                    const int L = __ffsll((unsigned long long)remL) - 1;
+                    const uint32_t subL = lane_read(subR, L);
+                    const uint64_t kL = lane_read64(kR, L);
+                    const bool sL = lane_read(sentR, L) != 0;
+                    uint64_t m[MPL], ins[MPL];
+                    bool whole = true;
+#pragma unroll
+                    for (int s = 0; s < MPL; ++s) {
+                        const bool same = act[s] && sub[s] == subL;
+                        ins[s] = __ballot(same);
+                        m[s] = sL ? ((s == sl) ? (1ull << L) : 0ull) : __ballot(same && !sent[s] && kk[s] == kL);
+                        whole &= m[s] == ins[s];
+                    }
+                    if (!whole) {
+                        // the subgroup splits here: place this class
+                        uint32_t pR = p[0], eR = e[0];
+#pragma unroll
+                        for (int s = 1; s < MPL; ++s)
+                            if (sl == s) {
+                                pR = p[s];
+                                eR = e[s];
+                            }
+                        const uint32_t pL = lane_read(pR, L), eL = lane_read(eR, L);
+                        uint32_t less = 0, cnt = 0;
+                        bool uni = true;
+#pragma unroll
+                        for (int s = 0; s < MPL; ++s) {
+                            const bool same = act[s] && sub[s] == subL;
+                            less += (uint32_t)__popcll(
+                                __ballot(same && (kk[s] < kL || (kk[s] == kL && sent[s] && p[s] < pL))));
+                            cnt += (uint32_t)__popcll(m[s]);
+                            uni &= (__ballot(e[s] == eL) & m[s]) == m[s];
+                        }
+                        const uint32_t base = subL + less;
+                        uint32_t pre = 0;
+#pragma unroll
+                        for (int s = 0; s < MPL; ++s) {
+                            if ((m[s] >> lane) & 1ull) {
+                                no[s] = base + pre + (uint32_t)__popcll(m[s] & below);
+                                nsub[s] = base;
+                                nact[s] = cnt >= 2 && !uni;
+                            }
+                            pre += (uint32_t)__popcll(m[s]);
+                        }
+                    }
+#pragma unroll
+                    for (int s = 0; s < MPL; ++s) rem[s] &= ~m[s];
+                }
+#pragma unroll
+                for (int s = 0; s < MPL; ++s) {
+                    o[s] = no[s];
+                    sub[s] = nsub[s];
+                    act[s] = nact[s];
+                }
             }
         }
-        if (member) SK[gs + o] = kp;
+#pragma unroll
+        for (int s = 0; s < MPL; ++s)
+            if ((uint32_t)(s * 64 + lane) < k) SK[gs + o[s]] = key[s];
     }
     const uint64_t tot = wave_sum_u64(steps);
     if (lane == 0 && tot) atomicAdd(reads, (unsigned long long)tot);
@@ -988,8 +1089,7 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint64_t *__restrict__ K
 // members carry different symbols. A split moves members, so the round ends
 // there and the next one loads from the following depth.
 template <int T, int MPT, int DEPTHS>
-__global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ K, const uint8_t *__restrict__ Q,
-                                                 int64_t n2, const uint32_t *__restrict__ SV,
+__global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, int64_t n2, const uint32_t *__restrict__ SV,
                                                  const uint32_t *__restrict__ glist, int64_t ng,
                                                  uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
                                                  unsigned long long *__restrict__ stat) {
@@ -1012,10 +1112,10 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ K,
             if (tid == 0) atomicOr(guard, GUARD_RERANK);
             continue;
         }
+        const uint64_t gkey = SK[gs] & ~7ull;
         for (int o = tid; o < k; o += T) {
-            uint32_t p = SV[gs + o];
-            spos[o] = p;
-            se[o] = (uint8_t)(K[p] & 7);
+            spos[o] = SV[gs + o];
+            se[o] = (uint8_t)(SK[gs + o] & 7);
             ssub[o] = 0;
             sact[o] = 1;
         }
@@ -1138,7 +1238,8 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ K,
             d0 += 8 * used;
         }
         maxd = d0 > maxd ? d0 : maxd;
-        for (int o = tid; o < k; o += T) SK[gs + o] = K[spos[o]];
+        // every thread read gkey before the first barrier of this group
+        for (int o = tid; o < k; o += T) SK[gs + o] = gkey | se[o];
         __syncthreads();
     }
     const uint64_t tot = wave_sum_u64(reads);
@@ -1433,28 +1534,28 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 int64_t wgs = (nq + LANES_WG - 1) / LANES_WG;
                 if (wgs > 2048) wgs = 2048;
                 RB3_LAUNCH("tie_lanes", k_tie_lanes, dim3((unsigned)wgs), dim3(LANES_WG), 0, c.stream,
-                           K.as<uint64_t>(), Qc, n2, SV, tl.l[0], (int64_t)hs2[0], tl.l[1], (int64_t)hs2[1],
+                           Qc, n2, SV, tl.l[0], (int64_t)hs2[0], tl.l[1], (int64_t)hs2[1],
                            qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, guard,
                            gtied.as<unsigned long long>() + 1);
                 // the deep list's length stays on the device: a fixed grid loops over it
-                RB3_LAUNCH("tie_deep", k_tie_deep, dim3(1024), dim3(256), 0, c.stream, K.as<uint64_t>(), Qc, n2, SV,
+                RB3_LAUNCH("tie_deep", k_tie_deep, dim3(1024), dim3(256), 0, c.stream, Qc, n2, SV,
                            dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, guard, gdeep.as<unsigned long long>());
             }
             if (hs2[2] > 0)
-                RB3_LAUNCH("tie_walk", k_tie_walk, grid_for(hs2[2], 4, 1 << 20), dim3(256), 0, c.stream,
-                           K.as<uint64_t>(), Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, guard,
+                RB3_LAUNCH("tie_walk", k_tie_walk<1>, grid_for(hs2[2], 4 * 8, 1 << 20), dim3(256), 0, c.stream,
+                           Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, guard,
                            gtied.as<unsigned long long>() + 3);
             if (hs2[3] > 0)
-                RB3_LAUNCH("tie_block128", (k_tie_block<128, 1, 4>), grid_for(hs2[3], 1, 8192), dim3(128), 0,
-                           c.stream, K.as<uint64_t>(), Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, guard,
-                           gblk.as<unsigned long long>());
+                RB3_LAUNCH("tie_walk128", k_tie_walk<2>, grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
+                           c.stream, Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, guard,
+                           gtied.as<unsigned long long>() + 3);
             if (hs2[4] > 0)
-                RB3_LAUNCH("tie_block256", (k_tie_block<256, 1, 4>), grid_for(hs2[4], 1, 4096), dim3(256), 0,
-                           c.stream, K.as<uint64_t>(), Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, guard,
-                           gblk.as<unsigned long long>());
+                RB3_LAUNCH("tie_walk256", k_tie_walk<4>, grid_for(hs2[4], 4 * 8, 1 << 20), dim3(256), 0,
+                           c.stream, Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, guard,
+                           gtied.as<unsigned long long>() + 3);
             if (hs2[5] > 0)
                 RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
-                           c.stream, K.as<uint64_t>(), Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, guard,
+                           c.stream, Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, guard,
                            gblk.as<unsigned long long>());
             unsigned long long hd[2], hb[2];
             RB3_HIP(hipMemcpyAsync(ht, gtied.p, sizeof(ht), hipMemcpyDeviceToHost, c.stream));
