@@ -37,6 +37,14 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Workgroups are dealt to the 8 XCDs round robin. Giving each XCD a
+// contiguous range of tiles keeps the neighbouring pieces of each digit's
+// output run, written by neighbouring tiles, in the same L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+    const int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // Scatter of one tile. The tile's keys are first ranked stably inside the
 // tile and staged in LDS in digit order; then the workgroup writes them out
 // with consecutive threads on consecutive output positions, so each digit's
@@ -60,7 +68,8 @@ __global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__res
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int i = tid; i < SC_WAVES * 256; i += SC_THREADS) (&wbase[0][0])[i] = 0;
     __syncthreads();
-    const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t tile0 = tile * RS_TILE;
     const int64_t base = tile0 + (int64_t)wave * (64 * SC_STEPS);
     uint64_t k[SC_STEPS];
     uint32_t v[SC_STEPS];
@@ -97,7 +106,7 @@ __global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__res
     if (tid < 256) {
         uint32_t pre = inc - tot;
         for (int w = 0; w < wave; ++w) pre += wsum[w];
-        gbase[tid] = O[(int64_t)tid * ntiles + blockIdx.x] - pre;
+        gbase[tid] = O[(int64_t)tid * ntiles + tile] - pre;
         uint32_t run = pre;
 #pragma unroll
         for (int w = 0; w < SC_WAVES; ++w) {
