@@ -306,7 +306,7 @@ def incremental_bench(args):
     total_s = 0.0
     rb3.rb3_prof_reset()
     rb3.rb3_prof_enable(True)
-    torch.cuda.reset_peak_stats()
+    torch.cuda.reset_peak_memory_stats()
     dev_free_min = None
     for b in range(args.batches):
         t = time.perf_counter()
