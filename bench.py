@@ -174,6 +174,9 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
     srv = rb3.Server(idx, workers=4)
     m_served = min(served_queries, n_queries)
     sq = w.queries.slice(0, m_served)
+    # warm-up: the workers' device pools fill on their first batches
+    wq = w.queries.slice(0, min(1000, m_served))
+    srv.replay(rb3.RB3_REQ_SMEM, wq.data, wq.lens, synth.poisson_arrivals(wq.n, rates[0] * qps), min_len, 1)
     for frac in rates:
         lam = frac * qps
         arr = synth.poisson_arrivals(m_served, lam)
@@ -454,7 +457,7 @@ def main():
     smem = None
     if not args.no_smem:
         b1.close()
-        smem = smem_bench(10_000_000, 32, 2000, 200, [0.5], 2000)
+        smem = smem_bench(10_000_000, 32, 10_000, 200, [0.5], 10_000)
 
     out = {
         "metric": "BWT-merge suffixes inserted/s",

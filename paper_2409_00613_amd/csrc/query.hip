@@ -69,42 +69,12 @@ __device__ __forceinline__ BiInt backward_ext(const DevIndex &ix, const BiInt &x
     return r;
 }
 
-// Algorithm 3, ForwardExt: the bi-interval of Pa, by extending rc(P)
-// backwards with comp(a) and swapping.
-__device__ __forceinline__ BiInt forward_ext(const DevIndex &ix, const BiInt &x, int a) {
-    BiInt y;
-    y.k = x.kr;
-    y.kr = x.k;
-    y.s = x.s;
-    BiInt z = backward_ext(ix, y, comp_sym(a));
-    BiInt r;
-    r.k = z.kr;
-    r.kr = z.k;
-    r.s = z.s;
-    return r;
-}
-
-__device__ __forceinline__ void emit_smem(rb3_smem_t *out, int64_t cap, unsigned long long *total, int64_t qid,
-                                          int32_t seq, int64_t st, int64_t en, const BiInt &x) {
-    unsigned long long slot = atomicAdd(total, 1ull);
-    if ((int64_t)slot < cap) {
-        rb3_smem_t r;
-        r.start = st;
-        r.end = en;
-        r.occ = x.s;
-        r.k = x.k;
-        r.krc = x.kr;
-        r.qid = (int32_t)qid;
-        r.pad = seq;
-        out[slot] = r;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Algorithm 4 over query segments
 // ---------------------------------------------------------------------------
 //
-// A query is cut into segments of SMEM_SEG positions. Algorithm 4 is run
+// A query is cut into segments of S positions (S from the batch size, see
+// smem_run). Algorithm 4 is run
 // from each segment's first position and stops once its start passes the
 // segment's end (forward extensions still read past it). Started at an
 // arbitrary position c, the algorithm reports exactly the SMEMs of length
@@ -182,66 +152,67 @@ __global__ void __launch_bounds__(SMEM_WG) k_smem_seg(DevIndex ix, const uint8_t
         bool emit = false, done = false;
         int64_t em_start = 0, em_end = 0;
         BiInt em_x = empty;
-        if (busy) {
-            if (phase == PH_START) {
-                if (i >= c1 || i + ell > L) {
-                    done = true;
-                } else {
-                    x = empty;
-                    j = i + ell - 1;
-                    phase = PH_BACK1;
-                }
+        if (busy && phase == PH_START) {
+            if (i >= c1 || i + ell > L) {
+                done = true;
+            } else {
+                x = empty;
+                j = i + ell - 1;
+                phase = PH_BACK1;
             }
-            if (!done) {
-                if (phase == PH_BACK1) {
-                    x = backward_ext(ix, x, P[j]);
-                    ++nexts;
-                    if (x.s < smin) {
-                        i = j + 1;
-                        phase = PH_START;
-                    } else if (j == i) {
-                        j = i + ell;
-                        phase = PH_FWD;
-                    } else {
-                        --j;
-                    }
-                } else if (phase == PH_FWD) {
-                    bool stop;
-                    BiInt y = x;
+        }
+        // every phase extends by one symbol; a forward extension is a
+        // backward one of the reverse-complement interval (Algorithm 3), so
+        // all busy lanes share one extension call and its block reads
+        const bool fwd = phase == PH_FWD;
+        const bool need = busy && !done && !(fwd && j >= L);
+        BiInt y = x;
+        if (need) {
+            const int a = P[j];
+            const BiInt in = fwd ? BiInt{x.kr, x.k, x.s} : x;
+            const BiInt z = backward_ext(ix, in, fwd ? comp_sym(a) : a);
+            y = fwd ? BiInt{z.kr, z.k, z.s} : z;
+            ++nexts;
+        }
+        if (busy && !done) {
+            if (phase == PH_BACK1) {
+                x = y;
+                if (x.s < smin) {
+                    i = j + 1;
+                    phase = PH_START;
+                } else if (j == i) {
+                    j = i + ell;
+                    phase = PH_FWD;
+                } else {
+                    --j;
+                }
+            } else if (phase == PH_FWD) {
+                const bool stop = j >= L || y.s < smin;
+                if (stop) {
+                    emit = true;
+                    em_start = i;
+                    em_end = j;
+                    em_x = x;
                     if (j >= L) {
-                        stop = true;
+                        done = true;  // an SMEM reaching the end: no later start can add one
                     } else {
-                        y = forward_ext(ix, x, P[j]);
-                        ++nexts;
-                        stop = y.s < smin;
+                        x = empty;
+                        phase = PH_BACK2;  // j stays at e
                     }
-                    if (stop) {
-                        emit = true;
-                        em_start = i;
-                        em_end = j;
-                        em_x = x;
-                        if (j >= L) {
-                            done = true;  // an SMEM reaching the end: no later start can add one
-                        } else {
-                            x = empty;
-                            phase = PH_BACK2;  // j stays at e
-                        }
-                    } else {
-                        x = y;
-                        ++j;
-                    }
-                } else if (phase == PH_BACK2) {
-                    x = backward_ext(ix, x, P[j]);
-                    ++nexts;
-                    if (x.s < smin) {
-                        i = j + 1;
-                        phase = PH_START;
-                    } else if (j == i + 1) {
-                        i = i + 1;
-                        phase = PH_START;
-                    } else {
-                        --j;
-                    }
+                } else {
+                    x = y;
+                    ++j;
+                }
+            } else if (phase == PH_BACK2) {
+                x = y;
+                if (x.s < smin) {
+                    i = j + 1;
+                    phase = PH_START;
+                } else if (j == i + 1) {
+                    i = i + 1;
+                    phase = PH_START;
+                } else {
+                    --j;
                 }
             }
         }
@@ -283,21 +254,39 @@ __global__ void __launch_bounds__(SMEM_WG) k_smem_seg(DevIndex ix, const uint8_t
 }
 
 // Per segment: whether its first report is contained in an SMEM of an
-// earlier segment of the same query, and how many reports it keeps.
-__global__ void k_smem_fix(const Seg *__restrict__ segs, int64_t nseg, const uint32_t *__restrict__ segcnt,
+// earlier segment of the same query (its end does not pass the largest end
+// reported before it in the query), and how many reports it keeps. One wave
+// per query walks its segments 64 at a time with a running maximum.
+__global__ void k_smem_fix(const int64_t *__restrict__ qseg, int64_t nq, const uint32_t *__restrict__ segcnt,
                            const int64_t *__restrict__ segfirst, const int64_t *__restrict__ seglast,
                            uint32_t *__restrict__ drop, uint32_t *__restrict__ kept) {
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nseg;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t d = 0;
-        if (segcnt[g] > 0) {
-            int64_t maxend = -1;
-            for (int64_t h = g - 1; h >= 0 && segs[h].qid == segs[g].qid; --h)
-                maxend = seglast[h] > maxend ? seglast[h] : maxend;
-            d = segfirst[g] <= maxend ? 1u : 0u;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t qq = wave; qq < nq; qq += nwaves) {
+        const int64_t s0 = qseg[qq], s1 = qseg[qq + 1];
+        int64_t carry = -1;  // largest end reported by the segments before this run
+        for (int64_t base = s0; base < s1; base += 64) {
+            const int64_t g = base + lane;
+            const bool in = g < s1;
+            const int64_t v = in ? seglast[g] : -1;
+            int64_t incl = v;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int64_t t = __shfl_up(incl, d);
+                if (lane >= d && t > incl) incl = t;
+            }
+            int64_t excl = __shfl_up(incl, 1);
+            if (lane == 0) excl = -1;
+            if (carry > excl) excl = carry;
+            if (in) {
+                const uint32_t n = segcnt[g];
+                const uint32_t d = (n > 0 && segfirst[g] <= excl) ? 1u : 0u;
+                drop[g] = d;
+                kept[g] = n - d;
+            }
+            const int64_t tot = __shfl(incl, 63);
+            if (tot > carry) carry = tot;
         }
-        drop[g] = d;
-        kept[g] = segcnt[g] - d;
     }
 }
 
@@ -331,11 +320,14 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
              int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
              int64_t *h_exts) {
     // segment table: segments short enough that the batch fills the GPU
-    // with lanes (each segment repeats about one SMEM's worth of work at its
-    // start, so not shorter than SMEM_SEG_MIN)
+    // with lanes. Each segment repeats some work at its start (the first
+    // min_len-symbol check, and the tail of an SMEM begun in the segment
+    // before), so segments stay long when the batch alone fills the GPU and
+    // shrink to SMEM_SEG_MIN for small batches, where latency matters.
     int64_t bases = 0;
     for (int64_t qq = 0; qq < nq; ++qq) bases += qlens[qq];
-    int64_t S = bases / SMEM_TARGET_SEGS;
+    const int64_t target = c.smem_segs > 0 ? c.smem_segs : SMEM_TARGET_SEGS;
+    int64_t S = bases / target;
     S = S < SMEM_SEG_MIN ? SMEM_SEG_MIN : (S > SMEM_SEG ? SMEM_SEG : S);
     std::vector<Seg> segs;
     std::vector<int64_t> qseg(nq + 1);
@@ -389,8 +381,8 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
                    d_segs.as<Seg>(), nseg, min_len, min_occ, qh.as<uint32_t>(), d_tmp, cap,
                    tot.as<unsigned long long>(), cnt.as<uint32_t>(), first.as<int64_t>(), last.as<int64_t>(),
                    ext.as<unsigned long long>());
-        RB3_LAUNCH("smem_fix", k_smem_fix, grid_for(nseg, 256, 1 << 20), dim3(256), 0, c.stream,
-                   d_segs.as<Seg>(), nseg, cnt.as<uint32_t>(), first.as<int64_t>(), last.as<int64_t>(),
+        RB3_LAUNCH("smem_fix", k_smem_fix, grid_for(nq, 4, 1 << 20), dim3(256), 0, c.stream,
+                   d_qseg.as<int64_t>(), nq, cnt.as<uint32_t>(), first.as<int64_t>(), last.as<int64_t>(),
                    drop.as<uint32_t>(), kept.as<uint32_t>());
     }
     RB3_TRY(scan_u32(c, kept.as<uint32_t>(), segoff.as<uint32_t>(), nseg + 1, false, false, nullptr));

@@ -228,6 +228,11 @@ void worker_main(rb3_server *s) {
             }
             s->inflight_bytes += bytes;
             s->inflight_batches += 1;
+            // batches running together share the GPU's lanes: each aims at
+            // its share of the SMEM segments that fill the chip, so segments
+            // are short (low latency) when the server is quiet and long (less
+            // repeated work per segment) when it is busy
+            c.smem_segs = SMEM_TARGET_SEGS / s->inflight_batches;
             s->batches += 1;
             if ((int64_t)batch.size() > s->max_batch) s->max_batch = (int64_t)batch.size();
         }
