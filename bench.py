@@ -444,7 +444,7 @@ def main():
     roofline = roofline_of(prof, st, args.steps, workload, src_hash)
 
     plain = None
-    if workload == "uneven_merge":
+    if workload == "uneven_merge" and args.plain_strings > 0:
         plain = plain_vs_batched(b1_strings, new_strings, args.chunk, args.plain_strings)
 
     cpu = None

@@ -1255,7 +1255,7 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, 
 // sorted entries land in non-decreasing blocks, so each wave adds one count
 // per run of equal blocks instead of one per entry.
 __global__ void k_block_count(const uint64_t *__restrict__ SK, int64_t n2, int64_t m1, int lshift,
-                              uint32_t *__restrict__ cnt) {
+                              int64_t nblk_out, uint32_t *__restrict__ cnt, int32_t *__restrict__ guard) {
     int lane = threadIdx.x & 63;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t base0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63);
@@ -1270,7 +1270,8 @@ __global__ void k_block_count(const uint64_t *__restrict__ SK, int64_t n2, int64
         if (head) {
             uint64_t above = heads & ~low_mask(lane + 1);
             int next = above ? __ffsll((unsigned long long)above) - 1 : 64 - __clzll((long long)vmask);
-            atomicAdd(&cnt[b], (uint32_t)(next - lane));
+            if (b >= 0 && b < nblk_out) atomicAdd(&cnt[b], (uint32_t)(next - lane));
+            else atomicOr(guard, GUARD_INTERLEAVE);
         }
     }
 }
@@ -1662,7 +1663,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     RB3_ALLOC(bcnt, &c, (nblk_out + 1) * sizeof(uint32_t));
     RB3_HIP(hipMemsetAsync(bcnt.p, 0, (nblk_out + 1) * sizeof(uint32_t), c.stream));
     RB3_LAUNCH("merge_block_count", k_block_count, grid_for(n2, 256 * 8), dim3(256), 0, c.stream, SK, n2, m1,
-               lshift, bcnt.as<uint32_t>());
+               lshift, nblk_out, bcnt.as<uint32_t>(), guard);
     RB3_TRY(scan_u32(c, bcnt.as<uint32_t>(), bcnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
     RB3_ALLOC(out_blk, &c, nblk_out * 64);
     RB3_ALLOC(out_sb, &c, num_superblocks(nout) * SB_STRIDE * sizeof(int64_t));

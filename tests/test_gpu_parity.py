@@ -146,17 +146,23 @@ def test_build_random_lists_equal_oracle():
             idx.close()
 
 
-def test_merge_pangenome_small():
-    say("case: pangenome merge, 20 kb genome, 8 + 8 haplotypes")
+@pytest.mark.parametrize("chunk_len", [1024, 40])
+def test_merge_pangenome_small(chunk_len):
+    """Haplotypes share long stretches with the index, so chain chunks
+    converge late; with 40-position chunks whole runs of chunks stay
+    unresolved after the chains, and the fix-up passes replay them."""
+    say(f"case: pangenome merge, 20 kb genome, 8 + 8 haplotypes, chunk_len={chunk_len}")
     w = synth.config_pangenome(genome_len=20_000, n_b1=8, n_new=8)
-    idx = rb3.rb3_build(w.b1.data, w.b1.lens, chunk_len=1024)
+    idx = rb3.rb3_build(w.b1.data, w.b1.lens, chunk_len=chunk_len)
     idx.merge(w.new.data, w.new.lens)
     st = idx.merge_stats()
     codes, lens = _expand(w.b1 + w.new)
     got = idx.export()
     assert np.array_equal(got, oracle.bwt(codes, lens))
-    assert st["tied_records"] > 0 and st["tie_groups"] > 0 and st["fixup_steps"] > 0
+    assert st["tied_records"] > 0 and st["tie_groups"] > 0
     assert st["tie_work"] + st["tie_small_reads"] > 0
+    if chunk_len == 40:
+        assert st["fixup_steps"] > 0 and st["fixup_passes"] >= 2
     idx.close()
 
 
