@@ -126,8 +126,11 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
     log(f"serving workload: {n_index} haplotypes of ~{genome} bases, {n_queries} queries "
         f"({w.queries.total} bases) in {time.perf_counter() - t:.1f} s")
     t = time.perf_counter()
-    # batches of 32 haplotypes keep every merge below the per-batch size limit
-    idx = rb3.rb3_build(w.index.slice(0, min(32, n_index)).data, w.index.slice(0, min(32, n_index)).lens)
+    # batches of 32 haplotypes keep every merge below the per-batch size limit;
+    # device memory from torch's caching allocator, as a caller would pass it
+    alloc = rb3.TorchAllocator(0)
+    idx = rb3.rb3_build(w.index.slice(0, min(32, n_index)).data, w.index.slice(0, min(32, n_index)).lens,
+                        allocator=alloc)
     for a in range(32, n_index, 32):
         part = w.index.slice(a, min(a + 32, n_index))
         idx.merge(part.data, part.lens)

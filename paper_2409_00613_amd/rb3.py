@@ -176,9 +176,16 @@ class TorchAllocator:
             except Exception:
                 return None
 
+        delete = torch.cuda.caching_allocator_delete
+
         def _free(ptr, ctx):
+            # an index freed while the interpreter shuts down may outlive
+            # torch's allocator: the memory goes with the process then
             if ptr:
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    delete(ptr)
+                except Exception:
+                    pass
 
         self.alloc_fn = _ALLOC_FN(_alloc)
         self.free_fn = _FREE_FN(_free)
@@ -287,7 +294,9 @@ def rb3_smem(idx: Index, q, qlens, min_len: int, min_occ: int = 1, cap: int | No
     la, lp = _lens(qlens)
     n = la.shape[0]
     if cap is None:
-        cap = max(1024, int(la.sum()) // 16 + 16 * n)
+        # about one SMEM per 100 bases on reads with 1% differences; a call
+        # that needs more is repeated with the exact size
+        cap = max(1024, int(la.sum()) // 48 + 16 * n)
     while True:
         out = np.zeros(max(cap, 1), dtype=SMEM_DTYPE)
         off = np.zeros(n + 1, np.int64)
