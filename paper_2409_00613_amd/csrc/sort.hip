@@ -49,7 +49,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 // tile and staged in LDS in digit order; then the workgroup writes them out
 // with consecutive threads on consecutive output positions, so each digit's
 // run leaves as whole lines instead of scattered 8- and 4-byte stores.
-constexpr int SC_THREADS = 512;
+constexpr int SC_THREADS = 1024;
 constexpr int SC_WAVES = SC_THREADS / 64;
 constexpr int SC_STEPS = RS_TILE / SC_THREADS;  // 64-key steps per wave
 
