@@ -371,7 +371,8 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // atomic per class per flush.
 constexpr int TG_THREADS = 256;
 constexpr int TG_CLASSES = 6;
-constexpr int TG_LCAP = 512;  // LDS list capacity per class
+constexpr int TG_WIN = 4;      // 64-key windows per wave per iteration, loaded together
+constexpr int TG_LCAP = 1024;  // LDS list capacity per class
 // class upper bounds: 2 | 3..8 | 9..64 | 65..128 | 129..256 | 257..8192
 constexpr uint32_t TG_BOUND[TG_CLASSES] = {2, 8, 64, 128, 256, 8192};
 
@@ -399,70 +400,84 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
     __syncthreads();
     uint64_t ntied = 0;
     uint32_t kmax = 0;
-    const int64_t ntiles = (n + TG_THREADS - 1) / TG_THREADS;
+    constexpr int64_t TILE = (int64_t)TG_THREADS * TG_WIN;
+    const int64_t ntiles = (n + TILE - 1) / TILE;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t w0 = tile * TG_THREADS + (int64_t)wv * 64;
-        const int64_t s = w0 + lane;
-        const bool in = s < n;
-        const uint64_t v = in ? SK[s] : ~0ull;
-        const uint64_t key = v >> 3;
-        const uint32_t e = (uint32_t)(v & 7);
-        uint64_t prevkey = __shfl_up(key, 1);
-        if (lane == 0) prevkey = (s > 0 && in) ? (SK[s - 1] >> 3) : ~0ull;
-        // a key holding its sentinel is unique: always a group of its own
-        const bool sent = (key & 7) == 0;
-        const bool start = in && (s == 0 || sent || key != prevkey);
-        const uint64_t smask = __ballot(start);
-        const uint64_t inmask = __ballot(in);
-        // leader of my group inside the window (lane of the last start at or below me)
-        const uint64_t below = smask & low_mask(lane + 1);
-        const int lead = below ? 63 - __clzll((long long)below) : -1;
-        const uint32_t le = __shfl(e, lead < 0 ? 0 : lead);
-        const bool mism = in && lead >= 0 && e != le;
-        const uint64_t mmask = __ballot(mism);
-        // the window's last group may run past its end: the whole wave
-        // extends it with coalesced 64-key reads of the following windows
-        const int last_in = inmask ? 63 - __clzll((long long)inmask) : -1;
-        const int ls = smask ? 63 - __clzll((long long)smask) : -1;
-        const uint64_t xkey = __shfl(key, ls < 0 ? 0 : ls);
-        const uint32_t xe = __shfl(e, ls < 0 ? 0 : ls);
-        int64_t ext = 0;
-        bool xuni = true;
-        if (ls >= 0 && last_in == 63 && (xkey & 7) != 0) {
-            for (int64_t t = w0 + 64; t < n; t += 64) {
-                const int64_t u = t + lane;
-                const uint64_t uv = u < n ? SK[u] : ~0ull;
-                const uint64_t mm = __ballot((uv >> 3) == xkey);
-                const int run = ~mm ? __ffsll((unsigned long long)~mm) - 1 : 64;
-                if (__ballot(lane < run && (uint32_t)(uv & 7) != xe)) xuni = false;
-                ext += run;
-                if (run < 64) break;
-            }
+        // this wave's TG_WIN consecutive windows, all loads in flight at once
+        const int64_t wbase = tile * TILE + (int64_t)wv * 64 * TG_WIN;
+        uint64_t vw[TG_WIN];
+#pragma unroll
+        for (int j = 0; j < TG_WIN; ++j) {
+            const int64_t sj = wbase + (int64_t)j * 64 + lane;
+            vw[j] = sj < n ? SK[sj] : ~0ull;
         }
-        if (start && !sent) {
-            const uint64_t above = smask & ~low_mask(lane + 1);
-            const int ns = above ? __ffsll((unsigned long long)above) - 1 : last_in + 1;
-            const int64_t k = (ns - lane) + (above ? 0 : ext);
-            const bool uni = (mmask & low_mask(ns) & ~low_mask(lane)) == 0 && (above || xuni);
-            if (k >= 2) {
-                ntied += (uint64_t)k;
-                if (!uni) {
-                    uint32_t kk = (uint32_t)(k > 0xFFFFFFFFll ? 0xFFFFFFFFll : k);
-                    int c = group_class(kk);
-                    uint32_t slot = atomicAdd(&lcnt[c], 1u);
-                    lst[c][slot][0] = (uint32_t)s;
-                    lst[c][slot][1] = kk;
-                    atomicAdd(&hist[31 - __clz(kk)], 1u);
-                    kmax = kk > kmax ? kk : kmax;
+        uint64_t carry = (wbase > 0 && wbase < n) ? (SK[wbase - 1] >> 3) : ~0ull;  // key before the first window
+#pragma unroll
+        for (int j = 0; j < TG_WIN; ++j) {
+            const int64_t w0 = wbase + (int64_t)j * 64;
+            const int64_t s = w0 + lane;
+            const bool in = s < n;
+            const uint64_t v = vw[j];
+            const uint64_t key = v >> 3;
+            const uint32_t e = (uint32_t)(v & 7);
+            uint64_t prevkey = __shfl_up(key, 1);
+            if (lane == 0) prevkey = in ? carry : ~0ull;
+            carry = __shfl(key, 63);
+            // a key holding its sentinel is unique: always a group of its own
+            const bool sent = (key & 7) == 0;
+            const bool start = in && (s == 0 || sent || key != prevkey);
+            const uint64_t smask = __ballot(start);
+            const uint64_t inmask = __ballot(in);
+            // leader of my group inside the window (lane of the last start at or below me)
+            const uint64_t below = smask & low_mask(lane + 1);
+            const int lead = below ? 63 - __clzll((long long)below) : -1;
+            const uint32_t le = __shfl(e, lead < 0 ? 0 : lead);
+            const bool mism = in && lead >= 0 && e != le;
+            const uint64_t mmask = __ballot(mism);
+            // the window's last group may run past its end: the whole wave
+            // extends it with coalesced 64-key reads of the following windows
+            const int last_in = inmask ? 63 - __clzll((long long)inmask) : -1;
+            const int ls = smask ? 63 - __clzll((long long)smask) : -1;
+            const uint64_t xkey = __shfl(key, ls < 0 ? 0 : ls);
+            const uint32_t xe = __shfl(e, ls < 0 ? 0 : ls);
+            int64_t ext = 0;
+            bool xuni = true;
+            if (ls >= 0 && last_in == 63 && (xkey & 7) != 0) {
+                for (int64_t t = w0 + 64; t < n; t += 64) {
+                    const int64_t u = t + lane;
+                    const uint64_t uv = u < n ? SK[u] : ~0ull;
+                    const uint64_t mm = __ballot((uv >> 3) == xkey);
+                    const int run = ~mm ? __ffsll((unsigned long long)~mm) - 1 : 64;
+                    if (__ballot(lane < run && (uint32_t)(uv & 7) != xe)) xuni = false;
+                    ext += run;
+                    if (run < 64) break;
+                }
+            }
+            if (start && !sent) {
+                const uint64_t above = smask & ~low_mask(lane + 1);
+                const int ns = above ? __ffsll((unsigned long long)above) - 1 : last_in + 1;
+                const int64_t k = (ns - lane) + (above ? 0 : ext);
+                const bool uni = (mmask & low_mask(ns) & ~low_mask(lane)) == 0 && (above || xuni);
+                if (k >= 2) {
+                    ntied += (uint64_t)k;
+                    if (!uni) {
+                        uint32_t kk = (uint32_t)(k > 0xFFFFFFFFll ? 0xFFFFFFFFll : k);
+                        int c = group_class(kk);
+                        uint32_t slot = atomicAdd(&lcnt[c], 1u);
+                        lst[c][slot][0] = (uint32_t)s;
+                        lst[c][slot][1] = kk;
+                        atomicAdd(&hist[31 - __clz(kk)], 1u);
+                        kmax = kk > kmax ? kk : kmax;
+                    }
                 }
             }
         }
         __syncthreads();
-        // flush a class list when the next tile could overflow it (a tile adds at most TG_THREADS / 2)
+        // flush a class list when the next tile could overflow it (a tile adds at most TILE / 2)
         const bool last_tile = tile + gridDim.x >= ntiles;
         for (int c = 0; c < TG_CLASSES; ++c) {
             uint32_t cnt = lcnt[c];
-            if (cnt == 0 || (!last_tile && cnt + TG_THREADS / 2 <= TG_LCAP)) continue;
+            if (cnt == 0 || (!last_tile && cnt + TILE / 2 <= TG_LCAP)) continue;
             if (threadIdx.x == 0) lbase[c] = atomicAdd(&gstat[c], cnt);
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < cnt; i += TG_THREADS) {
@@ -1508,7 +1523,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_HIP(hipMemsetAsync(gtied.p, 0, 4 * sizeof(unsigned long long), c.stream));
         RB3_HIP(hipMemsetAsync(gdeep.p, 0, 2 * sizeof(unsigned long long), c.stream));
         RB3_HIP(hipMemsetAsync(gblk.p, 0, 2 * sizeof(unsigned long long), c.stream));
-        RB3_LAUNCH("tie_groups", k_tie_groups, grid_for(n2, TG_THREADS * 64, 2048), dim3(TG_THREADS), 0,
+        RB3_LAUNCH("tie_groups", k_tie_groups, grid_for(n2, TG_THREADS * TG_WIN * 16, 2048), dim3(TG_THREADS), 0,
                    c.stream, SK, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>());
         uint32_t hs2[8];
         unsigned long long ht[4];
