@@ -27,9 +27,11 @@
 namespace rb3 {
 
 struct Chunk {
-    int64_t p0;    // position in Q of the chunk's first symbol
-    int32_t len;   // symbols in the chunk
-    int32_t last;  // 1 if the chunk ends at the strand's sentinel
+    int64_t p0;     // position in Q of the chunk's first symbol
+    int32_t len;    // symbols in the chunk
+    int32_t last;   // 1 if the chunk ends at the strand's sentinel
+    int32_t first;  // 1 if the chunk starts at the strand's first symbol
+    int32_t pad;
 };
 
 // Sort key of a new suffix at position p:
@@ -88,9 +90,23 @@ struct KeyWindow {
     }
 };
 
+// Left neighbours whose unresolved ends one lane may walk after its own
+// chunk (more are left to the fix-up passes).
+constexpr int CHAIN_TAKEOVER = 2;
+
+// One lane per chunk. The walk covers the chunk right to left; once its
+// value is exact the lane publishes how many of its positions it walked
+// before that (conv, a device-scope store nobody waits for). A lane whose
+// value is exact at its chunk's start then reads its left neighbour's
+// count once and walks exactly those positions, the neighbour's unresolved
+// end, with exact values (fixed[] marks the neighbour as complete). If the
+// neighbour has not published (it has not converged, or not yet), the lane
+// walks the whole neighbour and may go on to the next one. The positions
+// walked this way are exactly the ones a fix-up pass would replay, but they
+// run while the other chains are still going.
 __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
                         int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K,
-                        int32_t *__restrict__ unres, int32_t *__restrict__ ready,
+                        int32_t *__restrict__ unres, int32_t *__restrict__ conv, int32_t *__restrict__ fixed,
                         unsigned long long *__restrict__ stats) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nch) return;
@@ -103,12 +119,13 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     if (c.last) {
         point = true;
         K[p1] = (uint64_t)Q[p1 - 1];  // sentinel suffix: l = m1, no symbols
+        __hip_atomic_store(&conv[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         point = false;
         packed = pack_ahead(Q, p1, w);
     }
     int32_t unresolved = 0;
-    int64_t wide = 0;
+    int64_t wide = 0, taken = 0;
     KeyWindow win;
     win.init();
     for (int64_t p = p1 - 1; p >= c.p0; --p) {
@@ -135,6 +152,7 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
                 point = true;
                 l = lo;
                 win.push(make_key(l - m1, packed, emit, lshift), true);
+                __hip_atomic_store(&conv[i], unresolved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 ++unresolved;
                 win.push(0, false);
@@ -143,9 +161,45 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
         if ((p & 7) == 0 || p == c.p0) win.flush(K, p);
     }
     unres[i] = unresolved;
-    ready[i] = point ? 1 : 0;
-    if (unresolved) atomicAdd(&stats[0], (unsigned long long)unresolved);
+    if (point) {
+        int64_t j = i;
+        for (int t = 0; t < CHAIN_TAKEOVER; ++t) {
+            if (ch[j].first) break;
+            const int64_t nb = j - 1;  // same strand: j does not start it
+            const Chunk cn = ch[nb];
+            const int32_t v = __hip_atomic_load(&conv[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int64_t end = cn.p0 + cn.len;
+            const int64_t stop = v >= 0 ? end - v : cn.p0;
+            for (int64_t p = end - 1; p >= stop; --p) {
+                uint32_t a = Q[p];
+                uint32_t emit = p > 0 ? Q[p - 1] : 0u;
+                packed = ((uint64_t)a << wsh) | (packed >> 3);
+                l = pi_sym(ix, (int)a, l);
+                win.push(make_key(l - m1, packed, emit, lshift), true);
+                if ((p & 7) == 0 || p == stop) win.flush(K, p);
+            }
+            taken += end - stop;
+            fixed[nb] = 1;
+            if (v >= 0) break;  // the neighbour resolved the rest itself
+            j = nb;
+        }
+    }
     if (wide) atomicAdd(&stats[1], (unsigned long long)wide);
+    if (taken) atomicAdd(&stats[2], (unsigned long long)taken);
+}
+
+// After the chains: chunks completed by a right neighbour have nothing left
+// to fix; the others keep their unresolved end, and a chunk's first
+// position is exact (ready) unless the whole chunk is unresolved.
+__global__ void k_chain_join(const Chunk *__restrict__ ch, int64_t nch, int32_t *__restrict__ unres,
+                             const int32_t *__restrict__ fixed, int32_t *__restrict__ ready,
+                             unsigned long long *__restrict__ stats) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nch) return;
+    int32_t u = fixed[i] ? 0 : unres[i];
+    unres[i] = u;
+    ready[i] = u < ch[i].len ? 1 : 0;
+    if (u) atomicAdd(&stats[0], (unsigned long long)u);
 }
 
 __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
@@ -1417,6 +1471,8 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 ck.p0 = off + t0;
                 ck.len = (int32_t)(t1 - t0);
                 ck.last = t1 == L ? 1 : 0;
+                ck.first = t0 == 0 ? 1 : 0;
+                ck.pad = 0;
                 chunks.push_back(ck);
             }
             off += L + 1;
@@ -1425,9 +1481,13 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         st.chunks = nch;
         st.chunk_len = CL;
         st.chain_steps = n2 - m2;
-        DBuf d_ch, unres, readyA, readyB, pend;
+        DBuf d_ch, unres, conv, fixed, readyA, readyB, pend;
         RB3_ALLOC(d_ch, &c, nch * sizeof(Chunk));
         RB3_ALLOC(unres, &c, nch * sizeof(int32_t));
+        RB3_ALLOC(conv, &c, nch * sizeof(int32_t));
+        RB3_ALLOC(fixed, &c, nch * sizeof(int32_t));
+        RB3_HIP(hipMemsetAsync(conv.p, 0xFF, nch * sizeof(int32_t), c.stream));
+        RB3_HIP(hipMemsetAsync(fixed.p, 0, nch * sizeof(int32_t), c.stream));
         RB3_ALLOC(readyA, &c, (nch + 1) * sizeof(int32_t));
         RB3_ALLOC(readyB, &c, (nch + 1) * sizeof(int32_t));
         RB3_ALLOC(pend, &c, sizeof(int32_t));
@@ -1441,18 +1501,22 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 if (k == 0) continue;
                 RB3_LAUNCH("chain", k_chain, grid_for(k, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
                            d_ch.as<Chunk>() + f, k, m1, w, K.as<uint64_t>(), unres.as<int32_t>() + f,
-                           readyA.as<int32_t>() + f, stats.as<unsigned long long>());
+                           conv.as<int32_t>() + f, fixed.as<int32_t>() + f, stats.as<unsigned long long>());
             }
         } else {
             RB3_LAUNCH("chain", k_chain, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
-                       d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(),
-                       readyA.as<int32_t>(), stats.as<unsigned long long>());
+                       d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(), conv.as<int32_t>(),
+                       fixed.as<int32_t>(), stats.as<unsigned long long>());
         }
+        RB3_LAUNCH("chain_join", k_chain_join, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
+                   d_ch.as<Chunk>(), nch, unres.as<int32_t>(), fixed.as<int32_t>(), readyA.as<int32_t>(),
+                   stats.as<unsigned long long>());
         unsigned long long hs[4];
         RB3_HIP(hipMemcpyAsync(hs, stats.p, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
         RB3_HIP(hipStreamSynchronize(c.stream));
         st.fixup_steps = (int64_t)hs[0];
-        st.chain_steps += (int64_t)hs[1];
+        st.chain_steps += (int64_t)hs[1] + (int64_t)hs[2];
+        st.chain_takeover = (int64_t)hs[2];
         int32_t *rin = readyA.as<int32_t>(), *rout = readyB.as<int32_t>();
         int64_t passes = 0;
         if (hs[0] > 0) {

@@ -301,6 +301,7 @@ struct MergeStats {
     int64_t chunks = 0, chunk_len = 0;
     int64_t chain_steps = 0;      // rank steps in the chain phase (point + interval)
     int64_t fixup_steps = 0;      // rank steps replayed by fix-up passes
+    int64_t chain_takeover = 0;   // neighbour positions completed by chain lanes after their own chunk
     int64_t fixup_passes = 0;
     int64_t key_syms = 0;         // symbols per initial sort key
     int64_t sort_bits = 0;
