@@ -207,9 +207,11 @@ int rb3_server_submit(rb3_server *s, int32_t kind, const uint8_t *q, int64_t len
  * not fit in an empty record buffer. */
 int rb3_server_poll(rb3_server *s, int32_t wait_ms, rb3_result *res, int64_t res_cap, rb3_smem_t *recs,
                     int64_t rec_cap, int64_t *n_res, int64_t *n_recs);
-/* Queue length, batches in flight, batches run, requests served, largest batch. */
+/* Queue length, batches in flight, batches run, requests served, largest
+ * batch, and the time the workers spent running batches (microseconds,
+ * summed over workers). Any pointer may be NULL. */
 int rb3_server_stats(rb3_server *s, int64_t *queued, int64_t *inflight, int64_t *batches, int64_t *served,
-                     int64_t *max_batch);
+                     int64_t *max_batch, int64_t *busy_us);
 /* Open-loop request driver for latency measurement: submits query i (kind,
  * min_len, min_occ shared) at arrival_s[i] seconds after the call starts
  * (arrival times non-decreasing), polls from a second thread, and writes

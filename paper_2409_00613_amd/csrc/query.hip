@@ -327,8 +327,9 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
     int64_t bases = 0;
     for (int64_t qq = 0; qq < nq; ++qq) bases += qlens[qq];
     const int64_t target = c.smem_segs > 0 ? c.smem_segs : SMEM_TARGET_SEGS;
+    const int64_t smin = c.smem_seg_min > 0 ? c.smem_seg_min : SMEM_SEG_MIN;
     int64_t S = bases / target;
-    S = S < SMEM_SEG_MIN ? SMEM_SEG_MIN : (S > SMEM_SEG ? SMEM_SEG : S);
+    S = S < smin ? smin : (S > SMEM_SEG ? SMEM_SEG : S);
     std::vector<Seg> segs;
     std::vector<int64_t> qseg(nq + 1);
     int64_t off = 0;

@@ -160,7 +160,8 @@ struct Ctx {
     void *alloc_ctx = nullptr;
     int64_t chunk_len = 0;
     int32_t launch_per_string = 0;
-    int64_t smem_segs = 0;  // SMEM segments to aim for per call; 0 = SMEM_TARGET_SEGS
+    int64_t smem_segs = 0;     // SMEM segments to aim for per call; 0 = SMEM_TARGET_SEGS
+    int64_t smem_seg_min = 0;  // shortest SMEM segment; 0 = SMEM_SEG_MIN
     int32_t both = 1;
     // Frees are deferred until flush(), called after the stream has drained,
     // so that a caching allocator never hands out memory a queued kernel
@@ -351,6 +352,7 @@ int count_queries(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t 
 // SMEM_TARGET_SEGS, within [SMEM_SEG_MIN, SMEM_SEG].
 constexpr int64_t SMEM_SEG = 4096;
 constexpr int64_t SMEM_SEG_MIN = 32;
+constexpr int64_t SMEM_SEG_BUSY = 128;  // shortest segment when batches share the GPU
 constexpr int64_t SMEM_TARGET_SEGS = 131072;
 // SMEMs of nq queries (codes at d_q, host lengths qlens). d_out_off
 // (device, nq + 1) receives the per-query offsets; when all *h_kept reports

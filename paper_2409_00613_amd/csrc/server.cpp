@@ -93,6 +93,7 @@ struct rb3_server {
     int64_t inflight_bytes = 0;
     int64_t inflight_batches = 0;
     int64_t batches = 0, served = 0, max_batch = 0;
+    int64_t busy_us = 0;  // summed over workers: time spent running batches
 };
 
 namespace {
@@ -229,18 +230,24 @@ void worker_main(rb3_server *s) {
             s->inflight_bytes += bytes;
             s->inflight_batches += 1;
             // batches running together share the GPU's lanes: each aims at
-            // its share of the SMEM segments that fill the chip, so segments
-            // are short (low latency) when the server is quiet and long (less
-            // repeated work per segment) when it is busy
+            // its share of the SMEM segments that fill the chip. A batch
+            // alone on the GPU may cut its queries into the shortest
+            // segments (lowest latency); when several run, segments keep at
+            // least SMEM_SEG_BUSY positions, since each repeats some work at
+            // its start and the server's throughput matters more then
             c.smem_segs = SMEM_TARGET_SEGS / s->inflight_batches;
+            c.smem_seg_min = s->inflight_batches > 1 ? SMEM_SEG_BUSY : SMEM_SEG_MIN;
             s->batches += 1;
             if ((int64_t)batch.size() > s->max_batch) s->max_batch = (int64_t)batch.size();
         }
+        const auto t0 = std::chrono::steady_clock::now();
         run_batch(s, c, batch);
+        const auto us = std::chrono::duration_cast<std::chrono::microseconds>(std::chrono::steady_clock::now() - t0);
         {
             std::lock_guard<std::mutex> lk(s->mu);
             s->inflight_bytes -= bytes;
             s->inflight_batches -= 1;
+            s->busy_us += (int64_t)us.count();
         }
         s->cv_work.notify_all();
     }
@@ -358,7 +365,7 @@ int rb3_server_poll(rb3_server *s, int32_t wait_ms, rb3_result *res, int64_t res
 }
 
 int rb3_server_stats(rb3_server *s, int64_t *queued, int64_t *inflight, int64_t *batches, int64_t *served,
-                     int64_t *max_batch) {
+                     int64_t *max_batch, int64_t *busy_us) {
     if (!s) {
         set_error(RB3_EINVAL, "server is NULL");
         return RB3_EINVAL;
@@ -369,6 +376,7 @@ int rb3_server_stats(rb3_server *s, int64_t *queued, int64_t *inflight, int64_t 
     if (batches) *batches = s->batches;
     if (served) *served = s->served;
     if (max_batch) *max_batch = s->max_batch;
+    if (busy_us) *busy_us = s->busy_us;
     return RB3_OK;
 }
 

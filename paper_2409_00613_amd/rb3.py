@@ -117,7 +117,7 @@ def lib():
     L.rb3_server_submit.argtypes = [_vp, _i32, _vp, _i64, _i32, _i64, ctypes.POINTER(ctypes.c_uint64)]
     L.rb3_server_poll.argtypes = [_vp, _i32, ctypes.POINTER(Result), _i64, ctypes.POINTER(SmemRec), _i64,
                                   _i64p, _i64p]
-    L.rb3_server_stats.argtypes = [_vp, _i64p, _i64p, _i64p, _i64p, _i64p]
+    L.rb3_server_stats.argtypes = [_vp, _i64p, _i64p, _i64p, _i64p, _i64p, _i64p]
     _dp = ctypes.POINTER(ctypes.c_double)
     L.rb3_server_replay.argtypes = [_vp, _i32, _vp, _i64p, _i64, _i32, _i64, _dp, _dp, _dp]
     L.rb3_server_free.argtypes = [_vp]
@@ -447,9 +447,9 @@ class Server:
         return lat[:la.shape[0]], wall.value
 
     def stats(self) -> dict:
-        v = [ctypes.c_int64() for _ in range(5)]
+        v = [ctypes.c_int64() for _ in range(6)]
         _check(lib().rb3_server_stats(self._h, *[ctypes.byref(x) for x in v]))
-        return dict(zip(["queued", "inflight", "batches", "served", "max_batch"], [x.value for x in v]))
+        return dict(zip(["queued", "inflight", "batches", "served", "max_batch", "busy_us"], [x.value for x in v]))
 
     def close(self):
         if self._h and self._h.value:
