@@ -353,7 +353,7 @@ int count_queries(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t 
 constexpr int64_t SMEM_SEG = 4096;
 constexpr int64_t SMEM_SEG_MIN = 32;
 constexpr int64_t SMEM_SEG_BUSY = 128;  // shortest segment when batches share the GPU
-constexpr int64_t SMEM_TARGET_SEGS = 131072;
+constexpr int64_t SMEM_TARGET_SEGS = 262144;
 // SMEMs of nq queries (codes at d_q, host lengths qlens). d_out_off
 // (device, nq + 1) receives the per-query offsets; when all *h_kept reports
 // fit in out_cap they are written in order to d_out. *h_exts: bi-interval
