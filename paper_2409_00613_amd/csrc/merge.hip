@@ -11,14 +11,18 @@
 //      sentinel starts from the closed range [m1, n1] of possible l values
 //      and maps both ends through the monotone l -> pi(a, l); once they meet,
 //      the value is exact whatever the true start was. The positions walked
-//      before that are replayed by a fix-up pass from the right neighbour's
-//      exact value.
+//      before that are completed from the right neighbour's exact value, by
+//      the neighbour's lane itself or by a fix-up pass.
 //   2. Order among the new suffixes without building B2. For new suffixes x,
 //      y: l(x) < l(y) implies x < y, and when l(x) = l(y) the order is the
 //      plain string order. So the new suffixes are radix-sorted by the key
-//      (l, first w symbols) and the remaining ties are broken by prefix
-//      doubling on the sequence of those keys (k_gather / k_rerank).
-//      Sentinel suffixes are unique and sort by strand index.
+//      (l, first w symbols). Inside a group of equal keys only members with
+//      different BWT symbols need an order (the group's rows record only the
+//      symbols): those groups are ordered by comparing the following
+//      symbols, by kernels chosen by group size (k_tie_*), and only groups
+//      of more than 8192 members fall back to prefix doubling on the key
+//      sequence (k_gather / k_rerank). Sentinel suffixes are unique and sort
+//      by strand index.
 //   3. Interleave (k_interleave): the s-th new suffix in sorted order lands
 //      on merged row l_s + s, its BWT symbol being the symbol before it; the
 //      B1 rows fill the remaining rows in order. Checkpoints are rebuilt.
@@ -397,10 +401,10 @@ __global__ void k_place(const uint32_t *__restrict__ SV, const uint32_t *__restr
 // The suffixes of one tied group occupy consecutive rows of the merged BWT,
 // and the rows only record each suffix's BWT symbol (bits 0..2 of its key).
 // So the order inside a group matters only between members whose symbols
-// differ. k_tie_groups lists the groups whose symbols are not all equal;
-// k_tie_walk sorts each of them by comparing the keys of the following
-// positions, depth by depth (the definition of suffix order on the key
-// sequence), and stops refining a subgroup as soon as its symbols agree.
+// differ. k_tie_groups lists the groups whose symbols are not all equal, by
+// size; the k_tie_* kernels order each of them by comparing the symbols
+// that follow the members, depth by depth (plain string order), and stop
+// refining a subgroup as soon as its symbols agree.
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
