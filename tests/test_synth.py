@@ -38,3 +38,27 @@ def test_mutate_and_segdups():
     assert m.shape == s.shape and 40 < int((m != s).sum()) < 200
     d = synth.segmental_duplications(s, 0.05, 100, 300, synth.rng(2, 2))
     assert d.shape == s.shape and (d != s).any()
+
+
+def test_uneven_lengths_follow_the_log_normal_reading():
+    """Contig lengths: log-normal around a 10 kb median with sigma = ln(100)/3
+    (so +-3 sigma spans 100 bp..1 Mb), redrawn outside [100, 10^6]; the
+    mean of that distribution is about 30 kb."""
+    u = synth.config_uneven(genome_len=200_000, n_b1=2, n_src=4, n_contigs=3000, chrom_len=1000,
+                            n_chrom=0, len_hi=1_000_000)
+    L = u.new.lens.astype(np.float64)
+    # contigs are cut to their 200 kb source haplotype here, so compare the
+    # median and the spread of the log-lengths, which the cut barely moves
+    assert 8_000 < np.median(L) < 12_500
+    assert 1.35 < np.std(np.log(L[L < 150_000])) < 1.6
+    assert L.min() >= 100
+
+
+def test_incremental_duplications_shared_by_haplotypes():
+    inc = synth.config_incremental(genome_len=300_000, n_hap=3, dup_frac=0.01, dup_lo=1000, dup_hi=5000)
+    base = synth.random_genome(300_000, synth.rng(inc.seed, synth.STREAM_BASE))
+    changed = int((inc.base != base).sum())
+    # about 1% of the genome overwritten (copies may overlap or copy equal bases)
+    assert 1_000 < changed < 9_000
+    h0, h0b = inc.haplotype(0), inc.haplotype(0)
+    assert np.array_equal(h0, h0b) and abs(h0.shape[0] - 300_000) < 300
