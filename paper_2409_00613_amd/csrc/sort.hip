@@ -49,23 +49,33 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 // tile and staged in LDS in digit order; then the workgroup writes them out
 // with consecutive threads on consecutive output positions, so each digit's
 // run leaves as whole lines instead of scattered 8- and 4-byte stores.
+//
+// Records travel in one of two forms: a key with a separate 32-bit value
+// (KV), or, when the key's bits and the value fit together, one packed word
+// key << pbits | value (PK), which moves 8 bytes instead of 12 per pass.
+// IN: 0 = KV, 1 = key with its index as the implicit value, 2 = PK.
+// OUT: 0 = KV, 1 = PK. shift selects the digit from the input word.
 constexpr int SC_THREADS = 1024;
 constexpr int SC_WAVES = SC_THREADS / 64;
 constexpr int SC_STEPS = RS_TILE / SC_THREADS;  // 64-key steps per wave
 
+template <int IN, int OUT>
 __global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__restrict__ kin,
-                                                           const uint32_t *__restrict__ vin, int iota,
+                                                           const uint32_t *__restrict__ vin, int pbits,
                                                            int64_t n, int shift, uint32_t dmask, int dbits,
                                                            const uint32_t *__restrict__ O, int64_t ntiles,
                                                            uint64_t *__restrict__ kout,
                                                            uint32_t *__restrict__ vout,
                                                            int32_t *__restrict__ guard) {
+    // staged words: packed records whenever either side is packed
+    constexpr bool STAGE_PK = IN == 2 || OUT == 1;
     __shared__ uint64_t sk[RS_TILE];
-    __shared__ uint32_t sv[RS_TILE];
+    __shared__ uint32_t sv[STAGE_PK ? 1 : RS_TILE];
     __shared__ uint32_t wbase[SC_WAVES][256];
     __shared__ uint32_t gbase[256];
     __shared__ uint32_t wsum[SC_WAVES];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const uint64_t vmask = (1ull << pbits) - 1ull;
     for (int i = tid; i < SC_WAVES * 256; i += SC_THREADS) (&wbase[0][0])[i] = 0;
     __syncthreads();
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -78,7 +88,7 @@ __global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__res
         int64_t idx = base + j * 64 + lane;
         if (idx < n) {
             k[j] = kin[idx];
-            v[j] = iota ? (uint32_t)idx : vin[idx];
+            v[j] = IN == 0 ? vin[idx] : (IN == 1 ? (uint32_t)idx : 0u);
             atomicAdd(&wbase[wave][(uint32_t)(k[j] >> shift) & dmask], 1u);
         } else {
             k[j] = 0;
@@ -131,8 +141,12 @@ __global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__res
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (valid) {
-            sk[pos] = k[j];
-            sv[pos] = v[j];
+            if (STAGE_PK) {
+                sk[pos] = IN == 2 ? k[j] : ((k[j] << pbits) | (uint64_t)v[j]);
+            } else {
+                sk[pos] = k[j];
+                sv[pos] = v[j];
+            }
             if (r == 0) wbase[wave][d] = pos + (uint32_t)__popcll(peers);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -140,13 +154,22 @@ __global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__res
     }
     __syncthreads();
     const int64_t tn = n - tile0 < RS_TILE ? n - tile0 : RS_TILE;
+    // the digit of a staged word: packed words carry the key pbits higher
+    const int sshift = (STAGE_PK && IN != 2) ? shift + pbits : shift;
     for (int i = tid; i < tn; i += SC_THREADS) {
-        uint64_t key = sk[i];
-        uint32_t d = (uint32_t)(key >> shift) & dmask;
+        uint64_t w = sk[i];
+        uint32_t d = (uint32_t)(w >> sshift) & dmask;
         uint32_t gpos = gbase[d] + (uint32_t)i;
         if ((int64_t)gpos < n) {
-            kout[gpos] = key;
-            vout[gpos] = sv[i];
+            if (OUT == 1) {
+                kout[gpos] = w;
+            } else if (STAGE_PK) {
+                kout[gpos] = w >> pbits;
+                vout[gpos] = (uint32_t)(w & vmask);
+            } else {
+                kout[gpos] = w;
+                vout[gpos] = sv[i];
+            }
         } else {
             atomicOr(guard, 1);
         }
@@ -163,15 +186,10 @@ int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *
     int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
     DBuf H;
     RB3_ALLOC(H, &c, 256 * (ntiles > 0 ? ntiles : 1) * sizeof(uint32_t));
-    const uint64_t *src_k = k_in;
-    const uint32_t *src_v = v_in;
-    bool iota = iota_vals;
-    uint64_t *dk = k_a;
-    uint32_t *dv = v_a;
     if (hi_bit <= lo_bit || n == 0) {
         // nothing to sort: copy through
         RB3_HIP(hipMemcpyAsync(k_a, k_in, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, c.stream));
-        if (iota) {
+        if (iota_vals) {
             set_error(RB3_EINVAL, "radix sort: empty key range with implicit values");
             return RB3_EINVAL;
         }
@@ -180,17 +198,47 @@ int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *
         *v_res = v_a;
         return RB3_OK;
     }
-    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
-        int dbits = hi_bit - shift < 8 ? hi_bit - shift : 8;
-        uint32_t dmask = (1u << dbits) - 1u;
+    const int npass = (hi_bit - lo_bit + 7) / 8;
+    // packed records when the key and the record index fit one word (the
+    // values are the indices, so they need bits_for(n - 1) bits)
+    int pbits = 1;
+    while (pbits < 32 && ((int64_t)1 << pbits) < n) ++pbits;
+    const bool packed = iota_vals && npass >= 2 && hi_bit + pbits <= 64;
+    const uint64_t *src_k = k_in;
+    const uint32_t *src_v = v_in;
+    int in_mode = iota_vals ? 1 : 0;
+    uint64_t *dk = k_a;
+    uint32_t *dv = v_a;
+    int pass = 0;
+    for (int shift = lo_bit; shift < hi_bit; shift += 8, ++pass) {
+        const int dbits = hi_bit - shift < 8 ? hi_bit - shift : 8;
+        const uint32_t dmask = (1u << dbits) - 1u;
+        const bool last = pass == npass - 1;
+        const int out_mode = packed && !last ? 1 : 0;
+        const int in_shift = in_mode == 2 ? shift + pbits : shift;
         RB3_LAUNCH("sort_hist", k_rs_hist, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, c.stream, src_k, n,
-                   shift, dmask, H.as<uint32_t>(), ntiles);
+                   in_shift, dmask, H.as<uint32_t>(), ntiles);
         RB3_TRY(scan_u32(c, H.as<uint32_t>(), H.as<uint32_t>(), 256 * ntiles, false, false, nullptr));
-        RB3_LAUNCH("sort_scatter", k_rs_scatter, dim3((unsigned)ntiles), dim3(SC_THREADS), 0, c.stream,
-                   src_k, src_v, (int)iota, n, shift, dmask, dbits, H.as<uint32_t>(), ntiles, dk, dv, d_guard);
+        const dim3 g((unsigned)ntiles), blk(SC_THREADS);
+        uint32_t *H_ = H.as<uint32_t>();
+        if (in_mode == 0 && out_mode == 0)
+            RB3_LAUNCH("sort_scatter", (k_rs_scatter<0, 0>), g, blk, 0, c.stream, src_k, src_v, pbits, n, in_shift,
+                       dmask, dbits, H_, ntiles, dk, dv, d_guard);
+        else if (in_mode == 1 && out_mode == 0)
+            RB3_LAUNCH("sort_scatter", (k_rs_scatter<1, 0>), g, blk, 0, c.stream, src_k, src_v, pbits, n, in_shift,
+                       dmask, dbits, H_, ntiles, dk, dv, d_guard);
+        else if (in_mode == 1 && out_mode == 1)
+            RB3_LAUNCH("sort_scatter", (k_rs_scatter<1, 1>), g, blk, 0, c.stream, src_k, src_v, pbits, n, in_shift,
+                       dmask, dbits, H_, ntiles, dk, dv, d_guard);
+        else if (in_mode == 2 && out_mode == 1)
+            RB3_LAUNCH("sort_scatter", (k_rs_scatter<2, 1>), g, blk, 0, c.stream, src_k, src_v, pbits, n, in_shift,
+                       dmask, dbits, H_, ntiles, dk, dv, d_guard);
+        else
+            RB3_LAUNCH("sort_scatter", (k_rs_scatter<2, 0>), g, blk, 0, c.stream, src_k, src_v, pbits, n, in_shift,
+                       dmask, dbits, H_, ntiles, dk, dv, d_guard);
         src_k = dk;
         src_v = dv;
-        iota = false;
+        in_mode = out_mode == 1 ? 2 : 0;
         if (dk == k_a) {
             dk = k_b;
             dv = v_b;
