@@ -52,8 +52,10 @@ def algorithmic_bytes(kernel: str, st: dict, steps: int) -> float | None:
         "chain_fixup": st["fixup_steps"] * (BLOCK_BYTES + 1 + 8),
         # per pass: key 8 B read for the histogram
         "sort_hist": n2 * 8 * max(1, -(-st["sort_bits"] // 8)),
-        # per pass: key + value read and written (the first pass has no value to read)
-        "sort_scatter": n2 * 24 * max(1, -(-st["sort_bits"] // 8)) - n2 * 4,
+        # per pass: key + value read and written (the first pass has no value
+        # to read); packed 8-byte records between the first and last passes
+        "sort_scatter": (n2 * (16 * (max(1, -(-st["sort_bits"] // 8)) - 1) + 20) if st.get("sort_packed")
+                         else n2 * 24 * max(1, -(-st["sort_bits"] // 8)) - n2 * 4),
         # per active record per round: position, rank h further on, key written
         "tie_gather": st["tie_work"] * 12 if st.get("tie_doubling") else None,
         # per active record per round: its record and group (16 B), key (4 B),
