@@ -22,10 +22,18 @@ __global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shif
     for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int i = 0; i < RS_TILE / RS_THREADS; ++i) {
-        int64_t idx = base + (int64_t)i * RS_THREADS + tid;
-        if (idx < n) atomicAdd(&h[wave][(uint32_t)(keys[idx] >> shift) & dmask], 1u);
+    // all loads first, then the counts, so the loads' latencies overlap
+    constexpr int PER = RS_TILE / RS_THREADS;
+    // (indices past the end read the last key, which is then not counted)
+    uint64_t kk[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int64_t idx = base + (int64_t)i * RS_THREADS + tid;
+        kk[i] = keys[idx < n ? idx : n - 1];
     }
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        if (base + (int64_t)i * RS_THREADS + tid < n) atomicAdd(&h[wave][(uint32_t)(kk[i] >> shift) & dmask], 1u);
     __syncthreads();
     for (int d = tid; d < 256; d += RS_THREADS)
         H[(int64_t)d * ntiles + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
@@ -83,18 +91,20 @@ __global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__res
     const int64_t base = tile0 + (int64_t)wave * (64 * SC_STEPS);
     uint64_t k[SC_STEPS];
     uint32_t v[SC_STEPS];
+    // the tile's digit offsets are read together with its keys, so the two
+    // memory latencies overlap
+    const uint32_t o = tid < 256 ? O[(int64_t)tid * ntiles + tile] : 0u;
+    // all loads are issued before the first count, so their latencies overlap
 #pragma unroll
     for (int j = 0; j < SC_STEPS; ++j) {
-        int64_t idx = base + j * 64 + lane;
-        if (idx < n) {
-            k[j] = kin[idx];
-            v[j] = IN == 0 ? vin[idx] : (IN == 1 ? (uint32_t)idx : 0u);
-            atomicAdd(&wbase[wave][(uint32_t)(k[j] >> shift) & dmask], 1u);
-        } else {
-            k[j] = 0;
-            v[j] = 0;
-        }
+        const int64_t idx = base + j * 64 + lane;
+        const bool ok = idx < n;
+        k[j] = ok ? kin[idx] : 0ull;
+        v[j] = IN == 0 ? (ok ? vin[idx] : 0u) : (IN == 1 ? (uint32_t)idx : 0u);
     }
+#pragma unroll
+    for (int j = 0; j < SC_STEPS; ++j)
+        if (base + j * 64 + lane < n) atomicAdd(&wbase[wave][(uint32_t)(k[j] >> shift) & dmask], 1u);
     __syncthreads();
     // digit totals of the tile, their exclusive prefix (tile-local digit
     // starts), and per (wave, digit) local bases
@@ -116,7 +126,7 @@ __global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__res
     if (tid < 256) {
         uint32_t pre = inc - tot;
         for (int w = 0; w < wave; ++w) pre += wsum[w];
-        gbase[tid] = O[(int64_t)tid * ntiles + tile] - pre;
+        gbase[tid] = o - pre;
         uint32_t run = pre;
 #pragma unroll
         for (int w = 0; w < SC_WAVES; ++w) {
