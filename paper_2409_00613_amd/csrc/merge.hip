@@ -426,11 +426,12 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // is extended by the whole wave. Groups whose members carry different
 // symbols are collected per workgroup in LDS, by size class, and flushed to
 // one global list of (first sorted index, member count) per class with one
-// atomic per class per flush.
+// atomic per class per flush; an entry that finds its LDS list full goes to
+// the global list directly.
 constexpr int TG_THREADS = 256;
 constexpr int TG_CLASSES = 6;
-constexpr int TG_WIN = 4;      // 64-key windows per wave per iteration, loaded together
-constexpr int TG_LCAP = 1024;  // LDS list capacity per class
+constexpr int TG_WIN = 8;     // 64-key windows per wave per iteration, loaded together
+constexpr int TG_LCAP = 256;  // LDS list capacity per class
 // class upper bounds: 2 | 3..8 | 9..64 | 65..128 | 129..256 | 257..8192
 constexpr uint32_t TG_BOUND[TG_CLASSES] = {2, 8, 64, 128, 256, 8192};
 
@@ -463,9 +464,10 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         // this wave's TG_WIN consecutive windows, all loads in flight at once
         const int64_t wbase = tile * TILE + (int64_t)wv * 64 * TG_WIN;
-        uint64_t vw[TG_WIN];
+        // (vw[TG_WIN] is the window after the last one, for the extension test)
+        uint64_t vw[TG_WIN + 1];
 #pragma unroll
-        for (int j = 0; j < TG_WIN; ++j) {
+        for (int j = 0; j <= TG_WIN; ++j) {
             const int64_t sj = wbase + (int64_t)j * 64 + lane;
             vw[j] = sj < n ? SK[sj] : ~0ull;
         }
@@ -501,14 +503,16 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
             int64_t ext = 0;
             bool xuni = true;
             if (ls >= 0 && last_in == 63 && (xkey & 7) != 0) {
-                for (int64_t t = w0 + 64; t < n; t += 64) {
-                    const int64_t u = t + lane;
-                    const uint64_t uv = u < n ? SK[u] : ~0ull;
+                // the first following window is already in registers
+                uint64_t uv = vw[j + 1];
+                for (int64_t t = w0 + 64; t < n;) {
                     const uint64_t mm = __ballot((uv >> 3) == xkey);
                     const int run = ~mm ? __ffsll((unsigned long long)~mm) - 1 : 64;
                     if (__ballot(lane < run && (uint32_t)(uv & 7) != xe)) xuni = false;
                     ext += run;
                     if (run < 64) break;
+                    t += 64;
+                    uv = t + lane < n ? SK[t + lane] : ~0ull;
                 }
             }
             if (start && !sent) {
@@ -521,9 +525,15 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
                     if (!uni) {
                         uint32_t kk = (uint32_t)(k > 0xFFFFFFFFll ? 0xFFFFFFFFll : k);
                         int c = group_class(kk);
-                        uint32_t slot = atomicAdd(&lcnt[c], 1u);
-                        lst[c][slot][0] = (uint32_t)s;
-                        lst[c][slot][1] = kk;
+                        const uint32_t slot = atomicAdd(&lcnt[c], 1u);
+                        if (slot < (uint32_t)TG_LCAP) {
+                            lst[c][slot][0] = (uint32_t)s;
+                            lst[c][slot][1] = kk;
+                        } else {
+                            const uint32_t g = atomicAdd(&gstat[c], 1u);
+                            lists.l[c][2 * (int64_t)g] = (uint32_t)s;
+                            lists.l[c][2 * (int64_t)g + 1] = kk;
+                        }
                         atomicAdd(&hist[31 - __clz(kk)], 1u);
                         kmax = kk > kmax ? kk : kmax;
                     }
@@ -531,11 +541,12 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
             }
         }
         __syncthreads();
-        // flush a class list when the next tile could overflow it (a tile adds at most TILE / 2)
+        // flush a class list once it is half full, and every list after the last tile
         const bool last_tile = tile + gridDim.x >= ntiles;
         for (int c = 0; c < TG_CLASSES; ++c) {
             uint32_t cnt = lcnt[c];
-            if (cnt == 0 || (!last_tile && cnt + TILE / 2 <= TG_LCAP)) continue;
+            if (cnt > (uint32_t)TG_LCAP) cnt = TG_LCAP;  // the rest went to the global list
+            if (cnt == 0 || (!last_tile && cnt < (uint32_t)TG_LCAP / 2)) continue;
             if (threadIdx.x == 0) lbase[c] = atomicAdd(&gstat[c], cnt);
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < cnt; i += TG_THREADS) {
@@ -596,7 +607,6 @@ __device__ __forceinline__ bool chunk_has_sentinel(uint64_t v) {
 // (one chunk). Two chunks that are equal and hold a sentinel belong to
 // suffixes reaching their strands' ends together: strand order, which is
 // position order in Q, decides.
-constexpr int WALK_MAXK = 64;
 constexpr int WALK_DEPTHS = 4;  // chunks per member per load round
 
 
@@ -1326,83 +1336,127 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, 
 
 // Number of new suffixes landing in each 128-row output block. Consecutive
 // sorted entries land in non-decreasing blocks, so each wave adds one count
-// per run of equal blocks instead of one per entry.
+// per run of equal blocks in a 64-entry window instead of one per entry.
+// Each wave loads its BC_WIN windows at once.
+constexpr int BC_WIN = 8;
+
 __global__ void k_block_count(const uint64_t *__restrict__ SK, int64_t n2, int64_t m1, int lshift,
                               int64_t nblk_out, uint32_t *__restrict__ cnt, int32_t *__restrict__ guard) {
-    int lane = threadIdx.x & 63;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t base0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63);
-    for (int64_t base = base0; base < n2; base += stride) {
-        int64_t s = base + lane;
-        bool valid = s < n2;
-        int64_t b = valid ? (((int64_t)(SK[s] >> lshift) + m1 + s) >> BLK_SHIFT) : -1;
-        int64_t bprev = __shfl_up(b, 1);
-        bool head = valid && (lane == 0 || b != bprev);
-        uint64_t heads = __ballot(head);
-        uint64_t vmask = __ballot(valid);
-        if (head) {
-            uint64_t above = heads & ~low_mask(lane + 1);
-            int next = above ? __ffsll((unsigned long long)above) - 1 : 64 - __clzll((long long)vmask);
-            if (b >= 0 && b < nblk_out) atomicAdd(&cnt[b], (uint32_t)(next - lane));
-            else atomicOr(guard, GUARD_INTERLEAVE);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w0 = wave * (64 * BC_WIN); w0 < n2; w0 += nwaves * (64 * BC_WIN)) {
+        uint64_t kk[BC_WIN];
+#pragma unroll
+        for (int j = 0; j < BC_WIN; ++j) {
+            const int64_t s = w0 + j * 64 + lane;
+            kk[j] = s < n2 ? SK[s] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < BC_WIN; ++j) {
+            const int64_t s = w0 + j * 64 + lane;
+            const bool valid = s < n2;
+            const int64_t b = valid ? (((int64_t)(kk[j] >> lshift) + m1 + s) >> BLK_SHIFT) : -1;
+            const int64_t bprev = __shfl_up(b, 1);
+            const bool head = valid && (lane == 0 || b != bprev);
+            const uint64_t heads = __ballot(head);
+            const uint64_t vmask = __ballot(valid);
+            if (head) {
+                const uint64_t above = heads & ~low_mask(lane + 1);
+                const int next = above ? __ffsll((unsigned long long)above) - 1 : 64 - __clzll((long long)vmask);
+                if (b >= 0 && b < nblk_out) atomicAdd(&cnt[b], (uint32_t)(next - lane));
+                else atomicOr(guard, GUARD_INTERLEAVE);
+            }
         }
     }
 }
 
-__device__ __forceinline__ uint32_t b1_symbol(const uint64_t *__restrict__ words, int64_t i) {
-    int64_t b = i >> BLK_SHIFT;
-    int r = (int)(i & 127);
-    int w = r >> 6, bit = r & 63;
-    const uint64_t *q = words + b * 8;
-    return (uint32_t)((q[w] >> bit) & 1u) | (uint32_t)(((q[2 + w] >> bit) & 1u) << 1) |
-           (uint32_t)(((q[4 + w] >> bit) & 1u) << 2);
-}
-
-__global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__ b1words,
+// One wave per 128-row output block. The old rows of a block are a run of
+// consecutive B1 rows, held by at most two B1 blocks: their plane words are
+// loaded together with the block's sorted entries (and the next block's
+// offsets are loaded a block ahead), so one memory latency is paid per block
+// instead of three dependent ones; lanes then take their old symbols from
+// the loaded words by lane shuffles.
+__global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__ b1words, int64_t nblk1,
                                                     const uint64_t *__restrict__ SK,
                                                     const uint32_t *__restrict__ bs, int64_t nout,
                                                     int64_t nblk_out, int64_t n1, int64_t m1, int lshift,
                                                     uint4 *__restrict__ out, int32_t *__restrict__ guard) {
     __shared__ uint8_t slot[4][128];
-    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    uint32_t s0n = 0, s1n = 0;
+    if (wave < nblk_out) {
+        s0n = bs[wave];
+        s1n = bs[wave + 1];
+    }
     for (int64_t b = wave; b < nblk_out; b += nwaves) {
-        int64_t P0 = b << BLK_SHIFT;
-        uint32_t s0 = bs[b], s1 = bs[b + 1];
-        int64_t i0 = P0 - (int64_t)s0;
+        const uint32_t s0 = s0n, s1 = s1n;
+        if (b + nwaves < nblk_out) {
+            s0n = bs[b + nwaves];
+            s1n = bs[b + nwaves + 1];
+        }
+        const int64_t P0 = b << BLK_SHIFT;
+        const int64_t i0 = P0 - (int64_t)s0;  // first old row of the block
+        const int64_t rows = nout - P0 < 128 ? nout - P0 : 128;
+        const int64_t nnew = (int64_t)s1 - (int64_t)s0;
+        const int64_t nold = rows - nnew;
+        const int64_t ib0 = i0 >> BLK_SHIFT;
+        // lane j < 12 holds plane word j % 6 of old block ib0 + j / 6
+        uint64_t wd = 0;
+        if (nold > 0 && lane < 12 && i0 >= 0 && i0 < n1) {
+            const int64_t ib = ib0 + lane / 6;
+            if (ib <= ((i0 + nold - 1) >> BLK_SHIFT) && ib < nblk1) wd = b1words[ib * 8 + lane % 6];
+        }
+        const uint32_t ka = s0 + (uint32_t)lane, kb = ka + 64u;
+        const uint64_t keya = ka < s1 ? SK[ka] : 0ull;
+        const uint64_t keyb = kb < s1 ? SK[kb] : 0ull;
         slot[wv][lane] = 0;
         slot[wv][lane + 64] = 0;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        for (uint32_t k = s0 + lane; k < s1; k += 64) {
-            uint64_t key = SK[k];
-            int64_t M = (int64_t)(key >> lshift) + m1 + k;
-            if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | (uint32_t)(key & 7));
+        if (ka < s1) {
+            const int64_t M = (int64_t)(keya >> lshift) + m1 + ka;
+            if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | (uint32_t)(keya & 7));
             else atomicOr(guard, GUARD_INTERLEAVE);
         }
+        if (kb < s1) {
+            const int64_t M = (int64_t)(keyb >> lshift) + m1 + kb;
+            if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | (uint32_t)(keyb & 7));
+            else atomicOr(guard, GUARD_INTERLEAVE);
+        }
+        if (nnew > 128 && lane == 0) atomicOr(guard, GUARD_INTERLEAVE);  // more entries than rows
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        uint32_t e0 = slot[wv][lane], e1 = slot[wv][lane + 64];
-        uint64_t nm0 = __ballot(e0 & 0x80u), nm1 = __ballot(e1 & 0x80u);
+        const uint32_t e0 = slot[wv][lane], e1 = slot[wv][lane + 64];
+        const uint64_t nm0 = __ballot(e0 & 0x80u), nm1 = __ballot(e1 & 0x80u);
+        // old row of each of my two output rows, and where its bits are
+        const int64_t ia = i0 + lane - __popcll(nm0 & low_mask(lane));
+        const int64_t ib = i0 + 64 + lane - __popcll(nm0) - __popcll(nm1 & low_mask(lane));
+        const bool olda = P0 + lane < nout && !(e0 & 0x80u);
+        const bool oldb = P0 + 64 + lane < nout && !(e1 & 0x80u);
+        const int sela = (int)((ia >> BLK_SHIFT) - ib0), selb = (int)((ib >> BLK_SHIFT) - ib0);
+        const bool oka = olda && ia >= 0 && ia < n1 && (sela == 0 || sela == 1);
+        const bool okb = oldb && ib >= 0 && ib < n1 && (selb == 0 || selb == 1);
+        if ((olda && !oka) || (oldb && !okb)) atomicOr(guard, GUARD_INTERLEAVE);
+        const int la = (oka ? sela : 0) * 6 + (int)((ia >> 6) & 1), lb = (okb ? selb : 0) * 6 + (int)((ib >> 6) & 1);
+        // shuffles run with every lane active
+        const uint64_t a0w = __shfl(wd, la), a1w = __shfl(wd, la + 2), a2w = __shfl(wd, la + 4);
+        const uint64_t b0w = __shfl(wd, lb), b1w = __shfl(wd, lb + 2), b2w = __shfl(wd, lb + 4);
+        const int ba = (int)(ia & 63), bb = (int)(ib & 63);
         uint32_t c0 = 7, c1 = 7;
         if (P0 + lane < nout) {
-            if (e0 & 0x80u) {
-                c0 = e0 & 7u;
-            } else {
-                int64_t i = i0 + lane - __popcll(nm0 & low_mask(lane));
-                if (i >= 0 && i < n1) c0 = b1_symbol(b1words, i);
-                else atomicOr(guard, GUARD_INTERLEAVE);
-            }
+            if (e0 & 0x80u) c0 = e0 & 7u;
+            else if (oka)
+                c0 = (uint32_t)((a0w >> ba) & 1u) | (uint32_t)(((a1w >> ba) & 1u) << 1) |
+                     (uint32_t)(((a2w >> ba) & 1u) << 2);
         }
         if (P0 + 64 + lane < nout) {
-            if (e1 & 0x80u) {
-                c1 = e1 & 7u;
-            } else {
-                int64_t i = i0 + 64 + lane - __popcll(nm0) - __popcll(nm1 & low_mask(lane));
-                if (i >= 0 && i < n1) c1 = b1_symbol(b1words, i);
-                else atomicOr(guard, GUARD_INTERLEAVE);
-            }
+            if (e1 & 0x80u) c1 = e1 & 7u;
+            else if (okb)
+                c1 = (uint32_t)((b0w >> bb) & 1u) | (uint32_t)(((b1w >> bb) & 1u) << 1) |
+                     (uint32_t)(((b2w >> bb) & 1u) << 2);
         }
         uint64_t a0 = __ballot(c0 & 1), a1 = __ballot(c0 & 2), a2 = __ballot(c0 & 4);
         uint64_t d0 = __ballot(c1 & 1), d1 = __ballot(c1 & 2), d2 = __ballot(c1 & 4);
@@ -1571,8 +1625,8 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     }
 
     // Groups whose members carry different BWT symbols need an order; the
-    // symbol walk handles groups of up to WALK_MAXK members, prefix doubling
-    // (which orders every tie) handles the rest.
+    // tie kernels handle groups of up to 8192 members by size class, prefix
+    // doubling (which orders every tie) handles larger ones.
     bool need_doubling = false;
     {
         DBuf lists[TG_CLASSES], gstat, gtied, ghist, gdeep, gblk;
@@ -1747,13 +1801,13 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     DBuf bcnt, out_blk, out_sb;
     RB3_ALLOC(bcnt, &c, (nblk_out + 1) * sizeof(uint32_t));
     RB3_HIP(hipMemsetAsync(bcnt.p, 0, (nblk_out + 1) * sizeof(uint32_t), c.stream));
-    RB3_LAUNCH("merge_block_count", k_block_count, grid_for(n2, 256 * 8), dim3(256), 0, c.stream, SK, n2, m1,
+    RB3_LAUNCH("merge_block_count", k_block_count, grid_for(n2, 256 * BC_WIN, 1 << 16), dim3(256), 0, c.stream, SK, n2, m1,
                lshift, nblk_out, bcnt.as<uint32_t>(), guard);
     RB3_TRY(scan_u32(c, bcnt.as<uint32_t>(), bcnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
     RB3_ALLOC(out_blk, &c, nblk_out * 64);
     RB3_ALLOC(out_sb, &c, num_superblocks(nout) * SB_STRIDE * sizeof(int64_t));
     RB3_LAUNCH("interleave", k_interleave, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream,
-               (const uint64_t *)b1.blk, SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
+               (const uint64_t *)b1.blk, num_blocks(n1), SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
                out_blk.as<uint4>(), guard);
     int64_t counts[6];
     RB3_TRY(build_checkpoints(c, out_blk.as<uint4>(), nout, out_sb.as<int64_t>(), new_C, counts));
