@@ -59,7 +59,10 @@ enum { RB3_MEM_HOST = 0, RB3_MEM_DEVICE = 1 };
  * symbols with occurrence checkpoints, superblock counts and C[]. */
 typedef struct rb3_index rb3_index;
 
-/* Device allocator hooks. dev_alloc returns NULL on failure. */
+/* Device allocator hooks. dev_alloc returns NULL on failure, else memory
+ * aligned to at least 16 bytes (hipMalloc and PyTorch's caching allocator
+ * give 256); a misaligned pointer is handed back to dev_free and the call
+ * fails with RB3_ENOMEM. */
 typedef void *(*rb3_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*rb3_free_fn)(void *ptr, void *ctx);
 

@@ -48,7 +48,15 @@ int check_launch(const char *name) {
 // memory
 // ---------------------------------------------------------------------------
 void *Ctx::dmalloc(size_t bytes) {
-    if (alloc) return alloc(bytes, alloc_ctx);
+    if (alloc) {
+        // kernels read buffers in 16-byte vectors and 8-byte words
+        void *p = alloc(bytes, alloc_ctx);
+        if (p && ((uintptr_t)p & 15u)) {
+            if (free_fn) free_fn(p, alloc_ctx);
+            return nullptr;
+        }
+        return p;
+    }
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();

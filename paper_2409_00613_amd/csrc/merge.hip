@@ -94,6 +94,38 @@ struct KeyWindow {
     }
 };
 
+// The symbols of a right-to-left walk over Q, read one aligned 8-byte word
+// at a time: the word below the current one is requested as soon as the
+// walk enters the current one, so the walk's steps wait only on the index.
+// Q must be 8-byte aligned with readable bytes up to the end of the word
+// holding its last symbol.
+struct BackSyms {
+    const uint64_t *w;
+    int64_t wi;     // index of the word holding the current position
+    uint64_t cur;   // word wi
+    uint64_t prv;   // word wi - 1 (0 when wi == 0)
+    __device__ __forceinline__ void init(const uint8_t *Q, int64_t p) {
+        w = (const uint64_t *)Q;
+        wi = p >> 3;
+        cur = w[wi];
+        prv = wi > 0 ? w[wi - 1] : 0ull;
+    }
+    // Q[p], p in word wi
+    __device__ __forceinline__ uint32_t at(int64_t p) const { return (uint32_t)(cur >> (8 * (p & 7))) & 0xFFu; }
+    // Q[p - 1], 0 for p == 0
+    __device__ __forceinline__ uint32_t before(int64_t p) const {
+        return (p & 7) ? (uint32_t)(cur >> (8 * ((p - 1) & 7))) & 0xFFu : (uint32_t)(prv >> 56);
+    }
+    // done with p: move to p - 1
+    __device__ __forceinline__ void next(int64_t p) {
+        if ((p & 7) == 0) {
+            --wi;
+            cur = prv;
+            prv = wi > 0 ? w[wi - 1] : 0ull;
+        }
+    }
+};
+
 // Left neighbours whose unresolved ends one lane may walk after its own
 // chunk (more are left to the fix-up passes).
 constexpr int CHAIN_TAKEOVER = 2;
@@ -132,9 +164,11 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     int64_t wide = 0, taken = 0;
     KeyWindow win;
     win.init();
+    BackSyms sy;
+    sy.init(Q, p1 - 1);
     for (int64_t p = p1 - 1; p >= c.p0; --p) {
-        uint32_t a = Q[p];
-        uint32_t emit = p > 0 ? Q[p - 1] : 0u;
+        const uint32_t a = sy.at(p);
+        const uint32_t emit = sy.before(p);
         packed = ((uint64_t)a << wsh) | (packed >> 3);
         if (point) {
             l = pi_sym(ix, (int)a, l);
@@ -163,6 +197,7 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
             }
         }
         if ((p & 7) == 0 || p == c.p0) win.flush(K, p);
+        sy.next(p);
     }
     unres[i] = unresolved;
     if (point) {
@@ -174,13 +209,15 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
             const int32_t v = __hip_atomic_load(&conv[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int64_t end = cn.p0 + cn.len;
             const int64_t stop = v >= 0 ? end - v : cn.p0;
+            // the neighbour ends where this walk stopped, so sy is at end - 1
             for (int64_t p = end - 1; p >= stop; --p) {
-                uint32_t a = Q[p];
-                uint32_t emit = p > 0 ? Q[p - 1] : 0u;
+                const uint32_t a = sy.at(p);
+                const uint32_t emit = sy.before(p);
                 packed = ((uint64_t)a << wsh) | (packed >> 3);
                 l = pi_sym(ix, (int)a, l);
                 win.push(make_key(l - m1, packed, emit, lshift), true);
                 if ((p & 7) == 0 || p == stop) win.flush(K, p);
+                sy.next(p);
             }
             taken += end - stop;
             fixed[nb] = 1;
@@ -227,13 +264,16 @@ __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     uint64_t packed = pack_ahead(Q, p1, w);
     KeyWindow win;
     win.init();
+    BackSyms sy;
+    sy.init(Q, p1 - 1);
     for (int64_t p = p1 - 1; p >= p1 - u; --p) {
-        uint32_t a = Q[p];
-        uint32_t emit = p > 0 ? Q[p - 1] : 0u;
+        const uint32_t a = sy.at(p);
+        const uint32_t emit = sy.before(p);
         packed = ((uint64_t)a << wsh) | (packed >> 3);
         l = pi_sym(ix, (int)a, l);
         win.push(make_key(l - m1, packed, emit, lshift), true);
         if ((p & 7) == 0 || p == p1 - u) win.flush(K, p);
+        sy.next(p);
     }
     unres[i] = 0;
     if (u == c.len) ready_out[i] = 1;
