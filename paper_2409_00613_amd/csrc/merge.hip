@@ -174,16 +174,14 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
             l = pi_sym(ix, (int)a, l);
             win.push(make_key(l - m1, packed, emit, lshift), true);
         } else {
-            int64_t bl = lo >> BLK_SHIFT, bh = hi >> BLK_SHIFT;
-            Block B = load_block(ix.blk, bl);
-            int64_t nlo = pi_from_block(ix, B, (int)a, lo);
-            int64_t nhi;
-            if (bh == bl) {
-                nhi = pi_from_block(ix, B, (int)a, hi);
-            } else {
-                nhi = pi_sym(ix, (int)a, hi);
-                ++wide;
-            }
+            // both ends' blocks are requested together (the same block
+            // twice when they share it)
+            const int64_t bl = lo >> BLK_SHIFT, bh = hi >> BLK_SHIFT;
+            const Block BL = load_block(ix.blk, bl);
+            const Block BH = load_block(ix.blk, bh);
+            const int64_t nlo = pi_from_block(ix, BL, (int)a, lo);
+            const int64_t nhi = pi_from_block(ix, BH, (int)a, hi);
+            if (bh != bl) ++wide;
             lo = nlo;
             hi = nhi;
             if (lo == hi) {

@@ -16,18 +16,13 @@ __global__ void k_count(DevIndex ix, const uint8_t *__restrict__ q, const int64_
     int64_t a0 = qoff[i], a1 = qoff[i + 1];
     int64_t lo = 0, hi = ix.n;
     for (int64_t t = a1 - 1; t >= a0; --t) {
-        int a = q[t];
-        if (lo == hi) {
-            lo = pi_sym(ix, a, lo);
-            hi = lo;
-        } else if ((lo >> BLK_SHIFT) == (hi >> BLK_SHIFT)) {
-            Block B = load_block(ix.blk, lo >> BLK_SHIFT);
-            lo = pi_from_block(ix, B, a, lo);
-            hi = pi_from_block(ix, B, a, hi);
-        } else {
-            lo = pi_sym(ix, a, lo);
-            hi = pi_sym(ix, a, hi);
-        }
+        // the symbol and both ends' blocks are requested together (the
+        // second block read is the first one again when they share it)
+        const int a = q[t];
+        const Block Bl = load_block(ix.blk, lo >> BLK_SHIFT);
+        const Block Bh = load_block(ix.blk, hi >> BLK_SHIFT);
+        lo = pi_from_block(ix, Bl, a, lo);
+        hi = pi_from_block(ix, Bh, a, hi);
     }
     lo_out[i] = lo;
     hi_out[i] = hi;
@@ -54,8 +49,7 @@ __device__ __forceinline__ int comp_sym(int c) { return (c == 0 || c == 5) ? c :
 // Algorithm 3, BackwardExt: the bi-interval of aP from that of P.
 __device__ __forceinline__ BiInt backward_ext(const DevIndex &ix, const BiInt &x, int a) {
     int64_t p0[6], p1[6];
-    pi_all(ix, x.k, p0);
-    pi_all(ix, x.k + x.s, p1);
+    pi_all2(ix, x.k, x.k + x.s, p0, p1);
     BiInt r;
     int64_t kr = x.kr;
     int abar = comp_sym(a);

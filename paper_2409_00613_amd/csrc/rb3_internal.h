@@ -129,11 +129,11 @@ __device__ __forceinline__ int64_t pi_sym(const DevIndex &ix, int a, int64_t k) 
     return pi_from_block(ix, B, a, k);
 }
 
-// pi_B(c, k) for every c in 0..5. rank($, k) is k minus the other ranks.
-__device__ __forceinline__ void pi_all(const DevIndex &ix, int64_t k, int64_t out[6]) {
-    Block B = load_block(ix.blk, k >> BLK_SHIFT);
+// pi_B(c, k) for every c in 0..5, from the block holding k and the
+// superblock row s of k. rank($, k) is k minus the other ranks.
+__device__ __forceinline__ void pi_all_from(const DevIndex &ix, const Block &B, const int64_t s[6], int64_t k,
+                                            int64_t out[6]) {
     int o = (int)(k & (BLK_SYMS - 1));
-    const int64_t *s = ix.sb + (k >> SB_SHIFT) * SB_STRIDE;
     uint64_t l0 = u64_lo(B.q0), l1 = u64_lo(B.q1), l2 = u64_lo(B.q2);
     uint64_t h0 = u64_hi(B.q0), h1 = u64_hi(B.q1), h2 = u64_hi(B.q2);
     uint64_t mlo = low_mask(o < 64 ? o : 64);
@@ -145,6 +145,29 @@ __device__ __forceinline__ void pi_all(const DevIndex &ix, int64_t k, int64_t ou
         others += out[a] - ix.C[a];
     }
     out[0] = k - others;  // C[0] = 0
+}
+
+__device__ __forceinline__ void load_sb_row(const DevIndex &ix, int64_t k, int64_t s[6]) {
+    const int64_t *r = ix.sb + (k >> SB_SHIFT) * SB_STRIDE;
+    s[0] = 0;
+#pragma unroll
+    for (int a = 1; a <= 5; ++a) s[a] = r[a];
+}
+
+// pi_all at two positions; every load of both is issued before any use,
+// so the two random block reads overlap.
+__device__ __forceinline__ void pi_all2(const DevIndex &ix, int64_t k0, int64_t k1, int64_t out0[6],
+                                        int64_t out1[6]) {
+    int64_t s0[6], s1[6];
+    load_sb_row(ix, k0, s0);
+    load_sb_row(ix, k1, s1);
+    const Block B0 = load_block(ix.blk, k0 >> BLK_SHIFT);
+    const Block B1 = load_block(ix.blk, k1 >> BLK_SHIFT);
+    // keep the scheduler from moving the first block's use above the
+    // second block's loads
+    __builtin_amdgcn_sched_barrier(0);
+    pi_all_from(ix, B0, s0, k0, out0);
+    pi_all_from(ix, B1, s1, k1, out1);
 }
 
 // ---------------------------------------------------------------------------
