@@ -1,19 +1,21 @@
 // Stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit digits.
 //
 // Per pass: (1) per-tile digit histograms in LDS, (2) one exclusive scan of
-// the digit-major histogram table, (3) a stable scatter. In the scatter each
-// wave owns a contiguous run of 1024 keys of the tile and ranks keys with
-// equal digits inside a 64-key step by matching the digit with 8 ballots, so
-// no cross-wave synchronisation is needed inside the scatter loop.
+// the digit-major histogram table, (3) a stable scatter. Tiles hold 8192
+// keys, so that each digit's share of a tile (32 keys on average) leaves the
+// scatter as whole lines. In the scatter each wave owns a contiguous run of
+// 1024 keys of the tile and ranks keys with equal digits inside a 64-key
+// step by matching the digit with 8 ballots, so no cross-wave
+// synchronisation is needed inside the scatter loop.
 #include "rb3_internal.h"
 
 namespace rb3 {
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
-constexpr int RS_STEPS = 16;                       // 64-key steps per wave
+constexpr int RS_STEPS = 32;                       // 64-key steps per wave
 constexpr int RS_WAVE_KEYS = 64 * RS_STEPS;        // 1024
-constexpr int RS_TILE = RS_WAVES * RS_WAVE_KEYS;   // 4096
+constexpr int RS_TILE = RS_WAVES * RS_WAVE_KEYS;   // 8192
 
 __global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t dmask,
                           uint32_t *__restrict__ H, int64_t ntiles) {
@@ -63,7 +65,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 // key << pbits | value (PK), which moves 8 bytes instead of 12 per pass.
 // IN: 0 = KV, 1 = key with its index as the implicit value, 2 = PK.
 // OUT: 0 = KV, 1 = PK. shift selects the digit from the input word.
-constexpr int SC_THREADS = 1024;
+constexpr int SC_THREADS = 512;
 constexpr int SC_WAVES = SC_THREADS / 64;
 constexpr int SC_STEPS = RS_TILE / SC_THREADS;  // 64-key steps per wave
 
