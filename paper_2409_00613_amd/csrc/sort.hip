@@ -17,13 +17,23 @@ constexpr int RS_STEPS = 32;                       // 64-key steps per wave
 constexpr int RS_WAVE_KEYS = 64 * RS_STEPS;        // 1024
 constexpr int RS_TILE = RS_WAVES * RS_WAVE_KEYS;   // 8192
 
+// Workgroups are dealt to the 8 XCDs round robin. Giving each XCD a
+// contiguous range of tiles keeps the neighbouring pieces of each digit's
+// output run, written by neighbouring tiles, in the same L2 (and, for the
+// histograms, the neighbouring counts of each digit row).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+    const int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
 __global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t dmask,
                           uint32_t *__restrict__ H, int64_t ntiles) {
     __shared__ uint32_t h[RS_WAVES][256];
     int tid = threadIdx.x, wave = tid >> 6;
     for (int i = tid; i < RS_WAVES * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    int64_t base = tile * RS_TILE;
     // all loads first, then the counts, so the loads' latencies overlap
     constexpr int PER = RS_TILE / RS_THREADS;
     // (indices past the end read the last key, which is then not counted)
@@ -38,21 +48,13 @@ __global__ void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shif
         if (base + (int64_t)i * RS_THREADS + tid < n) atomicAdd(&h[wave][(uint32_t)(kk[i] >> shift) & dmask], 1u);
     __syncthreads();
     for (int d = tid; d < 256; d += RS_THREADS)
-        H[(int64_t)d * ntiles + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+        H[(int64_t)d * ntiles + tile] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     // number of set bits of mask below this lane
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Workgroups are dealt to the 8 XCDs round robin. Giving each XCD a
-// contiguous range of tiles keeps the neighbouring pieces of each digit's
-// output run, written by neighbouring tiles, in the same L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
-    const int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
 }
 
 // Scatter of one tile. The tile's keys are first ranked stably inside the
