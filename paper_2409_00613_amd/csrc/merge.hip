@@ -241,20 +241,26 @@ __global__ void k_chain_join(const Chunk *__restrict__ ch, int64_t nch, int32_t 
     if (u) atomicAdd(&stats[0], (unsigned long long)u);
 }
 
+// Fix-up pass: a chunk with an unresolved end whose right neighbour's first
+// position is exact walks that end. A chunk that was unresolved throughout
+// becomes exact at its first position, so the same lane goes on into its
+// left neighbour's unresolved end, and so on: a run of unresolved chunks is
+// completed in one pass. (Only this lane writes the chunks of its run: their
+// own lanes see a right neighbour that was not ready when the pass began,
+// and a run ends at a chunk with an exact first position, so two runs never
+// meet.) k_unres_count then counts what is left; the host repeats passes
+// while anything is.
 __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
                         int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K,
                         int32_t *__restrict__ unres, const int32_t *__restrict__ ready_in,
-                        int32_t *__restrict__ ready_out, int32_t *__restrict__ pending) {
+                        int32_t *__restrict__ ready_out, unsigned long long *__restrict__ runmax) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nch) return;
     int32_t u = unres[i];
     if (u == 0) return;
     // an unresolved chunk is never the last of its strand, so i+1 is its
     // right neighbour; its first position must already be exact
-    if (!ready_in[i + 1]) {
-        atomicAdd(pending, 1);
-        return;
-    }
+    if (!ready_in[i + 1]) return;
     Chunk c = ch[i];
     const int lshift = 3 + 3 * w, wsh = 3 * (w - 1);
     int64_t p1 = c.p0 + c.len;
@@ -264,17 +270,41 @@ __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     win.init();
     BackSyms sy;
     sy.init(Q, p1 - 1);
-    for (int64_t p = p1 - 1; p >= p1 - u; --p) {
-        const uint32_t a = sy.at(p);
-        const uint32_t emit = sy.before(p);
-        packed = ((uint64_t)a << wsh) | (packed >> 3);
-        l = pi_sym(ix, (int)a, l);
-        win.push(make_key(l - m1, packed, emit, lshift), true);
-        if ((p & 7) == 0 || p == p1 - u) win.flush(K, p);
-        sy.next(p);
+    int64_t j = i;
+    unsigned long long run = 0;  // chunks completed by this lane
+    for (;;) {
+        // positions p1 - u .. p1 - 1 of chunk j
+        for (int64_t p = p1 - 1; p >= p1 - u; --p) {
+            const uint32_t a = sy.at(p);
+            const uint32_t emit = sy.before(p);
+            packed = ((uint64_t)a << wsh) | (packed >> 3);
+            l = pi_sym(ix, (int)a, l);
+            win.push(make_key(l - m1, packed, emit, lshift), true);
+            if ((p & 7) == 0 || p == p1 - u) win.flush(K, p);
+            sy.next(p);
+        }
+        unres[j] = 0;
+        ++run;
+        if (u < c.len) break;
+        ready_out[j] = 1;
+        if (c.first) break;
+        // chunk j was unresolved throughout: its left neighbour's end follows
+        const int64_t nb = j - 1;
+        const int32_t un = unres[nb];
+        if (un == 0) break;
+        j = nb;
+        c = ch[nb];
+        p1 = c.p0 + c.len;
+        u = un;
     }
-    unres[i] = 0;
-    if (u == c.len) ready_out[i] = 1;
+    atomicMax(runmax, run);
+}
+
+// Chunks still holding unresolved positions after a fix-up pass.
+__global__ void k_unres_count(const int32_t *__restrict__ unres, int64_t nch, int32_t *__restrict__ left) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const uint64_t m = __ballot(i < nch && unres[i] > 0);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(left, (int32_t)__popcll(m));
 }
 
 // Keys for a merge into an empty index: every l is 0.
@@ -1622,7 +1652,9 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 RB3_HIP(hipMemsetAsync(pend.p, 0, sizeof(int32_t), c.stream));
                 RB3_LAUNCH("chain_fixup", k_fixup, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
                            b1, d_Q, d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(),
-                           rin, rout, pend.as<int32_t>());
+                           rin, rout, stats.as<unsigned long long>() + 3);
+                RB3_LAUNCH("chain_left", k_unres_count, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
+                           unres.as<int32_t>(), nch, pend.as<int32_t>());
                 int32_t hp = 0;
                 RB3_HIP(hipMemcpyAsync(&hp, pend.p, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
                 RB3_HIP(hipStreamSynchronize(c.stream));
@@ -1636,6 +1668,13 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
             }
         }
         st.fixup_passes = passes;
+        if (passes > 0) {
+            unsigned long long rm = 0;
+            RB3_HIP(hipMemcpyAsync(&rm, stats.as<unsigned long long>() + 3, sizeof(rm), hipMemcpyDeviceToHost,
+                                   c.stream));
+            RB3_HIP(hipStreamSynchronize(c.stream));
+            st.fixup_run_max = (int64_t)rm;
+        }
     } else {
         RB3_LAUNCH("build_keys", k_build_keys, grid_for(n2, 256 * 4), dim3(256), 0, c.stream, d_Q, n2, w,
                    K.as<uint64_t>());

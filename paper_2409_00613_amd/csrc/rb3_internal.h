@@ -327,6 +327,7 @@ struct MergeStats {
     int64_t fixup_steps = 0;      // rank steps replayed by fix-up passes
     int64_t chain_takeover = 0;   // neighbour positions completed by chain lanes after their own chunk
     int64_t fixup_passes = 0;
+    int64_t fixup_run_max = 0;    // most chunks one fix-up lane completed
     int64_t key_syms = 0;         // symbols per initial sort key
     int64_t sort_bits = 0;
     int64_t sort_packed = 0;      // 1 when the sort moved packed 8-byte records
