@@ -861,7 +861,7 @@ constexpr int DEEP_DPL = 4;  // depths per lane per window
 // covers 4W depths. The wave finds the first depth where some subgroup
 // splits, applies the same refinement as k_tie_lanes there (all lanes keep
 // the same copy of the members' state), and goes on from the next depth.
-__global__ void __launch_bounds__(256) k_tie_deep(const uint8_t *__restrict__ Q, int64_t n2,
+__global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ dlist,
                                                   const uint32_t *__restrict__ dcount,
