@@ -117,10 +117,11 @@ def cpu_baseline(sample_len: int, threads: int):
 
 
 def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, rates: list[float],
-               served_queries: int, min_len: int = 31, steps: int = 2):
+               served_queries: int, min_len: int = 31, steps: int = 2, batched_only: bool = False):
     """SMEM finding on a serving-shaped workload: closed-loop batched
     throughput, the plain one-query-per-call form, and served latency under
-    Poisson arrivals at fractions of the batched saturation rate."""
+    Poisson arrivals at fractions of the batched saturation rate
+    (batched_only: the batched calls alone, for counter runs)."""
     import synth
     from paper_2409_00613_amd import rb3
     t = time.perf_counter()
@@ -161,10 +162,19 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
         ab = exts * 2 * BLOCK_BYTES
         ach = ab / (k_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": "smem", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes_per_launch": ab,
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": read_traffic("smem", f"serving{n_index}", kernel_source_hash()),
+                "algorithmic_bytes_per_launch": ab,
                 "avg_launch_ms": k_ms, "extensions_per_base": round(exts / bases, 3)}
     log(f"SMEM batched: {batched / 1e9:.3f} G bases/s, {qps:.0f} queries/s, {len(recs)} SMEMs, "
         f"{exts} extensions, smem kernel {k_ms:.2f} ms")
+    config = {"workload": "serving", "genome_len": genome, "haplotypes_indexed": n_index,
+              "both_strands": True, "n": n, "queries": n_queries, "query_bases": bases,
+              "min_len": min_len, "min_occ": 1, "query_lengths": "log-uniform 100-100000"}
+    if batched_only:
+        idx.close()
+        return {"metric": "SMEM query bases/s", "value": round(batched, 1), "unit": "bases/s",
+                "config": config, "roofline": roof}
     # plain form: one query per call
     k = min(plain_queries, n_queries)
     pq = w.queries.slice(0, k)
@@ -196,10 +206,7 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
     idx.close()
     return {"metric": "SMEM query bases/s", "value": round(batched, 1), "unit": "bases/s",
             "plain_one_query_per_call": round(plain, 1), "served": served, "server": st,
-            "config": {"workload": "serving", "genome_len": genome, "haplotypes_indexed": n_index,
-                       "both_strands": True, "n": n, "queries": n_queries, "query_bases": bases,
-                       "min_len": min_len, "min_occ": 1, "query_lengths": "log-uniform 100-100000"},
-            "roofline": roof}
+            "config": config, "roofline": roof}
 
 
 def timed_merges(b1, new, steps: int, warmup: int):
@@ -375,6 +382,8 @@ def main():
                     help="haplotype prefix length for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-smem", action="store_true", help="skip the SMEM serving measurement")
+    ap.add_argument("--smem-batched-only", action="store_true",
+                    help="SMEM: the batched calls only (no per-query calls, no served latency); for counter runs")
     ap.add_argument("--workload", default="pangenome_merge",
                     choices=["pangenome_merge", "uneven_merge", "incremental", "serving"],
                     help="pangenome_merge: 32 haplotypes into 32 (default); uneven_merge: 10,000 "
@@ -462,7 +471,7 @@ def main():
     smem = None
     if not args.no_smem:
         b1.close()
-        smem = smem_bench(10_000_000, 32, 10_000, 200, [0.5], 10_000)
+        smem = smem_bench(10_000_000, 32, 10_000, 200, [0.5], 10_000, batched_only=args.smem_batched_only)
 
     out = {
         "metric": "BWT-merge suffixes inserted/s",
