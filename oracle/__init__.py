@@ -16,6 +16,9 @@ Functions (each follows a definition of arXiv 2409.00613):
   insertion_ranks
               l(x) of each new suffix: number of existing-index suffixes below
               it (the quantity Algorithm 1 accumulates)
+  locate      the suffix-array entry of a row written as (string index,
+              offset within the string) (Sec. 2.4)
+  rows_of     the inverse: the row of the suffix at (string index, offset)
 """
 from __future__ import annotations
 
@@ -257,3 +260,32 @@ def insertion_ranks(S: np.ndarray, lens: np.ndarray, m1: int) -> np.ndarray:
     l = np.empty(n - n1, dtype=np.int64)
     l[S[is_new] - n1] = rows_old_before[is_new]
     return l
+
+
+def _string_starts(lens: np.ndarray) -> np.ndarray:
+    """Start of each string in the concatenated text (each string is
+    followed by its sentinel)."""
+    lens = np.asarray(lens, dtype=np.int64)
+    return np.concatenate([[0], np.cumsum(lens + 1)])[:-1]
+
+
+def locate(S: np.ndarray, lens: np.ndarray, rows) -> tuple[np.ndarray, np.ndarray]:
+    """Position of the suffix at each row (Sec. 2.4): S(row) is a position of
+    the concatenated text; it is reported as the index of the string that
+    holds it and the offset within that string (offset = the string's length
+    for its sentinel suffix)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    starts = _string_starts(lens)
+    pos = np.asarray(S, dtype=np.int64)[rows]
+    j = np.searchsorted(starts, pos, side="right") - 1
+    return j.astype(np.int64), (pos - starts[j]).astype(np.int64)
+
+
+def rows_of(S: np.ndarray, lens: np.ndarray, strings, offsets) -> np.ndarray:
+    """Row of the suffix starting at (string, offset): the inverse suffix
+    array at that text position."""
+    S = np.asarray(S, dtype=np.int64)
+    inv = np.empty_like(S)
+    inv[S] = np.arange(S.shape[0], dtype=np.int64)
+    starts = _string_starts(lens)
+    return inv[starts[np.asarray(strings, dtype=np.int64)] + np.asarray(offsets, dtype=np.int64)]

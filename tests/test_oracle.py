@@ -432,3 +432,53 @@ def test_insertion_ranks_brute_force():
             off += len(s)
             assert l[off] == len(old)
             off += 1
+
+
+# --- locate (suffix-array positions) -------------------------------------------
+
+def test_locate_hand_worked():
+    for strands, want, _ in _read_table("locate_hand.txt"):
+        codes, lens = _codes(strands.split(","))
+        _, S = oracle.bwt(codes, lens, nthreads=1, want_sa=True)
+        j, off = oracle.locate(S, lens, np.arange(S.shape[0]))
+        got = " ".join(f"{a}:{b}" for a, b in zip(j, off))
+        assert got == want, strands
+
+
+def test_locate_brute_force_and_inverse():
+    """Every row's position against the pure-Python suffix sort, and rows_of
+    as its inverse."""
+    rnd = random.Random(41)
+    for _ in range(150):
+        strands = ["".join(rnd.choice("ACGTN") for _ in range(rnd.randint(1, 9)))
+                   for _ in range(rnd.randint(1, 5))]
+        codes, lens = _codes(strands)
+        _, S = oracle.bwt(codes, lens, want_sa=True)
+        j, off = oracle.locate(S, lens, np.arange(S.shape[0]))
+        want = [(x[1], x[2]) for x in sorted(_suffixes(strands))]
+        assert list(zip(j.tolist(), off.tolist())) == want
+        assert np.array_equal(oracle.rows_of(S, lens, j, off), np.arange(S.shape[0]))
+
+
+def test_locate_follows_lf_on_the_bwt():
+    """LF on the BWT alone (pi(r) = C(B[r]) + rank(B[r], r), Table 1) moves a
+    row to the suffix one position earlier in the same string; rows whose BWT
+    symbol is $ hold offset 0. This ties locate to B, not to the sort."""
+    rnd = random.Random(43)
+    for _ in range(60):
+        raw = ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 30)))
+               for _ in range(rnd.randint(1, 6))]
+        strands = [x for s in raw for x in (s, _rc(s))]
+        codes, lens = _codes(strands)
+        B, S = oracle.bwt(codes, lens, want_sa=True)
+        n = B.shape[0]
+        C = [int((B < c).sum()) for c in range(6)]
+        j, off = oracle.locate(S, lens, np.arange(n))
+        for r in range(n):
+            c = int(B[r])
+            if c == 0:
+                assert off[r] == 0
+                continue
+            assert off[r] > 0 and strands[j[r]][off[r] - 1] == SYM[c]
+            pr = C[c] + int((B[:r] == c).sum())
+            assert (j[pr], off[pr]) == (j[r], off[r] - 1)
