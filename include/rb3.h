@@ -82,7 +82,17 @@ typedef struct rb3_opts {
                               of a merge. 1: the plain form, one launch per
                               new string (over that string's chunks); same
                               result, for measuring what batching gains. */
-    int32_t reserved;      /* must be 0 */
+    int32_t ssa_rate;      /* suffix-array sampling distance s for rb3_locate
+                              and rb3_locate1 (Sec. 2.4); 0 (default): no
+                              samples. Taken at rb3_build and kept by every
+                              merge: a suffix is sampled when its position in
+                              its merge batch (the strands of the batch laid
+                              end to end, each with its sentinel) is a
+                              multiple of s, or when it starts its strand, so
+                              a locate needs at most s - 1 LF steps. Costs
+                              one bit per row plus 8 bytes per sample; an
+                              index keeps fewer than 2^32 samples and 2^24
+                              strands (RB3_ELIMIT otherwise). */
 } rb3_opts;
 
 /* Fill *o with the defaults above. */
@@ -142,6 +152,37 @@ int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64
 /* Work done by the calling thread's last successful rb3_smem call: the
  * number of bi-interval extensions (each reads rank-all at two positions). */
 int rb3_last_smem_stats(int64_t *extensions);
+
+/*
+ * rb3_locate: position of the suffix at each row (Sec. 2.4): strand[i] is
+ * the index of the strand holding row rows[i]'s suffix in the index's list
+ * (strands numbered in the order they were added, both strands counted) and
+ * offset[i] its offset in that strand (the strand's length for its
+ * sentinel suffix). rows: n entries in host or device memory (mem); every
+ * row must be in [0, n_index), else RB3_EINVAL. strand and offset: host
+ * arrays of n entries. The index must have samples (ssa_rate > 0), else
+ * RB3_EINVAL.
+ */
+int rb3_locate(const rb3_index *idx, const int64_t *rows, int64_t n, int32_t mem, int64_t *strand,
+               int64_t *offset);
+
+/*
+ * rb3_locate1: one occurrence in each SA interval [lo[i], hi[i]) (Locate1 of
+ * Algorithm 2: the largest remaining interval is tested for a sampled row,
+ * else extended backwards by every symbol). Outputs as rb3_locate; an empty
+ * interval gives strand = offset = -1. Intervals must satisfy
+ * 0 <= lo <= hi <= n_index, else RB3_EINVAL. Which occurrence is returned is
+ * not specified; it is always one whose row lies in [lo, hi).
+ */
+int rb3_locate1(const rb3_index *idx, const int64_t *lo, const int64_t *hi, int64_t n, int32_t mem,
+                int64_t *strand, int64_t *offset);
+
+/* Sampling distance (0: no samples) and number of samples of an index. */
+int rb3_ssa_info(const rb3_index *idx, int32_t *rate, int64_t *nsamples);
+
+/* LF or rank-all steps taken by the calling thread's last successful
+ * rb3_locate / rb3_locate1 call. */
+int rb3_last_locate_stats(int64_t *lf_steps);
 
 /* Size of the BWT n, number of sentinels m, and C[c] = number of symbols
  * smaller than c (Table 1) for c = 0..5. Any output pointer may be NULL. */

@@ -23,6 +23,7 @@ namespace rb3 {
 static thread_local std::string g_err;
 // extensions performed by the last rb3_smem call of this thread
 static thread_local int64_t g_last_smem_exts = 0;
+static thread_local int64_t g_last_locate_steps = 0;
 static thread_local int g_err_code = 0;
 
 void set_error(int code, const std::string &msg) {
@@ -159,7 +160,8 @@ static int ctx_from_opts(const rb3_opts *o, Ctx &c) {
     c.launch_per_string = o->launch_per_string ? 1 : 0;
     c.both = o->both_strands ? 1 : 0;
     if ((c.alloc == nullptr) != (c.free_fn == nullptr)) return fail(RB3_EINVAL, "dev_alloc and dev_free must be given together");
-    if (o->reserved != 0) return fail(RB3_EINVAL, "rb3_opts.reserved must be 0");
+    if (o->ssa_rate < 0 || o->ssa_rate > (1 << 24)) return fail(RB3_EINVAL, "ssa_rate must be in 0 .. 2^24");
+    c.ssa = o->ssa_rate;
     RB3_HIP(hipSetDevice(c.device));
     if (o->stream) {
         c.stream = (hipStream_t)o->stream;
@@ -184,6 +186,7 @@ static Ctx call_ctx(const IndexData &d) {
     c.chunk_len = d.ctx.chunk_len;
     c.launch_per_string = d.ctx.launch_per_string;
     c.both = d.ctx.both;
+    c.ssa = d.ctx.ssa;
     return c;
 }
 
@@ -236,6 +239,20 @@ static int init_empty(Ctx &c, IndexData &d) {
     RB3_HIP(hipMemsetAsync(blk.p, 0xFF, 48, c.stream));
     RB3_HIP(hipMemsetAsync((uint8_t *)blk.p + 48, 0, 16, c.stream));
     RB3_HIP(hipMemsetAsync(sb.p, 0, SB_STRIDE * sizeof(int64_t), c.stream));
+    if (d.ctx.ssa > 0) {
+        // one block's sample words and counts, all zero
+        DBuf sbits, scnt;
+        RB3_ALLOC(sbits, &c, 2 * sizeof(uint64_t));
+        RB3_ALLOC(scnt, &c, 2 * sizeof(uint32_t));
+        RB3_HIP(hipMemsetAsync(sbits.p, 0, 2 * sizeof(uint64_t), c.stream));
+        RB3_HIP(hipMemsetAsync(scnt.p, 0, 2 * sizeof(uint32_t), c.stream));
+        d.smp_bits = sbits.as<uint64_t>();
+        d.smp_cnt = scnt.as<uint32_t>();
+        d.smp_val = nullptr;
+        d.nsmp = 0;
+        sbits.release();
+        scnt.release();
+    }
     d.blk = blk.as<uint4>();
     d.sb = sb.as<int64_t>();
     blk.release();
@@ -274,11 +291,21 @@ static int do_merge(Ctx &c, IndexData &d, const uint8_t *seq, const int64_t *len
     int64_t *nsb = nullptr;
     int64_t C[6];
     MergeStats st;
-    RB3_TRY(merge_into(c, d, Q.as<uint8_t>(), slens.data(), m2, n2, &nb, &nsb, C, st));
+    SmpOut so;
+    RB3_TRY(merge_into(c, d, Q.as<uint8_t>(), slens.data(), m2, n2, &nb, &nsb, C, st, &so));
     c.dfree(d.blk);
     c.dfree(d.sb);
     d.blk = nb;
     d.sb = nsb;
+    if (d.ctx.ssa > 0) {
+        c.dfree(d.smp_bits);
+        c.dfree(d.smp_cnt);
+        c.dfree(d.smp_val);
+        d.smp_bits = so.bits;
+        d.smp_cnt = so.cnt;
+        d.smp_val = so.val;
+        d.nsmp = so.nsmp;
+    }
     d.n += n2;
     d.m += m2;
     for (int i = 0; i < 6; ++i) d.C[i] = C[i];
@@ -441,6 +468,90 @@ int rb3_last_smem_stats(int64_t *extensions) {
     return RB3_OK;
 }
 
+// Rows or interval ends in host or device memory, as int64 arrays on the
+// device.
+static int stage_i64(Ctx &c, const int64_t *p, int64_t n, int32_t mem, DBuf &hold, const int64_t **dptr) {
+    const uint8_t *d = nullptr;
+    RB3_TRY(stage(c, (const uint8_t *)p, n * (int64_t)sizeof(int64_t), mem, hold, &d));
+    *dptr = (const int64_t *)d;
+    return RB3_OK;
+}
+
+static int run_locate(Ctx &c, const IndexData &d, const int64_t *a, const int64_t *b, int64_t n, int32_t mem,
+                      int64_t *strand, int64_t *offset) {
+    DBuf ha, hb, ds, doff, err, stp;
+    const int64_t *da = nullptr, *db = nullptr;
+    RB3_TRY(stage_i64(c, a, n, mem, ha, &da));
+    if (b) RB3_TRY(stage_i64(c, b, n, mem, hb, &db));
+    RB3_ALLOC(ds, &c, n * sizeof(int64_t));
+    RB3_ALLOC(doff, &c, n * sizeof(int64_t));
+    RB3_ALLOC(err, &c, sizeof(int32_t));
+    RB3_ALLOC(stp, &c, sizeof(unsigned long long));
+    RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
+    RB3_HIP(hipMemsetAsync(stp.p, 0, sizeof(unsigned long long), c.stream));
+    if (b)
+        RB3_TRY(locate_one(c, d.dev(), d.smp(), da, db, n, ds.as<int64_t>(), doff.as<int64_t>(), err.as<int32_t>(),
+                           stp.as<unsigned long long>()));
+    else
+        RB3_TRY(locate_rows(c, d.dev(), d.smp(), da, n, ds.as<int64_t>(), doff.as<int64_t>(), err.as<int32_t>(),
+                            stp.as<unsigned long long>()));
+    RB3_HIP(hipMemcpyAsync(strand, ds.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipMemcpyAsync(offset, doff.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    unsigned long long steps = 0;
+    RB3_HIP(hipMemcpyAsync(&steps, stp.p, sizeof(steps), hipMemcpyDeviceToHost, c.stream));
+    int32_t bad = 0;
+    RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
+    if (bad) return fail(RB3_EINVAL, b ? "an interval is outside [0, n] or reversed" : "a row is outside [0, n)");
+    g_last_locate_steps = (int64_t)steps;
+    return RB3_OK;
+}
+
+int rb3_locate(const rb3_index *idx, const int64_t *rows, int64_t n, int32_t mem, int64_t *strand,
+               int64_t *offset) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    if (idx->d.ctx.ssa <= 0) return fail(RB3_EINVAL, "the index has no suffix-array samples (ssa_rate = 0)");
+    if (mem != RB3_MEM_HOST && mem != RB3_MEM_DEVICE) return fail(RB3_EINVAL, "bad mem");
+    if (n < 0 || (n > 0 && (!rows || !strand || !offset))) return fail(RB3_EINVAL, "bad arguments");
+    if (n == 0) return RB3_OK;
+    if (mem == RB3_MEM_HOST)
+        for (int64_t i = 0; i < n; ++i)
+            if (rows[i] < 0 || rows[i] >= idx->d.n) return fail(RB3_EINVAL, "a row is outside [0, n)");
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    Ctx c = call_ctx(idx->d);
+    int rc = run_locate(c, idx->d, rows, nullptr, n, mem, strand, offset);
+    return finish(c, rc);
+}
+
+int rb3_locate1(const rb3_index *idx, const int64_t *lo, const int64_t *hi, int64_t n, int32_t mem,
+                int64_t *strand, int64_t *offset) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    if (idx->d.ctx.ssa <= 0) return fail(RB3_EINVAL, "the index has no suffix-array samples (ssa_rate = 0)");
+    if (mem != RB3_MEM_HOST && mem != RB3_MEM_DEVICE) return fail(RB3_EINVAL, "bad mem");
+    if (n < 0 || (n > 0 && (!lo || !hi || !strand || !offset))) return fail(RB3_EINVAL, "bad arguments");
+    if (n == 0) return RB3_OK;
+    if (mem == RB3_MEM_HOST)
+        for (int64_t i = 0; i < n; ++i)
+            if (lo[i] < 0 || hi[i] > idx->d.n || lo[i] > hi[i])
+                return fail(RB3_EINVAL, "an interval is outside [0, n] or reversed");
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    Ctx c = call_ctx(idx->d);
+    int rc = run_locate(c, idx->d, lo, hi, n, mem, strand, offset);
+    return finish(c, rc);
+}
+
+int rb3_ssa_info(const rb3_index *idx, int32_t *rate, int64_t *nsamples) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    if (rate) *rate = idx->d.ctx.ssa;
+    if (nsamples) *nsamples = idx->d.nsmp;
+    return RB3_OK;
+}
+
+int rb3_last_locate_stats(int64_t *lf_steps) {
+    if (!lf_steps) return fail(RB3_EINVAL, "lf_steps is NULL");
+    *lf_steps = g_last_locate_steps;
+    return RB3_OK;
+}
+
 int rb3_info(const rb3_index *idx, int64_t *n, int64_t *m, int64_t C[6]) {
     if (!idx) return fail(RB3_EINVAL, "index is NULL");
     if (n) *n = idx->d.n;
@@ -470,6 +581,8 @@ int rb3_import(const rb3_opts *o, const uint8_t *codes, int64_t n, int32_t mem, 
     if (!out) return fail(RB3_EINVAL, "out is NULL");
     if (n < 1 || !codes) return fail(RB3_EINVAL, "need at least one code");
     if (mem != RB3_MEM_HOST && mem != RB3_MEM_DEVICE) return fail(RB3_EINVAL, "bad mem");
+    if (o && o->ssa_rate != 0)
+        return fail(RB3_EINVAL, "suffix-array samples need the strings: build the index with rb3_build");
     rb3_index *ix = new (std::nothrow) rb3_index();
     if (!ix) return fail(RB3_ENOMEM, "host allocation failed");
     int rc = ctx_from_opts(o, ix->d.ctx);
@@ -536,6 +649,25 @@ int rb3_clone(const rb3_index *src, rb3_index **out) {
         RB3_ALLOC(sb, &c, sbb);
         RB3_HIP(hipMemcpyAsync(blk.p, src->d.blk, bb, hipMemcpyDeviceToDevice, c.stream));
         RB3_HIP(hipMemcpyAsync(sb.p, src->d.sb, sbb, hipMemcpyDeviceToDevice, c.stream));
+        if (src->d.ctx.ssa > 0) {
+            DBuf sbits, scnt, sval;
+            const int64_t nb = num_blocks(src->d.n);
+            RB3_ALLOC(sbits, &c, nb * 2 * sizeof(uint64_t));
+            RB3_ALLOC(scnt, &c, (nb + 1) * sizeof(uint32_t));
+            RB3_HIP(hipMemcpyAsync(sbits.p, src->d.smp_bits, nb * 2 * sizeof(uint64_t), hipMemcpyDeviceToDevice,
+                                   c.stream));
+            RB3_HIP(hipMemcpyAsync(scnt.p, src->d.smp_cnt, (nb + 1) * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                   c.stream));
+            if (src->d.nsmp > 0) {
+                RB3_ALLOC(sval, &c, src->d.nsmp * sizeof(uint64_t));
+                RB3_HIP(hipMemcpyAsync(sval.p, src->d.smp_val, src->d.nsmp * sizeof(uint64_t),
+                                       hipMemcpyDeviceToDevice, c.stream));
+            }
+            ix->d.smp_bits = (uint64_t *)sbits.release();
+            ix->d.smp_cnt = (uint32_t *)scnt.release();
+            ix->d.smp_val = src->d.nsmp > 0 ? (uint64_t *)sval.release() : nullptr;
+            ix->d.nsmp = src->d.nsmp;
+        }
         ix->d.n = src->d.n;
         ix->d.m = src->d.m;
         for (int i = 0; i < 6; ++i) ix->d.C[i] = src->d.C[i];
@@ -559,6 +691,9 @@ void rb3_index_free(rb3_index *idx) {
     Ctx c = call_ctx(idx->d);
     c.free_now(idx->d.blk);
     c.free_now(idx->d.sb);
+    c.free_now(idx->d.smp_bits);
+    c.free_now(idx->d.smp_cnt);
+    c.free_now(idx->d.smp_val);
     if (idx->d.ctx.own_stream && idx->d.ctx.stream) (void)hipStreamDestroy(idx->d.ctx.stream);
     delete idx;
 }

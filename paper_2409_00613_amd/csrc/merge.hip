@@ -445,7 +445,7 @@ __global__ void k_compact(const uint32_t *__restrict__ tpos, const uint32_t *__r
 // Move tied records to their final rows: SK[R[pos]] = K[pos].
 __global__ void k_place(const uint32_t *__restrict__ SV, const uint32_t *__restrict__ R,
                         const uint64_t *__restrict__ K, int64_t n, uint64_t *__restrict__ SK,
-                        int32_t *__restrict__ guard) {
+                        uint32_t *__restrict__ PF, int32_t *__restrict__ guard) {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
          s += (int64_t)gridDim.x * blockDim.x) {
         uint32_t p = SV[s];
@@ -459,6 +459,7 @@ __global__ void k_place(const uint32_t *__restrict__ SV, const uint32_t *__restr
             continue;
         }
         if (r != (uint32_t)s) SK[r] = K[p];
+        if (PF) PF[r] = p;
     }
 }
 
@@ -473,6 +474,14 @@ __global__ void k_place(const uint32_t *__restrict__ SV, const uint32_t *__restr
 // size; the k_tie_* kernels order each of them by comparing the symbols
 // that follow the members, depth by depth (plain string order), and stop
 // refining a subgroup as soon as its symbols agree.
+
+// With suffix-array samples a new suffix is sampled when its position in the
+// batch is a multiple of the sampling distance or it starts its strand (BWT
+// symbol $). Tied suffixes with a sampled member need their exact order even
+// when their BWT symbols agree, because the sample lands on its own row.
+__device__ __forceinline__ bool sampled_pos(uint32_t p, uint32_t e, int32_t srate) {
+    return srate > 0 && (p % (uint32_t)srate == 0u || e == 0u);
+}
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -511,7 +520,8 @@ struct TieLists {
     uint32_t *l[TG_CLASSES];
 };
 
-__global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__restrict__ SK, int64_t n,
+__global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__restrict__ SK,
+                                                           const uint32_t *__restrict__ SV, int32_t srate, int64_t n,
                                                            TieLists lists, uint32_t *__restrict__ gstat,
                                                            unsigned long long *__restrict__ tied,
                                                            uint32_t *__restrict__ ghist) {
@@ -534,10 +544,12 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
         const int64_t wbase = tile * TILE + (int64_t)wv * 64 * TG_WIN;
         // (vw[TG_WIN] is the window after the last one, for the extension test)
         uint64_t vw[TG_WIN + 1];
+        uint32_t pw[TG_WIN + 1];  // positions, read only with samples
 #pragma unroll
         for (int j = 0; j <= TG_WIN; ++j) {
             const int64_t sj = wbase + (int64_t)j * 64 + lane;
             vw[j] = sj < n ? SK[sj] : ~0ull;
+            pw[j] = (srate > 0 && sj < n) ? SV[sj] : 1u;
         }
         uint64_t carry = (wbase > 0 && wbase < n) ? (SK[wbase - 1] >> 3) : ~0ull;  // key before the first window
 #pragma unroll
@@ -560,7 +572,7 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
             const uint64_t below = smask & low_mask(lane + 1);
             const int lead = below ? 63 - __clzll((long long)below) : -1;
             const uint32_t le = __shfl(e, lead < 0 ? 0 : lead);
-            const bool mism = in && lead >= 0 && e != le;
+            const bool mism = in && lead >= 0 && (e != le || sampled_pos(pw[j], e, srate));
             const uint64_t mmask = __ballot(mism);
             // the window's last group may run past its end: the whole wave
             // extends it with coalesced 64-key reads of the following windows
@@ -573,14 +585,17 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
             if (ls >= 0 && last_in == 63 && (xkey & 7) != 0) {
                 // the first following window is already in registers
                 uint64_t uv = vw[j + 1];
+                uint32_t up = pw[j + 1];
                 for (int64_t t = w0 + 64; t < n;) {
                     const uint64_t mm = __ballot((uv >> 3) == xkey);
                     const int run = ~mm ? __ffsll((unsigned long long)~mm) - 1 : 64;
-                    if (__ballot(lane < run && (uint32_t)(uv & 7) != xe)) xuni = false;
+                    const uint32_t ue = (uint32_t)(uv & 7);
+                    if (__ballot(lane < run && (ue != xe || sampled_pos(up, ue, srate)))) xuni = false;
                     ext += run;
                     if (run < 64) break;
                     t += 64;
                     uv = t + lane < n ? SK[t + lane] : ~0ull;
+                    up = (srate > 0 && t + lane < n) ? SV[t + lane] : 1u;
                 }
             }
             if (start && !sent) {
@@ -694,7 +709,8 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restric
                                                         const uint32_t *__restrict__ slist, int64_t ns,
                                                         uint32_t *__restrict__ qhead,
                                                         uint32_t *__restrict__ dlist, uint32_t *__restrict__ dcount,
-                                                        uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
+                                                        uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
+                                                        int32_t srate, int32_t *__restrict__ guard,
                                                         unsigned long long *__restrict__ reads) {
     const int lane = threadIdx.x & 63;
     const int64_t total = np + ns;
@@ -809,7 +825,7 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restric
                 for (int j = 0; j < SMALL_MAXK; ++j) {
                     bool same = act[j] && nsb[j] == nsb[i];
                     cnt += same ? 1u : 0u;
-                    uni &= !same || e[j] == e[i];
+                    uni &= !same || (e[j] == e[i] && !sampled_pos(pos[j], e[j], srate));
                 }
                 nact[i] = act[i] && cnt >= 2 && !uni;
                 any |= nact[i];
@@ -825,7 +841,10 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restric
         if (!any) {
 #pragma unroll
             for (int i = 0; i < SMALL_MAXK; ++i)
-                if (i < k) SK[gs + o[i]] = gkey | e[i];
+                if (i < k) {
+                    SK[gs + o[i]] = gkey | e[i];
+                    if (PF) PF[gs + o[i]] = pos[i];
+                }
             busy = false;
             maxdepth = (uint32_t)d0 > maxdepth ? (uint32_t)d0 : maxdepth;
         }
@@ -865,7 +884,8 @@ __global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ dlist,
                                                   const uint32_t *__restrict__ dcount,
-                                                  uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
+                                                  uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
+                                                  int32_t srate, int32_t *__restrict__ guard,
                                                   unsigned long long *__restrict__ reads) {
     const int lane = threadIdx.x & 63;
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -993,7 +1013,7 @@ __global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__
                     for (int j = 0; j < SMALL_MAXK; ++j) {
                         bool same = act[j] && nsb[j] == nsb[i];
                         cnt += same ? 1u : 0u;
-                        uni &= !same || e[j] == e[i];
+                        uni &= !same || (e[j] == e[i] && !sampled_pos(pos[j], e[j], srate));
                         if (same && no[j] == nsb[i]) ld = (uint32_t)j;
                     }
                     nact[i] = act[i] && cnt >= 2 && !uni;
@@ -1020,14 +1040,16 @@ __global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__
         }
         maxdepth = (uint32_t)d0 > maxdepth ? (uint32_t)d0 : maxdepth;
         if (lane < k) {
-            uint32_t oo = 0, ee = 0;
+            uint32_t oo = 0, ee = 0, pp = 0;
 #pragma unroll
             for (int i = 0; i < SMALL_MAXK; ++i)
                 if (i == lane) {
                     oo = o[i];
                     ee = e[i];
+                    pp = pos[i];
                 }
             SK[gs + oo] = gkey | ee;
+            if (PF) PF[gs + oo] = pp;
         }
     }
     if (lane == 0 && steps) atomicAdd(reads, (unsigned long long)steps);
@@ -1059,7 +1081,8 @@ template <int MPL>
 __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ glist, int64_t ng,
-                                                  uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
+                                                  uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
+                                                  int32_t srate, int32_t *__restrict__ guard,
                                                   unsigned long long *__restrict__ reads) {
     constexpr uint32_t MAXK = 64 * MPL;
     const int lane = threadIdx.x & 63;
@@ -1196,7 +1219,7 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q,
                             less += (uint32_t)__popcll(
                                 __ballot(same && (kk[s] < kL || (kk[s] == kL && sent[s] && p[s] < pL))));
                             cnt += (uint32_t)__popcll(m[s]);
-                            uni &= (__ballot(e[s] == eL) & m[s]) == m[s];
+                            uni &= (__ballot(e[s] == eL && !sampled_pos(p[s], e[s], srate)) & m[s]) == m[s];
                         }
                         const uint32_t base = subL + less;
                         uint32_t pre = 0;
@@ -1223,7 +1246,10 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q,
         }
 #pragma unroll
         for (int s = 0; s < MPL; ++s)
-            if ((uint32_t)(s * 64 + lane) < k) SK[gs + o[s]] = key[s];
+            if ((uint32_t)(s * 64 + lane) < k) {
+                SK[gs + o[s]] = key[s];
+                if (PF) PF[gs + o[s]] = p[s];
+            }
     }
     const uint64_t tot = wave_sum_u64(steps);
     if (lane == 0 && tot) atomicAdd(reads, (unsigned long long)tot);
@@ -1242,7 +1268,8 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q,
 template <int T, int MPT, int DEPTHS>
 __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, int64_t n2, const uint32_t *__restrict__ SV,
                                                  const uint32_t *__restrict__ glist, int64_t ng,
-                                                 uint64_t *__restrict__ SK, int32_t *__restrict__ guard,
+                                                 uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
+                                                 int32_t srate, int32_t *__restrict__ guard,
                                                  unsigned long long *__restrict__ stat) {
     constexpr int MAXK = T * MPT;
     static_assert(MAXK <= 65535, "places must fit 16 bits");
@@ -1360,10 +1387,10 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, 
                     const int o = tid + j * T;
                     if (o < k && sact[o] && ssub[o] == o) {
                         const uint8_t e0 = se[o];
-                        bool uni = true;
+                        bool uni = !sampled_pos(spos[o], e0, srate);
                         int x = o + 1;
                         while (x < k && ssub[x] == o) {
-                            uni &= se[x] == e0;
+                            uni &= se[x] == e0 && !sampled_pos(spos[x], se[x], srate);
                             ++x;
                         }
                         ssz[o] = (uint16_t)(x - o);
@@ -1390,7 +1417,10 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, 
         }
         maxd = d0 > maxd ? d0 : maxd;
         // every thread read gkey before the first barrier of this group
-        for (int o = tid; o < k; o += T) SK[gs + o] = gkey | se[o];
+        for (int o = tid; o < k; o += T) {
+            SK[gs + o] = gkey | se[o];
+            if (PF) PF[gs + o] = spos[o];
+        }
         __syncthreads();
     }
     const uint64_t tot = wave_sum_u64(reads);
@@ -1445,11 +1475,20 @@ __global__ void k_block_count(const uint64_t *__restrict__ SK, int64_t n2, int64
 // offsets are loaded a block ahead), so one memory latency is paid per block
 // instead of three dependent ones; lanes then take their old symbols from
 // the loaded words by lane shuffles.
+//
+// With suffix-array samples (srate > 0) the wave also writes the block's
+// sample bits and count: an old row keeps its bit from the existing index
+// (lanes 12..15 hold the old blocks' sample words), a new row is sampled
+// when its position in the batch is a multiple of srate or starts a strand
+// (its BWT symbol is $).
 __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__ b1words, int64_t nblk1,
                                                     const uint64_t *__restrict__ SK,
                                                     const uint32_t *__restrict__ bs, int64_t nout,
                                                     int64_t nblk_out, int64_t n1, int64_t m1, int lshift,
-                                                    uint4 *__restrict__ out, int32_t *__restrict__ guard) {
+                                                    uint4 *__restrict__ out, int32_t *__restrict__ guard,
+                                                    int32_t srate, const uint64_t *__restrict__ obits,
+                                                    const uint32_t *__restrict__ PF,
+                                                    uint64_t *__restrict__ nbits, uint32_t *__restrict__ ncnt) {
     __shared__ uint8_t slot[4][128];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -1471,27 +1510,40 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
         const int64_t nnew = (int64_t)s1 - (int64_t)s0;
         const int64_t nold = rows - nnew;
         const int64_t ib0 = i0 >> BLK_SHIFT;
-        // lane j < 12 holds plane word j % 6 of old block ib0 + j / 6
+        // lane j < 12 holds plane word j % 6 of old block ib0 + j / 6; with
+        // samples, lane 12 + j (j < 4) holds sample word j % 2 of old block
+        // ib0 + j / 2
         uint64_t wd = 0;
-        if (nold > 0 && lane < 12 && i0 >= 0 && i0 < n1) {
-            const int64_t ib = ib0 + lane / 6;
-            if (ib <= ((i0 + nold - 1) >> BLK_SHIFT) && ib < nblk1) wd = b1words[ib * 8 + lane % 6];
+        if (nold > 0 && i0 >= 0 && i0 < n1) {
+            if (lane < 12) {
+                const int64_t ib = ib0 + lane / 6;
+                if (ib <= ((i0 + nold - 1) >> BLK_SHIFT) && ib < nblk1) wd = b1words[ib * 8 + lane % 6];
+            } else if (srate > 0 && lane < 16) {
+                const int64_t ib = ib0 + ((lane - 12) >> 1);
+                if (ib <= ((i0 + nold - 1) >> BLK_SHIFT) && ib < nblk1) wd = obits[ib * 2 + (lane & 1)];
+            }
         }
         const uint32_t ka = s0 + (uint32_t)lane, kb = ka + 64u;
         const uint64_t keya = ka < s1 ? SK[ka] : 0ull;
         const uint64_t keyb = kb < s1 ? SK[kb] : 0ull;
+        const uint32_t pa = (srate > 0 && ka < s1) ? PF[ka] : 1u;
+        const uint32_t pb = (srate > 0 && kb < s1) ? PF[kb] : 1u;
         slot[wv][lane] = 0;
         slot[wv][lane + 64] = 0;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (ka < s1) {
             const int64_t M = (int64_t)(keya >> lshift) + m1 + ka;
-            if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | (uint32_t)(keya & 7));
+            const uint32_t ea = (uint32_t)(keya & 7);
+            const uint32_t sa = (srate > 0 && (pa % (uint32_t)srate == 0u || ea == 0u)) ? 0x40u : 0u;
+            if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | sa | ea);
             else atomicOr(guard, GUARD_INTERLEAVE);
         }
         if (kb < s1) {
             const int64_t M = (int64_t)(keyb >> lshift) + m1 + kb;
-            if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | (uint32_t)(keyb & 7));
+            const uint32_t eb = (uint32_t)(keyb & 7);
+            const uint32_t sb = (srate > 0 && (pb % (uint32_t)srate == 0u || eb == 0u)) ? 0x40u : 0u;
+            if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | sb | eb);
             else atomicOr(guard, GUARD_INTERLEAVE);
         }
         if (nnew > 128 && lane == 0) atomicOr(guard, GUARD_INTERLEAVE);  // more entries than rows
@@ -1526,6 +1578,21 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
                 c1 = (uint32_t)((b0w >> bb) & 1u) | (uint32_t)(((b1w >> bb) & 1u) << 1) |
                      (uint32_t)(((b2w >> bb) & 1u) << 2);
         }
+        if (srate > 0) {
+            // old rows' sample bits, with every lane active for the shuffles
+            const uint64_t swa = __shfl(wd, 12 + 2 * (oka ? sela : 0) + (int)((ia >> 6) & 1));
+            const uint64_t swb = __shfl(wd, 12 + 2 * (okb ? selb : 0) + (int)((ib >> 6) & 1));
+            const bool sma = P0 + lane < nout &&
+                             ((e0 & 0x80u) ? (e0 & 0x40u) != 0u : (oka && ((swa >> (ia & 63)) & 1ull)));
+            const bool smb = P0 + 64 + lane < nout &&
+                             ((e1 & 0x80u) ? (e1 & 0x40u) != 0u : (okb && ((swb >> (ib & 63)) & 1ull)));
+            const uint64_t q0 = __ballot(sma), q1 = __ballot(smb);
+            if (lane == 0) {
+                nbits[2 * b] = q0;
+                nbits[2 * b + 1] = q1;
+                ncnt[b] = (uint32_t)(__popcll(q0) + __popcll(q1));
+            }
+        }
         uint64_t a0 = __ballot(c0 & 1), a1 = __ballot(c0 & 2), a2 = __ballot(c0 & 4);
         uint64_t d0 = __ballot(c1 & 1), d1 = __ballot(c1 & 2), d2 = __ballot(c1 & 4);
         uint32_t cnt = 0;
@@ -1547,6 +1614,89 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
     }
 }
 
+// Sample values of the merged index, one wave per 128-row output block with
+// a sampled row: the block's new rows are found again from its sorted
+// entries; a sampled new row gets (strand, offset) of its position in the
+// batch (strands numbered on from sid0; sstart holds the m2 + 1 strand
+// starts in the batch), a sampled old row brings the existing index's value
+// along. The k-th sampled row of the block goes to nval[nbase[b] + k].
+__global__ void __launch_bounds__(256) k_smp_values(const uint64_t *__restrict__ SK, const uint32_t *__restrict__ PF,
+                                                    const uint32_t *__restrict__ bs, int64_t nout, int64_t nblk_out,
+                                                    int64_t n1, int64_t m1, int lshift,
+                                                    const uint64_t *__restrict__ nbits,
+                                                    const uint32_t *__restrict__ nbase, int64_t nsmp,
+                                                    const uint64_t *__restrict__ obits,
+                                                    const uint32_t *__restrict__ ocnt,
+                                                    const uint64_t *__restrict__ oval, int64_t onsmp, int64_t nblk1,
+                                                    const int64_t *__restrict__ sstart, int64_t m2, int64_t sid0,
+                                                    uint64_t *__restrict__ nval, int32_t *__restrict__ guard) {
+    __shared__ uint8_t slot[4][128];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t below = low_mask(lane);
+    for (int64_t b = wave; b < nblk_out; b += nwaves) {
+        const uint64_t w0 = nbits[2 * b], w1 = nbits[2 * b + 1];
+        if ((w0 | w1) == 0ull) continue;
+        const uint32_t s0 = bs[b], s1 = bs[b + 1];
+        const int64_t P0 = b << BLK_SHIFT;
+        const int64_t i0 = P0 - (int64_t)s0;
+        slot[wv][lane] = 0;
+        slot[wv][lane + 64] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t k = s0 + (uint32_t)lane; k < s1 && k < s0 + 128u; k += 64u) {
+            const int64_t M = (int64_t)(SK[k] >> lshift) + m1 + k;
+            if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(k - s0 + 1u);
+            else atomicOr(guard, GUARD_SAMPLE);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t ea = slot[wv][lane], eb = slot[wv][lane + 64];
+        const uint64_t na = __ballot(ea != 0u), nb = __ballot(eb != 0u);
+        const uint32_t base = nbase[b];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint64_t w = h ? w1 : w0;
+            if (!((w >> lane) & 1ull)) continue;
+            const int64_t r = P0 + 64 * h + lane;
+            const int64_t outi = (int64_t)base + (h ? __popcll(w0) + __popcll(w1 & below) : __popcll(w0 & below));
+            const uint32_t e = h ? eb : ea;
+            uint64_t v = 0;
+            bool ok = outi < nsmp && r < nout;
+            if (e) {
+                const uint32_t p = PF[s0 + e - 1u];
+                int64_t lo = 0, hi = m2;  // sstart[lo] <= p < sstart[hi]
+                while (hi - lo > 1) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (sstart[mid] <= (int64_t)p) lo = mid;
+                    else hi = mid;
+                }
+                const int64_t off = (int64_t)p - sstart[lo];
+                ok = ok && off >= 0 && (uint64_t)off <= SMP_OFF_MASK;
+                v = ((uint64_t)(sid0 + lo) << SMP_ID_SHIFT) | (uint64_t)off;
+            } else {
+                const int64_t before = h ? __popcll(na) + __popcll(nb & below) : __popcll(na & below);
+                const int64_t i = i0 + 64 * h + lane - before;  // old row
+                ok = ok && i >= 0 && i < n1 && (i >> BLK_SHIFT) < nblk1;
+                if (ok) {
+                    const int64_t ob = i >> BLK_SHIFT;
+                    const uint64_t u0 = obits[2 * ob], u1 = obits[2 * ob + 1];
+                    const int o = (int)(i & (BLK_SYMS - 1));
+                    const int64_t idx = (int64_t)ocnt[ob] +
+                                        (o < 64 ? __popcll(u0 & low_mask(o)) : __popcll(u0) + __popcll(u1 & low_mask(o - 64)));
+                    ok = idx < onsmp;
+                    if (ok) v = oval[idx];
+                }
+            }
+            if (ok) nval[outi] = v;
+            else atomicOr(guard, GUARD_SAMPLE);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 static int bits_for(int64_t v) {  // bits to hold values 0..v
     int b = 0;
     while (b < 63 && (v >> b) != 0) ++b;
@@ -1554,7 +1704,8 @@ static int bits_for(int64_t v) {  // bits to hold values 0..v
 }
 
 int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_lens, int64_t m2,
-               int64_t n2, uint4 **new_blk, int64_t **new_sb, int64_t new_C[6], MergeStats &st) {
+               int64_t n2, uint4 **new_blk, int64_t **new_sb, int64_t new_C[6], MergeStats &st,
+               SmpOut *smp) {
     const DevIndex b1 = ix.dev();
     const int64_t n1 = ix.n, m1 = ix.m;
     const int w = n1 == 0 ? 20 : 1;
@@ -1571,6 +1722,17 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     if (hi_bit > 64) {
         set_error(RB3_ELIMIT, "index too large for the merge key");
         return RB3_ELIMIT;
+    }
+    if (ix.ctx.ssa > 0) {
+        // at most one sample per multiple of the distance plus one per strand
+        if (ix.nsmp + n2 / ix.ctx.ssa + m2 + 1 >= (int64_t)UINT32_MAX) {
+            set_error(RB3_ELIMIT, "too many suffix-array samples (raise the sampling distance)");
+            return RB3_ELIMIT;
+        }
+        if (m1 + m2 > SMP_MAX_STRANDS) {
+            set_error(RB3_ELIMIT, "too many strands for suffix-array samples");
+            return RB3_ELIMIT;
+        }
     }
 
     DBuf K, stats, guardb;
@@ -1700,6 +1862,18 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         ka.reset();
         va.reset();
     }
+    // With suffix-array samples the interleave needs every new suffix's
+    // position in its final order: PF starts as the sorted positions, and
+    // the tie kernels write their groups' final order into it.
+    const bool samples = ix.ctx.ssa > 0;
+    const int32_t srate = samples ? ix.ctx.ssa : 0;
+    DBuf pfb;
+    uint32_t *PF = nullptr;
+    if (samples) {
+        RB3_ALLOC(pfb, &c, n2 * sizeof(uint32_t));
+        PF = pfb.as<uint32_t>();
+        RB3_HIP(hipMemcpyAsync(PF, SV, n2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, c.stream));
+    }
 
     // Groups whose members carry different BWT symbols need an order; the
     // tie kernels handle groups of up to 8192 members by size class, prefix
@@ -1725,7 +1899,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_HIP(hipMemsetAsync(gdeep.p, 0, 2 * sizeof(unsigned long long), c.stream));
         RB3_HIP(hipMemsetAsync(gblk.p, 0, 2 * sizeof(unsigned long long), c.stream));
         RB3_LAUNCH("tie_groups", k_tie_groups, grid_for(n2, TG_THREADS * TG_WIN * 16, 2048), dim3(TG_THREADS), 0,
-                   c.stream, SK, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>());
+                   c.stream, SK, SV, srate, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>());
         uint32_t hs2[8];
         unsigned long long ht[4];
         RB3_HIP(hipMemcpyAsync(st.group_hist, ghist.p, sizeof(st.group_hist), hipMemcpyDeviceToHost, c.stream));
@@ -1752,27 +1926,28 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 if (wgs > 2048) wgs = 2048;
                 RB3_LAUNCH("tie_lanes", k_tie_lanes, dim3((unsigned)wgs), dim3(LANES_WG), 0, c.stream,
                            Qc, n2, SV, tl.l[0], (int64_t)hs2[0], tl.l[1], (int64_t)hs2[1],
-                           qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, guard,
+                           qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
                            gtied.as<unsigned long long>() + 1);
                 // the deep list's length stays on the device: a fixed grid loops over it
                 RB3_LAUNCH("tie_deep", k_tie_deep, dim3(1024), dim3(256), 0, c.stream, Qc, n2, SV,
-                           dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, guard, gdeep.as<unsigned long long>());
+                           dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
+                           gdeep.as<unsigned long long>());
             }
             if (hs2[2] > 0)
                 RB3_LAUNCH("tie_walk", k_tie_walk<1>, grid_for(hs2[2], 4 * 8, 1 << 20), dim3(256), 0, c.stream,
-                           Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, guard,
+                           Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, PF, srate, guard,
                            gtied.as<unsigned long long>() + 3);
             if (hs2[3] > 0)
                 RB3_LAUNCH("tie_walk128", k_tie_walk<2>, grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
-                           c.stream, Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, guard,
+                           c.stream, Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
                            gtied.as<unsigned long long>() + 3);
             if (hs2[4] > 0)
                 RB3_LAUNCH("tie_walk256", k_tie_walk<4>, grid_for(hs2[4], 4 * 8, 1 << 20), dim3(256), 0,
-                           c.stream, Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, guard,
+                           c.stream, Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, PF, srate, guard,
                            gtied.as<unsigned long long>() + 3);
             if (hs2[5] > 0)
                 RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
-                           c.stream, Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, guard,
+                           c.stream, Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, PF, srate, guard,
                            gblk.as<unsigned long long>());
             unsigned long long hd[2], hb[2];
             RB3_HIP(hipMemcpyAsync(ht, gtied.p, sizeof(ht), hipMemcpyDeviceToHost, c.stream));
@@ -1868,7 +2043,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
             }
             st.tie_rounds = rounds;
             RB3_LAUNCH("tie_place", k_place, g, dim3(256), 0, c.stream, SV, R.as<uint32_t>(), K.as<uint64_t>(),
-                       n2, SK, guard);
+                       n2, SK, PF, guard);
         }
     }
 
@@ -1883,9 +2058,37 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     RB3_TRY(scan_u32(c, bcnt.as<uint32_t>(), bcnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
     RB3_ALLOC(out_blk, &c, nblk_out * 64);
     RB3_ALLOC(out_sb, &c, num_superblocks(nout) * SB_STRIDE * sizeof(int64_t));
+    DBuf sbits, scnt, sval, sst;
+    if (samples) {
+        RB3_ALLOC(sbits, &c, nblk_out * 2 * sizeof(uint64_t));
+        RB3_ALLOC(scnt, &c, (nblk_out + 1) * sizeof(uint32_t));
+        RB3_HIP(hipMemsetAsync(sbits.p, 0, nblk_out * 2 * sizeof(uint64_t), c.stream));
+        RB3_HIP(hipMemsetAsync(scnt.p, 0, (nblk_out + 1) * sizeof(uint32_t), c.stream));
+    }
     RB3_LAUNCH("interleave", k_interleave, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream,
                (const uint64_t *)b1.blk, num_blocks(n1), SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
-               out_blk.as<uint4>(), guard);
+               out_blk.as<uint4>(), guard, srate, (const uint64_t *)ix.smp_bits, PF,
+               samples ? sbits.as<uint64_t>() : nullptr, samples ? scnt.as<uint32_t>() : nullptr);
+    int64_t nsmp_new = 0;
+    if (samples) {
+        RB3_TRY(scan_u32(c, scnt.as<uint32_t>(), scnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
+        uint32_t tot = 0;
+        RB3_HIP(hipMemcpyAsync(&tot, scnt.as<uint32_t>() + nblk_out, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               c.stream));
+        RB3_HIP(hipStreamSynchronize(c.stream));
+        nsmp_new = tot;
+        std::vector<int64_t> hst(m2 + 1);
+        hst[0] = 0;
+        for (int64_t j = 0; j < m2; ++j) hst[j + 1] = hst[j] + strand_lens[j] + 1;
+        RB3_ALLOC(sst, &c, (m2 + 1) * sizeof(int64_t));
+        RB3_HIP(hipMemcpyAsync(sst.p, hst.data(), (m2 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+        RB3_ALLOC(sval, &c, (nsmp_new > 0 ? nsmp_new : 1) * sizeof(uint64_t));
+        RB3_LAUNCH("smp_values", k_smp_values, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream, SK, PF,
+                   bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift, sbits.as<uint64_t>(), scnt.as<uint32_t>(),
+                   nsmp_new, (const uint64_t *)ix.smp_bits, (const uint32_t *)ix.smp_cnt,
+                   (const uint64_t *)ix.smp_val, ix.nsmp, num_blocks(n1), sst.as<int64_t>(), m2, m1,
+                   sval.as<uint64_t>(), guard);
+    }
     int64_t counts[6];
     RB3_TRY(build_checkpoints(c, out_blk.as<uint4>(), nout, out_sb.as<int64_t>(), new_C, counts));
     int32_t hg = 0;
@@ -1898,6 +2101,15 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     if (counts[0] != m1 + m2) {
         set_error(RB3_EDEVICE, "merged BWT has the wrong number of sentinels");
         return RB3_EDEVICE;
+    }
+    if (samples && smp) {
+        smp->bits = sbits.as<uint64_t>();
+        smp->cnt = scnt.as<uint32_t>();
+        smp->val = sval.as<uint64_t>();
+        smp->nsmp = nsmp_new;
+        sbits.release();
+        scnt.release();
+        sval.release();
     }
     *new_blk = (uint4 *)out_blk.release();
     *new_sb = (int64_t *)out_sb.release();

@@ -186,6 +186,7 @@ struct Ctx {
     int64_t smem_segs = 0;     // SMEM segments to aim for per call; 0 = SMEM_TARGET_SEGS
     int64_t smem_seg_min = 0;  // shortest SMEM segment; 0 = SMEM_SEG_MIN
     int32_t both = 1;
+    int32_t ssa = 0;           // suffix-array sampling distance (0: no samples)
     // Frees are deferred until flush(), called after the stream has drained,
     // so that a caching allocator never hands out memory a queued kernel
     // still uses.
@@ -235,7 +236,8 @@ enum {
     GUARD_RERANK = 4,
     GUARD_COMPACT = 8,
     GUARD_INTERLEAVE = 16,
-    GUARD_PLACE = 32
+    GUARD_PLACE = 32,
+    GUARD_SAMPLE = 64
 };
 
 // Error state: thread-local message for rb3_strerror.
@@ -345,13 +347,46 @@ struct MergeStats {
                                   // or active records summed over doubling rounds
 };
 
+// Suffix-array samples (Sec. 2.4), kept by text position: the suffix at
+// position p of a merge batch is sampled when p is a multiple of the
+// sampling distance s or starts its strand, so every strand has a sample at
+// offset 0 and at least one in any s consecutive positions. A bit per BWT
+// row marks the sampled rows (two words per 128-row block, cnt = samples
+// before each block), and val holds each sampled row's position, in row
+// order, packed as strand << SMP_ID_SHIFT | offset.
+constexpr int SMP_ID_SHIFT = 40;
+constexpr uint64_t SMP_OFF_MASK = (1ull << SMP_ID_SHIFT) - 1;
+constexpr int64_t SMP_MAX_STRANDS = (int64_t)1 << (64 - SMP_ID_SHIFT);
+
+struct DevSmp {
+    const uint64_t *bits;  // 2 per block
+    const uint32_t *cnt;   // blocks + 1 (fewer than 2^32 samples)
+    const uint64_t *val;   // nsmp
+    int64_t nsmp;
+    int32_t rate;
+};
+
 struct IndexData {
     Ctx ctx;
     int64_t n = 0, m = 0;
     int64_t C[6] = {0, 0, 0, 0, 0, 0};
     uint4 *blk = nullptr;  // owned
     int64_t *sb = nullptr; // owned
+    // samples (owned; null when ctx.ssa == 0)
+    uint64_t *smp_bits = nullptr;
+    uint32_t *smp_cnt = nullptr;
+    uint64_t *smp_val = nullptr;
+    int64_t nsmp = 0;
     MergeStats last;
+    DevSmp smp() const {
+        DevSmp s;
+        s.bits = smp_bits;
+        s.cnt = smp_cnt;
+        s.val = smp_val;
+        s.nsmp = nsmp;
+        s.rate = ctx.ssa;
+        return s;
+    }
     DevIndex dev() const {
         DevIndex d;
         d.blk = blk;
@@ -367,8 +402,40 @@ struct IndexData {
 
 // d_Q: the n2 codes of the m2 new strands, each followed by its sentinel
 // (code 0), then 16 zero bytes of padding.
+// With samples (ix.ctx.ssa > 0) the merged index's sample arrays are
+// returned through smp (bits, cnt, val, nsmp); otherwise smp is untouched.
+struct SmpOut {
+    uint64_t *bits = nullptr;
+    uint32_t *cnt = nullptr;
+    uint64_t *val = nullptr;
+    int64_t nsmp = 0;
+};
 int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_lens, int64_t m2,
-               int64_t n2, uint4 **new_blk, int64_t **new_sb, int64_t new_C[6], MergeStats &st);
+               int64_t n2, uint4 **new_blk, int64_t **new_sb, int64_t new_C[6], MergeStats &st,
+               SmpOut *smp);
+
+// Rank of sampled rows before row r (and whether r is sampled): cnt of r's
+// block plus the set bits below r in it. Rows up to n are valid.
+__device__ __forceinline__ bool smp_rank(const DevSmp &s, int64_t r, int64_t *rank) {
+    const int64_t b = r >> BLK_SHIFT;
+    const uint64_t w0 = s.bits[2 * b], w1 = s.bits[2 * b + 1];
+    const int64_t c = (int64_t)s.cnt[b];
+    const int o = (int)(r & (BLK_SYMS - 1));
+    if (o < 64) {
+        *rank = c + __popcll(w0 & low_mask(o));
+        return (w0 >> o) & 1ull;
+    }
+    *rank = c + __popcll(w0) + __popcll(w1 & low_mask(o - 64));
+    return (w1 >> (o - 64)) & 1ull;
+}
+
+// locate.hip
+// Position (strand, offset) of each row: LF steps until a sampled row.
+int locate_rows(Ctx &c, const DevIndex &ix, const DevSmp &sm, const int64_t *d_rows, int64_t n,
+                int64_t *d_strand, int64_t *d_off, int32_t *d_err, unsigned long long *d_steps);
+// One occurrence in each SA interval [lo, hi) (Locate1, Algorithm 2).
+int locate_one(Ctx &c, const DevIndex &ix, const DevSmp &sm, const int64_t *d_lo, const int64_t *d_hi,
+               int64_t n, int64_t *d_strand, int64_t *d_off, int32_t *d_err, unsigned long long *d_steps);
 
 // query.hip
 int count_queries(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *d_qoff,

@@ -30,7 +30,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("both_strands", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN),
                 ("alloc_ctx", ctypes.c_void_p), ("chunk_len", ctypes.c_int64),
-                ("launch_per_string", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("launch_per_string", ctypes.c_int32), ("ssa_rate", ctypes.c_int32)]
 
 
 class SmemRec(ctypes.Structure):
@@ -44,7 +44,8 @@ SMEM_DTYPE = np.dtype([("start", np.int64), ("end", np.int64), ("occ", np.int64)
 assert SMEM_DTYPE.itemsize == ctypes.sizeof(SmemRec) == 48
 
 # Every function declared in include/rb3.h.
-EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats", "rb3_info",
+EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats",
+           "rb3_locate", "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info",
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
            "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats",
            "rb3_server_opts_init", "rb3_server_create", "rb3_server_submit", "rb3_server_poll",
@@ -100,6 +101,10 @@ def lib():
     L.rb3_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, ctypes.POINTER(SmemRec), _i64, _i64p]
     L.rb3_info.argtypes = [_vp, _i64p, _i64p, _i64p]
     L.rb3_last_smem_stats.argtypes = [_i64p]
+    L.rb3_locate.argtypes = [_vp, _vp, _i64, _i32, _i64p, _i64p]
+    L.rb3_locate1.argtypes = [_vp, _vp, _vp, _i64, _i32, _i64p, _i64p]
+    L.rb3_ssa_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), _i64p]
+    L.rb3_last_locate_stats.argtypes = [_i64p]
     L.rb3_export.argtypes = [_vp, _vp]
     L.rb3_import.argtypes = [ctypes.POINTER(Opts), _vp, _i64, _i32, ctypes.POINTER(_vp)]
     L.rb3_clone.argtypes = [_vp, ctypes.POINTER(_vp)]
@@ -125,7 +130,8 @@ def lib():
     for name in ("rb3_server_create", "rb3_server_submit", "rb3_server_poll", "rb3_server_stats",
                  "rb3_server_replay"):
         getattr(L, name).restype = ctypes.c_int
-    for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats", "rb3_info", "rb3_export",
+    for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats", "rb3_locate",
+                 "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info", "rb3_export",
                  "rb3_import", "rb3_clone", "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read",
                  "rb3_merge_stats"):
         getattr(L, name).restype = ctypes.c_int
@@ -153,6 +159,20 @@ def _buffer(x):
     if isinstance(x, (bytes, bytearray)):
         x = np.frombuffer(x, dtype=np.uint8)
     a = np.ascontiguousarray(x, dtype=np.uint8)
+    return (a.ctypes.data if a.size else None), a.size, RB3_MEM_HOST, a
+
+
+def _i64buf(x):
+    """(pointer, count, mem, keepalive) of an int64 host array or GPU tensor."""
+    if hasattr(x, "is_cuda") and hasattr(x, "data_ptr") and x.is_cuda:
+        import torch
+        if x.dtype != torch.int64 or not x.is_contiguous():
+            raise ValueError("device rows must be a contiguous int64 tensor")
+        torch.cuda.current_stream(x.device).synchronize()
+        return x.data_ptr(), x.numel(), RB3_MEM_DEVICE, x
+    if hasattr(x, "numpy"):
+        x = x.numpy()
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.int64))
     return (a.ctypes.data if a.size else None), a.size, RB3_MEM_HOST, a
 
 
@@ -192,7 +212,7 @@ class TorchAllocator:
 
 
 def make_opts(both_strands: bool = True, device: int = 0, stream=None, allocator: TorchAllocator | None = None,
-              chunk_len: int = 0, launch_per_string: bool = False) -> Opts:
+              chunk_len: int = 0, launch_per_string: bool = False, ssa_rate: int = 0) -> Opts:
     o = Opts()
     lib().rb3_opts_init(ctypes.byref(o))
     o.both_strands = 1 if both_strands else 0
@@ -206,6 +226,7 @@ def make_opts(both_strands: bool = True, device: int = 0, stream=None, allocator
         o.dev_free = allocator.free_fn
     o.chunk_len = int(chunk_len)
     o.launch_per_string = 1 if launch_per_string else 0
+    o.ssa_rate = int(ssa_rate)
     return o
 
 
@@ -250,6 +271,15 @@ class Index:
     def info(self):
         return rb3_info(self)
 
+    def locate(self, rows):
+        return rb3_locate(self, rows)
+
+    def locate1(self, lo, hi):
+        return rb3_locate1(self, lo, hi)
+
+    def ssa_info(self):
+        return rb3_ssa_info(self)
+
     def export(self) -> np.ndarray:
         return rb3_export(self)
 
@@ -262,8 +292,8 @@ class Index:
 
 def rb3_build(seq, lens, both_strands: bool = True, device: int = 0, stream=None,
               allocator: TorchAllocator | None = None, chunk_len: int = 0,
-              launch_per_string: bool = False) -> Index:
-    o = make_opts(both_strands, device, stream, allocator, chunk_len, launch_per_string)
+              launch_per_string: bool = False, ssa_rate: int = 0) -> Index:
+    o = make_opts(both_strands, device, stream, allocator, chunk_len, launch_per_string, ssa_rate)
     ptr, _, mem, keep = _buffer(seq)
     la, lp = _lens(lens)
     h = ctypes.c_void_p()
@@ -307,6 +337,42 @@ def rb3_smem(idx: Index, q, qlens, min_len: int, min_occ: int = 1, cap: int | No
             continue
         _check(rc)
         return out[:off[-1]], off
+
+
+def rb3_locate(idx: Index, rows):
+    """(strand, offset) arrays: the position of the suffix at each row."""
+    ptr, n, mem, keep = _i64buf(rows)
+    st = np.zeros(max(n, 1), np.int64)
+    off = np.zeros(max(n, 1), np.int64)
+    _check(lib().rb3_locate(idx.handle, ptr, n, mem, st.ctypes.data_as(_i64p), off.ctypes.data_as(_i64p)))
+    return st[:n], off[:n]
+
+
+def rb3_locate1(idx: Index, lo, hi):
+    """(strand, offset) arrays: one occurrence in each SA interval [lo, hi)."""
+    plo, n, mem, k1 = _i64buf(lo)
+    phi, n2, mem2, k2 = _i64buf(hi)
+    if n != n2 or mem != mem2:
+        raise ValueError("lo and hi must have the same length and memory kind")
+    st = np.zeros(max(n, 1), np.int64)
+    off = np.zeros(max(n, 1), np.int64)
+    _check(lib().rb3_locate1(idx.handle, plo, phi, n, mem, st.ctypes.data_as(_i64p), off.ctypes.data_as(_i64p)))
+    return st[:n], off[:n]
+
+
+def rb3_ssa_info(idx: Index):
+    """(sampling distance, number of samples)."""
+    r = ctypes.c_int32()
+    k = ctypes.c_int64()
+    _check(lib().rb3_ssa_info(idx.handle, ctypes.byref(r), ctypes.byref(k)))
+    return r.value, k.value
+
+
+def rb3_last_locate_stats() -> dict:
+    """Work of this thread's last rb3_locate / rb3_locate1 call."""
+    e = ctypes.c_int64()
+    _check(lib().rb3_last_locate_stats(ctypes.byref(e)))
+    return {"lf_steps": e.value}
 
 
 def rb3_last_smem_stats() -> dict:
