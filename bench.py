@@ -302,6 +302,130 @@ def plain_vs_batched(b1_strings, new, chunk: int, k: int):
     return out
 
 
+def locate_bench(args):
+    """Locate on the pangenome index of the default workload (32 + 32
+    haplotypes of a 4 Mb genome, both strands, 512 M symbols) with
+    suffix-array samples every 32 positions: the index is built from the
+    first 32 haplotypes and the other 32 are merged in (the merge keeps the
+    samples; its time with samples is reported), then rows drawn uniformly
+    are located (value: located rows/s), and Locate1 returns one occurrence
+    for the SA interval of each of 100,000 25-mers cut from the haplotypes.
+    Inputs are device-resident before timing."""
+    import torch
+    import synth
+    from paper_2409_00613_amd import rb3
+    rate = args.ssa
+    w = synth.config_pangenome(genome_len=args.genome)
+    alloc = rb3.TorchAllocator(0)
+    idx = rb3.rb3_build(w.b1.data, w.b1.lens, allocator=alloc, ssa_rate=rate)
+    plain = rb3.rb3_build(w.b1.data, w.b1.lens, allocator=alloc)
+    new_dev = torch.from_numpy(w.new.data).cuda()
+    torch.cuda.synchronize()
+    merge_ms = {}
+    for name, ix in (("with_samples", idx), ("without_samples", plain)):
+        t0 = time.perf_counter()
+        ix.merge(new_dev, w.new.lens)
+        torch.cuda.synchronize()
+        merge_ms[name] = round((time.perf_counter() - t0) * 1e3, 2)
+    plain.close()
+    n, m, _ = idx.info()
+    r_, nsmp = idx.ssa_info()
+    log(f"index n={n}, {nsmp} samples (distance {rate}); merge of the second 32 haplotypes: "
+        f"{merge_ms['with_samples']} ms with samples, {merge_ms['without_samples']} ms without")
+    g = torch.Generator(device="cpu").manual_seed(7)
+    nrows = args.locate_rows
+    rows = torch.randint(0, n, (nrows,), generator=g, dtype=torch.int64).cuda()
+    torch.cuda.synchronize()
+    idx.locate(rows)  # warm-up
+    rb3.rb3_prof_reset()
+    rb3.rb3_prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        idx.locate(rows)
+    t1 = time.perf_counter()
+    rb3.rb3_prof_enable(False)
+    prof = rb3.rb3_prof_read()
+    steps_lf = rb3.rb3_last_locate_stats()["lf_steps"]
+    k_ms = prof.get("locate", (0, 0.0))[1] / args.steps
+    rate_rows = nrows * args.steps / (t1 - t0)
+    # per LF step: the row's 64-byte block, its 16 bytes of sample words and
+    # 4-byte block count; per row: its index in, the final sample test, the
+    # 8-byte sample value and the 16-byte answer out
+    ab = steps_lf * (BLOCK_BYTES + 16 + 4) + nrows * (8 + 20 + 8 + 16)
+    ach = ab / (k_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
+    log(f"locate: {rate_rows / 1e6:.1f} M rows/s ({steps_lf / nrows:.2f} LF steps per row), "
+        f"kernel {k_ms:.2f} ms per {nrows} rows")
+    # Locate1 on the intervals of 25-mers cut from the haplotypes
+    rnd = np.random.default_rng(11)
+    allst = w.b1 + w.new
+    pats = []
+    for _ in range(args.locate1_queries):
+        sidx = int(rnd.integers(0, allst.n))
+        s_ = allst.get(sidx)
+        a = int(rnd.integers(0, len(s_) - 25))
+        pats.append(s_[a:a + 25])
+    q = synth.pack(pats)
+    lo, hi = idx.count(q.data, q.lens)
+    lo_d, hi_d = torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()
+    torch.cuda.synchronize()
+    idx.locate1(lo_d, hi_d)  # warm-up
+    rb3.rb3_prof_reset()
+    rb3.rb3_prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        idx.locate1(lo_d, hi_d)
+    t1 = time.perf_counter()
+    rb3.rb3_prof_enable(False)
+    prof1 = rb3.rb3_prof_read()
+    l1_steps = rb3.rb3_last_locate_stats()["lf_steps"]
+    l1_ms = prof1.get("locate1", (0, 0.0))[1] / args.steps
+    l1_rate = len(pats) * args.steps / (t1 - t0)
+    occ = hi - lo
+    log(f"locate1: {l1_rate / 1e6:.2f} M intervals/s, {l1_steps / len(pats):.2f} rank-all steps per interval "
+        f"(mean occurrences {occ.mean():.1f}), kernel {l1_ms:.2f} ms per {len(pats)} intervals")
+    idx.close()
+    out = {"metric": "located rows/s", "value": round(rate_rows, 1), "unit": "rows/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": round((t1 - t0) / args.steps * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+           "data": "synthetic",
+           "config": {"workload": "locate", "genome_len": args.genome, "haplotypes": 64, "both_strands": True,
+                      "n": n, "ssa_rate": rate, "samples": nsmp, "rows": nrows,
+                      "locate1_intervals": len(pats), "locate1_pattern_len": 25},
+           "roofline": {"bound": "hbm", "kernel": "locate", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "traffic": read_traffic("locate", "locate", kernel_source_hash()),
+                        "algorithmic_bytes_per_launch": ab, "avg_launch_ms": k_ms,
+                        "lf_steps_per_row": round(steps_lf / nrows, 3)},
+           "locate1": {"intervals_per_s": round(l1_rate, 1), "kernel_ms": round(l1_ms, 3),
+                       "rank_all_steps_per_interval": round(l1_steps / len(pats), 3),
+                       "mean_occurrences": round(float(occ.mean()), 2)},
+           "merge_ms": merge_ms, "source_hash": kernel_source_hash()}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = locate_cpu_baseline(args.cpu_sample)
+    return out
+
+
+def locate_cpu_baseline(sample_len: int):
+    """The oracle on a bounded sample of the same workload: every haplotype
+    cut to its first sample_len bases; the oracle sorts every suffix to get
+    the suffix array and reads each row's position from it. Reported as
+    located rows per second over the whole sample."""
+    import oracle
+    import synth
+    w = synth.config_pangenome(genome_len=sample_len + 200, n_b1=32, n_new=32)
+    cut = lambda s: synth.pack([x[:sample_len] for x in s.as_list()])
+    allst = cut(w.b1) + cut(w.new)
+    codes, lens = oracle.expand(allst.data, allst.lens)
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    _, S = oracle.bwt(codes, lens, nthreads=threads, want_sa=True)
+    j, off = oracle.locate(S, lens, np.arange(S.shape[0]))
+    dt = time.perf_counter() - t0
+    return {"value": round(S.shape[0] / dt, 1), "unit": "rows/s", "cores": threads, "kind": "oracle",
+            "sample": f"suffix sort of the 64 haplotypes cut to their first {sample_len} bases "
+                      f"({S.shape[0]} rows), then every row located; {dt:.2f} s"}
+
+
 def incremental_bench(args):
     """Large incremental build: 100 haplotypes of a 100 Mb genome with
     segmental duplications, merged 10 at a time (the first batch is a build
@@ -385,15 +509,19 @@ def main():
     ap.add_argument("--smem-batched-only", action="store_true",
                     help="SMEM: the batched calls only (no per-query calls, no served latency); for counter runs")
     ap.add_argument("--workload", default="pangenome_merge",
-                    choices=["pangenome_merge", "uneven_merge", "incremental", "serving"],
+                    choices=["pangenome_merge", "uneven_merge", "incremental", "serving", "locate"],
                     help="pangenome_merge: 32 haplotypes into 32 (default); uneven_merge: 10,000 "
                          "log-normal contigs and 2 chromosomes into the same index, plus the plain "
                          "one-launch-per-string form on a sample; incremental: 100 haplotypes of a "
                          "100 Mb genome merged in 10 batches; serving: the full serving configuration "
-                         "(320 haplotypes) only")
+                         "(320 haplotypes) only; locate: rows located and Locate1 on the pangenome "
+                         "index with suffix-array samples")
     ap.add_argument("--plain-strings", type=int, default=200,
                     help="uneven_merge: input strings in the plain-vs-batched sample")
     ap.add_argument("--batches", type=int, default=10, help="incremental: number of batches")
+    ap.add_argument("--ssa", type=int, default=32, help="locate: suffix-array sampling distance")
+    ap.add_argument("--locate-rows", type=int, default=4_000_000, help="locate: rows per call")
+    ap.add_argument("--locate1-queries", type=int, default=100_000, help="locate: Locate1 intervals per call")
 
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (three times) and exit; "
@@ -431,6 +559,10 @@ def main():
         return
     if args.workload == "incremental":
         res = incremental_bench(args)
+        print(json.dumps(res), flush=True)
+        return
+    if args.workload == "locate":
+        res = locate_bench(args)
         print(json.dumps(res), flush=True)
         return
     workload = args.workload
