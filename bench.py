@@ -322,12 +322,20 @@ def locate_bench(args):
     new_dev = torch.from_numpy(w.new.data).cuda()
     torch.cuda.synchronize()
     merge_ms = {}
+    merge_kernels = {}
     for name, ix in (("with_samples", idx), ("without_samples", plain)):
+        rb3.rb3_prof_reset()
+        rb3.rb3_prof_enable(True)
         t0 = time.perf_counter()
         ix.merge(new_dev, w.new.lens)
         torch.cuda.synchronize()
         merge_ms[name] = round((time.perf_counter() - t0) * 1e3, 2)
+        rb3.rb3_prof_enable(False)
+        merge_kernels[name] = {k: round(v[1], 3) for k, v in rb3.rb3_prof_read().items() if v[1] >= 0.2}
     plain.close()
+    for k in sorted(merge_kernels["with_samples"], key=lambda k: -merge_kernels["with_samples"][k])[:10]:
+        log(f"  merge kernel {k:16s} {merge_kernels['with_samples'][k]:8.2f} ms with samples, "
+            f"{merge_kernels['without_samples'].get(k, 0.0):8.2f} ms without")
     n, m, _ = idx.info()
     r_, nsmp = idx.ssa_info()
     log(f"index n={n}, {nsmp} samples (distance {rate}); merge of the second 32 haplotypes: "
@@ -399,7 +407,7 @@ def locate_bench(args):
            "locate1": {"intervals_per_s": round(l1_rate, 1), "kernel_ms": round(l1_ms, 3),
                        "rank_all_steps_per_interval": round(l1_steps / len(pats), 3),
                        "mean_occurrences": round(float(occ.mean()), 2)},
-           "merge_ms": merge_ms, "source_hash": kernel_source_hash()}
+           "merge_ms": merge_ms, "merge_kernels_ms": merge_kernels, "source_hash": kernel_source_hash()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = locate_cpu_baseline(args.cpu_sample)
     return out

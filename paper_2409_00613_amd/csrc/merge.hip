@@ -520,11 +520,13 @@ struct TieLists {
     uint32_t *l[TG_CLASSES];
 };
 
+template <bool SMP>
 __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__restrict__ SK,
                                                            const uint32_t *__restrict__ SV, int32_t srate, int64_t n,
                                                            TieLists lists, uint32_t *__restrict__ gstat,
                                                            unsigned long long *__restrict__ tied,
                                                            uint32_t *__restrict__ ghist) {
+    const int32_t sr = SMP ? srate : 0;  // 0: the variant without samples
     __shared__ uint32_t lst[TG_CLASSES][TG_LCAP][2];
     __shared__ uint32_t hist[32];
     __shared__ uint32_t lcnt[TG_CLASSES];
@@ -549,7 +551,7 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
         for (int j = 0; j <= TG_WIN; ++j) {
             const int64_t sj = wbase + (int64_t)j * 64 + lane;
             vw[j] = sj < n ? SK[sj] : ~0ull;
-            pw[j] = (srate > 0 && sj < n) ? SV[sj] : 1u;
+            pw[j] = (sr > 0 && sj < n) ? SV[sj] : 1u;
         }
         uint64_t carry = (wbase > 0 && wbase < n) ? (SK[wbase - 1] >> 3) : ~0ull;  // key before the first window
 #pragma unroll
@@ -572,7 +574,7 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
             const uint64_t below = smask & low_mask(lane + 1);
             const int lead = below ? 63 - __clzll((long long)below) : -1;
             const uint32_t le = __shfl(e, lead < 0 ? 0 : lead);
-            const bool mism = in && lead >= 0 && (e != le || sampled_pos(pw[j], e, srate));
+            const bool mism = in && lead >= 0 && (e != le || sampled_pos(pw[j], e, sr));
             const uint64_t mmask = __ballot(mism);
             // the window's last group may run past its end: the whole wave
             // extends it with coalesced 64-key reads of the following windows
@@ -590,12 +592,12 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
                     const uint64_t mm = __ballot((uv >> 3) == xkey);
                     const int run = ~mm ? __ffsll((unsigned long long)~mm) - 1 : 64;
                     const uint32_t ue = (uint32_t)(uv & 7);
-                    if (__ballot(lane < run && (ue != xe || sampled_pos(up, ue, srate)))) xuni = false;
+                    if (__ballot(lane < run && (ue != xe || sampled_pos(up, ue, sr)))) xuni = false;
                     ext += run;
                     if (run < 64) break;
                     t += 64;
                     uv = t + lane < n ? SK[t + lane] : ~0ull;
-                    up = (srate > 0 && t + lane < n) ? SV[t + lane] : 1u;
+                    up = (sr > 0 && t + lane < n) ? SV[t + lane] : 1u;
                 }
             }
             if (start && !sent) {
@@ -703,6 +705,7 @@ constexpr int LANES_MAX_DEPTH = 1024;  // symbols
 // wave refill), so no lane idles while a neighbour walks a deep group. The
 // queue is the pair list (entries 0..np) followed by the 3..8 list. Members
 // are held in registers; every loop over them is unrolled.
+template <bool SMP>
 __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restrict__ Q, int64_t n2,
                                                         const uint32_t *__restrict__ SV,
                                                         const uint32_t *__restrict__ plist, int64_t np,
@@ -712,6 +715,7 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restric
                                                         uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
                                                         int32_t srate, int32_t *__restrict__ guard,
                                                         unsigned long long *__restrict__ reads) {
+    const int32_t sr = SMP ? srate : 0;  // 0: the variant without samples
     const int lane = threadIdx.x & 63;
     const int64_t total = np + ns;
     uint64_t steps = 0;
@@ -825,7 +829,7 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restric
                 for (int j = 0; j < SMALL_MAXK; ++j) {
                     bool same = act[j] && nsb[j] == nsb[i];
                     cnt += same ? 1u : 0u;
-                    uni &= !same || (e[j] == e[i] && !sampled_pos(pos[j], e[j], srate));
+                    uni &= !same || (e[j] == e[i] && !sampled_pos(pos[j], e[j], sr));
                 }
                 nact[i] = act[i] && cnt >= 2 && !uni;
                 any |= nact[i];
@@ -843,7 +847,7 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restric
             for (int i = 0; i < SMALL_MAXK; ++i)
                 if (i < k) {
                     SK[gs + o[i]] = gkey | e[i];
-                    if (PF) PF[gs + o[i]] = pos[i];
+                    if (SMP && PF) PF[gs + o[i]] = pos[i];
                 }
             busy = false;
             maxdepth = (uint32_t)d0 > maxdepth ? (uint32_t)d0 : maxdepth;
@@ -880,6 +884,7 @@ constexpr int DEEP_DPL = 4;  // depths per lane per window
 // covers 4W depths. The wave finds the first depth where some subgroup
 // splits, applies the same refinement as k_tie_lanes there (all lanes keep
 // the same copy of the members' state), and goes on from the next depth.
+template <bool SMP>
 __global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ dlist,
@@ -887,6 +892,7 @@ __global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__
                                                   uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
                                                   int32_t srate, int32_t *__restrict__ guard,
                                                   unsigned long long *__restrict__ reads) {
+    const int32_t sr = SMP ? srate : 0;  // 0: the variant without samples
     const int lane = threadIdx.x & 63;
     int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -1013,7 +1019,7 @@ __global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__
                     for (int j = 0; j < SMALL_MAXK; ++j) {
                         bool same = act[j] && nsb[j] == nsb[i];
                         cnt += same ? 1u : 0u;
-                        uni &= !same || (e[j] == e[i] && !sampled_pos(pos[j], e[j], srate));
+                        uni &= !same || (e[j] == e[i] && !sampled_pos(pos[j], e[j], sr));
                         if (same && no[j] == nsb[i]) ld = (uint32_t)j;
                     }
                     nact[i] = act[i] && cnt >= 2 && !uni;
@@ -1049,7 +1055,7 @@ __global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__
                     pp = pos[i];
                 }
             SK[gs + oo] = gkey | ee;
-            if (PF) PF[gs + oo] = pp;
+            if (SMP && PF) PF[gs + oo] = pp;
         }
     }
     if (lane == 0 && steps) atomicAdd(reads, (unsigned long long)steps);
@@ -1077,13 +1083,14 @@ __device__ __forceinline__ uint64_t lane_read64(uint64_t v, int l) {
 // Members of a group share their sort key except for its symbol bits, so
 // the symbols come from the group's run of sorted keys (coalesced). The next
 // group's members are fetched while the current one is walked.
-template <int MPL>
+template <int MPL, bool SMP>
 __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ glist, int64_t ng,
                                                   uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
                                                   int32_t srate, int32_t *__restrict__ guard,
                                                   unsigned long long *__restrict__ reads) {
+    const int32_t sr = SMP ? srate : 0;  // 0: the variant without samples
     constexpr uint32_t MAXK = 64 * MPL;
     const int lane = threadIdx.x & 63;
     const uint64_t below = low_mask(lane);
@@ -1219,7 +1226,7 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q,
                             less += (uint32_t)__popcll(
                                 __ballot(same && (kk[s] < kL || (kk[s] == kL && sent[s] && p[s] < pL))));
                             cnt += (uint32_t)__popcll(m[s]);
-                            uni &= (__ballot(e[s] == eL && !sampled_pos(p[s], e[s], srate)) & m[s]) == m[s];
+                            uni &= (__ballot(e[s] == eL && !sampled_pos(p[s], e[s], sr)) & m[s]) == m[s];
                         }
                         const uint32_t base = subL + less;
                         uint32_t pre = 0;
@@ -1248,7 +1255,7 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q,
         for (int s = 0; s < MPL; ++s)
             if ((uint32_t)(s * 64 + lane) < k) {
                 SK[gs + o[s]] = key[s];
-                if (PF) PF[gs + o[s]] = p[s];
+                if (SMP && PF) PF[gs + o[s]] = p[s];
             }
     }
     const uint64_t tot = wave_sum_u64(steps);
@@ -1265,12 +1272,13 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q,
 // their new places, measures the new subgroups and keeps only those whose
 // members carry different symbols. A split moves members, so the round ends
 // there and the next one loads from the following depth.
-template <int T, int MPT, int DEPTHS>
+template <int T, int MPT, int DEPTHS, bool SMP>
 __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, int64_t n2, const uint32_t *__restrict__ SV,
                                                  const uint32_t *__restrict__ glist, int64_t ng,
                                                  uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
                                                  int32_t srate, int32_t *__restrict__ guard,
                                                  unsigned long long *__restrict__ stat) {
+    const int32_t sr = SMP ? srate : 0;  // 0: the variant without samples
     constexpr int MAXK = T * MPT;
     static_assert(MAXK <= 65535, "places must fit 16 bits");
     __shared__ uint64_t sc[MAXK];   // chunk at the current depth
@@ -1387,10 +1395,10 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, 
                     const int o = tid + j * T;
                     if (o < k && sact[o] && ssub[o] == o) {
                         const uint8_t e0 = se[o];
-                        bool uni = !sampled_pos(spos[o], e0, srate);
+                        bool uni = !sampled_pos(spos[o], e0, sr);
                         int x = o + 1;
                         while (x < k && ssub[x] == o) {
-                            uni &= se[x] == e0 && !sampled_pos(spos[x], se[x], srate);
+                            uni &= se[x] == e0 && !sampled_pos(spos[x], se[x], sr);
                             ++x;
                         }
                         ssz[o] = (uint16_t)(x - o);
@@ -1419,7 +1427,7 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, 
         // every thread read gkey before the first barrier of this group
         for (int o = tid; o < k; o += T) {
             SK[gs + o] = gkey | se[o];
-            if (PF) PF[gs + o] = spos[o];
+            if (SMP && PF) PF[gs + o] = spos[o];
         }
         __syncthreads();
     }
@@ -1481,6 +1489,7 @@ __global__ void k_block_count(const uint64_t *__restrict__ SK, int64_t n2, int64
 // (lanes 12..15 hold the old blocks' sample words), a new row is sampled
 // when its position in the batch is a multiple of srate or starts a strand
 // (its BWT symbol is $).
+template <bool SMP>
 __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__ b1words, int64_t nblk1,
                                                     const uint64_t *__restrict__ SK,
                                                     const uint32_t *__restrict__ bs, int64_t nout,
@@ -1489,6 +1498,7 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
                                                     int32_t srate, const uint64_t *__restrict__ obits,
                                                     const uint32_t *__restrict__ PF,
                                                     uint64_t *__restrict__ nbits, uint32_t *__restrict__ ncnt) {
+    const int32_t sr = SMP ? srate : 0;  // 0: the variant without samples
     __shared__ uint8_t slot[4][128];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -1518,7 +1528,7 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
             if (lane < 12) {
                 const int64_t ib = ib0 + lane / 6;
                 if (ib <= ((i0 + nold - 1) >> BLK_SHIFT) && ib < nblk1) wd = b1words[ib * 8 + lane % 6];
-            } else if (srate > 0 && lane < 16) {
+            } else if (sr > 0 && lane < 16) {
                 const int64_t ib = ib0 + ((lane - 12) >> 1);
                 if (ib <= ((i0 + nold - 1) >> BLK_SHIFT) && ib < nblk1) wd = obits[ib * 2 + (lane & 1)];
             }
@@ -1526,8 +1536,8 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
         const uint32_t ka = s0 + (uint32_t)lane, kb = ka + 64u;
         const uint64_t keya = ka < s1 ? SK[ka] : 0ull;
         const uint64_t keyb = kb < s1 ? SK[kb] : 0ull;
-        const uint32_t pa = (srate > 0 && ka < s1) ? PF[ka] : 1u;
-        const uint32_t pb = (srate > 0 && kb < s1) ? PF[kb] : 1u;
+        const uint32_t pa = (sr > 0 && ka < s1) ? PF[ka] : 1u;
+        const uint32_t pb = (sr > 0 && kb < s1) ? PF[kb] : 1u;
         slot[wv][lane] = 0;
         slot[wv][lane + 64] = 0;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1535,14 +1545,14 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
         if (ka < s1) {
             const int64_t M = (int64_t)(keya >> lshift) + m1 + ka;
             const uint32_t ea = (uint32_t)(keya & 7);
-            const uint32_t sa = (srate > 0 && (pa % (uint32_t)srate == 0u || ea == 0u)) ? 0x40u : 0u;
+            const uint32_t sa = (sr > 0 && (pa % (uint32_t)sr == 0u || ea == 0u)) ? 0x40u : 0u;
             if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | sa | ea);
             else atomicOr(guard, GUARD_INTERLEAVE);
         }
         if (kb < s1) {
             const int64_t M = (int64_t)(keyb >> lshift) + m1 + kb;
             const uint32_t eb = (uint32_t)(keyb & 7);
-            const uint32_t sb = (srate > 0 && (pb % (uint32_t)srate == 0u || eb == 0u)) ? 0x40u : 0u;
+            const uint32_t sb = (sr > 0 && (pb % (uint32_t)sr == 0u || eb == 0u)) ? 0x40u : 0u;
             if (M >= P0 && M < P0 + 128) slot[wv][M - P0] = (uint8_t)(0x80u | sb | eb);
             else atomicOr(guard, GUARD_INTERLEAVE);
         }
@@ -1578,7 +1588,7 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
                 c1 = (uint32_t)((b0w >> bb) & 1u) | (uint32_t)(((b1w >> bb) & 1u) << 1) |
                      (uint32_t)(((b2w >> bb) & 1u) << 2);
         }
-        if (srate > 0) {
+        if (sr > 0) {
             // old rows' sample bits, with every lane active for the shuffles
             const uint64_t swa = __shfl(wd, 12 + 2 * (oka ? sela : 0) + (int)((ia >> 6) & 1));
             const uint64_t swb = __shfl(wd, 12 + 2 * (okb ? selb : 0) + (int)((ib >> 6) & 1));
@@ -1898,8 +1908,12 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_HIP(hipMemsetAsync(gtied.p, 0, 4 * sizeof(unsigned long long), c.stream));
         RB3_HIP(hipMemsetAsync(gdeep.p, 0, 2 * sizeof(unsigned long long), c.stream));
         RB3_HIP(hipMemsetAsync(gblk.p, 0, 2 * sizeof(unsigned long long), c.stream));
-        RB3_LAUNCH("tie_groups", k_tie_groups, grid_for(n2, TG_THREADS * TG_WIN * 16, 2048), dim3(TG_THREADS), 0,
-                   c.stream, SK, SV, srate, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>());
+        if (samples)
+            RB3_LAUNCH("tie_groups", k_tie_groups<true>, grid_for(n2, TG_THREADS * TG_WIN * 16, 2048), dim3(TG_THREADS), 0,
+                       c.stream, SK, SV, srate, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>());
+        else
+            RB3_LAUNCH("tie_groups", k_tie_groups<false>, grid_for(n2, TG_THREADS * TG_WIN * 16, 2048), dim3(TG_THREADS), 0,
+                       c.stream, SK, SV, srate, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>());
         uint32_t hs2[8];
         unsigned long long ht[4];
         RB3_HIP(hipMemcpyAsync(st.group_hist, ghist.p, sizeof(st.group_hist), hipMemcpyDeviceToHost, c.stream));
@@ -1924,31 +1938,66 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 // persistent: enough waves to fill the chip, no more than the work
                 int64_t wgs = (nq + LANES_WG - 1) / LANES_WG;
                 if (wgs > 2048) wgs = 2048;
-                RB3_LAUNCH("tie_lanes", k_tie_lanes, dim3((unsigned)wgs), dim3(LANES_WG), 0, c.stream,
-                           Qc, n2, SV, tl.l[0], (int64_t)hs2[0], tl.l[1], (int64_t)hs2[1],
-                           qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
-                           gtied.as<unsigned long long>() + 1);
+                if (samples)
+                    RB3_LAUNCH("tie_lanes", k_tie_lanes<true>, dim3((unsigned)wgs), dim3(LANES_WG), 0, c.stream,
+                               Qc, n2, SV, tl.l[0], (int64_t)hs2[0], tl.l[1], (int64_t)hs2[1],
+                               qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 1);
+                else
+                    RB3_LAUNCH("tie_lanes", k_tie_lanes<false>, dim3((unsigned)wgs), dim3(LANES_WG), 0, c.stream,
+                               Qc, n2, SV, tl.l[0], (int64_t)hs2[0], tl.l[1], (int64_t)hs2[1],
+                               qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 1);
                 // the deep list's length stays on the device: a fixed grid loops over it
-                RB3_LAUNCH("tie_deep", k_tie_deep, dim3(1024), dim3(256), 0, c.stream, Qc, n2, SV,
-                           dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
-                           gdeep.as<unsigned long long>());
+                if (samples)
+                    RB3_LAUNCH("tie_deep", k_tie_deep<true>, dim3(1024), dim3(256), 0, c.stream, Qc, n2, SV,
+                               dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
+                               gdeep.as<unsigned long long>());
+                else
+                    RB3_LAUNCH("tie_deep", k_tie_deep<false>, dim3(1024), dim3(256), 0, c.stream, Qc, n2, SV,
+                               dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
+                               gdeep.as<unsigned long long>());
             }
-            if (hs2[2] > 0)
-                RB3_LAUNCH("tie_walk", k_tie_walk<1>, grid_for(hs2[2], 4 * 8, 1 << 20), dim3(256), 0, c.stream,
-                           Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, PF, srate, guard,
-                           gtied.as<unsigned long long>() + 3);
-            if (hs2[3] > 0)
-                RB3_LAUNCH("tie_walk128", k_tie_walk<2>, grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
-                           c.stream, Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
-                           gtied.as<unsigned long long>() + 3);
-            if (hs2[4] > 0)
-                RB3_LAUNCH("tie_walk256", k_tie_walk<4>, grid_for(hs2[4], 4 * 8, 1 << 20), dim3(256), 0,
-                           c.stream, Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, PF, srate, guard,
-                           gtied.as<unsigned long long>() + 3);
-            if (hs2[5] > 0)
-                RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
-                           c.stream, Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, PF, srate, guard,
-                           gblk.as<unsigned long long>());
+            if (hs2[2] > 0) {
+                if (samples)
+                    RB3_LAUNCH("tie_walk", (k_tie_walk<1, true>), grid_for(hs2[2], 4 * 8, 1 << 20), dim3(256), 0, c.stream,
+                               Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 3);
+                else
+                    RB3_LAUNCH("tie_walk", (k_tie_walk<1, false>), grid_for(hs2[2], 4 * 8, 1 << 20), dim3(256), 0, c.stream,
+                               Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 3);
+            }
+            if (hs2[3] > 0) {
+                if (samples)
+                    RB3_LAUNCH("tie_walk128", (k_tie_walk<2, true>), grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
+                               c.stream, Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 3);
+                else
+                    RB3_LAUNCH("tie_walk128", (k_tie_walk<2, false>), grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
+                               c.stream, Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 3);
+            }
+            if (hs2[4] > 0) {
+                if (samples)
+                    RB3_LAUNCH("tie_walk256", (k_tie_walk<4, true>), grid_for(hs2[4], 4 * 8, 1 << 20), dim3(256), 0,
+                               c.stream, Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 3);
+                else
+                    RB3_LAUNCH("tie_walk256", (k_tie_walk<4, false>), grid_for(hs2[4], 4 * 8, 1 << 20), dim3(256), 0,
+                               c.stream, Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 3);
+            }
+            if (hs2[5] > 0) {
+                if (samples)
+                    RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1, true>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
+                               c.stream, Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, PF, srate, guard,
+                               gblk.as<unsigned long long>());
+                else
+                    RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1, false>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
+                               c.stream, Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, PF, srate, guard,
+                               gblk.as<unsigned long long>());
+            }
             unsigned long long hd[2], hb[2];
             RB3_HIP(hipMemcpyAsync(ht, gtied.p, sizeof(ht), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipMemcpyAsync(hd, gdeep.p, sizeof(hd), hipMemcpyDeviceToHost, c.stream));
@@ -2065,10 +2114,16 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_HIP(hipMemsetAsync(sbits.p, 0, nblk_out * 2 * sizeof(uint64_t), c.stream));
         RB3_HIP(hipMemsetAsync(scnt.p, 0, (nblk_out + 1) * sizeof(uint32_t), c.stream));
     }
-    RB3_LAUNCH("interleave", k_interleave, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream,
-               (const uint64_t *)b1.blk, num_blocks(n1), SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
-               out_blk.as<uint4>(), guard, srate, (const uint64_t *)ix.smp_bits, PF,
-               samples ? sbits.as<uint64_t>() : nullptr, samples ? scnt.as<uint32_t>() : nullptr);
+    if (samples)
+        RB3_LAUNCH("interleave", k_interleave<true>, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream,
+                   (const uint64_t *)b1.blk, num_blocks(n1), SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
+                   out_blk.as<uint4>(), guard, srate, (const uint64_t *)ix.smp_bits, PF,
+                   samples ? sbits.as<uint64_t>() : nullptr, samples ? scnt.as<uint32_t>() : nullptr);
+    else
+        RB3_LAUNCH("interleave", k_interleave<false>, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream,
+                   (const uint64_t *)b1.blk, num_blocks(n1), SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
+                   out_blk.as<uint4>(), guard, srate, (const uint64_t *)ix.smp_bits, PF,
+                   samples ? sbits.as<uint64_t>() : nullptr, samples ? scnt.as<uint32_t>() : nullptr);
     int64_t nsmp_new = 0;
     if (samples) {
         RB3_TRY(scan_u32(c, scnt.as<uint32_t>(), scnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
