@@ -90,7 +90,7 @@ typedef struct rb3_opts {
                               end to end, each with its sentinel) is a
                               multiple of s, or when it starts its strand, so
                               a locate needs at most s - 1 LF steps. Costs
-                              one bit per row plus 8 bytes per sample; an
+                              two bits per row plus 8 bytes per sample; an
                               index keeps fewer than 2^32 samples and 2^24
                               strands (RB3_ELIMIT otherwise). */
 } rb3_opts;
@@ -158,10 +158,9 @@ int rb3_last_smem_stats(int64_t *extensions);
  * the index of the strand holding row rows[i]'s suffix in the index's list
  * (strands numbered in the order they were added, both strands counted) and
  * offset[i] its offset in that strand (the strand's length for its
- * sentinel suffix). rows: n entries in host or device memory (mem); every
- * row must be in [0, n_index), else RB3_EINVAL. strand and offset: host
- * arrays of n entries. The index must have samples (ssa_rate > 0), else
- * RB3_EINVAL.
+ * sentinel suffix). rows, strand and offset: n entries each, all in host
+ * or all in device memory (mem); every row must be in [0, n_index), else
+ * RB3_EINVAL. The index must have samples (ssa_rate > 0), else RB3_EINVAL.
  */
 int rb3_locate(const rb3_index *idx, const int64_t *rows, int64_t n, int32_t mem, int64_t *strand,
                int64_t *offset);

@@ -240,18 +240,14 @@ static int init_empty(Ctx &c, IndexData &d) {
     RB3_HIP(hipMemsetAsync((uint8_t *)blk.p + 48, 0, 16, c.stream));
     RB3_HIP(hipMemsetAsync(sb.p, 0, SB_STRIDE * sizeof(int64_t), c.stream));
     if (d.ctx.ssa > 0) {
-        // one block's sample words and counts, all zero
-        DBuf sbits, scnt;
-        RB3_ALLOC(sbits, &c, 2 * sizeof(uint64_t));
-        RB3_ALLOC(scnt, &c, 2 * sizeof(uint32_t));
-        RB3_HIP(hipMemsetAsync(sbits.p, 0, 2 * sizeof(uint64_t), c.stream));
-        RB3_HIP(hipMemsetAsync(scnt.p, 0, 2 * sizeof(uint32_t), c.stream));
-        d.smp_bits = sbits.as<uint64_t>();
-        d.smp_cnt = scnt.as<uint32_t>();
+        // one block's sample record, all zero
+        DBuf srec;
+        RB3_ALLOC(srec, &c, SMP_REC * sizeof(uint64_t));
+        RB3_HIP(hipMemsetAsync(srec.p, 0, SMP_REC * sizeof(uint64_t), c.stream));
+        d.smp_rec = srec.as<uint64_t>();
         d.smp_val = nullptr;
         d.nsmp = 0;
-        sbits.release();
-        scnt.release();
+        srec.release();
     }
     d.blk = blk.as<uint4>();
     d.sb = sb.as<int64_t>();
@@ -298,11 +294,9 @@ static int do_merge(Ctx &c, IndexData &d, const uint8_t *seq, const int64_t *len
     d.blk = nb;
     d.sb = nsb;
     if (d.ctx.ssa > 0) {
-        c.dfree(d.smp_bits);
-        c.dfree(d.smp_cnt);
+        c.dfree(d.smp_rec);
         c.dfree(d.smp_val);
-        d.smp_bits = so.bits;
-        d.smp_cnt = so.cnt;
+        d.smp_rec = so.rec;
         d.smp_val = so.val;
         d.nsmp = so.nsmp;
     }
@@ -483,20 +477,26 @@ static int run_locate(Ctx &c, const IndexData &d, const int64_t *a, const int64_
     const int64_t *da = nullptr, *db = nullptr;
     RB3_TRY(stage_i64(c, a, n, mem, ha, &da));
     if (b) RB3_TRY(stage_i64(c, b, n, mem, hb, &db));
-    RB3_ALLOC(ds, &c, n * sizeof(int64_t));
-    RB3_ALLOC(doff, &c, n * sizeof(int64_t));
+    // outputs go straight to the caller's arrays when they are device memory
+    int64_t *os = strand, *oo = offset;
+    if (mem == RB3_MEM_HOST) {
+        RB3_ALLOC(ds, &c, n * sizeof(int64_t));
+        RB3_ALLOC(doff, &c, n * sizeof(int64_t));
+        os = ds.as<int64_t>();
+        oo = doff.as<int64_t>();
+    }
     RB3_ALLOC(err, &c, sizeof(int32_t));
     RB3_ALLOC(stp, &c, sizeof(unsigned long long));
     RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
     RB3_HIP(hipMemsetAsync(stp.p, 0, sizeof(unsigned long long), c.stream));
     if (b)
-        RB3_TRY(locate_one(c, d.dev(), d.smp(), da, db, n, ds.as<int64_t>(), doff.as<int64_t>(), err.as<int32_t>(),
-                           stp.as<unsigned long long>()));
+        RB3_TRY(locate_one(c, d.dev(), d.smp(), da, db, n, os, oo, err.as<int32_t>(), stp.as<unsigned long long>()));
     else
-        RB3_TRY(locate_rows(c, d.dev(), d.smp(), da, n, ds.as<int64_t>(), doff.as<int64_t>(), err.as<int32_t>(),
-                            stp.as<unsigned long long>()));
-    RB3_HIP(hipMemcpyAsync(strand, ds.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
-    RB3_HIP(hipMemcpyAsync(offset, doff.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+        RB3_TRY(locate_rows(c, d.dev(), d.smp(), da, n, os, oo, err.as<int32_t>(), stp.as<unsigned long long>()));
+    if (mem == RB3_MEM_HOST) {
+        RB3_HIP(hipMemcpyAsync(strand, ds.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+        RB3_HIP(hipMemcpyAsync(offset, doff.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    }
     unsigned long long steps = 0;
     RB3_HIP(hipMemcpyAsync(&steps, stp.p, sizeof(steps), hipMemcpyDeviceToHost, c.stream));
     int32_t bad = 0;
@@ -650,21 +650,17 @@ int rb3_clone(const rb3_index *src, rb3_index **out) {
         RB3_HIP(hipMemcpyAsync(blk.p, src->d.blk, bb, hipMemcpyDeviceToDevice, c.stream));
         RB3_HIP(hipMemcpyAsync(sb.p, src->d.sb, sbb, hipMemcpyDeviceToDevice, c.stream));
         if (src->d.ctx.ssa > 0) {
-            DBuf sbits, scnt, sval;
+            DBuf srec, sval;
             const int64_t nb = num_blocks(src->d.n);
-            RB3_ALLOC(sbits, &c, nb * 2 * sizeof(uint64_t));
-            RB3_ALLOC(scnt, &c, (nb + 1) * sizeof(uint32_t));
-            RB3_HIP(hipMemcpyAsync(sbits.p, src->d.smp_bits, nb * 2 * sizeof(uint64_t), hipMemcpyDeviceToDevice,
-                                   c.stream));
-            RB3_HIP(hipMemcpyAsync(scnt.p, src->d.smp_cnt, (nb + 1) * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+            RB3_ALLOC(srec, &c, nb * SMP_REC * sizeof(uint64_t));
+            RB3_HIP(hipMemcpyAsync(srec.p, src->d.smp_rec, nb * SMP_REC * sizeof(uint64_t), hipMemcpyDeviceToDevice,
                                    c.stream));
             if (src->d.nsmp > 0) {
                 RB3_ALLOC(sval, &c, src->d.nsmp * sizeof(uint64_t));
                 RB3_HIP(hipMemcpyAsync(sval.p, src->d.smp_val, src->d.nsmp * sizeof(uint64_t),
                                        hipMemcpyDeviceToDevice, c.stream));
             }
-            ix->d.smp_bits = (uint64_t *)sbits.release();
-            ix->d.smp_cnt = (uint32_t *)scnt.release();
+            ix->d.smp_rec = (uint64_t *)srec.release();
             ix->d.smp_val = src->d.nsmp > 0 ? (uint64_t *)sval.release() : nullptr;
             ix->d.nsmp = src->d.nsmp;
         }
@@ -691,8 +687,7 @@ void rb3_index_free(rb3_index *idx) {
     Ctx c = call_ctx(idx->d);
     c.free_now(idx->d.blk);
     c.free_now(idx->d.sb);
-    c.free_now(idx->d.smp_bits);
-    c.free_now(idx->d.smp_cnt);
+    c.free_now(idx->d.smp_rec);
     c.free_now(idx->d.smp_val);
     if (idx->d.ctx.own_stream && idx->d.ctx.stream) (void)hipStreamDestroy(idx->d.ctx.stream);
     delete idx;

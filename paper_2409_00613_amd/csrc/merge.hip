@@ -1495,7 +1495,7 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
                                                     const uint32_t *__restrict__ bs, int64_t nout,
                                                     int64_t nblk_out, int64_t n1, int64_t m1, int lshift,
                                                     uint4 *__restrict__ out, int32_t *__restrict__ guard,
-                                                    int32_t srate, const uint64_t *__restrict__ obits,
+                                                    int32_t srate, const uint64_t *__restrict__ orec,
                                                     const uint32_t *__restrict__ PF,
                                                     uint64_t *__restrict__ nbits, uint32_t *__restrict__ ncnt) {
     const int32_t sr = SMP ? srate : 0;  // 0: the variant without samples
@@ -1530,7 +1530,7 @@ __global__ void __launch_bounds__(256) k_interleave(const uint64_t *__restrict__
                 if (ib <= ((i0 + nold - 1) >> BLK_SHIFT) && ib < nblk1) wd = b1words[ib * 8 + lane % 6];
             } else if (sr > 0 && lane < 16) {
                 const int64_t ib = ib0 + ((lane - 12) >> 1);
-                if (ib <= ((i0 + nold - 1) >> BLK_SHIFT) && ib < nblk1) wd = obits[ib * 2 + (lane & 1)];
+                if (ib <= ((i0 + nold - 1) >> BLK_SHIFT) && ib < nblk1) wd = orec[ib * SMP_REC + (lane & 1)];
             }
         }
         const uint32_t ka = s0 + (uint32_t)lane, kb = ka + 64u;
@@ -1635,8 +1635,7 @@ __global__ void __launch_bounds__(256) k_smp_values(const uint64_t *__restrict__
                                                     int64_t n1, int64_t m1, int lshift,
                                                     const uint64_t *__restrict__ nbits,
                                                     const uint32_t *__restrict__ nbase, int64_t nsmp,
-                                                    const uint64_t *__restrict__ obits,
-                                                    const uint32_t *__restrict__ ocnt,
+                                                    const uint64_t *__restrict__ orec,
                                                     const uint64_t *__restrict__ oval, int64_t onsmp, int64_t nblk1,
                                                     const int64_t *__restrict__ sstart, int64_t m2, int64_t sid0,
                                                     uint64_t *__restrict__ nval, int32_t *__restrict__ guard) {
@@ -1690,11 +1689,8 @@ __global__ void __launch_bounds__(256) k_smp_values(const uint64_t *__restrict__
                 const int64_t i = i0 + 64 * h + lane - before;  // old row
                 ok = ok && i >= 0 && i < n1 && (i >> BLK_SHIFT) < nblk1;
                 if (ok) {
-                    const int64_t ob = i >> BLK_SHIFT;
-                    const uint64_t u0 = obits[2 * ob], u1 = obits[2 * ob + 1];
-                    const int o = (int)(i & (BLK_SYMS - 1));
-                    const int64_t idx = (int64_t)ocnt[ob] +
-                                        (o < 64 ? __popcll(u0 & low_mask(o)) : __popcll(u0) + __popcll(u1 & low_mask(o - 64)));
+                    int64_t idx = 0;
+                    smp_rank_rec(orec, i, &idx);
                     ok = idx < onsmp;
                     if (ok) v = oval[idx];
                 }
@@ -1704,6 +1700,19 @@ __global__ void __launch_bounds__(256) k_smp_values(const uint64_t *__restrict__
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// The merged index's sample records: each block's two bit words and the
+// number of samples before it.
+__global__ void k_smp_pack(const uint64_t *__restrict__ nbits, const uint32_t *__restrict__ nbase, int64_t nblk,
+                           uint64_t *__restrict__ rec) {
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nblk;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        rec[b * SMP_REC] = nbits[2 * b];
+        rec[b * SMP_REC + 1] = nbits[2 * b + 1];
+        rec[b * SMP_REC + 2] = nbase[b];
+        rec[b * SMP_REC + 3] = 0;
     }
 }
 
@@ -2107,7 +2116,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     RB3_TRY(scan_u32(c, bcnt.as<uint32_t>(), bcnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
     RB3_ALLOC(out_blk, &c, nblk_out * 64);
     RB3_ALLOC(out_sb, &c, num_superblocks(nout) * SB_STRIDE * sizeof(int64_t));
-    DBuf sbits, scnt, sval, sst;
+    DBuf sbits, scnt, sval, sst, srec;
     if (samples) {
         RB3_ALLOC(sbits, &c, nblk_out * 2 * sizeof(uint64_t));
         RB3_ALLOC(scnt, &c, (nblk_out + 1) * sizeof(uint32_t));
@@ -2117,12 +2126,12 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     if (samples)
         RB3_LAUNCH("interleave", k_interleave<true>, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream,
                    (const uint64_t *)b1.blk, num_blocks(n1), SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
-                   out_blk.as<uint4>(), guard, srate, (const uint64_t *)ix.smp_bits, PF,
+                   out_blk.as<uint4>(), guard, srate, (const uint64_t *)ix.smp_rec, PF,
                    samples ? sbits.as<uint64_t>() : nullptr, samples ? scnt.as<uint32_t>() : nullptr);
     else
         RB3_LAUNCH("interleave", k_interleave<false>, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream,
                    (const uint64_t *)b1.blk, num_blocks(n1), SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
-                   out_blk.as<uint4>(), guard, srate, (const uint64_t *)ix.smp_bits, PF,
+                   out_blk.as<uint4>(), guard, srate, (const uint64_t *)ix.smp_rec, PF,
                    samples ? sbits.as<uint64_t>() : nullptr, samples ? scnt.as<uint32_t>() : nullptr);
     int64_t nsmp_new = 0;
     if (samples) {
@@ -2140,9 +2149,12 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_ALLOC(sval, &c, (nsmp_new > 0 ? nsmp_new : 1) * sizeof(uint64_t));
         RB3_LAUNCH("smp_values", k_smp_values, grid_for(nblk_out, 4, 1 << 18), dim3(256), 0, c.stream, SK, PF,
                    bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift, sbits.as<uint64_t>(), scnt.as<uint32_t>(),
-                   nsmp_new, (const uint64_t *)ix.smp_bits, (const uint32_t *)ix.smp_cnt,
+                   nsmp_new, (const uint64_t *)ix.smp_rec,
                    (const uint64_t *)ix.smp_val, ix.nsmp, num_blocks(n1), sst.as<int64_t>(), m2, m1,
                    sval.as<uint64_t>(), guard);
+        RB3_ALLOC(srec, &c, nblk_out * SMP_REC * sizeof(uint64_t));
+        RB3_LAUNCH("smp_pack", k_smp_pack, grid_for(nblk_out, 256), dim3(256), 0, c.stream, sbits.as<uint64_t>(),
+                   scnt.as<uint32_t>(), nblk_out, srec.as<uint64_t>());
     }
     int64_t counts[6];
     RB3_TRY(build_checkpoints(c, out_blk.as<uint4>(), nout, out_sb.as<int64_t>(), new_C, counts));
@@ -2158,12 +2170,10 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         return RB3_EDEVICE;
     }
     if (samples && smp) {
-        smp->bits = sbits.as<uint64_t>();
-        smp->cnt = scnt.as<uint32_t>();
+        smp->rec = srec.as<uint64_t>();
         smp->val = sval.as<uint64_t>();
         smp->nsmp = nsmp_new;
-        sbits.release();
-        scnt.release();
+        srec.release();
         sval.release();
     }
     *new_blk = (uint4 *)out_blk.release();

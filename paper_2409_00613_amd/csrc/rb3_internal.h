@@ -351,16 +351,19 @@ struct MergeStats {
 // position p of a merge batch is sampled when p is a multiple of the
 // sampling distance s or starts its strand, so every strand has a sample at
 // offset 0 and at least one in any s consecutive positions. A bit per BWT
-// row marks the sampled rows (two words per 128-row block, cnt = samples
-// before each block), and val holds each sampled row's position, in row
-// order, packed as strand << SMP_ID_SHIFT | offset.
+// row marks the sampled rows: per 128-row block one 32-byte record of four
+// words (the block's two bit words, the number of samples before the block,
+// padding), so that a locate step reads one line for its block's samples.
+// val holds each sampled row's position, in row order, packed as
+// strand << SMP_ID_SHIFT | offset.
 constexpr int SMP_ID_SHIFT = 40;
 constexpr uint64_t SMP_OFF_MASK = (1ull << SMP_ID_SHIFT) - 1;
 constexpr int64_t SMP_MAX_STRANDS = (int64_t)1 << (64 - SMP_ID_SHIFT);
 
+constexpr int SMP_REC = 4;  // words per block record
+
 struct DevSmp {
-    const uint64_t *bits;  // 2 per block
-    const uint32_t *cnt;   // blocks + 1 (fewer than 2^32 samples)
+    const uint64_t *rec;   // SMP_REC words per block (fewer than 2^32 samples)
     const uint64_t *val;   // nsmp
     int64_t nsmp;
     int32_t rate;
@@ -373,15 +376,13 @@ struct IndexData {
     uint4 *blk = nullptr;  // owned
     int64_t *sb = nullptr; // owned
     // samples (owned; null when ctx.ssa == 0)
-    uint64_t *smp_bits = nullptr;
-    uint32_t *smp_cnt = nullptr;
+    uint64_t *smp_rec = nullptr;
     uint64_t *smp_val = nullptr;
     int64_t nsmp = 0;
     MergeStats last;
     DevSmp smp() const {
         DevSmp s;
-        s.bits = smp_bits;
-        s.cnt = smp_cnt;
+        s.rec = smp_rec;
         s.val = smp_val;
         s.nsmp = nsmp;
         s.rate = ctx.ssa;
@@ -405,8 +406,7 @@ struct IndexData {
 // With samples (ix.ctx.ssa > 0) the merged index's sample arrays are
 // returned through smp (bits, cnt, val, nsmp); otherwise smp is untouched.
 struct SmpOut {
-    uint64_t *bits = nullptr;
-    uint32_t *cnt = nullptr;
+    uint64_t *rec = nullptr;
     uint64_t *val = nullptr;
     int64_t nsmp = 0;
 };
@@ -414,12 +414,12 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                int64_t n2, uint4 **new_blk, int64_t **new_sb, int64_t new_C[6], MergeStats &st,
                SmpOut *smp);
 
-// Rank of sampled rows before row r (and whether r is sampled): cnt of r's
-// block plus the set bits below r in it. Rows up to n are valid.
-__device__ __forceinline__ bool smp_rank(const DevSmp &s, int64_t r, int64_t *rank) {
-    const int64_t b = r >> BLK_SHIFT;
-    const uint64_t w0 = s.bits[2 * b], w1 = s.bits[2 * b + 1];
-    const int64_t c = (int64_t)s.cnt[b];
+// Rank of sampled rows before row r (and whether r is sampled): the count of
+// r's block plus the set bits below r in it. Rows up to n are valid.
+__device__ __forceinline__ bool smp_rank_rec(const uint64_t *rec, int64_t r, int64_t *rank) {
+    const uint64_t *q = rec + (r >> BLK_SHIFT) * SMP_REC;
+    const uint64_t w0 = q[0], w1 = q[1];
+    const int64_t c = (int64_t)(uint32_t)q[2];
     const int o = (int)(r & (BLK_SYMS - 1));
     if (o < 64) {
         *rank = c + __popcll(w0 & low_mask(o));
@@ -427,6 +427,9 @@ __device__ __forceinline__ bool smp_rank(const DevSmp &s, int64_t r, int64_t *ra
     }
     *rank = c + __popcll(w0) + __popcll(w1 & low_mask(o - 64));
     return (w1 >> (o - 64)) & 1ull;
+}
+__device__ __forceinline__ bool smp_rank(const DevSmp &s, int64_t r, int64_t *rank) {
+    return smp_rank_rec(s.rec, r, rank);
 }
 
 // locate.hip

@@ -339,24 +339,37 @@ def rb3_smem(idx: Index, q, qlens, min_len: int, min_occ: int = 1, cap: int | No
         return out[:off[-1]], off
 
 
+def _i64out(n, mem, like):
+    """Two int64 output arrays of n entries in the inputs' memory: numpy
+    arrays for host inputs, tensors on the same device for device inputs."""
+    if mem == RB3_MEM_DEVICE:
+        import torch
+        a = torch.empty(max(n, 1), dtype=torch.int64, device=like.device)
+        b = torch.empty(max(n, 1), dtype=torch.int64, device=like.device)
+        return a, b, ctypes.cast(a.data_ptr(), _i64p), ctypes.cast(b.data_ptr(), _i64p)
+    a = np.zeros(max(n, 1), np.int64)
+    b = np.zeros(max(n, 1), np.int64)
+    return a, b, a.ctypes.data_as(_i64p), b.ctypes.data_as(_i64p)
+
+
 def rb3_locate(idx: Index, rows):
-    """(strand, offset) arrays: the position of the suffix at each row."""
+    """(strand, offset): the position of the suffix at each row; numpy arrays
+    for host rows, device tensors for device rows."""
     ptr, n, mem, keep = _i64buf(rows)
-    st = np.zeros(max(n, 1), np.int64)
-    off = np.zeros(max(n, 1), np.int64)
-    _check(lib().rb3_locate(idx.handle, ptr, n, mem, st.ctypes.data_as(_i64p), off.ctypes.data_as(_i64p)))
+    st, off, pst, poff = _i64out(n, mem, keep)
+    _check(lib().rb3_locate(idx.handle, ptr, n, mem, pst, poff))
     return st[:n], off[:n]
 
 
 def rb3_locate1(idx: Index, lo, hi):
-    """(strand, offset) arrays: one occurrence in each SA interval [lo, hi)."""
+    """(strand, offset): one occurrence in each SA interval [lo, hi); numpy
+    arrays for host inputs, device tensors for device inputs."""
     plo, n, mem, k1 = _i64buf(lo)
     phi, n2, mem2, k2 = _i64buf(hi)
     if n != n2 or mem != mem2:
         raise ValueError("lo and hi must have the same length and memory kind")
-    st = np.zeros(max(n, 1), np.int64)
-    off = np.zeros(max(n, 1), np.int64)
-    _check(lib().rb3_locate1(idx.handle, plo, phi, n, mem, st.ctypes.data_as(_i64p), off.ctypes.data_as(_i64p)))
+    st, off, pst, poff = _i64out(n, mem, k1)
+    _check(lib().rb3_locate1(idx.handle, plo, phi, n, mem, pst, poff))
     return st[:n], off[:n]
 
 

@@ -152,7 +152,13 @@ def test_locate_device_rows_and_errors():
     rows = np.array([0, n - 1, n // 2, 7], np.int64)
     st_h, off_h = idx.locate(rows)
     st_d, off_d = idx.locate(torch.from_numpy(rows).cuda())
-    assert np.array_equal(st_h, st_d) and np.array_equal(off_h, off_d)
+    assert st_d.is_cuda and off_d.is_cuda
+    assert np.array_equal(st_h, st_d.cpu().numpy()) and np.array_equal(off_h, off_d.cpu().numpy())
+    lo_d = torch.tensor([0, 5], dtype=torch.int64, device="cuda")
+    hi_d = torch.tensor([n, 6], dtype=torch.int64, device="cuda")
+    st1, off1 = idx.locate1(lo_d, hi_d)
+    st1h, off1h = idx.locate1(np.array([0, 5]), np.array([n, 6]))
+    assert np.array_equal(st1.cpu().numpy(), st1h) and np.array_equal(off1.cpu().numpy(), off1h)
     for bad in ([-1], [n]):
         with pytest.raises(rb3.RB3Error) as e:
             idx.locate(np.array(bad, np.int64))
