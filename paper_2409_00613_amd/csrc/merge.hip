@@ -28,6 +28,8 @@
 //      B1 rows fill the remaining rows in order. Checkpoints are rebuilt.
 #include "rb3_internal.h"
 
+#include <mutex>
+
 namespace rb3 {
 
 struct Chunk {
@@ -1716,6 +1718,60 @@ __global__ void k_smp_pack(const uint64_t *__restrict__ nbits, const uint32_t *_
     }
 }
 
+// Side streams for the tie kernels. The size classes order disjoint groups
+// (each kernel reads and writes only its own groups' rows), so their kernels
+// may run at the same time: a class of few large groups then fills the CUs
+// that a class of many small groups leaves idle in its tail. Two streams per
+// device, default priority, created on first use and kept for the process.
+constexpr int TIE_SIDE = 2;
+static std::mutex g_side_mu;
+static hipStream_t g_side[64][TIE_SIDE];
+
+struct TieStreams {
+    hipStream_t main;
+    hipStream_t s[TIE_SIDE + 1];
+    hipEvent_t ev[TIE_SIDE + 1] = {};
+    bool joined = true;
+
+    explicit TieStreams(hipStream_t m) : main(m) {
+        for (int k = 0; k <= TIE_SIDE; ++k) s[k] = m;
+    }
+    // Work queued on main so far happens before any work on the side streams.
+    int fork(int dev) {
+        if (dev < 0 || dev >= 64) return RB3_OK;  // stays on main
+        {
+            std::lock_guard<std::mutex> g(g_side_mu);
+            for (int k = 0; k < TIE_SIDE; ++k)
+                if (!g_side[dev][k]) RB3_HIP(hipStreamCreateWithFlags(&g_side[dev][k], hipStreamNonBlocking));
+        }
+        for (int k = 0; k <= TIE_SIDE; ++k) RB3_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+        RB3_HIP(hipEventRecord(ev[0], main));
+        for (int k = 0; k < TIE_SIDE; ++k) {
+            RB3_HIP(hipStreamWaitEvent(g_side[dev][k], ev[0], 0));
+            s[k + 1] = g_side[dev][k];
+        }
+        joined = false;
+        return RB3_OK;
+    }
+    // Later work on main waits for everything queued on the side streams.
+    int join() {
+        if (joined) return RB3_OK;
+        joined = true;
+        for (int k = 1; k <= TIE_SIDE; ++k) {
+            RB3_HIP(hipEventRecord(ev[k], s[k]));
+            RB3_HIP(hipStreamWaitEvent(main, ev[k], 0));
+        }
+        return RB3_OK;
+    }
+    ~TieStreams() {
+        // on an early return the side streams drain before the caller's
+        // deferred frees can release their buffers
+        if (!joined && join() == RB3_OK) (void)hipStreamSynchronize(main);
+        for (int k = 0; k <= TIE_SIDE; ++k)
+            if (ev[k]) (void)hipEventDestroy(ev[k]);
+    }
+};
+
 static int bits_for(int64_t v) {  // bits to hold values 0..v
     int b = 0;
     while (b < 63 && (v >> b) != 0) ++b;
@@ -1938,75 +1994,84 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
             need_doubling = true;
         } else if (st.tie_groups > 0) {
             const uint8_t *Qc = d_Q;
-            if (hs2[0] + hs2[1] > 0) {
-                DBuf qh, dl;
-                int64_t nq = (int64_t)hs2[0] + hs2[1];
+            DBuf qh, dl;
+            const int64_t nq = (int64_t)hs2[0] + hs2[1];
+            if (nq > 0) {
                 RB3_ALLOC(qh, &c, 2 * sizeof(uint32_t));
                 RB3_ALLOC(dl, &c, nq * 2 * sizeof(uint32_t));
                 RB3_HIP(hipMemsetAsync(qh.p, 0, 2 * sizeof(uint32_t), c.stream));
+            }
+            // main: 9..64 members; side 1: up to 8 (and their deep part),
+            // then 129..256; side 2: 257..8192, then 65..128
+            TieStreams ts(c.stream);
+            RB3_TRY(ts.fork(c.device));
+            if (hs2[5] > 0) {
+                if (samples)
+                    RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1, true>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
+                               ts.s[2], Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, PF, srate, guard,
+                               gblk.as<unsigned long long>());
+                else
+                    RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1, false>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
+                               ts.s[2], Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, PF, srate, guard,
+                               gblk.as<unsigned long long>());
+            }
+            if (nq > 0) {
                 // persistent: enough waves to fill the chip, no more than the work
                 int64_t wgs = (nq + LANES_WG - 1) / LANES_WG;
                 if (wgs > 2048) wgs = 2048;
                 if (samples)
-                    RB3_LAUNCH("tie_lanes", k_tie_lanes<true>, dim3((unsigned)wgs), dim3(LANES_WG), 0, c.stream,
+                    RB3_LAUNCH("tie_lanes", k_tie_lanes<true>, dim3((unsigned)wgs), dim3(LANES_WG), 0, ts.s[1],
                                Qc, n2, SV, tl.l[0], (int64_t)hs2[0], tl.l[1], (int64_t)hs2[1],
                                qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
                                gtied.as<unsigned long long>() + 1);
                 else
-                    RB3_LAUNCH("tie_lanes", k_tie_lanes<false>, dim3((unsigned)wgs), dim3(LANES_WG), 0, c.stream,
+                    RB3_LAUNCH("tie_lanes", k_tie_lanes<false>, dim3((unsigned)wgs), dim3(LANES_WG), 0, ts.s[1],
                                Qc, n2, SV, tl.l[0], (int64_t)hs2[0], tl.l[1], (int64_t)hs2[1],
                                qh.as<uint32_t>(), dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
                                gtied.as<unsigned long long>() + 1);
-                // the deep list's length stays on the device: a fixed grid loops over it
-                if (samples)
-                    RB3_LAUNCH("tie_deep", k_tie_deep<true>, dim3(1024), dim3(256), 0, c.stream, Qc, n2, SV,
-                               dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
-                               gdeep.as<unsigned long long>());
-                else
-                    RB3_LAUNCH("tie_deep", k_tie_deep<false>, dim3(1024), dim3(256), 0, c.stream, Qc, n2, SV,
-                               dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
-                               gdeep.as<unsigned long long>());
             }
             if (hs2[2] > 0) {
                 if (samples)
-                    RB3_LAUNCH("tie_walk", (k_tie_walk<1, true>), grid_for(hs2[2], 4 * 8, 1 << 20), dim3(256), 0, c.stream,
+                    RB3_LAUNCH("tie_walk", (k_tie_walk<1, true>), grid_for(hs2[2], 4 * 8, 1 << 20), dim3(256), 0, ts.s[0],
                                Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, PF, srate, guard,
                                gtied.as<unsigned long long>() + 3);
                 else
-                    RB3_LAUNCH("tie_walk", (k_tie_walk<1, false>), grid_for(hs2[2], 4 * 8, 1 << 20), dim3(256), 0, c.stream,
+                    RB3_LAUNCH("tie_walk", (k_tie_walk<1, false>), grid_for(hs2[2], 4 * 8, 1 << 20), dim3(256), 0, ts.s[0],
                                Qc, n2, SV, tl.l[2], (int64_t)hs2[2], SK, PF, srate, guard,
                                gtied.as<unsigned long long>() + 3);
+            }
+            if (nq > 0) {
+                // the deep list's length stays on the device: a fixed grid loops over it
+                if (samples)
+                    RB3_LAUNCH("tie_deep", k_tie_deep<true>, dim3(1024), dim3(256), 0, ts.s[1], Qc, n2, SV,
+                               dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
+                               gdeep.as<unsigned long long>());
+                else
+                    RB3_LAUNCH("tie_deep", k_tie_deep<false>, dim3(1024), dim3(256), 0, ts.s[1], Qc, n2, SV,
+                               dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
+                               gdeep.as<unsigned long long>());
             }
             if (hs2[3] > 0) {
                 if (samples)
                     RB3_LAUNCH("tie_walk128", (k_tie_walk<2, true>), grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
-                               c.stream, Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
+                               ts.s[2], Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
                                gtied.as<unsigned long long>() + 3);
                 else
                     RB3_LAUNCH("tie_walk128", (k_tie_walk<2, false>), grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
-                               c.stream, Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
+                               ts.s[2], Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
                                gtied.as<unsigned long long>() + 3);
             }
             if (hs2[4] > 0) {
                 if (samples)
                     RB3_LAUNCH("tie_walk256", (k_tie_walk<4, true>), grid_for(hs2[4], 4 * 8, 1 << 20), dim3(256), 0,
-                               c.stream, Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, PF, srate, guard,
+                               ts.s[1], Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, PF, srate, guard,
                                gtied.as<unsigned long long>() + 3);
                 else
                     RB3_LAUNCH("tie_walk256", (k_tie_walk<4, false>), grid_for(hs2[4], 4 * 8, 1 << 20), dim3(256), 0,
-                               c.stream, Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, PF, srate, guard,
+                               ts.s[1], Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, PF, srate, guard,
                                gtied.as<unsigned long long>() + 3);
             }
-            if (hs2[5] > 0) {
-                if (samples)
-                    RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1, true>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
-                               c.stream, Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, PF, srate, guard,
-                               gblk.as<unsigned long long>());
-                else
-                    RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1, false>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
-                               c.stream, Qc, n2, SV, tl.l[5], (int64_t)hs2[5], SK, PF, srate, guard,
-                               gblk.as<unsigned long long>());
-            }
+            RB3_TRY(ts.join());
             unsigned long long hd[2], hb[2];
             RB3_HIP(hipMemcpyAsync(ht, gtied.p, sizeof(ht), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipMemcpyAsync(hd, gdeep.p, sizeof(hd), hipMemcpyDeviceToHost, c.stream));
