@@ -522,12 +522,36 @@ struct TieLists {
     uint32_t *l[TG_CLASSES];
 };
 
+// Number of new suffixes landing in each 128-row output block (the
+// interleave's input), counted while the sorted keys pass by: consecutive
+// sorted entries land in non-decreasing blocks, so a wave adds one count per
+// run of equal blocks in its 64-entry window instead of one per entry. The
+// key bits (the rank in the existing index) are all it needs, so the count
+// does not wait for the tie kernels, which only reorder equal keys.
+__device__ __forceinline__ void count_out_blocks(uint64_t v, int64_t s, bool in, int lane, int64_t m1, int lshift,
+                                                 int64_t nblk_out, uint32_t *__restrict__ cnt,
+                                                 int32_t *__restrict__ guard) {
+    const int64_t b = in ? (((int64_t)(v >> lshift) + m1 + s) >> BLK_SHIFT) : -1;
+    const int64_t bprev = __shfl_up(b, 1);
+    const bool head = in && (lane == 0 || b != bprev);
+    const uint64_t heads = __ballot(head);
+    const uint64_t vmask = __ballot(in);
+    if (head) {
+        const uint64_t above = heads & ~low_mask(lane + 1);
+        const int next = above ? __ffsll((unsigned long long)above) - 1 : 64 - __clzll((long long)vmask);
+        if (b >= 0 && b < nblk_out) atomicAdd(&cnt[b], (uint32_t)(next - lane));
+        else atomicOr(guard, GUARD_INTERLEAVE);
+    }
+}
+
 template <bool SMP>
 __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__restrict__ SK,
                                                            const uint32_t *__restrict__ SV, int32_t srate, int64_t n,
                                                            TieLists lists, uint32_t *__restrict__ gstat,
                                                            unsigned long long *__restrict__ tied,
-                                                           uint32_t *__restrict__ ghist) {
+                                                           uint32_t *__restrict__ ghist, int64_t m1, int lshift,
+                                                           int64_t nblk_out, uint32_t *__restrict__ bcnt,
+                                                           int32_t *__restrict__ guard) {
     const int32_t sr = SMP ? srate : 0;  // 0: the variant without samples
     __shared__ uint32_t lst[TG_CLASSES][TG_LCAP][2];
     __shared__ uint32_t hist[32];
@@ -562,6 +586,7 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
             const int64_t s = w0 + lane;
             const bool in = s < n;
             const uint64_t v = vw[j];
+            count_out_blocks(v, s, in, lane, m1, lshift, nblk_out, bcnt, guard);
             const uint64_t key = v >> 3;
             const uint32_t e = (uint32_t)(v & 7);
             uint64_t prevkey = __shfl_up(key, 1);
@@ -1442,43 +1467,6 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, 
 // Interleave
 // ---------------------------------------------------------------------------
 
-// Number of new suffixes landing in each 128-row output block. Consecutive
-// sorted entries land in non-decreasing blocks, so each wave adds one count
-// per run of equal blocks in a 64-entry window instead of one per entry.
-// Each wave loads its BC_WIN windows at once.
-constexpr int BC_WIN = 8;
-
-__global__ void k_block_count(const uint64_t *__restrict__ SK, int64_t n2, int64_t m1, int lshift,
-                              int64_t nblk_out, uint32_t *__restrict__ cnt, int32_t *__restrict__ guard) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t w0 = wave * (64 * BC_WIN); w0 < n2; w0 += nwaves * (64 * BC_WIN)) {
-        uint64_t kk[BC_WIN];
-#pragma unroll
-        for (int j = 0; j < BC_WIN; ++j) {
-            const int64_t s = w0 + j * 64 + lane;
-            kk[j] = s < n2 ? SK[s] : 0ull;
-        }
-#pragma unroll
-        for (int j = 0; j < BC_WIN; ++j) {
-            const int64_t s = w0 + j * 64 + lane;
-            const bool valid = s < n2;
-            const int64_t b = valid ? (((int64_t)(kk[j] >> lshift) + m1 + s) >> BLK_SHIFT) : -1;
-            const int64_t bprev = __shfl_up(b, 1);
-            const bool head = valid && (lane == 0 || b != bprev);
-            const uint64_t heads = __ballot(head);
-            const uint64_t vmask = __ballot(valid);
-            if (head) {
-                const uint64_t above = heads & ~low_mask(lane + 1);
-                const int next = above ? __ffsll((unsigned long long)above) - 1 : 64 - __clzll((long long)vmask);
-                if (b >= 0 && b < nblk_out) atomicAdd(&cnt[b], (uint32_t)(next - lane));
-                else atomicOr(guard, GUARD_INTERLEAVE);
-            }
-        }
-    }
-}
-
 // One wave per 128-row output block. The old rows of a block are a run of
 // consecutive B1 rows, held by at most two B1 blocks: their plane words are
 // loaded together with the block's sorted entries (and the next block's
@@ -1950,6 +1938,13 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_HIP(hipMemcpyAsync(PF, SV, n2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, c.stream));
     }
 
+    const int64_t nout = n1 + n2;
+    const int64_t nblk_out = num_blocks(nout);
+    DBuf bcnt;
+    RB3_ALLOC(bcnt, &c, (nblk_out + 1) * sizeof(uint32_t));
+    RB3_HIP(hipMemsetAsync(bcnt.p, 0, (nblk_out + 1) * sizeof(uint32_t), c.stream));
+    bool bcnt_scanned = false;
+
     // Groups whose members carry different BWT symbols need an order; the
     // tie kernels handle groups of up to 8192 members by size class, prefix
     // doubling (which orders every tie) handles larger ones.
@@ -1973,12 +1968,15 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_HIP(hipMemsetAsync(gtied.p, 0, 4 * sizeof(unsigned long long), c.stream));
         RB3_HIP(hipMemsetAsync(gdeep.p, 0, 2 * sizeof(unsigned long long), c.stream));
         RB3_HIP(hipMemsetAsync(gblk.p, 0, 2 * sizeof(unsigned long long), c.stream));
+        // (the pass over the sorted keys also counts each output block's new rows)
         if (samples)
             RB3_LAUNCH("tie_groups", k_tie_groups<true>, grid_for(n2, TG_THREADS * TG_WIN * 16, 2048), dim3(TG_THREADS), 0,
-                       c.stream, SK, SV, srate, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>());
+                       c.stream, SK, SV, srate, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>(),
+                       m1, lshift, nblk_out, bcnt.as<uint32_t>(), guard);
         else
             RB3_LAUNCH("tie_groups", k_tie_groups<false>, grid_for(n2, TG_THREADS * TG_WIN * 16, 2048), dim3(TG_THREADS), 0,
-                       c.stream, SK, SV, srate, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>());
+                       c.stream, SK, SV, srate, n2, tl, gstat.as<uint32_t>(), gtied.as<unsigned long long>(), ghist.as<uint32_t>(),
+                       m1, lshift, nblk_out, bcnt.as<uint32_t>(), guard);
         uint32_t hs2[8];
         unsigned long long ht[4];
         RB3_HIP(hipMemcpyAsync(st.group_hist, ghist.p, sizeof(st.group_hist), hipMemcpyDeviceToHost, c.stream));
@@ -2005,6 +2003,9 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
             // then 129..256; side 2: 257..8192, then 65..128
             TieStreams ts(c.stream);
             RB3_TRY(ts.fork(c.device));
+            // the block counts' scan runs beside the side streams' first kernels
+            RB3_TRY(scan_u32(c, bcnt.as<uint32_t>(), bcnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
+            bcnt_scanned = true;
             if (hs2[5] > 0) {
                 if (samples)
                     RB3_LAUNCH("tie_block8k", (k_tie_block<1024, 8, 1, true>), grid_for(hs2[5], 1, 256), dim3(1024), 0,
@@ -2171,14 +2172,9 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     }
 
     // ---- 3. interleave into the merged BWT ----
-    const int64_t nout = n1 + n2;
-    const int64_t nblk_out = num_blocks(nout);
-    DBuf bcnt, out_blk, out_sb;
-    RB3_ALLOC(bcnt, &c, (nblk_out + 1) * sizeof(uint32_t));
-    RB3_HIP(hipMemsetAsync(bcnt.p, 0, (nblk_out + 1) * sizeof(uint32_t), c.stream));
-    RB3_LAUNCH("merge_block_count", k_block_count, grid_for(n2, 256 * BC_WIN, 1 << 16), dim3(256), 0, c.stream, SK, n2, m1,
-               lshift, nblk_out, bcnt.as<uint32_t>(), guard);
-    RB3_TRY(scan_u32(c, bcnt.as<uint32_t>(), bcnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
+    if (!bcnt_scanned)
+        RB3_TRY(scan_u32(c, bcnt.as<uint32_t>(), bcnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
+    DBuf out_blk, out_sb;
     RB3_ALLOC(out_blk, &c, nblk_out * 64);
     RB3_ALLOC(out_sb, &c, num_superblocks(nout) * SB_STRIDE * sizeof(int64_t));
     DBuf sbits, scnt, sval, sst, srec;
