@@ -11,8 +11,9 @@
 //      sentinel starts from the closed range [m1, n1] of possible l values
 //      and maps both ends through the monotone l -> pi(a, l); once they meet,
 //      the value is exact whatever the true start was. The positions walked
-//      before that are completed from the right neighbour's exact value, by
-//      the neighbour's lane itself or by a fix-up pass.
+//      before that are completed from the right neighbour's exact value by
+//      a fix-up pass, from records the chain leaves (no index reads while
+//      the interval spans at most 64 rows).
 //   2. Order among the new suffixes without building B2. For new suffixes x,
 //      y: l(x) < l(y) implies x < y, and when l(x) = l(y) the order is the
 //      plain string order. So the new suffixes are radix-sorted by the key
@@ -37,7 +38,7 @@ struct Chunk {
     int32_t len;    // symbols in the chunk
     int32_t last;   // 1 if the chunk ends at the strand's sentinel
     int32_t first;  // 1 if the chunk starts at the strand's first symbol
-    int32_t pad;
+    int32_t pad;    // index of the chunk's first fix-up segment
 };
 
 // Sort key of a new suffix at position p:
@@ -128,23 +129,33 @@ struct BackSyms {
     }
 };
 
-// Left neighbours whose unresolved ends one lane may walk after its own
-// chunk (more are left to the fix-up passes).
-constexpr int CHAIN_TAKEOVER = 2;
+// Rows lo .. lo + 63 of B1 holding symbol a, as a mask (bit j: row lo + j),
+// from the block holding lo (BL) and, when two is set, the block after it
+// (BH). Rows past the blocks read as 0: a caller only uses rows below the
+// interval's high end, which lie in these blocks.
+__device__ __forceinline__ uint64_t rows_with(const Block &BL, const Block &BH, bool two, int64_t lo, int a) {
+    const uint64_t e0 = plane_match(u64_lo(BL.q0), u64_lo(BL.q1), u64_lo(BL.q2), a);
+    const uint64_t e1 = plane_match(u64_hi(BL.q0), u64_hi(BL.q1), u64_hi(BL.q2), a);
+    const uint64_t e2 = two ? plane_match(u64_lo(BH.q0), u64_lo(BH.q1), u64_lo(BH.q2), a) : 0ull;
+    const int o = (int)(lo & (BLK_SYMS - 1));
+    const uint64_t x = o < 64 ? e0 : e1, y = o < 64 ? e1 : e2;
+    const int sh = o & 63;
+    return sh ? (x >> sh) | (y << (64 - sh)) : x;
+}
 
-// One lane per chunk. The walk covers the chunk right to left; once its
-// value is exact the lane publishes how many of its positions it walked
-// before that (conv, a device-scope store nobody waits for). A lane whose
-// value is exact at its chunk's start then reads its left neighbour's
-// count once and walks exactly those positions, the neighbour's unresolved
-// end, with exact values (fixed[] marks the neighbour as complete). If the
-// neighbour has not published (it has not converged, or not yet), the lane
-// walks the whole neighbour and may go on to the next one. The positions
-// walked this way are exactly the ones a fix-up pass would replay, but they
-// run while the other chains are still going.
+// One lane per chunk. The walk covers the chunk right to left. Until the
+// interval [lo, hi] of possible values closes, each step records the
+// interval's new low end pi(a, lo) (in K, where the position's key goes
+// later) and, when the interval spans at most 64 rows, which of the rows
+// lo .. lo + 63 hold the step's symbol a (in M; 0 for a wider interval).
+// An exact value l in [lo, hi] then moves to
+//   pi(a, l) = pi(a, lo) + #(rows lo .. l - 1 holding a),
+// so the fix-up pass completes an unresolved end from the right
+// neighbour's exact value with a popcount per position instead of a
+// dependent read of the index.
 __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
-                        int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K,
-                        int32_t *__restrict__ unres, int32_t *__restrict__ conv, int32_t *__restrict__ fixed,
+                        int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K, uint64_t *__restrict__ M,
+                        int32_t *__restrict__ unres, int32_t *__restrict__ ulen, int32_t *__restrict__ nwu,
                         unsigned long long *__restrict__ stats) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nch) return;
@@ -157,15 +168,15 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     if (c.last) {
         point = true;
         K[p1] = (uint64_t)Q[p1 - 1];  // sentinel suffix: l = m1, no symbols
-        __hip_atomic_store(&conv[i], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         point = false;
         packed = pack_ahead(Q, p1, w);
     }
-    int32_t unresolved = 0;
-    int64_t wide = 0, taken = 0;
-    KeyWindow win;
+    int32_t unresolved = 0, nwide = 0;
+    int64_t wide = 0;
+    KeyWindow win, rec;
     win.init();
+    rec.init();
     BackSyms sy;
     sy.init(Q, p1 - 1);
     for (int64_t p = p1 - 1; p >= c.p0; --p) {
@@ -184,78 +195,117 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
             const int64_t nlo = pi_from_block(ix, BL, (int)a, lo);
             const int64_t nhi = pi_from_block(ix, BH, (int)a, hi);
             if (bh != bl) ++wide;
-            lo = nlo;
-            hi = nhi;
-            if (lo == hi) {
+            if (nlo == nhi) {
                 point = true;
-                l = lo;
+                l = nlo;
                 win.push(make_key(l - m1, packed, emit, lshift), true);
-                __hip_atomic_store(&conv[i], unresolved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // the records end at p + 1
+                if (rec.vm) rec.flush(M, p + 1);
             } else {
                 ++unresolved;
-                win.push(0, false);
+                win.push((uint64_t)nlo, true);
+                if (hi - lo > 64) ++nwide;  // the widths only shrink: these come first
+                rec.push(hi - lo <= 64 ? rows_with(BL, BH, bh != bl, lo, (int)a) & low_mask((int)(hi - lo)) : 0ull,
+                         true);
+                if ((p & 7) == 0 || p == c.p0) rec.flush(M, p);
             }
+            lo = nlo;
+            hi = nhi;
         }
         if ((p & 7) == 0 || p == c.p0) win.flush(K, p);
         sy.next(p);
     }
     unres[i] = unresolved;
-    if (point) {
-        int64_t j = i;
-        for (int t = 0; t < CHAIN_TAKEOVER; ++t) {
-            if (ch[j].first) break;
-            const int64_t nb = j - 1;  // same strand: j does not start it
-            const Chunk cn = ch[nb];
-            const int32_t v = __hip_atomic_load(&conv[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int64_t end = cn.p0 + cn.len;
-            const int64_t stop = v >= 0 ? end - v : cn.p0;
-            // the neighbour ends where this walk stopped, so sy is at end - 1
-            for (int64_t p = end - 1; p >= stop; --p) {
-                const uint32_t a = sy.at(p);
-                const uint32_t emit = sy.before(p);
-                packed = ((uint64_t)a << wsh) | (packed >> 3);
-                l = pi_sym(ix, (int)a, l);
-                win.push(make_key(l - m1, packed, emit, lshift), true);
-                if ((p & 7) == 0 || p == stop) win.flush(K, p);
-                sy.next(p);
-            }
-            taken += end - stop;
-            fixed[nb] = 1;
-            if (v >= 0) break;  // the neighbour resolved the rest itself
-            j = nb;
-        }
-    }
+    ulen[i] = unresolved;
+    nwu[i] = nwide;
     if (wide) atomicAdd(&stats[1], (unsigned long long)wide);
-    if (taken) atomicAdd(&stats[2], (unsigned long long)taken);
 }
 
-// After the chains: chunks completed by a right neighbour have nothing left
-// to fix; the others keep their unresolved end, and a chunk's first
-// position is exact (ready) unless the whole chunk is unresolved.
-__global__ void k_chain_join(const Chunk *__restrict__ ch, int64_t nch, int32_t *__restrict__ unres,
-                             const int32_t *__restrict__ fixed, int32_t *__restrict__ ready,
-                             unsigned long long *__restrict__ stats) {
+// After the chains: a chunk's first position is exact (ready) unless the
+// whole chunk is unresolved.
+__global__ void k_chain_join(const Chunk *__restrict__ ch, int64_t nch, const int32_t *__restrict__ unres,
+                             int32_t *__restrict__ ready, unsigned long long *__restrict__ stats) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nch) return;
-    int32_t u = fixed[i] ? 0 : unres[i];
-    unres[i] = u;
+    const int32_t u = unres[i];
     ready[i] = u < ch[i].len ? 1 : 0;
     if (u) atomicAdd(&stats[0], (unsigned long long)u);
 }
 
+// The fix-up. In chunk i's unresolved end, number the steps t = 0, 1, ...
+// from the chunk's right end (position p1 - 1 - t). Step t maps the exact
+// value entering it, L_t in [lo_t, hi_t], to L_{t+1} = pi(a, L_t). The first
+// nw[i] steps, whose interval spans more than 64 rows, read the index. For
+// the others, with d_t = L_t - lo_t,
+//   d_{t+1} = f_t(d_t) = popcount(M_t & low_mask(d_t)),
+// a non-decreasing map of 0..64 that starts at 0 and rises by at most 1 per
+// step of d. Such a map is its mask of rises, and the mask of f_t after g is
+// the bits of M_t deposited on the set bits of g's mask. So the steps are cut
+// into segments of FIX_SEG: k_fix_compose folds each segment's maps into one
+// mask (all segments at once), k_fixup walks each run of chunks through the
+// index steps and the segment masks only, recording every segment's entry
+// value, and k_fix_keys replays every segment from its entry value, writing
+// the keys (all segments at once).
+constexpr int FIX_SEG = 256;
+
+// Bits of src, lowest first, placed on the set bits of mask, lowest first.
+__device__ __forceinline__ uint64_t deposit_bits(uint64_t src, uint64_t mask) {
+    uint64_t r = 0;
+    while (mask && src) {
+        const uint64_t low = mask & (~mask + 1ull);
+        if (src & 1ull) r |= low;
+        src >>= 1;
+        mask ^= low;
+    }
+    return r;
+}
+
+// Segment k of chunk i (lanes k-major: one wave covers 64 chunks at the same
+// k) folds the masks of its steps t0 .. t1 - 1.
+__global__ void k_fix_compose(const Chunk *__restrict__ ch, int64_t nch, int32_t segs_max,
+                              const uint64_t *__restrict__ M, const int32_t *__restrict__ ulen,
+                              const int32_t *__restrict__ nwu, uint64_t *__restrict__ HS) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nch * (int64_t)segs_max) return;
+    const int64_t i = g % nch;
+    const int32_t k = (int32_t)(g / nch);
+    const int32_t u = ulen[i];
+    const int64_t t0 = (int64_t)nwu[i] + (int64_t)k * FIX_SEG;
+    if (t0 >= u) return;
+    const int64_t t1 = t0 + FIX_SEG < u ? t0 + FIX_SEG : u;
+    const Chunk c = ch[i];
+    const int64_t top = c.p0 + c.len - 1;  // position of step 0
+    uint64_t H = M[top - t0];
+    for (int64_t tb = t0 + 1; tb < t1; tb += 8) {
+        uint64_t m[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) m[q] = tb + q < t1 ? M[top - tb - q] : 0ull;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (tb + q < t1) H = deposit_bits(m[q], H);
+    }
+    HS[c.pad + k] = H;
+}
+
 // Fix-up pass: a chunk with an unresolved end whose right neighbour's first
-// position is exact walks that end. A chunk that was unresolved throughout
-// becomes exact at its first position, so the same lane goes on into its
-// left neighbour's unresolved end, and so on: a run of unresolved chunks is
+// position is exact walks its index steps (writing their keys), then the
+// segment masks, recording each segment's entry value of d; the
+// end of the walk is exact at the chunk's last unresolved position. A chunk
+// that was unresolved throughout becomes exact at its first position (its
+// key is written here too), so the same lane goes on into its left
+// neighbour's unresolved end, and so on: a run of unresolved chunks is
 // completed in one pass. (Only this lane writes the chunks of its run: their
 // own lanes see a right neighbour that was not ready when the pass began,
 // and a run ends at a chunk with an exact first position, so two runs never
 // meet.) k_unres_count then counts what is left; the host repeats passes
-// while anything is.
+// while anything is (one pass covers every run: a run's right neighbour is
+// exact from the chains).
 __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
                         int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K,
-                        int32_t *__restrict__ unres, const int32_t *__restrict__ ready_in,
-                        int32_t *__restrict__ ready_out, unsigned long long *__restrict__ runmax) {
+                        int32_t *__restrict__ unres, const int32_t *__restrict__ nwu,
+                        const uint64_t *__restrict__ HS, int32_t *__restrict__ SD, int64_t *__restrict__ EX, const int32_t *__restrict__ ready_in,
+                        int32_t *__restrict__ ready_out,
+                        unsigned long long *__restrict__ stats, int32_t *__restrict__ guard) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nch) return;
     int32_t u = unres[i];
@@ -266,31 +316,54 @@ __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     Chunk c = ch[i];
     const int lshift = 3 + 3 * w, wsh = 3 * (w - 1);
     int64_t p1 = c.p0 + c.len;
-    int64_t l = (int64_t)(K[p1] >> lshift) + m1;
-    uint64_t packed = pack_ahead(Q, p1, w);
-    KeyWindow win;
-    win.init();
-    BackSyms sy;
-    sy.init(Q, p1 - 1);
+    // the neighbour's first position: its key, or its value from an earlier pass
+    const int64_t ex = EX[i + 1];
+    int64_t l = ex >= 0 ? ex : (int64_t)(K[p1] >> lshift) + m1;
     int64_t j = i;
-    unsigned long long run = 0;  // chunks completed by this lane
+    unsigned long long run = 0;   // chunks completed by this lane
+    unsigned long long slow = 0;  // steps that read the index
+    bool bad = false;
     for (;;) {
-        // positions p1 - u .. p1 - 1 of chunk j
-        for (int64_t p = p1 - 1; p >= p1 - u; --p) {
-            const uint32_t a = sy.at(p);
-            const uint32_t emit = sy.before(p);
+        const int32_t nw = nwu[j];
+        uint64_t packed = pack_ahead(Q, p1, w);
+        int64_t lo = m1;
+        for (int32_t t = 0; t < nw; ++t) {
+            const int64_t p = p1 - 1 - t;
+            const uint32_t a = Q[p];
             packed = ((uint64_t)a << wsh) | (packed >> 3);
+            const int64_t nlo = (int64_t)K[p];
             l = pi_sym(ix, (int)a, l);
-            win.push(make_key(l - m1, packed, emit, lshift), true);
-            if ((p & 7) == 0 || p == p1 - u) win.flush(K, p);
-            sy.next(p);
+            lo = nlo;
+            K[p] = make_key(l - m1, packed, p > 0 ? Q[p - 1] : 0u, lshift);
+        }
+        slow += (unsigned long long)nw;
+        if (nw < u) {
+            int64_t d = l - lo;
+            if (d < 0 || d > 64) {
+                bad = true;
+                d = d < 0 ? 0 : 64;
+            }
+            int64_t seg = c.pad;
+            for (int64_t t0 = nw; t0 < u; t0 += FIX_SEG, ++seg) {
+                SD[seg] = (int32_t)d;
+                d = __popcll(HS[seg] & low_mask((int)d));
+            }
+            // exact at the last unresolved position p1 - u
+            l = (int64_t)K[p1 - u] + d;
+            if (l > ix.n) {  // never for consistent records: keeps reads in range
+                l = ix.n;
+                bad = true;
+            }
         }
         unres[j] = 0;
         ++run;
         if (u < c.len) break;
+        // chunk j was unresolved throughout: its first position is exact now
+        // (its key is written by k_fix_keys; a later pass reads the value here)
+        EX[j] = l;
         ready_out[j] = 1;
         if (c.first) break;
-        // chunk j was unresolved throughout: its left neighbour's end follows
+        // its left neighbour's end follows
         const int64_t nb = j - 1;
         const int32_t un = unres[nb];
         if (un == 0) break;
@@ -299,7 +372,80 @@ __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
         p1 = c.p0 + c.len;
         u = un;
     }
-    atomicMax(runmax, run);
+    if (bad) atomicOr(guard, GUARD_CHAIN);
+    if (slow) atomicAdd(&stats[2], slow);
+    atomicMax(&stats[3], run);
+}
+
+// Segment k of chunk i replays its steps from its entry value and writes
+// their keys; the records of the next 8 steps are requested while the
+// current 8 are walked.
+__global__ void k_fix_keys(const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch, int64_t nch,
+                           int32_t segs_max, int64_t m1, int w, uint64_t *__restrict__ K,
+                           const uint64_t *__restrict__ M, const int32_t *__restrict__ ulen,
+                           const int32_t *__restrict__ nwu, const int32_t *__restrict__ SD,
+                           int32_t *__restrict__ guard) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nch * (int64_t)segs_max) return;
+    const int64_t i = g % nch;
+    const int32_t k = (int32_t)(g / nch);
+    const int32_t u = ulen[i];
+    const int64_t t0 = (int64_t)nwu[i] + (int64_t)k * FIX_SEG;
+    if (t0 >= u) return;
+    const int64_t t1 = t0 + FIX_SEG < u ? t0 + FIX_SEG : u;
+    const Chunk c = ch[i];
+    const int lshift = 3 + 3 * w, wsh = 3 * (w - 1);
+    const int64_t seg = c.pad + k;
+    int64_t d = SD[seg];
+    if (d < 0 || d > 64) {  // no entry: the fix-up passes did not reach this chunk
+        atomicOr(guard, GUARD_CHAIN);
+        return;
+    }
+    const int64_t top = c.p0 + c.len - 1;
+    const int64_t ps = top - t0, pe = top - (t1 - 1);  // positions ps down to pe
+    uint64_t packed = pack_ahead(Q, ps + 1, w);
+    KeyWindow win;
+    win.init();
+    BackSyms sy;
+    sy.init(Q, ps);
+    uint64_t nk[8], nm[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        nk[q] = ps - q >= pe ? K[ps - q] : 0ull;
+        nm[q] = ps - q >= pe ? M[ps - q] : 0ull;
+    }
+    bool bad = false;
+    for (int64_t pb = ps; pb >= pe; pb -= 8) {
+        uint64_t ck[8], cm[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            ck[q] = nk[q];
+            cm[q] = nm[q];
+        }
+        if (pb - 8 >= pe) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                nk[q] = pb - 8 - q >= pe ? K[pb - 8 - q] : 0ull;
+                nm[q] = pb - 8 - q >= pe ? M[pb - 8 - q] : 0ull;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t p = pb - q;
+            if (p >= pe) {
+                const uint32_t a = sy.at(p);
+                const uint32_t emit = sy.before(p);
+                packed = ((uint64_t)a << wsh) | (packed >> 3);
+                d = __popcll(cm[q] & low_mask((int)d));
+                if (cm[q] == 0ull) bad = true;  // a step of the narrow part always has a mask
+                const int64_t l = (int64_t)ck[q] + d;
+                win.push(make_key(l - m1, packed, emit, lshift), true);
+                if ((p & 7) == 0 || p == pe) win.flush(K, p);
+                sy.next(p);
+            }
+        }
+    }
+    if (bad) atomicOr(guard, GUARD_CHAIN);
 }
 
 // Chunks still holding unresolved positions after a fix-up pass.
@@ -1832,13 +1978,22 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         st.chunks = nch;
         st.chunk_len = CL;
         st.chain_steps = n2 - m2;
-        DBuf d_ch, unres, conv, fixed, readyA, readyB, pend;
+        // fix-up segments: at most ceil(len / FIX_SEG) per chunk
+        int64_t nseg = 0, maxlen = 0;
+        for (Chunk &ck : chunks) {
+            ck.pad = (int32_t)nseg;
+            nseg += (ck.len + FIX_SEG - 1) / FIX_SEG;
+            maxlen = ck.len > maxlen ? ck.len : maxlen;
+        }
+        const int32_t segs_max = (int32_t)((maxlen + FIX_SEG - 1) / FIX_SEG);
+        DBuf d_ch, unres, ulen, nwu, recm, readyA, readyB, pend;
         RB3_ALLOC(d_ch, &c, nch * sizeof(Chunk));
         RB3_ALLOC(unres, &c, nch * sizeof(int32_t));
-        RB3_ALLOC(conv, &c, nch * sizeof(int32_t));
-        RB3_ALLOC(fixed, &c, nch * sizeof(int32_t));
-        RB3_HIP(hipMemsetAsync(conv.p, 0xFF, nch * sizeof(int32_t), c.stream));
-        RB3_HIP(hipMemsetAsync(fixed.p, 0, nch * sizeof(int32_t), c.stream));
+        RB3_ALLOC(ulen, &c, nch * sizeof(int32_t));
+        RB3_ALLOC(nwu, &c, nch * sizeof(int32_t));
+        // the chains' records for unresolved positions (with K, which holds
+        // their interval low ends until the fix-up writes their keys)
+        RB3_ALLOC(recm, &c, n2 * sizeof(uint64_t));
         RB3_ALLOC(readyA, &c, (nch + 1) * sizeof(int32_t));
         RB3_ALLOC(readyB, &c, (nch + 1) * sizeof(int32_t));
         RB3_ALLOC(pend, &c, sizeof(int32_t));
@@ -1851,33 +2006,43 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 const int64_t f = first_chunk[s], k = first_chunk[s + 1] - f;
                 if (k == 0) continue;
                 RB3_LAUNCH("chain", k_chain, grid_for(k, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
-                           d_ch.as<Chunk>() + f, k, m1, w, K.as<uint64_t>(), unres.as<int32_t>() + f,
-                           conv.as<int32_t>() + f, fixed.as<int32_t>() + f, stats.as<unsigned long long>());
+                           d_ch.as<Chunk>() + f, k, m1, w, K.as<uint64_t>(), recm.as<uint64_t>(),
+                           unres.as<int32_t>() + f, ulen.as<int32_t>() + f, nwu.as<int32_t>() + f,
+                           stats.as<unsigned long long>());
             }
         } else {
             RB3_LAUNCH("chain", k_chain, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
-                       d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(), conv.as<int32_t>(),
-                       fixed.as<int32_t>(), stats.as<unsigned long long>());
+                       d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), recm.as<uint64_t>(), unres.as<int32_t>(),
+                       ulen.as<int32_t>(), nwu.as<int32_t>(), stats.as<unsigned long long>());
         }
         RB3_LAUNCH("chain_join", k_chain_join, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
-                   d_ch.as<Chunk>(), nch, unres.as<int32_t>(), fixed.as<int32_t>(), readyA.as<int32_t>(),
-                   stats.as<unsigned long long>());
+                   d_ch.as<Chunk>(), nch, unres.as<int32_t>(), readyA.as<int32_t>(), stats.as<unsigned long long>());
         unsigned long long hs[4];
         RB3_HIP(hipMemcpyAsync(hs, stats.p, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
         RB3_HIP(hipStreamSynchronize(c.stream));
         st.fixup_steps = (int64_t)hs[0];
-        st.chain_steps += (int64_t)hs[1] + (int64_t)hs[2];
-        st.chain_takeover = (int64_t)hs[2];
+        st.chain_steps += (int64_t)hs[1];
         int32_t *rin = readyA.as<int32_t>(), *rout = readyB.as<int32_t>();
         int64_t passes = 0;
         if (hs[0] > 0) {
+            DBuf HS, SD, EX;
+            RB3_ALLOC(HS, &c, (nseg > 0 ? nseg : 1) * sizeof(uint64_t));
+            RB3_ALLOC(SD, &c, (nseg > 0 ? nseg : 1) * sizeof(int32_t));
+            RB3_ALLOC(EX, &c, (nch + 1) * sizeof(int64_t));
+            RB3_HIP(hipMemsetAsync(SD.p, 0xFF, (nseg > 0 ? nseg : 1) * sizeof(int32_t), c.stream));
+            RB3_HIP(hipMemsetAsync(EX.p, 0xFF, (nch + 1) * sizeof(int64_t), c.stream));
+            const int64_t nlanes = nch * (int64_t)segs_max;
+            RB3_LAUNCH("fix_compose", k_fix_compose, grid_for(nlanes, 256, 1 << 30), dim3(256), 0, c.stream,
+                       d_ch.as<Chunk>(), nch, segs_max, recm.as<uint64_t>(), ulen.as<int32_t>(), nwu.as<int32_t>(),
+                       HS.as<uint64_t>());
             for (;;) {
                 RB3_HIP(hipMemcpyAsync(rout, rin, (nch + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice,
                                        c.stream));
                 RB3_HIP(hipMemsetAsync(pend.p, 0, sizeof(int32_t), c.stream));
                 RB3_LAUNCH("chain_fixup", k_fixup, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
                            b1, d_Q, d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(),
-                           rin, rout, stats.as<unsigned long long>() + 3);
+                           nwu.as<int32_t>(), HS.as<uint64_t>(), SD.as<int32_t>(), EX.as<int64_t>(), rin, rout,
+                           stats.as<unsigned long long>(), guard);
                 RB3_LAUNCH("chain_left", k_unres_count, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
                            unres.as<int32_t>(), nch, pend.as<int32_t>());
                 int32_t hp = 0;
@@ -1891,15 +2056,17 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                     return RB3_EDEVICE;
                 }
             }
+            RB3_LAUNCH("fix_keys", k_fix_keys, grid_for(nlanes, 256, 1 << 30), dim3(256), 0, c.stream,
+                       d_Q, d_ch.as<Chunk>(), nch, segs_max, m1, w, K.as<uint64_t>(), recm.as<uint64_t>(),
+                       ulen.as<int32_t>(), nwu.as<int32_t>(), SD.as<int32_t>(), guard);
+            RB3_HIP(hipMemcpyAsync(hs, stats.p, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
+            RB3_HIP(hipStreamSynchronize(c.stream));
+            st.fixup_index_steps = (int64_t)hs[2];
+            st.fixup_run_max = (int64_t)hs[3];
         }
         st.fixup_passes = passes;
-        if (passes > 0) {
-            unsigned long long rm = 0;
-            RB3_HIP(hipMemcpyAsync(&rm, stats.as<unsigned long long>() + 3, sizeof(rm), hipMemcpyDeviceToHost,
-                                   c.stream));
-            RB3_HIP(hipStreamSynchronize(c.stream));
-            st.fixup_run_max = (int64_t)rm;
-        }
+        // the stream has drained: the records go back to the allocator now
+        c.free_now(recm.release());
     } else {
         RB3_LAUNCH("build_keys", k_build_keys, grid_for(n2, 256 * 4), dim3(256), 0, c.stream, d_Q, n2, w,
                    K.as<uint64_t>());

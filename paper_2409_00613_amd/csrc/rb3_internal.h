@@ -237,7 +237,8 @@ enum {
     GUARD_COMPACT = 8,
     GUARD_INTERLEAVE = 16,
     GUARD_PLACE = 32,
-    GUARD_SAMPLE = 64
+    GUARD_SAMPLE = 64,
+    GUARD_CHAIN = 128
 };
 
 // Error state: thread-local message for rb3_strerror.
@@ -327,7 +328,7 @@ struct MergeStats {
     int64_t chunks = 0, chunk_len = 0;
     int64_t chain_steps = 0;      // rank steps in the chain phase (point + interval)
     int64_t fixup_steps = 0;      // rank steps replayed by fix-up passes
-    int64_t chain_takeover = 0;   // neighbour positions completed by chain lanes after their own chunk
+    int64_t fixup_index_steps = 0;  // fix-up steps whose interval spanned more than 64 rows (read the index)
     int64_t fixup_passes = 0;
     int64_t fixup_run_max = 0;    // most chunks one fix-up lane completed
     int64_t key_syms = 0;         // symbols per initial sort key
