@@ -38,7 +38,7 @@ struct Chunk {
     int32_t len;    // symbols in the chunk
     int32_t last;   // 1 if the chunk ends at the strand's sentinel
     int32_t first;  // 1 if the chunk starts at the strand's first symbol
-    int32_t pad;    // index of the chunk's first fix-up segment
+    int32_t pad;
 };
 
 // Sort key of a new suffix at position p:
@@ -221,15 +221,27 @@ __global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     if (wide) atomicAdd(&stats[1], (unsigned long long)wide);
 }
 
+// Steps of a fix-up segment (see k_fix_compose).
+constexpr int FIX_SEG = 256;
+
 // After the chains: a chunk's first position is exact (ready) unless the
-// whole chunk is unresolved.
+// whole chunk is unresolved; segn = number of fix-up segments of the chunk.
 __global__ void k_chain_join(const Chunk *__restrict__ ch, int64_t nch, const int32_t *__restrict__ unres,
-                             int32_t *__restrict__ ready, unsigned long long *__restrict__ stats) {
+                             const int32_t *__restrict__ nwu, int32_t *__restrict__ ready,
+                             uint32_t *__restrict__ segn, unsigned long long *__restrict__ stats) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nch) return;
-    const int32_t u = unres[i];
+    const int32_t u = unres[i], nw = nwu[i];
     ready[i] = u < ch[i].len ? 1 : 0;
+    segn[i] = u > nw ? (uint32_t)((u - nw + FIX_SEG - 1) / FIX_SEG) : 0u;
     if (u) atomicAdd(&stats[0], (unsigned long long)u);
+}
+
+// The fix-up segments, one entry each: the chunk it belongs to.
+__global__ void k_seg_list(const uint32_t *__restrict__ segoff, int64_t nch, uint32_t *__restrict__ owner) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nch) return;
+    for (uint32_t sg = segoff[i]; sg < segoff[i + 1]; ++sg) owner[sg] = (uint32_t)i;
 }
 
 // The fix-up. In chunk i's unresolved end, number the steps t = 0, 1, ...
@@ -246,45 +258,82 @@ __global__ void k_chain_join(const Chunk *__restrict__ ch, int64_t nch, const in
 // index steps and the segment masks only, recording every segment's entry
 // value, and k_fix_keys replays every segment from its entry value, writing
 // the keys (all segments at once).
-constexpr int FIX_SEG = 256;
 
-// Bits of src, lowest first, placed on the set bits of mask, lowest first.
-__device__ __forceinline__ uint64_t deposit_bits(uint64_t src, uint64_t mask) {
-    uint64_t r = 0;
-    while (mask && src) {
-        const uint64_t low = mask & (~mask + 1ull);
-        if (src & 1ull) r |= low;
-        src >>= 1;
-        mask ^= low;
+// The r-th set bit of m (r below popcount(m)), as a one-bit mask.
+__device__ __forceinline__ uint64_t nth_set_bit(uint64_t m, int r) {
+    int pos = 0;
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        const int cnt = __popcll(m & low_mask(sh));
+        if (r >= cnt) {
+            r -= cnt;
+            m >>= sh;
+            pos += sh;
+        }
     }
-    return r;
+    return 1ull << pos;
 }
 
-// Segment k of chunk i (lanes k-major: one wave covers 64 chunks at the same
-// k) folds the masks of its steps t0 .. t1 - 1.
-__global__ void k_fix_compose(const Chunk *__restrict__ ch, int64_t nch, int32_t segs_max,
-                              const uint64_t *__restrict__ M, const int32_t *__restrict__ ulen,
-                              const int32_t *__restrict__ nwu, uint64_t *__restrict__ HS) {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= nch * (int64_t)segs_max) return;
-    const int64_t i = g % nch;
-    const int32_t k = (int32_t)(g / nch);
+// Bits of src, lowest first, placed on the set bits of mask, lowest first:
+// the set bits of mask whose rank r has bit r of src clear are dropped
+// (usually none: every occurrence in the interval goes on with the step's
+// symbol). Dropping the highest rank first leaves the lower ranks in place.
+__device__ __forceinline__ uint64_t deposit_bits(uint64_t src, uint64_t mask) {
+    uint64_t drop = ~src & low_mask(__popcll(mask));
+    while (drop) {
+        const int r = 63 - __clzll((long long)drop);
+        mask &= ~nth_set_bit(mask, r);
+        drop &= ~(1ull << r);
+    }
+    return mask;
+}
+
+// Word q of an 8-word line held as four 16-byte vectors.
+__device__ __forceinline__ uint64_t line_word(const uint4 (&v)[4], int q) {
+    const uint4 &x = v[q >> 1];
+    return (q & 1) ? ((uint64_t)x.w << 32 | x.z) : ((uint64_t)x.y << 32 | x.x);
+}
+
+__device__ __forceinline__ void load_line(const uint64_t *__restrict__ a, int64_t base, uint4 (&v)[4]) {
+    const uint4 *src = (const uint4 *)(a + base);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = src[j];
+}
+
+// Segment s of the list folds the masks of its steps, walking the
+// 8-position lines of M from the one holding the segment's first position
+// down (the next line is requested while the current one is used). Lines
+// are read whole: M is padded to a whole line past its end.
+__global__ void k_fix_compose(const Chunk *__restrict__ ch, const uint32_t *__restrict__ owner,
+                              const uint32_t *__restrict__ segoff, int64_t nseg, const uint64_t *__restrict__ M,
+                              const int32_t *__restrict__ ulen, const int32_t *__restrict__ nwu,
+                              uint64_t *__restrict__ HS) {
+    const int64_t sg = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (sg >= nseg) return;
+    const uint32_t i = owner[sg];
+    const int64_t k = sg - (int64_t)segoff[i];
     const int32_t u = ulen[i];
-    const int64_t t0 = (int64_t)nwu[i] + (int64_t)k * FIX_SEG;
-    if (t0 >= u) return;
+    const int64_t t0 = (int64_t)nwu[i] + k * FIX_SEG;
     const int64_t t1 = t0 + FIX_SEG < u ? t0 + FIX_SEG : u;
     const Chunk c = ch[i];
-    const int64_t top = c.p0 + c.len - 1;  // position of step 0
-    uint64_t H = M[top - t0];
-    for (int64_t tb = t0 + 1; tb < t1; tb += 8) {
-        uint64_t m[8];
+    const int64_t top = c.p0 + c.len - 1;
+    const int64_t ps = top - t0, pe = top - (t1 - 1);  // positions ps down to pe
+    const int64_t bend = pe >> 3;
+    uint4 cur[4], nxt[4];
+    load_line(M, (ps >> 3) << 3, cur);
+    uint64_t H = ~0ull;  // the identity map
+    for (int64_t b = ps >> 3; b >= bend; --b) {
+        if (b > bend) load_line(M, (b - 1) << 3, nxt);
+        const int64_t base = b << 3;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) m[q] = tb + q < t1 ? M[top - tb - q] : 0ull;
+        for (int q = 7; q >= 0; --q) {
+            const int64_t p = base + q;
+            if (p <= ps && p >= pe) H = p == ps ? line_word(cur, q) : deposit_bits(line_word(cur, q), H);
+        }
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (tb + q < t1) H = deposit_bits(m[q], H);
+        for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
     }
-    HS[c.pad + k] = H;
+    HS[sg] = H;
 }
 
 // Fix-up pass: a chunk with an unresolved end whose right neighbour's first
@@ -303,7 +352,8 @@ __global__ void k_fix_compose(const Chunk *__restrict__ ch, int64_t nch, int32_t
 __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
                         int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K,
                         int32_t *__restrict__ unres, const int32_t *__restrict__ nwu,
-                        const uint64_t *__restrict__ HS, int32_t *__restrict__ SD, int64_t *__restrict__ EX, const int32_t *__restrict__ ready_in,
+                        const uint32_t *__restrict__ segoff, const uint64_t *__restrict__ HS,
+                        int32_t *__restrict__ SD, int64_t *__restrict__ EX, const int32_t *__restrict__ ready_in,
                         int32_t *__restrict__ ready_out,
                         unsigned long long *__restrict__ stats, int32_t *__restrict__ guard) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -343,7 +393,7 @@ __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
                 bad = true;
                 d = d < 0 ? 0 : 64;
             }
-            int64_t seg = c.pad;
+            int64_t seg = segoff[j];
             for (int64_t t0 = nw; t0 < u; t0 += FIX_SEG, ++seg) {
                 SD[seg] = (int32_t)d;
                 d = __popcll(HS[seg] & low_mask((int)d));
@@ -377,72 +427,75 @@ __global__ void k_fixup(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk 
     atomicMax(&stats[3], run);
 }
 
-// Segment k of chunk i replays its steps from its entry value and writes
-// their keys; the records of the next 8 steps are requested while the
-// current 8 are walked.
-__global__ void k_fix_keys(const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch, int64_t nch,
-                           int32_t segs_max, int64_t m1, int w, uint64_t *__restrict__ K,
-                           const uint64_t *__restrict__ M, const int32_t *__restrict__ ulen,
-                           const int32_t *__restrict__ nwu, const int32_t *__restrict__ SD,
-                           int32_t *__restrict__ guard) {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= nch * (int64_t)segs_max) return;
-    const int64_t i = g % nch;
-    const int32_t k = (int32_t)(g / nch);
+// Segment s of the list replays its steps from its entry value and writes
+// their keys, a whole 8-position line of K at a time where the segment
+// covers the line (the next line's records are requested while the current
+// one is walked). K and M are padded to a whole line past their end.
+__global__ void k_fix_keys(const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
+                           const uint32_t *__restrict__ owner, const uint32_t *__restrict__ segoff, int64_t nseg,
+                           int64_t m1, int w, uint64_t *__restrict__ K, const uint64_t *__restrict__ M,
+                           const int32_t *__restrict__ ulen, const int32_t *__restrict__ nwu,
+                           const int32_t *__restrict__ SD, int32_t *__restrict__ guard) {
+    const int64_t sg = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (sg >= nseg) return;
+    const uint32_t i = owner[sg];
+    const int64_t k = sg - (int64_t)segoff[i];
     const int32_t u = ulen[i];
-    const int64_t t0 = (int64_t)nwu[i] + (int64_t)k * FIX_SEG;
-    if (t0 >= u) return;
+    const int64_t t0 = (int64_t)nwu[i] + k * FIX_SEG;
     const int64_t t1 = t0 + FIX_SEG < u ? t0 + FIX_SEG : u;
     const Chunk c = ch[i];
     const int lshift = 3 + 3 * w, wsh = 3 * (w - 1);
-    const int64_t seg = c.pad + k;
-    int64_t d = SD[seg];
+    int d = SD[sg];
     if (d < 0 || d > 64) {  // no entry: the fix-up passes did not reach this chunk
         atomicOr(guard, GUARD_CHAIN);
         return;
     }
     const int64_t top = c.p0 + c.len - 1;
     const int64_t ps = top - t0, pe = top - (t1 - 1);  // positions ps down to pe
+    const int64_t bend = pe >> 3;
+    const uint64_t *Qw = (const uint64_t *)Q;
     uint64_t packed = pack_ahead(Q, ps + 1, w);
-    KeyWindow win;
-    win.init();
-    BackSyms sy;
-    sy.init(Q, ps);
-    uint64_t nk[8], nm[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        nk[q] = ps - q >= pe ? K[ps - q] : 0ull;
-        nm[q] = ps - q >= pe ? M[ps - q] : 0ull;
-    }
+    uint4 ck[4], cm[4], nk[4], nm[4];
+    load_line(K, (ps >> 3) << 3, ck);
+    load_line(M, (ps >> 3) << 3, cm);
     bool bad = false;
-    for (int64_t pb = ps; pb >= pe; pb -= 8) {
-        uint64_t ck[8], cm[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            ck[q] = nk[q];
-            cm[q] = nm[q];
+    for (int64_t b = ps >> 3; b >= bend; --b) {
+        if (b > bend) {
+            load_line(K, (b - 1) << 3, nk);
+            load_line(M, (b - 1) << 3, nm);
         }
-        if (pb - 8 >= pe) {
+        const int64_t base = b << 3;
+        const uint64_t qw = Qw[b], qp = b > 0 ? Qw[b - 1] : 0ull;
+        uint64_t kw[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                nk[q] = pb - 8 - q >= pe ? K[pb - 8 - q] : 0ull;
-                nm[q] = pb - 8 - q >= pe ? M[pb - 8 - q] : 0ull;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t p = pb - q;
-            if (p >= pe) {
-                const uint32_t a = sy.at(p);
-                const uint32_t emit = sy.before(p);
+        for (int q = 7; q >= 0; --q) {
+            const int64_t p = base + q;
+            kw[q] = 0;
+            if (p <= ps && p >= pe) {
+                const uint32_t a = (uint32_t)(qw >> (8 * q)) & 0xFFu;
+                const uint32_t emit = q ? (uint32_t)(qw >> (8 * (q - 1))) & 0xFFu : (uint32_t)(qp >> 56);
                 packed = ((uint64_t)a << wsh) | (packed >> 3);
-                d = __popcll(cm[q] & low_mask((int)d));
-                if (cm[q] == 0ull) bad = true;  // a step of the narrow part always has a mask
-                const int64_t l = (int64_t)ck[q] + d;
-                win.push(make_key(l - m1, packed, emit, lshift), true);
-                if ((p & 7) == 0 || p == pe) win.flush(K, p);
-                sy.next(p);
+                const uint64_t mq = line_word(cm, q);
+                if (mq == 0ull) bad = true;  // a step of the narrow part always has a mask
+                d = __popcll(mq & low_mask(d));
+                kw[q] = make_key((int64_t)line_word(ck, q) + d - m1, packed, emit, lshift);
             }
+        }
+        if (base >= pe && base + 7 <= ps) {
+            uint4 *dst = (uint4 *)(K + base);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                dst[j] = make_uint4((uint32_t)kw[2 * j], (uint32_t)(kw[2 * j] >> 32), (uint32_t)kw[2 * j + 1],
+                                    (uint32_t)(kw[2 * j + 1] >> 32));
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (base + q <= ps && base + q >= pe) K[base + q] = kw[q];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            ck[j] = nk[j];
+            cm[j] = nm[j];
         }
     }
     if (bad) atomicOr(guard, GUARD_CHAIN);
@@ -1945,7 +1998,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     }
 
     DBuf K, stats, guardb;
-    RB3_ALLOC(K, &c, n2 * sizeof(uint64_t));
+    RB3_ALLOC(K, &c, (n2 + 8) * sizeof(uint64_t));  // (a whole line past the end: the fix-up reads lines)
     RB3_ALLOC(guardb, &c, sizeof(int32_t));
     RB3_HIP(hipMemsetAsync(guardb.p, 0, sizeof(int32_t), c.stream));
     int32_t *guard = guardb.as<int32_t>();
@@ -1978,22 +2031,17 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         st.chunks = nch;
         st.chunk_len = CL;
         st.chain_steps = n2 - m2;
-        // fix-up segments: at most ceil(len / FIX_SEG) per chunk
-        int64_t nseg = 0, maxlen = 0;
-        for (Chunk &ck : chunks) {
-            ck.pad = (int32_t)nseg;
-            nseg += (ck.len + FIX_SEG - 1) / FIX_SEG;
-            maxlen = ck.len > maxlen ? ck.len : maxlen;
-        }
-        const int32_t segs_max = (int32_t)((maxlen + FIX_SEG - 1) / FIX_SEG);
-        DBuf d_ch, unres, ulen, nwu, recm, readyA, readyB, pend;
+        DBuf d_ch, unres, ulen, nwu, segn, recm, readyA, readyB, pend;
         RB3_ALLOC(d_ch, &c, nch * sizeof(Chunk));
         RB3_ALLOC(unres, &c, nch * sizeof(int32_t));
         RB3_ALLOC(ulen, &c, nch * sizeof(int32_t));
         RB3_ALLOC(nwu, &c, nch * sizeof(int32_t));
+        RB3_ALLOC(segn, &c, (nch + 1) * sizeof(uint32_t));
+        RB3_HIP(hipMemsetAsync(segn.p, 0, (nch + 1) * sizeof(uint32_t), c.stream));
         // the chains' records for unresolved positions (with K, which holds
-        // their interval low ends until the fix-up writes their keys)
-        RB3_ALLOC(recm, &c, n2 * sizeof(uint64_t));
+        // their interval low ends until the fix-up writes their keys), padded
+        // to a whole line past the end
+        RB3_ALLOC(recm, &c, (n2 + 8) * sizeof(uint64_t));
         RB3_ALLOC(readyA, &c, (nch + 1) * sizeof(int32_t));
         RB3_ALLOC(readyB, &c, (nch + 1) * sizeof(int32_t));
         RB3_ALLOC(pend, &c, sizeof(int32_t));
@@ -2016,33 +2064,45 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                        ulen.as<int32_t>(), nwu.as<int32_t>(), stats.as<unsigned long long>());
         }
         RB3_LAUNCH("chain_join", k_chain_join, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
-                   d_ch.as<Chunk>(), nch, unres.as<int32_t>(), readyA.as<int32_t>(), stats.as<unsigned long long>());
+                   d_ch.as<Chunk>(), nch, unres.as<int32_t>(), nwu.as<int32_t>(), readyA.as<int32_t>(),
+                   segn.as<uint32_t>(), stats.as<unsigned long long>());
+        // fix-up segments: offsets per chunk (exclusive scan), total at nch
+        RB3_TRY(scan_u32(c, segn.as<uint32_t>(), segn.as<uint32_t>(), nch + 1, false, false, nullptr));
         unsigned long long hs[4];
+        uint32_t nseg_h = 0;
         RB3_HIP(hipMemcpyAsync(hs, stats.p, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
+        RB3_HIP(hipMemcpyAsync(&nseg_h, segn.as<uint32_t>() + nch, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               c.stream));
         RB3_HIP(hipStreamSynchronize(c.stream));
+        const int64_t nseg = nseg_h;
         st.fixup_steps = (int64_t)hs[0];
         st.chain_steps += (int64_t)hs[1];
         int32_t *rin = readyA.as<int32_t>(), *rout = readyB.as<int32_t>();
         int64_t passes = 0;
         if (hs[0] > 0) {
-            DBuf HS, SD, EX;
-            RB3_ALLOC(HS, &c, (nseg > 0 ? nseg : 1) * sizeof(uint64_t));
-            RB3_ALLOC(SD, &c, (nseg > 0 ? nseg : 1) * sizeof(int32_t));
+            DBuf HS, SD, EX, owner;
+            const int64_t ns1 = nseg > 0 ? nseg : 1;
+            RB3_ALLOC(HS, &c, ns1 * sizeof(uint64_t));
+            RB3_ALLOC(SD, &c, ns1 * sizeof(int32_t));
+            RB3_ALLOC(owner, &c, ns1 * sizeof(uint32_t));
             RB3_ALLOC(EX, &c, (nch + 1) * sizeof(int64_t));
-            RB3_HIP(hipMemsetAsync(SD.p, 0xFF, (nseg > 0 ? nseg : 1) * sizeof(int32_t), c.stream));
+            RB3_HIP(hipMemsetAsync(SD.p, 0xFF, ns1 * sizeof(int32_t), c.stream));
             RB3_HIP(hipMemsetAsync(EX.p, 0xFF, (nch + 1) * sizeof(int64_t), c.stream));
-            const int64_t nlanes = nch * (int64_t)segs_max;
-            RB3_LAUNCH("fix_compose", k_fix_compose, grid_for(nlanes, 256, 1 << 30), dim3(256), 0, c.stream,
-                       d_ch.as<Chunk>(), nch, segs_max, recm.as<uint64_t>(), ulen.as<int32_t>(), nwu.as<int32_t>(),
-                       HS.as<uint64_t>());
+            if (nseg > 0) {
+                RB3_LAUNCH("fix_list", k_seg_list, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
+                           segn.as<uint32_t>(), nch, owner.as<uint32_t>());
+                RB3_LAUNCH("fix_compose", k_fix_compose, grid_for(nseg, 256, 1 << 30), dim3(256), 0, c.stream,
+                           d_ch.as<Chunk>(), owner.as<uint32_t>(), segn.as<uint32_t>(), nseg, recm.as<uint64_t>(),
+                           ulen.as<int32_t>(), nwu.as<int32_t>(), HS.as<uint64_t>());
+            }
             for (;;) {
                 RB3_HIP(hipMemcpyAsync(rout, rin, (nch + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice,
                                        c.stream));
                 RB3_HIP(hipMemsetAsync(pend.p, 0, sizeof(int32_t), c.stream));
                 RB3_LAUNCH("chain_fixup", k_fixup, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
                            b1, d_Q, d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), unres.as<int32_t>(),
-                           nwu.as<int32_t>(), HS.as<uint64_t>(), SD.as<int32_t>(), EX.as<int64_t>(), rin, rout,
-                           stats.as<unsigned long long>(), guard);
+                           nwu.as<int32_t>(), segn.as<uint32_t>(), HS.as<uint64_t>(), SD.as<int32_t>(),
+                           EX.as<int64_t>(), rin, rout, stats.as<unsigned long long>(), guard);
                 RB3_LAUNCH("chain_left", k_unres_count, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
                            unres.as<int32_t>(), nch, pend.as<int32_t>());
                 int32_t hp = 0;
@@ -2056,9 +2116,11 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                     return RB3_EDEVICE;
                 }
             }
-            RB3_LAUNCH("fix_keys", k_fix_keys, grid_for(nlanes, 256, 1 << 30), dim3(256), 0, c.stream,
-                       d_Q, d_ch.as<Chunk>(), nch, segs_max, m1, w, K.as<uint64_t>(), recm.as<uint64_t>(),
-                       ulen.as<int32_t>(), nwu.as<int32_t>(), SD.as<int32_t>(), guard);
+            if (nseg > 0)
+                RB3_LAUNCH("fix_keys", k_fix_keys, grid_for(nseg, 256, 1 << 30), dim3(256), 0, c.stream, d_Q,
+                           d_ch.as<Chunk>(), owner.as<uint32_t>(), segn.as<uint32_t>(), nseg, m1, w,
+                           K.as<uint64_t>(), recm.as<uint64_t>(), ulen.as<int32_t>(), nwu.as<int32_t>(),
+                           SD.as<int32_t>(), guard);
             RB3_HIP(hipMemcpyAsync(hs, stats.p, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipStreamSynchronize(c.stream));
             st.fixup_index_steps = (int64_t)hs[2];
