@@ -46,10 +46,18 @@ def algorithmic_bytes(kernel: str, st: dict, steps: int) -> float | None:
     counters)."""
     n1, n2, m2 = st["n1"], st["n2"], st["m2"]
     per_step = {
-        # one random 64-byte block per rank step, plus the symbol read and the
-        # 8-byte key written per new suffix
-        "chain": st["chain_steps"] * BLOCK_BYTES + (n2 - m2) * 1 + n2 * 8,
-        "chain_fixup": st["fixup_steps"] * (BLOCK_BYTES + 1 + 8),
+        # one random 64-byte block per rank step (two where the interval's
+        # ends lie in different blocks), the symbol read and the 8-byte key
+        # (or interval low end) written per new suffix, and the 8-byte row
+        # mask recorded per unresolved step
+        "chain": st["chain_steps"] * BLOCK_BYTES + (n2 - m2) * 1 + n2 * 8 + st["fixup_steps"] * 8,
+        # fix-up steps over wide intervals: a block, the recorded low end, the
+        # symbol, the key written
+        "chain_fixup": st.get("fixup_index_steps", 0) * (BLOCK_BYTES + 8 + 1 + 8),
+        # the other fix-up steps: the mask read to fold segments, then the
+        # mask, low end and symbol read and the key written to replay them
+        "fix_compose": (st["fixup_steps"] - st.get("fixup_index_steps", 0)) * 8,
+        "fix_keys": (st["fixup_steps"] - st.get("fixup_index_steps", 0)) * (8 + 8 + 1 + 8),
         # per pass: key 8 B read for the histogram
         "sort_hist": n2 * 8 * max(1, -(-st["sort_bits"] // 8)),
         # per pass: key + value read and written (the first pass has no value

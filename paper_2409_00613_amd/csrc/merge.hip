@@ -2007,7 +2007,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
 
     // ---- 1. insertion ranks ----
     if (n1 > 0) {
-        int64_t CL = c.chunk_len > 0 ? c.chunk_len : 4096;
+        int64_t CL = c.chunk_len > 0 ? c.chunk_len : 2048;
         if (CL > (1 << 30)) CL = 1 << 30;
         std::vector<Chunk> chunks;
         std::vector<int64_t> first_chunk;  // per strand, for the one-launch-per-string form
