@@ -889,35 +889,56 @@ __global__ void __launch_bounds__(TG_THREADS) k_tie_groups(const uint64_t *__res
     if (threadIdx.x < 32 && hist[threadIdx.x]) atomicAdd(&ghist[threadIdx.x], hist[threadIdx.x]);
 }
 
-// Eight symbols of the new strands starting at position q of Q, the first in
-// the most significant byte, so that unsigned order is lexicographic order.
-// Bytes after a sentinel (code 0) belong to the next strand and are cleared.
-// Q holds 16 readable bytes past its last symbol.
-__device__ __forceinline__ uint64_t load_chunk(const uint8_t *__restrict__ Q, int64_t q) {
-    const uint64_t *w = (const uint64_t *)(Q + (q & ~(int64_t)7));
-    const int sh = (int)(q & 7) * 8;
-    uint64_t v = w[0];
-    if (sh) v = (v >> sh) | (w[1] << (64 - sh));
-    v = __builtin_bswap64(v);
-    // codes are below 0x80: a byte is zero iff adding 0x7F leaves its top bit clear
-    const uint64_t t = (v & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full;
-    const uint64_t z = ~(t | v) & 0x8080808080808080ull;
-    if (z) v &= ~0ull << (56 - (__clzll((long long)z) & ~7));
+// Sixteen symbols of the new strands starting at position q, from the
+// batch packed 4 bits per symbol (k_pack_nibbles), the first in the most
+// significant nibble, so that unsigned order is lexicographic order.
+// Symbols after a sentinel (code 0) belong to the next strand and are
+// cleared. QN holds a readable word past the one holding its last symbol.
+__device__ __forceinline__ uint64_t load_chunk(const uint64_t *__restrict__ QN, int64_t q) {
+    const int64_t j = q >> 4;
+    const int sh = (int)(q & 15) * 4;
+    uint64_t v = QN[j];
+    if (sh) v = (v << sh) | (QN[j + 1] >> (64 - sh));
+    // codes are below 8: a nibble is zero iff adding 7 leaves its top bit clear
+    const uint64_t t = (v & 0x7777777777777777ull) + 0x7777777777777777ull;
+    const uint64_t z = ~(t | v) & 0x8888888888888888ull;
+    if (z) v &= ~0ull << (60 - (__clzll((long long)z) & ~3));
     return v;
 }
 
-// A chunk holds a sentinel iff it has a zero byte (symbol codes are 1..5).
+// A chunk holds a sentinel iff it has a zero nibble (symbol codes are 1..5).
 __device__ __forceinline__ bool chunk_has_sentinel(uint64_t v) {
-    const uint64_t t = (v & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full;
-    return (~(t | v) & 0x8080808080808080ull) != 0;
+    const uint64_t t = (v & 0x7777777777777777ull) + 0x7777777777777777ull;
+    return (~(t | v) & 0x8888888888888888ull) != 0;
+}
+
+// The batch 4 bits per symbol, 16 symbols per word, the first in the most
+// significant nibble; positions past n2 read as 0.
+__global__ void k_pack_nibbles(const uint8_t *__restrict__ Q, int64_t n2, int64_t nw, uint64_t *__restrict__ QN) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nw;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t v = 0;
+        if (16 * j < n2) {
+            // Q is 8-byte aligned with 16 readable bytes past its last symbol
+            const uint64_t *w = (const uint64_t *)Q + 2 * j;
+            const uint64_t w0 = w[0], w1 = w[1];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const uint64_t c = ((t < 8 ? w0 >> (8 * t) : w1 >> (8 * (t - 8))) & 0xFull);
+                if (16 * j + t < n2) v |= c << (60 - 4 * t);
+            }
+        }
+        QN[j] = v;
+    }
 }
 
 // The tie kernels below compare suffixes that share their sort key, i.e.
 // their insertion rank l and first symbol. Their order is then plain string
-// order from the second symbol on, which they read eight symbols at a time
-// (one chunk). Two chunks that are equal and hold a sentinel belong to
+// order from the second symbol on, which they read sixteen symbols at a time
+// (one chunk, CHUNK_SYMS). Two chunks that are equal and hold a sentinel belong to
 // suffixes reaching their strands' ends together: strand order, which is
 // position order in Q, decides.
+constexpr int CHUNK_SYMS = 16;  // symbols per chunk
 constexpr int WALK_DEPTHS = 4;  // chunks per member per load round
 
 
@@ -932,7 +953,7 @@ constexpr int LANES_MAX_DEPTH = 1024;  // symbols
 // queue is the pair list (entries 0..np) followed by the 3..8 list. Members
 // are held in registers; every loop over them is unrolled.
 template <bool SMP>
-__global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restrict__ Q, int64_t n2,
+__global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint64_t *__restrict__ Q, int64_t n2,
                                                         const uint32_t *__restrict__ SV,
                                                         const uint32_t *__restrict__ plist, int64_t np,
                                                         const uint32_t *__restrict__ slist, int64_t ns,
@@ -1000,7 +1021,7 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restric
         for (int i = 0; i < SMALL_MAXK; ++i)
 #pragma unroll
             for (int t = 0; t < SMALL_DEPTHS; ++t) {
-                int64_t q = (int64_t)pos[i] + d0 + 8 * t;
+                int64_t q = (int64_t)pos[i] + d0 + CHUNK_SYMS * t;
                 kv[i][t] = (act[i] && q < n2) ? load_chunk(Q, q) : ~0ull;
             }
         bool any = true;
@@ -1067,7 +1088,7 @@ __global__ void __launch_bounds__(LANES_WG) k_tie_lanes(const uint8_t *__restric
                 act[i] = nact[i];
             }
         }
-        d0 += 8 * SMALL_DEPTHS;
+        d0 += CHUNK_SYMS * SMALL_DEPTHS;
         if (!any) {
 #pragma unroll
             for (int i = 0; i < SMALL_MAXK; ++i)
@@ -1111,7 +1132,7 @@ constexpr int DEEP_DPL = 4;  // depths per lane per window
 // splits, applies the same refinement as k_tie_lanes there (all lanes keep
 // the same copy of the members' state), and goes on from the next depth.
 template <bool SMP>
-__global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__ Q, int64_t n2,
+__global__ void __launch_bounds__(256, 4) k_tie_deep(const uint64_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ dlist,
                                                   const uint32_t *__restrict__ dcount,
@@ -1163,7 +1184,7 @@ __global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__
             uint64_t kv[DEEP_DPL];
 #pragma unroll
             for (int j = 0; j < DEEP_DPL; ++j) {
-                int64_t q = (int64_t)mypos + d0 + 8 * (ti * DEEP_DPL + j);
+                int64_t q = (int64_t)mypos + d0 + CHUNK_SYMS * (ti * DEEP_DPL + j);
                 kv[j] = (mi < k && myact && q < n2) ? load_chunk(Q, q) : ~0ull;
             }
             int u0 = 0;  // first depth of the window not yet processed
@@ -1268,7 +1289,7 @@ __global__ void __launch_bounds__(256, 4) k_tie_deep(const uint8_t *__restrict__
 #pragma unroll
             for (int i = 0; i < SMALL_MAXK; ++i)
                 if (i == mi) myact = act[i];
-            d0 += 8 * WIN;
+            d0 += CHUNK_SYMS * WIN;
         }
         maxdepth = (uint32_t)d0 > maxdepth ? (uint32_t)d0 : maxdepth;
         if (lane < k) {
@@ -1310,7 +1331,7 @@ __device__ __forceinline__ uint64_t lane_read64(uint64_t v, int l) {
 // the symbols come from the group's run of sorted keys (coalesced). The next
 // group's members are fetched while the current one is walked.
 template <int MPL, bool SMP>
-__global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q, int64_t n2,
+__global__ void __launch_bounds__(256) k_tie_walk(const uint64_t *__restrict__ Q, int64_t n2,
                                                   const uint32_t *__restrict__ SV,
                                                   const uint32_t *__restrict__ glist, int64_t ng,
                                                   uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
@@ -1366,7 +1387,7 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q,
             sub[s] = 0;
             act[s] = i < k;
         }
-        for (int64_t d0 = 1;; d0 += 8 * WALK_DEPTHS) {
+        for (int64_t d0 = 1;; d0 += CHUNK_SYMS * WALK_DEPTHS) {
             bool any = false;
 #pragma unroll
             for (int s = 0; s < MPL; ++s) any |= __ballot(act[s]) != 0;
@@ -1376,7 +1397,7 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q,
             for (int s = 0; s < MPL; ++s)
 #pragma unroll
                 for (int t = 0; t < WALK_DEPTHS; ++t) {
-                    const int64_t q = (int64_t)p[s] + d0 + 8 * t;
+                    const int64_t q = (int64_t)p[s] + d0 + CHUNK_SYMS * t;
                     kv[s][t] = (act[s] && q < n2) ? load_chunk(Q, q) : ~0ull;
                 }
 #pragma unroll
@@ -1499,7 +1520,7 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint8_t *__restrict__ Q,
 // members carry different symbols. A split moves members, so the round ends
 // there and the next one loads from the following depth.
 template <int T, int MPT, int DEPTHS, bool SMP>
-__global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, int64_t n2, const uint32_t *__restrict__ SV,
+__global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ Q, int64_t n2, const uint32_t *__restrict__ SV,
                                                  const uint32_t *__restrict__ glist, int64_t ng,
                                                  uint64_t *__restrict__ SK, uint32_t *__restrict__ PF,
                                                  int32_t srate, int32_t *__restrict__ guard,
@@ -1543,7 +1564,7 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, 
                 const int64_t p = o < k ? (int64_t)spos[o] : 0;
 #pragma unroll
                 for (int t = 0; t < DEPTHS; ++t) {
-                    const int64_t q = p + d0 + 8 * t;
+                    const int64_t q = p + d0 + CHUNK_SYMS * t;
                     kv[j][t] = a ? (q < n2 ? load_chunk(Q, q) : ~0ull) : 0ull;
                     reads += a ? 1u : 0u;
                 }
@@ -1647,7 +1668,7 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint8_t *__restrict__ Q, 
                 break;
             }
             if (!any) break;
-            d0 += 8 * used;
+            d0 += CHUNK_SYMS * used;
         }
         maxd = d0 > maxd ? d0 : maxd;
         // every thread read gkey before the first barrier of this group
@@ -2220,7 +2241,14 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         if (hs2[TG_CLASSES] > TG_BOUND[TG_CLASSES - 1]) {
             need_doubling = true;
         } else if (st.tie_groups > 0) {
-            const uint8_t *Qc = d_Q;
+            // the batch 4 bits per symbol for the comparisons (a word past the
+            // one holding the last symbol stays readable)
+            DBuf qn;
+            const int64_t nqw = (n2 >> 4) + 3;
+            RB3_ALLOC(qn, &c, nqw * sizeof(uint64_t));
+            RB3_LAUNCH("tie_pack", k_pack_nibbles, grid_for(nqw, 256, 1 << 16), dim3(256), 0, c.stream, d_Q, n2, nqw,
+                       qn.as<uint64_t>());
+            const uint64_t *Qc = qn.as<uint64_t>();
             DBuf qh, dl;
             const int64_t nq = (int64_t)hs2[0] + hs2[1];
             if (nq > 0) {
