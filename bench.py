@@ -474,7 +474,7 @@ def incremental_bench(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if idx is None:
-            idx = rb3.rb3_build(bdev, batch.lens, allocator=alloc)
+            idx = rb3.rb3_build(bdev, batch.lens, allocator=alloc, chunk_len=args.chunk)
         else:
             idx.merge(bdev, batch.lens)
         torch.cuda.synchronize()
@@ -489,7 +489,8 @@ def incremental_bench(args):
         total_s += dt
         batches.append({"batch": b, "n1": st["n1"], "n2": new_suffixes, "n": n, "ms": round(dt * 1e3, 1),
                         "suffixes_per_s": round(new_suffixes / dt, 1), "tie_max_depth": st["tie_max_depth"],
-                        "max_group": st["max_group"], "tie_doubling": st["tie_doubling"]})
+                        "max_group": st["max_group"], "tie_doubling": st["tie_doubling"],
+                        "fixup_steps": st["fixup_steps"], "fixup_index_steps": st["fixup_index_steps"]})
         log(f"batch {b}: {per} haplotypes generated in {gen_s:.1f} s; {new_suffixes} new suffixes merged "
             f"into n1={st['n1']} in {dt * 1e3:.1f} ms ({new_suffixes / dt / 1e9:.2f} G/s); n={n}")
     rb3.rb3_prof_enable(False)

@@ -76,7 +76,8 @@ typedef struct rb3_opts {
     rb3_alloc_fn dev_alloc; /* NULL: hipMalloc/hipFree */
     rb3_free_fn dev_free;
     void *alloc_ctx;
-    int64_t chunk_len;     /* LF-chain chunk length for merges; 0 = default */
+    int64_t chunk_len;     /* LF-chain chunk length for merges; 0 = default (2048, doubled
+                              while a batch would make more than 2^17 chunks) */
     int32_t launch_per_string; /* 0 (default): one launch of the LF-chain
                               kernel covers every chunk of every new string
                               of a merge. 1: the plain form, one launch per

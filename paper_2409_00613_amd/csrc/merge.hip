@@ -2028,7 +2028,14 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
 
     // ---- 1. insertion ranks ----
     if (n1 > 0) {
-        int64_t CL = c.chunk_len > 0 ? c.chunk_len : 2048;
+        // default: 2048 positions, doubled while the batch would make more than
+        // 2^17 chunks (past that many lanes, random block reads stop gaining
+        // throughput, while the unresolved share of each chunk still grows)
+        int64_t CL = c.chunk_len;
+        if (CL <= 0) {
+            CL = 2048;
+            while (CL < (1 << 20) && n2 / CL > (1 << 17)) CL *= 2;
+        }
         if (CL > (1 << 30)) CL = 1 << 30;
         std::vector<Chunk> chunks;
         std::vector<int64_t> first_chunk;  // per strand, for the one-launch-per-string form
