@@ -945,7 +945,7 @@ constexpr int WALK_DEPTHS = 4;  // chunks per member per load round
 constexpr int SMALL_MAXK = 8;
 constexpr int SMALL_DEPTHS = 4;
 constexpr int LANES_WG = 256;
-constexpr int LANES_MAX_DEPTH = 1024;  // symbols
+constexpr int LANES_MAX_DEPTH = 2048;  // symbols
 
 // Groups of 2..8 members, one lane per group, persistent: a lane that has
 // ordered its group takes the next one from a shared queue (one atomic per
