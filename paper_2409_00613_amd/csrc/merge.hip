@@ -2103,6 +2103,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                                c.stream));
         RB3_HIP(hipStreamSynchronize(c.stream));
         const int64_t nseg = nseg_h;
+        st.fixup_segments = nseg;
         st.fixup_steps = (int64_t)hs[0];
         st.chain_steps += (int64_t)hs[1];
         int32_t *rin = readyA.as<int32_t>(), *rout = readyB.as<int32_t>();

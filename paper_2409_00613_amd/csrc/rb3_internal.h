@@ -329,6 +329,7 @@ struct MergeStats {
     int64_t chain_steps = 0;      // rank steps in the chain phase (point + interval)
     int64_t fixup_steps = 0;      // rank steps replayed by fix-up passes
     int64_t fixup_index_steps = 0;  // fix-up steps whose interval spanned more than 64 rows (read the index)
+    int64_t fixup_segments = 0;   // segments of the fix-up's folded rank maps
     int64_t fixup_passes = 0;
     int64_t fixup_run_max = 0;    // most chunks one fix-up lane completed
     int64_t key_syms = 0;         // symbols per initial sort key

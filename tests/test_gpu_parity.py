@@ -166,6 +166,50 @@ def test_merge_pangenome_small(chunk_len):
     idx.close()
 
 
+def test_fixup_segments_and_runs():
+    """Unresolved ends longer than one 256-step segment of folded rank maps,
+    and runs of several unresolved chunks: the fix-up's fold, run walk and
+    segment replay against the oracle."""
+    say("case: pangenome merge, 20 kb genome, 8 + 8 haplotypes, 700-position chunks")
+    w = synth.config_pangenome(genome_len=20_000, n_b1=8, n_new=8)
+    idx = rb3.rb3_build(w.b1.data, w.b1.lens, chunk_len=700)
+    idx.merge(w.new.data, w.new.lens)
+    st = idx.merge_stats()
+    codes, lens = _expand(w.b1 + w.new)
+    assert np.array_equal(idx.export(), oracle.bwt(codes, lens))
+    # more segments than chunks: many unresolved ends span several segments
+    assert st["fixup_segments"] > st["chunks"]
+    assert st["fixup_passes"] == 1 and st["fixup_run_max"] >= 2
+    idx.close()
+
+
+def test_fixup_intervals_wider_than_64_rows():
+    """An index holding 70 near-copies of one string: while a new copy's
+    context matches more than 64 of them the chain interval spans more than
+    64 rows, so the fix-up reads the index for those steps, then switches to
+    the recorded row masks as copies drop out."""
+    say("case: 70 near-copies of a 1000-base string in the index, 4 new copies merged")
+    rnd = random.Random(21)
+    base = [rnd.choice("ACGT") for _ in range(1000)]
+
+    def mutated(k):
+        s = list(base)
+        for _ in range(k):
+            i = rnd.randrange(len(s))
+            s[i] = rnd.choice("ACGT".replace(s[i], ""))
+        return "".join(s).encode()
+    old = synth.pack([mutated(rnd.randint(0, 2)) for _ in range(70)])
+    new = synth.pack([mutated(1) for _ in range(4)])
+    idx = rb3.rb3_build(old.data, old.lens, chunk_len=300)
+    idx.merge(new.data, new.lens)
+    st = idx.merge_stats()
+    codes, lens = _expand(old + new)
+    assert np.array_equal(idx.export(), oracle.bwt(codes, lens))
+    assert st["fixup_index_steps"] > 1000
+    assert st["fixup_steps"] > st["fixup_index_steps"]
+    idx.close()
+
+
 def test_incremental_merges_equal_one_build():
     say("case: merge(build(X), Y, Z) == build(X ++ Y ++ Z)")
     w = synth.config_pangenome(genome_len=5_000, n_b1=6, n_new=6)
