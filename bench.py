@@ -522,7 +522,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--genome", type=int, default=4_000_000, help="base genome length")
     ap.add_argument("--chunk", type=int, default=0, help="LF-chain chunk length (0 = library default)")
-    ap.add_argument("--cpu-sample", type=int, default=40_000,
+    ap.add_argument("--cpu-sample", type=int, default=120_000,
                     help="haplotype prefix length for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-smem", action="store_true", help="skip the SMEM serving measurement")
