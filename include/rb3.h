@@ -274,7 +274,10 @@ void rb3_server_free(rb3_server *s);
  * synchronizes those events and reports, per kernel name, the number of
  * launches and the summed GPU time in milliseconds. Names are copied into
  * names[i*32 .. i*32+31] (NUL-terminated). *n_out receives the number of
- * distinct kernels (entries beyond cap are not written).
+ * distinct kernels (entries beyond cap are not written). A merge runs its
+ * tie kernels of different group sizes at the same time on three streams
+ * (joined before the interleave): their times overlap, and each includes
+ * waiting for the compute units the others hold.
  */
 int rb3_prof_enable(int on);
 int rb3_prof_reset(void);
