@@ -258,6 +258,61 @@ def timed_merges(b1, new, steps: int, warmup: int):
     return {"ms": (t1 - t0) / steps * 1e3, "prof": prof, "stats": st, "n_out": n_out}
 
 
+def host_input_merges(b1, new, steps: int):
+    """The same merge fed from host memory (the batch in pinned host memory),
+    every upload inside the timed region. Sequential: each step uploads its
+    batch, then merges it. Overlapped: while a step merges (on the index's own
+    stream), the next step's batch is uploaded on a side stream (default
+    priority) into the other of two device buffers, so the PCIe transfer hides
+    behind the merge."""
+    import torch
+    host = torch.from_numpy(new.data).pin_memory()
+    lens = new.lens.copy()
+    bufs = [torch.empty(host.numel(), dtype=torch.uint8, device="cuda") for _ in range(2)]
+    side = torch.cuda.Stream()
+
+    def merge_from(buf):
+        idx = b1.clone()
+        idx.merge(buf, lens)
+        return idx
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        bufs[0].copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    up_ms = (time.perf_counter() - t) / steps * 1e3
+    merge_from(bufs[0]).close()  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        bufs[0].copy_(host, non_blocking=True)
+        torch.cuda.synchronize()
+        merge_from(bufs[0]).close()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t) / steps * 1e3
+    t = time.perf_counter()
+    with torch.cuda.stream(side):
+        bufs[0].copy_(host, non_blocking=True)
+    side.synchronize()
+    for i in range(steps):
+        if i + 1 < steps:
+            with torch.cuda.stream(side):
+                bufs[(i + 1) % 2].copy_(host, non_blocking=True)
+        merge_from(bufs[i % 2]).close()
+        side.synchronize()
+    torch.cuda.synchronize()
+    ovl_ms = (time.perf_counter() - t) / steps * 1e3
+    n2 = 2 * (new.total + new.n)
+    log(f"host input: upload {up_ms:.2f} ms; upload then merge {seq_ms:.2f} ms/step; "
+        f"upload beside the previous merge {ovl_ms:.2f} ms/step")
+    return {"batch_bytes": int(host.numel()), "upload_ms": round(up_ms, 3),
+            "upload_gb_per_s": round(host.numel() / (up_ms / 1e3) / 1e9, 2),
+            "sequential_ms_per_step": round(seq_ms, 3), "overlapped_ms_per_step": round(ovl_ms, 3),
+            "sequential_suffixes_per_s": round(n2 / (seq_ms / 1e3), 1),
+            "overlapped_suffixes_per_s": round(n2 / (ovl_ms / 1e3), 1), "steps": steps}
+
+
 def roofline_of(prof: dict, st: dict, steps: int, workload: str, src_hash: str):
     """Roofline entry for the kernel with the largest total time among those
     that run alone: the tie kernels of the size classes run at the same time
@@ -525,6 +580,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=120_000,
                     help="haplotype prefix length for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-host-input", action="store_true",
+                    help="skip the merges fed from pinned host memory (PCIe-inclusive rate)")
     ap.add_argument("--no-smem", action="store_true", help="skip the SMEM serving measurement")
     ap.add_argument("--smem-batched-only", action="store_true",
                     help="SMEM: the batched calls only (no per-query calls, no served latency); for counter runs")
@@ -609,6 +666,10 @@ def main():
     src_hash = kernel_source_hash()
     roofline = roofline_of(prof, st, args.steps, workload, src_hash)
 
+    host_input = None
+    if workload == "pangenome_merge" and not args.no_host_input:
+        host_input = host_input_merges(b1, new_strings, 5)
+
     plain = None
     if workload == "uneven_merge" and args.plain_strings > 0:
         plain = plain_vs_batched(b1_strings, new_strings, args.chunk, args.plain_strings)
@@ -645,6 +706,7 @@ def main():
         "cpu_baseline": cpu,
         "smem": smem,
         "plain_vs_batched": plain,
+        "host_input": host_input,
         "merge_stats": st,
         "kernels": kernels,
         "source_hash": src_hash,
