@@ -128,6 +128,26 @@ int rb3_merge(rb3_index *idx, const uint8_t *seq, const int64_t *lens, int64_t n
 int rb3_count(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q,
               int32_t mem, int64_t *lo, int64_t *hi);
 
+/*
+ * rb3_count_noalloc: rb3_count for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments and results as rb3_count, except that lo
+ * and hi are in the same memory as the queries (mem): host arrays for host
+ * queries, device arrays for device queries. The call allocates nothing: its
+ * temporaries (error flag, query offsets, symbol codes, and the staged
+ * results when they go to host memory) live in one fixed scratch array of
+ * RB3_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends. Queries that need more scratch than that give
+ * RB3_ELIMIT: 256 bytes + the query bytes + 8 bytes per query (+ 16 bytes per
+ * query for host results), each part rounded up to 256 bytes. Every call on
+ * a device shares that device's array; the array keeps the last call's
+ * contents, and calls from several host threads on one device take turns on
+ * a lock (left to overlap they would race on the array).
+ */
+#define RB3_NOALLOC_SCRATCH_BYTES (32u << 20)
+int rb3_count_noalloc(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q,
+                      int32_t mem, int64_t *lo, int64_t *hi);
+
 /* One SMEM: query interval [start, end), its occurrence count occ, and its
  * SA bi-interval starts k = lo(P[start,end)), krc = lo(rc(P[start,end)))
  * (Sec. 2.5). */

@@ -362,6 +362,7 @@ int run_smem(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens,
 
 const DevIndex index_dev(const rb3_index *idx) { return idx->d.dev(); }
 int index_device(const rb3_index *idx) { return idx->d.ctx.device; }
+hipStream_t index_stream(const rb3_index *idx) { return idx->d.ctx.stream; }
 int32_t index_both(const rb3_index *idx) { return idx->d.ctx.both; }
 
 }  // namespace rb3
@@ -434,6 +435,17 @@ int rb3_count(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int6
     Ctx c = call_ctx(idx->d);
     int rc = run_count(c, idx->d.dev(), q, qlens, n_q, total, mem, lo, hi);
     return finish(c, rc);
+}
+
+int rb3_count_noalloc(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
+                      int64_t *lo, int64_t *hi) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    if (n_q > 0 && (!lo || !hi)) return fail(RB3_EINVAL, "output arrays are NULL");
+    int64_t total = 0;
+    RB3_TRY(check_strings(q, qlens, n_q, mem, true, &total));
+    if (n_q == 0) return RB3_OK;
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    return count_noalloc(idx->d.dev(), idx->d.ctx.device, idx->d.ctx.stream, q, qlens, n_q, total, mem, lo, hi);
 }
 
 int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,

@@ -4,18 +4,6 @@
 
 namespace rb3 {
 
-// ASCII -> code: A=1 C=2 G=3 T=4 N=5 in either case; -1 for anything else.
-__device__ __forceinline__ int ascii_code(uint32_t ch) {
-    switch (ch | 0x20u) {
-    case 'a': return 1;
-    case 'c': return 2;
-    case 'g': return 3;
-    case 't': return 4;
-    case 'n': return 5;
-    default: return -1;
-    }
-}
-
 // Watson-Crick complement on codes (Sec. 2.5): A<->T, C<->G, N<->N, $<->$.
 __device__ __forceinline__ uint8_t comp_code(int c) { return (uint8_t)(c == 5 ? 5 : (c == 0 ? 0 : 5 - c)); }
 

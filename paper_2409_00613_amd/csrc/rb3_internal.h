@@ -170,6 +170,18 @@ __device__ __forceinline__ void pi_all2(const DevIndex &ix, int64_t k0, int64_t 
     pi_all_from(ix, B1, s1, k1, out1);
 }
 
+// ASCII -> code: A=1 C=2 G=3 T=4 N=5 in either case; -1 for anything else.
+__device__ __forceinline__ int ascii_code(uint32_t ch) {
+    switch (ch | 0x20u) {
+    case 'a': return 1;
+    case 'c': return 2;
+    case 'g': return 3;
+    case 't': return 4;
+    case 'n': return 5;
+    default: return -1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side context
 // ---------------------------------------------------------------------------
@@ -467,6 +479,11 @@ int run_smem(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens,
              int32_t mem, int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off,
              int64_t *exts);
 const DevIndex index_dev(const rb3_index *idx);
+hipStream_t index_stream(const rb3_index *idx);
+// noalloc.hip: rb3_count with every temporary in the library's fixed
+// scratch array (no allocation). Arguments checked by the caller.
+int count_noalloc(const DevIndex &ix, int dev, hipStream_t stream, const uint8_t *q, const int64_t *qlens,
+                  int64_t n_q, int64_t total, int32_t mem, int64_t *lo, int64_t *hi);
 int index_device(const rb3_index *idx);
 int32_t index_both(const rb3_index *idx);
 

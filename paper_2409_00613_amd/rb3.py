@@ -44,7 +44,7 @@ SMEM_DTYPE = np.dtype([("start", np.int64), ("end", np.int64), ("occ", np.int64)
 assert SMEM_DTYPE.itemsize == ctypes.sizeof(SmemRec) == 48
 
 # Every function declared in include/rb3.h.
-EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats",
+EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_count_noalloc", "rb3_smem", "rb3_last_smem_stats",
            "rb3_locate", "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info",
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
            "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats",
@@ -98,6 +98,7 @@ def lib():
     L.rb3_build.argtypes = [ctypes.POINTER(Opts), _vp, _i64p, _i64, _i32, ctypes.POINTER(_vp)]
     L.rb3_merge.argtypes = [_vp, _vp, _i64p, _i64, _i32]
     L.rb3_count.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p]
+    L.rb3_count_noalloc.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p]
     L.rb3_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, ctypes.POINTER(SmemRec), _i64, _i64p]
     L.rb3_info.argtypes = [_vp, _i64p, _i64p, _i64p]
     L.rb3_last_smem_stats.argtypes = [_i64p]
@@ -130,7 +131,7 @@ def lib():
     for name in ("rb3_server_create", "rb3_server_submit", "rb3_server_poll", "rb3_server_stats",
                  "rb3_server_replay"):
         getattr(L, name).restype = ctypes.c_int
-    for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_smem", "rb3_last_smem_stats", "rb3_locate",
+    for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_count_noalloc", "rb3_smem", "rb3_last_smem_stats", "rb3_locate",
                  "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info", "rb3_export",
                  "rb3_import", "rb3_clone", "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read",
                  "rb3_merge_stats"):
@@ -314,6 +315,17 @@ def rb3_count(idx: Index, q, qlens):
     lo = np.zeros(max(n, 1), np.int64)
     hi = np.zeros(max(n, 1), np.int64)
     _check(lib().rb3_count(idx.handle, ptr, lp, n, mem, lo.ctypes.data_as(_i64p), hi.ctypes.data_as(_i64p)))
+    return lo[:n], hi[:n]
+
+
+def rb3_count_noalloc(idx: Index, q, qlens):
+    """rb3_count without device allocation: (lo, hi) as numpy arrays for host
+    queries, device tensors for device queries."""
+    ptr, _, mem, keep = _buffer(q)
+    la, lp = _lens(qlens)
+    n = la.shape[0]
+    lo, hi, plo, phi = _i64out(n, mem, keep)
+    _check(lib().rb3_count_noalloc(idx.handle, ptr, lp, n, mem, plo, phi))
     return lo[:n], hi[:n]
 
 
