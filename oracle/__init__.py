@@ -16,6 +16,11 @@ Functions (each follows a definition of arXiv 2409.00613):
   insertion_ranks
               l(x) of each new suffix: number of existing-index suffixes below
               it (the quantity Algorithm 1 accumulates)
+  scan_intervals
+              the same [lo, hi) for a batch of patterns in one pass over every
+              suffix (for texts too large for a suffix sort)
+  smem_scan   the SMEMs of Text.smem for a batch of queries by a seeded scan
+              of the text (hashed min_len-mers, diagonal runs), no suffix array
   locate      the suffix-array entry of a row written as (string index,
               offset within the string) (Sec. 2.4)
   rows_of     the inverse: the row of the suffix at (string index, offset)
@@ -78,6 +83,12 @@ def _load():
     lib.orc_smem.argtypes = [ctypes.c_void_p, _i64p, _u8p, ctypes.c_int64, ctypes.c_int64,
                              ctypes.c_int64, _i64p, ctypes.c_int64]
     lib.orc_smem.restype = ctypes.c_int64
+    lib.orc_scan_intervals.argtypes = [_u8p, _i64p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64,
+                                       ctypes.c_int, _i64p, _i64p]
+    lib.orc_scan_intervals.restype = ctypes.c_int
+    lib.orc_smem_scan.argtypes = [_u8p, _i64p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_int, _i64p, ctypes.c_int64, _i64p]
+    lib.orc_smem_scan.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -86,8 +97,22 @@ def _p(a: np.ndarray, t):
     return a.ctypes.data_as(t)
 
 
+def host_threads() -> int:
+    """Threads the oracle uses by default: the CPUs this process may run on,
+    no more than OMP_NUM_THREADS when that is set (a shared GPU host grants
+    each GPU a share of its cores that way)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
 def _threads(nthreads):
-    return int(nthreads) if nthreads else max(1, min(os.cpu_count() or 1, 16))
+    return int(nthreads) if nthreads else host_threads()
 
 
 def expand(data: np.ndarray, lens: np.ndarray, both: bool = True, allow_empty: bool = False):
@@ -198,6 +223,68 @@ def count(codes: np.ndarray, lens: np.ndarray, qcodes: np.ndarray, qlens: np.nda
     if rc != 0:
         raise MemoryError("oracle count: allocation failed")
     return lo[:nq], hi[:nq]
+
+
+# Patterns given to scan_intervals / SMEMs found by smem_scan: at least this
+# long, and their first SCAN_K symbols are A..T (the scan's bucket key).
+SCAN_K = 12
+
+
+def scan_intervals(codes: np.ndarray, lens: np.ndarray, pcodes: np.ndarray, plens: np.ndarray,
+                   nthreads: int | None = None):
+    """SA intervals (lo, hi) of each pattern, as count() gives them, by one
+    pass over every suffix. Each pattern must be at least SCAN_K long and
+    start with SCAN_K symbols of A..T (ValueError otherwise)."""
+    lib = _load()
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    lens = np.ascontiguousarray(lens, dtype=np.int64)
+    pcodes = np.ascontiguousarray(pcodes, dtype=np.uint8)
+    plens = np.ascontiguousarray(plens, dtype=np.int64)
+    npat = plens.shape[0]
+    lo = np.zeros(max(npat, 1), dtype=np.int64)
+    hi = np.zeros(max(npat, 1), dtype=np.int64)
+    pp = pcodes if pcodes.size else np.zeros(1, np.uint8)
+    cod = codes if codes.size else np.zeros(1, np.uint8)
+    rc = lib.orc_scan_intervals(_p(cod, _u8p), _p(lens, _i64p), lens.shape[0], _p(pp, _u8p), _p(plens, _i64p),
+                                npat, _threads(nthreads), _p(lo, _i64p), _p(hi, _i64p))
+    if rc == -4:
+        raise ValueError(f"scan_intervals: every pattern must start with {SCAN_K} symbols of A..T")
+    if rc != 0:
+        raise MemoryError("oracle scan_intervals: allocation failed")
+    return lo[:npat], hi[:npat]
+
+
+def smem_scan(codes: np.ndarray, lens: np.ndarray, qcodes: np.ndarray, qlens: np.ndarray, min_len: int,
+              min_occ: int = 1, nthreads: int | None = None):
+    """SMEMs of each query (as Text.smem gives them) by a seeded scan of the
+    text. Returns (records, offsets): records is an (k, 5) int64 array of
+    start, end, occ, lo, lo_rc; query i owns records[offsets[i]:offsets[i+1]].
+    min_len must be at least SCAN_K, and each SMEM and its reverse complement
+    must start with SCAN_K symbols of A..T (ValueError otherwise)."""
+    lib = _load()
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    lens = np.ascontiguousarray(lens, dtype=np.int64)
+    qcodes = np.ascontiguousarray(qcodes, dtype=np.uint8)
+    qlens = np.ascontiguousarray(qlens, dtype=np.int64)
+    nq = qlens.shape[0]
+    qq = qcodes if qcodes.size else np.zeros(1, np.uint8)
+    cod = codes if codes.size else np.zeros(1, np.uint8)
+    cap = max(1024, int(qlens.sum()) // 32)
+    while True:
+        out = np.zeros((cap, 5), dtype=np.int64)
+        off = np.zeros(nq + 1, dtype=np.int64)
+        k = lib.orc_smem_scan(_p(cod, _u8p), _p(lens, _i64p), lens.shape[0], _p(qq, _u8p), _p(qlens, _i64p), nq,
+                              int(min_len), int(min_occ), _threads(nthreads), _p(out, _i64p), cap, _p(off, _i64p))
+        if k == -4:
+            raise ValueError(f"smem_scan: min_len must be >= {SCAN_K} and every SMEM must start with "
+                             f"{SCAN_K} symbols of A..T on both strands")
+        if k == -5:
+            raise RuntimeError("smem_scan: run count and suffix count of an SMEM disagree")
+        if k < 0:
+            raise MemoryError("oracle smem_scan: allocation failed")
+        if k <= cap:
+            return out[:k], off
+        cap = int(k)
 
 
 class Text:

@@ -601,3 +601,543 @@ int64_t orc_smem(void *h, const int64_t *S, const uint8_t *P, int64_t len, int64
     free(rc);
     return found;
 }
+
+/* ------------------------------------------------------------------------ */
+/* SA intervals of many patterns in one pass over every suffix               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The same [lo, hi) as orc_count (Sec. 2.3: lo = number of suffixes below P,
+ * hi = lo + number of suffixes with prefix P), for a batch of patterns,
+ * with one pass over the suffixes instead of one per pattern.
+ *
+ * Each pattern P gives two probes: P followed by a symbol below every
+ * symbol (lo counts the suffixes below it) and P followed by a symbol above
+ * every symbol (hi counts the suffixes below that one). A suffix never
+ * equals a probe, so with the probes sorted, the probes above a suffix x
+ * are exactly those from the g(x)-th on, where g(x) is the number of probes
+ * below x; a histogram of g over all suffixes, summed up to a probe's place,
+ * gives the number of suffixes below that probe.
+ *
+ * g(x) comes from the first ORC_SCAN_K symbols of x when they are all bases
+ * A..T: the probes whose first ORC_SCAN_K symbols are smaller all lie below
+ * x, the larger ones above, and only the probes sharing x's prefix are
+ * compared in full (binary search). Any other suffix (a sentinel or an N
+ * among its first ORC_SCAN_K symbols) is compared with every probe by
+ * binary search; those comparisons end within ORC_SCAN_K symbols.
+ *
+ * Precondition: every pattern is at least ORC_SCAN_K long and its first
+ * ORC_SCAN_K symbols are A..T (codes 1..4). Returns 0, -1 on allocation
+ * failure, -4 when a pattern breaks the precondition.
+ */
+#define ORC_SCAN_K 12
+#define ORC_SCAN_NB (1u << (2 * ORC_SCAN_K))
+
+typedef struct {
+    const uint8_t *codes;       /* text strands, concatenated, no sentinels */
+    const int64_t *lens, *start;
+    int64_t m;
+    const uint8_t *pc;          /* pattern codes */
+    const int64_t *poff, *plen;
+    const int64_t *probe;       /* sorted probes: pattern index * 2 + (0: lo, 1: hi) */
+    int64_t np2;                /* number of probes */
+    const uint32_t *first;      /* probes with a smaller K-prefix code, per code */
+} orc_scan_ctx;
+
+/* 1 if the suffix at offset t of strand j is below probe pr, else 0. */
+static int orc_suffix_below(const orc_scan_ctx *x, int64_t j, int64_t t, int64_t pr)
+{
+    const uint8_t *S = x->codes + x->start[j];
+    const int64_t L = x->lens[j];
+    const int64_t pi = pr >> 1;
+    const uint8_t *P = x->pc + x->poff[pi];
+    const int64_t pl = x->plen[pi];
+    for (int64_t d = 0;; ++d) {
+        if (d == pl) return (int)(pr & 1);     /* past P: below the "above all" probe only */
+        if (t + d == L) return 1;              /* the suffix's sentinel is below every base */
+        const uint8_t s = S[t + d];
+        if (s != P[d]) return s < P[d];
+    }
+}
+
+/* Probe order: compare the patterns, then the terminal symbol (lo < hi). */
+static int orc_probe_cmp(const orc_scan_ctx *x, int64_t a, int64_t b)
+{
+    const uint8_t *A = x->pc + x->poff[a >> 1], *B = x->pc + x->poff[b >> 1];
+    const int64_t la = x->plen[a >> 1], lb = x->plen[b >> 1];
+    const int64_t n = la < lb ? la : lb;
+    for (int64_t d = 0; d < n; ++d)
+        if (A[d] != B[d]) return A[d] < B[d] ? -1 : 1;
+    if (la == lb) return (int)(a & 1) - (int)(b & 1);
+    /* the shorter one ends in its terminal, below or above every symbol */
+    if (la < lb) return (a & 1) ? 1 : -1;
+    return (b & 1) ? -1 : 1;
+}
+
+static void orc_probe_sort(const orc_scan_ctx *x, int64_t *a, int64_t *tmp, int64_t n)
+{
+    if (n < 2) return;
+    if (n <= 16) {
+        for (int64_t i = 1; i < n; ++i) {
+            int64_t v = a[i], j = i;
+            while (j > 0 && orc_probe_cmp(x, a[j - 1], v) > 0) { a[j] = a[j - 1]; --j; }
+            a[j] = v;
+        }
+        return;
+    }
+    int64_t h = n / 2;
+    orc_probe_sort(x, a, tmp, h);
+    orc_probe_sort(x, a + h, tmp + h, n - h);
+    int64_t i = 0, j = h, k = 0;
+    while (i < h && j < n) tmp[k++] = (orc_probe_cmp(x, a[j], a[i]) < 0) ? a[j++] : a[i++];
+    while (i < h) tmp[k++] = a[i++];
+    while (j < n) tmp[k++] = a[j++];
+    memcpy(a, tmp, (size_t)n * sizeof(int64_t));
+}
+
+/* Number of probes in [f0, f1) below the suffix (t of strand j), given that
+ * the probes before f0 are below it and those from f1 on above it. */
+static int64_t orc_probes_below(const orc_scan_ctx *x, int64_t j, int64_t t, int64_t f0, int64_t f1)
+{
+    while (f0 < f1) { /* first probe the suffix is below */
+        int64_t mid = f0 + (f1 - f0) / 2;
+        if (orc_suffix_below(x, j, t, x->probe[mid])) f1 = mid; else f0 = mid + 1;
+    }
+    return f0;
+}
+
+typedef struct {
+    const orc_scan_ctx *x;
+    int64_t j0, t0, j1, t1;   /* suffixes from (j0, t0) up to, not including, (j1, t1) */
+    int64_t *hist;            /* np2 + 1 */
+} orc_scan_job;
+
+static void *orc_scan_worker(void *p)
+{
+    orc_scan_job *jb = (orc_scan_job *)p;
+    const orc_scan_ctx *x = jb->x;
+    const uint32_t mask = ORC_SCAN_NB - 1;
+    for (int64_t j = jb->j0; j <= jb->j1 && j < x->m; ++j) {
+        const int64_t L = x->lens[j];
+        const int64_t a = j == jb->j0 ? jb->t0 : 0;
+        const int64_t b = j == jb->j1 ? jb->t1 : L + 1; /* offsets [a, b), L = the sentinel */
+        if (a >= b) continue;
+        const uint8_t *S = x->codes + x->start[j];
+        /* the window of K symbols starting at b: its 2-bit code and how many
+         * of its leading symbols are A..T */
+        uint32_t code = 0;
+        int run = 0;
+        for (int d = ORC_SCAN_K - 1; d >= 0; --d) {
+            const int64_t q = b + d;
+            const int s = q < L ? S[q] : 0;
+            if (s >= 1 && s <= 4) {
+                code = (code >> 2) | ((uint32_t)(s - 1) << (2 * ORC_SCAN_K - 2));
+                run = run < ORC_SCAN_K ? run + 1 : ORC_SCAN_K;
+            } else {
+                run = 0;
+            }
+        }
+        for (int64_t t = b - 1; t >= a; --t) {
+            const int s = t < L ? S[t] : 0;
+            if (s >= 1 && s <= 4) {
+                code = ((code >> 2) | ((uint32_t)(s - 1) << (2 * ORC_SCAN_K - 2))) & mask;
+                run = run < ORC_SCAN_K ? run + 1 : ORC_SCAN_K;
+            } else {
+                run = 0;
+            }
+            int64_t g;
+            if (run >= ORC_SCAN_K) {
+                const int64_t f0 = x->first[code], f1 = x->first[code + 1];
+                g = f0 < f1 ? orc_probes_below(x, j, t, f0, f1) : f0;
+            } else {
+                g = orc_probes_below(x, j, t, 0, x->np2);
+            }
+            jb->hist[g]++;
+        }
+    }
+    return NULL;
+}
+
+int orc_scan_intervals(const uint8_t *codes, const int64_t *lens, int64_t m, const uint8_t *pcodes,
+                       const int64_t *plens, int64_t np, int nthreads, int64_t *lo, int64_t *hi)
+{
+    if (np == 0) return 0;
+    for (int64_t i = 0, o = 0; i < np; o += plens[i], ++i) {
+        if (plens[i] < ORC_SCAN_K) return -4;
+        for (int d = 0; d < ORC_SCAN_K; ++d)
+            if (pcodes[o + d] < 1 || pcodes[o + d] > 4) return -4;
+    }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > ORC_MAX_THREADS) nthreads = ORC_MAX_THREADS;
+    const int64_t np2 = 2 * np;
+    int64_t *start = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t *poff = (int64_t *)malloc((size_t)np * sizeof(int64_t));
+    int64_t *probe = (int64_t *)malloc((size_t)np2 * sizeof(int64_t));
+    int64_t *tmp = (int64_t *)malloc((size_t)np2 * sizeof(int64_t));
+    int64_t *place = (int64_t *)malloc((size_t)np2 * sizeof(int64_t));
+    uint32_t *first = (uint32_t *)calloc((size_t)ORC_SCAN_NB + 1, sizeof(uint32_t));
+    int64_t *hist = (int64_t *)calloc((size_t)nthreads * (size_t)(np2 + 1), sizeof(int64_t));
+    int rc = -1;
+    if (!start || !poff || !probe || !tmp || !place || !first || !hist) goto done;
+    int64_t nsuf = 0;
+    for (int64_t j = 0, s = 0; j < m; s += lens[j], ++j) { start[j] = s; nsuf += lens[j] + 1; }
+    for (int64_t i = 0, o = 0; i < np; o += plens[i], ++i) poff[i] = o;
+    orc_scan_ctx x = {codes, lens, start, m, pcodes, poff, plens, probe, np2, first};
+    for (int64_t i = 0; i < np2; ++i) probe[i] = i;
+    orc_probe_sort(&x, probe, tmp, np2);
+    /* first[c] = probes whose K-prefix code is below c */
+    for (int64_t i = 0; i < np2; ++i) {
+        const uint8_t *P = pcodes + poff[probe[i] >> 1];
+        uint32_t c = 0;
+        for (int d = 0; d < ORC_SCAN_K; ++d) c = (c << 2) | (uint32_t)(P[d] - 1);
+        first[c + 1]++;
+    }
+    for (uint32_t c = 0; c < ORC_SCAN_NB; ++c) first[c + 1] += first[c];
+    /* the suffixes, cut into nthreads equal ranges */
+    pthread_t th[ORC_MAX_THREADS];
+    orc_scan_job jobs[ORC_MAX_THREADS];
+    {
+        int64_t j = 0, before = 0; /* suffixes of strands before j */
+        for (int t = 0; t < nthreads; ++t) {
+            const int64_t g0 = nsuf * t / nthreads, g1 = nsuf * (t + 1) / nthreads;
+            while (j < m && before + lens[j] + 1 <= g0) { before += lens[j] + 1; ++j; }
+            jobs[t].j0 = j;
+            jobs[t].t0 = g0 - before;
+            int64_t jj = j, bb = before;
+            while (jj < m && bb + lens[jj] + 1 <= g1) { bb += lens[jj] + 1; ++jj; }
+            jobs[t].j1 = jj;
+            jobs[t].t1 = g1 - bb;
+            jobs[t].x = &x;
+            jobs[t].hist = hist + (size_t)t * (size_t)(np2 + 1);
+        }
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, orc_scan_worker, &jobs[t]);
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    /* suffixes below sorted probe k: histogram summed over g <= k */
+    int64_t run = 0;
+    for (int64_t k = 0; k < np2; ++k) {
+        for (int t = 0; t < nthreads; ++t) run += hist[(size_t)t * (size_t)(np2 + 1) + k];
+        place[probe[k]] = run;
+    }
+    for (int64_t i = 0; i < np; ++i) {
+        lo[i] = place[2 * i];
+        hi[i] = place[2 * i + 1];
+    }
+    rc = 0;
+done:
+    free(start); free(poff); free(probe); free(tmp); free(place); free(first); free(hist);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SMEMs by a seeded scan of the text                                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The SMEMs of orc_smem (length >= min_len, occurring >= min_occ times;
+ * Sec. 2.6), for a batch of queries, found without a suffix array, by one
+ * pass over the text:
+ *
+ *   1. every min_len-mer of every query is hashed;
+ *   2. one pass over the text hashes each min_len-mer of it; a text window
+ *      equal to query window (q, i) is a hit, and the hits of one query on
+ *      one diagonal (text position - query position) at consecutive i form
+ *      a run; a hit whose left neighbours also match is inside a run, so
+ *      only a run's first hit is extended, to the right, once: the run
+ *      starting at i is the exact match P[i, r) of the text at that
+ *      diagonal, with r as far as the match goes;
+ *   3. an occurrence of P[i, e) with e - i >= min_len contains the hit of
+ *      P[i, i + min_len), so occ(P[i, e)) is the number of runs covering
+ *      query position i (as a hit) with r >= e. So e(i) (largest e with
+ *      occ >= min_occ) is the min_occ-th largest r of those runs, and the
+ *      SMEMs are [i, e(i)) with i = 0 or e(i) > e(i-1), as in orc_smem (a
+ *      position with fewer covering runs has e(i) < i + min_len, so it
+ *      starts no SMEM and any longer e(i+1) exceeds it);
+ *   4. k and krc, the lo of P[i, e) and of its reverse complement, come
+ *      from orc_scan_intervals, whose hi - lo must equal the run count.
+ *
+ * out: 5 int64 per SMEM (start, end, occ, k, krc), query by query in
+ * increasing start; qoff (nq + 1) the offsets. Returns the number of SMEMs
+ * (only the first cap are written); -1 allocation failure; -4 min_len below
+ * ORC_SCAN_K or an SMEM whose first ORC_SCAN_K symbols (or those of its
+ * reverse complement) are not all A..T; -5 when the two counts of an SMEM
+ * disagree (an internal inconsistency).
+ */
+static uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+#define ORC_HASH_B 0x9E3779B97F4A7C15ULL
+
+typedef struct {
+    uint64_t key;
+    int64_t q, i;
+} orc_seed;
+
+typedef struct {
+    int64_t q, i, r; /* query q matches the text on [i, r) at one diagonal */
+} orc_run;
+
+typedef struct {
+    const uint8_t *codes;
+    const int64_t *lens, *start;
+    const uint8_t *qc;
+    const int64_t *qoff, *qlen;
+    int64_t ell;
+    const orc_seed *seed;
+    const int64_t *bstart;
+    int bshift;
+    int64_t j0, j1; /* strands [j0, j1) */
+    orc_run *runs;
+    int64_t nruns, cap;
+    int failed;
+} orc_seedscan_job;
+
+static void orc_push_run(orc_seedscan_job *jb, int64_t q, int64_t i, int64_t r)
+{
+    if (jb->nruns == jb->cap) {
+        int64_t nc = jb->cap ? 2 * jb->cap : 4096;
+        orc_run *nr = (orc_run *)realloc(jb->runs, (size_t)nc * sizeof(orc_run));
+        if (!nr) { jb->failed = 1; return; }
+        jb->runs = nr;
+        jb->cap = nc;
+    }
+    jb->runs[jb->nruns].q = q;
+    jb->runs[jb->nruns].i = i;
+    jb->runs[jb->nruns].r = r;
+    jb->nruns++;
+}
+
+static void *orc_seedscan_worker(void *p)
+{
+    orc_seedscan_job *jb = (orc_seedscan_job *)p;
+    const int64_t ell = jb->ell;
+    uint64_t bpow = 1; /* B^(ell-1) */
+    for (int64_t d = 1; d < ell; ++d) bpow *= ORC_HASH_B;
+    for (int64_t j = jb->j0; j < jb->j1 && !jb->failed; ++j) {
+        const int64_t L = jb->lens[j];
+        if (L < ell) continue;
+        const uint8_t *T = jb->codes + jb->start[j];
+        uint64_t h = 0;
+        for (int64_t d = 0; d < ell; ++d) h = h * ORC_HASH_B + T[d];
+        for (int64_t t = 0;; ++t) {
+            const uint64_t key = orc_mix64(h);
+            const int64_t b = (int64_t)(key >> jb->bshift);
+            for (int64_t e = jb->bstart[b]; e < jb->bstart[b + 1]; ++e) {
+                if (jb->seed[e].key != key) continue;
+                const int64_t q = jb->seed[e].q, i = jb->seed[e].i;
+                const uint8_t *P = jb->qc + jb->qoff[q];
+                /* inside a run that starts further left */
+                if (i > 0 && t > 0 && P[i - 1] == T[t - 1]) continue;
+                if (memcmp(P + i, T + t, (size_t)ell) != 0) continue;
+                int64_t r = i + ell;
+                while (r < jb->qlen[q] && t + (r - i) < L && P[r] == T[t + (r - i)]) ++r;
+                orc_push_run(jb, q, i, r);
+            }
+            if (t + ell >= L) break;
+            h = (h - T[t] * bpow) * ORC_HASH_B + T[t + ell];
+        }
+    }
+    return NULL;
+}
+
+static int orc_seed_cmp(const void *a, const void *b)
+{
+    const uint64_t x = ((const orc_seed *)a)->key, y = ((const orc_seed *)b)->key;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int orc_run_cmp(const void *a, const void *b)
+{
+    const orc_run *x = (const orc_run *)a, *y = (const orc_run *)b;
+    if (x->q != y->q) return x->q < y->q ? -1 : 1;
+    if (x->i != y->i) return x->i < y->i ? -1 : 1;
+    return x->r < y->r ? -1 : (x->r > y->r ? 1 : 0);
+}
+
+int64_t orc_smem_scan(const uint8_t *codes, const int64_t *lens, int64_t m, const uint8_t *qcodes,
+                      const int64_t *qlens, int64_t nq, int64_t min_len, int64_t min_occ, int nthreads,
+                      int64_t *out, int64_t cap, int64_t *qoff_out)
+{
+    if (min_len < ORC_SCAN_K) return -4;
+    if (min_occ < 1) min_occ = 1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > ORC_MAX_THREADS) nthreads = ORC_MAX_THREADS;
+    const int64_t ell = min_len;
+    int64_t rc = -1;
+    int64_t *start = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t *qoff = (int64_t *)malloc((size_t)(nq + 1) * sizeof(int64_t));
+    orc_seed *seed = NULL;
+    int64_t *bstart = NULL;
+    orc_run *runs = NULL;
+    int64_t *sm = NULL;      /* SMEMs: q, start, end, occ */
+    uint8_t *pat = NULL;     /* the SMEM strings and their reverse complements */
+    int64_t *plen = NULL, *plo = NULL, *phi = NULL;
+    int64_t *act = NULL;
+    orc_seedscan_job jobs[ORC_MAX_THREADS];
+    memset(jobs, 0, sizeof(jobs));
+    if (!start || !qoff) goto done;
+    int64_t ntext = 0;
+    for (int64_t j = 0; j < m; ++j) { start[j] = ntext; ntext += lens[j]; }
+    qoff[0] = 0;
+    for (int64_t q = 0; q < nq; ++q) qoff[q + 1] = qoff[q] + qlens[q];
+    /* 1. seeds */
+    int64_t nseed = 0;
+    for (int64_t q = 0; q < nq; ++q) if (qlens[q] >= ell) nseed += qlens[q] - ell + 1;
+    seed = (orc_seed *)malloc((size_t)(nseed > 0 ? nseed : 1) * sizeof(orc_seed));
+    if (!seed) goto done;
+    {
+        uint64_t bpow = 1;
+        for (int64_t d = 1; d < ell; ++d) bpow *= ORC_HASH_B;
+        int64_t k = 0;
+        for (int64_t q = 0; q < nq; ++q) {
+            if (qlens[q] < ell) continue;
+            const uint8_t *P = qcodes + qoff[q];
+            uint64_t h = 0;
+            for (int64_t d = 0; d < ell; ++d) h = h * ORC_HASH_B + P[d];
+            for (int64_t i = 0;; ++i) {
+                seed[k].key = orc_mix64(h);
+                seed[k].q = q;
+                seed[k].i = i;
+                ++k;
+                if (i + ell >= qlens[q]) break;
+                h = (h - P[i] * bpow) * ORC_HASH_B + P[i + ell];
+            }
+        }
+    }
+    qsort(seed, (size_t)nseed, sizeof(orc_seed), orc_seed_cmp);
+    int bbits = 10;
+    while (bbits < 30 && ((int64_t)1 << bbits) < 2 * nseed) ++bbits;
+    const int bshift = 64 - bbits;
+    const int64_t nb = (int64_t)1 << bbits;
+    bstart = (int64_t *)malloc((size_t)(nb + 1) * sizeof(int64_t));
+    if (!bstart) goto done;
+    for (int64_t b = 0, e = 0; b <= nb; ++b) {
+        while (e < nseed && (int64_t)(seed[e].key >> bshift) < b) ++e;
+        bstart[b] = e;
+    }
+    /* 2. the text, strands dealt to threads in nearly equal symbol counts */
+    {
+        int64_t j = 0, acc = 0;
+        for (int t = 0; t < nthreads; ++t) {
+            const int64_t goal = ntext * (t + 1) / nthreads;
+            jobs[t].j0 = j;
+            while (j < m && (acc < goal || t == nthreads - 1)) acc += lens[j++];
+            jobs[t].j1 = j;
+            jobs[t].codes = codes; jobs[t].lens = lens; jobs[t].start = start;
+            jobs[t].qc = qcodes; jobs[t].qoff = qoff; jobs[t].qlen = qlens; jobs[t].ell = ell;
+            jobs[t].seed = seed; jobs[t].bstart = bstart; jobs[t].bshift = bshift;
+        }
+        pthread_t th[ORC_MAX_THREADS];
+        for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, orc_seedscan_worker, &jobs[t]);
+        for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    }
+    int64_t nrun = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (jobs[t].failed) goto done;
+        nrun += jobs[t].nruns;
+    }
+    runs = (orc_run *)malloc((size_t)(nrun > 0 ? nrun : 1) * sizeof(orc_run));
+    if (!runs) goto done;
+    {
+        int64_t k = 0;
+        for (int t = 0; t < nthreads; ++t) {
+            memcpy(runs + k, jobs[t].runs, (size_t)jobs[t].nruns * sizeof(orc_run));
+            k += jobs[t].nruns;
+        }
+    }
+    qsort(runs, (size_t)nrun, sizeof(orc_run), orc_run_cmp);
+    /* 3. e(i) per query from the runs covering i, then the SMEMs */
+    int64_t nsm = 0, smcap = 1024;
+    sm = (int64_t *)malloc((size_t)smcap * 4 * sizeof(int64_t));
+    if (!sm) goto done;
+    int64_t actcap = 1024;
+    act = (int64_t *)malloc((size_t)actcap * sizeof(int64_t)); /* run ends r */
+    if (!act) goto done;
+    for (int64_t q = 0, ri = 0; q < nq; ++q) {
+        qoff_out[q] = nsm;
+        const int64_t len = qlens[q];
+        int64_t na = 0, eprev = -1; /* eprev: e(i-1), or -1 when below i-1+ell */
+        for (int64_t i = 0; i + ell <= len; ++i) {
+            /* drop runs that no longer cover i (their last hit is at r - ell) */
+            int64_t w = 0;
+            for (int64_t a = 0; a < na; ++a)
+                if (act[a] - ell >= i) act[w++] = act[a];
+            na = w;
+            while (ri < nrun && runs[ri].q == q && runs[ri].i == i) {
+                if (na == actcap) {
+                    actcap *= 2;
+                    int64_t *nw = (int64_t *)realloc(act, (size_t)actcap * sizeof(int64_t));
+                    if (!nw) goto done;
+                    act = nw;
+                }
+                act[na++] = runs[ri++].r;
+            }
+            int64_t e = -1, occ = 0;
+            if (na >= min_occ) {
+                /* the min_occ-th largest end: the largest e with occ >= min_occ */
+                int64_t lo_ = i + ell, hi_ = len;
+                while (lo_ < hi_) { /* largest e in [i+ell, len] with count(r >= e) >= min_occ */
+                    const int64_t mid = hi_ - (hi_ - lo_) / 2;
+                    int64_t c = 0;
+                    for (int64_t a = 0; a < na; ++a) c += act[a] >= mid;
+                    if (c >= min_occ) lo_ = mid; else hi_ = mid - 1;
+                }
+                e = lo_;
+                for (int64_t a = 0; a < na; ++a) occ += act[a] >= e;
+            }
+            if (e >= 0 && (i == 0 || e > eprev)) {
+                if (nsm == smcap) {
+                    smcap *= 2;
+                    int64_t *nw = (int64_t *)realloc(sm, (size_t)smcap * 4 * sizeof(int64_t));
+                    if (!nw) goto done;
+                    sm = nw;
+                }
+                sm[nsm * 4 + 0] = q; sm[nsm * 4 + 1] = i; sm[nsm * 4 + 2] = e; sm[nsm * 4 + 3] = occ;
+                ++nsm;
+            }
+            eprev = e;
+        }
+        while (ri < nrun && runs[ri].q == q) ++ri;
+    }
+    qoff_out[nq] = nsm;
+    /* 4. intervals of each SMEM and of its reverse complement */
+    {
+        int64_t tot = 0;
+        for (int64_t s = 0; s < nsm; ++s) tot += 2 * (sm[s * 4 + 2] - sm[s * 4 + 1]);
+        pat = (uint8_t *)malloc((size_t)(tot > 0 ? tot : 1));
+        plen = (int64_t *)malloc((size_t)(2 * nsm + 1) * sizeof(int64_t));
+        plo = (int64_t *)malloc((size_t)(2 * nsm + 1) * sizeof(int64_t));
+        phi = (int64_t *)malloc((size_t)(2 * nsm + 1) * sizeof(int64_t));
+        if (!pat || !plen || !plo || !phi) goto done;
+        int64_t o = 0;
+        for (int64_t s = 0; s < nsm; ++s) {
+            const uint8_t *P = qcodes + qoff[sm[s * 4]];
+            const int64_t a = sm[s * 4 + 1], b = sm[s * 4 + 2], L = b - a;
+            memcpy(pat + o, P + a, (size_t)L);
+            for (int64_t d = 0; d < L; ++d) pat[o + L + d] = orc_comp(P[b - 1 - d]);
+            plen[2 * s] = L;
+            plen[2 * s + 1] = L;
+            o += 2 * L;
+        }
+        const int r2 = orc_scan_intervals(codes, lens, m, pat, plen, 2 * nsm, nthreads, plo, phi);
+        if (r2 != 0) { rc = r2; goto done; }
+        for (int64_t s = 0; s < nsm; ++s) {
+            const int64_t occ = sm[s * 4 + 3];
+            if (phi[2 * s] - plo[2 * s] != occ || phi[2 * s + 1] - plo[2 * s + 1] != occ) { rc = -5; goto done; }
+            if (s < cap) {
+                int64_t *w = out + s * 5;
+                w[0] = sm[s * 4 + 1]; w[1] = sm[s * 4 + 2]; w[2] = occ; w[3] = plo[2 * s]; w[4] = plo[2 * s + 1];
+            }
+        }
+    }
+    rc = nsm;
+done:
+    for (int t = 0; t < ORC_MAX_THREADS; ++t) free(jobs[t].runs);
+    free(start); free(qoff); free(seed); free(bstart); free(runs); free(sm); free(pat);
+    free(plen); free(plo); free(phi); free(act);
+    return rc;
+}

@@ -125,6 +125,31 @@ def _brute_smem(strands, P, min_len):
     return res
 
 
+def _occ(strands, sub):
+    """Occurrences of sub over every strand (overlaps counted; a match never
+    crosses a strand's end)."""
+    return sum(1 for s in strands for t in range(len(s) - len(sub) + 1) if s[t:t + len(sub)] == sub)
+
+
+def _brute_smem_occ(strands, P, min_len, smin):
+    """SMEMs with a minimum occurrence count, from the containment definition
+    (Sec. 2.6 with the min-occurrence threshold): among all pattern intervals
+    [a, b) whose substring occurs at least smin times, keep those that no
+    other such interval contains. No e(i) recurrence is used."""
+    freq = [(a, b) for a in range(len(P)) for b in range(a + 1, len(P) + 1) if _occ(strands, P[a:b]) >= smin]
+    keep = [iv for iv in freq
+            if not any(o != iv and o[0] <= iv[0] and iv[1] <= o[1] for o in freq)]
+    return sorted((a, b, _occ(strands, P[a:b])) for a, b in keep if b - a >= min_len)
+
+
+def _pangenome_strands(rnd, n_hap, length, sub, with_n=False):
+    base = "".join(rnd.choice("ACGT") for _ in range(length))
+    haps = ["".join(c if rnd.random() > sub else rnd.choice("ACGT") for c in base) for _ in range(n_hap)]
+    if with_n:
+        haps = ["".join(c if rnd.random() > 0.03 else "N" for c in h) for h in haps]
+    return base, [x for h in haps for x in (h, _rc(h))]
+
+
 def _read_table(name):
     rows = []
     with open(os.path.join(GOLD, name)) as f:
@@ -403,6 +428,158 @@ def test_smem_min_occ():
             if a > 0:
                 lo, hi = _brute_interval(strands, P[a - 1:b])
                 assert hi - lo < smin
+
+
+def test_smem_brute_force_min_occ():
+    """orc_smem at min_occ 2 and 3 against the containment definition, with
+    occ, lo and lo_rc from brute-force intervals: a dropped or misplaced SMEM,
+    a wrong count or a wrong interval fails here."""
+    rnd = random.Random(41)
+    cases = 0
+    for trial in range(60):
+        base, strands = _pangenome_strands(rnd, rnd.randint(2, 4), rnd.randint(6, 16), 0.15)
+        codes, lens = _codes(strands)
+        text = oracle.Text(codes, lens)
+        P = "".join(c if rnd.random() > 0.15 else rnd.choice("ACGT") for c in base)
+        P = "".join(rnd.choice("ACGT") for _ in range(rnd.randint(0, 2))) + P
+        q = np.array([CODE[c] for c in P], np.uint8)
+        for smin in (2, 3):
+            for min_len in (1, 2, 3):
+                want = _brute_smem_occ(strands, P, min_len, smin)
+                got = text.smem(q, min_len, smin)
+                assert [tuple(int(x) for x in r[:3]) for r in got] == want, (strands, P, min_len, smin)
+                for a, b, occ, k, krc in got:
+                    assert (k, k + occ) == _brute_interval(strands, P[a:b])
+                    assert (krc, krc + occ) == _brute_interval(strands, _rc(P[a:b]))
+                cases += len(want)
+    assert cases > 100
+
+
+# --- batched intervals and the seeded SMEM scan --------------------------------
+
+def _scan_patterns(rnd, strands, n, k=oracle.SCAN_K):
+    """Patterns at least k long whose first k symbols are A..T: excerpts of
+    the strands (some running past a strand's end, some mutated) and random
+    strings."""
+    out = []
+    while len(out) < n:
+        if rnd.random() < 0.75:
+            s = rnd.choice(strands)
+            if len(s) < 2:
+                continue
+            t = rnd.randrange(len(s))
+            L = rnd.randint(k, k + 25)
+            p = s[t:t + L]
+            if len(p) < L and rnd.random() < 0.5:
+                p += "".join(rnd.choice("ACGT") for _ in range(L - len(p)))
+            if rnd.random() < 0.3:
+                p = "".join(c if rnd.random() > 0.1 else rnd.choice("ACGT") for c in p)
+        else:
+            p = "".join(rnd.choice("ACGTN" if i >= k else "ACGT") for i in range(rnd.randint(k, k + 10)))
+        if len(p) >= k and all(c in "ACGT" for c in p[:k]):
+            out.append(p)
+    return out
+
+
+def test_scan_intervals_brute_force():
+    """scan_intervals against pure-Python intervals on small lists, with N in
+    the text, patterns that run past strand ends, duplicates and prefixes of
+    one another."""
+    rnd = random.Random(43)
+    for trial in range(25):
+        _, strands = _pangenome_strands(rnd, rnd.randint(1, 4), rnd.randint(10, 45), 0.05, with_n=trial % 2 == 0)
+        strands += ["".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 14)))]
+        pats = _scan_patterns(rnd, strands, 40)
+        pats += [pats[0], pats[1] + "A", pats[1] + "T", pats[2][:oracle.SCAN_K]]
+        codes, lens = _codes(strands)
+        pc, pl = _codes(pats)
+        lo, hi = oracle.scan_intervals(codes, lens, pc, pl)
+        for i, p in enumerate(pats):
+            assert (int(lo[i]), int(hi[i])) == _brute_interval(strands, p), (strands, p)
+
+
+def test_scan_intervals_equals_count():
+    """On a larger pangenome-like list, the one-pass intervals equal the
+    per-pattern scan of orc_count."""
+    rnd = random.Random(47)
+    _, strands = _pangenome_strands(rnd, 16, 3000, 0.01, with_n=True)
+    pats = _scan_patterns(rnd, strands, 3000)
+    codes, lens = _codes(strands)
+    pc, pl = _codes(pats)
+    lo, hi = oracle.scan_intervals(codes, lens, pc, pl, nthreads=3)
+    lo2, hi2 = oracle.count(codes, lens, pc, pl)
+    assert np.array_equal(lo, lo2) and np.array_equal(hi, hi2)
+    assert (hi - lo).max() >= 8
+
+
+def test_scan_intervals_precondition():
+    codes, lens = _codes(["ACGTACGTACGTACGT"])
+    for bad in ("ACGTACGTACG", "ACGTNCGTACGTA"):
+        pc, pl = _codes([bad])
+        with pytest.raises(ValueError):
+            oracle.scan_intervals(codes, lens, pc, pl)
+
+
+def test_smem_scan_brute_force():
+    """The seeded scan against the containment definition directly (pure
+    Python) at min_len 12 and 13, min_occ 1-3."""
+    rnd = random.Random(53)
+    total = 0
+    for trial in range(12):
+        base, strands = _pangenome_strands(rnd, rnd.randint(2, 4), rnd.randint(20, 34), 0.04)
+        P = "".join(c if rnd.random() > 0.04 else rnd.choice("ACGT") for c in base)
+        codes, lens = _codes(strands)
+        q = np.array([CODE[c] for c in P], np.uint8)
+        for smin in (1, 2, 3):
+            for min_len in (12, 13):
+                recs, off = oracle.smem_scan(codes, lens, q, np.array([len(P)], np.int64), min_len, smin)
+                want = _brute_smem_occ(strands, P, min_len, smin)
+                assert [tuple(int(x) for x in r[:3]) for r in recs] == want, (strands, P, min_len, smin)
+                for a, b, occ, k, krc in recs:
+                    assert (k, k + occ) == _brute_interval(strands, P[a:b])
+                    assert (krc, krc + occ) == _brute_interval(strands, _rc(P[a:b]))
+                total += len(want)
+    assert total > 20
+
+
+def test_smem_scan_equals_text_smem():
+    """On pangenome-like lists (the shape the scan is used on), the scan's
+    SMEMs equal Text.smem's, for several min_len and min_occ."""
+    import synth
+    base = synth.random_genome(6000, synth.rng(61, 0))
+    haps = [synth.haplotype(base, 5e-3, 1e-3, synth.rng(61, 1 + h)) for h in range(10)]
+    S = synth.pack(haps)
+    codes, lens = oracle.expand(S.data, S.lens)
+    text = oracle.Text(codes, lens)
+    unseen = [synth.haplotype(base, 5e-3, 1e-3, synth.rng(61, 100 + h)) for h in range(3)]
+    g = np.random.default_rng(61)
+    qs = []
+    for k in range(30):
+        h = unseen[k % 3]
+        L = int(g.integers(40, 1500))
+        st = int(g.integers(0, len(h) - L))
+        q = synth.mutate(h[st:st + L].copy(), 0.01, 0.001, synth.rng(62, k))
+        if k % 2:  # half of them from the other strand
+            q = np.frombuffer(bytes(q[::-1]).translate(bytes.maketrans(b"ACGT", b"TGCA")), np.uint8)
+        qs.append(q)
+    Q = synth.pack(qs)
+    qc, ql = oracle.encode(Q.data, Q.lens)
+    qo = np.concatenate([[0], np.cumsum(ql)])
+    total = 0
+    for min_len, smin in ((12, 1), (15, 2), (20, 3), (31, 1), (31, 2)):
+        recs, off = oracle.smem_scan(codes, lens, qc, ql, min_len, smin, nthreads=4)
+        for i in range(len(qs)):
+            want = text.smem(qc[qo[i]:qo[i + 1]], min_len, smin)
+            assert np.array_equal(recs[off[i]:off[i + 1]], want), (i, min_len, smin)
+            total += len(want)
+    assert total > 500
+
+
+def test_smem_scan_precondition():
+    codes, lens = _codes(["ACGTACGTACGTACGTACGT", "ACGTACGTACGTACGTACGT"])
+    q = np.array([CODE[c] for c in "ACGTACGTACGTACGT"], np.uint8)
+    with pytest.raises(ValueError):
+        oracle.smem_scan(codes, lens, q, np.array([16], np.int64), 11, 1)
 
 
 # --- insertion ranks ----------------------------------------------------------
