@@ -67,6 +67,8 @@ def _load():
     lib.orc_verify.restype = ctypes.c_int64
     lib.orc_verifier_new.argtypes = [_u8p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64, _i64p]
     lib.orc_verifier_new.restype = ctypes.c_void_p
+    lib.orc_verifier_new_mt.argtypes = [_u8p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64, ctypes.c_int, _i64p]
+    lib.orc_verifier_new_mt.restype = ctypes.c_void_p
     lib.orc_verifier_walk.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
     lib.orc_verifier_walk.restype = ctypes.c_int64
     lib.orc_verifier_free.argtypes = [ctypes.c_void_p]
@@ -177,7 +179,7 @@ class Verifier:
     list passes when status is 0 and every string of [0, m) walks cleanly.
     The arrays are kept referenced for the verifier's lifetime."""
 
-    def __init__(self, B: np.ndarray, codes: np.ndarray, lens: np.ndarray):
+    def __init__(self, B: np.ndarray, codes: np.ndarray, lens: np.ndarray, nthreads: int | None = None):
         lib = _load()
         self.B = np.ascontiguousarray(B, dtype=np.uint8)
         self.codes = np.ascontiguousarray(codes, dtype=np.uint8)
@@ -187,8 +189,8 @@ class Verifier:
         cod = self.codes if self.codes.size else np.zeros(1, np.uint8)
         self._keep = (b, cod)
         st = ctypes.c_int64(0)
-        self._h = lib.orc_verifier_new(_p(b, _u8p), self.B.shape[0], _p(cod, _u8p), _p(self.lens, _i64p),
-                                       self.m, ctypes.byref(st))
+        self._h = lib.orc_verifier_new_mt(_p(b, _u8p), self.B.shape[0], _p(cod, _u8p), _p(self.lens, _i64p),
+                                          self.m, _threads(nthreads), ctypes.byref(st))
         self.status = int(st.value)
 
     def walk(self, j0: int, j1: int, nthreads: int | None = None) -> int:

@@ -274,28 +274,65 @@ typedef struct {
     int64_t bad; /* first failing string + 1, or 0 */
 } orc_walk_job;
 
+/* Occurrences of c in B[0, k): the table entry of k's 64-symbol block plus
+ * the matching bytes of the block before k, eight at a time (a byte of
+ * w ^ c8 is zero exactly where B holds c). */
 static int64_t orc_rank(const uint8_t *B, const int64_t *occ, int c, int64_t k)
 {
-    int64_t b = k >> 6, r = occ[b * 6 + c];
-    for (int64_t i = b << 6; i < k; ++i) r += (B[i] == c);
+    int64_t i = k & ~(int64_t)63, r = occ[(k >> 6) * 6 + c];
+    const uint64_t c8 = 0x0101010101010101ULL * (uint64_t)c, lo7 = 0x7F7F7F7F7F7F7F7FULL;
+    for (; i + 8 <= k; i += 8) {
+        uint64_t w;
+        memcpy(&w, B + i, 8);
+        const uint64_t x = w ^ c8;
+        const uint64_t z = ~(((x & lo7) + lo7) | x | lo7); /* high bit of each zero byte */
+        r += __builtin_popcountll(z);
+    }
+    for (; i < k; ++i) r += (B[i] == c);
     return r;
 }
 
+/* Walks the job's strings, several at a time in turn, so that the memory
+ * reads of independent walks overlap. Each walk is the LF walk of one
+ * string: row j holds the sentinel-only suffix of string j, its BWT symbol
+ * is the string's last base, and LF steps the string right to left. */
+#define ORC_WALKS 8
 static void *orc_walk_worker(void *p)
 {
     orc_walk_job *jb = (orc_walk_job *)p;
     jb->bad = 0;
-    for (int64_t j = jb->j0; j < jb->j1; ++j) {
-        /* row j holds the sentinel-only suffix of string j; its BWT symbol is
-         * the string's last base, and LF walks the string right to left */
-        int64_t k = j;
-        const uint8_t *Q = jb->codes + jb->start[j];
-        for (int64_t t = jb->lens[j] - 1; t >= 0; --t) {
-            int c = jb->B[k];
-            if (c != Q[t]) { jb->bad = j + 1; return NULL; }
-            k = jb->C[c] + orc_rank(jb->B, jb->occ, c, k);
+    int64_t wj[ORC_WALKS], wt[ORC_WALKS], wk[ORC_WALKS];
+    int nw = 0;
+    int64_t next = jb->j0;
+    for (;;) {
+        while (nw < ORC_WALKS && next < jb->j1) {
+            wj[nw] = next;
+            wt[nw] = jb->lens[next] - 1;
+            wk[nw] = next;
+            ++nw;
+            ++next;
         }
-        if (jb->B[k] != 0) { jb->bad = j + 1; return NULL; }
+        if (nw == 0) break;
+        for (int a = 0; a < nw;) {
+            const int64_t j = wj[a], k = wk[a], t = wt[a];
+            if (t < 0) {
+                /* the walk is back at the string's start: its row's symbol is $ */
+                if (jb->B[k] != 0 && (!jb->bad || j + 1 < jb->bad)) jb->bad = j + 1;
+                --nw;
+                wj[a] = wj[nw]; wt[a] = wt[nw]; wk[a] = wk[nw];
+                continue;
+            }
+            const int c = jb->B[k];
+            if (c != jb->codes[jb->start[j] + t]) {
+                if (!jb->bad || j + 1 < jb->bad) jb->bad = j + 1;
+                --nw;
+                wj[a] = wj[nw]; wt[a] = wt[nw]; wk[a] = wk[nw];
+                continue;
+            }
+            wk[a] = jb->C[c] + orc_rank(jb->B, jb->occ, c, k);
+            wt[a] = t - 1;
+            ++a;
+        }
     }
     return NULL;
 }
@@ -328,13 +365,44 @@ void orc_verifier_free(void *h)
     free(v);
 }
 
+/* The occurrence table in parallel: each thread counts its range of B
+ * (ranges start at multiples of 64), then writes the running counts of its
+ * range's 64-symbol blocks from the counts of the ranges before it. */
+typedef struct {
+    const uint8_t *B;
+    int64_t *occ;
+    int64_t i0, i1, n;
+    int64_t cnt[8];   /* pass 1: symbols 0..5 of the range, [6] = codes above 5 */
+    int64_t base[6];  /* pass 2: counts before the range */
+    int pass;
+} orc_occ_job;
+
+static void *orc_occ_worker(void *p)
+{
+    orc_occ_job *jb = (orc_occ_job *)p;
+    if (jb->pass == 1) {
+        int64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t i = jb->i0; i < jb->i1; ++i) c[jb->B[i] < 6 ? jb->B[i] : 6]++;
+        memcpy(jb->cnt, c, sizeof(c));
+        return NULL;
+    }
+    int64_t run[6];
+    memcpy(run, jb->base, sizeof(run));
+    for (int64_t i = jb->i0; i < jb->i1; ++i) {
+        if ((i & 63) == 0) memcpy(jb->occ + (i >> 6) * 6, run, sizeof(run));
+        run[jb->B[i]]++;
+    }
+    if (jb->i1 == jb->n && (jb->n & 63) == 0) memcpy(jb->occ + (jb->n >> 6) * 6, run, sizeof(run));
+    return NULL;
+}
+
 /* *status: 0 ok, -1 wrong n, -2 symbol counts differ, -3 allocation failure
  * (the handle is NULL unless *status is 0). */
-void *orc_verifier_new(const uint8_t *B, int64_t n, const uint8_t *codes, const int64_t *lens,
-                       int64_t m, int64_t *status)
+void *orc_verifier_new_mt(const uint8_t *B, int64_t n, const uint8_t *codes, const int64_t *lens,
+                          int64_t m, int nthreads, int64_t *status)
 {
     int64_t want = 0;
-    int64_t cnt[6] = {0, 0, 0, 0, 0, 0}, got[6] = {0, 0, 0, 0, 0, 0};
+    int64_t cnt[6] = {0, 0, 0, 0, 0, 0}, got[7] = {0, 0, 0, 0, 0, 0, 0};
     int64_t q = 0;
     for (int64_t j = 0; j < m; ++j) {
         want += lens[j] + 1;
@@ -342,31 +410,49 @@ void *orc_verifier_new(const uint8_t *B, int64_t n, const uint8_t *codes, const 
     }
     cnt[0] = m;
     if (want != n) { *status = -1; return NULL; }
-    for (int64_t i = 0; i < n; ++i) {
-        if (B[i] > 5) { *status = -2; return NULL; }
-        got[B[i]]++;
-    }
-    for (int c = 0; c < 6; ++c)
-        if (got[c] != cnt[c]) { *status = -2; return NULL; }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > ORC_MAX_THREADS) nthreads = ORC_MAX_THREADS;
     orc_verifier *v = (orc_verifier *)calloc(1, sizeof(orc_verifier));
     if (!v) { *status = -3; return NULL; }
     v->B = B; v->n = n; v->codes = codes; v->lens = lens; v->m = m;
-    v->C[0] = 0;
-    for (int c = 1; c < 6; ++c) v->C[c] = v->C[c - 1] + cnt[c - 1];
-    int64_t nb = (n >> 6) + 1;
+    const int64_t nb = (n >> 6) + 1;
     v->occ = (int64_t *)malloc((size_t)nb * 6 * sizeof(int64_t));
     v->start = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
     if (!v->occ || !v->start) { orc_verifier_free(v); *status = -3; return NULL; }
-    int64_t run[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t i = 0; i < n; ++i) {
-        if ((i & 63) == 0) memcpy(v->occ + (i >> 6) * 6, run, sizeof(run));
-        run[B[i]]++;
+    pthread_t th[ORC_MAX_THREADS];
+    orc_occ_job jobs[ORC_MAX_THREADS];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].B = B; jobs[t].occ = v->occ; jobs[t].n = n; jobs[t].pass = 1;
+        jobs[t].i0 = ((n >> 6) * t / nthreads) << 6;
+        jobs[t].i1 = t == nthreads - 1 ? n : ((n >> 6) * (t + 1) / nthreads) << 6;
+        pthread_create(&th[t], NULL, orc_occ_worker, &jobs[t]);
     }
-    if ((n & 63) == 0) memcpy(v->occ + (n >> 6) * 6, run, sizeof(run));
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    for (int t = 0; t < nthreads; ++t)
+        for (int c = 0; c < 7; ++c) got[c] += jobs[t].cnt[c];
+    int ok = got[6] == 0;
+    for (int c = 0; c < 6; ++c) ok &= got[c] == cnt[c];
+    if (!ok) { orc_verifier_free(v); *status = -2; return NULL; }
+    int64_t run[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < nthreads; ++t) {
+        memcpy(jobs[t].base, run, sizeof(run));
+        for (int c = 0; c < 6; ++c) run[c] += jobs[t].cnt[c];
+        jobs[t].pass = 2;
+        pthread_create(&th[t], NULL, orc_occ_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    v->C[0] = 0;
+    for (int c = 1; c < 6; ++c) v->C[c] = v->C[c - 1] + cnt[c - 1];
     q = 0;
     for (int64_t j = 0; j < m; ++j) { v->start[j] = q; q += lens[j]; }
     *status = 0;
     return v;
+}
+
+void *orc_verifier_new(const uint8_t *B, int64_t n, const uint8_t *codes, const int64_t *lens,
+                       int64_t m, int64_t *status)
+{
+    return orc_verifier_new_mt(B, n, codes, lens, m, 1, status);
 }
 
 /* 0 when strings [j0, j1) are all recovered, else the first failing j + 1. */
@@ -406,7 +492,7 @@ int64_t orc_verify(const uint8_t *B, int64_t n, const uint8_t *codes, const int6
                    int64_t m, int nthreads)
 {
     int64_t status = 0;
-    void *h = orc_verifier_new(B, n, codes, lens, m, &status);
+    void *h = orc_verifier_new_mt(B, n, codes, lens, m, nthreads, &status);
     if (!h) return status;
     int64_t bad = orc_verifier_walk(h, 0, m, nthreads);
     orc_verifier_free(h);
