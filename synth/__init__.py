@@ -12,8 +12,10 @@ own reproducible stream independent of how many others are drawn.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -224,13 +226,34 @@ def config_tiny(seed: int = SEED + 1, n_str: int = 64, length: int = 2000,
     return MergeWorkload("tiny", pack(strs[:half]), pack(strs[half:]), pack(qs))
 
 
+def _workers() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def haplotypes(base: np.ndarray, seed: int, hs, snp: float = 1e-3, indel: float = 1e-4) -> list[np.ndarray]:
+    """Haplotypes h in ``hs`` of ``base``, each from its own stream
+    (STREAM_HAP + h), drawn on a pool of threads; the result does not depend
+    on the number of threads."""
+    hs = list(hs)
+    if len(hs) <= 1:
+        return [haplotype(base, snp, indel, rng(seed, STREAM_HAP + h)) for h in hs]
+    with concurrent.futures.ThreadPoolExecutor(min(_workers(), len(hs))) as ex:
+        return list(ex.map(lambda h: haplotype(base, snp, indel, rng(seed, STREAM_HAP + h)), hs))
+
+
 def pangenome_haplotypes(seed: int, genome_len: int, n_hap: int, snp: float = 1e-3,
                          indel: float = 1e-4, first: int = 0,
                          base: np.ndarray | None = None) -> list[np.ndarray]:
     if base is None:
         base = random_genome(genome_len, rng(seed, STREAM_BASE))
-    return [haplotype(base, snp, indel, rng(seed, STREAM_HAP + h))
-            for h in range(first, first + n_hap)]
+    return haplotypes(base, seed, range(first, first + n_hap), snp, indel)
 
 
 def config_pangenome(seed: int = SEED + 2, genome_len: int = 4_000_000,
@@ -290,9 +313,8 @@ def config_serving(seed: int = SEED + 4, genome_len: int = 10_000_000,
     excerpts of ``n_unseen`` other haplotypes with 1% substitutions and 0.1%
     1-5 bp indels."""
     base = random_genome(genome_len, rng(seed, STREAM_BASE))
-    idx = [haplotype(base, 1e-3, 1e-4, rng(seed, STREAM_HAP + h)) for h in range(n_index)]
-    unseen = [haplotype(base, 1e-3, 1e-4, rng(seed, STREAM_HAP + h))
-              for h in range(n_index, n_index + n_unseen)]
+    idx = haplotypes(base, seed, range(n_index))
+    unseen = haplotypes(base, seed, range(n_index, n_index + n_unseen))
     qs = []
     for q in range(n_queries):
         g = rng(seed, STREAM_QUERY + q)
@@ -326,7 +348,7 @@ class IncrementalWorkload:
         return haplotype(self.base, 1e-3, 1e-4, rng(self.seed, STREAM_HAP + h))
 
     def batch(self, first: int, count: int) -> Strings:
-        return pack([self.haplotype(h) for h in range(first, first + count)])
+        return pack(haplotypes(self.base, self.seed, range(first, first + count)))
 
 
 def config_incremental(seed: int = SEED + 5, genome_len: int = 100_000_000,
