@@ -50,7 +50,8 @@ enum {
     RB3_ENOMEM = -2,   /* device or host allocation failed */
     RB3_EDEVICE = -3,  /* a HIP runtime call or kernel failed */
     RB3_ENOSPC = -4,   /* caller output buffer too small (sizes are reported) */
-    RB3_ELIMIT = -5    /* input beyond a documented size limit */
+    RB3_ELIMIT = -5,   /* input beyond a documented size limit */
+    RB3_EAGAIN = -6    /* the server's queue is full: poll results, then retry */
 };
 
 enum { RB3_MEM_HOST = 0, RB3_MEM_DEVICE = 1 };
@@ -76,8 +77,10 @@ typedef struct rb3_opts {
     rb3_alloc_fn dev_alloc; /* NULL: hipMalloc/hipFree */
     rb3_free_fn dev_free;
     void *alloc_ctx;
-    int64_t chunk_len;     /* LF-chain chunk length for merges; 0 = default (2048, doubled
-                              while a batch would make more than 2^17 chunks) */
+    int64_t chunk_len;     /* longest LF-chain chunk of a merge (chunks are cut
+                              at content-defined positions, at most this long);
+                              0 = default (2048, doubled while a batch would
+                              make more than 2^17 chunks of that length) */
     int32_t launch_per_string; /* 0 (default): one launch of the LF-chain
                               kernel covers every chunk of every new string
                               of a merge. 1: the plain form, one launch per
@@ -94,6 +97,14 @@ typedef struct rb3_opts {
                               two bits per row plus 8 bytes per sample; an
                               index keeps fewer than 2^32 samples and 2^24
                               strands (RB3_ELIMIT otherwise). */
+    int32_t occ_interval;  /* occurrence-checkpoint interval I of the index
+                              (symbols per checkpoint, Table 1's occ sampled
+                              every I symbols): 0 (default) = the library's
+                              choice, else 128; other values give RB3_EINVAL. */
+    int32_t smem_segment;  /* rb3_smem cuts long queries into segments of this
+                              many positions, each searched by its own lane
+                              (results do not depend on it). 0 (default): from
+                              the batch size (32 .. 4096). Else 1 .. 2^20. */
 } rb3_opts;
 
 /* Fill *o with the defaults above. */
@@ -171,8 +182,11 @@ int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64
              int64_t *out_off);
 
 /* Work done by the calling thread's last successful rb3_smem call: the
- * number of bi-interval extensions (each reads rank-all at two positions). */
-int rb3_last_smem_stats(int64_t *extensions);
+ * number of bi-interval extensions (each reads rank-all at two positions,
+ * k and k + s) and the number of distinct 64-byte index blocks those reads
+ * touched (one per extension when both positions share a block, else two).
+ * Either pointer may be NULL. */
+int rb3_last_smem_stats(int64_t *extensions, int64_t *blocks);
 
 /*
  * rb3_locate: position of the suffix at each row (Sec. 2.4): strand[i] is
@@ -211,11 +225,15 @@ int rb3_info(const rb3_index *idx, int64_t *n, int64_t *m, int64_t C[6]);
 /* Write the BWT as n symbol codes into codes (host, n bytes). */
 int rb3_export(const rb3_index *idx, uint8_t *codes);
 
-/* Build an index from n BWT symbol codes (host or device per mem). Codes
- * must be 0..5 and include at least one 0; otherwise RB3_EINVAL. The codes
- * are taken as given: the call does not check that they form a BWT. */
-int rb3_import(const rb3_opts *o, const uint8_t *codes, int64_t n, int32_t mem,
-               rb3_index **out);
+/* Build an index from n BWT symbol codes (host or device per mem), the BWT
+ * of m strands whose lengths (sentinels excluded) are lens[0..m) (host).
+ * Symbol-count check (Sec. 2.1: a BWT of m sentinel-terminated strings holds
+ * each string's symbols plus one $ per string): the codes must be 0..5, hold
+ * exactly m sentinels (0), and n must equal sum(lens[j] + 1); otherwise
+ * RB3_EINVAL. Beyond these counts the codes are taken as given: the call
+ * does not walk them to check that they form a BWT. */
+int rb3_import(const rb3_opts *o, const uint8_t *codes, int64_t n, const int64_t *lens, int64_t m,
+               int32_t mem, rb3_index **out);
 
 /* Deep copy of an index on the same device. The copy uses the caller's
  * stream if the source was given one; otherwise it gets a stream of its own,
@@ -248,7 +266,11 @@ typedef struct rb3_server_opts {
     int32_t pad;
     int64_t max_batch_queries;  /* default 4096 */
     int64_t max_batch_bases;    /* query bases per batch; default 8 Mi */
-    int64_t mem_budget;         /* device bytes for requests in flight; default 4 GiB */
+    int64_t mem_budget;         /* device bytes for requests in flight; 0 (default):
+                                   half of the device memory free when the server
+                                   is created (at least 64 MiB) */
+    int64_t max_queued;         /* requests waiting for a batch; a submission
+                                   beyond it gives RB3_EAGAIN; default 65536 */
 } rb3_server_opts;
 
 typedef struct rb3_result {
@@ -262,7 +284,8 @@ typedef struct rb3_result {
 void rb3_server_opts_init(rb3_server_opts *so);
 int rb3_server_create(const rb3_index *idx, const rb3_server_opts *so, rb3_server **out);
 /* Queue one request; the query is copied. min_len / min_occ are used by SMEM
- * requests (>= 1). Invalid bytes give RB3_EINVAL at submission. */
+ * requests (>= 1). Invalid bytes give RB3_EINVAL at submission; a full queue
+ * (max_queued requests waiting) gives RB3_EAGAIN and queues nothing. */
 int rb3_server_submit(rb3_server *s, int32_t kind, const uint8_t *q, int64_t len, int32_t min_len,
                       int64_t min_occ, uint64_t *ticket);
 /* Move finished results into res (res_cap entries) and their SMEM records into
@@ -272,16 +295,21 @@ int rb3_server_submit(rb3_server *s, int32_t kind, const uint8_t *q, int64_t len
 int rb3_server_poll(rb3_server *s, int32_t wait_ms, rb3_result *res, int64_t res_cap, rb3_smem_t *recs,
                     int64_t rec_cap, int64_t *n_res, int64_t *n_recs);
 /* Queue length, batches in flight, batches run, requests served, largest
- * batch, and the time the workers spent running batches (microseconds,
- * summed over workers). Any pointer may be NULL. */
+ * batch, the time the workers spent running batches (microseconds, summed
+ * over workers) and the device-memory budget in use. Any pointer may be
+ * NULL. */
 int rb3_server_stats(rb3_server *s, int64_t *queued, int64_t *inflight, int64_t *batches, int64_t *served,
-                     int64_t *max_batch, int64_t *busy_us);
+                     int64_t *max_batch, int64_t *busy_us, int64_t *mem_budget);
 /* Open-loop request driver for latency measurement: submits query i (kind,
  * min_len, min_occ shared) at arrival_s[i] seconds after the call starts
  * (arrival times non-decreasing), polls from a second thread, and writes
  * latency_s[i] = time from the arrival to the result. *wall_s (may be NULL)
  * receives the time until the last result. The results themselves are
- * discarded. The call returns after every accepted request is answered. */
+ * discarded; results of other requests stay queued for their clients, but no
+ * other thread may call rb3_server_poll while a replay runs (it could take
+ * the replay's results). A submission refused with RB3_EAGAIN is retried
+ * until accepted, its latency counting from its arrival time. The call
+ * returns after every request is answered. */
 int rb3_server_replay(rb3_server *s, int32_t kind, const uint8_t *q, const int64_t *qlens, int64_t n,
                       int32_t min_len, int64_t min_occ, const double *arrival_s, double *latency_s,
                       double *wall_s);
@@ -302,6 +330,18 @@ void rb3_server_free(rb3_server *s);
 int rb3_prof_enable(int on);
 int rb3_prof_reset(void);
 int rb3_prof_read(char *names, int64_t *launches, double *ms, int64_t cap, int64_t *n_out);
+
+/*
+ * Test hook for failure handling: while stage is nonzero, every rb3_merge
+ * and rb3_build in the process stops after that stage of the merge and
+ * returns RB3_EDEVICE (1 insertion ranks by LF chains, 2 radix sort of the
+ * new suffixes, 3 ordering of tied suffixes, 4 interleave into the merged
+ * BWT, 5 checkpoint rebuild), after the kernels already queued have run to
+ * completion. 0 switches it off. The merge's strong guarantee means the
+ * index is then unchanged; tests use this (with an allocator hook that
+ * fails at a chosen allocation) to check that guarantee at every stage.
+ */
+int rb3_test_fail_merge_after(int32_t stage);
 
 /* Last merge statistics: per-stage counters useful for throughput accounting
  * (suffixes inserted, rank steps, tie rounds, ...). keys receives up to cap

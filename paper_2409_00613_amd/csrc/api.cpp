@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -22,7 +23,7 @@ namespace rb3 {
 // ---------------------------------------------------------------------------
 static thread_local std::string g_err;
 // extensions performed by the last rb3_smem call of this thread
-static thread_local int64_t g_last_smem_exts = 0;
+static thread_local int64_t g_last_smem_exts[2] = {0, 0};
 static thread_local int64_t g_last_locate_steps = 0;
 static thread_local int g_err_code = 0;
 
@@ -34,6 +35,14 @@ void set_error(int code, const std::string &msg) {
 static int fail(int code, const char *msg) {
     set_error(code, msg);
     return code;
+}
+
+static std::atomic<int> g_fail_after{0};
+
+int fault_point(int stage) {
+    if (g_fail_after.load(std::memory_order_relaxed) != stage) return RB3_OK;
+    set_error(RB3_EDEVICE, "merge stopped after stage " + std::to_string(stage) + " (test hook)");
+    return RB3_EDEVICE;
 }
 
 int check_launch(const char *name) {
@@ -162,6 +171,10 @@ static int ctx_from_opts(const rb3_opts *o, Ctx &c) {
     if ((c.alloc == nullptr) != (c.free_fn == nullptr)) return fail(RB3_EINVAL, "dev_alloc and dev_free must be given together");
     if (o->ssa_rate < 0 || o->ssa_rate > (1 << 24)) return fail(RB3_EINVAL, "ssa_rate must be in 0 .. 2^24");
     c.ssa = o->ssa_rate;
+    if (o->occ_interval != 0 && o->occ_interval != (int32_t)BLK_SYMS)
+        return fail(RB3_EINVAL, "occ_interval must be 0 or 128");
+    if (o->smem_segment < 0 || o->smem_segment > (1 << 20)) return fail(RB3_EINVAL, "smem_segment must be in 0 .. 2^20");
+    c.smem_seg_fixed = o->smem_segment;
     RB3_HIP(hipSetDevice(c.device));
     if (o->stream) {
         c.stream = (hipStream_t)o->stream;
@@ -187,6 +200,7 @@ static Ctx call_ctx(const IndexData &d) {
     c.launch_per_string = d.ctx.launch_per_string;
     c.both = d.ctx.both;
     c.ssa = d.ctx.ssa;
+    c.smem_seg_fixed = d.ctx.smem_seg_fixed;
     return c;
 }
 
@@ -270,9 +284,9 @@ static int do_merge(Ctx &c, IndexData &d, const uint8_t *seq, const int64_t *len
     DBuf hold, Q, err;
     const uint8_t *d_seq = nullptr;
     RB3_TRY(stage(c, seq, total, mem, hold, &d_seq));
-    // the tie kernels read whole 8-byte words: 16 zero bytes follow the codes
-    RB3_ALLOC(Q, &c, n2 + 16);
-    RB3_HIP(hipMemsetAsync(Q.as<uint8_t>() + n2, 0, 16, c.stream));
+    // kernels read whole words and lines past a strand's end: zero bytes follow the codes
+    RB3_ALLOC(Q, &c, n2 + Q_PAD);
+    RB3_HIP(hipMemsetAsync(Q.as<uint8_t>() + n2, 0, Q_PAD, c.stream));
     RB3_ALLOC(err, &c, sizeof(int32_t));
     RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
     RB3_TRY(encode_strands(c, d_seq, lens, n_seqs, d.ctx.both, Q.as<uint8_t>(), n2, err.as<int32_t>()));
@@ -387,6 +401,7 @@ const char *rb3_strerror(int err) {
     case RB3_EDEVICE: return "device error";
     case RB3_ENOSPC: return "output buffer too small";
     case RB3_ELIMIT: return "size limit exceeded";
+    case RB3_EAGAIN: return "queue full, retry later";
     default: return "unknown error";
     }
 }
@@ -462,15 +477,18 @@ int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64
     if (n_q == 0) return RB3_OK;
     RB3_HIP(hipSetDevice(idx->d.ctx.device));
     Ctx c = call_ctx(idx->d);
-    int64_t exts = 0;
-    int rc = run_smem(c, idx->d.dev(), q, qlens, n_q, total, mem, min_len, min_occ, out, out_cap, out_off, &exts);
-    if (rc == RB3_OK) g_last_smem_exts = exts;
+    int64_t exts[2] = {0, 0};
+    int rc = run_smem(c, idx->d.dev(), q, qlens, n_q, total, mem, min_len, min_occ, out, out_cap, out_off, exts);
+    if (rc == RB3_OK) {
+        g_last_smem_exts[0] = exts[0];
+        g_last_smem_exts[1] = exts[1];
+    }
     return finish(c, rc);
 }
 
-int rb3_last_smem_stats(int64_t *extensions) {
-    if (!extensions) return fail(RB3_EINVAL, "extensions is NULL");
-    *extensions = g_last_smem_exts;
+int rb3_last_smem_stats(int64_t *extensions, int64_t *blocks) {
+    if (extensions) *extensions = g_last_smem_exts[0];
+    if (blocks) *blocks = g_last_smem_exts[1];
     return RB3_OK;
 }
 
@@ -589,10 +607,21 @@ int rb3_export(const rb3_index *idx, uint8_t *codes) {
     return finish(c, rc);
 }
 
-int rb3_import(const rb3_opts *o, const uint8_t *codes, int64_t n, int32_t mem, rb3_index **out) {
+int rb3_import(const rb3_opts *o, const uint8_t *codes, int64_t n, const int64_t *lens, int64_t m, int32_t mem,
+               rb3_index **out) {
     if (!out) return fail(RB3_EINVAL, "out is NULL");
     if (n < 1 || !codes) return fail(RB3_EINVAL, "need at least one code");
+    if (m < 1 || !lens) return fail(RB3_EINVAL, "need the lengths of the m >= 1 strands");
     if (mem != RB3_MEM_HOST && mem != RB3_MEM_DEVICE) return fail(RB3_EINVAL, "bad mem");
+    {
+        // a BWT of m strands of these lengths has n = sum (L_j + 1) symbols
+        int64_t want = 0;
+        for (int64_t j = 0; j < m; ++j) {
+            if (lens[j] < 1) return fail(RB3_EINVAL, "a strand length is below 1");
+            want += lens[j] + 1;
+        }
+        if (want != n) return fail(RB3_EINVAL, "symbol-count check: n differs from the sum of strand lengths + m");
+    }
     if (o && o->ssa_rate != 0)
         return fail(RB3_EINVAL, "suffix-array samples need the strings: build the index with rb3_build");
     rb3_index *ix = new (std::nothrow) rb3_index();
@@ -618,7 +647,7 @@ int rb3_import(const rb3_opts *o, const uint8_t *codes, int64_t n, int32_t mem, 
         RB3_TRY(pack_codes(c, d_codes, n, blk.as<uint4>()));
         int64_t C[6], cnt[6];
         RB3_TRY(build_checkpoints(c, blk.as<uint4>(), n, sb.as<int64_t>(), C, cnt));
-        if (cnt[0] < 1) return fail(RB3_EINVAL, "no sentinel ($) in the codes");
+        if (cnt[0] != m) return fail(RB3_EINVAL, "symbol-count check: the codes hold a number of sentinels ($) other than m");
         ix->d.n = n;
         ix->d.m = cnt[0];
         for (int i = 0; i < 6; ++i) ix->d.C[i] = C[i];
@@ -703,6 +732,12 @@ void rb3_index_free(rb3_index *idx) {
     c.free_now(idx->d.smp_val);
     if (idx->d.ctx.own_stream && idx->d.ctx.stream) (void)hipStreamDestroy(idx->d.ctx.stream);
     delete idx;
+}
+
+int rb3_test_fail_merge_after(int32_t stage) {
+    if (stage < 0 || stage > 5) return fail(RB3_EINVAL, "stage must be 0 .. 5");
+    g_fail_after.store(stage);
+    return RB3_OK;
 }
 
 int rb3_prof_enable(int on) {

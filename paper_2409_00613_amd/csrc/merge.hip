@@ -33,14 +33,6 @@
 
 namespace rb3 {
 
-struct Chunk {
-    int64_t p0;     // position in Q of the chunk's first symbol
-    int32_t len;    // symbols in the chunk
-    int32_t last;   // 1 if the chunk ends at the strand's sentinel
-    int32_t first;  // 1 if the chunk starts at the strand's first symbol
-    int32_t pad;
-};
-
 // Sort key of a new suffix at position p:
 //   (l - m1) << lshift | packed(Q[p..p+w)) << 3 | emit
 // where packed holds w codes, the first in the most significant place, with
@@ -63,72 +55,6 @@ __device__ __forceinline__ uint64_t pack_ahead(const uint8_t *__restrict__ Q, in
 }
 
 
-// Keys of consecutive positions, walked downwards, collected in an 8-entry
-// register window: slot j holds the key of position p + j, where p is the
-// last position pushed. Flushing at a multiple of 8 with all slots valid
-// writes one whole 64-byte line; otherwise only the valid slots are stored.
-struct KeyWindow {
-    uint64_t b[8];
-    uint32_t vm;  // bit j: slot j holds a key to store
-    __device__ __forceinline__ void init() {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) b[j] = 0;
-        vm = 0;
-    }
-    __device__ __forceinline__ void push(uint64_t key, bool valid) {
-#pragma unroll
-        for (int j = 7; j > 0; --j) b[j] = b[j - 1];
-        b[0] = key;
-        vm = ((vm << 1) | (valid ? 1u : 0u)) & 0xFFu;
-    }
-    __device__ __forceinline__ void flush(uint64_t *__restrict__ K, int64_t p) {
-        // the keys are streamed out: non-temporal stores keep them from
-        // displacing the index in the caches
-        if (vm == 0xFFu && (p & 7) == 0) {
-            uint64_t *dst = K + p;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) __builtin_nontemporal_store(b[j], dst + j);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if ((vm >> j) & 1u) __builtin_nontemporal_store(b[j], K + p + j);
-        }
-        vm = 0;
-    }
-};
-
-// The symbols of a right-to-left walk over Q, read one aligned 8-byte word
-// at a time: the word below the current one is requested as soon as the
-// walk enters the current one, so the walk's steps wait only on the index.
-// Q must be 8-byte aligned with readable bytes up to the end of the word
-// holding its last symbol.
-struct BackSyms {
-    const uint64_t *w;
-    int64_t wi;     // index of the word holding the current position
-    uint64_t cur;   // word wi
-    uint64_t prv;   // word wi - 1 (0 when wi == 0)
-    __device__ __forceinline__ void init(const uint8_t *Q, int64_t p) {
-        w = (const uint64_t *)Q;
-        wi = p >> 3;
-        cur = w[wi];
-        prv = wi > 0 ? w[wi - 1] : 0ull;
-    }
-    // Q[p], p in word wi
-    __device__ __forceinline__ uint32_t at(int64_t p) const { return (uint32_t)(cur >> (8 * (p & 7))) & 0xFFu; }
-    // Q[p - 1], 0 for p == 0
-    __device__ __forceinline__ uint32_t before(int64_t p) const {
-        return (p & 7) ? (uint32_t)(cur >> (8 * ((p - 1) & 7))) & 0xFFu : (uint32_t)(prv >> 56);
-    }
-    // done with p: move to p - 1
-    __device__ __forceinline__ void next(int64_t p) {
-        if ((p & 7) == 0) {
-            --wi;
-            cur = prv;
-            prv = wi > 0 ? w[wi - 1] : 0ull;
-        }
-    }
-};
-
 // Rows lo .. lo + 63 of B1 holding symbol a, as a mask (bit j: row lo + j),
 // from the block holding lo (BL) and, when two is set, the block after it
 // (BH). Rows past the blocks read as 0: a caller only uses rows below the
@@ -143,6 +69,44 @@ __device__ __forceinline__ uint64_t rows_with(const Block &BL, const Block &BH, 
     return sh ? (x >> sh) | (y << (64 - sh)) : x;
 }
 
+// Byte x of a 16-byte window held as two words (x in [0, 16)).
+__device__ __forceinline__ uint32_t win_byte(uint64_t w0, uint64_t w1, int x) {
+    return (uint32_t)((x < 8 ? (w0 >> (8 * x)) : (w1 >> (8 * (x - 8)))) & 0xFFu);
+}
+
+constexpr int CH_GROUP = 8;       // steps per group (keys written out per group)
+constexpr int CH_WG = 256;        // threads per workgroup of the chain kernel
+constexpr int CH_SB_LDS_MAX = 640;  // superblocks whose rows fit in LDS (5 int64 each)
+
+// A wave's keys (or records) of one group, slot s of a lane holding position
+// P - s, written out through LDS: lane L puts its 8 values in order of
+// position, then in each store instruction eight consecutive lanes write
+// one lane's run of 8 positions (64 bytes, each lane an aligned 8-byte
+// word), so an instruction writes 8 whole runs instead of 64 values
+// scattered over 64 runs. nvalid (per lane): the slots 0 .. nvalid - 1 hold
+// values to write (the others are past the chunk's end, or not records).
+// buf: this wave's 64 x 8 words of LDS.
+__device__ __forceinline__ void wave_write_group(uint64_t *__restrict__ buf, const uint64_t (&v)[CH_GROUP],
+                                                 int64_t P, int nvalid, uint64_t *__restrict__ dst) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 0; s < CH_GROUP; ++s) buf[lane * CH_GROUP + (CH_GROUP - 1 - s)] = v[s];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int k = lane & (CH_GROUP - 1);  // run slot k holds position P_L - 7 + k
+#pragma unroll
+    for (int r = 0; r < 64 / CH_GROUP; ++r) {
+        const int L = CH_GROUP * r + (lane >> 3);
+        const int64_t PL = __shfl(P, L);
+        const int nv = __shfl(nvalid, L);
+        const uint64_t x = buf[L * CH_GROUP + k];
+        if (k >= CH_GROUP - nv) dst[PL - (CH_GROUP - 1) + k] = x;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // One lane per chunk. The walk covers the chunk right to left. Until the
 // interval [lo, hi] of possible values closes, each step records the
 // interval's new low end pi(a, lo) (in K, where the position's key goes
@@ -153,71 +117,120 @@ __device__ __forceinline__ uint64_t rows_with(const Block &BL, const Block &BH, 
 // so the fix-up pass completes an unresolved end from the right
 // neighbour's exact value with a popcount per position instead of a
 // dependent read of the index.
-__global__ void k_chain(DevIndex ix, const uint8_t *__restrict__ Q, const Chunk *__restrict__ ch,
-                        int64_t nch, int64_t m1, int w, uint64_t *__restrict__ K, uint64_t *__restrict__ M,
-                        int32_t *__restrict__ unres, int32_t *__restrict__ ulen, int32_t *__restrict__ nwu,
-                        unsigned long long *__restrict__ stats) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= nch) return;
-    Chunk c = ch[i];
-    const int lshift = 3 + 3 * w, wsh = 3 * (w - 1);
-    int64_t p1 = c.p0 + c.len;
-    uint64_t packed = 0;
-    bool point;
-    int64_t l = m1, lo = m1, hi = ix.n;
-    if (c.last) {
-        point = true;
-        K[p1] = (uint64_t)Q[p1 - 1];  // sentinel suffix: l = m1, no symbols
-    } else {
-        point = false;
-        packed = pack_ahead(Q, p1, w);
+//
+// Lane t walks chunk perm[t] (chunk t when perm is null): neighbouring lanes
+// get chunks whose walks begin with the same symbols (chunks.hip), so they
+// read the same index blocks at the same step. The lanes of a wave step
+// together in groups of CH_GROUP steps: a step's key and record go to
+// registers (slot s of the group), and the wave writes the group's keys and
+// records out together (wave_write_group) and fetches the symbols of its
+// next group. Point lanes (value known) and interval lanes (value in
+// [lo, hi]) share one step: the block of l or lo is read by every lane, the
+// block of hi only by interval lanes. With SB_LDS the superblock rows (the
+// int64 counts before each 2^24-symbol superblock) are read from LDS. Merges
+// into a non-empty index only: keys hold one symbol (key_syms = 1).
+template <bool SB_LDS>
+__global__ void __launch_bounds__(CH_WG) k_chain(DevIndex ix, const uint8_t *__restrict__ Q,
+                                                 const Chunk *__restrict__ ch, const uint32_t *__restrict__ perm,
+                                                 int64_t nch, int64_t m1, uint64_t *__restrict__ K,
+                                                 uint64_t *__restrict__ M, int32_t *__restrict__ unres,
+                                                 int32_t *__restrict__ ulen, int32_t *__restrict__ nwu,
+                                                 unsigned long long *__restrict__ stats) {
+    extern __shared__ int64_t sb_lds[];  // SB_LDS: 5 per superblock (A .. N)
+    __shared__ uint64_t stage[CH_WG / 64][64 * CH_GROUP];
+    if (SB_LDS) {
+        const int64_t nsb = num_superblocks(ix.n);
+        for (int64_t e = threadIdx.x; e < nsb * 5; e += CH_WG)
+            sb_lds[e] = ix.sb[(e / 5) * SB_STRIDE + 1 + (e % 5)];
+        __syncthreads();
     }
+    uint64_t *buf = stage[threadIdx.x >> 6];
+    const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool live = lane < nch;
+    const int64_t i = !live ? 0 : (perm ? (int64_t)perm[lane] : lane);
+    Chunk c;
+    c.p0 = 0;
+    c.len = 0;
+    c.last = 1;
+    if (live) c = ch[i];
+    const int64_t p1 = c.p0 + c.len;
+    const int32_t len = c.len;
+    bool point = c.last != 0;
+    int64_t l = m1, lo = m1, hi = ix.n;
+    if (live && c.last) K[p1] = (uint64_t)Q[p1 - 1];  // sentinel suffix: l = m1, no symbols
+    const uint64_t *Qw = (const uint64_t *)Q;
     int32_t unresolved = 0, nwide = 0;
     int64_t wide = 0;
-    KeyWindow win, rec;
-    win.init();
-    rec.init();
-    BackSyms sy;
-    sy.init(Q, p1 - 1);
-    for (int64_t p = p1 - 1; p >= c.p0; --p) {
-        const uint32_t a = sy.at(p);
-        const uint32_t emit = sy.before(p);
-        packed = ((uint64_t)a << wsh) | (packed >> 3);
-        if (point) {
-            l = pi_sym(ix, (int)a, l);
-            win.push(make_key(l - m1, packed, emit, lshift), true);
-        } else {
-            // both ends' blocks are requested together (the same block
-            // twice when they share it)
-            const int64_t bl = lo >> BLK_SHIFT, bh = hi >> BLK_SHIFT;
-            const Block BL = load_block(ix.blk, bl);
-            const Block BH = load_block(ix.blk, bh);
-            const int64_t nlo = pi_from_block(ix, BL, (int)a, lo);
-            const int64_t nhi = pi_from_block(ix, BH, (int)a, hi);
-            if (bh != bl) ++wide;
-            if (nlo == nhi) {
-                point = true;
-                l = nlo;
-                win.push(make_key(l - m1, packed, emit, lshift), true);
-                // the records end at p + 1
-                if (rec.vm) rec.flush(M, p + 1);
+    for (int32_t t0 = 0; __ballot(t0 < len) != 0; t0 += CH_GROUP) {
+        // positions P .. P - 7 of this group need the symbols Q[P - 8 .. P]
+        const int64_t P = p1 - 1 - t0;
+        const int64_t wb = (t0 < len ? (P - CH_GROUP > 0 ? P - CH_GROUP : 0) : 0) >> 3;
+        const uint64_t w0 = Qw[wb], w1 = Qw[wb + 1];
+        uint64_t kslot[CH_GROUP], rslot[CH_GROUP];
+        int nrec = 0;
+#pragma clang loop unroll(full)
+        for (int s = 0; s < CH_GROUP; ++s) {
+            kslot[s] = 0;
+            rslot[s] = 0;
+            const bool act = t0 + s < len;
+            const int64_t p = P - s;
+            const int x = (int)(p - (wb << 3));
+            const uint32_t a = act ? win_byte(w0, w1, x) : 1u;
+            const uint32_t emit = (act && p > 0) ? win_byte(w0, w1, x - 1) : 0u;
+            // the block of l (point) or lo (interval), and of hi (interval)
+            const int64_t x0 = act ? (point ? l : lo) : 0;
+            const bool two = act && !point;
+            const int64_t x1 = two ? hi : x0;
+            const int64_t b0 = x0 >> BLK_SHIFT, b1 = x1 >> BLK_SHIFT;
+            const Block B0 = load_block(ix.blk, b0);
+            Block B1 = B0;
+            if (two) B1 = load_block(ix.blk, b1);
+            int64_t s0, s1;
+            if (SB_LDS) {
+                s0 = sb_lds[(x0 >> SB_SHIFT) * 5 + (a - 1)];
+                s1 = sb_lds[(x1 >> SB_SHIFT) * 5 + (a - 1)];
             } else {
-                ++unresolved;
-                win.push((uint64_t)nlo, true);
-                if (hi - lo > 64) ++nwide;  // the widths only shrink: these come first
-                rec.push(hi - lo <= 64 ? rows_with(BL, BH, bh != bl, lo, (int)a) & low_mask((int)(hi - lo)) : 0ull,
-                         true);
-                if ((p & 7) == 0 || p == c.p0) rec.flush(M, p);
+                s0 = ix.sb[(x0 >> SB_SHIFT) * SB_STRIDE + a];
+                s1 = two ? ix.sb[(x1 >> SB_SHIFT) * SB_STRIDE + a] : s0;
             }
-            lo = nlo;
-            hi = nhi;
+            __builtin_amdgcn_sched_barrier(0);
+            const int64_t n0 = s0 + (int64_t)ckpt_field(B0.q3, (int)a - 1) +
+                               inblock_count(B0, (int)a, (int)(x0 & (BLK_SYMS - 1)));
+            const int64_t n1 = two ? s1 + (int64_t)ckpt_field(B1.q3, (int)a - 1) +
+                                         inblock_count(B1, (int)a, (int)(x1 & (BLK_SYMS - 1)))
+                                   : n0;
+            if (act) {
+                if (point) {
+                    l = n0;
+                    kslot[s] = make_key(l - m1, a, emit, 6);
+                } else {
+                    if (b1 != b0) ++wide;
+                    if (n0 == n1) {
+                        point = true;
+                        l = n0;
+                        kslot[s] = make_key(l - m1, a, emit, 6);
+                    } else {
+                        ++unresolved;
+                        kslot[s] = (uint64_t)n0;
+                        const int64_t span = hi - lo;
+                        if (span > 64) ++nwide;  // the widths only shrink: these come first
+                        rslot[s] = span <= 64 ? rows_with(B0, B1, b1 != b0, lo, (int)a) & low_mask((int)span) : 0ull;
+                        nrec = s + 1;  // a chunk's records are its first steps
+                    }
+                    lo = n0;
+                    hi = n1;
+                }
+            }
         }
-        if ((p & 7) == 0 || p == c.p0) win.flush(K, p);
-        sy.next(p);
+        const int nkey = len - t0 < 0 ? 0 : (len - t0 > CH_GROUP ? CH_GROUP : len - t0);
+        wave_write_group(buf, kslot, P, nkey, K);
+        if (__ballot(nrec > 0) != 0) wave_write_group(buf, rslot, P, nrec, M);
     }
-    unres[i] = unresolved;
-    ulen[i] = unresolved;
-    nwu[i] = nwide;
+    if (live) {
+        unres[i] = unresolved;
+        ulen[i] = unresolved;
+        nwu[i] = nwide;
+    }
     if (wide) atomicAdd(&stats[1], (unsigned long long)wide);
 }
 
@@ -1387,7 +1400,9 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint64_t *__restrict__ Q
             sub[s] = 0;
             act[s] = i < k;
         }
+        bool past = false;  // a member read past the batch (inconsistent keys): abandon the group
         for (int64_t d0 = 1;; d0 += CHUNK_SYMS * WALK_DEPTHS) {
+            if (__ballot(past) != 0) break;
             bool any = false;
 #pragma unroll
             for (int s = 0; s < MPL; ++s) any |= __ballot(act[s]) != 0;
@@ -1410,7 +1425,10 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint64_t *__restrict__ Q
                     kk[s] = act[s] ? kv[s][t] : 0ull;
                     if (act[s]) {
                         ++steps;
-                        if (kk[s] == ~0ull) atomicOr(guard, GUARD_RERANK);
+                        if (kk[s] == ~0ull) {
+                            atomicOr(guard, GUARD_RERANK);
+                            past = true;
+                        }
                     }
                     sent[s] = act[s] && chunk_has_sentinel(kk[s]);
                     rem[s] = __ballot(act[s]);
@@ -1555,7 +1573,9 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ Q,
         if (tid == 0) ssz[0] = (uint16_t)k;
         __syncthreads();
         int64_t d0 = 1;
+        int past = 0;  // a member read past the batch (inconsistent keys): abandon the group
         for (;;) {
+            if (__syncthreads_or(past)) break;
             uint64_t kv[MPT][DEPTHS];
 #pragma unroll
             for (int j = 0; j < MPT; ++j) {
@@ -1576,7 +1596,10 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ Q,
                 for (int j = 0; j < MPT; ++j) {
                     const int o = tid + j * T;
                     if (o < k && sact[o]) {
-                        if (kv[j][t] == ~0ull) atomicOr(guard, GUARD_RERANK);
+                        if (kv[j][t] == ~0ull) {
+                            atomicOr(guard, GUARD_RERANK);
+                            past = 1;
+                        }
                         sc[o] = kv[j][t];
                     }
                 }
@@ -2028,39 +2051,24 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
 
     // ---- 1. insertion ranks ----
     if (n1 > 0) {
-        // default: 2048 positions, doubled while the batch would make more than
-        // 2^17 chunks (past that many lanes, random block reads stop gaining
-        // throughput, while the unresolved share of each chunk still grows)
+        // default: at most 2048 positions, doubled while the batch would make
+        // more than 2^17 chunks (past that many lanes, random block reads stop
+        // gaining throughput, while the unresolved share of each chunk still
+        // grows)
         int64_t CL = c.chunk_len;
         if (CL <= 0) {
             CL = 2048;
             while (CL < (1 << 20) && n2 / CL > (1 << 17)) CL *= 2;
         }
         if (CL > (1 << 30)) CL = 1 << 30;
-        std::vector<Chunk> chunks;
-        std::vector<int64_t> first_chunk;  // per strand, for the one-launch-per-string form
-        int64_t off = 0;
-        for (int64_t s = 0; s < m2; ++s) {
-            int64_t L = strand_lens[s];
-            first_chunk.push_back((int64_t)chunks.size());
-            for (int64_t t0 = 0; t0 < L; t0 += CL) {
-                int64_t t1 = t0 + CL < L ? t0 + CL : L;
-                Chunk ck;
-                ck.p0 = off + t0;
-                ck.len = (int32_t)(t1 - t0);
-                ck.last = t1 == L ? 1 : 0;
-                ck.first = t0 == 0 ? 1 : 0;
-                ck.pad = 0;
-                chunks.push_back(ck);
-            }
-            off += L + 1;
-        }
-        int64_t nch = (int64_t)chunks.size();
+        if (CL < 16) CL = 16;
+        DBuf d_ch, d_perm;
+        int64_t nch = 0;
+        RB3_TRY(make_chunks(c, d_Q, n2, CL, d_ch, &nch, d_perm, guard));
         st.chunks = nch;
         st.chunk_len = CL;
         st.chain_steps = n2 - m2;
-        DBuf d_ch, unres, ulen, nwu, segn, recm, readyA, readyB, pend;
-        RB3_ALLOC(d_ch, &c, nch * sizeof(Chunk));
+        DBuf unres, ulen, nwu, segn, recm, readyA, readyB, pend;
         RB3_ALLOC(unres, &c, nch * sizeof(int32_t));
         RB3_ALLOC(ulen, &c, nch * sizeof(int32_t));
         RB3_ALLOC(nwu, &c, nch * sizeof(int32_t));
@@ -2073,23 +2081,45 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         RB3_ALLOC(readyA, &c, (nch + 1) * sizeof(int32_t));
         RB3_ALLOC(readyB, &c, (nch + 1) * sizeof(int32_t));
         RB3_ALLOC(pend, &c, sizeof(int32_t));
-        RB3_HIP(hipMemcpyAsync(d_ch.p, chunks.data(), nch * sizeof(Chunk), hipMemcpyHostToDevice, c.stream));
         RB3_HIP(hipMemsetAsync(readyA.p, 0, (nch + 1) * sizeof(int32_t), c.stream));
+        // superblock rows in LDS when the table is small enough
+        const int64_t nsb1 = num_superblocks(n1);
+        const bool sb_lds = nsb1 <= CH_SB_LDS_MAX;
+        const size_t sb_bytes = sb_lds ? (size_t)nsb1 * 5 * sizeof(int64_t) : 0;
         if (c.launch_per_string) {
-            // the plain form: each new string's chunks in a launch of their own
+            // the plain form: each new string's chunks (in string order) in a
+            // launch of their own
+            std::vector<Chunk> hch(nch);
+            RB3_HIP(hipMemcpyAsync(hch.data(), d_ch.p, nch * sizeof(Chunk), hipMemcpyDeviceToHost, c.stream));
+            RB3_HIP(hipStreamSynchronize(c.stream));
+            std::vector<int64_t> first_chunk;
+            for (int64_t i = 0; i < nch; ++i)
+                if (hch[i].first) first_chunk.push_back(i);
             first_chunk.push_back(nch);
-            for (int64_t s = 0; s < m2; ++s) {
+            for (size_t s = 0; s + 1 < first_chunk.size(); ++s) {
                 const int64_t f = first_chunk[s], k = first_chunk[s + 1] - f;
-                if (k == 0) continue;
-                RB3_LAUNCH("chain", k_chain, grid_for(k, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
-                           d_ch.as<Chunk>() + f, k, m1, w, K.as<uint64_t>(), recm.as<uint64_t>(),
-                           unres.as<int32_t>() + f, ulen.as<int32_t>() + f, nwu.as<int32_t>() + f,
-                           stats.as<unsigned long long>());
+                if (sb_lds)
+                    RB3_LAUNCH("chain", k_chain<true>, grid_for(k, CH_WG, 1 << 30), dim3(CH_WG), sb_bytes, c.stream,
+                               b1, d_Q, d_ch.as<Chunk>() + f, (const uint32_t *)nullptr, k, m1, K.as<uint64_t>(),
+                               recm.as<uint64_t>(), unres.as<int32_t>() + f, ulen.as<int32_t>() + f,
+                               nwu.as<int32_t>() + f, stats.as<unsigned long long>());
+                else
+                    RB3_LAUNCH("chain", k_chain<false>, grid_for(k, CH_WG, 1 << 30), dim3(CH_WG), 0, c.stream, b1,
+                               d_Q, d_ch.as<Chunk>() + f, (const uint32_t *)nullptr, k, m1, K.as<uint64_t>(),
+                               recm.as<uint64_t>(), unres.as<int32_t>() + f, ulen.as<int32_t>() + f,
+                               nwu.as<int32_t>() + f, stats.as<unsigned long long>());
             }
         } else {
-            RB3_LAUNCH("chain", k_chain, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream, b1, d_Q,
-                       d_ch.as<Chunk>(), nch, m1, w, K.as<uint64_t>(), recm.as<uint64_t>(), unres.as<int32_t>(),
-                       ulen.as<int32_t>(), nwu.as<int32_t>(), stats.as<unsigned long long>());
+            if (sb_lds)
+                RB3_LAUNCH("chain", k_chain<true>, grid_for(nch, CH_WG, 1 << 30), dim3(CH_WG), sb_bytes, c.stream, b1,
+                           d_Q, d_ch.as<Chunk>(), d_perm.as<uint32_t>(), nch, m1, K.as<uint64_t>(),
+                           recm.as<uint64_t>(), unres.as<int32_t>(), ulen.as<int32_t>(), nwu.as<int32_t>(),
+                           stats.as<unsigned long long>());
+            else
+                RB3_LAUNCH("chain", k_chain<false>, grid_for(nch, CH_WG, 1 << 30), dim3(CH_WG), 0, c.stream, b1,
+                           d_Q, d_ch.as<Chunk>(), d_perm.as<uint32_t>(), nch, m1, K.as<uint64_t>(),
+                           recm.as<uint64_t>(), unres.as<int32_t>(), ulen.as<int32_t>(), nwu.as<int32_t>(),
+                           stats.as<unsigned long long>());
         }
         RB3_LAUNCH("chain_join", k_chain_join, grid_for(nch, 256, 1 << 30), dim3(256), 0, c.stream,
                    d_ch.as<Chunk>(), nch, unres.as<int32_t>(), nwu.as<int32_t>(), readyA.as<int32_t>(),
@@ -2163,6 +2193,8 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                    K.as<uint64_t>());
     }
 
+    RB3_TRY(fault_point(1));
+
     // ---- 2. order of the new suffixes ----
     DBuf ka, va, kb, vb;
     RB3_ALLOC(ka, &c, n2 * sizeof(uint64_t));
@@ -2175,6 +2207,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     RB3_TRY(radix_sort(c, K.as<uint64_t>(), nullptr, ka.as<uint64_t>(), va.as<uint32_t>(), kb.as<uint64_t>(),
                        vb.as<uint32_t>(), n2, 3, hi_bit, true, &SK, &SV, guard, &packed_sort));
     st.sort_packed = packed_sort;
+    RB3_TRY(fault_point(2));
     // free the other buffer pair early
     if (SK == ka.as<uint64_t>()) {
         kb.reset();
@@ -2436,6 +2469,8 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         }
     }
 
+    RB3_TRY(fault_point(3));
+
     // ---- 3. interleave into the merged BWT ----
     if (!bcnt_scanned)
         RB3_TRY(scan_u32(c, bcnt.as<uint32_t>(), bcnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
@@ -2459,6 +2494,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                    (const uint64_t *)b1.blk, num_blocks(n1), SK, bcnt.as<uint32_t>(), nout, nblk_out, n1, m1, lshift,
                    out_blk.as<uint4>(), guard, srate, (const uint64_t *)ix.smp_rec, PF,
                    samples ? sbits.as<uint64_t>() : nullptr, samples ? scnt.as<uint32_t>() : nullptr);
+    RB3_TRY(fault_point(4));
     int64_t nsmp_new = 0;
     if (samples) {
         RB3_TRY(scan_u32(c, scnt.as<uint32_t>(), scnt.as<uint32_t>(), nblk_out + 1, false, false, nullptr));
@@ -2484,6 +2520,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     }
     int64_t counts[6];
     RB3_TRY(build_checkpoints(c, out_blk.as<uint4>(), nout, out_sb.as<int64_t>(), new_C, counts));
+    RB3_TRY(fault_point(5));
     int32_t hg = 0;
     RB3_HIP(hipMemcpyAsync(&hg, guard, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
     RB3_HIP(hipStreamSynchronize(c.stream));

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(SMEM_WG) k_smem_seg(DevIndex ix, const uint8_t
     BiInt x = empty;
     uint32_t nrec = 0;
     int64_t first_end = -1, last_end = -1;
-    uint64_t nexts = 0;
+    uint64_t nexts = 0, nblks = 0;
     for (;;) {
         uint64_t idle = __ballot(!busy);
         if (idle && !exhausted) {
@@ -167,6 +167,8 @@ __global__ void __launch_bounds__(SMEM_WG) k_smem_seg(DevIndex ix, const uint8_t
             const BiInt z = backward_ext(ix, in, fwd ? comp_sym(a) : a);
             y = fwd ? BiInt{z.kr, z.k, z.s} : z;
             ++nexts;
+            // distinct index blocks the extension read (rank-all at k and k + s)
+            nblks += 1 + ((in.k >> BLK_SHIFT) != ((in.k + in.s) >> BLK_SHIFT));
         }
         if (busy && !done) {
             if (phase == PH_BACK1) {
@@ -242,9 +244,15 @@ __global__ void __launch_bounds__(SMEM_WG) k_smem_seg(DevIndex ix, const uint8_t
             busy = false;
         }
     }
-    uint64_t t = nexts;
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-    if (lane == 0 && t) atomicAdd(exts, (unsigned long long)t);
+    uint64_t t = nexts, b = nblks;
+    for (int o = 32; o > 0; o >>= 1) {
+        t += __shfl_xor(t, o);
+        b += __shfl_xor(b, o);
+    }
+    if (lane == 0 && t) {
+        atomicAdd(&exts[0], (unsigned long long)t);
+        atomicAdd(&exts[1], (unsigned long long)b);
+    }
 }
 
 // Per segment: whether its first report is contained in an SMEM of an
@@ -324,6 +332,7 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
     const int64_t smin = c.smem_seg_min > 0 ? c.smem_seg_min : SMEM_SEG_MIN;
     int64_t S = bases / target;
     S = S < smin ? smin : (S > SMEM_SEG ? SMEM_SEG : S);
+    if (c.smem_seg_fixed > 0) S = c.smem_seg_fixed;
     std::vector<Seg> segs;
     std::vector<int64_t> qseg(nq + 1);
     int64_t off = 0;
@@ -355,7 +364,7 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
     RB3_ALLOC(d_qseg, &c, (nq + 1) * sizeof(int64_t));
     RB3_ALLOC(qh, &c, sizeof(uint32_t));
     RB3_ALLOC(tot, &c, sizeof(unsigned long long));
-    RB3_ALLOC(ext, &c, sizeof(unsigned long long));
+    RB3_ALLOC(ext, &c, 2 * sizeof(unsigned long long));
     RB3_ALLOC(cnt, &c, (nseg + 1) * sizeof(uint32_t));
     RB3_ALLOC(first, &c, (nseg + 1) * sizeof(int64_t));
     RB3_ALLOC(last, &c, (nseg + 1) * sizeof(int64_t));
@@ -367,7 +376,7 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
     RB3_HIP(hipMemcpyAsync(d_qseg.p, qseg.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
     RB3_HIP(hipMemsetAsync(qh.p, 0, sizeof(uint32_t), c.stream));
     RB3_HIP(hipMemsetAsync(tot.p, 0, sizeof(unsigned long long), c.stream));
-    RB3_HIP(hipMemsetAsync(ext.p, 0, sizeof(unsigned long long), c.stream));
+    RB3_HIP(hipMemsetAsync(ext.p, 0, 2 * sizeof(unsigned long long), c.stream));
     RB3_HIP(hipMemsetAsync(kept.p, 0, (nseg + 1) * sizeof(uint32_t), c.stream));
     if (nseg > 0) {
         int64_t wgs = (nseg + SMEM_WG - 1) / SMEM_WG;
@@ -383,14 +392,15 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
     RB3_TRY(scan_u32(c, kept.as<uint32_t>(), segoff.as<uint32_t>(), nseg + 1, false, false, nullptr));
     RB3_LAUNCH("smem_qoff", k_smem_qoff, grid_for(nq + 1, 256, 1 << 20), dim3(256), 0, c.stream,
                d_qseg.as<int64_t>(), nq, segoff.as<uint32_t>(), d_out_off);
-    unsigned long long htot = 0, hext = 0;
+    unsigned long long htot = 0, hext[2] = {0, 0};
     int64_t hkept = 0;
     RB3_HIP(hipMemcpyAsync(&htot, tot.p, sizeof(htot), hipMemcpyDeviceToHost, c.stream));
-    RB3_HIP(hipMemcpyAsync(&hext, ext.p, sizeof(hext), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipMemcpyAsync(hext, ext.p, sizeof(hext), hipMemcpyDeviceToHost, c.stream));
     RB3_HIP(hipMemcpyAsync(&hkept, d_out_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
     RB3_HIP(hipStreamSynchronize(c.stream));
     *h_kept = hkept;
-    *h_exts = (int64_t)hext;
+    h_exts[0] = (int64_t)hext[0];
+    h_exts[1] = (int64_t)hext[1];
     if ((int64_t)htot <= cap && hkept <= out_cap && htot > 0)
         RB3_LAUNCH("smem_order", k_smem_order, grid_for((int64_t)htot, 256 * 4), dim3(256), 0, c.stream, d_tmp,
                    (int64_t)htot, d_segs.as<Seg>(), segoff.as<uint32_t>(), drop.as<uint32_t>(), d_out);

@@ -73,18 +73,17 @@ __device__ __forceinline__ uint64_t low_mask(int o) {  // bits [0, o), o in [0, 
     return o >= 64 ? ~0ull : ((1ull << o) - 1ull);
 }
 
-// 24-bit checkpoint field f (0..4 for A..N) of q[3].
+// 24-bit checkpoint field f (0..4 for A..N) of q[3]: bits 24 f .. 24 f + 23
+// of the 128-bit word, taken without branches (lanes of a wave usually ask
+// for different fields) and with shifts only, so the block stays in
+// registers (indexing its 32-bit parts by a variable would put it in
+// scratch memory).
 __device__ __forceinline__ uint32_t ckpt_field(const uint4 &q3, int f) {
-    uint64_t c0 = u64_lo(q3), c1 = u64_hi(q3);
-    uint64_t v;
-    switch (f) {
-    case 0: v = c0; break;
-    case 1: v = c0 >> 24; break;
-    case 2: v = (c0 >> 48) | (c1 << 16); break;
-    case 3: v = c1 >> 8; break;
-    default: v = c1 >> 32; break;
-    }
-    return (uint32_t)(v & CNT_MASK);
+    const uint64_t c0 = u64_lo(q3), c1 = u64_hi(q3);
+    const uint32_t bit = 24u * (uint32_t)f;  // 0, 24, 48, 72, 96
+    const uint64_t low = (c0 >> (bit & 63u)) | ((c1 << 1) << (63u - (bit & 63u)));
+    const uint64_t v = bit < 64u ? low : (c1 >> (bit - 64u));
+    return (uint32_t)v & CNT_MASK;
 }
 
 __device__ __forceinline__ uint4 pack_ckpt(const uint32_t c[5]) {
@@ -197,6 +196,7 @@ struct Ctx {
     int32_t launch_per_string = 0;
     int64_t smem_segs = 0;     // SMEM segments to aim for per call; 0 = SMEM_TARGET_SEGS
     int64_t smem_seg_min = 0;  // shortest SMEM segment; 0 = SMEM_SEG_MIN
+    int64_t smem_seg_fixed = 0;  // fixed SMEM segment length; 0 = from the batch
     int32_t both = 1;
     int32_t ssa = 0;           // suffix-array sampling distance (0: no samples)
     // Frees are deferred until flush(), called after the stream has drained,
@@ -333,6 +333,32 @@ int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *
                uint32_t *v_b, int64_t n, int lo_bit, int hi_bit, bool iota_vals, uint64_t **k_res,
                uint32_t **v_res, int32_t *d_guard, int *used_packed);
 
+// A piece of a new strand walked by one lane of the LF-chain kernel.
+struct Chunk {
+    int64_t p0;     // position in Q of the chunk's first symbol
+    int32_t len;    // symbols in the chunk
+    int32_t last;   // 1 if the chunk ends at the strand's sentinel
+    int32_t first;  // 1 if the chunk starts at the strand's first symbol
+    int32_t pad;
+};
+
+// Zero bytes after the last code of a merge batch (Q): word and line reads
+// past the end stay inside the buffer.
+constexpr int64_t Q_PAD = 128;
+
+// chunks.hip: the chunks of the n2 codes at d_Q (strands each followed by
+// their sentinel, Q_PAD zero bytes past the end), in string order, at most
+// lmax symbols each and cut at content-defined positions; perm receives the
+// order in which the chain kernel's lanes take them (uint32 chunk indices).
+int make_chunks(Ctx &c, const uint8_t *d_Q, int64_t n2, int64_t lmax, DBuf &chunks, int64_t *nch_out, DBuf &perm,
+                int32_t *d_guard);
+
+// api.cpp: the merge-failure test hook (rb3_test_fail_merge_after). Returns
+// RB3_EDEVICE, with a message, when the hook names this stage of a merge
+// (1 insertion ranks, 2 radix sort, 3 tie resolution, 4 interleave, 5
+// checkpoints), else RB3_OK.
+int fault_point(int stage);
+
 // merge.hip
 struct MergeStats {
     int64_t n1 = 0, m1 = 0, n2 = 0, m2 = 0;
@@ -416,7 +442,7 @@ struct IndexData {
 };
 
 // d_Q: the n2 codes of the m2 new strands, each followed by its sentinel
-// (code 0), then 16 zero bytes of padding.
+// (code 0), then Q_PAD zero bytes of padding.
 // With samples (ix.ctx.ssa > 0) the merged index's sample arrays are
 // returned through smp (bits, cnt, val, nsmp); otherwise smp is untouched.
 struct SmpOut {
@@ -465,8 +491,8 @@ constexpr int64_t SMEM_SEG_BUSY = 128;  // shortest segment when batches share t
 constexpr int64_t SMEM_TARGET_SEGS = 262144;
 // SMEMs of nq queries (codes at d_q, host lengths qlens). d_out_off
 // (device, nq + 1) receives the per-query offsets; when all *h_kept reports
-// fit in out_cap they are written in order to d_out. *h_exts: bi-interval
-// extensions performed.
+// fit in out_cap they are written in order to d_out. h_exts[0]: bi-interval
+// extensions performed, h_exts[1]: distinct index blocks they read.
 int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlens, int64_t nq, int32_t min_len,
              int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
              int64_t *h_exts);

@@ -165,9 +165,9 @@ void run_batch(rb3_server *s, Ctx &c, std::vector<Request> &batch) {
         int rc = RB3_OK;
         for (int attempt = 0; attempt < 2; ++attempt) {
             recs.resize(cap);
-            int64_t exts = 0;
+            int64_t exts[2] = {0, 0};
             rc = run_smem(c, ix, buf.data(), lens.data(), nq, (int64_t)buf.size(), RB3_MEM_HOST, g.first.first,
-                          g.first.second, recs.data(), cap, off.data(), &exts);
+                          g.first.second, recs.data(), cap, off.data(), exts);
             int r2 = c.flush();
             if (rc == RB3_OK) rc = r2;
             if (rc != RB3_ENOSPC) break;
@@ -265,7 +265,8 @@ void rb3_server_opts_init(rb3_server_opts *so) {
     so->workers = 4;
     so->max_batch_queries = 4096;
     so->max_batch_bases = 8 << 20;
-    so->mem_budget = (int64_t)4 << 30;
+    so->mem_budget = 0;  // from the device's free memory at creation
+    so->max_queued = 1 << 16;
 }
 
 int rb3_server_create(const rb3_index *idx, const rb3_server_opts *so, rb3_server **out) {
@@ -277,9 +278,18 @@ int rb3_server_create(const rb3_index *idx, const rb3_server_opts *so, rb3_serve
     rb3_server_opts_init(&d);
     if (!so) so = &d;
     if (so->workers < 1 || so->workers > 64 || so->max_batch_queries < 1 || so->max_batch_bases < 1 ||
-        so->mem_budget < 1) {
+        so->mem_budget < 0 || so->max_queued < 1) {
         set_error(RB3_EINVAL, "bad server options");
         return RB3_EINVAL;
+    }
+    rb3_server_opts eff = *so;
+    if (eff.mem_budget == 0) {
+        // half of the device memory free now: the index and other users keep the rest
+        size_t fr = 0, tot = 0;
+        RB3_HIP(hipSetDevice(index_device(idx)));
+        RB3_HIP(hipMemGetInfo(&fr, &tot));
+        eff.mem_budget = (int64_t)(fr / 2);
+        if (eff.mem_budget < ((int64_t)1 << 26)) eff.mem_budget = (int64_t)1 << 26;
     }
     rb3_server *s = new (std::nothrow) rb3_server();
     if (!s) {
@@ -287,7 +297,7 @@ int rb3_server_create(const rb3_index *idx, const rb3_server_opts *so, rb3_serve
         return RB3_ENOMEM;
     }
     s->idx = idx;
-    s->so = *so;
+    s->so = eff;
     for (int i = 0; i < so->workers; ++i) s->workers.emplace_back(worker_main, s);
     *out = s;
     return RB3_OK;
@@ -322,6 +332,10 @@ int rb3_server_submit(rb3_server *s, int32_t kind, const uint8_t *q, int64_t len
     r.q.assign(q, q + len);
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        if ((int64_t)s->pending.size() >= s->so.max_queued) {
+            set_error(RB3_EAGAIN, "server queue full: retry after polling results");
+            return RB3_EAGAIN;
+        }
         r.ticket = s->next_ticket++;
         *ticket = r.ticket;
         s->pending.push_back(std::move(r));
@@ -365,13 +379,14 @@ int rb3_server_poll(rb3_server *s, int32_t wait_ms, rb3_result *res, int64_t res
 }
 
 int rb3_server_stats(rb3_server *s, int64_t *queued, int64_t *inflight, int64_t *batches, int64_t *served,
-                     int64_t *max_batch, int64_t *busy_us) {
+                     int64_t *max_batch, int64_t *busy_us, int64_t *mem_budget) {
     if (!s) {
         set_error(RB3_EINVAL, "server is NULL");
         return RB3_EINVAL;
     }
     std::lock_guard<std::mutex> lk(s->mu);
     if (queued) *queued = (int64_t)s->pending.size();
+    if (mem_budget) *mem_budget = s->so.mem_budget;
     if (inflight) *inflight = s->inflight_batches;
     if (batches) *batches = s->batches;
     if (served) *served = s->served;
@@ -396,25 +411,31 @@ int rb3_server_replay(rb3_server *s, int32_t kind, const uint8_t *q, const int64
     std::atomic<int64_t> expected(n);  // results still to come; lowered by failed submissions
     const auto t0 = clk::now();
     auto since = [&](clk::time_point t) { return std::chrono::duration<double>(t - t0).count(); };
+    // The poller takes out of the done queue only the results of this call's
+    // own tickets; results of other clients' requests stay for their polls.
     std::thread poller([&] {
-        std::vector<rb3_result> res(1024);
-        std::vector<rb3_smem_t> recs(1 << 16);
         int64_t got = 0;
         while (got < expected.load()) {
-            int64_t nr = 0, nk = 0;
-            int rc = rb3_server_poll(s, 20, res.data(), (int64_t)res.size(), recs.data(), (int64_t)recs.size(), &nr,
-                                     &nk);
-            if (rc == RB3_ENOSPC) {
-                recs.resize((size_t)nk * 2);
-                continue;
+            std::vector<std::pair<uint64_t, int32_t>> mine;
+            {
+                std::unique_lock<std::mutex> lk(s->mu);
+                s->cv_done.wait_for(lk, std::chrono::milliseconds(20), [&] { return !s->done.empty(); });
+                std::lock_guard<std::mutex> lw(wmu);
+                for (auto it = s->done.begin(); it != s->done.end();) {
+                    if (who.count(it->r.ticket)) {
+                        mine.emplace_back(it->r.ticket, it->r.status);
+                        it = s->done.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
             }
-            double now = since(clk::now());
-            std::lock_guard<std::mutex> lk(wmu);
-            for (int64_t k = 0; k < nr; ++k) {
-                auto it = who.find(res[k].ticket);
-                if (it == who.end()) continue;  // a result of another client's request
-                latency_s[it->second] = now - arrival_s[it->second];
-                status[it->second] = res[k].status;
+            const double now = since(clk::now());
+            std::lock_guard<std::mutex> lw(wmu);
+            for (auto &tk : mine) {
+                const int64_t i = who[tk.first];
+                latency_s[i] = now - arrival_s[i];
+                status[i] = tk.second;
                 ++got;
             }
         }
@@ -422,13 +443,17 @@ int rb3_server_replay(rb3_server *s, int32_t kind, const uint8_t *q, const int64
     for (int64_t i = 0; i < n; ++i) {
         while (since(clk::now()) < arrival_s[i]) std::this_thread::yield();
         uint64_t t = 0;
-        std::lock_guard<std::mutex> lk(wmu);
-        int rc = rb3_server_submit(s, kind, q + off[i], qlens[i], min_len, min_occ, &t);
+        int rc;
+        // (wmu is never held across a submit: the poller takes s->mu, then wmu)
+        while ((rc = rb3_server_submit(s, kind, q + off[i], qlens[i], min_len, min_occ, &t)) == RB3_EAGAIN)
+            std::this_thread::yield();  // a full queue: the request waits, its latency counting from its arrival
         if (rc != RB3_OK) {
+            std::lock_guard<std::mutex> lk(wmu);
             latency_s[i] = -1;
             status[i] = rc;
             expected.fetch_sub(1);
         } else {
+            std::lock_guard<std::mutex> lk(wmu);
             who[t] = i;
         }
     }

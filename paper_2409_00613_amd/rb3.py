@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librb3.so")
 
-RB3_OK, RB3_EINVAL, RB3_ENOMEM, RB3_EDEVICE, RB3_ENOSPC, RB3_ELIMIT = 0, -1, -2, -3, -4, -5
+RB3_OK, RB3_EINVAL, RB3_ENOMEM, RB3_EDEVICE, RB3_ENOSPC, RB3_ELIMIT, RB3_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 RB3_MEM_HOST, RB3_MEM_DEVICE = 0, 1
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -30,7 +30,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("both_strands", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN),
                 ("alloc_ctx", ctypes.c_void_p), ("chunk_len", ctypes.c_int64),
-                ("launch_per_string", ctypes.c_int32), ("ssa_rate", ctypes.c_int32)]
+                ("launch_per_string", ctypes.c_int32), ("ssa_rate", ctypes.c_int32),
+                ("occ_interval", ctypes.c_int32), ("smem_segment", ctypes.c_int32)]
 
 
 class SmemRec(ctypes.Structure):
@@ -47,7 +48,7 @@ assert SMEM_DTYPE.itemsize == ctypes.sizeof(SmemRec) == 48
 EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_count_noalloc", "rb3_smem", "rb3_last_smem_stats",
            "rb3_locate", "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info",
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
-           "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats",
+           "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats", "rb3_test_fail_merge_after",
            "rb3_server_opts_init", "rb3_server_create", "rb3_server_submit", "rb3_server_poll",
            "rb3_server_stats", "rb3_server_replay", "rb3_server_free"]
 
@@ -56,7 +57,7 @@ RB3_REQ_COUNT, RB3_REQ_SMEM = 0, 1
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("workers", ctypes.c_int32), ("pad", ctypes.c_int32), ("max_batch_queries", ctypes.c_int64),
-                ("max_batch_bases", ctypes.c_int64), ("mem_budget", ctypes.c_int64)]
+                ("max_batch_bases", ctypes.c_int64), ("mem_budget", ctypes.c_int64), ("max_queued", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):
@@ -101,13 +102,13 @@ def lib():
     L.rb3_count_noalloc.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p]
     L.rb3_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, ctypes.POINTER(SmemRec), _i64, _i64p]
     L.rb3_info.argtypes = [_vp, _i64p, _i64p, _i64p]
-    L.rb3_last_smem_stats.argtypes = [_i64p]
+    L.rb3_last_smem_stats.argtypes = [_i64p, _i64p]
     L.rb3_locate.argtypes = [_vp, _vp, _i64, _i32, _i64p, _i64p]
     L.rb3_locate1.argtypes = [_vp, _vp, _vp, _i64, _i32, _i64p, _i64p]
     L.rb3_ssa_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), _i64p]
     L.rb3_last_locate_stats.argtypes = [_i64p]
     L.rb3_export.argtypes = [_vp, _vp]
-    L.rb3_import.argtypes = [ctypes.POINTER(Opts), _vp, _i64, _i32, ctypes.POINTER(_vp)]
+    L.rb3_import.argtypes = [ctypes.POINTER(Opts), _vp, _i64, _i64p, _i64, _i32, ctypes.POINTER(_vp)]
     L.rb3_clone.argtypes = [_vp, ctypes.POINTER(_vp)]
     L.rb3_index_free.argtypes = [_vp]
     L.rb3_index_free.restype = None
@@ -117,13 +118,14 @@ def lib():
     L.rb3_prof_reset.argtypes = []
     L.rb3_prof_read.argtypes = [ctypes.c_char_p, _i64p, ctypes.POINTER(ctypes.c_double), _i64, _i64p]
     L.rb3_merge_stats.argtypes = [_vp, ctypes.c_char_p, _i64p, _i64, _i64p]
+    L.rb3_test_fail_merge_after.argtypes = [_i32]
     L.rb3_server_opts_init.argtypes = [ctypes.POINTER(ServerOpts)]
     L.rb3_server_opts_init.restype = None
     L.rb3_server_create.argtypes = [_vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
     L.rb3_server_submit.argtypes = [_vp, _i32, _vp, _i64, _i32, _i64, ctypes.POINTER(ctypes.c_uint64)]
     L.rb3_server_poll.argtypes = [_vp, _i32, ctypes.POINTER(Result), _i64, ctypes.POINTER(SmemRec), _i64,
                                   _i64p, _i64p]
-    L.rb3_server_stats.argtypes = [_vp, _i64p, _i64p, _i64p, _i64p, _i64p, _i64p]
+    L.rb3_server_stats.argtypes = [_vp, _i64p, _i64p, _i64p, _i64p, _i64p, _i64p, _i64p]
     _dp = ctypes.POINTER(ctypes.c_double)
     L.rb3_server_replay.argtypes = [_vp, _i32, _vp, _i64p, _i64, _i32, _i64, _dp, _dp, _dp]
     L.rb3_server_free.argtypes = [_vp]
@@ -134,7 +136,7 @@ def lib():
     for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_count_noalloc", "rb3_smem", "rb3_last_smem_stats", "rb3_locate",
                  "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info", "rb3_export",
                  "rb3_import", "rb3_clone", "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read",
-                 "rb3_merge_stats"):
+                 "rb3_merge_stats", "rb3_test_fail_merge_after"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -213,7 +215,8 @@ class TorchAllocator:
 
 
 def make_opts(both_strands: bool = True, device: int = 0, stream=None, allocator: TorchAllocator | None = None,
-              chunk_len: int = 0, launch_per_string: bool = False, ssa_rate: int = 0) -> Opts:
+              chunk_len: int = 0, launch_per_string: bool = False, ssa_rate: int = 0, occ_interval: int = 0,
+              smem_segment: int = 0) -> Opts:
     o = Opts()
     lib().rb3_opts_init(ctypes.byref(o))
     o.both_strands = 1 if both_strands else 0
@@ -228,6 +231,8 @@ def make_opts(both_strands: bool = True, device: int = 0, stream=None, allocator
     o.chunk_len = int(chunk_len)
     o.launch_per_string = 1 if launch_per_string else 0
     o.ssa_rate = int(ssa_rate)
+    o.occ_interval = int(occ_interval)
+    o.smem_segment = int(smem_segment)
     return o
 
 
@@ -293,8 +298,10 @@ class Index:
 
 def rb3_build(seq, lens, both_strands: bool = True, device: int = 0, stream=None,
               allocator: TorchAllocator | None = None, chunk_len: int = 0,
-              launch_per_string: bool = False, ssa_rate: int = 0) -> Index:
-    o = make_opts(both_strands, device, stream, allocator, chunk_len, launch_per_string, ssa_rate)
+              launch_per_string: bool = False, ssa_rate: int = 0, occ_interval: int = 0,
+              smem_segment: int = 0) -> Index:
+    o = make_opts(both_strands, device, stream, allocator, chunk_len, launch_per_string, ssa_rate, occ_interval,
+                  smem_segment)
     ptr, _, mem, keep = _buffer(seq)
     la, lp = _lens(lens)
     h = ctypes.c_void_p()
@@ -401,10 +408,12 @@ def rb3_last_locate_stats() -> dict:
 
 
 def rb3_last_smem_stats() -> dict:
-    """Work of this thread's last rb3_smem call."""
+    """Work of this thread's last rb3_smem call: bi-interval extensions and
+    the distinct index blocks they read."""
     e = ctypes.c_int64()
-    _check(lib().rb3_last_smem_stats(ctypes.byref(e)))
-    return {"extensions": e.value}
+    b = ctypes.c_int64()
+    _check(lib().rb3_last_smem_stats(ctypes.byref(e), ctypes.byref(b)))
+    return {"extensions": e.value, "blocks": b.value}
 
 
 def rb3_info(idx: Index):
@@ -422,12 +431,15 @@ def rb3_export(idx: Index) -> np.ndarray:
     return out[:n]
 
 
-def rb3_import(codes, both_strands: bool = True, device: int = 0, stream=None,
-               allocator: TorchAllocator | None = None) -> Index:
-    o = make_opts(both_strands, device, stream, allocator)
+def rb3_import(codes, lens, both_strands: bool = True, device: int = 0, stream=None,
+               allocator: TorchAllocator | None = None, occ_interval: int = 0, smem_segment: int = 0) -> Index:
+    """Index from BWT codes of the strands whose lengths are ``lens`` (the
+    strand list the BWT was built from, both strands counted)."""
+    o = make_opts(both_strands, device, stream, allocator, occ_interval=occ_interval, smem_segment=smem_segment)
     ptr, nbytes, mem, keep = _buffer(codes)
+    la, lp = _lens(lens)
     h = ctypes.c_void_p()
-    _check(lib().rb3_import(ctypes.byref(o), ptr, nbytes, mem, ctypes.byref(h)))
+    _check(lib().rb3_import(ctypes.byref(o), ptr, nbytes, lp, la.shape[0], mem, ctypes.byref(h)))
     return Index(h.value, keep=[o, allocator])
 
 
@@ -445,6 +457,36 @@ def rb3_merge_stats(idx: Index) -> dict:
     _check(lib().rb3_merge_stats(idx.handle, keys, vals.ctypes.data_as(_i64p), cap, ctypes.byref(n)))
     raw = keys.raw
     return {raw[i * 32:(i + 1) * 32].split(b"\0")[0].decode(): int(vals[i]) for i in range(min(n.value, cap))}
+
+
+def rb3_test_fail_merge_after(stage: int):
+    """Test hook: merges stop with RB3_EDEVICE after this stage (0: off)."""
+    _check(lib().rb3_test_fail_merge_after(int(stage)))
+
+
+class CountingAllocator(TorchAllocator):
+    """Torch's caching allocator behind a counter: allocation number
+    ``fail_at`` (1-based, counted from the last reset) returns NULL, as a
+    device out of memory would. For tests of failure handling."""
+
+    def __init__(self, device: int = 0, stream=None):
+        super().__init__(device, stream)
+        self.calls = 0
+        self.fail_at = 0
+        inner = self.alloc_fn
+
+        def _alloc(nbytes, ctx):
+            self.calls += 1
+            if self.fail_at and self.calls == self.fail_at:
+                return None
+            return inner(nbytes, ctx)
+
+        self._inner = inner
+        self.alloc_fn = _ALLOC_FN(_alloc)
+
+    def reset(self, fail_at: int = 0):
+        self.calls = 0
+        self.fail_at = fail_at
 
 
 def rb3_prof_enable(on: bool = True):
@@ -473,7 +515,7 @@ class Server:
     """rb3_server: continuous-batching count / SMEM service over an Index."""
 
     def __init__(self, idx: Index, workers: int = 4, max_batch_queries: int = 4096,
-                 max_batch_bases: int = 8 << 20, mem_budget: int = 4 << 30):
+                 max_batch_bases: int = 8 << 20, mem_budget: int = 0, max_queued: int = 1 << 16):
         L = lib()
         so = ServerOpts()
         L.rb3_server_opts_init(ctypes.byref(so))
@@ -481,6 +523,7 @@ class Server:
         so.max_batch_queries = max_batch_queries
         so.max_batch_bases = max_batch_bases
         so.mem_budget = mem_budget
+        so.max_queued = max_queued
         h = ctypes.c_void_p()
         _check(L.rb3_server_create(idx.handle, ctypes.byref(so), ctypes.byref(h)))
         self._h = h
@@ -538,9 +581,10 @@ class Server:
         return lat[:la.shape[0]], wall.value
 
     def stats(self) -> dict:
-        v = [ctypes.c_int64() for _ in range(6)]
+        v = [ctypes.c_int64() for _ in range(7)]
         _check(lib().rb3_server_stats(self._h, *[ctypes.byref(x) for x in v]))
-        return dict(zip(["queued", "inflight", "batches", "served", "max_batch", "busy_us"], [x.value for x in v]))
+        return dict(zip(["queued", "inflight", "batches", "served", "max_batch", "busy_us", "mem_budget"],
+                        [x.value for x in v]))
 
     def close(self):
         if self._h and self._h.value:

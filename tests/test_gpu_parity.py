@@ -48,28 +48,45 @@ def tiny():
     return synth.config_tiny()
 
 
+def _codes_with_strands(rng, n, m):
+    """n random codes 1..5 with exactly m sentinels, and m strand lengths >= 1
+    summing to n - m."""
+    codes = rng.integers(1, 6, n).astype(np.uint8)
+    codes[rng.choice(n, m, replace=False)] = 0
+    cuts = np.sort(rng.choice(np.arange(1, n - m), m - 1, replace=False)) if m > 1 else np.zeros(0, np.int64)
+    lens = np.diff(np.concatenate([[0], cuts, [n - m]])).astype(np.int64)
+    assert lens.min() >= 1 and int(lens.sum()) + m == n
+    return codes, lens
+
+
 def test_import_export_roundtrip():
     say("case: import/export round trip")
     rng = np.random.default_rng(5)
-    for n in (1, 2, 127, 128, 129, 5000, 300_001):
-        codes = rng.integers(0, 6, n).astype(np.uint8)
-        codes[rng.integers(0, n)] = 0
-        idx = rb3.rb3_import(codes)
+    for n, m in ((2, 1), (3, 1), (127, 2), (128, 3), (129, 64), (5000, 7), (300_001, 1000)):
+        codes, lens = _codes_with_strands(rng, n, m)
+        idx = rb3.rb3_import(codes, lens)
         assert np.array_equal(idx.export(), codes)
-        nn, m, C = idx.info()
-        assert nn == n and m == int((codes == 0).sum())
+        nn, mm, C = idx.info()
+        assert nn == n and mm == m
         cnt = np.bincount(codes, minlength=6)
         assert C == [int(x) for x in np.concatenate([[0], np.cumsum(cnt)[:-1]])]
         idx.close()
 
 
-def test_import_rejects_bad_codes():
-    say("case: import rejects bad codes")
-    with pytest.raises(rb3.RB3Error) as e:
-        rb3.rb3_import(np.array([1, 2, 7, 0], np.uint8))
-    assert e.value.code == rb3.RB3_EINVAL
-    with pytest.raises(rb3.RB3Error):
-        rb3.rb3_import(np.array([1, 2, 3], np.uint8))  # no sentinel
+def test_import_rejects_failed_count_checks():
+    say("case: import rejects bad codes and failed symbol-count checks")
+    cases = [
+        (np.array([1, 2, 7, 0], np.uint8), [3]),   # code 7
+        (np.array([1, 2, 3], np.uint8), [2]),      # no sentinel, n != sum(L + 1)
+        (np.array([1, 2, 3, 4], np.uint8), [3]),   # n = sum(L + 1) but no sentinel
+        (np.array([0, 2, 0, 4], np.uint8), [3]),   # two sentinels for one strand
+        (np.array([1, 0, 3, 4], np.uint8), [1, 1]),  # n != sum(L + 1)
+        (np.array([1, 0, 0, 4], np.uint8), [2, 0]),  # an empty strand
+    ]
+    for codes, lens in cases:
+        with pytest.raises(rb3.RB3Error) as e:
+            rb3.rb3_import(codes, lens)
+        assert e.value.code == rb3.RB3_EINVAL, (codes, lens)
 
 
 def test_count_on_imported_oracle_bwt(tiny):
@@ -77,7 +94,7 @@ def test_count_on_imported_oracle_bwt(tiny):
     allst = tiny.b1 + tiny.new
     codes, lens = _expand(allst)
     B = oracle.bwt(codes, lens)
-    idx = rb3.rb3_import(B)
+    idx = rb3.rb3_import(B, lens)
     qc, ql = oracle.encode(tiny.queries.data, tiny.queries.lens)
     lo, hi = idx.count(tiny.queries.data, tiny.queries.lens)
     olo, ohi = oracle.count(codes, lens, qc, ql)
