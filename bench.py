@@ -40,17 +40,32 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def merge_method_bytes(st: dict) -> dict:
+    """Bytes the method itself must move for one merge, per unit of work
+    (the per-suffix figures of the measurement plan): for each non-sentinel
+    new suffix one random index block for its rank, 1 B symbol read and 8 B
+    rank written by the chain; one ideal sort pass over a 12-byte record,
+    read and written (24 B); the emitted BWT symbol (1 B); and the
+    interleave's streaming of the old and the merged BWT at 0.5 B per
+    symbol."""
+    n1, n2, m2 = st["n1"], st["n2"], st["m2"]
+    rank = (n2 - m2) * BLOCK_BYTES
+    chain_io = (n2 - m2) * 1 + n2 * 8
+    sort = n2 * 24
+    emit = n2 * 1
+    interleave = n1 * 0.5 + (n1 + n2) * 0.5
+    return {"rank": rank, "chain_io": chain_io, "sort": sort, "emit": emit, "interleave": interleave,
+            "chain": rank + chain_io, "total": rank + chain_io + sort + emit + interleave}
+
+
 def algorithmic_bytes(kernel: str, st: dict, steps: int) -> float | None:
-    """Bytes the method must move in all launches of one kernel over the timed
-    steps (per-unit figures times units, the units taken from the merge's own
-    counters)."""
+    """Bytes moved by all launches of one kernel over the timed steps (per-unit
+    figures times units, the units taken from the merge's own counters). For
+    `chain` these are the method's bytes only (merge_method_bytes); what the
+    implementation adds is in overhead_bytes."""
     n1, n2, m2 = st["n1"], st["n2"], st["m2"]
     per_step = {
-        # one random 64-byte block per rank step (two where the interval's
-        # ends lie in different blocks), the symbol read and the 8-byte key
-        # (or interval low end) written per new suffix, and the 8-byte row
-        # mask recorded per unresolved step
-        "chain": st["chain_steps"] * BLOCK_BYTES + (n2 - m2) * 1 + n2 * 8 + st["fixup_steps"] * 8,
+        "chain": merge_method_bytes(st)["chain"],
         # fix-up steps over wide intervals: a block, the recorded low end, the
         # symbol, the key written
         "chain_fixup": st.get("fixup_index_steps", 0) * (BLOCK_BYTES + 8 + 1 + 8),
@@ -81,6 +96,26 @@ def algorithmic_bytes(kernel: str, st: dict, steps: int) -> float | None:
     }
     v = per_step.get(kernel)
     return None if v is None else float(v) * steps
+
+
+def overhead_bytes(kernel: str, st: dict) -> float | None:
+    """Per merge, what the implementation moves beyond the method's bytes:
+    for `chain`, the second block of interval steps whose ends lie in
+    different blocks and the 8-byte row mask recorded per unresolved step."""
+    if kernel != "chain":
+        return None
+    return float((st["chain_steps"] - (st["n2"] - st["m2"])) * BLOCK_BYTES + st["fixup_steps"] * 8)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def read_traffic(kernel: str, workload: str, src_hash: str):
@@ -119,6 +154,7 @@ def cpu_baseline(sample_len: int, threads: int):
     oracle.bwt(codes, lens, nthreads=threads)
     dt = time.perf_counter() - t0
     return {"value": n2 / dt, "unit": "suffixes/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"naive-sort BWT of the merged list with every haplotype cut to its first "
                       f"{sample_len} bases ({int(lens.sum()) + lens.shape[0]} suffixes, {n2} of them new); "
                       f"{dt:.2f} s"}
@@ -161,19 +197,24 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
     t1 = time.perf_counter()
     rb3.rb3_prof_enable(False)
     prof = rb3.rb3_prof_read()
-    exts = rb3.rb3_last_smem_stats()["extensions"]
+    sst = rb3.rb3_last_smem_stats()
+    exts, blocks = sst["extensions"], sst["blocks"]
     batched = bases * steps / (t1 - t0)
     qps = n_queries * steps / (t1 - t0)
     k_ms = prof.get("smem", (0, 0.0))[1] / steps
     roof = None
     if k_ms > 0:
-        ab = exts * 2 * BLOCK_BYTES
+        # the distinct index blocks the extensions read (one per extension
+        # whose two rank positions share a block, else two), counted on the
+        # device
+        ab = blocks * BLOCK_BYTES
         ach = ab / (k_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": "smem", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": read_traffic("smem", f"serving{n_index}", kernel_source_hash()),
                 "algorithmic_bytes_per_launch": ab,
-                "avg_launch_ms": k_ms, "extensions_per_base": round(exts / bases, 3)}
+                "avg_launch_ms": k_ms, "extensions_per_base": round(exts / bases, 3),
+                "blocks_per_extension": round(blocks / max(exts, 1), 3)}
     log(f"SMEM batched: {batched / 1e9:.3f} G bases/s, {qps:.0f} queries/s, {len(recs)} SMEMs, "
         f"{exts} extensions, smem kernel {k_ms:.2f} ms")
     config = {"workload": "serving", "genome_len": genome, "haplotypes_indexed": n_index,
@@ -284,33 +325,44 @@ def host_input_merges(b1, new, steps: int):
     up_ms = (time.perf_counter() - t) / steps * 1e3
     merge_from(bufs[0]).close()  # warm-up
     torch.cuda.synchronize()
-    t = time.perf_counter()
+    seq = []
     for _ in range(steps):
+        t = time.perf_counter()
         bufs[0].copy_(host, non_blocking=True)
         torch.cuda.synchronize()
         merge_from(bufs[0]).close()
-    torch.cuda.synchronize()
-    seq_ms = (time.perf_counter() - t) / steps * 1e3
-    t = time.perf_counter()
+        torch.cuda.synchronize()
+        seq.append((time.perf_counter() - t) * 1e3)
+    # overlapped: step i's time runs from the end of step i - 1 (its batch
+    # uploaded during that step) to the end of its own merge and the next
+    # batch's upload
+    ovl = []
     with torch.cuda.stream(side):
         bufs[0].copy_(host, non_blocking=True)
     side.synchronize()
+    t = time.perf_counter()
     for i in range(steps):
         if i + 1 < steps:
             with torch.cuda.stream(side):
                 bufs[(i + 1) % 2].copy_(host, non_blocking=True)
         merge_from(bufs[i % 2]).close()
         side.synchronize()
-    torch.cuda.synchronize()
-    ovl_ms = (time.perf_counter() - t) / steps * 1e3
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ovl.append((t1 - t) * 1e3)
+        t = t1
     n2 = 2 * (new.total + new.n)
-    log(f"host input: upload {up_ms:.2f} ms; upload then merge {seq_ms:.2f} ms/step; "
-        f"upload beside the previous merge {ovl_ms:.2f} ms/step")
+    sq, ov = float(np.median(seq)), float(np.median(ovl))
+    log(f"host input: upload {up_ms:.2f} ms; upload then merge median {sq:.2f} ms/step "
+        f"({min(seq):.2f}-{max(seq):.2f}); upload beside the previous merge median {ov:.2f} ms/step "
+        f"({min(ovl):.2f}-{max(ovl):.2f})")
     return {"batch_bytes": int(host.numel()), "upload_ms": round(up_ms, 3),
             "upload_gb_per_s": round(host.numel() / (up_ms / 1e3) / 1e9, 2),
-            "sequential_ms_per_step": round(seq_ms, 3), "overlapped_ms_per_step": round(ovl_ms, 3),
-            "sequential_suffixes_per_s": round(n2 / (seq_ms / 1e3), 1),
-            "overlapped_suffixes_per_s": round(n2 / (ovl_ms / 1e3), 1), "steps": steps}
+            "sequential_ms_per_step": {"median": round(sq, 3), "min": round(min(seq), 3), "max": round(max(seq), 3)},
+            "overlapped_ms_per_step": {"median": round(ov, 3), "min": round(min(ovl), 3), "max": round(max(ovl), 3)},
+            "sequential_suffixes_per_s": round(n2 / (sq / 1e3), 1),
+            "overlapped_suffixes_per_s": round(n2 / (ov / 1e3), 1), "steps": steps,
+            "overlap_gain": round(sq / ov, 3)}
 
 
 def roofline_of(prof: dict, st: dict, steps: int, workload: str, src_hash: str):
@@ -327,10 +379,24 @@ def roofline_of(prof: dict, st: dict, steps: int, workload: str, src_hash: str):
     if ab is None or dom_ms_total <= 0:
         return None
     achieved = ab / (dom_ms_total / 1e3) / 1e9
+    ov = overhead_bytes(dom, st)
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": read_traffic(dom, workload, src_hash), "algorithmic_bytes_per_launch": ab / launches,
-            "avg_launch_ms": dom_ms_total / launches}
+            "avg_launch_ms": dom_ms_total / launches,
+            "implementation_overhead_bytes_per_launch": ov}
+
+
+def merge_roofline(st: dict, ms_per_step: float):
+    """The whole merge against the HBM roofline: the method's bytes for one
+    merge (merge_method_bytes) over the measured time of a step (the step also
+    copies the 0.5 B-per-symbol existing index first)."""
+    mb = merge_method_bytes(st)
+    achieved = mb["total"] / (ms_per_step / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "method_bytes_per_merge": mb,
+            "method_bytes_per_new_suffix": round(mb["total"] / st["n2"], 2),
+            "roofline_suffixes_per_s": round(st["n2"] / (mb["total"] / (HBM_PEAK_GBS * 1e9)), 1)}
 
 
 def plain_vs_batched(b1_strings, new, chunk: int, k: int):
@@ -583,6 +649,11 @@ def main():
     ap.add_argument("--no-host-input", action="store_true",
                     help="skip the merges fed from pinned host memory (PCIe-inclusive rate)")
     ap.add_argument("--no-smem", action="store_true", help="skip the SMEM serving measurement")
+    ap.add_argument("--no-incremental", action="store_true",
+                    help="skip the large incremental build (10 batches of 10 haplotypes of 100 Mb)")
+    ap.add_argument("--smem-haplotypes", type=int, default=320,
+                    help="haplotypes in the SMEM serving index of the default run (320: the full serving "
+                         "configuration)")
     ap.add_argument("--smem-batched-only", action="store_true",
                     help="SMEM: the batched calls only (no per-query calls, no served latency); for counter runs")
     ap.add_argument("--workload", default="pangenome_merge",
@@ -668,7 +739,7 @@ def main():
 
     host_input = None
     if workload == "pangenome_merge" and not args.no_host_input:
-        host_input = host_input_merges(b1, new_strings, 5)
+        host_input = host_input_merges(b1, new_strings, 10)
 
     plain = None
     if workload == "uneven_merge" and args.plain_strings > 0:
@@ -676,15 +747,27 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        threads = max(1, min(16, os.cpu_count() or 1))
+        import oracle
+        threads = oracle.host_threads()
         log(f"timing the oracle on {threads} host threads ...")
         cpu = cpu_baseline(args.cpu_sample, threads)
         log(f"oracle: {cpu['value']:.3g} suffixes/s ({cpu['sample']})")
 
+    b1.close()
+    torch.cuda.empty_cache()
     smem = None
     if not args.no_smem:
-        b1.close()
-        smem = smem_bench(10_000_000, 32, 10_000, 200, [0.5], 10_000, batched_only=args.smem_batched_only)
+        rates = [0.25, 0.5, 0.8] if args.smem_haplotypes >= 320 else [0.5]
+        smem = smem_bench(10_000_000, args.smem_haplotypes, 10_000, 200, rates, 10_000,
+                          batched_only=args.smem_batched_only)
+        torch.cuda.empty_cache()
+    incremental = None
+    if workload == "pangenome_merge" and not args.no_incremental:
+        r = incremental_bench(args)
+        incremental = {"value": r["value"], "unit": r["unit"], "config": r["config"], "batches": r["batches"],
+                       "total_merge_s": r["total_merge_s"], "peak_hbm_allocated_bytes": r["peak_hbm_allocated_bytes"],
+                       "device_free_min_bytes": r["device_free_min_bytes"]}
+        torch.cuda.empty_cache()
 
     out = {
         "metric": "BWT-merge suffixes inserted/s",
@@ -703,8 +786,10 @@ def main():
                    "strings_merged": new_strings.n, "both_strands": True, "n1": n1, "n2": n2,
                    "n_merged": n_out, "chunk_len": st["chunk_len"]},
         "roofline": roofline,
+        "merge_roofline": merge_roofline(st, ms),
         "cpu_baseline": cpu,
         "smem": smem,
+        "incremental": incremental,
         "plain_vs_batched": plain,
         "host_input": host_input,
         "merge_stats": st,
