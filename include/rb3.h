@@ -103,8 +103,10 @@ typedef struct rb3_opts {
                               choice, else 128; other values give RB3_EINVAL. */
     int32_t smem_segment;  /* rb3_smem cuts long queries into segments of this
                               many positions, each searched by its own lane
-                              (results do not depend on it). 0 (default): from
-                              the batch size (32 .. 4096). Else 1 .. 2^20. */
+                              (results do not depend on it). 0 (default): the
+                              length rb3_tune_smem chose for the batch's size
+                              class, else from the batch size (32 .. 4096).
+                              Else 1 .. 2^20. */
 } rb3_opts;
 
 /* Fill *o with the defaults above. */
@@ -330,6 +332,28 @@ void rb3_server_free(rb3_server *s);
 int rb3_prof_enable(int on);
 int rb3_prof_reset(void);
 int rb3_prof_read(char *names, int64_t *launches, double *ms, int64_t cap, int64_t *n_out);
+
+/*
+ * Autotuner. rb3_tune_merge times merges of the given strings into copies
+ * of idx (idx itself is unchanged) at several LF-chain chunk lengths and
+ * keeps the fastest for the size class (GPU architecture, log2 of the index
+ * size, of the batch size and of the mean strand length); later merges with
+ * chunk_len = 0 in their options use it. rb3_tune_smem times rb3_smem on the
+ * given queries at several segment lengths (and the automatic rule) and
+ * keeps the fastest for (architecture, log2 index size, log2 batch bases,
+ * log2 mean query length); rb3_smem with smem_segment = 0 uses it (-1 in
+ * *segment: the automatic rule won). The table is per process; with the
+ * environment variable RB3_TUNE_CACHE set to a file path it is also read
+ * from and written to that file. cand / ms (cap entries, may be NULL with
+ * cap 0) receive each candidate and its time in milliseconds, *n_out their
+ * number. The calls allocate like the merge / SMEM calls they time (the
+ * merge tuner also a copy of the index).
+ */
+int rb3_tune_merge(rb3_index *idx, const uint8_t *seq, const int64_t *lens, int64_t n_seqs, int32_t mem,
+                   int64_t *chunk_len, int64_t *cand, double *ms, int64_t cap, int64_t *n_out);
+int rb3_tune_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
+                  int32_t min_len, int64_t min_occ, int64_t *segment, int64_t *cand, double *ms, int64_t cap,
+                  int64_t *n_out);
 
 /*
  * Test hook for failure handling: while stage is nonzero, every rb3_merge

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -732,6 +733,124 @@ void rb3_index_free(rb3_index *idx) {
     c.free_now(idx->d.smp_val);
     if (idx->d.ctx.own_stream && idx->d.ctx.stream) (void)hipStreamDestroy(idx->d.ctx.stream);
     delete idx;
+}
+
+// The autotuner's trials: candidates timed on clones (merge) or on the
+// index itself (SMEM, read-only), inputs staged on the device once.
+int rb3_tune_merge(rb3_index *idx, const uint8_t *seq, const int64_t *lens, int64_t n_seqs, int32_t mem,
+                   int64_t *chunk_len, int64_t *cand, double *ms, int64_t cap, int64_t *n_out) {
+    if (!idx || !chunk_len) return fail(RB3_EINVAL, "NULL argument");
+    if (idx->d.n == 0) return fail(RB3_EINVAL, "tuning needs a non-empty index (a build has no chains)");
+    if (cap < 0 || (cap > 0 && (!cand || !ms))) return fail(RB3_EINVAL, "bad output arrays");
+    int64_t total = 0;
+    RB3_TRY(check_strings(seq, lens, n_seqs, mem, false, &total));
+    if (n_seqs == 0) return fail(RB3_EINVAL, "no strings to tune on");
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    const int k = idx->d.ctx.both ? 2 : 1;
+    const int64_t m2 = k * n_seqs, n2 = k * (total + n_seqs);
+    Ctx c = call_ctx(idx->d);
+    const int64_t cands[] = {1024, 2048, 4096, 8192};
+    std::vector<std::pair<int64_t, double>> res;
+    int rc = [&]() -> int {
+        DBuf hold;
+        const uint8_t *d_seq = nullptr;
+        RB3_TRY(stage(c, seq, total, mem, hold, &d_seq));
+        RB3_TRY(c.flush());
+        for (int trial = -1; trial < (int)(sizeof(cands) / sizeof(cands[0])); ++trial) {
+            const int64_t CL = cands[trial < 0 ? 1 : trial];
+            if (n2 / CL > ((int64_t)1 << 21)) continue;  // more chunks than lanes in flight
+            rb3_index *cl = nullptr;
+            RB3_TRY(rb3_clone(idx, &cl));
+            cl->d.ctx.chunk_len = CL;
+            Ctx cc = call_ctx(cl->d);
+            RB3_HIP(hipStreamSynchronize(cc.stream));
+            const auto t0 = std::chrono::steady_clock::now();
+            int r = do_merge(cc, cl->d, d_seq, lens, n_seqs, RB3_MEM_DEVICE);
+            r = finish(cc, r);
+            const auto t1 = std::chrono::steady_clock::now();
+            rb3_index_free(cl);
+            RB3_TRY(r);
+            if (trial >= 0) res.push_back({CL, std::chrono::duration<double, std::milli>(t1 - t0).count()});
+        }
+        return RB3_OK;
+    }();
+    rc = finish(c, rc);
+    if (rc != RB3_OK) return rc;
+    if (res.empty()) return fail(RB3_EINVAL, "batch too large for every candidate chunk length");
+    size_t best = 0;
+    for (size_t j = 0; j < res.size(); ++j)
+        if (res[j].second < res[best].second) best = j;
+    *chunk_len = res[best].first;
+    tune_store(merge_tune_key(idx->d.ctx.device, idx->d.n, n2, m2), res[best].first);
+    for (int64_t j = 0; j < (int64_t)res.size() && j < cap; ++j) {
+        cand[j] = res[j].first;
+        ms[j] = res[j].second;
+    }
+    if (n_out) *n_out = (int64_t)res.size();
+    return RB3_OK;
+}
+
+int rb3_tune_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
+                  int32_t min_len, int64_t min_occ, int64_t *segment, int64_t *cand, double *ms, int64_t cap,
+                  int64_t *n_out) {
+    if (!idx || !segment) return fail(RB3_EINVAL, "NULL argument");
+    if (min_len < 1 || min_occ < 1) return fail(RB3_EINVAL, "min_len and min_occ must be >= 1");
+    if (!idx->d.ctx.both) return fail(RB3_EINVAL, "SMEM finding needs an index of both strands");
+    if (cap < 0 || (cap > 0 && (!cand || !ms))) return fail(RB3_EINVAL, "bad output arrays");
+    int64_t total = 0;
+    RB3_TRY(check_strings(q, qlens, n_q, mem, true, &total));
+    if (n_q == 0 || total == 0) return fail(RB3_EINVAL, "no queries to tune on");
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    // -1: the automatic rule (from the batch size)
+    const int64_t cands[] = {-1, 64, 128, 256, 512, 1024, 2048, 4096};
+    std::vector<std::pair<int64_t, double>> res;
+    Ctx c = call_ctx(idx->d);
+    int rc = [&]() -> int {
+        DBuf hold;
+        const uint8_t *d_q = nullptr;
+        RB3_TRY(stage(c, q, total, mem, hold, &d_q));
+        RB3_TRY(c.flush());
+        int64_t ocap = total / 16 + 16 * n_q + 16;
+        std::vector<rb3_smem_t> out;
+        std::vector<int64_t> off(n_q + 1);
+        for (int64_t sg : cands) {
+            double best_ms = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                Ctx cc = call_ctx(idx->d);
+                cc.smem_seg_fixed = sg;
+                out.resize(ocap);
+                int64_t exts[2] = {0, 0};
+                const auto t0 = std::chrono::steady_clock::now();
+                int r = run_smem(cc, idx->d.dev(), d_q, qlens, n_q, total, RB3_MEM_DEVICE, min_len, min_occ,
+                                 out.data(), ocap, off.data(), exts);
+                r = finish(cc, r);
+                const auto t1 = std::chrono::steady_clock::now();
+                if (r == RB3_ENOSPC) {
+                    ocap = off[n_q];
+                    --rep;
+                    continue;
+                }
+                RB3_TRY(r);
+                const double t = std::chrono::duration<double, std::milli>(t1 - t0).count();
+                if (t < best_ms) best_ms = t;
+            }
+            res.push_back({sg, best_ms});
+        }
+        return RB3_OK;
+    }();
+    rc = finish(c, rc);
+    if (rc != RB3_OK) return rc;
+    size_t best = 0;
+    for (size_t j = 0; j < res.size(); ++j)
+        if (res[j].second < res[best].second) best = j;
+    *segment = res[best].first;
+    tune_store(smem_tune_key(idx->d.ctx.device, idx->d.n, total, n_q), res[best].first);
+    for (int64_t j = 0; j < (int64_t)res.size() && j < cap; ++j) {
+        cand[j] = res[j].first;
+        ms[j] = res[j].second;
+    }
+    if (n_out) *n_out = (int64_t)res.size();
+    return RB3_OK;
 }
 
 int rb3_test_fail_merge_after(int32_t stage) {

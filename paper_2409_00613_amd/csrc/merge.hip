@@ -2056,6 +2056,7 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
         // gaining throughput, while the unresolved share of each chunk still
         // grows)
         int64_t CL = c.chunk_len;
+        if (CL <= 0) CL = tuned_chunk_len(c.device, n1, n2, m2);
         if (CL <= 0) {
             CL = 2048;
             while (CL < (1 << 20) && n2 / CL > (1 << 17)) CL *= 2;

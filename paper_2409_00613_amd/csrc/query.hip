@@ -332,7 +332,12 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
     const int64_t smin = c.smem_seg_min > 0 ? c.smem_seg_min : SMEM_SEG_MIN;
     int64_t S = bases / target;
     S = S < smin ? smin : (S > SMEM_SEG ? SMEM_SEG : S);
-    if (c.smem_seg_fixed > 0) S = c.smem_seg_fixed;
+    if (c.smem_seg_fixed > 0) {
+        S = c.smem_seg_fixed;
+    } else if (c.smem_seg_fixed == 0) {
+        const int64_t t = tuned_smem_segment(c.device, ix.n, bases, nq);
+        if (t > 0) S = t;
+    }
     std::vector<Seg> segs;
     std::vector<int64_t> qseg(nq + 1);
     int64_t off = 0;

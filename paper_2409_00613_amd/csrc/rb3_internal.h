@@ -196,7 +196,7 @@ struct Ctx {
     int32_t launch_per_string = 0;
     int64_t smem_segs = 0;     // SMEM segments to aim for per call; 0 = SMEM_TARGET_SEGS
     int64_t smem_seg_min = 0;  // shortest SMEM segment; 0 = SMEM_SEG_MIN
-    int64_t smem_seg_fixed = 0;  // fixed SMEM segment length; 0 = from the batch
+    int64_t smem_seg_fixed = 0;  // fixed SMEM segment length; 0 = tuned or from the batch; -1 = from the batch
     int32_t both = 1;
     int32_t ssa = 0;           // suffix-array sampling distance (0: no samples)
     // Frees are deferred until flush(), called after the stream has drained,
@@ -504,6 +504,13 @@ int run_count(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens
 int run_smem(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
              int32_t mem, int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off,
              int64_t *exts);
+// tune.cpp: the autotuner's table (see rb3_tune_merge / rb3_tune_smem).
+std::string merge_tune_key(int dev, int64_t n1, int64_t n2, int64_t m2);
+std::string smem_tune_key(int dev, int64_t n, int64_t bases, int64_t nq);
+int64_t tuned_chunk_len(int dev, int64_t n1, int64_t n2, int64_t m2);        // 0: none
+int64_t tuned_smem_segment(int dev, int64_t n, int64_t bases, int64_t nq);   // 0: none, -1: automatic
+void tune_store(const std::string &key, int64_t v);
+
 const DevIndex index_dev(const rb3_index *idx);
 hipStream_t index_stream(const rb3_index *idx);
 // noalloc.hip: rb3_count with every temporary in the library's fixed

@@ -49,6 +49,7 @@ EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_count_no
            "rb3_locate", "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info",
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
            "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats", "rb3_test_fail_merge_after",
+           "rb3_tune_merge", "rb3_tune_smem",
            "rb3_server_opts_init", "rb3_server_create", "rb3_server_submit", "rb3_server_poll",
            "rb3_server_stats", "rb3_server_replay", "rb3_server_free"]
 
@@ -119,6 +120,9 @@ def lib():
     L.rb3_prof_read.argtypes = [ctypes.c_char_p, _i64p, ctypes.POINTER(ctypes.c_double), _i64, _i64p]
     L.rb3_merge_stats.argtypes = [_vp, ctypes.c_char_p, _i64p, _i64, _i64p]
     L.rb3_test_fail_merge_after.argtypes = [_i32]
+    _dp0 = ctypes.POINTER(ctypes.c_double)
+    L.rb3_tune_merge.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p, _dp0, _i64, _i64p]
+    L.rb3_tune_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, _i64p, _i64p, _dp0, _i64, _i64p]
     L.rb3_server_opts_init.argtypes = [ctypes.POINTER(ServerOpts)]
     L.rb3_server_opts_init.restype = None
     L.rb3_server_create.argtypes = [_vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
@@ -136,7 +140,7 @@ def lib():
     for name in ("rb3_build", "rb3_merge", "rb3_count", "rb3_count_noalloc", "rb3_smem", "rb3_last_smem_stats", "rb3_locate",
                  "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info", "rb3_export",
                  "rb3_import", "rb3_clone", "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read",
-                 "rb3_merge_stats", "rb3_test_fail_merge_after"):
+                 "rb3_merge_stats", "rb3_test_fail_merge_after", "rb3_tune_merge", "rb3_tune_smem"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -457,6 +461,34 @@ def rb3_merge_stats(idx: Index) -> dict:
     _check(lib().rb3_merge_stats(idx.handle, keys, vals.ctypes.data_as(_i64p), cap, ctypes.byref(n)))
     raw = keys.raw
     return {raw[i * 32:(i + 1) * 32].split(b"\0")[0].decode(): int(vals[i]) for i in range(min(n.value, cap))}
+
+
+def rb3_tune_merge(idx: Index, seq, lens) -> dict:
+    """Autotune the merge chunk length on this batch (idx unchanged)."""
+    ptr, _, mem, keep = _buffer(seq)
+    la, lp = _lens(lens)
+    best = ctypes.c_int64()
+    cand = np.zeros(16, np.int64)
+    ms = np.zeros(16, np.float64)
+    n = ctypes.c_int64()
+    _check(lib().rb3_tune_merge(idx.handle, ptr, lp, la.shape[0], mem, ctypes.byref(best),
+                                cand.ctypes.data_as(_i64p), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                16, ctypes.byref(n)))
+    return {"chunk_len": best.value, "trials": {int(c): round(float(t), 3) for c, t in zip(cand[:n.value], ms[:n.value])}}
+
+
+def rb3_tune_smem(idx: Index, q, qlens, min_len: int, min_occ: int = 1) -> dict:
+    """Autotune the SMEM segment length on these queries (-1: the automatic rule)."""
+    ptr, _, mem, keep = _buffer(q)
+    la, lp = _lens(qlens)
+    best = ctypes.c_int64()
+    cand = np.zeros(16, np.int64)
+    ms = np.zeros(16, np.float64)
+    n = ctypes.c_int64()
+    _check(lib().rb3_tune_smem(idx.handle, ptr, lp, la.shape[0], mem, int(min_len), int(min_occ),
+                               ctypes.byref(best), cand.ctypes.data_as(_i64p),
+                               ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 16, ctypes.byref(n)))
+    return {"segment": best.value, "trials": {int(c): round(float(t), 3) for c, t in zip(cand[:n.value], ms[:n.value])}}
 
 
 def rb3_test_fail_merge_after(stage: int):
