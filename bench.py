@@ -74,11 +74,11 @@ def algorithmic_bytes(kernel: str, st: dict, steps: int) -> float | None:
         "fix_compose": (st["fixup_steps"] - st.get("fixup_index_steps", 0)) * 8,
         "fix_keys": (st["fixup_steps"] - st.get("fixup_index_steps", 0)) * (8 + 8 + 1 + 8),
         # per pass: key 8 B read for the histogram
-        "sort_hist": n2 * 8 * max(1, -(-st["sort_bits"] // 8)),
+        "sort_hist": n2 * 8 * st["sort_passes"],
         # per pass: key + value read and written (the first pass has no value
         # to read); packed 8-byte records between the first and last passes
-        "sort_scatter": (n2 * (16 * (max(1, -(-st["sort_bits"] // 8)) - 1) + 20) if st.get("sort_packed")
-                         else n2 * 24 * max(1, -(-st["sort_bits"] // 8)) - n2 * 4),
+        "sort_scatter": (n2 * (16 * (st["sort_passes"] - 1) + 20) if st.get("sort_packed")
+                         else n2 * 24 * st["sort_passes"] - n2 * 4),
         # per active record per round: position, rank h further on, key written
         "tie_gather": st["tie_work"] * 12 if st.get("tie_doubling") else None,
         # per active record per round: its record and group (16 B), key (4 B),

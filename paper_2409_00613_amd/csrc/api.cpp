@@ -898,7 +898,7 @@ int rb3_merge_stats(const rb3_index *idx, char *keys, int64_t *vals, int64_t cap
         {"n1", s.n1}, {"m1", s.m1}, {"n2", s.n2}, {"m2", s.m2},
         {"chunks", s.chunks}, {"chunk_len", s.chunk_len}, {"chain_steps", s.chain_steps},
         {"fixup_steps", s.fixup_steps}, {"fixup_index_steps", s.fixup_index_steps}, {"fixup_segments", s.fixup_segments}, {"fixup_passes", s.fixup_passes}, {"fixup_run_max", s.fixup_run_max}, {"key_syms", s.key_syms},
-        {"sort_bits", s.sort_bits}, {"sort_packed", s.sort_packed}, {"tied_records", s.tied_records}, {"tie_groups", s.tie_groups}, {"tie_pairs", s.tie_pairs}, {"tie_small_reads", s.tie_small_reads}, {"tie_max_depth", s.tie_max_depth}, {"tie_deep_reads", s.tie_deep_reads},
+        {"sort_bits", s.sort_bits}, {"sort_packed", s.sort_packed}, {"sort_passes", s.sort_passes}, {"tied_records", s.tied_records}, {"tie_groups", s.tie_groups}, {"tie_pairs", s.tie_pairs}, {"tie_small_reads", s.tie_small_reads}, {"tie_max_depth", s.tie_max_depth}, {"tie_deep_reads", s.tie_deep_reads},
         {"max_group", s.max_group}, {"tie_doubling", s.tie_doubling}, {"tie_rounds", s.tie_rounds},
         {"tie_work", s.tie_work}, {"tie_block_reads", s.tie_block_reads}};
     static const char *hist_names[32] = {

@@ -2204,10 +2204,11 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
     RB3_ALLOC(vb, &c, n2 * sizeof(uint32_t));
     uint64_t *SK = nullptr;
     uint32_t *SV = nullptr;
-    int packed_sort = 0;
+    int packed_sort = 0, sort_passes = 0;
     RB3_TRY(radix_sort(c, K.as<uint64_t>(), nullptr, ka.as<uint64_t>(), va.as<uint32_t>(), kb.as<uint64_t>(),
-                       vb.as<uint32_t>(), n2, 3, hi_bit, true, &SK, &SV, guard, &packed_sort));
+                       vb.as<uint32_t>(), n2, 3, hi_bit, true, &SK, &SV, guard, &packed_sort, &sort_passes));
     st.sort_packed = packed_sort;
+    st.sort_passes = sort_passes;
     RB3_TRY(fault_point(2));
     // free the other buffer pair early
     if (SK == ka.as<uint64_t>()) {

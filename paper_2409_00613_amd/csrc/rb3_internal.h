@@ -331,7 +331,7 @@ int scan_u32(Ctx &c, const uint32_t *d_in, uint32_t *d_out, int64_t n, bool incl
 // The input pair (k_in, v_in) is left untouched.
 int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *v_a, uint64_t *k_b,
                uint32_t *v_b, int64_t n, int lo_bit, int hi_bit, bool iota_vals, uint64_t **k_res,
-               uint32_t **v_res, int32_t *d_guard, int *used_packed);
+               uint32_t **v_res, int32_t *d_guard, int *used_packed, int *used_passes = nullptr);
 
 // A piece of a new strand walked by one lane of the LF-chain kernel.
 struct Chunk {
@@ -373,6 +373,7 @@ struct MergeStats {
     int64_t key_syms = 0;         // symbols per initial sort key
     int64_t sort_bits = 0;
     int64_t sort_packed = 0;      // 1 when the sort moved packed 8-byte records
+    int64_t sort_passes = 0;      // passes over the records (8-bit digits)
     int64_t tied_records = 0;     // records in non-singleton groups after the sort
     int64_t tie_groups = 0;       // tied groups whose members carry different symbols
     int64_t tie_pairs = 0;        // ... of which have two members

@@ -1,5 +1,7 @@
 // Device-wide scans of uint32 arrays (sum or max), three passes:
-// per-tile reduce, scan of tile partials in one workgroup, per-tile rescan.
+// per-tile reduce, scan of the tile partials (in one workgroup, or
+// recursively when there are more partials than one tile holds), per-tile
+// rescan.
 #include "rb3_internal.h"
 
 namespace rb3 {
@@ -109,17 +111,27 @@ int scan_u32(Ctx &c, const uint32_t *d_in, uint32_t *d_out, int64_t n, bool incl
     DBuf part;
     RB3_ALLOC(part, &c, np * sizeof(uint32_t));
     dim3 g((unsigned)np), b(SCAN_THREADS);
-    if (max_op) {
+    if (max_op)
         RB3_LAUNCH("scan_reduce", k_scan_reduce<true>, g, b, 0, c.stream, d_in, n, part.as<uint32_t>());
+    else
+        RB3_LAUNCH("scan_reduce", k_scan_reduce<false>, g, b, 0, c.stream, d_in, n, part.as<uint32_t>());
+    // The tile partials are scanned by one workgroup when they fit one of its
+    // tiles, else by the same three steps one level up: a single workgroup
+    // walking tens of thousands of partials serially costs more than the
+    // two extra launches.
+    if (np > SCAN_TILE) {
+        RB3_TRY(scan_u32(c, part.as<uint32_t>(), part.as<uint32_t>(), np, false, max_op, d_total));
+    } else if (max_op) {
         RB3_LAUNCH("scan_parts", k_scan_parts<true>, dim3(1), b, 0, c.stream, part.as<uint32_t>(), np, d_total);
+    } else {
+        RB3_LAUNCH("scan_parts", k_scan_parts<false>, dim3(1), b, 0, c.stream, part.as<uint32_t>(), np, d_total);
+    }
+    if (max_op)
         RB3_LAUNCH("scan_down", k_scan_down<true>, g, b, 0, c.stream, d_in, d_out, n, part.as<uint32_t>(),
                    (int)inclusive);
-    } else {
-        RB3_LAUNCH("scan_reduce", k_scan_reduce<false>, g, b, 0, c.stream, d_in, n, part.as<uint32_t>());
-        RB3_LAUNCH("scan_parts", k_scan_parts<false>, dim3(1), b, 0, c.stream, part.as<uint32_t>(), np, d_total);
+    else
         RB3_LAUNCH("scan_down", k_scan_down<false>, g, b, 0, c.stream, d_in, d_out, n, part.as<uint32_t>(),
                    (int)inclusive);
-    }
     return RB3_OK;
 }
 

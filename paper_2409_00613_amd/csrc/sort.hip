@@ -192,8 +192,9 @@ __global__ void __launch_bounds__(SC_THREADS) k_rs_scatter(const uint64_t *__res
 
 int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *v_a, uint64_t *k_b,
                uint32_t *v_b, int64_t n, int lo_bit, int hi_bit, bool iota_vals, uint64_t **k_res,
-               uint32_t **v_res, int32_t *d_guard, int *used_packed) {
+               uint32_t **v_res, int32_t *d_guard, int *used_packed, int *used_passes) {
     if (used_packed) *used_packed = 0;
+    if (used_passes) *used_passes = 0;
     if (n >= (int64_t)UINT32_MAX) {
         set_error(RB3_ELIMIT, "radix sort: too many records");
         return RB3_ELIMIT;
@@ -220,6 +221,7 @@ int radix_sort(Ctx &c, uint64_t *k_in, uint32_t *v_in, uint64_t *k_a, uint32_t *
     while (pbits < 32 && ((int64_t)1 << pbits) < n) ++pbits;
     const bool packed = iota_vals && npass >= 2 && hi_bit + pbits <= 64;
     if (used_packed) *used_packed = packed ? 1 : 0;
+    if (used_passes) *used_passes = npass;
     const uint64_t *src_k = k_in;
     const uint32_t *src_v = v_in;
     int in_mode = iota_vals ? 1 : 0;
