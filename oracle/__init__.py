@@ -24,6 +24,10 @@ Functions (each follows a definition of arXiv 2409.00613):
   locate      the suffix-array entry of a row written as (string index,
               offset within the string) (Sec. 2.4)
   rows_of     the inverse: the row of the suffix at (string index, offset)
+  rle_encode / rle_decode / rle_rank / delta_code
+              the run-length static format (Sec. 2.2, Fig. 2b): blocks of
+              Elias-delta coded runs with marginal counts and an index row,
+              and rank by decoding them (``rle.c`` holds the definition)
 """
 from __future__ import annotations
 
@@ -34,7 +38,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "rle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -43,11 +47,11 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so with gcc."""
+    """Compile oracle.c and rle.c into liboracle.so with gcc."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-std=c99",
-                               "-Wall", "-Wextra", "-o", tmp, _SRC])
+                               "-Wall", "-Wextra", "-o", tmp] + _SRCS)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -91,6 +95,19 @@ def _load():
     lib.orc_smem_scan.argtypes = [_u8p, _i64p, ctypes.c_int64, _u8p, _i64p, ctypes.c_int64, ctypes.c_int64,
                                   ctypes.c_int64, ctypes.c_int, _i64p, ctypes.c_int64, _i64p]
     lib.orc_smem_scan.restype = ctypes.c_int64
+    _u64p = ctypes.POINTER(ctypes.c_uint64)
+    _u16p = ctypes.POINTER(ctypes.c_uint16)
+    lib.orc_delta_len.argtypes = [ctypes.c_uint64]
+    lib.orc_delta_len.restype = ctypes.c_int
+    lib.orc_delta_string.argtypes = [ctypes.c_uint64, ctypes.c_char_p]
+    lib.orc_delta_string.restype = ctypes.c_int
+    lib.orc_rle_encode.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, _u64p, _i64p, _u16p, _i64p]
+    lib.orc_rle_encode.restype = ctypes.c_int
+    lib.orc_rle_decode.argtypes = [_u64p, _i64p, ctypes.c_int64, _u8p]
+    lib.orc_rle_decode.restype = ctypes.c_int
+    lib.orc_rle_rank.argtypes = [_u64p, _i64p, _u16p, ctypes.c_int64, ctypes.c_int, _i64p, ctypes.c_int64,
+                                 _i64p]
+    lib.orc_rle_rank.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -378,3 +395,74 @@ def rows_of(S: np.ndarray, lens: np.ndarray, strings, offsets) -> np.ndarray:
     inv[S] = np.arange(S.shape[0], dtype=np.int64)
     starts = _string_starts(lens)
     return inv[starts[np.asarray(strings, dtype=np.int64)] + np.asarray(offsets, dtype=np.int64)]
+
+
+# ---------------------------------------------------------------------------
+# Run-length static format (rle.c)
+# ---------------------------------------------------------------------------
+
+RLE_SEG_SHIFT = 20
+RLE_WORDS = 16
+
+
+def delta_code(L: int) -> str:
+    """The Elias delta code of L >= 1 as a '0'/'1' string (MSB first)."""
+    buf = ctypes.create_string_buffer(80)
+    _load().orc_delta_string(ctypes.c_uint64(L), buf)
+    return buf.value.decode()
+
+
+class Rle:
+    """The format's three arrays: blocks (nblocks x 16 uint64), seg
+    ((nseg + 1) x 8 int64), row (uint16), with n and the row shift q."""
+
+    def __init__(self, blocks, seg, row, n, q):
+        self.blocks, self.seg, self.row, self.n, self.q = blocks, seg, row, int(n), int(q)
+
+    @property
+    def nbytes(self) -> int:
+        return self.blocks.nbytes + self.seg.nbytes + self.row.nbytes
+
+
+def rle_encode(B: np.ndarray, q: int) -> Rle:
+    """Encode a BWT (codes 0..5) in the run-length format with row shift q."""
+    lib = _load()
+    B = np.ascontiguousarray(B, dtype=np.uint8)
+    n = B.shape[0]
+    _u64p = ctypes.POINTER(ctypes.c_uint64)
+    _u16p = ctypes.POINTER(ctypes.c_uint16)
+    nb = np.zeros(1, np.int64)
+    if lib.orc_rle_encode(_p(B, _u8p), n, q, None, None, None, _p(nb, _i64p)) != 0:
+        raise ValueError("rle_encode: bad arguments")
+    nseg = (n + (1 << RLE_SEG_SHIFT) - 1) >> RLE_SEG_SHIFT
+    blocks = np.zeros((int(nb[0]), RLE_WORDS), np.uint64)
+    seg = np.zeros((nseg + 1, 8), np.int64)
+    row = np.zeros(((n - 1) >> q) + 1, np.uint16)
+    lib.orc_rle_encode(_p(B, _u8p), n, q, _p(blocks, _u64p), _p(seg, _i64p), _p(row, _u16p), _p(nb, _i64p))
+    return Rle(blocks, seg, row, n, q)
+
+
+def rle_decode(r: Rle) -> np.ndarray:
+    """The BWT back out of its blocks."""
+    out = np.zeros(r.n, np.uint8)
+    blocks = np.ascontiguousarray(r.blocks, dtype=np.uint64)
+    seg = np.ascontiguousarray(r.seg, dtype=np.int64)
+    if _load().orc_rle_decode(_p(blocks, ctypes.POINTER(ctypes.c_uint64)), _p(seg, _i64p), r.n,
+                              _p(out, _u8p)) != 0:
+        raise ValueError("rle_decode: malformed blocks")
+    return out
+
+
+def rle_rank(r: Rle, positions) -> np.ndarray:
+    """Occurrences of $, A, C, G, T, N in B[0, i) for each position i, by the
+    format's rank rule (rows of 6)."""
+    pos = np.ascontiguousarray(positions, dtype=np.int64)
+    out = np.zeros((pos.shape[0], 6), np.int64)
+    blocks = np.ascontiguousarray(r.blocks, dtype=np.uint64)
+    seg = np.ascontiguousarray(r.seg, dtype=np.int64)
+    row = np.ascontiguousarray(r.row, dtype=np.uint16)
+    if _load().orc_rle_rank(_p(blocks, ctypes.POINTER(ctypes.c_uint64)), _p(seg, _i64p),
+                            _p(row, ctypes.POINTER(ctypes.c_uint16)), r.n, r.q, _p(pos, _i64p),
+                            pos.shape[0], _p(out, _i64p)) != 0:
+        raise ValueError("rle_rank: bad position or malformed blocks")
+    return out
