@@ -247,6 +247,75 @@ void rb3_index_free(rb3_index *idx);
 const char *rb3_strerror(int err);
 
 /*
+ * Run-length static index: the BWT in the static, bit-packed run-length
+ * form of Sec. 2.2 (Fig. 2b), for indices whose 3-bit-plane form would not
+ * fit in device memory. It answers the same counts and SMEMs as the index
+ * it was built from (pi_B by decoding, Table 1), but cannot be merged into.
+ *
+ * Format (all arrays little-endian):
+ *   - B[0, n) is cut into segments of 2^20 symbols; each segment into its
+ *     maximal runs of one symbol (pieces, at most 2^20 long).
+ *   - A piece is coded as its symbol in 3 bits, then its length L in the
+ *     Elias delta code (K - 1 zeros, N in K bits, the N - 1 low bits of L,
+ *     where N is the bit length of L and K that of N); most significant bit
+ *     first.
+ *   - blocks: 128-byte blocks of 16 uint64 words. Words 0-1: header; words
+ *     2-15: 896 stream bits, stream bit t at bit 63 - t % 64 of word
+ *     2 + t / 64, unused bits 0. Header word 0: bits 0-19 the offset of the
+ *     block's first symbol in its segment, 20-39 and 40-59 the occurrences
+ *     of A and C in the segment before the block, 60-63 the low 4 bits of
+ *     the block's piece count; word 1: bits 0-19, 20-39, 40-59 the
+ *     occurrences of G, T, N before the block in the segment, 60-63 the
+ *     high 4 bits of the piece count. A segment's pieces fill its blocks in
+ *     order, greedily (a block takes pieces while their codes fit); every
+ *     segment starts a new block.
+ *   - segs: (nseg + 1) rows of 8 int64, nseg = ceil(n / 2^20): occurrences
+ *     of $, A, C, G, T, N in B before the segment, the index of its first
+ *     block, 0. Row nseg holds the totals and the number of blocks.
+ *   - row: ((n - 1) >> row_shift) + 1 uint16; entry j is the block holding
+ *     position j << row_shift, counted from its segment's first block.
+ *
+ * The object keeps its arrays in device memory of the index's device (from
+ * the index's allocator, which must outlive it) and has a stream of its own,
+ * so it outlives the index it was built from.
+ */
+typedef struct rb3_rle rb3_rle;
+
+/* Build from an index. row_shift: 4..20, or 0 for the automatic choice
+ * (the largest value in 4..16 with 2^row_shift <= n / (4 * blocks)). An
+ * empty index gives RB3_EINVAL; 2^32 or more pieces give RB3_ELIMIT. */
+int rb3_rle_build(const rb3_index *idx, int32_t row_shift, rb3_rle **out);
+
+/* Load the three arrays (host memory; sizes as above, nblocks blocks) on
+ * the device of o (NULL: defaults), after checking them against the format:
+ * the table on the host, then every block's codes, offsets and header
+ * counts and every index-row entry on the device. Data that fail a check
+ * give RB3_EINVAL. both != 0 marks an index of both strands (for SMEMs). */
+int rb3_rle_load(const rb3_opts *o, const uint64_t *blocks, int64_t nblocks, const int64_t *segs,
+                 const uint16_t *row, int64_t n, int32_t row_shift, int32_t both, rb3_rle **out);
+
+/* Sizes: symbols n, sentinels m, pieces (runs cut at segment starts),
+ * blocks, the row shift, and the bytes of the three arrays. Any pointer may
+ * be NULL. */
+int rb3_rle_info(const rb3_rle *r, int64_t *n, int64_t *m, int64_t *runs, int64_t *blocks, int32_t *row_shift,
+                 int64_t *bytes);
+
+/* Copy the three arrays to host buffers sized from rb3_rle_info. */
+int rb3_rle_image(const rb3_rle *r, uint64_t *blocks, int64_t *segs, uint16_t *row);
+
+/* Decode the whole BWT into codes (host, n bytes). */
+int rb3_rle_export(const rb3_rle *r, uint8_t *codes);
+
+/* rb3_count and rb3_smem on the run-length index: same arguments, rules and
+ * results. rb3_last_smem_stats then counts the 128-byte blocks decoded. */
+int rb3_rle_count(const rb3_rle *r, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem, int64_t *lo,
+                  int64_t *hi);
+int rb3_rle_smem(const rb3_rle *r, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
+                 int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off);
+
+void rb3_rle_free(rb3_rle *r);
+
+/*
  * Continuous-batching query server over one index.
  *
  * Requests (count or SMEM queries, one string each) are submitted from any

@@ -12,9 +12,37 @@
 #include <vector>
 
 #include "rb3_internal.h"
+#include "rle.h"
 
 struct rb3_index {
     rb3::IndexData d;
+};
+
+// Run-length static index: its arrays on the device and its own stream, so
+// it outlives the index it was built from.
+struct rb3_rle {
+    rb3::Ctx ctx;
+    uint64_t *blk = nullptr;
+    int64_t *seg = nullptr;
+    uint16_t *row = nullptr;
+    int64_t n = 0, m = 0, nseg = 0, nblk = 0, npieces = 0;
+    int32_t q = 0, both = 0;
+    int64_t C[6] = {0, 0, 0, 0, 0, 0};
+    rb3::RleView view() const {
+        rb3::RleView v;
+        v.blk = blk;
+        v.seg = seg;
+        v.row = row;
+        v.n = n;
+        v.m = m;
+        v.nseg = nseg;
+        v.nblk = nblk;
+        for (int i = 0; i < 6; ++i) v.C[i] = C[i];
+        v.C[6] = n;
+        v.C[7] = 0;
+        v.q = q;
+        return v;
+    }
 };
 
 namespace rb3 {
@@ -324,7 +352,7 @@ static int do_merge(Ctx &c, IndexData &d, const uint8_t *seq, const int64_t *len
 
 
 int run_count(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
-              int32_t mem, int64_t *lo, int64_t *hi) {
+              int32_t mem, int64_t *lo, int64_t *hi, const RleView *rle) {
     DBuf hold, codes, err, off, dlo, dhi;
     const uint8_t *d_q = nullptr;
     RB3_TRY(stage(c, q, total, mem, hold, &d_q));
@@ -342,7 +370,12 @@ int run_count(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens
     int32_t bad = 0;
     RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
     if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in a query");
-    RB3_TRY(count_queries(c, ix, codes.as<uint8_t>(), off.as<int64_t>(), n_q, dlo.as<int64_t>(), dhi.as<int64_t>()));
+    if (rle)
+        RB3_TRY(count_queries_rle(c, *rle, codes.as<uint8_t>(), off.as<int64_t>(), n_q, dlo.as<int64_t>(),
+                                  dhi.as<int64_t>()));
+    else
+        RB3_TRY(count_queries(c, ix, codes.as<uint8_t>(), off.as<int64_t>(), n_q, dlo.as<int64_t>(),
+                              dhi.as<int64_t>()));
     RB3_HIP(hipMemcpyAsync(lo, dlo.p, n_q * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
     RB3_HIP(hipMemcpyAsync(hi, dhi.p, n_q * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
     RB3_HIP(hipStreamSynchronize(c.stream));
@@ -351,7 +384,7 @@ int run_count(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens
 
 int run_smem(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
              int32_t mem, int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off,
-             int64_t *exts) {
+             int64_t *exts, const RleView *rle) {
     DBuf hold, codes, err, ordered, coff;
     const uint8_t *d_q = nullptr;
     RB3_TRY(stage(c, q, total, mem, hold, &d_q));
@@ -365,8 +398,12 @@ int run_smem(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens,
     RB3_ALLOC(ordered, &c, (out_cap > 0 ? out_cap : 1) * sizeof(rb3_smem_t));
     RB3_ALLOC(coff, &c, (n_q + 1) * sizeof(int64_t));
     int64_t kept = 0;
-    RB3_TRY(smem_run(c, ix, codes.as<uint8_t>(), qlens, n_q, min_len, min_occ, out_cap, ordered.as<rb3_smem_t>(),
-                     coff.as<int64_t>(), &kept, exts));
+    if (rle)
+        RB3_TRY(smem_run_rle(c, *rle, codes.as<uint8_t>(), qlens, n_q, min_len, min_occ, out_cap,
+                             ordered.as<rb3_smem_t>(), coff.as<int64_t>(), &kept, exts));
+    else
+        RB3_TRY(smem_run(c, ix, codes.as<uint8_t>(), qlens, n_q, min_len, min_occ, out_cap, ordered.as<rb3_smem_t>(),
+                         coff.as<int64_t>(), &kept, exts));
     RB3_HIP(hipMemcpyAsync(out_off, coff.p, (n_q + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
     if (kept <= out_cap && kept > 0)
         RB3_HIP(hipMemcpyAsync(out, ordered.p, kept * sizeof(rb3_smem_t), hipMemcpyDeviceToHost, c.stream));
@@ -924,6 +961,243 @@ int rb3_merge_stats(const rb3_index *idx, char *keys, int64_t *vals, int64_t cap
     }
     if (n_out) *n_out = i;
     return RB3_OK;
+}
+
+// ---------------------------------------------------------------------------
+// run-length static index
+// ---------------------------------------------------------------------------
+
+static Ctx rle_ctx(const rb3_rle *r) {
+    Ctx c;
+    c.device = r->ctx.device;
+    c.stream = r->ctx.stream;
+    c.own_stream = false;
+    c.alloc = r->ctx.alloc;
+    c.free_fn = r->ctx.free_fn;
+    c.alloc_ctx = r->ctx.alloc_ctx;
+    c.both = r->both;
+    c.smem_seg_fixed = r->ctx.smem_seg_fixed;
+    return c;
+}
+
+static void rle_totals(rb3_rle *r, const int64_t tot[6]) {
+    r->m = tot[0];
+    int64_t acc = 0;
+    for (int i = 0; i < 6; ++i) {
+        r->C[i] = acc;
+        acc += tot[i];
+    }
+}
+
+void rb3_rle_free(rb3_rle *r) {
+    if (!r) return;
+    (void)hipSetDevice(r->ctx.device);
+    if (r->ctx.stream) (void)hipStreamSynchronize(r->ctx.stream);
+    Ctx c = rle_ctx(r);
+    c.free_now(r->blk);
+    c.free_now(r->seg);
+    c.free_now(r->row);
+    if (r->ctx.own_stream && r->ctx.stream) (void)hipStreamDestroy(r->ctx.stream);
+    delete r;
+}
+
+static int rle_new(int device, const Ctx &like, rb3_rle **out) {
+    rb3_rle *r = new (std::nothrow) rb3_rle();
+    if (!r) return fail(RB3_ENOMEM, "host allocation failed");
+    r->ctx.device = device;
+    r->ctx.alloc = like.alloc;
+    r->ctx.free_fn = like.free_fn;
+    r->ctx.alloc_ctx = like.alloc_ctx;
+    r->ctx.smem_seg_fixed = like.smem_seg_fixed;
+    if (hipStreamCreateWithFlags(&r->ctx.stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete r;
+        return fail(RB3_EDEVICE, "stream creation failed");
+    }
+    r->ctx.own_stream = true;
+    *out = r;
+    return RB3_OK;
+}
+
+int rb3_rle_build(const rb3_index *idx, int32_t row_shift, rb3_rle **out) {
+    if (!idx || !out) return fail(RB3_EINVAL, "index or out is NULL");
+    if (idx->d.n == 0) return fail(RB3_EINVAL, "run-length index of an empty BWT");
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    rb3_rle *r = nullptr;
+    RB3_TRY(rle_new(idx->d.ctx.device, idx->d.ctx, &r));
+    r->both = idx->d.ctx.both;
+    // the build runs on the index's stream (it reads the index)
+    Ctx c = call_ctx(idx->d);
+    int rc = [&]() -> int {
+        RleBuild b;
+        RB3_TRY(rle_build(c, idx->d.dev(), row_shift, b));
+        r->n = b.n;
+        r->nseg = b.nseg;
+        r->nblk = b.nblk;
+        r->npieces = b.npieces;
+        r->q = b.q;
+        rle_totals(r, b.tot);
+        r->blk = (uint64_t *)b.blk.release();
+        r->seg = (int64_t *)b.seg.release();
+        r->row = (uint16_t *)b.row.release();
+        return RB3_OK;
+    }();
+    rc = finish(c, rc);
+    if (rc != RB3_OK) {
+        rb3_rle_free(r);
+        return rc;
+    }
+    *out = r;
+    return RB3_OK;
+}
+
+int rb3_rle_load(const rb3_opts *o, const uint64_t *blocks, int64_t nblocks, const int64_t *segs,
+                 const uint16_t *row, int64_t n, int32_t row_shift, int32_t both, rb3_rle **out) {
+    if (!out || !blocks || !segs || !row) return fail(RB3_EINVAL, "NULL argument");
+    if (n <= 0 || nblocks <= 0) return fail(RB3_EINVAL, "empty run-length index");
+    if (row_shift < 4 || row_shift > 20) return fail(RB3_EINVAL, "row shift must be in 4 .. 20");
+    const int64_t nseg = (n + RLE_SEG - 1) >> RLE_SEG_SHIFT;
+    // the segment table on the host: zero counts first, every segment's
+    // counts adding up to its length, first blocks increasing to nblocks
+    for (int k = 0; k < 7; ++k)
+        if (segs[k] != 0) return fail(RB3_EINVAL, "run-length index: first table row is not zero");
+    for (int64_t s = 0; s < nseg; ++s) {
+        const int64_t len = (s + 1) * RLE_SEG < n ? RLE_SEG : n - s * RLE_SEG;
+        int64_t sum = 0;
+        for (int k = 0; k < 6; ++k) {
+            const int64_t d = segs[(s + 1) * 8 + k] - segs[s * 8 + k];
+            if (d < 0) return fail(RB3_EINVAL, "run-length index: decreasing counts");
+            sum += d;
+        }
+        const int64_t nb = segs[(s + 1) * 8 + 6] - segs[s * 8 + 6];
+        if (sum != len || nb < 1 || nb >= 65536)
+            return fail(RB3_EINVAL, "run-length index: a segment's counts or blocks are out of range");
+    }
+    if (segs[nseg * 8 + 6] != nblocks) return fail(RB3_EINVAL, "run-length index: block count mismatch");
+    rb3_opts d;
+    rb3_opts_init(&d);
+    if (!o) o = &d;
+    Ctx like;
+    RB3_TRY(ctx_from_opts(o, like));
+    if (like.own_stream && like.stream) (void)hipStreamDestroy(like.stream);
+    rb3_rle *r = nullptr;
+    RB3_TRY(rle_new(o->device, like, &r));
+    r->both = both ? 1 : 0;
+    r->n = n;
+    r->nseg = nseg;
+    r->nblk = nblocks;
+    r->q = row_shift;
+    rle_totals(r, segs + nseg * 8);
+    Ctx c = rle_ctx(r);
+    int rc = [&]() -> int {
+        const int64_t nrow = ((n - 1) >> row_shift) + 1;
+        DBuf bb, sb, rb, bad;
+        RB3_ALLOC(bb, &c, nblocks * RLE_WORDS * sizeof(uint64_t));
+        RB3_ALLOC(sb, &c, (nseg + 1) * 8 * sizeof(int64_t));
+        RB3_ALLOC(rb, &c, nrow * sizeof(uint16_t));
+        RB3_ALLOC(bad, &c, sizeof(int32_t));
+        RB3_HIP(hipMemcpyAsync(bb.p, blocks, nblocks * RLE_WORDS * sizeof(uint64_t), hipMemcpyHostToDevice,
+                               c.stream));
+        RB3_HIP(hipMemcpyAsync(sb.p, segs, (nseg + 1) * 8 * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+        RB3_HIP(hipMemcpyAsync(rb.p, row, nrow * sizeof(uint16_t), hipMemcpyHostToDevice, c.stream));
+        RB3_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), c.stream));
+        r->blk = (uint64_t *)bb.release();
+        r->seg = (int64_t *)sb.release();
+        r->row = (uint16_t *)rb.release();
+        RB3_TRY(rle_check(c, r->view(), bad.as<int32_t>()));
+        int32_t hbad = 0;
+        RB3_TRY(read_flag(c, bad.as<int32_t>(), &hbad));
+        if (hbad) return fail(RB3_EINVAL, "run-length index: blocks or index row fail the format checks");
+        return RB3_OK;
+    }();
+    rc = finish(c, rc);
+    if (rc != RB3_OK) {
+        rb3_rle_free(r);
+        return rc;
+    }
+    *out = r;
+    return RB3_OK;
+}
+
+int rb3_rle_info(const rb3_rle *r, int64_t *n, int64_t *m, int64_t *runs, int64_t *blocks, int32_t *row_shift,
+                 int64_t *bytes) {
+    if (!r) return fail(RB3_EINVAL, "run-length index is NULL");
+    if (n) *n = r->n;
+    if (m) *m = r->m;
+    if (runs) *runs = r->npieces;
+    if (blocks) *blocks = r->nblk;
+    if (row_shift) *row_shift = r->q;
+    if (bytes)
+        *bytes = r->nblk * RLE_WORDS * 8 + (r->nseg + 1) * 8 * 8 + ((((r->n - 1) >> r->q) + 1) * 2);
+    return RB3_OK;
+}
+
+int rb3_rle_image(const rb3_rle *r, uint64_t *blocks, int64_t *segs, uint16_t *row) {
+    if (!r || !blocks || !segs || !row) return fail(RB3_EINVAL, "NULL argument");
+    RB3_HIP(hipSetDevice(r->ctx.device));
+    Ctx c = rle_ctx(r);
+    int rc = [&]() -> int {
+        RB3_HIP(hipMemcpyAsync(blocks, r->blk, r->nblk * RLE_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                               c.stream));
+        RB3_HIP(hipMemcpyAsync(segs, r->seg, (r->nseg + 1) * 8 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                               c.stream));
+        RB3_HIP(hipMemcpyAsync(row, r->row, ((((r->n - 1) >> r->q) + 1) * sizeof(uint16_t)), hipMemcpyDeviceToHost,
+                               c.stream));
+        return RB3_OK;
+    }();
+    return finish(c, rc);
+}
+
+int rb3_rle_export(const rb3_rle *r, uint8_t *codes) {
+    if (!r || !codes) return fail(RB3_EINVAL, "NULL argument");
+    RB3_HIP(hipSetDevice(r->ctx.device));
+    Ctx c = rle_ctx(r);
+    int rc = [&]() -> int {
+        DBuf dc;
+        RB3_ALLOC(dc, &c, r->n);
+        RB3_TRY(rle_decode_all(c, r->view(), dc.as<uint8_t>()));
+        RB3_HIP(hipMemcpyAsync(codes, dc.p, r->n, hipMemcpyDeviceToHost, c.stream));
+        return RB3_OK;
+    }();
+    return finish(c, rc);
+}
+
+int rb3_rle_count(const rb3_rle *r, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem, int64_t *lo,
+                  int64_t *hi) {
+    if (!r) return fail(RB3_EINVAL, "run-length index is NULL");
+    if (n_q > 0 && (!lo || !hi)) return fail(RB3_EINVAL, "output arrays are NULL");
+    int64_t total = 0;
+    RB3_TRY(check_strings(q, qlens, n_q, mem, true, &total));
+    if (n_q == 0) return RB3_OK;
+    RB3_HIP(hipSetDevice(r->ctx.device));
+    Ctx c = rle_ctx(r);
+    const RleView v = r->view();
+    int rc = run_count(c, DevIndex{}, q, qlens, n_q, total, mem, lo, hi, &v);
+    return finish(c, rc);
+}
+
+int rb3_rle_smem(const rb3_rle *r, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
+                 int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off) {
+    if (!r) return fail(RB3_EINVAL, "run-length index is NULL");
+    if (!out_off) return fail(RB3_EINVAL, "out_off is NULL");
+    if (min_len < 1 || min_occ < 1) return fail(RB3_EINVAL, "min_len and min_occ must be >= 1");
+    if (out_cap < 0 || (out_cap > 0 && !out)) return fail(RB3_EINVAL, "bad output buffer");
+    if (!r->both) return fail(RB3_EINVAL, "SMEM finding needs an index of both strands");
+    if (n_q >= (int64_t)INT32_MAX) return fail(RB3_ELIMIT, "too many queries");
+    int64_t total = 0;
+    RB3_TRY(check_strings(q, qlens, n_q, mem, true, &total));
+    out_off[0] = 0;
+    if (n_q == 0) return RB3_OK;
+    RB3_HIP(hipSetDevice(r->ctx.device));
+    Ctx c = rle_ctx(r);
+    const RleView v = r->view();
+    int64_t exts[2] = {0, 0};
+    int rc = run_smem(c, DevIndex{}, q, qlens, n_q, total, mem, min_len, min_occ, out, out_cap, out_off, exts, &v);
+    if (rc == RB3_OK) {
+        g_last_smem_exts[0] = exts[0];
+        g_last_smem_exts[1] = exts[1];
+    }
+    return finish(c, rc);
 }
 
 }  // extern "C"

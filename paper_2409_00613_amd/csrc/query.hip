@@ -1,29 +1,79 @@
 // Queries on the device-resident BWT: backward-search counts (Sec. 2.3) and
 // SMEM finding (Sec. 2.6, Algorithm 4) over SA bi-interval extensions on the
 // double-strand BWT (Sec. 2.5, Algorithm 3).
-#include "rb3_internal.h"
+#include "rle.h"
 
 #include <vector>
 
 namespace rb3 {
 
-// [lo, hi) of each query. The search runs over the whole query even after
-// the interval empties, because lo of the full query is part of the answer.
-__global__ void k_count(DevIndex ix, const uint8_t *__restrict__ q, const int64_t *__restrict__ qoff,
-                        int64_t nq, int64_t *__restrict__ lo_out, int64_t *__restrict__ hi_out) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= nq) return;
-    int64_t a0 = qoff[i], a1 = qoff[i + 1];
-    int64_t lo = 0, hi = ix.n;
-    for (int64_t t = a1 - 1; t >= a0; --t) {
+// The queries run over either index form through a view: the 3-bit-plane
+// index (one 64-byte block per rank) or the run-length static one (one
+// 128-byte block per rank, decoded up to the position).
+struct PlainView {
+    DevIndex ix;
+    __host__ __device__ int64_t size() const { return ix.n; }
+    // one backward-search step of both ends for symbol a
+    __device__ __forceinline__ void step(int a, int64_t &lo, int64_t &hi) const {
         // the symbol and both ends' blocks are requested together (the
         // second block read is the first one again when they share it)
-        const int a = q[t];
         const Block Bl = load_block(ix.blk, lo >> BLK_SHIFT);
         const Block Bh = load_block(ix.blk, hi >> BLK_SHIFT);
         lo = pi_from_block(ix, Bl, a, lo);
         hi = pi_from_block(ix, Bh, a, hi);
     }
+    __device__ __forceinline__ void pi2(int64_t k0, int64_t k1, int64_t o0[6], int64_t o1[6]) const {
+        pi_all2(ix, k0, k1, o0, o1);
+    }
+    // distinct index blocks that rank-all at k0 and k1 reads
+    __device__ __forceinline__ uint64_t units(int64_t k0, int64_t k1) const {
+        return 1 + ((k0 >> BLK_SHIFT) != (k1 >> BLK_SHIFT));
+    }
+};
+
+// o[a] as a sum of masked terms: a select chain over a register array is
+// turned into an indexed load from scratch memory by the compiler.
+__device__ __forceinline__ int64_t pick6(const int64_t o[6], int a) {
+    int64_t r = 0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) r += o[c] & -(int64_t)(a == c);
+    return r;
+}
+
+struct RleQView {
+    RleView v;
+    __host__ __device__ int64_t size() const { return v.n; }
+    __device__ __forceinline__ void pi2(int64_t k0, int64_t k1, int64_t o0[6], int64_t o1[6]) const {
+        rle_occ_all(v, k0, o0);
+        rle_occ_all(v, k1, o1);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            o0[c] += v.C[c];
+            o1[c] += v.C[c];
+        }
+    }
+    __device__ __forceinline__ void step(int a, int64_t &lo, int64_t &hi) const {
+        int64_t o0[6], o1[6];
+        pi2(lo, hi, o0, o1);
+        lo = pick6(o0, a);
+        hi = pick6(o1, a);
+    }
+    // 128-byte blocks decoded (ends at a segment start or at n read none)
+    __device__ __forceinline__ uint64_t units(int64_t k0, int64_t k1) const {
+        return (uint64_t)((k0 & (RLE_SEG - 1)) != 0 && k0 < v.n) + (uint64_t)((k1 & (RLE_SEG - 1)) != 0 && k1 < v.n);
+    }
+};
+
+// [lo, hi) of each query. The search runs over the whole query even after
+// the interval empties, because lo of the full query is part of the answer.
+template <class V>
+__global__ void k_count(V ix, const uint8_t *__restrict__ q, const int64_t *__restrict__ qoff, int64_t nq,
+                        int64_t *__restrict__ lo_out, int64_t *__restrict__ hi_out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    int64_t a0 = qoff[i], a1 = qoff[i + 1];
+    int64_t lo = 0, hi = ix.size();
+    for (int64_t t = a1 - 1; t >= a0; --t) ix.step(q[t], lo, hi);
     lo_out[i] = lo;
     hi_out[i] = hi;
 }
@@ -31,8 +81,16 @@ __global__ void k_count(DevIndex ix, const uint8_t *__restrict__ q, const int64_
 int count_queries(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *d_qoff, int64_t nq,
                   int64_t *d_lo, int64_t *d_hi) {
     if (nq == 0) return RB3_OK;
-    RB3_LAUNCH("count", k_count, grid_for(nq, 256, 1 << 30), dim3(256), 0, c.stream, ix, d_q, d_qoff, nq,
-               d_lo, d_hi);
+    RB3_LAUNCH("count", k_count<PlainView>, grid_for(nq, 256, 1 << 30), dim3(256), 0, c.stream, PlainView{ix},
+               d_q, d_qoff, nq, d_lo, d_hi);
+    return RB3_OK;
+}
+
+int count_queries_rle(Ctx &c, const RleView &v, const uint8_t *d_q, const int64_t *d_qoff, int64_t nq,
+                      int64_t *d_lo, int64_t *d_hi) {
+    if (nq == 0) return RB3_OK;
+    RB3_LAUNCH("count_rle", k_count<RleQView>, grid_for(nq, 256, 1 << 30), dim3(256), 0, c.stream, RleQView{v},
+               d_q, d_qoff, nq, d_lo, d_hi);
     return RB3_OK;
 }
 
@@ -47,9 +105,10 @@ struct BiInt {
 __device__ __forceinline__ int comp_sym(int c) { return (c == 0 || c == 5) ? c : 5 - c; }
 
 // Algorithm 3, BackwardExt: the bi-interval of aP from that of P.
-__device__ __forceinline__ BiInt backward_ext(const DevIndex &ix, const BiInt &x, int a) {
+template <class V>
+__device__ __forceinline__ BiInt backward_ext(const V &ix, const BiInt &x, int a) {
     int64_t p0[6], p1[6];
-    pi_all2(ix, x.k, x.k + x.s, p0, p1);
+    ix.pi2(x.k, x.k + x.s, p0, p1);
     BiInt r;
     int64_t kr = x.kr;
     int abar = comp_sym(a);
@@ -97,7 +156,8 @@ constexpr int SMEM_WG = 256;
 // One lane per segment, persistent. Each turn of the loop every busy lane
 // performs one extension (two rank-all block reads); a lane that finishes
 // its segment takes the next one from a shared queue.
-__global__ void __launch_bounds__(SMEM_WG) k_smem_seg(DevIndex ix, const uint8_t *__restrict__ q,
+template <class V>
+__global__ void __launch_bounds__(SMEM_WG) k_smem_seg(V ix, const uint8_t *__restrict__ q,
                                                       const Seg *__restrict__ segs, int64_t nseg, int32_t ell,
                                                       int64_t smin, uint32_t *__restrict__ qhead,
                                                       rb3_smem_t *__restrict__ tmp, int64_t cap,
@@ -106,7 +166,7 @@ __global__ void __launch_bounds__(SMEM_WG) k_smem_seg(DevIndex ix, const uint8_t
                                                       int64_t *__restrict__ seglast,
                                                       unsigned long long *__restrict__ exts) {
     const int lane = threadIdx.x & 63;
-    const BiInt empty = {0, 0, ix.n};
+    const BiInt empty = {0, 0, ix.size()};
     bool busy = false, exhausted = false;
     int64_t g = 0;
     const uint8_t *P = q;
@@ -167,8 +227,8 @@ __global__ void __launch_bounds__(SMEM_WG) k_smem_seg(DevIndex ix, const uint8_t
             const BiInt z = backward_ext(ix, in, fwd ? comp_sym(a) : a);
             y = fwd ? BiInt{z.kr, z.k, z.s} : z;
             ++nexts;
-            // distinct index blocks the extension read (rank-all at k and k + s)
-            nblks += 1 + ((in.k >> BLK_SHIFT) != ((in.k + in.s) >> BLK_SHIFT));
+            // index blocks the extension read (rank-all at k and k + s)
+            nblks += ix.units(in.k, in.k + in.s);
         }
         if (busy && !done) {
             if (phase == PH_BACK1) {
@@ -318,9 +378,10 @@ __global__ void k_smem_order(const rb3_smem_t *__restrict__ tmp, int64_t total, 
     }
 }
 
-int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlens, int64_t nq, int32_t min_len,
-             int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
-             int64_t *h_exts) {
+template <class V>
+static int smem_run_v(Ctx &c, const V &ix, const char *kname, const uint8_t *d_q, const int64_t *qlens, int64_t nq,
+                      int32_t min_len, int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off,
+                      int64_t *h_kept, int64_t *h_exts) {
     // segment table: segments short enough that the batch fills the GPU
     // with lanes. Each segment repeats some work at its start (the first
     // min_len-symbol check, and the tail of an SMEM begun in the segment
@@ -335,7 +396,7 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
     if (c.smem_seg_fixed > 0) {
         S = c.smem_seg_fixed;
     } else if (c.smem_seg_fixed == 0) {
-        const int64_t t = tuned_smem_segment(c.device, ix.n, bases, nq);
+        const int64_t t = tuned_smem_segment(c.device, ix.size(), bases, nq);
         if (t > 0) S = t;
     }
     std::vector<Seg> segs;
@@ -386,7 +447,7 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
     if (nseg > 0) {
         int64_t wgs = (nseg + SMEM_WG - 1) / SMEM_WG;
         if (wgs > 2048) wgs = 2048;
-        RB3_LAUNCH("smem", k_smem_seg, dim3((unsigned)wgs), dim3(SMEM_WG), 0, c.stream, ix, d_q,
+        RB3_LAUNCH(kname, k_smem_seg<V>, dim3((unsigned)wgs), dim3(SMEM_WG), 0, c.stream, ix, d_q,
                    d_segs.as<Seg>(), nseg, min_len, min_occ, qh.as<uint32_t>(), d_tmp, cap,
                    tot.as<unsigned long long>(), cnt.as<uint32_t>(), first.as<int64_t>(), last.as<int64_t>(),
                    ext.as<unsigned long long>());
@@ -410,6 +471,20 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
         RB3_LAUNCH("smem_order", k_smem_order, grid_for((int64_t)htot, 256 * 4), dim3(256), 0, c.stream, d_tmp,
                    (int64_t)htot, d_segs.as<Seg>(), segoff.as<uint32_t>(), drop.as<uint32_t>(), d_out);
     return RB3_OK;
+}
+
+int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlens, int64_t nq, int32_t min_len,
+             int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
+             int64_t *h_exts) {
+    return smem_run_v(c, PlainView{ix}, "smem", d_q, qlens, nq, min_len, min_occ, out_cap, d_out, d_out_off, h_kept,
+                      h_exts);
+}
+
+int smem_run_rle(Ctx &c, const RleView &v, const uint8_t *d_q, const int64_t *qlens, int64_t nq, int32_t min_len,
+                 int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
+                 int64_t *h_exts) {
+    return smem_run_v(c, RleQView{v}, "smem_rle", d_q, qlens, nq, min_len, min_occ, out_cap, d_out, d_out_off,
+                      h_kept, h_exts);
 }
 
 }  // namespace rb3

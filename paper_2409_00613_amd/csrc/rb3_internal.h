@@ -499,12 +499,14 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
              int64_t *h_exts);
 
 // api.cpp: one synchronous count / SMEM call on a context's stream (the
-// caller flushes the context afterwards). total = sum of qlens.
+// caller flushes the context afterwards). total = sum of qlens. With rle
+// set the call runs on that run-length index instead of ix.
+struct RleView;
 int run_count(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
-              int32_t mem, int64_t *lo, int64_t *hi);
+              int32_t mem, int64_t *lo, int64_t *hi, const RleView *rle = nullptr);
 int run_smem(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
              int32_t mem, int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off,
-             int64_t *exts);
+             int64_t *exts, const RleView *rle = nullptr);
 // tune.cpp: the autotuner's table (see rb3_tune_merge / rb3_tune_smem).
 std::string merge_tune_key(int dev, int64_t n1, int64_t n2, int64_t m2);
 std::string smem_tune_key(int dev, int64_t n, int64_t bases, int64_t nq);

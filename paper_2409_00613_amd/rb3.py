@@ -50,6 +50,8 @@ EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_count_no
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
            "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats", "rb3_test_fail_merge_after",
            "rb3_tune_merge", "rb3_tune_smem",
+           "rb3_rle_build", "rb3_rle_load", "rb3_rle_info", "rb3_rle_image", "rb3_rle_export", "rb3_rle_count",
+           "rb3_rle_smem", "rb3_rle_free",
            "rb3_server_opts_init", "rb3_server_create", "rb3_server_submit", "rb3_server_poll",
            "rb3_server_stats", "rb3_server_replay", "rb3_server_free"]
 
@@ -123,6 +125,21 @@ def lib():
     _dp0 = ctypes.POINTER(ctypes.c_double)
     L.rb3_tune_merge.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p, _dp0, _i64, _i64p]
     L.rb3_tune_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, _i64p, _i64p, _dp0, _i64, _i64p]
+    _u64p_ = ctypes.POINTER(ctypes.c_uint64)
+    _u16p_ = ctypes.POINTER(ctypes.c_uint16)
+    L.rb3_rle_build.argtypes = [_vp, _i32, ctypes.POINTER(_vp)]
+    L.rb3_rle_load.argtypes = [ctypes.POINTER(Opts), _u64p_, _i64, _i64p, _u16p_, _i64, _i32, _i32,
+                               ctypes.POINTER(_vp)]
+    L.rb3_rle_info.argtypes = [_vp, _i64p, _i64p, _i64p, _i64p, ctypes.POINTER(ctypes.c_int32), _i64p]
+    L.rb3_rle_image.argtypes = [_vp, _u64p_, _i64p, _u16p_]
+    L.rb3_rle_export.argtypes = [_vp, _vp]
+    L.rb3_rle_count.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p]
+    L.rb3_rle_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, ctypes.POINTER(SmemRec), _i64, _i64p]
+    L.rb3_rle_free.argtypes = [_vp]
+    L.rb3_rle_free.restype = None
+    for name in ("rb3_rle_build", "rb3_rle_load", "rb3_rle_info", "rb3_rle_image", "rb3_rle_export",
+                 "rb3_rle_count", "rb3_rle_smem"):
+        getattr(L, name).restype = ctypes.c_int
     L.rb3_server_opts_init.argtypes = [ctypes.POINTER(ServerOpts)]
     L.rb3_server_opts_init.restype = None
     L.rb3_server_create.argtypes = [_vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
@@ -360,6 +377,105 @@ def rb3_smem(idx: Index, q, qlens, min_len: int, min_occ: int = 1, cap: int | No
             continue
         _check(rc)
         return out[:off[-1]], off
+
+
+class Rle:
+    """An rb3_rle handle: the run-length static index (counts and SMEMs like
+    Index, no merges)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().rb3_rle_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self) -> dict:
+        n, m, runs, blocks, nbytes = (ctypes.c_int64() for _ in range(5))
+        q = ctypes.c_int32()
+        _check(lib().rb3_rle_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(runs),
+                                  ctypes.byref(blocks), ctypes.byref(q), ctypes.byref(nbytes)))
+        return {"n": n.value, "m": m.value, "runs": runs.value, "blocks": blocks.value, "row_shift": q.value,
+                "bytes": nbytes.value}
+
+    def image(self):
+        """(blocks [nblocks, 16] uint64, segs [nseg + 1, 8] int64, row uint16)."""
+        i = self.info()
+        n, q = i["n"], i["row_shift"]
+        blocks = np.zeros((i["blocks"], 16), np.uint64)
+        segs = np.zeros((((n + (1 << 20) - 1) >> 20) + 1, 8), np.int64)
+        row = np.zeros(((n - 1) >> q) + 1, np.uint16)
+        _check(lib().rb3_rle_image(self._h, blocks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                   segs.ctypes.data_as(_i64p), row.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))))
+        return blocks, segs, row
+
+    def export(self) -> np.ndarray:
+        n = self.info()["n"]
+        out = np.zeros(n, np.uint8)
+        _check(lib().rb3_rle_export(self._h, out.ctypes.data))
+        return out
+
+    def count(self, q, qlens):
+        ptr, _, mem, keep = _buffer(q)
+        la, lp = _lens(qlens)
+        n = la.shape[0]
+        lo = np.zeros(max(n, 1), np.int64)
+        hi = np.zeros(max(n, 1), np.int64)
+        _check(lib().rb3_rle_count(self._h, ptr, lp, n, mem, lo.ctypes.data_as(_i64p), hi.ctypes.data_as(_i64p)))
+        return lo[:n], hi[:n]
+
+    def smem(self, q, qlens, min_len: int, min_occ: int = 1, cap: int | None = None):
+        ptr, _, mem, keep = _buffer(q)
+        la, lp = _lens(qlens)
+        n = la.shape[0]
+        if cap is None:
+            cap = max(1024, int(la.sum()) // 48 + 16 * n)
+        while True:
+            out = np.zeros(max(cap, 1), dtype=SMEM_DTYPE)
+            off = np.zeros(n + 1, np.int64)
+            rc = lib().rb3_rle_smem(self._h, ptr, lp, n, mem, int(min_len), int(min_occ),
+                                    out.ctypes.data_as(ctypes.POINTER(SmemRec)), cap, off.ctypes.data_as(_i64p))
+            if rc == RB3_ENOSPC:
+                cap = int(off[-1])
+                continue
+            _check(rc)
+            return out[:off[-1]], off
+
+
+def rb3_rle_build(idx: Index, row_shift: int = 0) -> Rle:
+    h = _vp()
+    _check(lib().rb3_rle_build(idx.handle, int(row_shift), ctypes.byref(h)))
+    return Rle(h.value)
+
+
+def rb3_rle_load(blocks, segs, row, n: int, row_shift: int, both_strands: bool = True, device: int = 0) -> Rle:
+    blocks = np.ascontiguousarray(blocks, dtype=np.uint64)
+    segs = np.ascontiguousarray(segs, dtype=np.int64)
+    row = np.ascontiguousarray(row, dtype=np.uint16)
+    o = make_opts(both_strands=both_strands, device=device)
+    h = _vp()
+    _check(lib().rb3_rle_load(ctypes.byref(o), blocks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                              blocks.shape[0], segs.ctypes.data_as(_i64p),
+                              row.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)), int(n), int(row_shift),
+                              1 if both_strands else 0, ctypes.byref(h)))
+    return Rle(h.value)
 
 
 def _i64out(n, mem, like):

@@ -160,6 +160,28 @@ def test_reduced_index_counts_and_locate1(reduced):
         assert np.array_equal(codes[a:a + L], pc[pstart[s]:pstart[s] + L]), f"Locate1 of SMEM {s}"
 
 
+def test_reduced_index_run_length_form(reduced):
+    idx, codes, lens, Q, qc, ql = reduced
+    say("case: reduced serving index in the run-length static form: image, counts, SMEMs vs the seeded scan")
+    B = idx.export()
+    r = rb3.rb3_rle_build(idx)
+    info = r.info()
+    blocks, segs, row = r.image()
+    want = oracle.rle_encode(B, info["row_shift"])
+    assert np.array_equal(blocks, want.blocks) and np.array_equal(segs, want.seg) and np.array_equal(row, want.row)
+    say(f"  {info['n']} symbols, {info['runs']} runs, {info['blocks']} blocks, {info['bytes'] / info['n']:.3f} B/symbol")
+    g = np.random.default_rng(17)
+    pos = np.concatenate([g.integers(0, B.shape[0] + 1, 20000), np.arange(0, B.shape[0], 1 << 20)])
+    cum = [np.concatenate([[0], np.cumsum(B == c)]) for c in range(6)]
+    assert np.array_equal(oracle.rle_rank(want, pos), np.stack([cum[c][pos] for c in range(6)], 1))
+    # SMEMs on the run-length form against the oracle's seeded scan
+    _compare_smems(r, Q, qc, ql, codes, lens, 31, 1, "run-length form, min_occ 1")
+    lo, hi = r.count(Q.data, Q.lens)
+    plo, phi = idx.count(Q.data, Q.lens)
+    assert np.array_equal(lo, plo) and np.array_equal(hi, phi)
+    r.close()
+
+
 def test_merge_past_2_32_symbols():
     say("case: merge past 2^32 symbols: 22 haplotypes of the 100 Mb genome as 8 + 7 + 7")
     import torch
