@@ -224,10 +224,11 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
     config = {"workload": "serving", "genome_len": genome, "haplotypes_indexed": n_index,
               "both_strands": True, "n": n, "queries": n_queries, "query_bases": bases,
               "min_len": min_len, "min_occ": 1, "query_lengths": "log-uniform 100-100000"}
+    rle = rle_bench(idx, n, qdev, w.queries.lens, min_len, bases, steps, recs, off)
     if batched_only:
         idx.close()
         return {"metric": "SMEM query bases/s", "value": round(batched, 1), "unit": "bases/s",
-                "config": config, "roofline": roof, "tuning": tuning}
+                "config": config, "roofline": roof, "tuning": tuning, "run_length": rle}
     # plain form: one query per call
     k = min(plain_queries, n_queries)
     pq = w.queries.slice(0, k)
@@ -259,7 +260,47 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
     idx.close()
     return {"metric": "SMEM query bases/s", "value": round(batched, 1), "unit": "bases/s",
             "plain_one_query_per_call": round(plain, 1), "served": served, "server": st,
-            "config": config, "roofline": roof, "tuning": tuning}
+            "config": config, "roofline": roof, "tuning": tuning, "run_length": rle}
+
+
+def rle_bench(idx, n, qdev, qlens, min_len, bases, steps, want_recs, want_off):
+    """The same index in the run-length static form: its size against the
+    3-bit-plane form, the build time, and the batched SMEM rate on it (the
+    records must equal the plane index's)."""
+    from paper_2409_00613_amd import rb3
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = rb3.rb3_rle_build(idx)
+    build_s = time.perf_counter() - t
+    info = r.info()
+    plain_bytes = ((n >> 7) + 1) * 64 + ((n >> 24) + 1) * 64
+    recs, off = r.smem(qdev, qlens, min_len)  # warm-up, and the parity check
+    same = bool(np.array_equal(recs, want_recs) and np.array_equal(off, want_off))
+    rb3.rb3_prof_reset()
+    rb3.rb3_prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.smem(qdev, qlens, min_len)
+    t1 = time.perf_counter()
+    rb3.rb3_prof_enable(False)
+    prof = rb3.rb3_prof_read()
+    sst = rb3.rb3_last_smem_stats()
+    k_ms = prof.get("smem_rle", (0, 0.0))[1] / steps
+    rate = bases * steps / (t1 - t0)
+    blk = sst["blocks"] * 128
+    out = {"bytes": info["bytes"], "bytes_per_symbol": round(info["bytes"] / n, 4),
+           "plane_form_bytes": plain_bytes, "compression": round(plain_bytes / info["bytes"], 2),
+           "runs": info["runs"], "mean_run": round(n / max(info["runs"], 1), 2), "blocks": info["blocks"],
+           "row_shift": info["row_shift"], "build_s": round(build_s, 3),
+           "smem_bases_per_s": round(rate, 1), "smem_kernel_ms": round(k_ms, 3),
+           "blocks_decoded": sst["blocks"], "block_GB_per_s": round(blk / (k_ms / 1e3) / 1e9, 1) if k_ms else None,
+           "smem_equal_to_plane_form": same}
+    log(f"run-length form: {info['bytes'] / 1e9:.3f} GB ({out['bytes_per_symbol']} B/symbol, "
+        f"{out['compression']}x smaller than the plane form), {info['runs']} runs, built in {build_s:.2f} s; "
+        f"SMEM {rate / 1e9:.3f} G bases/s (kernel {k_ms:.2f} ms), records equal: {same}")
+    r.close()
+    return out
 
 
 def timed_merges(b1, new, steps: int, warmup: int):

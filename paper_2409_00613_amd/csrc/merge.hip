@@ -22,7 +22,9 @@
 //      symbols): those groups are ordered by comparing the following
 //      symbols, by kernels chosen by group size (k_tie_*), and only groups
 //      of more than 8192 members fall back to prefix doubling on the key
-//      sequence (k_gather / k_rerank). Sentinel suffixes are unique and sort
+//      sequence (k_gather, then k_rerank by direct counting within groups of
+//      up to 2048 members, or a radix sort of the active records by (group,
+//      key) when a group is larger). Sentinel suffixes are unique and sort
 //      by strand index.
 //   3. Interleave (k_interleave): the s-th new suffix in sorted order lands
 //      on merged row l_s + s, its BWT symbol being the symbol before it; the
@@ -75,6 +77,9 @@ __device__ __forceinline__ uint32_t win_byte(uint64_t w0, uint64_t w1, int x) {
 }
 
 constexpr int CH_GROUP = 8;       // steps per group (keys written out per group)
+// prefix-doubling rounds whose largest group is at most this large rank by
+// direct counting; larger ones sort the active records
+constexpr uint32_t TIE_RERANK_DIRECT = 2048;
 constexpr int CH_WG = 256;        // threads per workgroup of the chain kernel
 constexpr int CH_SB_LDS_MAX = 640;  // superblocks whose rows fit in LDS (5 int64 each)
 
@@ -635,11 +640,51 @@ __global__ void k_rerank(const uint32_t *__restrict__ apos, const uint32_t *__re
     }
 }
 
+// The same refinement for rounds with large groups, in linear work: the
+// active records sorted stably by (group start, rank h further on) land
+// exactly where k_rerank puts them (group start + smaller keys + equal keys
+// before), so each sorted slot s reads its record from SV2[s] and its run of
+// equal keys from the run's first slot (rstart, a max-scan of run heads).
+__global__ void k_rr_keys(const uint32_t *__restrict__ ags, const uint32_t *__restrict__ key2, int64_t A, int kbits,
+                          uint64_t *__restrict__ K2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A; i += (int64_t)gridDim.x * blockDim.x)
+        K2[i] = ((uint64_t)ags[i] << kbits) | (uint64_t)key2[i];
+}
+
+__global__ void k_rr_heads(const uint64_t *__restrict__ SK2, int64_t A, uint32_t *__restrict__ hs) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < A; s += (int64_t)gridDim.x * blockDim.x)
+        hs[s] = (s == 0 || SK2[s] != SK2[s - 1]) ? (uint32_t)s : 0u;
+}
+
+__global__ void k_rr_apply(const uint64_t *__restrict__ SK2, const uint32_t *__restrict__ SV2,
+                           const uint32_t *__restrict__ rstart, int64_t A, int kbits,
+                           const uint32_t *__restrict__ apos, const uint32_t *__restrict__ ahead,
+                           uint32_t *__restrict__ R, uint32_t *__restrict__ tpos, uint32_t *__restrict__ thead,
+                           uint32_t *__restrict__ tkeep, uint32_t *__restrict__ tsub, uint32_t *__restrict__ teq,
+                           int32_t *__restrict__ guard) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < A; s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = SV2[s], r0 = rstart[s];
+        const uint32_t gs = (uint32_t)(SK2[s] >> kbits);
+        if ((int64_t)i >= A || r0 > (uint32_t)s || r0 < gs) {
+            atomicOr(guard, GUARD_RERANK);
+            continue;
+        }
+        const uint32_t nh = ahead[i] + (r0 - gs);
+        R[apos[i]] = nh;
+        tpos[s] = apos[i];
+        thead[s] = nh;
+        tsub[s] = (uint32_t)s - r0;
+        const bool tail = s + 1 == A || SK2[s + 1] != SK2[s];
+        tkeep[s] = ((uint32_t)s > r0 || !tail) ? 1u : 0u;
+        if (tail) teq[r0] = (uint32_t)s - r0 + 1u;  // read at the run's first slot
+    }
+}
+
 __global__ void k_compact(const uint32_t *__restrict__ tpos, const uint32_t *__restrict__ thead,
                           const uint32_t *__restrict__ tkeep, const uint32_t *__restrict__ tsub,
                           const uint32_t *__restrict__ teq, const uint32_t *__restrict__ nidx, int64_t A,
                           uint32_t *__restrict__ apos, uint32_t *__restrict__ ahead,
-                          uint32_t *__restrict__ ags, uint32_t *__restrict__ agsz,
+                          uint32_t *__restrict__ ags, uint32_t *__restrict__ agsz, uint32_t *__restrict__ maxg,
                           int32_t *__restrict__ guard) {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < A;
          s += (int64_t)gridDim.x * blockDim.x) {
@@ -652,7 +697,10 @@ __global__ void k_compact(const uint32_t *__restrict__ tpos, const uint32_t *__r
         apos[ni] = tpos[s];
         ahead[ni] = thead[s];
         ags[ni] = ni - tsub[s];
-        if (tsub[s] == 0) agsz[ni] = teq[s];
+        if (tsub[s] == 0) {
+            agsz[ni] = teq[s];
+            atomicMax(maxg, teq[s]);
+        }
     }
 }
 
@@ -2428,35 +2476,64 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                        ahead[0].as<uint32_t>(), ags[0].as<uint32_t>(), agsz[0].as<uint32_t>(), d_tot + 1);
             RB3_HIP(hipMemcpyAsync(h_cnt, cnt.p, sizeof(h_cnt), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipStreamSynchronize(c.stream));
-            if (h_cnt[1] > 65536) {
-                set_error(RB3_ELIMIT, "a group of more than 65536 new suffixes shares its sort key "
-                                      "(highly repetitive batch)");
-                return RB3_ELIMIT;
-            }
+            uint32_t maxg = h_cnt[1];
             head.reset();
             tied.reset();
             idx.reset();
             int cur = 0;
             int64_t h = w;
             int rounds = 0;
+            // rank bits of the keys h further on (ranks are below n2)
+            int kbits = 1;
+            while (kbits < 32 && ((int64_t)1 << kbits) < n2) ++kbits;
             while (A > 0) {
                 dim3 ga = grid_for(A, 256 * 4);
                 RB3_LAUNCH("tie_gather", k_gather, ga, dim3(256), 0, c.stream, apos[cur].as<uint32_t>(), A,
                            R.as<uint32_t>(), h, n2, key2.as<uint32_t>(), guard);
-                RB3_LAUNCH("tie_rerank", k_rerank, ga, dim3(256), 0, c.stream, apos[cur].as<uint32_t>(),
-                           ahead[cur].as<uint32_t>(), ags[cur].as<uint32_t>(), agsz[cur].as<uint32_t>(),
-                           key2.as<uint32_t>(), A, R.as<uint32_t>(), tpos.as<uint32_t>(),
-                           thead.as<uint32_t>(), tkeep.as<uint32_t>(), tsub.as<uint32_t>(), teq.as<uint32_t>(), guard);
+                if (maxg <= TIE_RERANK_DIRECT) {
+                    // every member counts the keys of its group: work A * group size
+                    RB3_LAUNCH("tie_rerank", k_rerank, ga, dim3(256), 0, c.stream, apos[cur].as<uint32_t>(),
+                               ahead[cur].as<uint32_t>(), ags[cur].as<uint32_t>(), agsz[cur].as<uint32_t>(),
+                               key2.as<uint32_t>(), A, R.as<uint32_t>(), tpos.as<uint32_t>(), thead.as<uint32_t>(),
+                               tkeep.as<uint32_t>(), tsub.as<uint32_t>(), teq.as<uint32_t>(), guard);
+                } else {
+                    // large groups (long runs of one symbol, many identical
+                    // strings): sort the active records by (group start, key)
+                    int abits = 1;
+                    while (abits < 32 && ((int64_t)1 << abits) < A) ++abits;
+                    DBuf k2, ka2, kb2, va2, vb2, hs;
+                    RB3_ALLOC(k2, &c, A * sizeof(uint64_t));
+                    RB3_ALLOC(ka2, &c, A * sizeof(uint64_t));
+                    RB3_ALLOC(kb2, &c, A * sizeof(uint64_t));
+                    RB3_ALLOC(va2, &c, A * sizeof(uint32_t));
+                    RB3_ALLOC(vb2, &c, A * sizeof(uint32_t));
+                    RB3_ALLOC(hs, &c, A * sizeof(uint32_t));
+                    RB3_LAUNCH("tie_rr_keys", k_rr_keys, ga, dim3(256), 0, c.stream, ags[cur].as<uint32_t>(),
+                               key2.as<uint32_t>(), A, kbits, k2.as<uint64_t>());
+                    uint64_t *SK2 = nullptr;
+                    uint32_t *SV2 = nullptr;
+                    RB3_TRY(radix_sort(c, k2.as<uint64_t>(), nullptr, ka2.as<uint64_t>(), va2.as<uint32_t>(),
+                                       kb2.as<uint64_t>(), vb2.as<uint32_t>(), A, 0, kbits + abits, true, &SK2, &SV2,
+                                       guard, nullptr));
+                    RB3_LAUNCH("tie_rr_heads", k_rr_heads, ga, dim3(256), 0, c.stream, SK2, A, hs.as<uint32_t>());
+                    RB3_TRY(scan_u32(c, hs.as<uint32_t>(), hs.as<uint32_t>(), A, true, true, nullptr));
+                    RB3_LAUNCH("tie_rr_apply", k_rr_apply, ga, dim3(256), 0, c.stream, SK2, SV2, hs.as<uint32_t>(), A,
+                               kbits, apos[cur].as<uint32_t>(), ahead[cur].as<uint32_t>(), R.as<uint32_t>(),
+                               tpos.as<uint32_t>(), thead.as<uint32_t>(), tkeep.as<uint32_t>(), tsub.as<uint32_t>(),
+                               teq.as<uint32_t>(), guard);
+                }
                 RB3_TRY(scan_u32(c, tkeep.as<uint32_t>(), nidx.as<uint32_t>(), A, false, false, d_tot));
                 int nx = cur ^ 1;
+                RB3_HIP(hipMemsetAsync(d_tot + 1, 0, sizeof(uint32_t), c.stream));
                 RB3_LAUNCH("tie_compact", k_compact, ga, dim3(256), 0, c.stream, tpos.as<uint32_t>(),
                            thead.as<uint32_t>(), tkeep.as<uint32_t>(), tsub.as<uint32_t>(), teq.as<uint32_t>(),
                            nidx.as<uint32_t>(), A, apos[nx].as<uint32_t>(), ahead[nx].as<uint32_t>(),
-                           ags[nx].as<uint32_t>(), agsz[nx].as<uint32_t>(), guard);
-                RB3_HIP(hipMemcpyAsync(h_cnt, cnt.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
+                           ags[nx].as<uint32_t>(), agsz[nx].as<uint32_t>(), d_tot + 1, guard);
+                RB3_HIP(hipMemcpyAsync(h_cnt, cnt.p, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, c.stream));
                 RB3_HIP(hipStreamSynchronize(c.stream));
                 st.tie_work += A;
                 A = h_cnt[0];
+                maxg = h_cnt[1];
                 cur = nx;
                 h *= 2;
                 ++rounds;

@@ -116,3 +116,42 @@ def test_batch_limit_is_rejected_before_reading():
     assert e.value.code == rb3.RB3_ELIMIT
     assert np.array_equal(idx.export(), before)
     idx.close()
+
+
+def test_run_of_n_longer_than_65536_merges():
+    """A 70,000-symbol run of N in a new string: its suffixes share the
+    insertion rank and the key for up to 70,000 symbols, so one tie group of
+    about 70,000 members goes through the prefix-doubling rounds."""
+    say("case: a string with a 70,000-base run of N merged into a small index (inverse-BWT check)")
+    g = np.random.default_rng(70000)
+    acgt = np.frombuffer(b"ACGT", np.uint8)
+    flank = [acgt[g.integers(0, 4, 1500)].tobytes() for _ in range(3)]
+    old = synth.pack([flank[0] + flank[1], flank[2]])
+    new = synth.pack([flank[1][:700] + b"N" * 70000 + flank[2][:900], acgt[g.integers(0, 4, 400)].tobytes()])
+    idx = rb3.rb3_build(old.data, old.lens)
+    idx.merge(new.data, new.lens)
+    st = idx.merge_stats()
+    assert st["tie_doubling"] == 1 and st["max_group"] >= 65536, st
+    B = idx.export()
+    allst = synth.pack([old.get(i) for i in range(old.n)] + [new.get(i) for i in range(new.n)])
+    codes, lens = oracle.expand(allst.data, allst.lens)
+    assert B.shape[0] == codes.shape[0] + lens.shape[0]
+    assert oracle.verify(B, codes, lens) == 0
+    idx.close()
+
+
+def test_70000_identical_reads_merge():
+    """70,000 copies of one 25-base read (and its reverse complement): tie
+    groups of 70,000 members at every offset, ordered in the end by the
+    strands' sentinels."""
+    say("case: 70,000 identical 25-base reads merged into an index holding the read once")
+    read = b"ACGTTGCAAGGCTTACCGATAGCAT"
+    old = synth.pack([b"GGGTACCA" + read + b"TTTAC", b"CCATG"])
+    new = synth.pack([read] * 70000)
+    idx = rb3.rb3_build(old.data, old.lens)
+    idx.merge(new.data, new.lens)
+    st = idx.merge_stats()
+    assert st["tie_doubling"] == 1 and st["max_group"] >= 65536, st
+    allst = synth.pack([old.get(i) for i in range(old.n)] + [read] * 70000)
+    assert np.array_equal(idx.export(), _bwt(allst))
+    idx.close()
