@@ -823,10 +823,10 @@ def main():
         torch.cuda.empty_cache()
     incremental = None
     if workload == "pangenome_merge" and not args.no_incremental:
-        r = incremental_bench(args)
-        incremental = {"value": r["value"], "unit": r["unit"], "config": r["config"], "batches": r["batches"],
-                       "total_merge_s": r["total_merge_s"], "peak_hbm_allocated_bytes": r["peak_hbm_allocated_bytes"],
-                       "device_free_min_bytes": r["device_free_min_bytes"]}
+        ri = incremental_bench(args)
+        incremental = {"value": ri["value"], "unit": ri["unit"], "config": ri["config"], "batches": ri["batches"],
+                       "total_merge_s": ri["total_merge_s"], "peak_hbm_allocated_bytes": ri["peak_hbm_allocated_bytes"],
+                       "device_free_min_bytes": ri["device_free_min_bytes"]}
         torch.cuda.empty_cache()
 
     out = {

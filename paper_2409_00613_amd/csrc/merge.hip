@@ -2348,7 +2348,9 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 RB3_HIP(hipMemsetAsync(qh.p, 0, 2 * sizeof(uint32_t), c.stream));
             }
             // main: 9..64 members; side 1: up to 8 (and their deep part),
-            // then 129..256; side 2: 257..8192, then 65..128
+            // then 129..256, then 65..128; side 2: 257..8192 (one workgroup
+            // a group, the longest-running class on batches with long
+            // repeats, so it runs alone)
             TieStreams ts(c.stream);
             RB3_TRY(ts.fork(c.device));
             // the block counts' scan runs beside the side streams' first kernels
@@ -2400,16 +2402,6 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                                dl.as<uint32_t>(), qh.as<uint32_t>() + 1, SK, PF, srate, guard,
                                gdeep.as<unsigned long long>());
             }
-            if (hs2[3] > 0) {
-                if (samples)
-                    RB3_LAUNCH("tie_walk128", (k_tie_walk<2, true>), grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
-                               ts.s[2], Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
-                               gtied.as<unsigned long long>() + 3);
-                else
-                    RB3_LAUNCH("tie_walk128", (k_tie_walk<2, false>), grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
-                               ts.s[2], Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
-                               gtied.as<unsigned long long>() + 3);
-            }
             if (hs2[4] > 0) {
                 if (samples)
                     RB3_LAUNCH("tie_walk256", (k_tie_walk<4, true>), grid_for(hs2[4], 4 * 8, 1 << 20), dim3(256), 0,
@@ -2418,6 +2410,16 @@ int merge_into(Ctx &c, IndexData &ix, const uint8_t *d_Q, const int64_t *strand_
                 else
                     RB3_LAUNCH("tie_walk256", (k_tie_walk<4, false>), grid_for(hs2[4], 4 * 8, 1 << 20), dim3(256), 0,
                                ts.s[1], Qc, n2, SV, tl.l[4], (int64_t)hs2[4], SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 3);
+            }
+            if (hs2[3] > 0) {
+                if (samples)
+                    RB3_LAUNCH("tie_walk128", (k_tie_walk<2, true>), grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
+                               ts.s[1], Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
+                               gtied.as<unsigned long long>() + 3);
+                else
+                    RB3_LAUNCH("tie_walk128", (k_tie_walk<2, false>), grid_for(hs2[3], 4 * 8, 1 << 20), dim3(256), 0,
+                               ts.s[1], Qc, n2, SV, tl.l[3], (int64_t)hs2[3], SK, PF, srate, guard,
                                gtied.as<unsigned long long>() + 3);
             }
             RB3_TRY(ts.join());
