@@ -166,11 +166,33 @@ __global__ void __launch_bounds__(CH_WG) k_chain(DevIndex ix, const uint8_t *__r
     const uint64_t *Qw = (const uint64_t *)Q;
     int32_t unresolved = 0, nwide = 0;
     int64_t wide = 0;
+    // Each step's block (and the symbol words of each group) is requested at
+    // the end of the step before it, so the next group's first loads go out
+    // before this group's keys are written: a wait for a load also waits for
+    // every store issued before it (one counter covers both on this GPU).
+    auto group_words = [&](int32_t t0, uint64_t &w0, uint64_t &w1, int64_t &wb) {
+        const int64_t P = p1 - 1 - t0;
+        wb = (t0 < len ? (P - CH_GROUP > 0 ? P - CH_GROUP : 0) : 0) >> 3;
+        w0 = Qw[wb];
+        w1 = Qw[wb + 1];
+    };
+    // (B1 keeps its old contents when only one block is read: the step
+    // selects B0 then, and copying B0 would wait for its load)
+    auto step_blocks = [&](bool act, Block &B0, Block &B1) {
+        const int64_t x0 = act ? (point ? l : lo) : 0;
+        B0 = load_block(ix.blk, x0 >> BLK_SHIFT);
+        if (act && !point) B1 = load_block(ix.blk, hi >> BLK_SHIFT);
+    };
+    uint64_t nw0, nw1;
+    int64_t nwb;
+    Block NB0, NB1 = {};
+    group_words(0, nw0, nw1, nwb);
+    step_blocks(0 < len, NB0, NB1);
     for (int32_t t0 = 0; __ballot(t0 < len) != 0; t0 += CH_GROUP) {
         // positions P .. P - 7 of this group need the symbols Q[P - 8 .. P]
         const int64_t P = p1 - 1 - t0;
-        const int64_t wb = (t0 < len ? (P - CH_GROUP > 0 ? P - CH_GROUP : 0) : 0) >> 3;
-        const uint64_t w0 = Qw[wb], w1 = Qw[wb + 1];
+        const uint64_t w0 = nw0, w1 = nw1;
+        const int64_t wb = nwb;
         uint64_t kslot[CH_GROUP], rslot[CH_GROUP];
         int nrec = 0;
 #pragma clang loop unroll(full)
@@ -187,9 +209,8 @@ __global__ void __launch_bounds__(CH_WG) k_chain(DevIndex ix, const uint8_t *__r
             const bool two = act && !point;
             const int64_t x1 = two ? hi : x0;
             const int64_t b0 = x0 >> BLK_SHIFT, b1 = x1 >> BLK_SHIFT;
-            const Block B0 = load_block(ix.blk, b0);
-            Block B1 = B0;
-            if (two) B1 = load_block(ix.blk, b1);
+            const Block B0 = NB0;
+            const Block B1 = two ? NB1 : NB0;
             int64_t s0, s1;
             if (SB_LDS) {
                 s0 = sb_lds[(x0 >> SB_SHIFT) * 5 + (a - 1)];
@@ -198,7 +219,6 @@ __global__ void __launch_bounds__(CH_WG) k_chain(DevIndex ix, const uint8_t *__r
                 s0 = ix.sb[(x0 >> SB_SHIFT) * SB_STRIDE + a];
                 s1 = two ? ix.sb[(x1 >> SB_SHIFT) * SB_STRIDE + a] : s0;
             }
-            __builtin_amdgcn_sched_barrier(0);
             const int64_t n0 = s0 + (int64_t)ckpt_field(B0.q3, (int)a - 1) +
                                inblock_count(B0, (int)a, (int)(x0 & (BLK_SYMS - 1)));
             const int64_t n1 = two ? s1 + (int64_t)ckpt_field(B1.q3, (int)a - 1) +
@@ -226,7 +246,15 @@ __global__ void __launch_bounds__(CH_WG) k_chain(DevIndex ix, const uint8_t *__r
                     hi = n1;
                 }
             }
+            // the next step's loads
+            if (s + 1 < CH_GROUP) {
+                step_blocks(t0 + s + 1 < len, NB0, NB1);
+            } else {
+                group_words(t0 + CH_GROUP, nw0, nw1, nwb);
+                step_blocks(t0 + CH_GROUP < len, NB0, NB1);
+            }
         }
+        __builtin_amdgcn_sched_barrier(0);
         const int nkey = len - t0 < 0 ? 0 : (len - t0 > CH_GROUP ? CH_GROUP : len - t0);
         wave_write_group(buf, kslot, P, nkey, K);
         if (__ballot(nrec > 0) != 0) wave_write_group(buf, rslot, P, nrec, M);
