@@ -24,6 +24,10 @@ Functions (each follows a definition of arXiv 2409.00613):
   locate      the suffix-array entry of a row written as (string index,
               offset within the string) (Sec. 2.4)
   rows_of     the inverse: the row of the suffix at (string index, offset)
+  Text.hapl   local haplotype enumeration (Sec. 2.8): semi-global alignment
+              of a query to the prefix DAWG by the revised BWA-SW recurrences
+              (Sec. 2.7, Algorithm 5) and the bi-interval redundancy filter
+              (``hapl.c`` holds the readings)
   rle_encode / rle_decode / rle_rank / delta_code
               the run-length static format (Sec. 2.2, Fig. 2b): blocks of
               Elias-delta coded runs with marginal counts and an index row,
@@ -38,7 +42,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "rle.c")]
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "rle.c"), os.path.join(_HERE, "hapl.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -47,7 +51,7 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c and rle.c into liboracle.so with gcc."""
+    """Compile oracle.c, rle.c and hapl.c into liboracle.so with gcc."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-std=c99",
@@ -108,6 +112,9 @@ def _load():
     lib.orc_rle_rank.argtypes = [_u64p, _i64p, _u16p, ctypes.c_int64, ctypes.c_int, _i64p, ctypes.c_int64,
                                  _i64p]
     lib.orc_rle_rank.restype = ctypes.c_int
+    lib.orc_hapl.argtypes = [ctypes.c_void_p, _i64p, ctypes.c_int64, _u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int64, _i64p, ctypes.c_int]
+    lib.orc_hapl.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -351,6 +358,30 @@ class Text:
             if k <= cap:
                 return out[:k]
             cap = int(k)
+
+
+def _text_hapl(self, P: np.ndarray, match: int = 1, mismatch: int = 4, gap_open: int = 6, gap_ext: int = 1,
+               band: int = 25, raw: bool = False) -> np.ndarray:
+    """Local haplotype enumeration of one query (codes 1..5): rows of
+    (k, k_rc, s, score), ordered by decreasing score; raw=True gives every
+    cell of the query's start before the redundancy filter."""
+    P = np.ascontiguousarray(P, dtype=np.uint8)
+    pp = P if P.size else np.zeros(1, np.uint8)
+    cap = 256
+    while True:
+        out = np.zeros((cap, 5), np.int64)
+        nraw = np.zeros(1, np.int64)
+        k = _lib.orc_hapl(self._h, _p(self.S, _i64p), self.n, _p(pp, _u8p), P.shape[0], int(match),
+                          int(mismatch), int(gap_open), int(gap_ext), int(band), _p(out, _i64p), cap,
+                          _p(nraw, _i64p), 1 if raw else 0)
+        if k < 0:
+            raise MemoryError("oracle hapl: allocation failed")
+        if k <= cap:
+            return out[:k, :4]
+        cap = int(k)
+
+
+Text.hapl = _text_hapl
 
 
 def insertion_ranks(S: np.ndarray, lens: np.ndarray, m1: int) -> np.ndarray:
