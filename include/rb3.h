@@ -191,6 +191,56 @@ int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64
 int rb3_last_smem_stats(int64_t *extensions, int64_t *blocks);
 
 /*
+ * Local haplotype enumeration (Sec. 2.7-2.8, Algorithm 5): each query P is
+ * aligned end to end (semi-globally) to the prefix DAWG of the index under
+ * affine gaps, walking P from its end to its start. A DAWG node is the SA
+ * bi-interval (k, krc, s) of a string; its children are its non-empty
+ * backward extensions by A, C, G, T (Algorithm 3). At each query position
+ * the cells come from the previous position's cells by a match or mismatch
+ * to a child (score match, or -mismatch; a query N mismatches every symbol)
+ * and by an insertion (same node), then from the position's own cells by
+ * deletions to children, repeated until no cell improves; a gap of length L
+ * costs gap_open + L * gap_ext. Cells with score <= 0 are dropped and, with
+ * band W > 0, only the W best cells are kept (ties: smaller k, then smaller
+ * s). The start cell (query end, the whole index) has score 0. The result is
+ * the cells left at the query's start, by decreasing score (same ties),
+ * without those whose [k, k+s) or [krc, krc+s) lies inside the same
+ * interval of a result before them.
+ */
+typedef struct rb3_hapl_opts {
+    int32_t match;     /* score of a match, 1 .. 2^20 (default 1) */
+    int32_t mismatch;  /* mismatch penalty, 0 .. 2^20 (default 4) */
+    int32_t gap_open;  /* 0 .. 2^20 (default 6) */
+    int32_t gap_ext;   /* 1 .. 2^20 (default 1) */
+    int32_t band;      /* W, cells kept per query position; 0 keeps all (default 25) */
+    int32_t max_cells; /* cells one query position may hold before the band, 1 .. 65535 (default 4096) */
+} rb3_hapl_opts;
+
+void rb3_hapl_opts_init(rb3_hapl_opts *o);
+
+/* One result: the bi-interval (k, krc, s) and the alignment score. */
+typedef struct rb3_hapl_t {
+    int64_t k, krc, s;
+    int32_t score;
+    int32_t qid;
+} rb3_hapl_t;
+
+/*
+ * rb3_hapl: the enumeration above for n_q queries (q, qlens, mem as in
+ * rb3_count; o NULL = defaults). Results for query i are out[out_off[i] ..
+ * out_off[i+1]) in result order; out (host, out_cap entries) and out_off
+ * (host, n_q + 1) are caller buffers. RB3_ENOSPC when out_cap is too small
+ * (out_off filled, so the caller can size a retry); RB3_ELIMIT when a query
+ * needs more than max_cells cells at one position, or match times a
+ * query's length reaches 2^29; RB3_EINVAL on options out of range or an
+ * index without both strands. Device memory: about 2 * max_cells * 48 +
+ * 8 * max_cells bytes per query in flight, at most 4 GiB (queries run in
+ * chunks).
+ */
+int rb3_hapl(const rb3_index *idx, const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q,
+             int32_t mem, rb3_hapl_t *out, int64_t out_cap, int64_t *out_off);
+
+/*
  * rb3_locate: position of the suffix at each row (Sec. 2.4): strand[i] is
  * the index of the strand holding row rows[i]'s suffix in the index's list
  * (strands numbered in the order they were added, both strands counted) and
@@ -312,6 +362,10 @@ int rb3_rle_count(const rb3_rle *r, const uint8_t *q, const int64_t *qlens, int6
                   int64_t *hi);
 int rb3_rle_smem(const rb3_rle *r, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
                  int32_t min_len, int64_t min_occ, rb3_smem_t *out, int64_t out_cap, int64_t *out_off);
+
+/* rb3_hapl on the run-length index: same arguments, rules and results. */
+int rb3_rle_hapl(const rb3_rle *r, const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q,
+                 int32_t mem, rb3_hapl_t *out, int64_t out_cap, int64_t *out_off);
 
 void rb3_rle_free(rb3_rle *r);
 

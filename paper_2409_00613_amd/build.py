@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librb3.so")
 
-SOURCES = ["index.hip", "scan.hip", "sort.hip", "chunks.hip", "merge.hip", "query.hip", "locate.hip", "noalloc.hip", "rle.hip", "api.cpp", "tune.cpp", "server.cpp"]
+SOURCES = ["index.hip", "scan.hip", "sort.hip", "chunks.hip", "merge.hip", "query.hip", "locate.hip", "noalloc.hip", "rle.hip", "hapl.hip", "api.cpp", "tune.cpp", "server.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

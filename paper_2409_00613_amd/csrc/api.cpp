@@ -412,6 +412,54 @@ int run_smem(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens,
     return RB3_OK;
 }
 
+// Options in range, and match times every query length below 2^29 so that
+// no score can overflow.
+static int check_hapl(const rb3_hapl_opts &o, const int64_t *qlens, int64_t n_q) {
+    const int32_t lim = 1 << 20;
+    if (o.match < 1 || o.match > lim || o.mismatch < 0 || o.mismatch > lim || o.gap_open < 0 || o.gap_open > lim ||
+        o.gap_ext < 1 || o.gap_ext > lim)
+        return fail(RB3_EINVAL, "scores out of range");
+    if (o.band < 0) return fail(RB3_EINVAL, "band must be >= 0");
+    if (o.max_cells < 1 || o.max_cells > 65535) return fail(RB3_EINVAL, "max_cells must be in 1 .. 65535");
+    for (int64_t i = 0; i < n_q; ++i)
+        if (qlens[i] * (int64_t)o.match >= ((int64_t)1 << 29))
+            return fail(RB3_ELIMIT, "match score times query length reaches 2^29");
+    return RB3_OK;
+}
+
+int run_hapl(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens, int64_t n_q, int64_t total,
+             int32_t mem, const rb3_hapl_opts &o, rb3_hapl_t *out, int64_t out_cap, int64_t *out_off,
+             const RleView *rle) {
+    DBuf hold, codes, err, recs;
+    const uint8_t *d_q = nullptr;
+    RB3_TRY(stage(c, q, total, mem, hold, &d_q));
+    RB3_ALLOC(codes, &c, total > 0 ? total : 1);
+    RB3_ALLOC(err, &c, sizeof(int32_t));
+    RB3_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), c.stream));
+    RB3_TRY(encode_plain(c, d_q, qlens, n_q, codes.as<uint8_t>(), total, err.as<int32_t>()));
+    int32_t bad = 0;
+    RB3_TRY(read_flag(c, err.as<int32_t>(), &bad));
+    if (bad) return fail(RB3_EINVAL, "byte outside ACGTNacgtn in a query");
+    hold.reset();
+    RB3_ALLOC(recs, &c, (out_cap > 0 ? out_cap : 1) * sizeof(rb3_hapl_t));
+    int64_t badq = -1;
+    const int rc = hapl_run(c, ix, rle, codes.as<uint8_t>(), qlens, n_q, o, out_cap, recs.as<rb3_hapl_t>(), out_off,
+                            &badq);
+    if (rc != RB3_OK) {
+        if (badq >= 0) {
+            const std::string m = "query " + std::to_string(badq) + " needs more than max_cells (" +
+                                  std::to_string(o.max_cells) + ") cells at one position";
+            return fail(rc, m.c_str());
+        }
+        return rc;
+    }
+    const int64_t kept = out_off[n_q];
+    if (kept > out_cap) return fail(RB3_ENOSPC, "haplotype output buffer too small; out_off holds the sizes");
+    if (kept > 0) RB3_HIP(hipMemcpyAsync(out, recs.p, kept * sizeof(rb3_hapl_t), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipStreamSynchronize(c.stream));
+    return RB3_OK;
+}
+
 const DevIndex index_dev(const rb3_index *idx) { return idx->d.dev(); }
 int index_device(const rb3_index *idx) { return idx->d.ctx.device; }
 hipStream_t index_stream(const rb3_index *idx) { return idx->d.ctx.stream; }
@@ -521,6 +569,47 @@ int rb3_smem(const rb3_index *idx, const uint8_t *q, const int64_t *qlens, int64
         g_last_smem_exts[0] = exts[0];
         g_last_smem_exts[1] = exts[1];
     }
+    return finish(c, rc);
+}
+
+void rb3_hapl_opts_init(rb3_hapl_opts *o) {
+    if (!o) return;
+    o->match = 1;
+    o->mismatch = 4;
+    o->gap_open = 6;
+    o->gap_ext = 1;
+    o->band = 25;
+    o->max_cells = 4096;
+}
+
+// The checks shared by both index forms; *o_out = the options to use.
+static int hapl_args(const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
+                     rb3_hapl_t *out, int64_t out_cap, int64_t *out_off, int32_t both, rb3_hapl_opts *o_out,
+                     int64_t *total) {
+    if (!out_off) return fail(RB3_EINVAL, "out_off is NULL");
+    if (out_cap < 0 || (out_cap > 0 && !out)) return fail(RB3_EINVAL, "bad output buffer");
+    if (!both) return fail(RB3_EINVAL, "haplotype enumeration needs an index of both strands");
+    if (n_q >= (int64_t)INT32_MAX) return fail(RB3_ELIMIT, "too many queries");
+    if (o)
+        *o_out = *o;
+    else
+        rb3_hapl_opts_init(o_out);
+    RB3_TRY(check_strings(q, qlens, n_q, mem, true, total));
+    RB3_TRY(check_hapl(*o_out, qlens, n_q));
+    out_off[0] = 0;
+    return RB3_OK;
+}
+
+int rb3_hapl(const rb3_index *idx, const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q,
+             int32_t mem, rb3_hapl_t *out, int64_t out_cap, int64_t *out_off) {
+    if (!idx) return fail(RB3_EINVAL, "index is NULL");
+    rb3_hapl_opts oo;
+    int64_t total = 0;
+    RB3_TRY(hapl_args(o, q, qlens, n_q, mem, out, out_cap, out_off, idx->d.ctx.both, &oo, &total));
+    if (n_q == 0) return RB3_OK;
+    RB3_HIP(hipSetDevice(idx->d.ctx.device));
+    Ctx c = call_ctx(idx->d);
+    int rc = run_hapl(c, idx->d.dev(), q, qlens, n_q, total, mem, oo, out, out_cap, out_off, nullptr);
     return finish(c, rc);
 }
 
@@ -1197,6 +1286,20 @@ int rb3_rle_smem(const rb3_rle *r, const uint8_t *q, const int64_t *qlens, int64
         g_last_smem_exts[0] = exts[0];
         g_last_smem_exts[1] = exts[1];
     }
+    return finish(c, rc);
+}
+
+int rb3_rle_hapl(const rb3_rle *r, const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q,
+                 int32_t mem, rb3_hapl_t *out, int64_t out_cap, int64_t *out_off) {
+    if (!r) return fail(RB3_EINVAL, "run-length index is NULL");
+    rb3_hapl_opts oo;
+    int64_t total = 0;
+    RB3_TRY(hapl_args(o, q, qlens, n_q, mem, out, out_cap, out_off, r->both, &oo, &total));
+    if (n_q == 0) return RB3_OK;
+    RB3_HIP(hipSetDevice(r->ctx.device));
+    Ctx c = rle_ctx(r);
+    const RleView v = r->view();
+    int rc = run_hapl(c, DevIndex{}, q, qlens, n_q, total, mem, oo, out, out_cap, out_off, &v);
     return finish(c, rc);
 }
 

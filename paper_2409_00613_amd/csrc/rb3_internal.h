@@ -498,6 +498,19 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
              int64_t min_occ, int64_t out_cap, rb3_smem_t *d_out, int64_t *d_out_off, int64_t *h_kept,
              int64_t *h_exts);
 
+// hapl.hip: local haplotype enumeration (Algorithm 5 and the bi-interval
+// filter) of nq queries (codes at d_codes, host lengths qlens) on ix, or on
+// the run-length index when rle is set. Queries run in chunks whose cell
+// tables fit HAPL_SCRATCH bytes. h_off (host, nq + 1) receives the
+// per-query offsets; when everything fits out_cap the records are written
+// in order to d_out. A query that needs more than o.max_cells cells at a
+// position gives RB3_ELIMIT with its index in *h_bad.
+constexpr int64_t HAPL_SCRATCH = (int64_t)4 << 30;
+struct RleView;
+int hapl_run(Ctx &c, const DevIndex &ix, const RleView *rle, const uint8_t *d_codes, const int64_t *qlens,
+             int64_t nq, const rb3_hapl_opts &o, int64_t out_cap, rb3_hapl_t *d_out, int64_t *h_off,
+             int64_t *h_bad);
+
 // api.cpp: one synchronous count / SMEM call on a context's stream (the
 // caller flushes the context afterwards). total = sum of qlens. With rle
 // set the call runs on that run-length index instead of ix.

@@ -44,14 +44,29 @@ SMEM_DTYPE = np.dtype([("start", np.int64), ("end", np.int64), ("occ", np.int64)
                        ("krc", np.int64), ("qid", np.int32), ("pad", np.int32)])
 assert SMEM_DTYPE.itemsize == ctypes.sizeof(SmemRec) == 48
 
+
+class HaplOpts(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap_open", ctypes.c_int32),
+                ("gap_ext", ctypes.c_int32), ("band", ctypes.c_int32), ("max_cells", ctypes.c_int32)]
+
+
+class HaplRec(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("krc", ctypes.c_int64), ("s", ctypes.c_int64),
+                ("score", ctypes.c_int32), ("qid", ctypes.c_int32)]
+
+
+HAPL_DTYPE = np.dtype([("k", np.int64), ("krc", np.int64), ("s", np.int64), ("score", np.int32),
+                       ("qid", np.int32)])
+assert HAPL_DTYPE.itemsize == ctypes.sizeof(HaplRec) == 32
+
 # Every function declared in include/rb3.h.
 EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_count_noalloc", "rb3_smem", "rb3_last_smem_stats",
            "rb3_locate", "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info",
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
            "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats", "rb3_test_fail_merge_after",
-           "rb3_tune_merge", "rb3_tune_smem",
+           "rb3_tune_merge", "rb3_tune_smem", "rb3_hapl_opts_init", "rb3_hapl",
            "rb3_rle_build", "rb3_rle_load", "rb3_rle_info", "rb3_rle_image", "rb3_rle_export", "rb3_rle_count",
-           "rb3_rle_smem", "rb3_rle_free",
+           "rb3_rle_smem", "rb3_rle_hapl", "rb3_rle_free",
            "rb3_server_opts_init", "rb3_server_create", "rb3_server_submit", "rb3_server_poll",
            "rb3_server_stats", "rb3_server_replay", "rb3_server_free"]
 
@@ -105,6 +120,11 @@ def lib():
     L.rb3_count_noalloc.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p]
     L.rb3_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, ctypes.POINTER(SmemRec), _i64, _i64p]
     L.rb3_info.argtypes = [_vp, _i64p, _i64p, _i64p]
+    L.rb3_hapl_opts_init.argtypes = [ctypes.POINTER(HaplOpts)]
+    L.rb3_hapl_opts_init.restype = None
+    L.rb3_hapl.argtypes = [_vp, ctypes.POINTER(HaplOpts), _vp, _i64p, _i64, _i32, ctypes.POINTER(HaplRec), _i64,
+                           _i64p]
+    L.rb3_hapl.restype = ctypes.c_int
     L.rb3_last_smem_stats.argtypes = [_i64p, _i64p]
     L.rb3_locate.argtypes = [_vp, _vp, _i64, _i32, _i64p, _i64p]
     L.rb3_locate1.argtypes = [_vp, _vp, _vp, _i64, _i32, _i64p, _i64p]
@@ -135,10 +155,12 @@ def lib():
     L.rb3_rle_export.argtypes = [_vp, _vp]
     L.rb3_rle_count.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i64p, _i64p]
     L.rb3_rle_smem.argtypes = [_vp, _vp, _i64p, _i64, _i32, _i32, _i64, ctypes.POINTER(SmemRec), _i64, _i64p]
+    L.rb3_rle_hapl.argtypes = [_vp, ctypes.POINTER(HaplOpts), _vp, _i64p, _i64, _i32, ctypes.POINTER(HaplRec),
+                               _i64, _i64p]
     L.rb3_rle_free.argtypes = [_vp]
     L.rb3_rle_free.restype = None
     for name in ("rb3_rle_build", "rb3_rle_load", "rb3_rle_info", "rb3_rle_image", "rb3_rle_export",
-                 "rb3_rle_count", "rb3_rle_smem"):
+                 "rb3_rle_count", "rb3_rle_smem", "rb3_rle_hapl"):
         getattr(L, name).restype = ctypes.c_int
     L.rb3_server_opts_init.argtypes = [ctypes.POINTER(ServerOpts)]
     L.rb3_server_opts_init.restype = None
@@ -295,6 +317,9 @@ class Index:
     def smem(self, q, qlens, min_len: int, min_occ: int = 1, cap: int | None = None):
         return rb3_smem(self, q, qlens, min_len, min_occ, cap)
 
+    def hapl(self, q, qlens, **kw):
+        return rb3_hapl(self, q, qlens, **kw)
+
     def info(self):
         return rb3_info(self)
 
@@ -379,6 +404,42 @@ def rb3_smem(idx: Index, q, qlens, min_len: int, min_occ: int = 1, cap: int | No
         return out[:off[-1]], off
 
 
+def hapl_opts(match: int = 1, mismatch: int = 4, gap_open: int = 6, gap_ext: int = 1, band: int = 25,
+              max_cells: int = 4096) -> HaplOpts:
+    o = HaplOpts()
+    lib().rb3_hapl_opts_init(ctypes.byref(o))
+    o.match, o.mismatch, o.gap_open, o.gap_ext = int(match), int(mismatch), int(gap_open), int(gap_ext)
+    o.band, o.max_cells = int(band), int(max_cells)
+    return o
+
+
+def _hapl_call(fn, handle, q, qlens, cap, kw):
+    ptr, _, mem, keep = _buffer(q)
+    la, lp = _lens(qlens)
+    n = la.shape[0]
+    o = hapl_opts(**kw)
+    if cap is None:
+        cap = max(1024, 8 * n)
+    while True:
+        out = np.zeros(max(cap, 1), dtype=HAPL_DTYPE)
+        off = np.zeros(n + 1, np.int64)
+        rc = fn(handle, ctypes.byref(o), ptr, lp, n, mem, out.ctypes.data_as(ctypes.POINTER(HaplRec)), cap,
+                off.ctypes.data_as(_i64p))
+        if rc == RB3_ENOSPC:
+            cap = int(off[-1])
+            continue
+        _check(rc)
+        return out[:off[-1]], off
+
+
+def rb3_hapl(idx: Index, q, qlens, cap: int | None = None, **kw):
+    """Local haplotype enumeration. Keyword options: match, mismatch,
+    gap_open, gap_ext, band, max_cells. Returns (records, offsets): records
+    is a structured array (HAPL_DTYPE); query i owns
+    records[offsets[i]:offsets[i+1]]."""
+    return _hapl_call(lib().rb3_hapl, idx.handle, q, qlens, cap, kw)
+
+
 class Rle:
     """An rb3_rle handle: the run-length static index (counts and SMEMs like
     Index, no merges)."""
@@ -457,6 +518,9 @@ class Rle:
                 continue
             _check(rc)
             return out[:off[-1]], off
+
+    def hapl(self, q, qlens, cap: int | None = None, **kw):
+        return _hapl_call(lib().rb3_rle_hapl, self._h, q, qlens, cap, kw)
 
 
 def rb3_rle_build(idx: Index, row_shift: int = 0) -> Rle:

@@ -1,0 +1,222 @@
+"""GPU parity of local haplotype enumeration (Sec. 2.7-2.8, Algorithm 5 and
+the bi-interval filter) through the C ABI: every result (bi-interval and
+score, in order) against the oracle on small pangenome indices, with and
+without a band, on both index forms; at larger sizes the properties that
+hold at any size; and the argument checks."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2409_00613_amd import rb3
+
+pytestmark = pytest.mark.gpu
+
+ENC = np.zeros(256, np.uint8)
+for _i, _c in enumerate(b"ACGTN"):
+    ENC[_c] = _i + 1
+    ENC[_c | 0x20] = _i + 1
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _reads(w, k, lmin, lmax, sub=0.02, indel=0.002, stream=0):
+    qs = []
+    for j in range(k):
+        g = synth.rng(synth.SEED, synth.STREAM_QUERY + stream + j)
+        src = w.new.get(j % w.new.n)
+        L = int(g.integers(lmin, lmax + 1))
+        s = int(g.integers(0, len(src) - L))
+        qs.append(bytes(synth.mutate(np.frombuffer(src[s:s + L], np.uint8), sub, indel, g)))
+    return qs
+
+
+def _compare(text, qs, recs, off, **kw):
+    assert off.shape[0] == len(qs) + 1
+    for i, q in enumerate(qs):
+        want = text.hapl(ENC[np.frombuffer(q, np.uint8)], **kw)
+        got = recs[off[i]:off[i + 1]]
+        assert [tuple(int(v) for v in x) for x in want] == \
+            [(int(a["k"]), int(a["krc"]), int(a["s"]), int(a["score"])) for a in got], (i, q)
+        assert np.all(got["qid"] == i)
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.config_pangenome(genome_len=3000, n_b1=6, n_new=2)
+    codes, lens = oracle.expand(w.b1.data, w.b1.lens)
+    idx = rb3.rb3_build(w.b1.data, w.b1.lens)
+    text = oracle.Text(codes, lens)
+    yield w, idx, text, codes
+    idx.close()
+
+
+@pytest.mark.parametrize("band", [25, 10, 1])
+def test_hapl_matches_oracle_banded(small, band):
+    say(f"case: haplotype enumeration, 3 kb x 6 haplotypes, reads 8-100 bp, band {band}")
+    w, idx, text, codes = small
+    qs = _reads(w, 120, 8, 100)
+    # exact substrings of indexed haplotypes, reads with N, the empty query
+    g = np.random.default_rng(band)
+    letters = np.frombuffer(b"$ACGTN", np.uint8)
+    for _ in range(20):
+        L = int(g.integers(1, 60))
+        s = int(g.integers(0, 3000 - L))
+        qs.append(w.b1.get(int(g.integers(0, w.b1.n)))[s:s + L])
+    qs.append(b"")
+    qs.append(b"N" * 5)
+    q = bytearray(w.new.get(1)[100:160])
+    q[30] = ord("N")
+    qs.append(bytes(q))
+    qs.append(letters[codes[500:540]].tobytes())
+    P = synth.pack(qs)
+    recs, off = idx.hapl(P.data, P.lens, band=band)
+    _compare(text, qs, recs, off, band=band)
+
+
+def test_hapl_matches_oracle_unbanded(small):
+    say("case: haplotype enumeration without a band, reads 4-14 bp")
+    w, idx, text, _ = small
+    qs = _reads(w, 80, 4, 14, stream=5000)
+    P = synth.pack(qs)
+    recs, off = idx.hapl(P.data, P.lens, band=0, max_cells=65535)
+    _compare(text, qs, recs, off, band=0)
+
+
+@pytest.mark.parametrize("scores", [(1, 4, 6, 1), (2, 3, 5, 2), (1, 2, 3, 2), (3, 1, 2, 3)])
+def test_hapl_other_scores(small, scores):
+    m, x, o, e = scores
+    say(f"case: haplotype enumeration with match {m}, mismatch {x}, gap open {o}, gap extension {e}")
+    w, idx, text, _ = small
+    qs = _reads(w, 40, 10, 50, sub=0.04, indel=0.01, stream=9000)
+    P = synth.pack(qs)
+    recs, off = idx.hapl(P.data, P.lens, match=m, mismatch=x, gap_open=o, gap_ext=e, band=25, max_cells=16384)
+    _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=25)
+
+
+def test_hapl_run_length_index_and_output_retry(small):
+    say("case: haplotype enumeration on the run-length index; output sized by a retry")
+    w, idx, text, _ = small
+    qs = _reads(w, 60, 20, 80, stream=12000)
+    P = synth.pack(qs)
+    r = rb3.rb3_rle_build(idx, 0)
+    recs, off = r.hapl(P.data, P.lens, cap=1)
+    precs, poff = idx.hapl(P.data, P.lens)
+    assert np.array_equal(off, poff) and np.array_equal(recs, precs)
+    _compare(text, qs, recs, off, band=25)
+    r.close()
+
+
+def test_hapl_argument_checks(small):
+    say("case: haplotype enumeration argument checks")
+    w, idx, _, _ = small
+    P = synth.pack(_reads(w, 4, 30, 40))
+    for kw in ({"match": 0}, {"gap_ext": 0}, {"mismatch": -1}, {"band": -1}, {"max_cells": 0},
+               {"max_cells": 65536}):
+        with pytest.raises(rb3.RB3Error) as e:
+            idx.hapl(P.data, P.lens, **kw)
+        assert e.value.code == rb3.RB3_EINVAL, kw
+    with pytest.raises(rb3.RB3Error) as e:
+        idx.hapl(P.data, P.lens, max_cells=2)
+    assert e.value.code == rb3.RB3_ELIMIT
+    with pytest.raises(rb3.RB3Error) as e:
+        idx.hapl(b"ACGTX", [5])
+    assert e.value.code == rb3.RB3_EINVAL
+    one = rb3.rb3_build(w.b1.data, w.b1.lens, both_strands=False)
+    with pytest.raises(rb3.RB3Error) as e:
+        one.hapl(P.data, P.lens)
+    assert e.value.code == rb3.RB3_EINVAL
+    one.close()
+    recs, off = idx.hapl(b"", np.zeros(0, np.int64))
+    assert recs.shape[0] == 0 and off.tolist() == [0]
+
+
+def _properties(idx, qs, recs, off, n, exact):
+    """What holds at any size: valid intervals, order by score, no result
+    inside an earlier one, scores at most the query length, and an exact
+    read's best result its own bi-interval with the full score."""
+    for i, q in enumerate(qs):
+        got = recs[off[i]:off[i + 1]]
+        assert np.all(got["s"] > 0) and np.all(got["k"] + got["s"] <= n) and np.all(got["krc"] + got["s"] <= n)
+        sc = got["score"].astype(np.int64)
+        assert np.all(sc > 0) and np.all(sc <= len(q))
+        assert np.all(np.diff(sc) <= 0)
+        for a in range(got.shape[0]):
+            for b in range(a):
+                x, y = got[a], got[b]
+                assert not (y["k"] <= x["k"] and x["k"] + x["s"] <= y["k"] + y["s"])
+                assert not (y["krc"] <= x["krc"] and x["krc"] + x["s"] <= y["krc"] + y["s"])
+    if exact:
+        P = synth.pack(qs)
+        lo, hi = idx.count(P.data, P.lens)
+        comp = bytes.maketrans(b"ACGT", b"TGCA")
+        R = synth.pack([q.translate(comp)[::-1] for q in qs])
+        rlo, _ = idx.count(R.data, R.lens)
+        for i, q in enumerate(qs):
+            top = recs[off[i]]
+            assert (int(top["k"]), int(top["krc"]), int(top["s"]), int(top["score"])) == \
+                (int(lo[i]), int(rlo[i]), int(hi[i] - lo[i]), len(q)), i
+
+
+def test_hapl_bench_shape_properties():
+    say("case: haplotype enumeration of 125 bp reads on 32 haplotypes x 200 kb, band 10: properties")
+    w = synth.config_pangenome(genome_len=200_000, n_b1=32, n_new=4)
+    idx = rb3.rb3_build(w.b1.data, w.b1.lens)
+    n = idx.info()[0]
+    qs = _reads(w, 3000, 125, 125, sub=0.01, indel=0.001, stream=20000)
+    P = synth.pack(qs)
+    recs, off = idx.hapl(P.data, P.lens, band=10)
+    _properties(idx, qs, recs, off, n, exact=False)
+    g = np.random.default_rng(4)
+    ex = []
+    for _ in range(300):
+        h = w.b1.get(int(g.integers(0, w.b1.n)))
+        s = int(g.integers(0, len(h) - 125))
+        ex.append(h[s:s + 125])
+    E = synth.pack(ex)
+    erecs, eoff = idx.hapl(E.data, E.lens, band=10)
+    _properties(idx, ex, erecs, eoff, n, exact=True)
+    idx.close()
+
+
+def test_hapl_125bp_sample_against_oracle():
+    say("case: haplotype enumeration of 125 bp reads on 32 haplotypes x 30 kb, band 10: a sample against the "
+        "oracle")
+    w = synth.config_pangenome(genome_len=30_000, n_b1=32, n_new=4)
+    idx = rb3.rb3_build(w.b1.data, w.b1.lens)
+    qs = _reads(w, 2000, 125, 125, sub=0.01, indel=0.001, stream=30000)
+    P = synth.pack(qs)
+    recs, off = idx.hapl(P.data, P.lens, band=10)
+    _properties(idx, qs, recs, off, idx.info()[0], exact=False)
+    codes, lens = oracle.expand(w.b1.data, w.b1.lens)
+    text = oracle.Text(codes, lens)
+    pick = list(range(0, 2000, 100))
+    _compare(text, [qs[i] for i in pick], *_subset(recs, off, pick), band=10)
+    idx.close()
+
+
+def _subset(recs, off, pick):
+    parts, o = [], [0]
+    for j, i in enumerate(pick):
+        r = recs[off[i]:off[i + 1]].copy()
+        r["qid"] = j
+        parts.append(r)
+        o.append(o[-1] + r.shape[0])
+    return np.concatenate(parts), np.array(o, np.int64)
+
+
+def test_hapl_query_longer_than_65535():
+    say("case: haplotype enumeration of a 70,000 bp exact query (hash generations wrap), band 1")
+    g = np.random.default_rng(11)
+    acgt = np.frombuffer(b"ACGT", np.uint8)
+    s = acgt[g.integers(0, 4, 80_000)].tobytes()
+    idx = rb3.rb3_build(np.frombuffer(s, np.uint8), np.array([len(s)], np.int64))
+    q = s[5000:75_000]
+    # gap extension so costly that no gap cell is ever positive
+    recs, off = idx.hapl(np.frombuffer(q, np.uint8), np.array([len(q)], np.int64), band=1, max_cells=16,
+                         gap_ext=1 << 20)
+    _properties(idx, [q], recs, off, idx.info()[0], exact=True)
+    assert off.tolist() == [0, 1]
+    idx.close()
