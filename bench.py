@@ -225,10 +225,11 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
               "both_strands": True, "n": n, "queries": n_queries, "query_bases": bases,
               "min_len": min_len, "min_occ": 1, "query_lengths": "log-uniform 100-100000"}
     rle = rle_bench(idx, n, qdev, w.queries.lens, min_len, bases, steps, recs, off)
+    hapl = hapl_bench(idx, n, w.queries, n_index, steps)
     if batched_only:
         idx.close()
         return {"metric": "SMEM query bases/s", "value": round(batched, 1), "unit": "bases/s",
-                "config": config, "roofline": roof, "tuning": tuning, "run_length": rle}
+                "config": config, "roofline": roof, "tuning": tuning, "run_length": rle, "hapl": hapl}
     # plain form: one query per call
     k = min(plain_queries, n_queries)
     pq = w.queries.slice(0, k)
@@ -260,7 +261,91 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
     idx.close()
     return {"metric": "SMEM query bases/s", "value": round(batched, 1), "unit": "bases/s",
             "plain_one_query_per_call": round(plain, 1), "served": served, "server": st,
-            "config": config, "roofline": roof, "tuning": tuning, "run_length": rle}
+            "config": config, "roofline": roof, "tuning": tuning, "run_length": rle, "hapl": hapl}
+
+
+def hapl_bench(idx, n, queries, n_index, steps, n_reads=200_000, read_len=125, bands=(10, 25)):
+    """Local haplotype enumeration (revised BWA-SW, semi-global) of short
+    reads on the serving index: n_reads windows of read_len bases cut at
+    seeded offsets from the serving queries (excerpts of unindexed
+    haplotypes with 1% substitutions and 0.1% indels), device-resident, at
+    the paper's bands (10 for short reads, 25 its default). Value: query
+    bases/s of the batched call; the kernel's index-block bytes over its
+    time give the roofline."""
+    from paper_2409_00613_amd import rb3
+    import torch
+    g = np.random.default_rng(17)
+    lens = queries.lens
+    offs = np.concatenate([[0], np.cumsum(lens)])
+    long_ = np.nonzero(lens >= read_len)[0]
+    pick = long_[g.integers(0, long_.shape[0], n_reads)]
+    st = offs[pick] + (g.random(n_reads) * (lens[pick] - read_len + 1)).astype(np.int64)
+    data = queries.data[(st[:, None] + np.arange(read_len)[None, :]).ravel()]
+    qlens = np.full(n_reads, read_len, np.int64)
+    qdev = torch.from_numpy(np.ascontiguousarray(data)).cuda()
+    torch.cuda.synchronize()
+    bases = n_reads * read_len
+    out = {"reads": n_reads, "read_len": read_len, "source": "windows of the serving queries", "bands": {}}
+    for band in bands:
+        idx.hapl(qdev, qlens, band=band)  # warm-up
+        rb3.rb3_prof_reset()
+        rb3.rb3_prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            recs, off = idx.hapl(qdev, qlens, band=band)
+        t1 = time.perf_counter()
+        rb3.rb3_prof_enable(False)
+        prof = rb3.rb3_prof_read()
+        hs = rb3.rb3_last_hapl_stats()
+        # the LDS-table kernel, plus the device-memory one for the queries
+        # that outgrew it
+        k_ms = (prof.get("hapl_wave", (0, 0.0))[1] + prof.get("hapl", (0, 0.0))[1]) / steps
+        rate = bases * steps / (t1 - t0)
+        ab = hs["blocks"] * BLOCK_BYTES
+        ach = ab / (k_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
+        out["bands"][str(band)] = {
+            "bases_per_s": round(rate, 1), "ms_per_call": round((t1 - t0) / steps * 1e3, 3),
+            "kernel_ms": round(k_ms, 3), "results": int(off[-1]),
+            "reads_with_results": int(np.count_nonzero(np.diff(off))),
+            "extensions_per_base": round(hs["extensions"] / bases, 3),
+            "blocks_per_extension": round(hs["blocks"] / max(hs["extensions"], 1), 3),
+            "cells_per_position": round(hs["cells"] / bases, 2),
+            "reads_moved_to_device_tables": hs["moved"],
+            "roofline": {"bound": "hbm", "kernel": "hapl_wave", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "traffic": read_traffic("hapl_wave", f"serving{n_index}_band{band}", kernel_source_hash()),
+                         "algorithmic_bytes_per_launch": ab, "avg_launch_ms": k_ms}}
+        log(f"haplotype enumeration, band {band}: {rate / 1e6:.2f} M bases/s ({n_reads} reads of {read_len}), "
+            f"kernel {k_ms:.1f} ms, {hs['extensions'] / bases:.2f} extensions/base, {int(off[-1])} results")
+    return out
+
+
+def hapl_cpu_baseline(n_reads: int = 40, read_len: int = 125):
+    """The oracle's haplotype enumeration on a bounded sample: reads of the
+    same shape against a 32-haplotype index of a 30 kb genome (the oracle
+    holds a suffix array of the whole text, so the serving index is out of
+    its reach), band 10. Reported as query bases/s."""
+    import oracle
+    import synth
+    w = synth.config_pangenome(genome_len=30_000, n_b1=32, n_new=4)
+    codes, lens = oracle.expand(w.b1.data, w.b1.lens)
+    text = oracle.Text(codes, lens)
+    enc = np.zeros(256, np.uint8)
+    for i, c in enumerate(b"ACGTN"):
+        enc[c] = i + 1
+    g = np.random.default_rng(3)
+    reads = []
+    for j in range(n_reads):
+        src = w.new.get(j % w.new.n)
+        s = int(g.integers(0, len(src) - read_len))
+        reads.append(enc[synth.mutate(np.frombuffer(src[s:s + read_len], np.uint8), 0.01, 0.001, g)])
+    t0 = time.perf_counter()
+    for r in reads:
+        text.hapl(r, band=10)
+    dt = time.perf_counter() - t0
+    return {"value": round(n_reads * read_len / dt, 1), "unit": "bases/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_reads} reads of {read_len} bases (1% substitutions, 0.1% indels) against 32 "
+                      f"haplotypes of a 30 kb genome ({codes.shape[0]} symbols), band 10; {dt:.2f} s"}
 
 
 def rle_bench(idx, n, qdev, qlens, min_len, bases, steps, want_recs, want_off):
@@ -753,6 +838,8 @@ def main():
         sys.exit(1)
     if args.workload == "serving":
         res = smem_bench(10_000_000, 320, 10_000, 500, [0.25, 0.5, 0.8], 10_000)
+        if not args.no_cpu_baseline:
+            res["hapl"]["cpu_baseline"] = hapl_cpu_baseline()
         res.update({"n_gpus": 1, "steps": 2, "warmup": 1, "higher_is_better": True, "scaling": "weak",
                     "vs_baseline": None, "dtype": "int64", "data": "synthetic"})
         print(json.dumps(res), flush=True)
@@ -820,6 +907,8 @@ def main():
         rates = [0.25, 0.5, 0.8] if args.smem_haplotypes >= 320 else [0.5]
         smem = smem_bench(10_000_000, args.smem_haplotypes, 10_000, 200, rates, 10_000,
                           batched_only=args.smem_batched_only)
+        if not args.no_cpu_baseline:
+            smem["hapl"]["cpu_baseline"] = hapl_cpu_baseline()
         torch.cuda.empty_cache()
     incremental = None
     if workload == "pangenome_merge" and not args.no_incremental:

@@ -213,7 +213,10 @@ typedef struct rb3_hapl_opts {
     int32_t gap_open;  /* 0 .. 2^20 (default 6) */
     int32_t gap_ext;   /* 1 .. 2^20 (default 1) */
     int32_t band;      /* W, cells kept per query position; 0 keeps all (default 25) */
-    int32_t max_cells; /* cells one query position may hold before the band, 1 .. 65535 (default 4096) */
+    int32_t max_cells; /* cells one query position may hold before the band, 1 .. 65535; 0 (default):
+                          8 * band + 256 with a band, else 4096 */
+    int32_t device_tables; /* 0 (default): each query's cells in the LDS of one wavefront while they fit
+                              (256 a position), else in device memory; 1: always in device memory */
 } rb3_hapl_opts;
 
 void rb3_hapl_opts_init(rb3_hapl_opts *o);
@@ -233,12 +236,23 @@ typedef struct rb3_hapl_t {
  * (out_off filled, so the caller can size a retry); RB3_ELIMIT when a query
  * needs more than max_cells cells at one position, or match times a
  * query's length reaches 2^29; RB3_EINVAL on options out of range or an
- * index without both strands. Device memory: about 2 * max_cells * 48 +
- * 8 * max_cells bytes per query in flight, at most 4 GiB (queries run in
- * chunks).
+ * index without both strands. With a band, the deletion step holds only
+ * the cells that can still reach the band (a cell is extended only when
+ * the F it passes on is at least the band's lowest score so far), which
+ * leaves the band's cells and scores unchanged. Device memory: about
+ * 2 * max_cells * 40 + 8 * max_cells bytes per query in flight, at most
+ * 8 GiB (queries run in chunks).
  */
 int rb3_hapl(const rb3_index *idx, const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q,
              int32_t mem, rb3_hapl_t *out, int64_t out_cap, int64_t *out_off);
+
+/* Work done by the calling thread's last rb3_hapl or rb3_rle_hapl call that
+ * reached the device: node extensions (each reads rank-all at k and k + s),
+ * the index blocks those reads touched (as in rb3_last_smem_stats), the
+ * cells held summed over all query positions, and the queries whose cells
+ * outgrew the LDS tables and were finished in device memory. Any pointer
+ * may be NULL. */
+int rb3_last_hapl_stats(int64_t *extensions, int64_t *blocks, int64_t *cells, int64_t *moved);
 
 /*
  * rb3_locate: position of the suffix at each row (Sec. 2.4): strand[i] is

@@ -51,6 +51,9 @@ namespace rb3 {
 // errors
 // ---------------------------------------------------------------------------
 static thread_local std::string g_err;
+// work of the last rb3_hapl call of this thread: extensions, blocks, cells,
+// queries moved to device-memory tables
+static thread_local int64_t g_last_hapl[4] = {0, 0, 0, 0};
 // extensions performed by the last rb3_smem call of this thread
 static thread_local int64_t g_last_smem_exts[2] = {0, 0};
 static thread_local int64_t g_last_locate_steps = 0;
@@ -420,7 +423,8 @@ static int check_hapl(const rb3_hapl_opts &o, const int64_t *qlens, int64_t n_q)
         o.gap_ext < 1 || o.gap_ext > lim)
         return fail(RB3_EINVAL, "scores out of range");
     if (o.band < 0) return fail(RB3_EINVAL, "band must be >= 0");
-    if (o.max_cells < 1 || o.max_cells > 65535) return fail(RB3_EINVAL, "max_cells must be in 1 .. 65535");
+    if (o.device_tables != 0 && o.device_tables != 1) return fail(RB3_EINVAL, "device_tables must be 0 or 1");
+    if (o.max_cells < 0 || o.max_cells > 65535) return fail(RB3_EINVAL, "max_cells must be in 0 .. 65535");
     for (int64_t i = 0; i < n_q; ++i)
         if (qlens[i] * (int64_t)o.match >= ((int64_t)1 << 29))
             return fail(RB3_ELIMIT, "match score times query length reaches 2^29");
@@ -443,8 +447,10 @@ int run_hapl(Ctx &c, const DevIndex &ix, const uint8_t *q, const int64_t *qlens,
     hold.reset();
     RB3_ALLOC(recs, &c, (out_cap > 0 ? out_cap : 1) * sizeof(rb3_hapl_t));
     int64_t badq = -1;
+    int64_t hst[4] = {0, 0, 0, 0};
     const int rc = hapl_run(c, ix, rle, codes.as<uint8_t>(), qlens, n_q, o, out_cap, recs.as<rb3_hapl_t>(), out_off,
-                            &badq);
+                            &badq, hst);
+    for (int i = 0; i < 4; ++i) g_last_hapl[i] = hst[i];
     if (rc != RB3_OK) {
         if (badq >= 0) {
             const std::string m = "query " + std::to_string(badq) + " needs more than max_cells (" +
@@ -579,7 +585,8 @@ void rb3_hapl_opts_init(rb3_hapl_opts *o) {
     o->gap_open = 6;
     o->gap_ext = 1;
     o->band = 25;
-    o->max_cells = 4096;
+    o->max_cells = 0;
+    o->device_tables = 0;
 }
 
 // The checks shared by both index forms; *o_out = the options to use.
@@ -596,6 +603,8 @@ static int hapl_args(const rb3_hapl_opts *o, const uint8_t *q, const int64_t *ql
         rb3_hapl_opts_init(o_out);
     RB3_TRY(check_strings(q, qlens, n_q, mem, true, total));
     RB3_TRY(check_hapl(*o_out, qlens, n_q));
+    if (o_out->max_cells == 0)
+        o_out->max_cells = o_out->band > 0 ? (int32_t)std::min<int64_t>(65535, 8 * (int64_t)o_out->band + 256) : 4096;
     out_off[0] = 0;
     return RB3_OK;
 }
@@ -611,6 +620,14 @@ int rb3_hapl(const rb3_index *idx, const rb3_hapl_opts *o, const uint8_t *q, con
     Ctx c = call_ctx(idx->d);
     int rc = run_hapl(c, idx->d.dev(), q, qlens, n_q, total, mem, oo, out, out_cap, out_off, nullptr);
     return finish(c, rc);
+}
+
+int rb3_last_hapl_stats(int64_t *extensions, int64_t *blocks, int64_t *cells, int64_t *moved) {
+    if (extensions) *extensions = g_last_hapl[0];
+    if (blocks) *blocks = g_last_hapl[1];
+    if (cells) *cells = g_last_hapl[2];
+    if (moved) *moved = g_last_hapl[3];
+    return RB3_OK;
 }
 
 int rb3_last_smem_stats(int64_t *extensions, int64_t *blocks) {

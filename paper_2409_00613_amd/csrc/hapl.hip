@@ -15,7 +15,7 @@
 // interval of a cell kept before them.
 //
 // One thread per query. Its cells live in device scratch: the previous and
-// the current position's cells (48 bytes each) and an open-addressing hash
+// the current position's cells (40 bytes each) and an open-addressing hash
 // of the current ones keyed by (k, s), whose entries carry the position's
 // generation so that it never needs clearing between positions.
 #include "views.h"
@@ -30,7 +30,6 @@ constexpr int32_t HP_NEG = -1000000000;
 struct HpCell {
     int64_t k, kr, s;
     int32_t H, E, F, dirty;
-    int64_t pad;
 };
 
 struct HpParams {
@@ -66,6 +65,15 @@ __device__ __forceinline__ void hp_children(const V &ix, int64_t k, int64_t kr, 
     ck[3] = p0[4], cs[3] = oT, ckr[3] = kr + oS;                 // T: comp A (1)
 }
 
+// v[b] as a sum of masked terms, so that a loop over b needs no indexed
+// register array (which the compiler would place in scratch memory)
+__device__ __forceinline__ int64_t hp_pick(const int64_t v[4], int b) {
+    int64_t r = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) r += v[c] & -(int64_t)(b == c);
+    return r;
+}
+
 __device__ __forceinline__ uint32_t hp_hash(int64_t k, int64_t s, uint32_t mask) {
     uint64_t z = (uint64_t)k * 0x9E3779B97F4A7C15ull ^ ((uint64_t)s + 0x632BE59BD9B4E019ull) * 0xC2B2AE3D27D4EB4Full;
     z ^= z >> 29;
@@ -94,28 +102,98 @@ __device__ __forceinline__ int32_t hp_upsert(HpCell *T, int32_t &nT, uint32_t *h
         c.s = s;
         c.H = c.E = c.F = HP_NEG;
         c.dirty = 1;
-        c.pad = 0;
         T[j] = c;
         hash[h] = (gen << 16) | (uint32_t)j;
         return j;
     }
 }
 
-// Per query: A (previous cells) then B (current cells), each cap cells, and
-// hcap hash entries. cnt[q] = result cells, written in order to the start
-// of the query's A; -1 when the query needed more than cap cells at a
-// position.
+// The w-th largest score among the positive cells of B[0, n), or 1 when
+// fewer than w cells are positive; *above = positive cells scoring higher.
+// The positive scores are copied to hv (n entries) and the w-th largest is
+// found there by selection (Hoare partitions around a median of three).
+__device__ int32_t hp_kth(const HpCell *B, int32_t n, int32_t w, int32_t *hv, int32_t *above) {
+    int32_t m = 0;
+    for (int32_t x = 0; x < n; ++x) {
+        const int32_t h = B[x].H;
+        if (h > 0) hv[m++] = h;
+    }
+    if (m < w) {
+        *above = m;
+        return 1;
+    }
+    // w-th largest = element of rank w - 1 in decreasing order
+    int32_t lo = 0, hi = m - 1;
+    const int32_t r = w - 1;
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        int32_t a = hv[lo], b = hv[mid], c = hv[hi];
+        // median of the three as pivot
+        const int32_t piv = a > b ? (b > c ? b : (a > c ? c : a)) : (a > c ? a : (b > c ? c : b));
+        int32_t i = lo, j = hi;
+        while (i <= j) {
+            while (hv[i] > piv) ++i;
+            while (hv[j] < piv) --j;
+            if (i <= j) {
+                const int32_t t = hv[i];
+                hv[i] = hv[j];
+                hv[j] = t;
+                ++i;
+                --j;
+            }
+        }
+        if (r <= j)
+            hi = j;
+        else if (r >= i)
+            lo = i;
+        else
+            break;
+    }
+    const int32_t tau = hv[r];
+    int32_t c = 0;
+    for (int32_t x = 0; x < m; ++x) c += hv[x] > tau;
+    *above = c;
+    return tau;
+}
+
+__device__ __forceinline__ void hp_swap(HpCell *B, int32_t x, int32_t y) {
+    if (x != y) {
+        const HpCell t = B[x];
+        B[x] = B[y];
+        B[y] = t;
+    }
+}
+
+// Device-memory tables, one thread per query (queries whose cells outgrow
+// the on-chip tables of k_hapl_wave, or all of them on request). Per query:
+// A (previous cells) then B (current cells), each cap cells, and hcap hash
+// entries. cnt[q] = result cells, written in order to the start of the
+// query's A; -1 when the query needed more than cap cells at a position.
+//
+// With a band W the deletion step only extends a cell whose F passed on,
+// f = max(H - q, F) - e, is at least tau, the W-th best score held after
+// the match and insertion steps:
+// the cells it would reach score at most f, scores only rise during the
+// step, so tau never exceeds the W-th best score at the end of the step,
+// and a cell scoring below that is neither kept nor the source of a kept
+// cell's score (a deletion parent always scores more than its child's F).
+// The band's cells and their H and E are therefore those of the full
+// closure; F is not carried to the next position.
 template <class V>
-__global__ void k_hapl(V ix, const uint8_t *__restrict__ Q, const int64_t *__restrict__ qoff, int64_t nq,
+__global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q, const int64_t *__restrict__ qse, int64_t nq,
                        HpParams p, HpCell *__restrict__ cells, uint32_t *__restrict__ hashes,
-                       int32_t *__restrict__ cnt) {
+                       int32_t *__restrict__ hvals, int32_t *__restrict__ cnt,
+                       unsigned long long *__restrict__ stats) {
     const int64_t qi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (qi >= nq) return;
     HpCell *A = cells + qi * 2 * (int64_t)p.cap;
     HpCell *B = A + p.cap;
     uint32_t *hash = hashes + qi * (int64_t)p.hcap;
-    const uint8_t *P = Q + qoff[qi];
-    const int64_t L = qoff[qi + 1] - qoff[qi];
+    int32_t *hv = hvals + qi * (int64_t)p.cap;
+    // qse: start and end of each query's codes, side by side
+    const uint8_t *P = Q + qse[2 * qi];
+    const int64_t L = qse[2 * qi + 1] - qse[2 * qi];
+    uint64_t n_ext = 0, n_units = 0, n_cells = 0;
     int32_t nA = 1, nB = 0;
     {
         HpCell r;
@@ -125,7 +203,6 @@ __global__ void k_hapl(V ix, const uint8_t *__restrict__ Q, const int64_t *__res
         r.H = 0;
         r.E = r.F = HP_NEG;
         r.dirty = 0;
-        r.pad = 0;
         A[0] = r;
     }
     bool full = false;
@@ -141,14 +218,18 @@ __global__ void k_hapl(V ix, const uint8_t *__restrict__ Q, const int64_t *__res
             const HpCell c = A[x];
             int64_t ck[4], ckr[4], cs[4];
             hp_children(ix, c.k, c.kr, c.s, ck, ckr, cs);
+            ++n_ext;
+            n_units += ix.units(c.k, c.k + c.s);
+#pragma unroll 1
             for (int b = 0; b < 4; ++b) {
-                if (cs[b] <= 0) continue;
-                const int32_t j = hp_upsert(B, nB, hash, p, gen, ck[b], ckr[b], cs[b]);
-                if (j < 0) {
-                    full = true;
-                    break;
+                const int64_t sb = hp_pick(cs, b);
+                if (!full && sb > 0) {
+                    const int32_t j = hp_upsert(B, nB, hash, p, gen, hp_pick(ck, b), hp_pick(ckr, b), sb);
+                    if (j < 0)
+                        full = true;
+                    else
+                        B[j].H = hp_max(B[j].H, c.H + ((uint32_t)(b + 1) == a ? p.match : -p.mismatch));
                 }
-                B[j].H = hp_max(B[j].H, c.H + ((uint32_t)(b + 1) == a ? p.match : -p.mismatch));
             }
             if (full) break;
             const int32_t j = hp_upsert(B, nB, hash, p, gen, c.k, c.kr, c.s);
@@ -162,48 +243,61 @@ __global__ void k_hapl(V ix, const uint8_t *__restrict__ Q, const int64_t *__res
         }
         // deletion, repeated until no cell improves: a cell whose H or F
         // rose since it last passed its F on is marked dirty
+        int32_t above = 0;
+        const int32_t tau = (p.band > 0 && !full) ? hp_kth(B, nB, p.band, hv, &above) : 1;
         bool changed = true;
         while (changed && !full) {
             changed = false;
             for (int32_t x = 0; x < nB && !full; ++x) {
                 if (!B[x].dirty) continue;
                 B[x].dirty = 0;
-                if (B[x].H <= 0) continue;
                 const int32_t f = hp_max(B[x].H - p.gap_open, B[x].F) - p.gap_ext;
-                if (f <= 0) continue;
+                if (f <= 0 || f < tau || B[x].H <= 0) continue;
                 int64_t ck[4], ckr[4], cs[4];
                 hp_children(ix, B[x].k, B[x].kr, B[x].s, ck, ckr, cs);
+                ++n_ext;
+                n_units += ix.units(B[x].k, B[x].k + B[x].s);
+#pragma unroll 1
                 for (int b = 0; b < 4; ++b) {
-                    if (cs[b] <= 0) continue;
-                    const int32_t j = hp_upsert(B, nB, hash, p, gen, ck[b], ckr[b], cs[b]);
-                    if (j < 0) {
-                        full = true;
-                        break;
-                    }
-                    if (f > B[j].F) {
-                        B[j].F = f;
-                        if (f > B[j].H) B[j].H = f;
-                        B[j].dirty = 1;
-                        changed = true;
+                    const int64_t sb = hp_pick(cs, b);
+                    if (!full && sb > 0) {
+                        const int32_t j = hp_upsert(B, nB, hash, p, gen, hp_pick(ck, b), hp_pick(ckr, b), sb);
+                        if (j < 0) {
+                            full = true;
+                        } else if (f > B[j].F) {
+                            B[j].F = f;
+                            if (f > B[j].H) B[j].H = f;
+                            B[j].dirty = 1;
+                            changed = true;
+                        }
                     }
                 }
             }
         }
         if (full) break;
+        n_cells += (uint64_t)nB;
         // keep H > 0; with a band, the W best
         int32_t w = 0;
         for (int32_t x = 0; x < nB; ++x)
             if (B[x].H > 0) B[w++] = B[x];
         if (p.band > 0 && w > p.band) {
-            // selection of the band's cells to the front
-            for (int32_t y = 0; y < p.band; ++y) {
-                int32_t best = y;
-                for (int32_t x = y + 1; x < w; ++x)
-                    if (hp_before(B[x], B[best])) best = x;
-                if (best != y) {
-                    const HpCell tmp = B[y];
-                    B[y] = B[best];
-                    B[best] = tmp;
+            const int32_t tau = hp_kth(B, w, p.band, hv, &above);
+            // the cells scoring above tau first, then those scoring tau
+            int32_t a0 = 0;
+            for (int32_t x = 0; x < w; ++x)
+                if (B[x].H > tau) hp_swap(B, a0++, x);
+            int32_t e0 = a0;
+            for (int32_t x = a0; x < w; ++x)
+                if (B[x].H == tau) hp_swap(B, e0++, x);
+            // of the ties, the band's remaining places go to the smallest
+            // (k, s)
+            const int32_t r = p.band - above;
+            if (e0 - a0 > r) {
+                for (int32_t y = a0; y < a0 + r; ++y) {
+                    int32_t best = y;
+                    for (int32_t x = y + 1; x < e0; ++x)
+                        if (B[x].k < B[best].k || (B[x].k == B[best].k && B[x].s < B[best].s)) best = x;
+                    hp_swap(B, y, best);
                 }
             }
             w = p.band;
@@ -214,6 +308,11 @@ __global__ void k_hapl(V ix, const uint8_t *__restrict__ Q, const int64_t *__res
             A[x] = c;
         }
         nA = w;
+    }
+    if (n_ext) {
+        atomicAdd(&stats[0], (unsigned long long)n_ext);
+        atomicAdd(&stats[1], (unsigned long long)n_units);
+        atomicAdd(&stats[2], (unsigned long long)n_cells);
     }
     if (full) {
         cnt[qi] = -1;
@@ -243,14 +342,401 @@ __global__ void k_hapl(V ix, const uint8_t *__restrict__ Q, const int64_t *__res
     cnt[qi] = w;
 }
 
-// Result records of a batch in order: query qi's cells go to out[off[qi] ..].
+// ---------------------------------------------------------------------------
+// One wavefront per query, cells in LDS
+// ---------------------------------------------------------------------------
+//
+// The lanes share the query's cells: each extends its own cells (so up to
+// 64 rank-all pairs of one query are in flight together) and inserts the
+// results into a hash in LDS. A cell is claimed by allocating it, writing
+// its key and publishing it in a hash slot with a compare-and-swap; a lane
+// that loses the race to an equal key leaves its allocation unlinked (s =
+// 0, scores at minus infinity), so no lane ever waits on another. Scores
+// are raised with LDS atomic max. A query whose cells outgrow the LDS
+// tables is finished by k_hapl instead (cnt = -2).
+constexpr int HW_CAP = 256;  // cells one position may hold in LDS
+constexpr int HW_HS = 512;   // hash slots (a power of two, at least 2 * HW_CAP)
+
+struct HwLds {
+    int64_t ck[HW_CAP], ckr[HW_CAP], cs[HW_CAP];    // current position's cells
+    int32_t cH[HW_CAP], cE[HW_CAP], cF[HW_CAP], cd[HW_CAP];
+    int32_t slot[HW_HS];                            // cell index + 1, 0 = empty
+    int64_t pk[HW_CAP], pkr[HW_CAP], ps[HW_CAP];    // previous position's cells
+    int32_t pH[HW_CAP], pE[HW_CAP];
+    int32_t hist[64];  // positive scores mx - i, for the band's threshold
+    int32_t nC, nP, flag, changed, tcount;
+};
+
+__device__ __forceinline__ int32_t hw_sum(int32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int32_t hw_maxr(int32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v = hp_max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t hw_sum64(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Index of the cell for (k, s), created when absent; -1 when the tables
+// are full.
+__device__ int32_t hw_upsert(HwLds &S, int32_t cap, int64_t k, int64_t kr, int64_t s) {
+    uint32_t h = hp_hash(k, s, HW_HS - 1);
+    int32_t j = -1;
+    for (int probe = 0; probe < HW_HS; ++probe) {
+        int32_t v = __hip_atomic_load(&S.slot[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (v == 0) {
+            if (j < 0) {
+                j = atomicAdd(&S.nC, 1);
+                if (j >= cap) return -1;
+                S.ck[j] = k;
+                S.ckr[j] = kr;
+                S.cs[j] = s;
+                S.cH[j] = HP_NEG;
+                S.cE[j] = HP_NEG;
+                S.cF[j] = HP_NEG;
+                S.cd[j] = 1;
+            }
+            int32_t expected = 0;
+            if (__hip_atomic_compare_exchange_strong(&S.slot[h], &expected, j + 1, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
+                return j;
+            v = expected;
+        }
+        const int32_t c = v - 1;
+        if (S.ck[c] == k && S.cs[c] == s) {
+            if (j >= 0) S.cs[j] = 0;  // the allocation stays unlinked
+            return c;
+        }
+        h = (h + 1) & (HW_HS - 1);
+    }
+    return -1;
+}
+
+constexpr int HW_BINS = 64;
+
+// Histogram of the positive scores mx - 63 .. mx, mx the highest (bin i
+// counts score mx - i); every lane gets mx and the positive cells' number.
+__device__ void hw_hist_build(HwLds &S, int32_t n, int lane, int32_t *mx_out, int32_t *pos_out) {
+    int32_t mx = 0, c = 0;
+    for (int32_t x = lane; x < n; x += 64) {
+        const int32_t h = S.cH[x];
+        if (h > 0) {
+            ++c;
+            mx = hp_max(mx, h);
+        }
+    }
+    *pos_out = hw_sum(c);
+    mx = hw_maxr(mx);
+    *mx_out = mx;
+    S.hist[lane] = 0;
+    __syncthreads();
+    for (int32_t x = lane; x < n; x += 64) {
+        const int32_t h = S.cH[x];
+        if (h > 0 && mx - h < HW_BINS) atomicAdd(&S.hist[mx - h], 1);
+    }
+    __syncthreads();
+}
+
+// The w-th largest positive score from the histogram, when its bins hold
+// at least w cells (else false): *above = cells scoring higher, *ties =
+// cells scoring it. A scan of the 64 bins across the lanes.
+__device__ bool hw_hist_tau(const HwLds &S, int32_t w, int lane, int32_t mx, int32_t *tau, int32_t *above,
+                            int32_t *ties) {
+    const int32_t c = S.hist[lane];
+    int32_t v = c;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t u = __shfl_up(v, d);
+        if (lane >= d) v += u;
+    }
+    const unsigned long long m = __ballot(v >= w);
+    if (m == 0) return false;
+    const int i = __ffsll(m) - 1;
+    const int32_t vi = __shfl(v, i), ci = __shfl(c, i);
+    *tau = mx - i;
+    *above = vi - ci;
+    *ties = ci;
+    return true;
+}
+
+// The same by a binary search over the scores 1 .. mx, each probe a count
+// over the n cells (for thresholds below the histogram's range); the n
+// cells hold at least w positive ones.
+__device__ int32_t hw_kth_search(const HwLds &S, int32_t n, int32_t w, int lane, int32_t mx, int32_t *above,
+                                 int32_t *ties) {
+    int32_t lo = 1, hi = mx;  // the largest v with w or more scores >= v
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo + 1) >> 1);
+        int32_t k = 0;
+        for (int32_t x = lane; x < n; x += 64) k += S.cH[x] >= mid;
+        if (hw_sum(k) >= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    int32_t ka = 0, kt = 0;
+    for (int32_t x = lane; x < n; x += 64) {
+        ka += S.cH[x] > lo;
+        kt += S.cH[x] == lo;
+    }
+    *above = hw_sum(ka);
+    *ties = hw_sum(kt);
+    return lo;
+}
+
+// One block of 64 threads (one wavefront) per query; cap <= HW_CAP cells
+// per position. Results (at most outcap) go to wout[qi * outcap ..] in
+// order, cnt[qi] = their number, or -2 when the cells outgrew cap.
+template <class V>
+__global__ __launch_bounds__(64) void k_hapl_wave(V ix, const uint8_t *__restrict__ Q,
+                                                  const int64_t *__restrict__ qoff, HpParams p, int32_t cap,
+                                                  int32_t outcap, int64_t qbase, rb3_hapl_t *__restrict__ wout,
+                                                  int32_t *__restrict__ cnt, unsigned long long *__restrict__ stats) {
+    __shared__ HwLds S;
+    const int64_t qi = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint8_t *P = Q + qoff[qi];
+    const int64_t L = qoff[qi + 1] - qoff[qi];
+    uint64_t n_ext = 0, n_units = 0, n_cells = 0;
+    if (lane == 0) {
+        S.pk[0] = 0;
+        S.pkr[0] = 0;
+        S.ps[0] = ix.size();
+        S.pH[0] = 0;
+        S.pE[0] = HP_NEG;
+        S.nP = 1;
+        S.flag = 0;
+    }
+    __syncthreads();
+    bool over = false;
+    for (int64_t t = L - 1; t >= 0; --t) {
+        const uint32_t a = P[t];
+        for (int h = lane; h < HW_HS; h += 64) S.slot[h] = 0;
+        if (lane == 0) S.nC = 0;
+        __syncthreads();
+        const int32_t nP = S.nP;
+        // match / mismatch and insertion from the previous position's cells
+        for (int32_t x = lane; x < nP; x += 64) {
+            const int64_t k = S.pk[x], kr = S.pkr[x], sz = S.ps[x];
+            const int32_t H = S.pH[x], E = S.pE[x];
+            int64_t ck[4], ckr[4], cs[4];
+            hp_children(ix, k, kr, sz, ck, ckr, cs);
+            ++n_ext;
+            n_units += ix.units(k, k + sz);
+            bool bad = false;
+#pragma unroll 1
+            for (int b = 0; b < 4; ++b) {
+                const int64_t sb = hp_pick(cs, b);
+                if (!bad && sb > 0) {
+                    const int32_t j = hw_upsert(S, cap, hp_pick(ck, b), hp_pick(ckr, b), sb);
+                    if (j < 0)
+                        bad = true;
+                    else
+                        atomicMax(&S.cH[j], H + ((uint32_t)(b + 1) == a ? p.match : -p.mismatch));
+                }
+            }
+            if (!bad) {
+                const int32_t j = hw_upsert(S, cap, k, kr, sz);
+                if (j < 0) {
+                    bad = true;
+                } else {
+                    const int32_t e = hp_max(H - p.gap_open, E) - p.gap_ext;
+                    atomicMax(&S.cE[j], e);
+                    atomicMax(&S.cH[j], e);
+                }
+            }
+            if (bad) S.flag = 1;
+        }
+        __syncthreads();
+        if (S.flag) {
+            over = true;
+            break;
+        }
+        // the band's threshold so far: the histogram of the top 64 scores
+        // is kept up to date through the deletion step (hm) when it holds
+        // the band, else a search gives a fixed lower bound
+        int32_t mx = 0, pos = 0, tau = 1, above = 0, ties = 0;
+        bool hm = false;
+        if (p.band > 0) {
+            hw_hist_build(S, S.nC, lane, &mx, &pos);
+            if (pos >= p.band) {
+                hm = hw_hist_tau(S, p.band, lane, mx, &tau, &above, &ties);
+                if (!hm) tau = hw_kth_search(S, S.nC, p.band, lane, mx, &above, &ties);
+            }
+        }
+        // deletion in rounds until no cell improves; a round extends the
+        // dirty cells present at its start
+        for (;;) {
+            if (lane == 0) S.changed = 0;
+            __syncthreads();
+            if (hm) hw_hist_tau(S, p.band, lane, mx, &tau, &above, &ties);  // tau only rises
+            const int32_t n0 = S.nC;
+            for (int32_t x = lane; x < n0; x += 64) {
+                if (!S.cd[x]) continue;
+                S.cd[x] = 0;
+                const int32_t H = S.cH[x];
+                const int32_t f = hp_max(H - p.gap_open, S.cF[x]) - p.gap_ext;
+                if (f <= 0 || f < tau || H <= 0) continue;
+                const int64_t k = S.ck[x], sz = S.cs[x];
+                int64_t ck[4], ckr[4], cs[4];
+                hp_children(ix, k, S.ckr[x], sz, ck, ckr, cs);
+                ++n_ext;
+                n_units += ix.units(k, k + sz);
+                bool bad = false;
+#pragma unroll 1
+                for (int b = 0; b < 4; ++b) {
+                    const int64_t sb = hp_pick(cs, b);
+                    if (!bad && sb > 0) {
+                        const int32_t j = hw_upsert(S, cap, hp_pick(ck, b), hp_pick(ckr, b), sb);
+                        if (j < 0) {
+                            bad = true;
+                        } else if (atomicMax(&S.cF[j], f) < f) {
+                            const int32_t old = atomicMax(&S.cH[j], f);
+                            // a deletion never tops its parent, so f < mx
+                            if (hm && old < f) {
+                                if (old > 0 && mx - old < HW_BINS) atomicSub(&S.hist[mx - old], 1);
+                                if (mx - f < HW_BINS) atomicAdd(&S.hist[mx - f], 1);
+                            }
+                            S.cd[j] = 1;
+                            S.changed = 1;
+                        }
+                    }
+                }
+                if (bad) S.flag = 1;
+            }
+            __syncthreads();
+            if (S.flag || !S.changed) break;
+        }
+        if (S.flag) {
+            over = true;
+            break;
+        }
+        // keep H > 0; with a band, the W best (ties: smaller k, then s)
+        const int32_t nC = S.nC;
+        n_cells += (uint64_t)nC;
+        bool cut = false;
+        if (p.band > 0) {
+            if (hm) {
+                hw_hist_tau(S, p.band, lane, mx, &tau, &above, &ties);
+                cut = true;
+            } else {
+                hw_hist_build(S, nC, lane, &mx, &pos);
+                if (pos >= p.band) {
+                    if (!hw_hist_tau(S, p.band, lane, mx, &tau, &above, &ties))
+                        tau = hw_kth_search(S, nC, p.band, lane, mx, &above, &ties);
+                    cut = true;
+                }
+            }
+        }
+        const int32_t r = p.band - above;
+        const bool rank_ties = cut && ties > r;
+        if (lane == 0) {
+            S.nP = 0;
+            S.tcount = 0;
+        }
+        __syncthreads();
+        if (rank_ties) {
+            // the tied cells' keys into the previous-cells arrays (free
+            // now); each tied cell's rank among them decides (in cd)
+            for (int32_t x = lane; x < nC; x += 64) {
+                if (S.cH[x] == tau) {
+                    const int32_t d = atomicAdd(&S.tcount, 1);
+                    S.pk[d] = S.ck[x];
+                    S.ps[d] = S.cs[x];
+                }
+            }
+            __syncthreads();
+            const int32_t T = S.tcount;
+            for (int32_t x = lane; x < nC; x += 64) {
+                if (S.cH[x] == tau) {
+                    const int64_t k = S.ck[x], sz = S.cs[x];
+                    int32_t rank = 0;
+                    for (int32_t y = 0; y < T; ++y) rank += S.pk[y] < k || (S.pk[y] == k && S.ps[y] < sz);
+                    S.cd[x] = rank < r;
+                }
+            }
+            __syncthreads();
+        }
+        for (int32_t x = lane; x < nC; x += 64) {
+            const int32_t H = S.cH[x];
+            bool keep = H > 0;
+            if (keep && cut) keep = H > tau || (H == tau && (!rank_ties || S.cd[x]));
+            if (keep) {
+                const int32_t d = atomicAdd(&S.nP, 1);
+                S.pk[d] = S.ck[x];
+                S.pkr[d] = S.ckr[x];
+                S.ps[d] = S.cs[x];
+                S.pH[d] = H;
+                S.pE[d] = S.cE[x];
+            }
+        }
+        __syncthreads();
+    }
+    n_ext = hw_sum64(n_ext);
+    n_units = hw_sum64(n_units);
+    if (lane == 0 && n_ext) {
+        atomicAdd(&stats[0], (unsigned long long)n_ext);
+        atomicAdd(&stats[1], (unsigned long long)n_units);
+        atomicAdd(&stats[2], (unsigned long long)n_cells);
+    }
+    if (lane != 0) return;
+    if (over) {
+        cnt[qi] = -2;
+        return;
+    }
+    // the cells of the query's start, ordered, then the redundancy filter
+    const int32_t n = L == 0 ? 0 : S.nP;  // the root alone is not a result
+    for (int32_t x = 1; x < n; ++x) {
+        const int64_t k = S.pk[x], kr = S.pkr[x], sz = S.ps[x];
+        const int32_t H = S.pH[x];
+        int32_t y = x - 1;
+        while (y >= 0 && (S.pH[y] < H || (S.pH[y] == H && (S.pk[y] > k || (S.pk[y] == k && S.ps[y] > sz))))) {
+            S.pk[y + 1] = S.pk[y];
+            S.pkr[y + 1] = S.pkr[y];
+            S.ps[y + 1] = S.ps[y];
+            S.pH[y + 1] = S.pH[y];
+            --y;
+        }
+        S.pk[y + 1] = k;
+        S.pkr[y + 1] = kr;
+        S.ps[y + 1] = sz;
+        S.pH[y + 1] = H;
+    }
+    rb3_hapl_t *out = wout + qi * (int64_t)outcap;
+    int32_t w = 0;
+    for (int32_t x = 0; x < n; ++x) {
+        const int64_t k = S.pk[x], kr = S.pkr[x], sz = S.ps[x];
+        bool inside = false;
+        for (int32_t y = 0; y < w && !inside; ++y)
+            inside = (k >= out[y].k && k + sz <= out[y].k + out[y].s) ||
+                     (kr >= out[y].krc && kr + sz <= out[y].krc + out[y].s);
+        if (!inside) {
+            rb3_hapl_t o;
+            o.k = k;
+            o.krc = kr;
+            o.s = sz;
+            o.score = S.pH[x];
+            o.qid = (int32_t)(qbase + qi);
+            out[w++] = o;
+        }
+    }
+    cnt[qi] = w;
+}
+
+// Result records in order: query qidx[i]'s cells (of the thread tables)
+// go to out[off[qidx[i]] ..].
 __global__ void k_hapl_gather(const HpCell *__restrict__ cells, int64_t nq, int32_t cap,
-                              const int32_t *__restrict__ cnt, const int64_t *__restrict__ off, int64_t qbase,
-                              rb3_hapl_t *__restrict__ out) {
-    const int64_t qi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (qi >= nq) return;
-    const HpCell *A = cells + qi * 2 * (int64_t)cap;
-    const int32_t c = cnt[qi];
+                              const int32_t *__restrict__ cnt, const int64_t *__restrict__ off,
+                              const int64_t *__restrict__ qidx, int64_t qbase, rb3_hapl_t *__restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const HpCell *A = cells + i * 2 * (int64_t)cap;
+    const int64_t qi = qidx[i];
+    const int32_t c = cnt[i];
     for (int32_t x = 0; x < c; ++x) {
         rb3_hapl_t r;
         r.k = A[x].k;
@@ -262,10 +748,20 @@ __global__ void k_hapl_gather(const HpCell *__restrict__ cells, int64_t nq, int3
     }
 }
 
+// The same for the results of k_hapl_wave (queries it finished).
+__global__ void k_hapl_wave_gather(const rb3_hapl_t *__restrict__ wout, int64_t nq, int32_t outcap,
+                                   const int32_t *__restrict__ cnt, const int64_t *__restrict__ off,
+                                   rb3_hapl_t *__restrict__ out) {
+    const int64_t qi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (qi >= nq) return;
+    const int32_t c = cnt[qi];
+    for (int32_t x = 0; x < c; ++x) out[off[qi] + x] = wout[qi * (int64_t)outcap + x];
+}
+
 template <class V>
-static int hapl_run_v(Ctx &c, const V &view, const char *name, const uint8_t *d_codes, const int64_t *qlens,
-                      int64_t nq, const rb3_hapl_opts &o, int64_t out_cap, rb3_hapl_t *d_out, int64_t *h_off,
-                      int64_t *h_bad) {
+static int hapl_run_v(Ctx &c, const V &view, const char *name, const char *wname, const uint8_t *d_codes,
+                      const int64_t *qlens, int64_t nq, const rb3_hapl_opts &o, int64_t out_cap, rb3_hapl_t *d_out,
+                      int64_t *h_off, int64_t *h_bad, int64_t *h_stats) {
     HpParams p;
     p.match = o.match;
     p.mismatch = o.mismatch;
@@ -276,51 +772,117 @@ static int hapl_run_v(Ctx &c, const V &view, const char *name, const uint8_t *d_
     int32_t h = 1;
     while (h < 2 * o.max_cells) h <<= 1;
     p.hcap = h;
+    const bool wave = !o.device_tables;
+    const int32_t wcap = std::min<int32_t>(HW_CAP, o.max_cells);
+    const int32_t outcap = o.band > 0 ? std::min<int32_t>(o.band, wcap) : wcap;
     std::vector<int64_t> qoff(nq + 1);
     qoff[0] = 0;
     for (int64_t i = 0; i < nq; ++i) qoff[i + 1] = qoff[i] + qlens[i];
-    const int64_t per = 2 * (int64_t)p.cap * (int64_t)sizeof(HpCell) + (int64_t)p.hcap * 4;
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, HAPL_SCRATCH / per));
-    DBuf dq, cells, hash, cnt, doff;
+    // a chunk's queries all fit the device-memory tables, so that those the
+    // LDS tables cannot hold are finished in one launch
+    const int64_t per_t = 2 * (int64_t)p.cap * (int64_t)sizeof(HpCell) + (int64_t)p.hcap * 4 + (int64_t)p.cap * 4;
+    const int64_t per_w = (int64_t)outcap * (int64_t)sizeof(rb3_hapl_t) + 4;
+    int64_t chunk = std::min<int64_t>(nq, std::max<int64_t>(1, HAPL_SCRATCH / per_t));
+    if (wave) chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, HAPL_SCRATCH / per_w));
+    chunk = std::min<int64_t>(chunk, (int64_t)1 << 30);
+    DBuf dq, wout, wcnt, cells, hash, hvals, tcnt, tq, doff, dst;
     RB3_ALLOC(dq, &c, (nq + 1) * sizeof(int64_t));
-    RB3_ALLOC(cells, &c, (size_t)chunk * 2 * (size_t)p.cap * sizeof(HpCell));
-    RB3_ALLOC(hash, &c, (size_t)chunk * (size_t)p.hcap * 4);
-    RB3_ALLOC(cnt, &c, (size_t)chunk * sizeof(int32_t));
     RB3_ALLOC(doff, &c, (size_t)chunk * sizeof(int64_t));
+    RB3_ALLOC(dst, &c, 4 * sizeof(unsigned long long));
+    if (wave) {
+        RB3_ALLOC(wout, &c, (size_t)chunk * (size_t)outcap * sizeof(rb3_hapl_t));
+        RB3_ALLOC(wcnt, &c, (size_t)chunk * sizeof(int32_t));
+    }
+    RB3_HIP(hipMemsetAsync(dst.p, 0, 4 * sizeof(unsigned long long), c.stream));
     RB3_HIP(hipMemcpyAsync(dq.p, qoff.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
-    std::vector<int32_t> hc(chunk);
+    std::vector<int32_t> hc(chunk), ht;
+    std::vector<int64_t> sub, hq;
+    int64_t tcap = 0;   // queries the device-memory tables are allocated for
+    int64_t moved = 0;  // queries the LDS tables could not hold
     h_off[0] = 0;
     for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
         const int64_t m = std::min(chunk, nq - q0);
-        RB3_HIP(hipMemsetAsync(hash.p, 0, (size_t)m * (size_t)p.hcap * 4, c.stream));
-        RB3_LAUNCH(name, k_hapl<V>, grid_for(m, 64, 1 << 30), dim3(64), 0, c.stream, view, d_codes,
-                   dq.as<int64_t>() + q0, m, p, cells.as<HpCell>(), hash.as<uint32_t>(), cnt.as<int32_t>());
-        RB3_HIP(hipMemcpyAsync(hc.data(), cnt.p, m * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
-        RB3_HIP(hipStreamSynchronize(c.stream));
-        for (int64_t i = 0; i < m; ++i) {
-            if (hc[i] < 0) {
-                *h_bad = q0 + i;
-                return RB3_ELIMIT;
-            }
-            h_off[q0 + i + 1] = h_off[q0 + i] + hc[i];
+        sub.clear();
+        if (wave) {
+            RB3_LAUNCH(wname, k_hapl_wave<V>, dim3((uint32_t)m), dim3(64), 0, c.stream, view, d_codes,
+                       dq.as<int64_t>() + q0, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(), wcnt.as<int32_t>(),
+                       dst.as<unsigned long long>());
+            RB3_HIP(hipMemcpyAsync(hc.data(), wcnt.p, m * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+            RB3_HIP(hipStreamSynchronize(c.stream));
+            for (int64_t i = 0; i < m; ++i)
+                if (hc[i] == -2) sub.push_back(i);
+            moved += (int64_t)sub.size();
+        } else {
+            for (int64_t i = 0; i < m; ++i) sub.push_back(i);
         }
+        const int64_t ns = (int64_t)sub.size();
+        if (ns > 0) {
+            if (ns > tcap) {
+                cells.reset();
+                hash.reset();
+                hvals.reset();
+                tcnt.reset();
+                tq.reset();
+                tcap = ns;
+                RB3_ALLOC(cells, &c, (size_t)tcap * 2 * (size_t)p.cap * sizeof(HpCell));
+                RB3_ALLOC(hash, &c, (size_t)tcap * (size_t)p.hcap * 4);
+                RB3_ALLOC(hvals, &c, (size_t)tcap * (size_t)p.cap * 4);
+                RB3_ALLOC(tcnt, &c, (size_t)tcap * sizeof(int32_t));
+                RB3_ALLOC(tq, &c, (size_t)tcap * 3 * sizeof(int64_t));
+            }
+            // start and end of each query's codes, then its index in the chunk
+            hq.resize(3 * ns);
+            for (int64_t i = 0; i < ns; ++i) {
+                hq[2 * i] = qoff[q0 + sub[i]];
+                hq[2 * i + 1] = qoff[q0 + sub[i] + 1];
+                hq[2 * ns + i] = sub[i];
+            }
+            RB3_HIP(hipMemcpyAsync(tq.p, hq.data(), 3 * ns * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+            RB3_HIP(hipMemsetAsync(hash.p, 0, (size_t)ns * (size_t)p.hcap * 4, c.stream));
+            RB3_LAUNCH(name, k_hapl<V>, grid_for(ns, 64, 1 << 30), dim3(64), 0, c.stream, view, d_codes,
+                       tq.as<int64_t>(), ns, p, cells.as<HpCell>(), hash.as<uint32_t>(), hvals.as<int32_t>(),
+                       tcnt.as<int32_t>(), dst.as<unsigned long long>());
+            ht.resize(ns);
+            RB3_HIP(hipMemcpyAsync(ht.data(), tcnt.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+            RB3_HIP(hipStreamSynchronize(c.stream));
+            for (int64_t i = 0; i < ns; ++i) {
+                if (ht[i] < 0) {
+                    *h_bad = q0 + sub[i];
+                    return RB3_ELIMIT;
+                }
+                hc[sub[i]] = ht[i];
+            }
+        }
+        for (int64_t i = 0; i < m; ++i) h_off[q0 + i + 1] = h_off[q0 + i] + hc[i];
         if (h_off[q0 + m] <= out_cap && h_off[q0 + m] > h_off[q0]) {
             RB3_HIP(hipMemcpyAsync(doff.p, h_off + q0, m * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
-            RB3_LAUNCH("hapl_gather", k_hapl_gather, grid_for(m, 64, 1 << 30), dim3(64), 0, c.stream,
-                       cells.as<HpCell>(), m, p.cap, cnt.as<int32_t>(), doff.as<int64_t>(), q0, d_out);
+            if (wave)
+                RB3_LAUNCH("hapl_wave_gather", k_hapl_wave_gather, grid_for(m, 64, 1 << 30), dim3(64), 0, c.stream,
+                           wout.as<rb3_hapl_t>(), m, outcap, wcnt.as<int32_t>(), doff.as<int64_t>(), d_out);
+            if (ns > 0)
+                RB3_LAUNCH("hapl_gather", k_hapl_gather, grid_for(ns, 64, 1 << 30), dim3(64), 0, c.stream,
+                           cells.as<HpCell>(), ns, p.cap, tcnt.as<int32_t>(), doff.as<int64_t>(),
+                           tq.as<int64_t>() + 2 * ns, q0, d_out);
             // the offsets and counts are rewritten by the next chunk
             RB3_HIP(hipStreamSynchronize(c.stream));
         }
     }
+    unsigned long long hs[4];
+    RB3_HIP(hipMemcpyAsync(hs, dst.p, sizeof(hs), hipMemcpyDeviceToHost, c.stream));
+    RB3_HIP(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < 3; ++i) h_stats[i] = (int64_t)hs[i];
+    h_stats[3] = moved;
     return RB3_OK;
 }
 
 int hapl_run(Ctx &c, const DevIndex &ix, const RleView *rle, const uint8_t *d_codes, const int64_t *qlens,
              int64_t nq, const rb3_hapl_opts &o, int64_t out_cap, rb3_hapl_t *d_out, int64_t *h_off,
-             int64_t *h_bad) {
+             int64_t *h_bad, int64_t *h_stats) {
     if (rle)
-        return hapl_run_v(c, RleQView{*rle}, "hapl_rle", d_codes, qlens, nq, o, out_cap, d_out, h_off, h_bad);
-    return hapl_run_v(c, PlainView{ix}, "hapl", d_codes, qlens, nq, o, out_cap, d_out, h_off, h_bad);
+        return hapl_run_v(c, RleQView{*rle}, "hapl_rle", "hapl_wave_rle", d_codes, qlens, nq, o, out_cap, d_out,
+                          h_off, h_bad, h_stats);
+    return hapl_run_v(c, PlainView{ix}, "hapl", "hapl_wave", d_codes, qlens, nq, o, out_cap, d_out, h_off, h_bad,
+                      h_stats);
 }
 
 }  // namespace rb3

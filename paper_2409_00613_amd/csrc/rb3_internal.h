@@ -504,12 +504,14 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
 // tables fit HAPL_SCRATCH bytes. h_off (host, nq + 1) receives the
 // per-query offsets; when everything fits out_cap the records are written
 // in order to d_out. A query that needs more than o.max_cells cells at a
-// position gives RB3_ELIMIT with its index in *h_bad.
-constexpr int64_t HAPL_SCRATCH = (int64_t)4 << 30;
+// position gives RB3_ELIMIT with its index in *h_bad. h_stats[0..3]:
+// extensions (rank-all pairs), index blocks they read, cells held summed
+// over the query positions, queries moved from LDS to device-memory tables.
+constexpr int64_t HAPL_SCRATCH = (int64_t)8 << 30;
 struct RleView;
 int hapl_run(Ctx &c, const DevIndex &ix, const RleView *rle, const uint8_t *d_codes, const int64_t *qlens,
              int64_t nq, const rb3_hapl_opts &o, int64_t out_cap, rb3_hapl_t *d_out, int64_t *h_off,
-             int64_t *h_bad);
+             int64_t *h_bad, int64_t *h_stats);
 
 // api.cpp: one synchronous count / SMEM call on a context's stream (the
 // caller flushes the context afterwards). total = sum of qlens. With rle

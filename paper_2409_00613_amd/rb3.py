@@ -47,7 +47,8 @@ assert SMEM_DTYPE.itemsize == ctypes.sizeof(SmemRec) == 48
 
 class HaplOpts(ctypes.Structure):
     _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap_open", ctypes.c_int32),
-                ("gap_ext", ctypes.c_int32), ("band", ctypes.c_int32), ("max_cells", ctypes.c_int32)]
+                ("gap_ext", ctypes.c_int32), ("band", ctypes.c_int32), ("max_cells", ctypes.c_int32),
+                ("device_tables", ctypes.c_int32)]
 
 
 class HaplRec(ctypes.Structure):
@@ -64,7 +65,7 @@ EXPORTS = ["rb3_opts_init", "rb3_build", "rb3_merge", "rb3_count", "rb3_count_no
            "rb3_locate", "rb3_locate1", "rb3_ssa_info", "rb3_last_locate_stats", "rb3_info",
            "rb3_export", "rb3_import", "rb3_clone", "rb3_index_free", "rb3_strerror",
            "rb3_prof_enable", "rb3_prof_reset", "rb3_prof_read", "rb3_merge_stats", "rb3_test_fail_merge_after",
-           "rb3_tune_merge", "rb3_tune_smem", "rb3_hapl_opts_init", "rb3_hapl",
+           "rb3_tune_merge", "rb3_tune_smem", "rb3_hapl_opts_init", "rb3_hapl", "rb3_last_hapl_stats",
            "rb3_rle_build", "rb3_rle_load", "rb3_rle_info", "rb3_rle_image", "rb3_rle_export", "rb3_rle_count",
            "rb3_rle_smem", "rb3_rle_hapl", "rb3_rle_free",
            "rb3_server_opts_init", "rb3_server_create", "rb3_server_submit", "rb3_server_poll",
@@ -125,6 +126,8 @@ def lib():
     L.rb3_hapl.argtypes = [_vp, ctypes.POINTER(HaplOpts), _vp, _i64p, _i64, _i32, ctypes.POINTER(HaplRec), _i64,
                            _i64p]
     L.rb3_hapl.restype = ctypes.c_int
+    L.rb3_last_hapl_stats.argtypes = [_i64p, _i64p, _i64p, _i64p]
+    L.rb3_last_hapl_stats.restype = ctypes.c_int
     L.rb3_last_smem_stats.argtypes = [_i64p, _i64p]
     L.rb3_locate.argtypes = [_vp, _vp, _i64, _i32, _i64p, _i64p]
     L.rb3_locate1.argtypes = [_vp, _vp, _vp, _i64, _i32, _i64p, _i64p]
@@ -405,11 +408,11 @@ def rb3_smem(idx: Index, q, qlens, min_len: int, min_occ: int = 1, cap: int | No
 
 
 def hapl_opts(match: int = 1, mismatch: int = 4, gap_open: int = 6, gap_ext: int = 1, band: int = 25,
-              max_cells: int = 4096) -> HaplOpts:
+              max_cells: int = 0, device_tables: bool = False) -> HaplOpts:
     o = HaplOpts()
     lib().rb3_hapl_opts_init(ctypes.byref(o))
     o.match, o.mismatch, o.gap_open, o.gap_ext = int(match), int(mismatch), int(gap_open), int(gap_ext)
-    o.band, o.max_cells = int(band), int(max_cells)
+    o.band, o.max_cells, o.device_tables = int(band), int(max_cells), int(bool(device_tables))
     return o
 
 
@@ -438,6 +441,15 @@ def rb3_hapl(idx: Index, q, qlens, cap: int | None = None, **kw):
     is a structured array (HAPL_DTYPE); query i owns
     records[offsets[i]:offsets[i+1]]."""
     return _hapl_call(lib().rb3_hapl, idx.handle, q, qlens, cap, kw)
+
+
+def rb3_last_hapl_stats() -> dict:
+    """Work of this thread's last haplotype-enumeration call: node extensions,
+    index blocks they read, cells held summed over query positions, and
+    queries moved from LDS to device-memory tables."""
+    e, b, c, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().rb3_last_hapl_stats(ctypes.byref(e), ctypes.byref(b), ctypes.byref(c), ctypes.byref(m)))
+    return {"extensions": e.value, "blocks": b.value, "cells": c.value, "moved": m.value}
 
 
 class Rle:

@@ -53,9 +53,10 @@ def small():
     idx.close()
 
 
+@pytest.mark.parametrize("dev", [False, True])
 @pytest.mark.parametrize("band", [25, 10, 1])
-def test_hapl_matches_oracle_banded(small, band):
-    say(f"case: haplotype enumeration, 3 kb x 6 haplotypes, reads 8-100 bp, band {band}")
+def test_hapl_matches_oracle_banded(small, band, dev):
+    say(f"case: haplotype enumeration, 3 kb x 6 haplotypes, reads 8-100 bp, band {band}, device tables {dev}")
     w, idx, text, codes = small
     qs = _reads(w, 120, 8, 100)
     # exact substrings of indexed haplotypes, reads with N, the empty query
@@ -72,16 +73,32 @@ def test_hapl_matches_oracle_banded(small, band):
     qs.append(bytes(q))
     qs.append(letters[codes[500:540]].tobytes())
     P = synth.pack(qs)
-    recs, off = idx.hapl(P.data, P.lens, band=band)
+    recs, off = idx.hapl(P.data, P.lens, band=band, device_tables=dev)
     _compare(text, qs, recs, off, band=band)
+    st = rb3.rb3_last_hapl_stats()
+    assert st["extensions"] > 0
 
 
-def test_hapl_matches_oracle_unbanded(small):
-    say("case: haplotype enumeration without a band, reads 4-14 bp")
+@pytest.mark.parametrize("dev", [False, True])
+def test_hapl_matches_oracle_unbanded(small, dev):
+    say(f"case: haplotype enumeration without a band, reads 4-14 bp, device tables {dev}")
     w, idx, text, _ = small
     qs = _reads(w, 80, 4, 14, stream=5000)
     P = synth.pack(qs)
+    recs, off = idx.hapl(P.data, P.lens, band=0, max_cells=65535, device_tables=dev)
+    _compare(text, qs, recs, off, band=0)
+
+
+def test_hapl_queries_moved_to_device_tables(small):
+    say("case: haplotype enumeration without a band, reads of 10-20 and of 80-100 bp: the queries whose cells "
+        "outgrow the LDS tables are finished in device memory")
+    w, idx, text, _ = small
+    qs = _reads(w, 30, 10, 20, stream=7000) + _reads(w, 30, 80, 100, sub=0.0, indel=0.0, stream=7100)
+    P = synth.pack(qs)
     recs, off = idx.hapl(P.data, P.lens, band=0, max_cells=65535)
+    st = rb3.rb3_last_hapl_stats()
+    say(f"moved {st['moved']} of {len(qs)}")
+    assert 0 < st["moved"] < len(qs)
     _compare(text, qs, recs, off, band=0)
 
 
@@ -113,7 +130,7 @@ def test_hapl_argument_checks(small):
     say("case: haplotype enumeration argument checks")
     w, idx, _, _ = small
     P = synth.pack(_reads(w, 4, 30, 40))
-    for kw in ({"match": 0}, {"gap_ext": 0}, {"mismatch": -1}, {"band": -1}, {"max_cells": 0},
+    for kw in ({"match": 0}, {"gap_ext": 0}, {"mismatch": -1}, {"band": -1}, {"max_cells": -1},
                {"max_cells": 65536}):
         with pytest.raises(rb3.RB3Error) as e:
             idx.hapl(P.data, P.lens, **kw)
