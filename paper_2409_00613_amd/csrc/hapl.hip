@@ -354,15 +354,20 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
 // 0, scores at minus infinity), so no lane ever waits on another. Scores
 // are raised with LDS atomic max. A query whose cells outgrow the LDS
 // tables is finished by k_hapl instead (cnt = -2).
-constexpr int HW_CAP = 256;  // cells one position may hold in LDS
-constexpr int HW_HS = 512;   // hash slots (a power of two, at least 2 * HW_CAP)
+// CAP = cells one position may hold in LDS: 128 (about 10 KB a wavefront,
+// 15 wavefronts a CU) for bands up to 32, else 256 (about 20 KB).
+constexpr int HW_CAP_SMALL = 128;
+constexpr int HW_CAP_LARGE = 256;
+constexpr int HW_SMALL_BAND = 32;
 
+template <int CAP>
 struct HwLds {
-    int64_t ck[HW_CAP], ckr[HW_CAP], cs[HW_CAP];    // current position's cells
-    int32_t cH[HW_CAP], cE[HW_CAP], cF[HW_CAP], cd[HW_CAP];
-    int32_t slot[HW_HS];                            // cell index + 1, 0 = empty
-    int64_t pk[HW_CAP], pkr[HW_CAP], ps[HW_CAP];    // previous position's cells
-    int32_t pH[HW_CAP], pE[HW_CAP];
+    static constexpr int HS = 2 * CAP;  // hash slots
+    int64_t ck[CAP], ckr[CAP], cs[CAP];  // current position's cells
+    int32_t cH[CAP], cE[CAP], cF[CAP], cd[CAP];
+    int32_t slot[HS];  // cell index + 1, 0 = empty
+    int64_t pk[CAP], pkr[CAP], ps[CAP];  // previous position's cells
+    int32_t pH[CAP], pE[CAP];
     int32_t hist[64];  // positive scores mx - i, for the band's threshold
     int32_t nC, nP, flag, changed, tcount;
 };
@@ -384,10 +389,12 @@ __device__ __forceinline__ uint64_t hw_sum64(uint64_t v) {
 
 // Index of the cell for (k, s), created when absent; -1 when the tables
 // are full.
-__device__ int32_t hw_upsert(HwLds &S, int32_t cap, int64_t k, int64_t kr, int64_t s) {
-    uint32_t h = hp_hash(k, s, HW_HS - 1);
+template <int CAP>
+__device__ int32_t hw_upsert(HwLds<CAP> &S, int32_t cap, int64_t k, int64_t kr, int64_t s) {
+    constexpr int HS = HwLds<CAP>::HS;
+    uint32_t h = hp_hash(k, s, HS - 1);
     int32_t j = -1;
-    for (int probe = 0; probe < HW_HS; ++probe) {
+    for (int probe = 0; probe < HS; ++probe) {
         int32_t v = __hip_atomic_load(&S.slot[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (v == 0) {
             if (j < 0) {
@@ -412,7 +419,7 @@ __device__ int32_t hw_upsert(HwLds &S, int32_t cap, int64_t k, int64_t kr, int64
             if (j >= 0) S.cs[j] = 0;  // the allocation stays unlinked
             return c;
         }
-        h = (h + 1) & (HW_HS - 1);
+        h = (h + 1) & (HS - 1);
     }
     return -1;
 }
@@ -421,7 +428,8 @@ constexpr int HW_BINS = 64;
 
 // Histogram of the positive scores mx - 63 .. mx, mx the highest (bin i
 // counts score mx - i); every lane gets mx and the positive cells' number.
-__device__ void hw_hist_build(HwLds &S, int32_t n, int lane, int32_t *mx_out, int32_t *pos_out) {
+template <int CAP>
+__device__ void hw_hist_build(HwLds<CAP> &S, int32_t n, int lane, int32_t *mx_out, int32_t *pos_out) {
     int32_t mx = 0, c = 0;
     for (int32_t x = lane; x < n; x += 64) {
         const int32_t h = S.cH[x];
@@ -445,7 +453,8 @@ __device__ void hw_hist_build(HwLds &S, int32_t n, int lane, int32_t *mx_out, in
 // The w-th largest positive score from the histogram, when its bins hold
 // at least w cells (else false): *above = cells scoring higher, *ties =
 // cells scoring it. A scan of the 64 bins across the lanes.
-__device__ bool hw_hist_tau(const HwLds &S, int32_t w, int lane, int32_t mx, int32_t *tau, int32_t *above,
+template <int CAP>
+__device__ bool hw_hist_tau(const HwLds<CAP> &S, int32_t w, int lane, int32_t mx, int32_t *tau, int32_t *above,
                             int32_t *ties) {
     const int32_t c = S.hist[lane];
     int32_t v = c;
@@ -466,7 +475,8 @@ __device__ bool hw_hist_tau(const HwLds &S, int32_t w, int lane, int32_t mx, int
 // The same by a binary search over the scores 1 .. mx, each probe a count
 // over the n cells (for thresholds below the histogram's range); the n
 // cells hold at least w positive ones.
-__device__ int32_t hw_kth_search(const HwLds &S, int32_t n, int32_t w, int lane, int32_t mx, int32_t *above,
+template <int CAP>
+__device__ int32_t hw_kth_search(const HwLds<CAP> &S, int32_t n, int32_t w, int lane, int32_t mx, int32_t *above,
                                  int32_t *ties) {
     int32_t lo = 1, hi = mx;  // the largest v with w or more scores >= v
     while (lo < hi) {
@@ -488,15 +498,15 @@ __device__ int32_t hw_kth_search(const HwLds &S, int32_t n, int32_t w, int lane,
     return lo;
 }
 
-// One block of 64 threads (one wavefront) per query; cap <= HW_CAP cells
+// One block of 64 threads (one wavefront) per query; cap <= CAP cells
 // per position. Results (at most outcap) go to wout[qi * outcap ..] in
 // order, cnt[qi] = their number, or -2 when the cells outgrew cap.
-template <class V>
+template <class V, int CAP>
 __global__ __launch_bounds__(64) void k_hapl_wave(V ix, const uint8_t *__restrict__ Q,
                                                   const int64_t *__restrict__ qoff, HpParams p, int32_t cap,
                                                   int32_t outcap, int64_t qbase, rb3_hapl_t *__restrict__ wout,
                                                   int32_t *__restrict__ cnt, unsigned long long *__restrict__ stats) {
-    __shared__ HwLds S;
+    __shared__ HwLds<CAP> S;
     const int64_t qi = blockIdx.x;
     const int lane = threadIdx.x;
     const uint8_t *P = Q + qoff[qi];
@@ -515,7 +525,7 @@ __global__ __launch_bounds__(64) void k_hapl_wave(V ix, const uint8_t *__restric
     bool over = false;
     for (int64_t t = L - 1; t >= 0; --t) {
         const uint32_t a = P[t];
-        for (int h = lane; h < HW_HS; h += 64) S.slot[h] = 0;
+        for (int h = lane; h < HwLds<CAP>::HS; h += 64) S.slot[h] = 0;
         if (lane == 0) S.nC = 0;
         __syncthreads();
         const int32_t nP = S.nP;
@@ -773,7 +783,8 @@ static int hapl_run_v(Ctx &c, const V &view, const char *name, const char *wname
     while (h < 2 * o.max_cells) h <<= 1;
     p.hcap = h;
     const bool wave = !o.device_tables;
-    const int32_t wcap = std::min<int32_t>(HW_CAP, o.max_cells);
+    const bool large = o.band == 0 || o.band > HW_SMALL_BAND;
+    const int32_t wcap = std::min<int32_t>(large ? HW_CAP_LARGE : HW_CAP_SMALL, o.max_cells);
     const int32_t outcap = o.band > 0 ? std::min<int32_t>(o.band, wcap) : wcap;
     std::vector<int64_t> qoff(nq + 1);
     qoff[0] = 0;
@@ -804,9 +815,14 @@ static int hapl_run_v(Ctx &c, const V &view, const char *name, const char *wname
         const int64_t m = std::min(chunk, nq - q0);
         sub.clear();
         if (wave) {
-            RB3_LAUNCH(wname, k_hapl_wave<V>, dim3((uint32_t)m), dim3(64), 0, c.stream, view, d_codes,
-                       dq.as<int64_t>() + q0, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(), wcnt.as<int32_t>(),
-                       dst.as<unsigned long long>());
+            if (large)
+                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_LARGE>), dim3((uint32_t)m), dim3(64), 0, c.stream, view,
+                           d_codes, dq.as<int64_t>() + q0, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(),
+                           wcnt.as<int32_t>(), dst.as<unsigned long long>());
+            else
+                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_SMALL>), dim3((uint32_t)m), dim3(64), 0, c.stream, view,
+                           d_codes, dq.as<int64_t>() + q0, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(),
+                           wcnt.as<int32_t>(), dst.as<unsigned long long>());
             RB3_HIP(hipMemcpyAsync(hc.data(), wcnt.p, m * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipStreamSynchronize(c.stream));
             for (int64_t i = 0; i < m; ++i)

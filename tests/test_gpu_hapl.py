@@ -54,7 +54,7 @@ def small():
 
 
 @pytest.mark.parametrize("dev", [False, True])
-@pytest.mark.parametrize("band", [25, 10, 1])
+@pytest.mark.parametrize("band", [40, 25, 10, 1])
 def test_hapl_matches_oracle_banded(small, band, dev):
     say(f"case: haplotype enumeration, 3 kb x 6 haplotypes, reads 8-100 bp, band {band}, device tables {dev}")
     w, idx, text, codes = small
