@@ -264,7 +264,8 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
             "config": config, "roofline": roof, "tuning": tuning, "run_length": rle, "hapl": hapl}
 
 
-def hapl_bench(idx, n, queries, n_index, steps, n_reads=200_000, read_len=125, bands=(10, 25)):
+def hapl_bench(idx, n, queries, n_index, steps, n_reads=200_000, read_len=125, bands=(10, 25),
+               long_reads=4000, long_len=10_000):
     """Local haplotype enumeration (revised BWA-SW, semi-global) of short
     reads on the serving index: n_reads windows of read_len bases cut at
     seeded offsets from the serving queries (excerpts of unindexed
@@ -317,6 +318,29 @@ def hapl_bench(idx, n, queries, n_index, steps, n_reads=200_000, read_len=125, b
                          "algorithmic_bytes_per_launch": ab, "avg_launch_ms": k_ms}}
         log(f"haplotype enumeration, band {band}: {rate / 1e6:.2f} M bases/s ({n_reads} reads of {read_len}), "
             f"kernel {k_ms:.1f} ms, {hs['extensions'] / bases:.2f} extensions/base, {int(off[-1])} results")
+    # long reads (the paper's long-read rows use band 25): windows of
+    # long_len bases of the serving queries, one call
+    if long_reads > 0:
+        lq = np.nonzero(lens >= long_len)[0]
+        pick = lq[g.integers(0, lq.shape[0], long_reads)]
+        st = offs[pick] + (g.random(long_reads) * (lens[pick] - long_len + 1)).astype(np.int64)
+        data = queries.data[(st[:, None] + np.arange(long_len)[None, :]).ravel()]
+        ldev = torch.from_numpy(np.ascontiguousarray(data)).cuda()
+        llens = np.full(long_reads, long_len, np.int64)
+        torch.cuda.synchronize()
+        idx.hapl(ldev, llens, band=25)  # warm-up
+        t0 = time.perf_counter()
+        recs, off = idx.hapl(ldev, llens, band=25)
+        t1 = time.perf_counter()
+        hs = rb3.rb3_last_hapl_stats()
+        lb = long_reads * long_len
+        out["long_reads"] = {"reads": long_reads, "read_len": long_len, "band": 25,
+                             "bases_per_s": round(lb / (t1 - t0), 1), "ms_per_call": round((t1 - t0) * 1e3, 3),
+                             "results": int(off[-1]), "reads_with_results": int(np.count_nonzero(np.diff(off))),
+                             "extensions_per_base": round(hs["extensions"] / lb, 3),
+                             "reads_moved_to_device_tables": hs["moved"]}
+        log(f"haplotype enumeration of long reads, band 25: {lb / (t1 - t0) / 1e6:.2f} M bases/s "
+            f"({long_reads} reads of {long_len}), {int(off[-1])} results, {hs['moved']} reads moved")
     return out
 
 
