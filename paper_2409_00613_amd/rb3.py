@@ -422,7 +422,10 @@ def _hapl_call(fn, handle, q, qlens, cap, kw):
     n = la.shape[0]
     o = hapl_opts(**kw)
     if cap is None:
-        cap = max(1024, 8 * n)
+        # a query keeps at most `band` results; without a band, a guess
+        # (a call that needs more is repeated with the exact size)
+        per = o.band if 0 < o.band <= 64 else 64
+        cap = min(max(1024, per * n), 1 << 24)
     while True:
         out = np.zeros(max(cap, 1), dtype=HAPL_DTYPE)
         off = np.zeros(n + 1, np.int64)
