@@ -1613,6 +1613,20 @@ __global__ void __launch_bounds__(256) k_tie_walk(const uint64_t *__restrict__ Q
 // their new places, measures the new subgroups and keeps only those whose
 // members carry different symbols. A split moves members, so the round ends
 // there and the next one loads from the following depth.
+//
+// Ranking inside subgroups. Near-identical members split a few at a time:
+// when at most TB_MINOR members hold a chunk other than their subgroup
+// head's, each member counts only those (the head's chunk holds no
+// sentinel, so its members keep their place order). Otherwise, while every
+// mixed subgroup has at most TB_SORT_MIN members, each member counts the
+// members of its subgroup that go before it; a larger one (which would
+// cost the square of its size) makes the workgroup sort all places by
+// (subgroup, chunk, strand position for sentinel chunks or else place)
+// with a bitonic network over an index array, and a member's new subgroup
+// starts at the first place holding its chunk, found by binary search.
+constexpr int TB_SORT_MIN = 256;
+constexpr int TB_MINOR = 256;
+
 template <int T, int MPT, int DEPTHS, bool SMP>
 __global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ Q, int64_t n2, const uint32_t *__restrict__ SV,
                                                  const uint32_t *__restrict__ glist, int64_t ng,
@@ -1629,6 +1643,9 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ Q,
     __shared__ uint8_t se[MAXK];    // the member's BWT symbol
     __shared__ uint8_t sact[MAXK];  // the member's subgroup still mixes symbols
     __shared__ uint8_t snew[MAXK];  // per new subgroup: still mixed
+    __shared__ int smx, snm, shs;   // largest mixed subgroup, minority count, a head's chunk ends a strand
+    __shared__ uint16_t sminor[TB_MINOR];  // places of the minority
+    uint16_t *const perm = ssz;     // the sort's index array (sizes are remeasured after it)
     const int tid = threadIdx.x;
     uint64_t reads = 0;
     int64_t maxd = 0;
@@ -1691,9 +1708,144 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ Q,
                     }
                 }
                 if (!__syncthreads_or(sp)) continue;
-                // rank every member of a mixed subgroup inside it
+                // rank every member of a mixed subgroup inside it: list the
+                // members whose chunk differs from their subgroup head's
+                // (the minority) and find the largest mixed subgroup
+                if (tid == 0) {
+                    smx = 0;
+                    snm = 0;
+                    shs = 0;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < MPT; ++j) {
+                    const int o = tid + j * T;
+                    if (o < k && sact[o]) {
+                        const int S = ssub[o];
+                        if (sc[o] != sc[S]) {
+                            const int d = atomicAdd(&snm, 1);
+                            if (d < TB_MINOR) sminor[d] = (uint16_t)o;
+                        }
+                        if (o == S) {
+                            atomicMax(&smx, (int)ssz[o]);
+                            if (chunk_has_sentinel(sc[o])) shs = 1;
+                        }
+                    }
+                }
+                __syncthreads();
+                const int nminor = snm;
+                const bool byminor = nminor <= TB_MINOR && !shs;
+                const bool bysort = !byminor && smx > TB_SORT_MIN;
                 uint32_t r_no[MPT], r_sub[MPT], r_pos[MPT];
                 uint8_t r_e[MPT], r_a[MPT];
+                if (byminor) {
+                    // a member's rank: minority members of its subgroup
+                    // below it, plus, for a minority member above its
+                    // head's chunk, the head's (majority) members; equal
+                    // non-sentinel chunks keep their place order
+#pragma unroll
+                    for (int j = 0; j < MPT; ++j) {
+                        const int o = tid + j * T;
+                        r_no[j] = r_sub[j] = r_pos[j] = 0;
+                        r_e[j] = r_a[j] = 0;
+                        if (o < k) {
+                            r_pos[j] = spos[o];
+                            r_e[j] = se[o];
+                            r_a[j] = sact[o];
+                            const int S = ssub[o];
+                            r_no[j] = (uint32_t)o;
+                            r_sub[j] = (uint32_t)S;
+                            if (r_a[j]) {
+                                const uint64_t v = sc[o], H = sc[S];
+                                const bool sv = chunk_has_sentinel(v);
+                                uint32_t less = 0, eqb = 0, nm = 0, nmb = 0;
+                                for (int q = 0; q < nminor; ++q) {
+                                    const int x = sminor[q];
+                                    if (ssub[x] != S) continue;
+                                    const uint64_t w = sc[x];
+                                    ++nm;
+                                    nmb += x < o ? 1u : 0u;
+                                    less += (w < v || (w == v && sv && spos[x] < r_pos[j])) ? 1u : 0u;
+                                    eqb += (w == v && !sv && x < o) ? 1u : 0u;
+                                }
+                                if (v == H) {
+                                    // majority: the minority below it, then the
+                                    // majority members at earlier places
+                                    eqb = (uint32_t)(o - S) - nmb;
+                                } else if (H < v) {
+                                    less += (uint32_t)ssz[S] - nm;
+                                }
+                                r_no[j] = (uint32_t)S + less + eqb;
+                                r_sub[j] = (uint32_t)S + less;
+                            }
+                        }
+                    }
+                } else if (bysort) {
+                    int P = 1;
+                    while (P < k) P <<= 1;
+                    __syncthreads();  // every thread has read smx and ssz before perm overwrites them
+                    for (int i = tid; i < P; i += T) perm[i] = (uint16_t)i;
+                    __syncthreads();
+                    // key of place a: (subgroup, chunk, strand position of a
+                    // sentinel chunk or else the place); places past k last
+                    auto gt = [&](int a, int b) -> bool {
+                        if (a >= k) return b < k || a > b;
+                        if (b >= k) return false;
+                        const int sa = ssub[a], sb = ssub[b];
+                        if (sa != sb) return sa > sb;
+                        const bool act = sact[a];
+                        const uint64_t va = act ? sc[a] : 0ull, vb = act ? sc[b] : 0ull;
+                        if (va != vb) return va > vb;
+                        const bool sent = act && chunk_has_sentinel(va);
+                        const uint32_t ta = sent ? spos[a] : (uint32_t)a, tb = sent ? spos[b] : (uint32_t)b;
+                        return ta > tb;
+                    };
+                    for (int size = 2; size <= P; size <<= 1) {
+                        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                            for (int i = tid; i < (P >> 1); i += T) {
+                                const int lo = (i / stride) * 2 * stride + (i % stride), hi = lo + stride;
+                                const int a = perm[lo], b = perm[hi];
+                                if (gt(a, b) == ((lo & size) == 0)) {
+                                    perm[lo] = (uint16_t)b;
+                                    perm[hi] = (uint16_t)a;
+                                }
+                            }
+                            __syncthreads();
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < MPT; ++j) {
+                        const int i = tid + j * T;  // the new place
+                        r_no[j] = r_sub[j] = r_pos[j] = 0;
+                        r_e[j] = r_a[j] = 0;
+                        if (i < k) {
+                            const int o = perm[i];
+                            const int S = ssub[o];
+                            r_no[j] = (uint32_t)i;
+                            r_pos[j] = spos[o];
+                            r_e[j] = se[o];
+                            r_a[j] = sact[o];
+                            r_sub[j] = (uint32_t)S;
+                            if (r_a[j]) {
+                                const uint64_t v = sc[o];
+                                if (chunk_has_sentinel(v)) {
+                                    r_sub[j] = (uint32_t)i;
+                                } else {
+                                    // the first place of the subgroup holding v
+                                    int lo = S, hi = i;
+                                    while (lo < hi) {
+                                        const int mid = (lo + hi) >> 1;
+                                        if (sc[perm[mid]] < v)
+                                            lo = mid + 1;
+                                        else
+                                            hi = mid;
+                                    }
+                                    r_sub[j] = (uint32_t)lo;
+                                }
+                            }
+                        }
+                    }
+                } else {
 #pragma unroll
                 for (int j = 0; j < MPT; ++j) {
                     const int o = tid + j * T;
@@ -1722,6 +1874,7 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ Q,
                         }
                     }
                 }
+                }
                 __syncthreads();
 #pragma unroll
                 for (int j = 0; j < MPT; ++j) {
@@ -1735,20 +1888,39 @@ __global__ void __launch_bounds__(T) k_tie_block(const uint64_t *__restrict__ Q,
                     }
                 }
                 __syncthreads();
-                // the first member of each new subgroup measures it
+                // measure the new subgroups: each member raises its
+                // subgroup's last place and clears its uniform flag when its
+                // symbol differs from the first member's or it is sampled
+                // (the chunks are reloaded before the next comparison, so
+                // their array holds the two counters meanwhile)
+                uint32_t *const mlast = reinterpret_cast<uint32_t *>(sc);
+                uint32_t *const muni = mlast + MAXK;
 #pragma unroll
                 for (int j = 0; j < MPT; ++j) {
                     const int o = tid + j * T;
                     if (o < k && sact[o] && ssub[o] == o) {
-                        const uint8_t e0 = se[o];
-                        bool uni = !sampled_pos(spos[o], e0, sr);
-                        int x = o + 1;
-                        while (x < k && ssub[x] == o) {
-                            uni &= se[x] == e0 && !sampled_pos(spos[x], se[x], sr);
-                            ++x;
-                        }
-                        ssz[o] = (uint16_t)(x - o);
-                        snew[o] = (x - o >= 2 && !uni) ? 1 : 0;
+                        mlast[o] = (uint32_t)o;
+                        muni[o] = 1u;
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < MPT; ++j) {
+                    const int o = tid + j * T;
+                    if (o < k && sact[o]) {
+                        const int S = ssub[o];
+                        if (o != S) atomicMax(&mlast[S], (uint32_t)o);
+                        if (se[o] != se[S] || sampled_pos(spos[o], se[o], sr)) atomicAnd(&muni[S], 0u);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < MPT; ++j) {
+                    const int o = tid + j * T;
+                    if (o < k && sact[o] && ssub[o] == o) {
+                        const uint32_t size = mlast[o] - (uint32_t)o + 1u;
+                        ssz[o] = (uint16_t)size;
+                        snew[o] = (size >= 2 && !muni[o]) ? 1 : 0;
                     }
                 }
                 __syncthreads();

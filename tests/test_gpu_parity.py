@@ -350,7 +350,7 @@ def test_smem_small_capacity_reports_sizes(tiny):
 
 
 @pytest.mark.parametrize("copies,tail_len,muts", [(6, 300, 0), (40, 300, 0), (70, 300, 0), (70, 300, 2),
-                                                  (200, 300, 2), (1000, 200, 3), (9000, 40, 0)])
+                                                  (200, 300, 2), (1000, 200, 3), (5000, 120, 2), (9000, 40, 0)])
 def test_large_mixed_symbol_groups(copies, tail_len, muts):
     """Many new strings sharing a long tail after different first bases:
     one tied group per position of the shared part, with mixed BWT symbols
