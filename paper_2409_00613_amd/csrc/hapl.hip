@@ -343,19 +343,28 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
 }
 
 // ---------------------------------------------------------------------------
-// One wavefront per query, cells in LDS
+// Queries on wavefronts, cells in LDS
 // ---------------------------------------------------------------------------
 //
-// The lanes share the query's cells: each extends its own cells (so up to
-// 64 rank-all pairs of one query are in flight together) and inserts the
-// results into a hash in LDS. A cell is claimed by allocating it, writing
-// its key and publishing it in a hash slot with a compare-and-swap; a lane
-// that loses the race to an equal key leaves its allocation unlinked (s =
-// 0, scores at minus infinity), so no lane ever waits on another. Scores
-// are raised with LDS atomic max. A query whose cells outgrow the LDS
-// tables is finished by k_hapl instead (cnt = -2).
-// CAP = cells one position may hold in LDS: 128 (about 10 KB a wavefront,
-// 15 wavefronts a CU) for bands up to 32, else 256 (about 20 KB).
+// A query gets 64 / QPW lanes of one wavefront (QPW = 1 or 2 queries a
+// wavefront). The lanes share the query's cells: each extends its own cells
+// (so up to that many rank-all pairs of one query are in flight together)
+// and inserts the results into a hash in LDS. A cell is claimed by
+// allocating it, writing its key and publishing it in a hash slot with a
+// compare-and-swap; a lane that loses the race to an equal key leaves its
+// allocation unlinked (s = 0, scores at minus infinity), so no lane ever
+// waits on another. Scores are raised with LDS atomic max. A query whose
+// cells outgrow the LDS tables is finished by k_hapl instead (cnt = -2).
+// The wavefront's barriers are reached by all its lanes: the queries of a
+// wavefront step through their positions and deletion rounds together, a
+// query that has finished (or moved) idling.
+//
+// CAP = cells one position may hold in LDS: 64 with two queries a
+// wavefront for bands up to 12 (about 11 KB a wavefront; registers for four
+// wavefronts a SIMD, so 32 queries a CU), 128 for bands up to 32 (about
+// 10 KB, 15 queries a CU), else 256 (about 20 KB).
+constexpr int HW_CAP_PAIR = 64;
+constexpr int HW_PAIR_BAND = 12;
 constexpr int HW_CAP_SMALL = 128;
 constexpr int HW_CAP_LARGE = 256;
 constexpr int HW_SMALL_BAND = 32;
@@ -372,18 +381,29 @@ struct HwLds {
     int32_t nC, nP, flag, changed, tcount;
 };
 
+// Reductions over the HW lanes of one query (HW = 64 or 32).
+template <int HW>
 __device__ __forceinline__ int32_t hw_sum(int32_t v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    for (int o = HW / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
+template <int HW>
 __device__ __forceinline__ int32_t hw_maxr(int32_t v) {
-    for (int o = 32; o > 0; o >>= 1) v = hp_max(v, __shfl_xor(v, o));
+    for (int o = HW / 2; o > 0; o >>= 1) v = hp_max(v, __shfl_xor(v, o));
     return v;
 }
 
 __device__ __forceinline__ uint64_t hw_sum64(uint64_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int64_t hw_max64(int64_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
     return v;
 }
 
@@ -424,48 +444,50 @@ __device__ int32_t hw_upsert(HwLds<CAP> &S, int32_t cap, int64_t k, int64_t kr, 
     return -1;
 }
 
-constexpr int HW_BINS = 64;
-
-// Histogram of the positive scores mx - 63 .. mx, mx the highest (bin i
-// counts score mx - i); every lane gets mx and the positive cells' number.
-template <int CAP>
-__device__ void hw_hist_build(HwLds<CAP> &S, int32_t n, int lane, int32_t *mx_out, int32_t *pos_out) {
+// Histogram of the positive scores mx - (HW - 1) .. mx, mx the highest
+// (bin i counts score mx - i), in two steps around a barrier: the maximum,
+// the positive cells' number and cleared bins, then the counts.
+template <int HW, int CAP>
+__device__ void hw_hist_start(HwLds<CAP> &S, int32_t n, int hl, int32_t *mx_out, int32_t *pos_out) {
     int32_t mx = 0, c = 0;
-    for (int32_t x = lane; x < n; x += 64) {
+    for (int32_t x = hl; x < n; x += HW) {
         const int32_t h = S.cH[x];
         if (h > 0) {
             ++c;
             mx = hp_max(mx, h);
         }
     }
-    *pos_out = hw_sum(c);
-    mx = hw_maxr(mx);
-    *mx_out = mx;
-    S.hist[lane] = 0;
-    __syncthreads();
-    for (int32_t x = lane; x < n; x += 64) {
+    *pos_out = hw_sum<HW>(c);
+    *mx_out = hw_maxr<HW>(mx);
+    S.hist[hl] = 0;
+}
+
+template <int HW, int CAP>
+__device__ void hw_hist_fill(HwLds<CAP> &S, int32_t n, int hl, int32_t mx) {
+    for (int32_t x = hl; x < n; x += HW) {
         const int32_t h = S.cH[x];
-        if (h > 0 && mx - h < HW_BINS) atomicAdd(&S.hist[mx - h], 1);
+        if (h > 0 && mx - h < HW) atomicAdd(&S.hist[mx - h], 1);
     }
-    __syncthreads();
 }
 
 // The w-th largest positive score from the histogram, when its bins hold
 // at least w cells (else false): *above = cells scoring higher, *ties =
-// cells scoring it. A scan of the 64 bins across the lanes.
-template <int CAP>
-__device__ bool hw_hist_tau(const HwLds<CAP> &S, int32_t w, int lane, int32_t mx, int32_t *tau, int32_t *above,
-                            int32_t *ties) {
-    const int32_t c = S.hist[lane];
+// cells scoring it. A scan of the bins across the query's lanes; hbase is
+// the first lane of the query in the wavefront.
+template <int HW, int CAP>
+__device__ bool hw_hist_tau(const HwLds<CAP> &S, int32_t w, int hl, int hbase, int32_t mx, int32_t *tau,
+                            int32_t *above, int32_t *ties) {
+    const int32_t c = S.hist[hl];
     int32_t v = c;
-    for (int d = 1; d < 64; d <<= 1) {
-        const int32_t u = __shfl_up(v, d);
-        if (lane >= d) v += u;
+    for (int d = 1; d < HW; d <<= 1) {
+        const int32_t u = __shfl_up(v, d, HW);
+        if (hl >= d) v += u;
     }
-    const unsigned long long m = __ballot(v >= w);
+    unsigned long long m = __ballot(v >= w);
+    if (HW < 64) m = (m >> hbase) & ((1ull << HW) - 1ull);
     if (m == 0) return false;
     const int i = __ffsll(m) - 1;
-    const int32_t vi = __shfl(v, i), ci = __shfl(c, i);
+    const int32_t vi = __shfl(v, hbase + i), ci = __shfl(c, hbase + i);
     *tau = mx - i;
     *above = vi - ci;
     *ties = ci;
@@ -475,44 +497,51 @@ __device__ bool hw_hist_tau(const HwLds<CAP> &S, int32_t w, int lane, int32_t mx
 // The same by a binary search over the scores 1 .. mx, each probe a count
 // over the n cells (for thresholds below the histogram's range); the n
 // cells hold at least w positive ones.
-template <int CAP>
-__device__ int32_t hw_kth_search(const HwLds<CAP> &S, int32_t n, int32_t w, int lane, int32_t mx, int32_t *above,
+template <int HW, int CAP>
+__device__ int32_t hw_kth_search(const HwLds<CAP> &S, int32_t n, int32_t w, int hl, int32_t mx, int32_t *above,
                                  int32_t *ties) {
     int32_t lo = 1, hi = mx;  // the largest v with w or more scores >= v
     while (lo < hi) {
         const int32_t mid = lo + ((hi - lo + 1) >> 1);
         int32_t k = 0;
-        for (int32_t x = lane; x < n; x += 64) k += S.cH[x] >= mid;
-        if (hw_sum(k) >= w)
+        for (int32_t x = hl; x < n; x += HW) k += S.cH[x] >= mid;
+        if (hw_sum<HW>(k) >= w)
             lo = mid;
         else
             hi = mid - 1;
     }
     int32_t ka = 0, kt = 0;
-    for (int32_t x = lane; x < n; x += 64) {
+    for (int32_t x = hl; x < n; x += HW) {
         ka += S.cH[x] > lo;
         kt += S.cH[x] == lo;
     }
-    *above = hw_sum(ka);
-    *ties = hw_sum(kt);
+    *above = hw_sum<HW>(ka);
+    *ties = hw_sum<HW>(kt);
     return lo;
 }
 
-// One block of 64 threads (one wavefront) per query; cap <= CAP cells
-// per position. Results (at most outcap) go to wout[qi * outcap ..] in
-// order, cnt[qi] = their number, or -2 when the cells outgrew cap.
-template <class V, int CAP>
-__global__ __launch_bounds__(64) void k_hapl_wave(V ix, const uint8_t *__restrict__ Q,
-                                                  const int64_t *__restrict__ qoff, HpParams p, int32_t cap,
-                                                  int32_t outcap, int64_t qbase, rb3_hapl_t *__restrict__ wout,
-                                                  int32_t *__restrict__ cnt, unsigned long long *__restrict__ stats) {
-    __shared__ HwLds<CAP> S;
-    const int64_t qi = blockIdx.x;
+// One block of 64 threads (one wavefront) holds QPW queries; cap <= CAP
+// cells per position. Query qi's results (at most outcap) go to
+// wout[qi * outcap ..] in order, cnt[qi] = their number, or -2 when its
+// cells outgrew cap.
+template <class V, int CAP, int QPW>
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(CAP > 128 ? 2 : 4))) void k_hapl_wave(V ix, const uint8_t *__restrict__ Q,
+                                                  const int64_t *__restrict__ qoff, int64_t nq, HpParams p,
+                                                  int32_t cap, int32_t outcap, int64_t qbase,
+                                                  rb3_hapl_t *__restrict__ wout, int32_t *__restrict__ cnt,
+                                                  unsigned long long *__restrict__ stats) {
+    constexpr int HW = 64 / QPW;  // lanes a query
+    __shared__ HwLds<CAP> SS[QPW];
     const int lane = threadIdx.x;
-    const uint8_t *P = Q + qoff[qi];
-    const int64_t L = qoff[qi + 1] - qoff[qi];
+    const int hq = lane / HW, hl = lane % HW, hbase = hq * HW;
+    HwLds<CAP> &S = SS[hq];
+    const int64_t qi = blockIdx.x * (int64_t)QPW + hq;
+    const bool real = qi < nq;
+    const uint8_t *P = Q + (real ? qoff[qi] : 0);
+    const int64_t L = real ? qoff[qi + 1] - qoff[qi] : 0;
+    const int64_t Lmax = hw_max64(L);
     uint64_t n_ext = 0, n_units = 0, n_cells = 0;
-    if (lane == 0) {
+    if (hl == 0) {
         S.pk[0] = 0;
         S.pkr[0] = 0;
         S.ps[0] = ix.size();
@@ -522,78 +551,23 @@ __global__ __launch_bounds__(64) void k_hapl_wave(V ix, const uint8_t *__restric
         S.flag = 0;
     }
     __syncthreads();
-    bool over = false;
-    for (int64_t t = L - 1; t >= 0; --t) {
-        const uint32_t a = P[t];
-        for (int h = lane; h < HwLds<CAP>::HS; h += 64) S.slot[h] = 0;
-        if (lane == 0) S.nC = 0;
+    bool over = false;  // the cells outgrew the tables: the query moves
+    for (int64_t step = 0; step < Lmax; ++step) {
+        bool on = step < L && !over;
+        const uint32_t a = on ? P[L - 1 - step] : 0u;
+        if (on) {
+            for (int h = hl; h < HwLds<CAP>::HS; h += HW) S.slot[h] = 0;
+            if (hl == 0) S.nC = 0;
+        }
         __syncthreads();
-        const int32_t nP = S.nP;
         // match / mismatch and insertion from the previous position's cells
-        for (int32_t x = lane; x < nP; x += 64) {
-            const int64_t k = S.pk[x], kr = S.pkr[x], sz = S.ps[x];
-            const int32_t H = S.pH[x], E = S.pE[x];
-            int64_t ck[4], ckr[4], cs[4];
-            hp_children(ix, k, kr, sz, ck, ckr, cs);
-            ++n_ext;
-            n_units += ix.units(k, k + sz);
-            bool bad = false;
-#pragma unroll 1
-            for (int b = 0; b < 4; ++b) {
-                const int64_t sb = hp_pick(cs, b);
-                if (!bad && sb > 0) {
-                    const int32_t j = hw_upsert(S, cap, hp_pick(ck, b), hp_pick(ckr, b), sb);
-                    if (j < 0)
-                        bad = true;
-                    else
-                        atomicMax(&S.cH[j], H + ((uint32_t)(b + 1) == a ? p.match : -p.mismatch));
-                }
-            }
-            if (!bad) {
-                const int32_t j = hw_upsert(S, cap, k, kr, sz);
-                if (j < 0) {
-                    bad = true;
-                } else {
-                    const int32_t e = hp_max(H - p.gap_open, E) - p.gap_ext;
-                    atomicMax(&S.cE[j], e);
-                    atomicMax(&S.cH[j], e);
-                }
-            }
-            if (bad) S.flag = 1;
-        }
-        __syncthreads();
-        if (S.flag) {
-            over = true;
-            break;
-        }
-        // the band's threshold so far: the histogram of the top 64 scores
-        // is kept up to date through the deletion step (hm) when it holds
-        // the band, else a search gives a fixed lower bound
-        int32_t mx = 0, pos = 0, tau = 1, above = 0, ties = 0;
-        bool hm = false;
-        if (p.band > 0) {
-            hw_hist_build(S, S.nC, lane, &mx, &pos);
-            if (pos >= p.band) {
-                hm = hw_hist_tau(S, p.band, lane, mx, &tau, &above, &ties);
-                if (!hm) tau = hw_kth_search(S, S.nC, p.band, lane, mx, &above, &ties);
-            }
-        }
-        // deletion in rounds until no cell improves; a round extends the
-        // dirty cells present at its start
-        for (;;) {
-            if (lane == 0) S.changed = 0;
-            __syncthreads();
-            if (hm) hw_hist_tau(S, p.band, lane, mx, &tau, &above, &ties);  // tau only rises
-            const int32_t n0 = S.nC;
-            for (int32_t x = lane; x < n0; x += 64) {
-                if (!S.cd[x]) continue;
-                S.cd[x] = 0;
-                const int32_t H = S.cH[x];
-                const int32_t f = hp_max(H - p.gap_open, S.cF[x]) - p.gap_ext;
-                if (f <= 0 || f < tau || H <= 0) continue;
-                const int64_t k = S.ck[x], sz = S.cs[x];
+        if (on) {
+            const int32_t nP = S.nP;
+            for (int32_t x = hl; x < nP; x += HW) {
+                const int64_t k = S.pk[x], kr = S.pkr[x], sz = S.ps[x];
+                const int32_t H = S.pH[x], E = S.pE[x];
                 int64_t ck[4], ckr[4], cs[4];
-                hp_children(ix, k, S.ckr[x], sz, ck, ckr, cs);
+                hp_children(ix, k, kr, sz, ck, ckr, cs);
                 ++n_ext;
                 n_units += ix.units(k, k + sz);
                 bool bad = false;
@@ -602,66 +576,137 @@ __global__ __launch_bounds__(64) void k_hapl_wave(V ix, const uint8_t *__restric
                     const int64_t sb = hp_pick(cs, b);
                     if (!bad && sb > 0) {
                         const int32_t j = hw_upsert(S, cap, hp_pick(ck, b), hp_pick(ckr, b), sb);
-                        if (j < 0) {
+                        if (j < 0)
                             bad = true;
-                        } else if (atomicMax(&S.cF[j], f) < f) {
-                            const int32_t old = atomicMax(&S.cH[j], f);
-                            // a deletion never tops its parent, so f < mx
-                            if (hm && old < f) {
-                                if (old > 0 && mx - old < HW_BINS) atomicSub(&S.hist[mx - old], 1);
-                                if (mx - f < HW_BINS) atomicAdd(&S.hist[mx - f], 1);
-                            }
-                            S.cd[j] = 1;
-                            S.changed = 1;
-                        }
+                        else
+                            atomicMax(&S.cH[j], H + ((uint32_t)(b + 1) == a ? p.match : -p.mismatch));
+                    }
+                }
+                if (!bad) {
+                    const int32_t j = hw_upsert(S, cap, k, kr, sz);
+                    if (j < 0) {
+                        bad = true;
+                    } else {
+                        const int32_t e = hp_max(H - p.gap_open, E) - p.gap_ext;
+                        atomicMax(&S.cE[j], e);
+                        atomicMax(&S.cH[j], e);
                     }
                 }
                 if (bad) S.flag = 1;
             }
+        }
+        __syncthreads();
+        if (on && S.flag) over = true;
+        on = on && !over;
+        // the band's threshold so far: the histogram of the top HW scores
+        // is kept up to date through the deletion step (hm) when it holds
+        // the band, else a search gives a fixed lower bound
+        int32_t mx = 0, pos = 0, tau = 1, above = 0, ties = 0;
+        bool hm = false;
+        const bool banded = on && p.band > 0;
+        if (banded) hw_hist_start<HW>(S, S.nC, hl, &mx, &pos);
+        __syncthreads();
+        if (banded) hw_hist_fill<HW>(S, S.nC, hl, mx);
+        __syncthreads();
+        if (banded && pos >= p.band) {
+            hm = hw_hist_tau<HW>(S, p.band, hl, hbase, mx, &tau, &above, &ties);
+            if (!hm) tau = hw_kth_search<HW>(S, S.nC, p.band, hl, mx, &above, &ties);
+        }
+        // deletion in rounds until no cell improves; a round extends the
+        // dirty cells present at its start
+        bool dl = on;
+        for (;;) {
+            if (dl && hl == 0) S.changed = 0;
             __syncthreads();
-            if (S.flag || !S.changed) break;
-        }
-        if (S.flag) {
-            over = true;
-            break;
-        }
-        // keep H > 0; with a band, the W best (ties: smaller k, then s)
-        const int32_t nC = S.nC;
-        n_cells += (uint64_t)nC;
-        bool cut = false;
-        if (p.band > 0) {
-            if (hm) {
-                hw_hist_tau(S, p.band, lane, mx, &tau, &above, &ties);
-                cut = true;
-            } else {
-                hw_hist_build(S, nC, lane, &mx, &pos);
-                if (pos >= p.band) {
-                    if (!hw_hist_tau(S, p.band, lane, mx, &tau, &above, &ties))
-                        tau = hw_kth_search(S, nC, p.band, lane, mx, &above, &ties);
-                    cut = true;
+            if (dl) {
+                if (hm) hw_hist_tau<HW>(S, p.band, hl, hbase, mx, &tau, &above, &ties);  // tau only rises
+                const int32_t n0 = S.nC;
+                for (int32_t x = hl; x < n0; x += HW) {
+                    if (!S.cd[x]) continue;
+                    S.cd[x] = 0;
+                    const int32_t H = S.cH[x];
+                    const int32_t f = hp_max(H - p.gap_open, S.cF[x]) - p.gap_ext;
+                    if (f <= 0 || f < tau || H <= 0) continue;
+                    const int64_t k = S.ck[x], sz = S.cs[x];
+                    int64_t ck[4], ckr[4], cs[4];
+                    hp_children(ix, k, S.ckr[x], sz, ck, ckr, cs);
+                    ++n_ext;
+                    n_units += ix.units(k, k + sz);
+                    bool bad = false;
+#pragma unroll 1
+                    for (int b = 0; b < 4; ++b) {
+                        const int64_t sb = hp_pick(cs, b);
+                        if (!bad && sb > 0) {
+                            const int32_t j = hw_upsert(S, cap, hp_pick(ck, b), hp_pick(ckr, b), sb);
+                            if (j < 0) {
+                                bad = true;
+                            } else if (atomicMax(&S.cF[j], f) < f) {
+                                const int32_t old = atomicMax(&S.cH[j], f);
+                                // a deletion never tops its parent, so f < mx
+                                if (hm && old < f) {
+                                    if (old > 0 && mx - old < HW) atomicSub(&S.hist[mx - old], 1);
+                                    if (mx - f < HW) atomicAdd(&S.hist[mx - f], 1);
+                                }
+                                S.cd[j] = 1;
+                                S.changed = 1;
+                            }
+                        }
+                    }
+                    if (bad) S.flag = 1;
                 }
             }
+            __syncthreads();
+            if (dl) {
+                if (S.flag) {
+                    over = true;
+                    dl = false;
+                } else if (!S.changed) {
+                    dl = false;
+                }
+            }
+            if (__ballot(dl) == 0) break;
+        }
+        on = on && !over;
+        // keep H > 0; with a band, the W best (ties: smaller k, then s)
+        const int32_t nC = on ? S.nC : 0;
+        if (on && hl == 0) n_cells += (uint64_t)nC;
+        bool cut = false;
+        const bool rebuild = on && p.band > 0 && !hm;
+        if (on && p.band > 0 && hm) {
+            hw_hist_tau<HW>(S, p.band, hl, hbase, mx, &tau, &above, &ties);
+            cut = true;
+        }
+        if (rebuild) hw_hist_start<HW>(S, nC, hl, &mx, &pos);
+        __syncthreads();
+        if (rebuild) hw_hist_fill<HW>(S, nC, hl, mx);
+        __syncthreads();
+        if (rebuild && pos >= p.band) {
+            if (!hw_hist_tau<HW>(S, p.band, hl, hbase, mx, &tau, &above, &ties))
+                tau = hw_kth_search<HW>(S, nC, p.band, hl, mx, &above, &ties);
+            cut = true;
         }
         const int32_t r = p.band - above;
-        const bool rank_ties = cut && ties > r;
-        if (lane == 0) {
+        const bool rank_ties = on && cut && ties > r;
+        if (on && hl == 0) {
             S.nP = 0;
             S.tcount = 0;
         }
         __syncthreads();
+        // the tied cells' keys into the previous-cells arrays (free now);
+        // each tied cell's rank among them decides (in cd)
         if (rank_ties) {
-            // the tied cells' keys into the previous-cells arrays (free
-            // now); each tied cell's rank among them decides (in cd)
-            for (int32_t x = lane; x < nC; x += 64) {
+            for (int32_t x = hl; x < nC; x += HW) {
                 if (S.cH[x] == tau) {
                     const int32_t d = atomicAdd(&S.tcount, 1);
                     S.pk[d] = S.ck[x];
                     S.ps[d] = S.cs[x];
                 }
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        if (rank_ties) {
             const int32_t T = S.tcount;
-            for (int32_t x = lane; x < nC; x += 64) {
+            for (int32_t x = hl; x < nC; x += HW) {
                 if (S.cH[x] == tau) {
                     const int64_t k = S.ck[x], sz = S.cs[x];
                     int32_t rank = 0;
@@ -669,31 +714,34 @@ __global__ __launch_bounds__(64) void k_hapl_wave(V ix, const uint8_t *__restric
                     S.cd[x] = rank < r;
                 }
             }
-            __syncthreads();
         }
-        for (int32_t x = lane; x < nC; x += 64) {
-            const int32_t H = S.cH[x];
-            bool keep = H > 0;
-            if (keep && cut) keep = H > tau || (H == tau && (!rank_ties || S.cd[x]));
-            if (keep) {
-                const int32_t d = atomicAdd(&S.nP, 1);
-                S.pk[d] = S.ck[x];
-                S.pkr[d] = S.ckr[x];
-                S.ps[d] = S.cs[x];
-                S.pH[d] = H;
-                S.pE[d] = S.cE[x];
+        __syncthreads();
+        if (on) {
+            for (int32_t x = hl; x < nC; x += HW) {
+                const int32_t H = S.cH[x];
+                bool keep = H > 0;
+                if (keep && cut) keep = H > tau || (H == tau && (!rank_ties || S.cd[x]));
+                if (keep) {
+                    const int32_t d = atomicAdd(&S.nP, 1);
+                    S.pk[d] = S.ck[x];
+                    S.pkr[d] = S.ckr[x];
+                    S.ps[d] = S.cs[x];
+                    S.pH[d] = H;
+                    S.pE[d] = S.cE[x];
+                }
             }
         }
         __syncthreads();
     }
     n_ext = hw_sum64(n_ext);
     n_units = hw_sum64(n_units);
+    n_cells = hw_sum64(n_cells);
     if (lane == 0 && n_ext) {
         atomicAdd(&stats[0], (unsigned long long)n_ext);
         atomicAdd(&stats[1], (unsigned long long)n_units);
         atomicAdd(&stats[2], (unsigned long long)n_cells);
     }
-    if (lane != 0) return;
+    if (hl != 0 || !real) return;
     if (over) {
         cnt[qi] = -2;
         return;
@@ -783,8 +831,11 @@ static int hapl_run_v(Ctx &c, const V &view, const char *name, const char *wname
     while (h < 2 * o.max_cells) h <<= 1;
     p.hcap = h;
     const bool wave = !o.device_tables;
-    const bool large = o.band == 0 || o.band > HW_SMALL_BAND;
-    const int32_t wcap = std::min<int32_t>(large ? HW_CAP_LARGE : HW_CAP_SMALL, o.max_cells);
+    // LDS tables by band: two queries a wavefront with 64 cells each, one
+    // with 128, or one with 256
+    const int kind = (o.band > 0 && o.band <= HW_PAIR_BAND) ? 0 : (o.band > 0 && o.band <= HW_SMALL_BAND) ? 1 : 2;
+    const int32_t wcap = std::min<int32_t>(kind == 0 ? HW_CAP_PAIR : kind == 1 ? HW_CAP_SMALL : HW_CAP_LARGE,
+                                           o.max_cells);
     const int32_t outcap = o.band > 0 ? std::min<int32_t>(o.band, wcap) : wcap;
     std::vector<int64_t> qoff(nq + 1);
     qoff[0] = 0;
@@ -815,13 +866,17 @@ static int hapl_run_v(Ctx &c, const V &view, const char *name, const char *wname
         const int64_t m = std::min(chunk, nq - q0);
         sub.clear();
         if (wave) {
-            if (large)
-                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_LARGE>), dim3((uint32_t)m), dim3(64), 0, c.stream, view,
-                           d_codes, dq.as<int64_t>() + q0, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(),
+            if (kind == 0)
+                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_PAIR, 2>), dim3((uint32_t)((m + 1) / 2)), dim3(64), 0,
+                           c.stream, view, d_codes, dq.as<int64_t>() + q0, m, p, wcap, outcap, q0,
+                           wout.as<rb3_hapl_t>(), wcnt.as<int32_t>(), dst.as<unsigned long long>());
+            else if (kind == 1)
+                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_SMALL, 1>), dim3((uint32_t)m), dim3(64), 0, c.stream, view,
+                           d_codes, dq.as<int64_t>() + q0, m, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(),
                            wcnt.as<int32_t>(), dst.as<unsigned long long>());
             else
-                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_SMALL>), dim3((uint32_t)m), dim3(64), 0, c.stream, view,
-                           d_codes, dq.as<int64_t>() + q0, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(),
+                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_LARGE, 1>), dim3((uint32_t)m), dim3(64), 0, c.stream, view,
+                           d_codes, dq.as<int64_t>() + q0, m, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(),
                            wcnt.as<int32_t>(), dst.as<unsigned long long>());
             RB3_HIP(hipMemcpyAsync(hc.data(), wcnt.p, m * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipStreamSynchronize(c.stream));
