@@ -359,24 +359,26 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
 // wavefront step through their positions and deletion rounds together, a
 // query that has finished (or moved) idling.
 //
-// CAP = cells one position may hold in LDS: 64 with two queries a
-// wavefront for bands up to 12 (about 11 KB a wavefront; registers for four
-// wavefronts a SIMD, so 32 queries a CU), 128 for bands up to 32 (about
-// 10 KB, 15 queries a CU), else 256 (about 20 KB).
+// CAP = cells one position may hold in LDS, PCAP = the previous position's
+// cells (the band): two queries a wavefront with 64 cells each for bands up
+// to 12 (about 11 KB a wavefront; registers for four wavefronts a SIMD, so
+// 32 queries a CU), two with 128 cells and 32 previous ones for bands up to
+// 32 (about 15 KB, 20 queries a CU), else one with 256 and 256 (about 20
+// KB).
 constexpr int HW_CAP_PAIR = 64;
 constexpr int HW_PAIR_BAND = 12;
 constexpr int HW_CAP_SMALL = 128;
 constexpr int HW_CAP_LARGE = 256;
 constexpr int HW_SMALL_BAND = 32;
 
-template <int CAP>
+template <int CAP, int PCAP>
 struct HwLds {
     static constexpr int HS = 2 * CAP;  // hash slots
     int64_t ck[CAP], ckr[CAP], cs[CAP];  // current position's cells
     int32_t cH[CAP], cE[CAP], cF[CAP], cd[CAP];
     int32_t slot[HS];  // cell index + 1, 0 = empty
-    int64_t pk[CAP], pkr[CAP], ps[CAP];  // previous position's cells
-    int32_t pH[CAP], pE[CAP];
+    int64_t pk[PCAP], pkr[PCAP], ps[PCAP];  // previous position's cells (at most the band)
+    int32_t pH[PCAP], pE[PCAP];
     int32_t hist[64];  // positive scores mx - i, for the band's threshold
     int32_t nC, nP, flag, changed, tcount;
 };
@@ -409,9 +411,9 @@ __device__ __forceinline__ int64_t hw_max64(int64_t v) {
 
 // Index of the cell for (k, s), created when absent; -1 when the tables
 // are full.
-template <int CAP>
-__device__ int32_t hw_upsert(HwLds<CAP> &S, int32_t cap, int64_t k, int64_t kr, int64_t s) {
-    constexpr int HS = HwLds<CAP>::HS;
+template <class LDS>
+__device__ int32_t hw_upsert(LDS &S, int32_t cap, int64_t k, int64_t kr, int64_t s) {
+    constexpr int HS = LDS::HS;
     uint32_t h = hp_hash(k, s, HS - 1);
     int32_t j = -1;
     for (int probe = 0; probe < HS; ++probe) {
@@ -447,8 +449,8 @@ __device__ int32_t hw_upsert(HwLds<CAP> &S, int32_t cap, int64_t k, int64_t kr, 
 // Histogram of the positive scores mx - (HW - 1) .. mx, mx the highest
 // (bin i counts score mx - i), in two steps around a barrier: the maximum,
 // the positive cells' number and cleared bins, then the counts.
-template <int HW, int CAP>
-__device__ void hw_hist_start(HwLds<CAP> &S, int32_t n, int hl, int32_t *mx_out, int32_t *pos_out) {
+template <int HW, class LDS>
+__device__ void hw_hist_start(LDS &S, int32_t n, int hl, int32_t *mx_out, int32_t *pos_out) {
     int32_t mx = 0, c = 0;
     for (int32_t x = hl; x < n; x += HW) {
         const int32_t h = S.cH[x];
@@ -462,8 +464,8 @@ __device__ void hw_hist_start(HwLds<CAP> &S, int32_t n, int hl, int32_t *mx_out,
     S.hist[hl] = 0;
 }
 
-template <int HW, int CAP>
-__device__ void hw_hist_fill(HwLds<CAP> &S, int32_t n, int hl, int32_t mx) {
+template <int HW, class LDS>
+__device__ void hw_hist_fill(LDS &S, int32_t n, int hl, int32_t mx) {
     for (int32_t x = hl; x < n; x += HW) {
         const int32_t h = S.cH[x];
         if (h > 0 && mx - h < HW) atomicAdd(&S.hist[mx - h], 1);
@@ -474,8 +476,8 @@ __device__ void hw_hist_fill(HwLds<CAP> &S, int32_t n, int hl, int32_t mx) {
 // at least w cells (else false): *above = cells scoring higher, *ties =
 // cells scoring it. A scan of the bins across the query's lanes; hbase is
 // the first lane of the query in the wavefront.
-template <int HW, int CAP>
-__device__ bool hw_hist_tau(const HwLds<CAP> &S, int32_t w, int hl, int hbase, int32_t mx, int32_t *tau,
+template <int HW, class LDS>
+__device__ bool hw_hist_tau(const LDS &S, int32_t w, int hl, int hbase, int32_t mx, int32_t *tau,
                             int32_t *above, int32_t *ties) {
     const int32_t c = S.hist[hl];
     int32_t v = c;
@@ -497,8 +499,8 @@ __device__ bool hw_hist_tau(const HwLds<CAP> &S, int32_t w, int hl, int hbase, i
 // The same by a binary search over the scores 1 .. mx, each probe a count
 // over the n cells (for thresholds below the histogram's range); the n
 // cells hold at least w positive ones.
-template <int HW, int CAP>
-__device__ int32_t hw_kth_search(const HwLds<CAP> &S, int32_t n, int32_t w, int hl, int32_t mx, int32_t *above,
+template <int HW, class LDS>
+__device__ int32_t hw_kth_search(const LDS &S, int32_t n, int32_t w, int hl, int32_t mx, int32_t *above,
                                  int32_t *ties) {
     int32_t lo = 1, hi = mx;  // the largest v with w or more scores >= v
     while (lo < hi) {
@@ -524,17 +526,18 @@ __device__ int32_t hw_kth_search(const HwLds<CAP> &S, int32_t n, int32_t w, int 
 // cells per position. Query qi's results (at most outcap) go to
 // wout[qi * outcap ..] in order, cnt[qi] = their number, or -2 when its
 // cells outgrew cap.
-template <class V, int CAP, int QPW>
-__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(CAP > 128 ? 2 : 4))) void k_hapl_wave(V ix, const uint8_t *__restrict__ Q,
+template <class V, int CAP, int PCAP, int QPW>
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(CAP >= 128 ? 2 : 4))) void k_hapl_wave(V ix, const uint8_t *__restrict__ Q,
                                                   const int64_t *__restrict__ qoff, int64_t nq, HpParams p,
                                                   int32_t cap, int32_t outcap, int64_t qbase,
                                                   rb3_hapl_t *__restrict__ wout, int32_t *__restrict__ cnt,
                                                   unsigned long long *__restrict__ stats) {
     constexpr int HW = 64 / QPW;  // lanes a query
-    __shared__ HwLds<CAP> SS[QPW];
+    using LDS = HwLds<CAP, PCAP>;
+    __shared__ LDS SS[QPW];
     const int lane = threadIdx.x;
     const int hq = lane / HW, hl = lane % HW, hbase = hq * HW;
-    HwLds<CAP> &S = SS[hq];
+    LDS &S = SS[hq];
     const int64_t qi = blockIdx.x * (int64_t)QPW + hq;
     const bool real = qi < nq;
     const uint8_t *P = Q + (real ? qoff[qi] : 0);
@@ -556,7 +559,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         bool on = step < L && !over;
         const uint32_t a = on ? P[L - 1 - step] : 0u;
         if (on) {
-            for (int h = hl; h < HwLds<CAP>::HS; h += HW) S.slot[h] = 0;
+            for (int h = hl; h < LDS::HS; h += HW) S.slot[h] = 0;
             if (hl == 0) S.nC = 0;
         }
         __syncthreads();
@@ -692,14 +695,18 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
             S.tcount = 0;
         }
         __syncthreads();
-        // the tied cells' keys into the previous-cells arrays (free now);
-        // each tied cell's rank among them decides (in cd)
+        // the tied cells' keys into the previous-cells arrays (free now,
+        // PCAP of them); each tied cell's rank among the tied cells decides
+        // (in cd), counted over that list or, when it overflowed, over all
+        // cells
         if (rank_ties) {
             for (int32_t x = hl; x < nC; x += HW) {
                 if (S.cH[x] == tau) {
                     const int32_t d = atomicAdd(&S.tcount, 1);
-                    S.pk[d] = S.ck[x];
-                    S.ps[d] = S.cs[x];
+                    if (d < PCAP) {
+                        S.pk[d] = S.ck[x];
+                        S.ps[d] = S.cs[x];
+                    }
                 }
             }
         }
@@ -710,7 +717,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
                 if (S.cH[x] == tau) {
                     const int64_t k = S.ck[x], sz = S.cs[x];
                     int32_t rank = 0;
-                    for (int32_t y = 0; y < T; ++y) rank += S.pk[y] < k || (S.pk[y] == k && S.ps[y] < sz);
+                    if (T <= PCAP) {
+                        for (int32_t y = 0; y < T; ++y) rank += S.pk[y] < k || (S.pk[y] == k && S.ps[y] < sz);
+                    } else {
+                        for (int32_t y = 0; y < nC; ++y)
+                            rank += S.cH[y] == tau && (S.ck[y] < k || (S.ck[y] == k && S.cs[y] < sz));
+                    }
                     S.cd[x] = rank < r;
                 }
             }
@@ -867,17 +879,17 @@ static int hapl_run_v(Ctx &c, const V &view, const char *name, const char *wname
         sub.clear();
         if (wave) {
             if (kind == 0)
-                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_PAIR, 2>), dim3((uint32_t)((m + 1) / 2)), dim3(64), 0,
+                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_PAIR, HW_CAP_PAIR, 2>), dim3((uint32_t)((m + 1) / 2)), dim3(64), 0,
                            c.stream, view, d_codes, dq.as<int64_t>() + q0, m, p, wcap, outcap, q0,
                            wout.as<rb3_hapl_t>(), wcnt.as<int32_t>(), dst.as<unsigned long long>());
             else if (kind == 1)
-                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_SMALL, 1>), dim3((uint32_t)m), dim3(64), 0, c.stream, view,
-                           d_codes, dq.as<int64_t>() + q0, m, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(),
-                           wcnt.as<int32_t>(), dst.as<unsigned long long>());
+                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_SMALL, HW_SMALL_BAND, 2>), dim3((uint32_t)((m + 1) / 2)),
+                           dim3(64), 0, c.stream, view, d_codes, dq.as<int64_t>() + q0, m, p, wcap, outcap, q0,
+                           wout.as<rb3_hapl_t>(), wcnt.as<int32_t>(), dst.as<unsigned long long>());
             else
-                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_LARGE, 1>), dim3((uint32_t)m), dim3(64), 0, c.stream, view,
-                           d_codes, dq.as<int64_t>() + q0, m, p, wcap, outcap, q0, wout.as<rb3_hapl_t>(),
-                           wcnt.as<int32_t>(), dst.as<unsigned long long>());
+                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_LARGE, HW_CAP_LARGE, 1>), dim3((uint32_t)m), dim3(64), 0,
+                           c.stream, view, d_codes, dq.as<int64_t>() + q0, m, p, wcap, outcap, q0,
+                           wout.as<rb3_hapl_t>(), wcnt.as<int32_t>(), dst.as<unsigned long long>());
             RB3_HIP(hipMemcpyAsync(hc.data(), wcnt.p, m * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
             RB3_HIP(hipStreamSynchronize(c.stream));
             for (int64_t i = 0; i < m; ++i)
