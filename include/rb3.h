@@ -215,8 +215,9 @@ typedef struct rb3_hapl_opts {
     int32_t band;      /* W, cells kept per query position; 0 keeps all (default 25) */
     int32_t max_cells; /* cells one query position may hold before the band, 1 .. 65535; 0 (default):
                           8 * band + 256 with a band, else 4096 */
-    int32_t device_tables; /* 0 (default): each query's cells in the LDS of one wavefront while they fit
-                              (256 a position), else in device memory; 1: always in device memory */
+    int32_t device_tables; /* 0 (default): each query's cells in LDS (half a wavefront's at bands up
+                              to 32, a whole one's otherwise) while they fit (64, 128 or 256 a
+                              position by band), else in device memory; 1: always in device memory */
 } rb3_hapl_opts;
 
 void rb3_hapl_opts_init(rb3_hapl_opts *o);
@@ -239,9 +240,11 @@ typedef struct rb3_hapl_t {
  * index without both strands. With a band, the deletion step holds only
  * the cells that can still reach the band (a cell is extended only when
  * the F it passes on is at least the band's lowest score so far), which
- * leaves the band's cells and scores unchanged. Device memory: about
- * 2 * max_cells * 40 + 8 * max_cells bytes per query in flight, at most
- * 8 GiB (queries run in chunks).
+ * leaves the band's cells and scores unchanged. Device memory: the
+ * results of the queries in flight (32 bytes each, at most the band's
+ * number a query), and, for queries kept in device memory, about
+ * 2 * max_cells * 40 + 12 * max_cells bytes each; queries run in chunks
+ * of at most 8 GiB.
  */
 int rb3_hapl(const rb3_index *idx, const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q,
              int32_t mem, rb3_hapl_t *out, int64_t out_cap, int64_t *out_off);

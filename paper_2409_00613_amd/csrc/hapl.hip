@@ -14,10 +14,13 @@
 // interval or reverse-complement interval lies inside the corresponding
 // interval of a cell kept before them.
 //
-// One thread per query. Its cells live in device scratch: the previous and
-// the current position's cells (40 bytes each) and an open-addressing hash
-// of the current ones keyed by (k, s), whose entries carry the position's
-// generation so that it never needs clearing between positions.
+// Two kernels. k_hapl_wave gives each query half or all of a wavefront and
+// keeps its cells in LDS (below). k_hapl, one thread per query, keeps them
+// in device memory, for the queries that outgrow the LDS tables (or all
+// queries, on request): the previous and the current position's cells (40
+// bytes each) and an open-addressing hash of the current ones keyed by (k,
+// s), whose entries carry the position's generation so that it never needs
+// clearing between positions.
 #include "views.h"
 
 #include <algorithm>
