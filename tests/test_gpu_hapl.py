@@ -226,8 +226,10 @@ def _subset(recs, off, pick):
     return np.concatenate(parts), np.array(o, np.int64)
 
 
-def test_hapl_query_longer_than_65535():
-    say("case: haplotype enumeration of a 70,000 bp exact query (hash generations wrap), band 1")
+@pytest.mark.parametrize("dev", [False, True])
+def test_hapl_query_longer_than_65535(dev):
+    say(f"case: haplotype enumeration of a 70,000 bp exact query, band 1, device tables {dev} (their 16-bit hash "
+        "generations wrap)")
     g = np.random.default_rng(11)
     acgt = np.frombuffer(b"ACGT", np.uint8)
     s = acgt[g.integers(0, 4, 80_000)].tobytes()
@@ -235,7 +237,7 @@ def test_hapl_query_longer_than_65535():
     q = s[5000:75_000]
     # gap extension so costly that no gap cell is ever positive
     recs, off = idx.hapl(np.frombuffer(q, np.uint8), np.array([len(q)], np.int64), band=1, max_cells=16,
-                         gap_ext=1 << 20)
+                         gap_ext=1 << 20, device_tables=dev)
     _properties(idx, [q], recs, off, idx.info()[0], exact=True)
     assert off.tolist() == [0, 1]
     idx.close()
