@@ -200,19 +200,20 @@ def test_hapl_bench_shape_properties():
     idx.close()
 
 
-def test_hapl_125bp_sample_against_oracle():
-    say("case: haplotype enumeration of 125 bp reads on 32 haplotypes x 30 kb, band 10: a sample against the "
+@pytest.mark.parametrize("band", [10, 25])
+def test_hapl_125bp_sample_against_oracle(band):
+    say(f"case: haplotype enumeration of 125 bp reads on 32 haplotypes x 30 kb, band {band}: a sample against the "
         "oracle")
     w = synth.config_pangenome(genome_len=30_000, n_b1=32, n_new=4)
     idx = rb3.rb3_build(w.b1.data, w.b1.lens)
     qs = _reads(w, 2000, 125, 125, sub=0.01, indel=0.001, stream=30000)
     P = synth.pack(qs)
-    recs, off = idx.hapl(P.data, P.lens, band=10)
+    recs, off = idx.hapl(P.data, P.lens, band=band)
     _properties(idx, qs, recs, off, idx.info()[0], exact=False)
     codes, lens = oracle.expand(w.b1.data, w.b1.lens)
     text = oracle.Text(codes, lens)
     pick = list(range(0, 2000, 100))
-    _compare(text, [qs[i] for i in pick], *_subset(recs, off, pick), band=10)
+    _compare(text, [qs[i] for i in pick], *_subset(recs, off, pick), band=band)
     idx.close()
 
 
