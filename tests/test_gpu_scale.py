@@ -18,7 +18,9 @@ suffix-sort-free checks (a naive sort of these texts does not fit test time).
 * Full serving index: 320 haplotypes of a 10 Mb genome (6.4 G symbols),
   built by ten merges of 32 as the serving benchmark builds it, with the
   benchmark's 553-position segments; SMEMs of 200 queries stratified by
-  length (50 per quarter of the log-length range) against the seeded scan.
+  length (50 per quarter of the log-length range) against the seeded scan;
+  haplotype enumeration of 125 bp reads at bands 10 and 25 checked by the
+  properties that hold at any size.
 """
 import time
 
@@ -222,8 +224,39 @@ def test_merge_past_2_32_symbols():
     v.close()
 
 
+def _hapl_properties(idx, qs, n, band, exact):
+    """Haplotype enumeration at any size: valid bi-intervals, scores in
+    (0, |P|] by decreasing value, no result inside an earlier one (either
+    interval), and an exact read's first result its own bi-interval with the
+    full score."""
+    P = synth.pack(qs)
+    recs, off = idx.hapl(P.data, P.lens, band=band)
+    assert off.shape[0] == len(qs) + 1 and np.all(np.diff(off) <= band)
+    for i, q in enumerate(qs):
+        got = recs[off[i]:off[i + 1]]
+        assert np.all(got["qid"] == i)
+        assert np.all(got["s"] > 0) and np.all(got["k"] + got["s"] <= n) and np.all(got["krc"] + got["s"] <= n)
+        sc = got["score"].astype(np.int64)
+        assert np.all(sc > 0) and np.all(sc <= len(q)) and np.all(np.diff(sc) <= 0)
+        for a in range(got.shape[0]):
+            for b in range(a):
+                x, y = got[a], got[b]
+                assert not (y["k"] <= x["k"] and x["k"] + x["s"] <= y["k"] + y["s"])
+                assert not (y["krc"] <= x["krc"] and x["krc"] + x["s"] <= y["krc"] + y["s"])
+    if exact:
+        lo, hi = idx.count(P.data, P.lens)
+        comp = bytes.maketrans(b"ACGT", b"TGCA")
+        R = synth.pack([q.translate(comp)[::-1] for q in qs])
+        rlo, _ = idx.count(R.data, R.lens)
+        for i, q in enumerate(qs):
+            top = recs[off[i]]
+            assert (int(top["k"]), int(top["krc"]), int(top["s"]), int(top["score"])) == \
+                (int(lo[i]), int(rlo[i]), int(hi[i] - lo[i]), len(q)), i
+
+
 def test_full_serving_index_smem_stratified():
-    say("case: full serving index (320 haplotypes x 10 Mb, 6.4 G symbols), 200 stratified queries vs the seeded scan")
+    say("case: full serving index (320 haplotypes x 10 Mb, 6.4 G symbols), 200 stratified queries vs the seeded scan; "
+        "haplotype enumeration properties")
     import torch
     seed = synth.SEED + 4  # the serving workload's seed
     t0 = time.time()
@@ -256,6 +289,24 @@ def test_full_serving_index_smem_stratified():
     assert len(pick) == 200
     Q = synth.pack([pool[i] for i in pick])
     qc, ql = oracle.encode(Q.data, Q.lens)
+    # haplotype enumeration at full size, in the bench's configuration: 125 bp
+    # windows of indexed haplotypes (exact) and of the queries (1% / 0.1%)
+    g = np.random.default_rng(29)
+    exact = []
+    for _ in range(1000):
+        h = haps[int(g.integers(0, len(haps)))]
+        a = int(g.integers(0, len(h) - 125))
+        exact.append(bytes(h[a:a + 125]))
+    longq = [q for q in pool if len(q) >= 125]
+    mutated = []
+    for _ in range(1000):
+        q = longq[int(g.integers(0, len(longq)))]
+        a = int(g.integers(0, len(q) - 124))
+        mutated.append(bytes(q[a:a + 125]))
+    for band in (10, 25):
+        _hapl_properties(idx, exact, n, band, exact=True)
+        _hapl_properties(idx, mutated, n, band, exact=False)
+    say("  haplotype enumeration properties hold at bands 10 and 25")
     allst = synth.pack(haps)
     del haps
     codes, lens = oracle.expand(allst.data, allst.lens)
