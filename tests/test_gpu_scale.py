@@ -181,6 +181,16 @@ def test_reduced_index_run_length_form(reduced):
     lo, hi = r.count(Q.data, Q.lens)
     plo, phi = idx.count(Q.data, Q.lens)
     assert np.array_equal(lo, plo) and np.array_equal(hi, phi)
+    # haplotype enumeration of 125 bp windows of the queries: the same
+    # records on both forms, past the first superblock
+    qo = np.concatenate([[0], np.cumsum(ql)])
+    wins = [bytes(Q.data[qo[i]:qo[i] + 125]) for i in range(Q.n) if ql[i] >= 125]
+    W = synth.pack(wins)
+    for band in (10, 25):
+        hr, ho = r.hapl(W.data, W.lens, band=band)
+        hp, hpo = idx.hapl(W.data, W.lens, band=band)
+        assert np.array_equal(ho, hpo) and np.array_equal(hr, hp), band
+        assert hr.shape[0] > 0 and (hr["k"] > (1 << 24)).any()
     r.close()
 
 
