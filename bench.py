@@ -346,6 +346,34 @@ def hapl_bench(idx, n, queries, n_index, steps, n_reads=200_000, read_len=125, b
     return out
 
 
+def hapl_only(args):
+    """Haplotype enumeration alone: the serving index (320 haplotypes of a
+    10 Mb genome, built by ten merges of 32), then hapl_bench. Value: query
+    bases/s of 125 bp reads at band 10."""
+    import synth
+    from paper_2409_00613_amd import rb3
+    w = synth.config_serving(genome_len=10_000_000, n_index=320, n_unseen=8, n_queries=10_000)
+    alloc = rb3.TorchAllocator(0)
+    idx = rb3.rb3_build(w.index.slice(0, 32).data, w.index.slice(0, 32).lens, allocator=alloc)
+    for a in range(32, 320, 32):
+        part = w.index.slice(a, a + 32)
+        idx.merge(part.data, part.lens)
+    n, m, _ = idx.info()
+    log(f"serving index: n={n}")
+    h = hapl_bench(idx, n, w.queries, 320, args.steps)
+    idx.close()
+    b10 = h["bands"]["10"]
+    out = {"metric": "haplotype enumeration query bases/s", "value": b10["bases_per_s"], "unit": "bases/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": b10["ms_per_call"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "hapl", "genome_len": 10_000_000, "haplotypes_indexed": 320, "n": n,
+                      "reads": h["reads"], "read_len": h["read_len"], "band": 10},
+           "roofline": b10["roofline"], "hapl": h}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = hapl_cpu_baseline()
+    return out
+
+
 def hapl_cpu_baseline(n_reads: int = 40, read_len: int = 125):
     """The oracle's haplotype enumeration on a bounded sample: reads of the
     same shape against a 32-haplotype index of a 30 kb genome (the oracle
@@ -820,13 +848,14 @@ def main():
     ap.add_argument("--smem-batched-only", action="store_true",
                     help="SMEM: the batched calls only (no per-query calls, no served latency); for counter runs")
     ap.add_argument("--workload", default="pangenome_merge",
-                    choices=["pangenome_merge", "uneven_merge", "incremental", "serving", "locate"],
+                    choices=["pangenome_merge", "uneven_merge", "incremental", "serving", "locate", "hapl"],
                     help="pangenome_merge: 32 haplotypes into 32 (default); uneven_merge: 10,000 "
                          "log-normal contigs and 2 chromosomes into the same index, plus the plain "
                          "one-launch-per-string form on a sample; incremental: 100 haplotypes of a "
                          "100 Mb genome merged in 10 batches; serving: the full serving configuration "
                          "(320 haplotypes) only; locate: rows located and Locate1 on the pangenome "
-                         "index with suffix-array samples")
+                         "index with suffix-array samples; hapl: haplotype enumeration alone on the "
+                         "serving index")
     ap.add_argument("--plain-strings", type=int, default=200,
                     help="uneven_merge: input strings in the plain-vs-batched sample")
     ap.add_argument("--batches", type=int, default=10, help="incremental: number of batches")
@@ -876,6 +905,10 @@ def main():
         return
     if args.workload == "locate":
         res = locate_bench(args)
+        print(json.dumps(res), flush=True)
+        return
+    if args.workload == "hapl":
+        res = hapl_only(args)
         print(json.dumps(res), flush=True)
         return
     workload = args.workload
