@@ -363,27 +363,38 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
 // query that has finished (or moved) idling.
 //
 // CAP = cells one position may hold in LDS, PCAP = the previous position's
-// cells (the band): two queries a wavefront with 64 cells each for bands up
-// to 12 (about 11 KB a wavefront; registers for four wavefronts a SIMD, so
-// 32 queries a CU), two with 128 cells and 32 previous ones for bands up to
-// 32 (about 15 KB, 20 queries a CU), else one with 256 and 256 (about 20
-// KB).
+// cells (the band). Near the query's end the cells' strings are short and
+// all their children occur, so a position can hold five cells per previous
+// one (four children and the insertion): 64 cells cover bands up to 12 and
+// 128 bands up to 25 that way, larger bands on 128 cells may move queries
+// to device memory. Occupancy is set by LDS (allocated in 512-byte
+// granules) and registers:
+//   bands up to 12: two queries a wavefront, 64 cells and 16 previous ones
+//     each (6.9 KB a wavefront; registers for four wavefronts a SIMD, so
+//     32 queries a CU);
+//   bands up to 32: two queries, 128 cells and 32 previous ones (13.5 KB:
+//     11 wavefronts, 22 queries a CU);
+//   else one query, 256 and 256 (19.5 KB: 8 queries a CU).
 constexpr int HW_CAP_PAIR = 64;
 constexpr int HW_PAIR_BAND = 12;
+constexpr int HW_PAIR_PREV = 16;
 constexpr int HW_CAP_SMALL = 128;
 constexpr int HW_CAP_LARGE = 256;
 constexpr int HW_SMALL_BAND = 32;
+static_assert(HW_PAIR_PREV >= HW_PAIR_BAND, "the previous cells hold the band");
 
-template <int CAP, int PCAP>
+// HB = histogram bins, one per lane of the query.
+template <int CAP, int PCAP, int HB>
 struct HwLds {
     static constexpr int HS = 2 * CAP;  // hash slots
     int64_t ck[CAP], ckr[CAP], cs[CAP];  // current position's cells
-    int32_t cH[CAP], cE[CAP], cF[CAP], cd[CAP];
+    int32_t cH[CAP], cE[CAP], cF[CAP];
     int32_t slot[HS];  // cell index + 1, 0 = empty
     int64_t pk[PCAP], pkr[PCAP], ps[PCAP];  // previous position's cells (at most the band)
     int32_t pH[PCAP], pE[PCAP];
-    int32_t hist[64];  // positive scores mx - i, for the band's threshold
+    int32_t hist[HB];  // positive scores mx - i, for the band's threshold
     int32_t nC, nP, flag, changed, tcount;
+    uint8_t cd[CAP];  // dirty (deletion step), then kept among the tied cells
 };
 
 // Reductions over the HW lanes of one query (HW = 64 or 32).
@@ -536,7 +547,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
                                                   rb3_hapl_t *__restrict__ wout, int32_t *__restrict__ cnt,
                                                   unsigned long long *__restrict__ stats) {
     constexpr int HW = 64 / QPW;  // lanes a query
-    using LDS = HwLds<CAP, PCAP>;
+    using LDS = HwLds<CAP, PCAP, HW>;
     __shared__ LDS SS[QPW];
     const int lane = threadIdx.x;
     const int hq = lane / HW, hl = lane % HW, hbase = hq * HW;
@@ -882,7 +893,7 @@ static int hapl_run_v(Ctx &c, const V &view, const char *name, const char *wname
         sub.clear();
         if (wave) {
             if (kind == 0)
-                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_PAIR, HW_CAP_PAIR, 2>), dim3((uint32_t)((m + 1) / 2)), dim3(64), 0,
+                RB3_LAUNCH(wname, (k_hapl_wave<V, HW_CAP_PAIR, HW_PAIR_PREV, 2>), dim3((uint32_t)((m + 1) / 2)), dim3(64), 0,
                            c.stream, view, d_codes, dq.as<int64_t>() + q0, m, p, wcap, outcap, q0,
                            wout.as<rb3_hapl_t>(), wcnt.as<int32_t>(), dst.as<unsigned long long>());
             else if (kind == 1)

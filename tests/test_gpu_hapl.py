@@ -115,6 +115,23 @@ def test_hapl_other_scores(small, scores):
     _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=25)
 
 
+@pytest.mark.parametrize("band", [10, 12])
+@pytest.mark.parametrize("scores", [(2, 1, 1, 1), (3, 1, 2, 3)])
+def test_hapl_many_tied_cells_small_band(small, band, scores):
+    # with cheap mismatches and gaps, more than 16 cells tie at the band's
+    # threshold at some positions (the oracle counts 80 such cuts for
+    # (2, 1, 1, 1) at band 10 on these reads), so the ranking of the tied
+    # cells counts over all cells instead of its 16-entry list
+    m, x, o, e = scores
+    say(f"case: haplotype enumeration at band {band} with match {m}, mismatch {x}, gap open {o}, gap extension {e}: "
+        "more tied cells than the tie list holds")
+    w, idx, text, _ = small
+    qs = _reads(w, 40, 10, 50, sub=0.04, indel=0.01, stream=9000)
+    P = synth.pack(qs)
+    recs, off = idx.hapl(P.data, P.lens, match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
+    _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
+
+
 def test_hapl_run_length_index_and_output_retry(small):
     say("case: haplotype enumeration on the run-length index; output sized by a retry")
     w, idx, text, _ = small
