@@ -370,7 +370,7 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
 // to device memory. Occupancy is set by LDS (allocated in 512-byte
 // granules) and registers:
 //   bands up to 12: two queries a wavefront, 64 cells and 16 previous ones
-//     each (6.9 KB a wavefront; registers for four wavefronts a SIMD, so
+//     each (7.9 KB a wavefront; registers for four wavefronts a SIMD, so
 //     32 queries a CU);
 //   bands up to 32: two queries, 128 cells and 32 previous ones (13.5 KB:
 //     11 wavefronts, 22 queries a CU);
@@ -383,10 +383,13 @@ constexpr int HW_CAP_LARGE = 256;
 constexpr int HW_SMALL_BAND = 32;
 static_assert(HW_PAIR_PREV >= HW_PAIR_BAND, "the previous cells hold the band");
 
-// HB = histogram bins, one per lane of the query.
+// HB = histogram bins, one per lane of the query. Hash slots: two per
+// cell, four for the 64-cell tables, whose occupancy registers bound (the
+// shorter probe chains are free there; eight cost more to clear at every
+// position than they save).
 template <int CAP, int PCAP, int HB>
 struct HwLds {
-    static constexpr int HS = 2 * CAP;  // hash slots
+    static constexpr int HS = (CAP <= HW_CAP_PAIR ? 4 : 2) * CAP;
     int64_t ck[CAP], ckr[CAP], cs[CAP];  // current position's cells
     int32_t cH[CAP], cE[CAP], cF[CAP];
     int32_t slot[HS];  // cell index + 1, 0 = empty
