@@ -132,16 +132,17 @@ def test_hapl_many_tied_cells_small_band(small, band, scores):
     _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
 
 
-def test_hapl_run_length_index_and_output_retry(small):
-    say("case: haplotype enumeration on the run-length index; output sized by a retry")
+@pytest.mark.parametrize("band", [10, 25])
+def test_hapl_run_length_index_and_output_retry(small, band):
+    say(f"case: haplotype enumeration on the run-length index at band {band}; output sized by a retry")
     w, idx, text, _ = small
     qs = _reads(w, 60, 20, 80, stream=12000)
     P = synth.pack(qs)
     r = rb3.rb3_rle_build(idx, 0)
-    recs, off = r.hapl(P.data, P.lens, cap=1)
-    precs, poff = idx.hapl(P.data, P.lens)
+    recs, off = r.hapl(P.data, P.lens, cap=1, band=band)
+    precs, poff = idx.hapl(P.data, P.lens, band=band)
     assert np.array_equal(off, poff) and np.array_equal(recs, precs)
-    _compare(text, qs, recs, off, band=25)
+    _compare(text, qs, recs, off, band=band)
     r.close()
 
 
