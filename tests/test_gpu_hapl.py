@@ -132,6 +132,29 @@ def test_hapl_many_tied_cells_small_band(small, band, scores):
     _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
 
 
+@pytest.mark.parametrize("band", [0, 1, 2, 20, 40])
+def test_hapl_band_tie_break_worked_case(band):
+    # AC and GC (both strands) against the query TC with a free mismatch:
+    # the cells AC and GC tie at score 1, and a band of one keeps AC, whose
+    # suffix-array interval starts first; each band runs a different kernel
+    say(f"case: haplotype enumeration tie at the band's edge, band {band}")
+    strs = [b"AC", b"GC"]
+    P0 = synth.pack(strs)
+    idx = rb3.rb3_build(P0.data, P0.lens)
+    codes, lens = oracle.expand(P0.data, P0.lens)
+    text = oracle.Text(codes, lens)
+    enc = lambda s: np.array([ENC[c] for c in s], np.uint8)
+    ac, _ = text.interval(enc(b"AC"))
+    gc, _ = text.interval(enc(b"GC"))
+    gt, _ = text.interval(enc(b"GT"))
+    Q = synth.pack([b"TC"])
+    recs, off = idx.hapl(Q.data, Q.lens, mismatch=0, band=band)
+    got = [(int(a["k"]), int(a["krc"]), int(a["s"]), int(a["score"])) for a in recs]
+    assert got == ([(ac, gt, 1, 1)] if band == 1 else [(ac, gt, 1, 1), (gc, gc, 2, 1)])
+    _compare(text, [b"TC"], recs, off, mismatch=0, band=band)
+    idx.close()
+
+
 @pytest.mark.parametrize("band", [10, 25])
 def test_hapl_run_length_index_and_output_retry(small, band):
     say(f"case: haplotype enumeration on the run-length index at band {band}; output sized by a retry")

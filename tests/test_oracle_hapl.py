@@ -12,12 +12,14 @@ import oracle
 import synth
 
 MATCH, MIS, GO, GE = 1, 4, 6, 1
+DEFAULT = (MATCH, MIS, GO, GE)
 NEG = -10 ** 9
 
 
-def _string_score(P, S):
+def _string_score(P, S, sc=DEFAULT):
     """Best score of P (whole) against S (whole), P and S read from their
     ends, keeping only positive cells (the start cell has score 0)."""
+    MATCH, MIS, GO, GE = sc
     m, L = len(P), len(S)
     H = [[NEG] * (L + 1) for _ in range(m + 1)]
     E = [[NEG] * (L + 1) for _ in range(m + 1)]
@@ -41,10 +43,13 @@ def _string_score(P, S):
     return H[0][0] if H[0][0] > 0 else None
 
 
-def _brute(text, codes, lens, P):
+def _brute(text, codes, lens, P, sc=DEFAULT):
     """{(k, s): best score} over every substring S of every strand."""
+    MATCH, MIS, GO, GE = sc
     best = {}
-    maxlen = len(P) + (len(P) * MATCH - GO) // GE + 1
+    # a deletion run of length d costs GO + d * GE and the best score is
+    # len(P) * MATCH, so no positive alignment holds more text symbols
+    maxlen = len(P) + max(0, len(P) * MATCH - GO) // GE + 1
     seen = set()
     starts = np.concatenate([[0], np.cumsum(lens)])
     for st in range(len(lens)):
@@ -55,12 +60,12 @@ def _brute(text, codes, lens, P):
                 if S in seen:
                     continue
                 seen.add(S)
-                sc = _string_score(P, S)
-                if sc is None:
+                v = _string_score(P, S, sc)
+                if v is None:
                     continue
                 k, hi = text.interval(np.frombuffer(S, np.uint8))
                 key = (k, hi - k)
-                best[key] = max(best.get(key, NEG), sc)
+                best[key] = max(best.get(key, NEG), v)
     return best
 
 
@@ -98,6 +103,47 @@ def test_hapl_dawg_equals_brute_force(seed):
         # every reverse-complement interval is the one of the string's reverse complement
         for r in got:
             assert r[1] >= 0 and r[1] + r[2] <= text.n
+
+
+@pytest.mark.parametrize("scores", [(2, 3, 5, 2), (3, 1, 2, 3), (2, 1, 1, 1)])
+def test_hapl_dawg_equals_brute_force_other_scores(scores):
+    # the score sets of the GPU parity tests: cheap gaps and mismatches make
+    # deletion chains, insertions and ties that the default scores rarely do
+    text, codes, lens = _text(21, nstr=3, length=24)
+    g = np.random.default_rng(31)
+    for trial in range(4):
+        L = int(g.integers(4, 7))
+        a = int(g.integers(0, codes.shape[0] - L))
+        P = codes[a:a + L].copy()
+        P[P == 0] = 1
+        if trial % 2 == 1:
+            P[int(g.integers(0, L))] = int(g.integers(1, 5))
+        want = _brute(text, codes, lens, P, scores)
+        got = text.hapl(P, *scores, band=0, raw=True)
+        assert {(int(r[0]), int(r[2])): int(r[3]) for r in got} == want, (scores, trial, P)
+
+
+def test_hapl_band_tie_break():
+    # AC and GC both align to the query TC with one match and one mismatch
+    # that costs nothing (mismatch score 0): their cells tie at score 1. A
+    # band of one keeps the cell whose suffix-array interval starts first
+    # (AC before GC), the band's order being score, then smaller k, then
+    # smaller s.
+    enc = {c: i + 1 for i, c in enumerate(b"ACGTN")}
+    w = synth.pack([b"AC", b"GC"])
+    codes, lens = oracle.expand(w.data, w.lens)
+    text = oracle.Text(codes, lens)
+
+    def iv(s):
+        return text.interval(np.array([enc[c] for c in s], np.uint8))
+
+    ac, gc, gt = iv(b"AC"), iv(b"GC"), iv(b"GT")
+    assert ac[0] < gc[0]
+    P = np.array([enc[c] for c in b"TC"], np.uint8)
+    rows = lambda r: [tuple(int(v) for v in x) for x in r]
+    # GC is its own reverse complement: it occurs once on each strand
+    assert rows(text.hapl(P, 1, 0, 6, 1, band=0)) == [(ac[0], gt[0], 1, 1), (gc[0], gc[0], 2, 1)]
+    assert rows(text.hapl(P, 1, 0, 6, 1, band=1)) == [(ac[0], gt[0], 1, 1)]
 
 
 def test_hapl_hand_scores():
