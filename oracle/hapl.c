@@ -26,11 +26,21 @@
  *     smaller s); a cell is dropped when its interval [k, k+s), or its
  *     reverse-complement interval [k', k'+s), lies inside the corresponding
  *     interval of a cell kept before it.
+ *   - A node holds every string with its SA interval (X and XZ when each
+ *     occurrence of X is followed by Z), and those strings' reverse
+ *     complements have different intervals. A cell's k' is that of a
+ *     representative string: among the strings of the node whose alignment
+ *     attains the cell's H, the one whose reverse complement's interval
+ *     starts first. Each of H, E and F keeps such a representative: a match,
+ *     insertion or deletion passes on the string of the score it extends
+ *     (b prepended for a match or a deletion), and an offer replaces a
+ *     score's representative when it scores higher, or equal with a
+ *     smaller k'.
  *
- * Here a node is found as the SA interval of a representative string of it,
- * by binary search over the oracle's own suffix array, and its
- * reverse-complement interval as the SA interval of the reverse complement
- * of that string: no backward-extension formula is used.
+ * Here a node is found as the SA interval of a string of it, by binary
+ * search over the oracle's own suffix array, and a string's
+ * reverse-complement interval as the SA interval of its reverse complement:
+ * no backward-extension formula is used.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -40,11 +50,18 @@ int orc_sa_interval(void *h, const int64_t *S, const uint8_t *P, int64_t len, in
 
 #define HP_NEG (-1000000000)
 
+/* a score with its representative string (codes, len symbols) and the start
+ * kr of its reverse complement's SA interval */
 typedef struct {
-    uint8_t *str; /* representative string (codes), len symbols */
+    int v;
+    uint8_t *str;
     int len;
-    int64_t k, kr, s;
-    int H, E, F;
+    int64_t kr;
+} hp_score;
+
+typedef struct {
+    int64_t k, s;
+    hp_score H, E, F;
 } hp_cell;
 
 typedef struct {
@@ -59,15 +76,22 @@ static int hp_find(const hp_table *t, int64_t k, int64_t s)
     return -1;
 }
 
+static void hp_free_cell(hp_cell *c)
+{
+    free(c->H.str);
+    free(c->E.str);
+    free(c->F.str);
+}
+
 static void hp_clear(hp_table *t)
 {
-    for (int i = 0; i < t->n; ++i) free(t->c[i].str);
+    for (int i = 0; i < t->n; ++i) hp_free_cell(&t->c[i]);
     t->n = 0;
 }
 
-/* the cell for string str (interval k, s given), created with all scores
- * at minus infinity when absent; -1 on allocation failure */
-static int hp_get(hp_table *t, const uint8_t *str, int len, int64_t k, int64_t s, void *h, const int64_t *S)
+/* the cell of interval (k, s), created with all scores at minus infinity
+ * and no representatives when absent; -1 on allocation failure */
+static int hp_get(hp_table *t, int64_t k, int64_t s)
 {
     int i = hp_find(t, k, s);
     if (i >= 0) return i;
@@ -79,41 +103,70 @@ static int hp_get(hp_table *t, const uint8_t *str, int len, int64_t k, int64_t s
         t->cap = nc;
     }
     hp_cell *c = &t->c[t->n];
-    c->str = (uint8_t *)malloc((size_t)(len > 0 ? len : 1));
-    if (!c->str) return -1;
-    memcpy(c->str, str, (size_t)len);
-    c->len = len;
+    memset(c, 0, sizeof(*c));
     c->k = k;
     c->s = s;
-    /* the reverse-complement interval, from the reverse complement itself */
-    {
-        static const uint8_t comp[6] = {0, 4, 3, 2, 1, 5};
-        uint8_t *rc = (uint8_t *)malloc((size_t)(len > 0 ? len : 1));
-        int64_t lo, hi;
-        if (!rc) return -1;
-        for (int j = 0; j < len; ++j) rc[j] = comp[str[len - 1 - j]];
-        orc_sa_interval(h, S, rc, len, &lo, &hi);
-        c->kr = lo;
-        free(rc);
-    }
-    c->H = c->E = c->F = HP_NEG;
+    c->H.v = c->E.v = c->F.v = HP_NEG;
     return t->n++;
 }
 
-/* bS for the cell's string: interval by binary search; s = 0 if absent */
-static void hp_child(const hp_cell *c, int b, void *h, const int64_t *S, uint8_t *buf, int64_t *k, int64_t *s)
+/* start of the SA interval of the reverse complement of str */
+static int64_t hp_rc_start(const uint8_t *str, int len, void *h, const int64_t *S)
+{
+    static const uint8_t comp[6] = {0, 4, 3, 2, 1, 5};
+    uint8_t *rc = (uint8_t *)malloc((size_t)(len > 0 ? len : 1));
+    int64_t lo, hi;
+    if (!rc) return -1;
+    for (int j = 0; j < len; ++j) rc[j] = comp[str[len - 1 - j]];
+    orc_sa_interval(h, S, rc, len, &lo, &hi);
+    free(rc);
+    return lo;
+}
+
+/* offer value v through string str to score x: it wins when higher, or
+ * equal with a reverse complement whose interval starts first. Returns 1
+ * when x changed, 0 when not, -1 on an allocation failure. */
+static int hp_offer(hp_score *x, int v, const uint8_t *str, int len, void *h, const int64_t *S)
+{
+    if (v < x->v) return 0;
+    const int64_t kr = hp_rc_start(str, len, h, S);
+    if (kr < 0) return -1;
+    if (v == x->v && x->str && kr >= x->kr) return 0;
+    uint8_t *cp = (uint8_t *)malloc((size_t)(len > 0 ? len : 1));
+    if (!cp) return -1;
+    memcpy(cp, str, (size_t)len);
+    free(x->str);
+    x->str = cp;
+    x->len = len;
+    x->kr = kr;
+    x->v = v;
+    return 1;
+}
+
+/* the representative a gap passes on: that of the higher of a (opening
+ * from H) and b (extending the gap), at a tie the one with the smaller kr */
+static const hp_score *hp_gap_rep(const hp_score *H, int a, const hp_score *G, int b)
+{
+    if (a != b || !G->str) return a >= b ? H : G;
+    return G->kr < H->kr ? G : H;
+}
+
+/* b prepended to str (len symbols), into buf; the SA interval of the
+ * result (s = 0 if it does not occur) */
+static void hp_child(const uint8_t *str, int len, int b, void *h, const int64_t *S, uint8_t *buf, int64_t *k,
+                     int64_t *s)
 {
     int64_t lo, hi;
     buf[0] = (uint8_t)b;
-    memcpy(buf + 1, c->str, (size_t)c->len);
-    orc_sa_interval(h, S, buf, c->len + 1, &lo, &hi);
+    memcpy(buf + 1, str, (size_t)len);
+    orc_sa_interval(h, S, buf, len + 1, &lo, &hi);
     *k = lo;
     *s = hi - lo;
 }
 
 static int hp_better(const hp_cell *a, const hp_cell *b)
 {
-    if (a->H != b->H) return a->H > b->H;
+    if (a->H.v != b->H.v) return a->H.v > b->H.v;
     if (a->k != b->k) return a->k < b->k;
     return a->s < b->s;
 }
@@ -141,56 +194,67 @@ int64_t orc_hapl(void *h, const int64_t *S, int64_t n, const uint8_t *P, int64_t
 {
     hp_table A = {0, 0, 0}, B = {0, 0, 0};
     uint8_t *buf = (uint8_t *)calloc((size_t)(len + 4096), 1);
+    uint8_t *rbuf = (uint8_t *)calloc((size_t)(len + 4096), 1);
     int64_t result = -1;
-    int ok = buf != NULL, maxlen = 4000;
+    int ok = buf != NULL && rbuf != NULL, maxlen = 4000;
     if (ok) {
-        int r = hp_get(&A, buf, 0, 0, n, h, S); /* the root, interval [0, n) */
-        if (r < 0) ok = 0;
-        else A.c[r].H = 0;
+        int r = hp_get(&A, 0, n); /* the root, interval [0, n), the empty string */
+        if (r < 0 || hp_offer(&A.c[r].H, 0, buf, 0, h, S) < 0) ok = 0;
     }
     for (int64_t i = len - 1; ok && i >= 0; --i) {
         const int a = P[i];
         hp_clear(&B);
-        /* match / mismatch and insertion from the cells of u' */
+        /* match / mismatch and insertion from the cells of u' (A is not
+         * changed meanwhile, so c's strings stay valid) */
         for (int x = 0; ok && x < A.n; ++x) {
-            hp_cell c = A.c[x];
-            if (c.len >= maxlen) continue;
-            for (int b = 1; b <= 4; ++b) {
+            const hp_cell c = A.c[x];
+            if (c.H.len >= maxlen) continue;
+            for (int b = 1; ok && b <= 4; ++b) {
                 int64_t k, s;
-                hp_child(&c, b, h, S, buf, &k, &s);
+                hp_child(c.H.str, c.H.len, b, h, S, buf, &k, &s);
                 if (s <= 0) continue;
-                int j = hp_get(&B, buf, c.len + 1, k, s, h, S);
-                if (j < 0) { ok = 0; break; }
-                B.c[j].H = hp_max(B.c[j].H, c.H + (a == b ? match : -mismatch));
+                const int v = c.H.v + (a == b ? match : -mismatch);
+                if (v <= 0) continue;
+                int j = hp_get(&B, k, s);
+                if (j < 0 || hp_offer(&B.c[j].H, v, buf, c.H.len + 1, h, S) < 0) ok = 0;
             }
             if (!ok) break;
             {
-                int j = hp_get(&B, c.str, c.len, c.k, c.s, h, S);
-                if (j < 0) { ok = 0; break; }
-                int e = hp_max(c.H - gap_open, c.E) - gap_ext;
-                B.c[j].E = hp_max(B.c[j].E, e);
-                B.c[j].H = hp_max(B.c[j].H, B.c[j].E);
+                const int eh = c.H.v - gap_open, ee = c.E.v;
+                const int e = hp_max(eh, ee) - gap_ext;
+                if (e > 0) {
+                    const hp_score *rep = hp_gap_rep(&c.H, eh, &c.E, ee);
+                    int j = hp_get(&B, c.k, c.s);
+                    if (j < 0 || hp_offer(&B.c[j].E, e, rep->str, rep->len, h, S) < 0 ||
+                        hp_offer(&B.c[j].H, e, rep->str, rep->len, h, S) < 0)
+                        ok = 0;
+                }
             }
         }
-        /* deletion, repeated until no cell of u improves */
+        /* deletion, repeated until no score of u improves (a higher score,
+         * or the same with a representative of smaller k') */
         int changed = 1;
         while (ok && changed) {
             changed = 0;
             for (int x = 0; ok && x < B.n; ++x) {
-                if (B.c[x].H <= 0 || B.c[x].len >= maxlen) continue;
-                const int f = hp_max(B.c[x].H - gap_open, B.c[x].F) - gap_ext;
+                if (B.c[x].H.v <= 0) continue;
+                const int fh = B.c[x].H.v - gap_open, ff = B.c[x].F.v;
+                const int f = hp_max(fh, ff) - gap_ext;
                 if (f <= 0) continue;
-                for (int b = 1; b <= 4; ++b) {
+                const hp_score *rep = hp_gap_rep(&B.c[x].H, fh, &B.c[x].F, ff);
+                const int rl = rep->len;
+                if (rl >= maxlen) continue;
+                memcpy(rbuf, rep->str, (size_t)rl); /* hp_get may move B's cells */
+                for (int b = 1; ok && b <= 4; ++b) {
                     int64_t k, s;
-                    hp_child(&B.c[x], b, h, S, buf, &k, &s);
+                    hp_child(rbuf, rl, b, h, S, buf, &k, &s);
                     if (s <= 0) continue;
-                    int j = hp_get(&B, buf, B.c[x].len + 1, k, s, h, S);
+                    int j = hp_get(&B, k, s);
                     if (j < 0) { ok = 0; break; }
-                    if (f > B.c[j].F) {
-                        B.c[j].F = f;
-                        if (f > B.c[j].H) B.c[j].H = f;
-                        changed = 1;
-                    }
+                    const int r1 = hp_offer(&B.c[j].F, f, buf, rl + 1, h, S);
+                    const int r2 = hp_offer(&B.c[j].H, f, buf, rl + 1, h, S);
+                    if (r1 < 0 || r2 < 0) ok = 0;
+                    if (r1 > 0 || r2 > 0) changed = 1;
                 }
             }
         }
@@ -198,13 +262,13 @@ int64_t orc_hapl(void *h, const int64_t *S, int64_t n, const uint8_t *P, int64_t
         /* keep H > 0, then the band */
         int w = 0;
         for (int x = 0; x < B.n; ++x) {
-            if (B.c[x].H > 0) B.c[w++] = B.c[x];
-            else free(B.c[x].str);
+            if (B.c[x].H.v > 0) B.c[w++] = B.c[x];
+            else hp_free_cell(&B.c[x]);
         }
         B.n = w;
         qsort(B.c, (size_t)B.n, sizeof(hp_cell), hp_cmp);
         if (band > 0 && B.n > band) {
-            for (int x = band; x < B.n; ++x) free(B.c[x].str);
+            for (int x = band; x < B.n; ++x) hp_free_cell(&B.c[x]);
             B.n = band;
         }
         hp_table t = A;
@@ -218,8 +282,8 @@ int64_t orc_hapl(void *h, const int64_t *S, int64_t n, const uint8_t *P, int64_t
         {
             int z = 0;
             for (int x = 0; x < A.n; ++x) {
-                if (A.c[x].H > 0) A.c[z++] = A.c[x];
-                else free(A.c[x].str);
+                if (A.c[x].H.v > 0) A.c[z++] = A.c[x];
+                else hp_free_cell(&A.c[x]);
             }
             A.n = z;
         }
@@ -227,9 +291,9 @@ int64_t orc_hapl(void *h, const int64_t *S, int64_t n, const uint8_t *P, int64_t
         if (raw) {
             for (int x = 0; x < A.n && x < cap; ++x) {
                 out[5 * x] = A.c[x].k;
-                out[5 * x + 1] = A.c[x].kr;
+                out[5 * x + 1] = A.c[x].H.kr;
                 out[5 * x + 2] = A.c[x].s;
-                out[5 * x + 3] = A.c[x].H;
+                out[5 * x + 3] = A.c[x].H.v;
                 out[5 * x + 4] = 0;
             }
             w = A.n;
@@ -241,15 +305,15 @@ int64_t orc_hapl(void *h, const int64_t *S, int64_t n, const uint8_t *P, int64_t
                     if (drop[y]) continue;
                     const hp_cell *p = &A.c[y], *q = &A.c[x];
                     if ((q->k >= p->k && q->k + q->s <= p->k + p->s) ||
-                        (q->kr >= p->kr && q->kr + q->s <= p->kr + p->s))
+                        (q->H.kr >= p->H.kr && q->H.kr + q->s <= p->H.kr + p->s))
                         drop[x] = 1;
                 }
                 if (!drop[x]) {
                     if (w < cap) {
                         out[5 * w] = A.c[x].k;
-                        out[5 * w + 1] = A.c[x].kr;
+                        out[5 * w + 1] = A.c[x].H.kr;
                         out[5 * w + 2] = A.c[x].s;
-                        out[5 * w + 3] = A.c[x].H;
+                        out[5 * w + 3] = A.c[x].H.v;
                         out[5 * w + 4] = 0;
                     }
                     ++w;
@@ -264,5 +328,6 @@ int64_t orc_hapl(void *h, const int64_t *S, int64_t n, const uint8_t *P, int64_t
     free(A.c);
     free(B.c);
     free(buf);
+    free(rbuf);
     return result;
 }

@@ -62,10 +62,14 @@ MUTANTS = [
      "the Elias delta code's length with the leading bit"),
     ("rle-rank-offset", "rle.c", "        if (off == 0) continue;", "        if (off <= 1) continue;",
      "rank skipping the first symbol of a segment"),
-    ("insertion-extension", "hapl.c", "int e = hp_max(c.H - gap_open, c.E) - gap_ext;",
-     "int e = hp_max(c.H - gap_open - gap_ext, c.E);", "an insertion run that stops paying its extension"),
-    ("deletion-extension", "hapl.c", "const int f = hp_max(B.c[x].H - gap_open, B.c[x].F) - gap_ext;",
-     "const int f = hp_max(B.c[x].H - gap_open, B.c[x].F - gap_ext);", "a deletion opened without its extension"),
+    ("insertion-extension", "hapl.c", "const int e = hp_max(eh, ee) - gap_ext;",
+     "const int e = hp_max(eh - gap_ext, ee);", "an insertion run that stops paying its extension"),
+    ("deletion-extension", "hapl.c", "const int f = hp_max(fh, ff) - gap_ext;",
+     "const int f = hp_max(fh - gap_ext, ff);", "a deletion run that stops paying its extension"),
+    ("representative-order", "hapl.c", "if (v == x->v && x->str && kr >= x->kr) return 0;",
+     "if (v == x->v && x->str && kr <= x->kr) return 0;", "equal scores keeping the larger reverse-complement start"),
+    ("gap-representative", "hapl.c", "    if (a != b || !G->str) return a >= b ? H : G;",
+     "    if (a != b || !G->str) return H;", "a gap passing on H's string when the gap's own score wins"),
     ("band-tie-order", "hapl.c", "if (a->k != b->k) return a->k < b->k;", "if (a->k != b->k) return a->k > b->k;",
      "tied cells of the band ordered by larger k first"),
 ]

@@ -43,8 +43,13 @@ def _string_score(P, S, sc=DEFAULT):
     return H[0][0] if H[0][0] > 0 else None
 
 
-def _brute(text, codes, lens, P, sc=DEFAULT):
-    """{(k, s): best score} over every substring S of every strand."""
+COMP = np.array([0, 4, 3, 2, 1, 5], np.uint8)
+
+
+def _brute(text, codes, lens, P, sc=DEFAULT, with_rc=False):
+    """{(k, s): best score} over every substring S of every strand; with_rc:
+    {(k, s): (best score, the smallest and the largest start of the reverse
+    complement's SA interval among the strings S of the node attaining it)}."""
     MATCH, MIS, GO, GE = sc
     best = {}
     # a deletion run of length d costs GO + d * GE and the best score is
@@ -63,9 +68,19 @@ def _brute(text, codes, lens, P, sc=DEFAULT):
                 v = _string_score(P, S, sc)
                 if v is None:
                     continue
-                k, hi = text.interval(np.frombuffer(S, np.uint8))
+                arr = np.frombuffer(S, np.uint8)
+                k, hi = text.interval(arr)
                 key = (k, hi - k)
-                best[key] = max(best.get(key, NEG), v)
+                if with_rc:
+                    krc, _ = text.interval(COMP[arr[::-1]])
+                    krc = int(krc)
+                    old = best.get(key)
+                    if old is None or v > old[0]:
+                        best[key] = (v, krc, krc)
+                    elif v == old[0]:
+                        best[key] = (v, min(old[1], krc), max(old[2], krc))
+                else:
+                    best[key] = max(best.get(key, NEG), v)
     return best
 
 
@@ -121,6 +136,47 @@ def test_hapl_dawg_equals_brute_force_other_scores(scores):
         want = _brute(text, codes, lens, P, scores)
         got = text.hapl(P, *scores, band=0, raw=True)
         assert {(int(r[0]), int(r[2])): int(r[3]) for r in got} == want, (scores, trial, P)
+
+
+@pytest.mark.parametrize("scores", [(2, 1, 1, 1), (3, 1, 2, 3)])
+def test_hapl_representative_brute_force(scores):
+    # a node holds several strings (X and XZ when every X is followed by Z),
+    # whose reverse complements have intervals of one size but different
+    # starts: the reported k' is that of the string with the smallest start
+    # among the node's strings whose own alignment attains the node's score
+    text, codes, lens = _text(41, nstr=3, length=24)
+    g = np.random.default_rng(43)
+    chosen = 0
+    for trial in range(5):
+        L = int(g.integers(4, 8))
+        a = int(g.integers(0, codes.shape[0] - L))
+        P = codes[a:a + L].copy()
+        P[P == 0] = 2
+        if trial % 2 == 1:
+            P[int(g.integers(0, L))] = int(g.integers(1, 5))
+        want = _brute(text, codes, lens, P, scores, with_rc=True)
+        got = text.hapl(P, *scores, band=0, raw=True)
+        assert {(int(r[0]), int(r[2])): (int(r[3]), int(r[1])) for r in got} == \
+            {key: (v[0], v[1]) for key, v in want.items()}, (scores, trial, P)
+        chosen += sum(1 for v in want.values() if v[1] != v[2])
+    # nodes whose optimal strings' reverse complements start at different
+    # rows, where the choice is made
+    assert chosen > 0
+
+
+@pytest.mark.parametrize("seed,scores,query", [(40, (2, 1, 1, 1), [2, 1, 2, 3, 3, 4]),
+                                               (41, (4, 2, 3, 1), [1, 2, 1, 3])])
+def test_hapl_gap_representative_brute_force(seed, scores, query):
+    # inputs where a cell's best score comes from an insertion or deletion
+    # run whose own string is not the representative of the score it left:
+    # the gap passes on the run's representative (a gap that passed on H's
+    # representative fails here)
+    text, codes, lens = _text(seed, nstr=3, length=24)
+    P = np.array(query, np.uint8)
+    want = _brute(text, codes, lens, P, scores, with_rc=True)
+    got = text.hapl(P, *scores, band=0, raw=True)
+    assert {(int(r[0]), int(r[2])): (int(r[3]), int(r[1])) for r in got} == \
+        {key: (v[0], v[1]) for key, v in want.items()}
 
 
 def test_hapl_band_tie_break():
