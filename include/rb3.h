@@ -193,9 +193,13 @@ int rb3_last_smem_stats(int64_t *extensions, int64_t *blocks);
 /*
  * Local haplotype enumeration (Sec. 2.7-2.8, Algorithm 5): each query P is
  * aligned end to end (semi-globally) to the prefix DAWG of the index under
- * affine gaps, walking P from its end to its start. A DAWG node is the SA
- * bi-interval (k, krc, s) of a string; its children are its non-empty
- * backward extensions by A, C, G, T (Algorithm 3). At each query position
+ * affine gaps, walking P from its end to its start. A DAWG node is an SA
+ * interval (k, s); its children are its non-empty backward extensions by
+ * A, C, G, T (Algorithm 3). A node holds every string with that interval
+ * (X and XZ when each occurrence of X is followed by Z), whose reverse
+ * complements have intervals of size s starting at different rows krc: a
+ * cell reports the krc of the string with the smallest krc among the
+ * node's strings whose alignment attains the cell's score. At each query position
  * the cells come from the previous position's cells by a match or mismatch
  * to a child (score match, or -mismatch; a query N mismatches every symbol)
  * and by an insertion (same node), then from the position's own cells by
@@ -235,15 +239,16 @@ typedef struct rb3_hapl_t {
  * out_off[i+1]) in result order; out (host, out_cap entries) and out_off
  * (host, n_q + 1) are caller buffers. RB3_ENOSPC when out_cap is too small
  * (out_off filled, so the caller can size a retry); RB3_ELIMIT when a query
- * needs more than max_cells cells at one position, or match times a
- * query's length reaches 2^29; RB3_EINVAL on options out of range or an
- * index without both strands. With a band, the deletion step holds only
+ * needs more than max_cells cells at one position, match times a query's
+ * length reaches 2^29, or the index holds 2^35 symbols or more; RB3_EINVAL
+ * on options out of range or an index without both strands. With a band,
+ * the deletion step holds only
  * the cells that can still reach the band (a cell is extended only when
  * the F it passes on is at least the band's lowest score so far), which
  * leaves the band's cells and scores unchanged. Device memory: the
  * results of the queries in flight (32 bytes each, at most the band's
  * number a query), and, for queries kept in device memory, about
- * 2 * max_cells * 40 + 12 * max_cells bytes each; queries run in chunks
+ * 2 * max_cells * 48 + 12 * max_cells bytes each; queries run in chunks
  * of at most 8 GiB.
  */
 int rb3_hapl(const rb3_index *idx, const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q,

@@ -591,11 +591,13 @@ void rb3_hapl_opts_init(rb3_hapl_opts *o) {
 
 // The checks shared by both index forms; *o_out = the options to use.
 static int hapl_args(const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q, int32_t mem,
-                     rb3_hapl_t *out, int64_t out_cap, int64_t *out_off, int32_t both, rb3_hapl_opts *o_out,
-                     int64_t *total) {
+                     rb3_hapl_t *out, int64_t out_cap, int64_t *out_off, int32_t both, int64_t n,
+                     rb3_hapl_opts *o_out, int64_t *total) {
     if (!out_off) return fail(RB3_EINVAL, "out_off is NULL");
     if (out_cap < 0 || (out_cap > 0 && !out)) return fail(RB3_EINVAL, "bad output buffer");
     if (!both) return fail(RB3_EINVAL, "haplotype enumeration needs an index of both strands");
+    if (n >= ((int64_t)1 << rb3::HAPL_KRC_BITS))
+        return fail(RB3_ELIMIT, "haplotype enumeration needs an index of fewer than 2^35 symbols");
     if (n_q >= (int64_t)INT32_MAX) return fail(RB3_ELIMIT, "too many queries");
     if (o)
         *o_out = *o;
@@ -614,7 +616,7 @@ int rb3_hapl(const rb3_index *idx, const rb3_hapl_opts *o, const uint8_t *q, con
     if (!idx) return fail(RB3_EINVAL, "index is NULL");
     rb3_hapl_opts oo;
     int64_t total = 0;
-    RB3_TRY(hapl_args(o, q, qlens, n_q, mem, out, out_cap, out_off, idx->d.ctx.both, &oo, &total));
+    RB3_TRY(hapl_args(o, q, qlens, n_q, mem, out, out_cap, out_off, idx->d.ctx.both, idx->d.n, &oo, &total));
     if (n_q == 0) return RB3_OK;
     RB3_HIP(hipSetDevice(idx->d.ctx.device));
     Ctx c = call_ctx(idx->d);
@@ -1311,7 +1313,7 @@ int rb3_rle_hapl(const rb3_rle *r, const rb3_hapl_opts *o, const uint8_t *q, con
     if (!r) return fail(RB3_EINVAL, "run-length index is NULL");
     rb3_hapl_opts oo;
     int64_t total = 0;
-    RB3_TRY(hapl_args(o, q, qlens, n_q, mem, out, out_cap, out_off, r->both, &oo, &total));
+    RB3_TRY(hapl_args(o, q, qlens, n_q, mem, out, out_cap, out_off, r->both, r->n, &oo, &total));
     if (n_q == 0) return RB3_OK;
     RB3_HIP(hipSetDevice(r->ctx.device));
     Ctx c = rle_ctx(r);

@@ -30,19 +30,56 @@ namespace rb3 {
 
 constexpr int32_t HP_NEG = -1000000000;
 
+// A cell's score H (best alignment), E (ending in an insertion) and F
+// (ending in a deletion) each come with a representative: a node holds
+// every string with its SA interval (X and XZ when each occurrence of X is
+// followed by Z), and their reverse complements start at different rows.
+// A score's representative is, among the node's strings whose alignment
+// attains it, the one whose reverse complement's interval starts first; a
+// match or deletion passes on the representative of the score it extends
+// with b prepended, an insertion passes it on unchanged. Backward extension
+// keeps the order of those starts among a node's strings, so keeping the
+// best (score, start) offer per score gives that string.
+//
+// A score and its representative's reverse-complement start travel as one
+// word: the score in the high bits, the start's complement in the low
+// HAPL_KRC_BITS bits, so that an unsigned maximum keeps the higher score
+// and, at equal scores, the smaller start. Only positive scores are packed;
+// 0 means none.
+constexpr uint64_t HP_KMASK = ((uint64_t)1 << HAPL_KRC_BITS) - 1u;
+
+__device__ __forceinline__ uint64_t hp_pack(int32_t v, int64_t kr) {
+    return ((uint64_t)(uint32_t)v << HAPL_KRC_BITS) | (HP_KMASK - (uint64_t)kr);
+}
+__device__ __forceinline__ int32_t hp_val(uint64_t w) { return (int32_t)(w >> HAPL_KRC_BITS); }
+__device__ __forceinline__ int64_t hp_rep(uint64_t w) { return (int64_t)(HP_KMASK - (w & HP_KMASK)); }
+
 struct HpCell {
-    int64_t k, kr, s;
-    int32_t H, E, F, dirty;
+    int64_t k, s;
+    uint64_t hw, ew, fw;  // packed H, E, F
+    int32_t dirty;
 };
 
 struct HpParams {
     int32_t match, mismatch, gap_open, gap_ext, band, cap, hcap;
 };
 
+// What a gap passes on from a cell with packed H hw (positive) and packed
+// gap score gw (E or F): max(H - open, G) - ext, with the representative of
+// the higher term (the smaller start at a tie); 0 when not positive.
+__device__ __forceinline__ uint64_t hp_gap(uint64_t hw, uint64_t gw, const HpParams &p) {
+    const int32_t a = hp_val(hw) - p.gap_open;
+    const int32_t b = gw ? hp_val(gw) : HP_NEG;
+    const int32_t v = (a > b ? a : b) - p.gap_ext;
+    if (v <= 0) return 0;
+    const int64_t ra = hp_rep(hw), rb = gw ? hp_rep(gw) : ra;
+    return hp_pack(v, a > b ? ra : (b > a ? rb : (ra < rb ? ra : rb)));
+}
+
 __device__ __forceinline__ int32_t hp_max(int32_t a, int32_t b) { return a > b ? a : b; }
 
 __device__ __forceinline__ bool hp_before(const HpCell &a, const HpCell &b) {
-    if (a.H != b.H) return a.H > b.H;
+    if (hp_val(a.hw) != hp_val(b.hw)) return hp_val(a.hw) > hp_val(b.hw);
     if (a.k != b.k) return a.k < b.k;
     return a.s < b.s;
 }
@@ -86,7 +123,7 @@ __device__ __forceinline__ uint32_t hp_hash(int64_t k, int64_t s, uint32_t mask)
 // Index of the current position's cell for (k, s), created when absent;
 // -1 when the table is full.
 __device__ __forceinline__ int32_t hp_upsert(HpCell *T, int32_t &nT, uint32_t *hash, const HpParams &p, uint32_t gen,
-                                             int64_t k, int64_t kr, int64_t s) {
+                                             int64_t k, int64_t s) {
     const uint32_t mask = (uint32_t)p.hcap - 1u;
     uint32_t h = hp_hash(k, s, mask);
     for (;;) {
@@ -101,9 +138,8 @@ __device__ __forceinline__ int32_t hp_upsert(HpCell *T, int32_t &nT, uint32_t *h
         const int32_t j = nT++;
         HpCell c;
         c.k = k;
-        c.kr = kr;
         c.s = s;
-        c.H = c.E = c.F = HP_NEG;
+        c.hw = c.ew = c.fw = 0;
         c.dirty = 1;
         T[j] = c;
         hash[h] = (gen << 16) | (uint32_t)j;
@@ -118,7 +154,7 @@ __device__ __forceinline__ int32_t hp_upsert(HpCell *T, int32_t &nT, uint32_t *h
 __device__ int32_t hp_kth(const HpCell *B, int32_t n, int32_t w, int32_t *hv, int32_t *above) {
     int32_t m = 0;
     for (int32_t x = 0; x < n; ++x) {
-        const int32_t h = B[x].H;
+        const int32_t h = hp_val(B[x].hw);
         if (h > 0) hv[m++] = h;
     }
     if (m < w) {
@@ -199,12 +235,11 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
     uint64_t n_ext = 0, n_units = 0, n_cells = 0;
     int32_t nA = 1, nB = 0;
     {
-        HpCell r;
+        HpCell r;  // the root: the empty string, score 0
         r.k = 0;
-        r.kr = 0;
         r.s = ix.size();
-        r.H = 0;
-        r.E = r.F = HP_NEG;
+        r.hw = hp_pack(0, 0);
+        r.ew = r.fw = 0;
         r.dirty = 0;
         A[0] = r;
     }
@@ -219,33 +254,41 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
         // match / mismatch and insertion from the previous position's cells
         for (int32_t x = 0; x < nA && !full; ++x) {
             const HpCell c = A[x];
+            const int32_t H = hp_val(c.hw);
             int64_t ck[4], ckr[4], cs[4];
-            hp_children(ix, c.k, c.kr, c.s, ck, ckr, cs);
+            hp_children(ix, c.k, hp_rep(c.hw), c.s, ck, ckr, cs);
             ++n_ext;
             n_units += ix.units(c.k, c.k + c.s);
 #pragma unroll 1
             for (int b = 0; b < 4; ++b) {
                 const int64_t sb = hp_pick(cs, b);
-                if (!full && sb > 0) {
-                    const int32_t j = hp_upsert(B, nB, hash, p, gen, hp_pick(ck, b), hp_pick(ckr, b), sb);
-                    if (j < 0)
+                const int32_t v = H + ((uint32_t)(b + 1) == a ? p.match : -p.mismatch);
+                if (!full && sb > 0 && v > 0) {
+                    const int32_t j = hp_upsert(B, nB, hash, p, gen, hp_pick(ck, b), sb);
+                    if (j < 0) {
                         full = true;
-                    else
-                        B[j].H = hp_max(B[j].H, c.H + ((uint32_t)(b + 1) == a ? p.match : -p.mismatch));
+                    } else {
+                        const uint64_t w = hp_pack(v, hp_pick(ckr, b));
+                        if (w > B[j].hw) B[j].hw = w;
+                    }
                 }
             }
             if (full) break;
-            const int32_t j = hp_upsert(B, nB, hash, p, gen, c.k, c.kr, c.s);
-            if (j < 0) {
-                full = true;
-                break;
+            const uint64_t iw = hp_gap(c.hw, c.ew, p);  // the insertion: the same string
+            if (iw) {
+                const int32_t j = hp_upsert(B, nB, hash, p, gen, c.k, c.s);
+                if (j < 0) {
+                    full = true;
+                    break;
+                }
+                if (iw > B[j].ew) B[j].ew = iw;
+                if (iw > B[j].hw) B[j].hw = iw;
             }
-            const int32_t e = hp_max(c.H - p.gap_open, c.E) - p.gap_ext;
-            B[j].E = hp_max(B[j].E, e);
-            B[j].H = hp_max(B[j].H, B[j].E);
         }
-        // deletion, repeated until no cell improves: a cell whose H or F
-        // rose since it last passed its F on is marked dirty
+        // deletion, repeated until no cell improves: a cell whose F rose
+        // (a higher score, or a representative starting first) since it last
+        // passed a deletion on is marked dirty; an offer that raises H raises
+        // F too, since every deletion offer goes to both
         int32_t above = 0;
         const int32_t tau = (p.band > 0 && !full) ? hp_kth(B, nB, p.band, hv, &above) : 1;
         bool changed = true;
@@ -254,22 +297,25 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
             for (int32_t x = 0; x < nB && !full; ++x) {
                 if (!B[x].dirty) continue;
                 B[x].dirty = 0;
-                const int32_t f = hp_max(B[x].H - p.gap_open, B[x].F) - p.gap_ext;
-                if (f <= 0 || f < tau || B[x].H <= 0) continue;
+                if (hp_val(B[x].hw) <= 0) continue;
+                const uint64_t fw = hp_gap(B[x].hw, B[x].fw, p);
+                const int32_t f = hp_val(fw);
+                if (f <= 0 || f < tau) continue;
                 int64_t ck[4], ckr[4], cs[4];
-                hp_children(ix, B[x].k, B[x].kr, B[x].s, ck, ckr, cs);
+                hp_children(ix, B[x].k, hp_rep(fw), B[x].s, ck, ckr, cs);
                 ++n_ext;
                 n_units += ix.units(B[x].k, B[x].k + B[x].s);
 #pragma unroll 1
                 for (int b = 0; b < 4; ++b) {
                     const int64_t sb = hp_pick(cs, b);
                     if (!full && sb > 0) {
-                        const int32_t j = hp_upsert(B, nB, hash, p, gen, hp_pick(ck, b), hp_pick(ckr, b), sb);
+                        const int32_t j = hp_upsert(B, nB, hash, p, gen, hp_pick(ck, b), sb);
+                        const uint64_t w = j < 0 ? 0 : hp_pack(f, hp_pick(ckr, b));
                         if (j < 0) {
                             full = true;
-                        } else if (f > B[j].F) {
-                            B[j].F = f;
-                            if (f > B[j].H) B[j].H = f;
+                        } else if (w > B[j].fw) {
+                            B[j].fw = w;
+                            if (w > B[j].hw) B[j].hw = w;
                             B[j].dirty = 1;
                             changed = true;
                         }
@@ -282,16 +328,16 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
         // keep H > 0; with a band, the W best
         int32_t w = 0;
         for (int32_t x = 0; x < nB; ++x)
-            if (B[x].H > 0) B[w++] = B[x];
+            if (hp_val(B[x].hw) > 0) B[w++] = B[x];
         if (p.band > 0 && w > p.band) {
             const int32_t tau = hp_kth(B, w, p.band, hv, &above);
             // the cells scoring above tau first, then those scoring tau
             int32_t a0 = 0;
             for (int32_t x = 0; x < w; ++x)
-                if (B[x].H > tau) hp_swap(B, a0++, x);
+                if (hp_val(B[x].hw) > tau) hp_swap(B, a0++, x);
             int32_t e0 = a0;
             for (int32_t x = a0; x < w; ++x)
-                if (B[x].H == tau) hp_swap(B, e0++, x);
+                if (hp_val(B[x].hw) == tau) hp_swap(B, e0++, x);
             // of the ties, the band's remaining places go to the smallest
             // (k, s)
             const int32_t r = p.band - above;
@@ -338,7 +384,8 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
         bool inside = false;
         for (int32_t y = 0; y < w && !inside; ++y) {
             const HpCell &q = A[y];
-            inside = (c.k >= q.k && c.k + c.s <= q.k + q.s) || (c.kr >= q.kr && c.kr + c.s <= q.kr + q.s);
+            const int64_t ckr = hp_rep(c.hw), qkr = hp_rep(q.hw);
+            inside = (c.k >= q.k && c.k + c.s <= q.k + q.s) || (ckr >= qkr && ckr + c.s <= qkr + q.s);
         }
         if (!inside) A[w++] = c;
     }
@@ -370,11 +417,11 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
 // to device memory. Occupancy is set by LDS (allocated in 512-byte
 // granules) and registers:
 //   bands up to 12: two queries a wavefront, 64 cells and 16 previous ones
-//     each (7.9 KB a wavefront; registers for four wavefronts a SIMD, so
+//     each (8.4 KB a wavefront; registers for four wavefronts a SIMD, so
 //     32 queries a CU);
-//   bands up to 32: two queries, 128 cells and 32 previous ones (13.5 KB:
-//     11 wavefronts, 22 queries a CU);
-//   else one query, 256 and 256 (19.5 KB: 8 queries a CU).
+//   bands up to 32: two queries, 128 cells and 32 previous ones (14.5 KB:
+//     10 wavefronts, 20 queries a CU);
+//   else one query, 256 and 256 (20.5 KB: 7 queries a CU).
 constexpr int HW_CAP_PAIR = 64;
 constexpr int HW_PAIR_BAND = 12;
 constexpr int HW_PAIR_PREV = 16;
@@ -390,11 +437,11 @@ static_assert(HW_PAIR_PREV >= HW_PAIR_BAND, "the previous cells hold the band");
 template <int CAP, int PCAP, int HB>
 struct HwLds {
     static constexpr int HS = (CAP <= HW_CAP_PAIR ? 4 : 2) * CAP;
-    int64_t ck[CAP], ckr[CAP], cs[CAP];  // current position's cells
-    int32_t cH[CAP], cE[CAP], cF[CAP];
+    int64_t ck[CAP], cs[CAP];  // current position's cells
+    uint64_t cH[CAP], cE[CAP], cF[CAP];  // packed scores with representatives
     int32_t slot[HS];  // cell index + 1, 0 = empty
-    int64_t pk[PCAP], pkr[PCAP], ps[PCAP];  // previous position's cells (at most the band)
-    int32_t pH[PCAP], pE[PCAP];
+    int64_t pk[PCAP], ps[PCAP];  // previous position's cells (at most the band)
+    uint64_t pH[PCAP], pE[PCAP];
     int32_t hist[HB];  // positive scores mx - i, for the band's threshold
     int32_t nC, nP, flag, changed, tcount;
     uint8_t cd[CAP];  // dirty (deletion step), then kept among the tied cells
@@ -429,7 +476,7 @@ __device__ __forceinline__ int64_t hw_max64(int64_t v) {
 // Index of the cell for (k, s), created when absent; -1 when the tables
 // are full.
 template <class LDS>
-__device__ int32_t hw_upsert(LDS &S, int32_t cap, int64_t k, int64_t kr, int64_t s) {
+__device__ int32_t hw_upsert(LDS &S, int32_t cap, int64_t k, int64_t s) {
     constexpr int HS = LDS::HS;
     uint32_t h = hp_hash(k, s, HS - 1);
     int32_t j = -1;
@@ -440,11 +487,10 @@ __device__ int32_t hw_upsert(LDS &S, int32_t cap, int64_t k, int64_t kr, int64_t
                 j = atomicAdd(&S.nC, 1);
                 if (j >= cap) return -1;
                 S.ck[j] = k;
-                S.ckr[j] = kr;
                 S.cs[j] = s;
-                S.cH[j] = HP_NEG;
-                S.cE[j] = HP_NEG;
-                S.cF[j] = HP_NEG;
+                S.cH[j] = 0;
+                S.cE[j] = 0;
+                S.cF[j] = 0;
                 S.cd[j] = 1;
             }
             int32_t expected = 0;
@@ -455,7 +501,7 @@ __device__ int32_t hw_upsert(LDS &S, int32_t cap, int64_t k, int64_t kr, int64_t
         }
         const int32_t c = v - 1;
         if (S.ck[c] == k && S.cs[c] == s) {
-            if (j >= 0) S.cs[j] = 0;  // the allocation stays unlinked
+            if (j >= 0) S.cs[j] = 0;  // the allocation stays unlinked (no score)
             return c;
         }
         h = (h + 1) & (HS - 1);
@@ -470,7 +516,7 @@ template <int HW, class LDS>
 __device__ void hw_hist_start(LDS &S, int32_t n, int hl, int32_t *mx_out, int32_t *pos_out) {
     int32_t mx = 0, c = 0;
     for (int32_t x = hl; x < n; x += HW) {
-        const int32_t h = S.cH[x];
+        const int32_t h = hp_val(S.cH[x]);
         if (h > 0) {
             ++c;
             mx = hp_max(mx, h);
@@ -484,7 +530,7 @@ __device__ void hw_hist_start(LDS &S, int32_t n, int hl, int32_t *mx_out, int32_
 template <int HW, class LDS>
 __device__ void hw_hist_fill(LDS &S, int32_t n, int hl, int32_t mx) {
     for (int32_t x = hl; x < n; x += HW) {
-        const int32_t h = S.cH[x];
+        const int32_t h = hp_val(S.cH[x]);
         if (h > 0 && mx - h < HW) atomicAdd(&S.hist[mx - h], 1);
     }
 }
@@ -523,7 +569,7 @@ __device__ int32_t hw_kth_search(const LDS &S, int32_t n, int32_t w, int hl, int
     while (lo < hi) {
         const int32_t mid = lo + ((hi - lo + 1) >> 1);
         int32_t k = 0;
-        for (int32_t x = hl; x < n; x += HW) k += S.cH[x] >= mid;
+        for (int32_t x = hl; x < n; x += HW) k += hp_val(S.cH[x]) >= mid;
         if (hw_sum<HW>(k) >= w)
             lo = mid;
         else
@@ -531,8 +577,8 @@ __device__ int32_t hw_kth_search(const LDS &S, int32_t n, int32_t w, int hl, int
     }
     int32_t ka = 0, kt = 0;
     for (int32_t x = hl; x < n; x += HW) {
-        ka += S.cH[x] > lo;
-        kt += S.cH[x] == lo;
+        ka += hp_val(S.cH[x]) > lo;
+        kt += hp_val(S.cH[x]) == lo;
     }
     *above = hw_sum<HW>(ka);
     *ties = hw_sum<HW>(kt);
@@ -561,12 +607,11 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
     const int64_t L = real ? qoff[qi + 1] - qoff[qi] : 0;
     const int64_t Lmax = hw_max64(L);
     uint64_t n_ext = 0, n_units = 0, n_cells = 0;
-    if (hl == 0) {
+    if (hl == 0) {  // the root: the empty string, score 0
         S.pk[0] = 0;
-        S.pkr[0] = 0;
         S.ps[0] = ix.size();
-        S.pH[0] = 0;
-        S.pE[0] = HP_NEG;
+        S.pH[0] = hp_pack(0, 0);
+        S.pE[0] = 0;
         S.nP = 1;
         S.flag = 0;
     }
@@ -584,32 +629,35 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         if (on) {
             const int32_t nP = S.nP;
             for (int32_t x = hl; x < nP; x += HW) {
-                const int64_t k = S.pk[x], kr = S.pkr[x], sz = S.ps[x];
-                const int32_t H = S.pH[x], E = S.pE[x];
+                const int64_t k = S.pk[x], sz = S.ps[x];
+                const uint64_t hw = S.pH[x];
+                const int32_t H = hp_val(hw);
                 int64_t ck[4], ckr[4], cs[4];
-                hp_children(ix, k, kr, sz, ck, ckr, cs);
+                hp_children(ix, k, hp_rep(hw), sz, ck, ckr, cs);
                 ++n_ext;
                 n_units += ix.units(k, k + sz);
                 bool bad = false;
 #pragma unroll 1
                 for (int b = 0; b < 4; ++b) {
                     const int64_t sb = hp_pick(cs, b);
-                    if (!bad && sb > 0) {
-                        const int32_t j = hw_upsert(S, cap, hp_pick(ck, b), hp_pick(ckr, b), sb);
+                    const int32_t v = H + ((uint32_t)(b + 1) == a ? p.match : -p.mismatch);
+                    if (!bad && sb > 0 && v > 0) {
+                        const int32_t j = hw_upsert(S, cap, hp_pick(ck, b), sb);
                         if (j < 0)
                             bad = true;
                         else
-                            atomicMax(&S.cH[j], H + ((uint32_t)(b + 1) == a ? p.match : -p.mismatch));
+                            atomicMax((unsigned long long *)&S.cH[j], (unsigned long long)hp_pack(v, hp_pick(ckr, b)));
                     }
                 }
-                if (!bad) {
-                    const int32_t j = hw_upsert(S, cap, k, kr, sz);
+                // the insertion: the same node and string
+                const uint64_t iw = bad ? 0 : hp_gap(hw, S.pE[x], p);
+                if (iw) {
+                    const int32_t j = hw_upsert(S, cap, k, sz);
                     if (j < 0) {
                         bad = true;
                     } else {
-                        const int32_t e = hp_max(H - p.gap_open, E) - p.gap_ext;
-                        atomicMax(&S.cE[j], e);
-                        atomicMax(&S.cH[j], e);
+                        atomicMax((unsigned long long *)&S.cE[j], (unsigned long long)iw);
+                        atomicMax((unsigned long long *)&S.cH[j], (unsigned long long)iw);
                     }
                 }
                 if (bad) S.flag = 1;
@@ -644,12 +692,14 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
                 for (int32_t x = hl; x < n0; x += HW) {
                     if (!S.cd[x]) continue;
                     S.cd[x] = 0;
-                    const int32_t H = S.cH[x];
-                    const int32_t f = hp_max(H - p.gap_open, S.cF[x]) - p.gap_ext;
-                    if (f <= 0 || f < tau || H <= 0) continue;
+                    const uint64_t hw = S.cH[x];
+                    if (hp_val(hw) <= 0) continue;
+                    const uint64_t fw = hp_gap(hw, S.cF[x], p);
+                    const int32_t f = hp_val(fw);
+                    if (f <= 0 || f < tau) continue;
                     const int64_t k = S.ck[x], sz = S.cs[x];
                     int64_t ck[4], ckr[4], cs[4];
-                    hp_children(ix, k, S.ckr[x], sz, ck, ckr, cs);
+                    hp_children(ix, k, hp_rep(fw), sz, ck, ckr, cs);
                     ++n_ext;
                     n_units += ix.units(k, k + sz);
                     bool bad = false;
@@ -657,11 +707,14 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
                     for (int b = 0; b < 4; ++b) {
                         const int64_t sb = hp_pick(cs, b);
                         if (!bad && sb > 0) {
-                            const int32_t j = hw_upsert(S, cap, hp_pick(ck, b), hp_pick(ckr, b), sb);
+                            const int32_t j = hw_upsert(S, cap, hp_pick(ck, b), sb);
+                            const unsigned long long w = j < 0 ? 0ull : hp_pack(f, hp_pick(ckr, b));
                             if (j < 0) {
                                 bad = true;
-                            } else if (atomicMax(&S.cF[j], f) < f) {
-                                const int32_t old = atomicMax(&S.cH[j], f);
+                            } else if (atomicMax((unsigned long long *)&S.cF[j], w) < w) {
+                                // every deletion offer goes to H as well, so
+                                // H only changes when F does
+                                const int32_t old = hp_val(atomicMax((unsigned long long *)&S.cH[j], w));
                                 // a deletion never tops its parent, so f < mx
                                 if (hm && old < f) {
                                     if (old > 0 && mx - old < HW) atomicSub(&S.hist[mx - old], 1);
@@ -718,7 +771,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         // cells
         if (rank_ties) {
             for (int32_t x = hl; x < nC; x += HW) {
-                if (S.cH[x] == tau) {
+                if (hp_val(S.cH[x]) == tau) {
                     const int32_t d = atomicAdd(&S.tcount, 1);
                     if (d < PCAP) {
                         S.pk[d] = S.ck[x];
@@ -731,14 +784,14 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         if (rank_ties) {
             const int32_t T = S.tcount;
             for (int32_t x = hl; x < nC; x += HW) {
-                if (S.cH[x] == tau) {
+                if (hp_val(S.cH[x]) == tau) {
                     const int64_t k = S.ck[x], sz = S.cs[x];
                     int32_t rank = 0;
                     if (T <= PCAP) {
                         for (int32_t y = 0; y < T; ++y) rank += S.pk[y] < k || (S.pk[y] == k && S.ps[y] < sz);
                     } else {
                         for (int32_t y = 0; y < nC; ++y)
-                            rank += S.cH[y] == tau && (S.ck[y] < k || (S.ck[y] == k && S.cs[y] < sz));
+                            rank += hp_val(S.cH[y]) == tau && (S.ck[y] < k || (S.ck[y] == k && S.cs[y] < sz));
                     }
                     S.cd[x] = rank < r;
                 }
@@ -747,15 +800,14 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
         __syncthreads();
         if (on) {
             for (int32_t x = hl; x < nC; x += HW) {
-                const int32_t H = S.cH[x];
+                const int32_t H = hp_val(S.cH[x]);
                 bool keep = H > 0;
                 if (keep && cut) keep = H > tau || (H == tau && (!rank_ties || S.cd[x]));
                 if (keep) {
                     const int32_t d = atomicAdd(&S.nP, 1);
                     S.pk[d] = S.ck[x];
-                    S.pkr[d] = S.ckr[x];
                     S.ps[d] = S.cs[x];
-                    S.pH[d] = H;
+                    S.pH[d] = S.cH[x];
                     S.pE[d] = S.cE[x];
                 }
             }
@@ -778,25 +830,25 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
     // the cells of the query's start, ordered, then the redundancy filter
     const int32_t n = L == 0 ? 0 : S.nP;  // the root alone is not a result
     for (int32_t x = 1; x < n; ++x) {
-        const int64_t k = S.pk[x], kr = S.pkr[x], sz = S.ps[x];
-        const int32_t H = S.pH[x];
+        const int64_t k = S.pk[x], sz = S.ps[x];
+        const uint64_t hw = S.pH[x];
+        const int32_t H = hp_val(hw);
         int32_t y = x - 1;
-        while (y >= 0 && (S.pH[y] < H || (S.pH[y] == H && (S.pk[y] > k || (S.pk[y] == k && S.ps[y] > sz))))) {
+        while (y >= 0 && (hp_val(S.pH[y]) < H ||
+                          (hp_val(S.pH[y]) == H && (S.pk[y] > k || (S.pk[y] == k && S.ps[y] > sz))))) {
             S.pk[y + 1] = S.pk[y];
-            S.pkr[y + 1] = S.pkr[y];
             S.ps[y + 1] = S.ps[y];
             S.pH[y + 1] = S.pH[y];
             --y;
         }
         S.pk[y + 1] = k;
-        S.pkr[y + 1] = kr;
         S.ps[y + 1] = sz;
-        S.pH[y + 1] = H;
+        S.pH[y + 1] = hw;
     }
     rb3_hapl_t *out = wout + qi * (int64_t)outcap;
     int32_t w = 0;
     for (int32_t x = 0; x < n; ++x) {
-        const int64_t k = S.pk[x], kr = S.pkr[x], sz = S.ps[x];
+        const int64_t k = S.pk[x], kr = hp_rep(S.pH[x]), sz = S.ps[x];
         bool inside = false;
         for (int32_t y = 0; y < w && !inside; ++y)
             inside = (k >= out[y].k && k + sz <= out[y].k + out[y].s) ||
@@ -806,7 +858,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
             o.k = k;
             o.krc = kr;
             o.s = sz;
-            o.score = S.pH[x];
+            o.score = hp_val(S.pH[x]);
             o.qid = (int32_t)(qbase + qi);
             out[w++] = o;
         }
@@ -827,9 +879,9 @@ __global__ void k_hapl_gather(const HpCell *__restrict__ cells, int64_t nq, int3
     for (int32_t x = 0; x < c; ++x) {
         rb3_hapl_t r;
         r.k = A[x].k;
-        r.krc = A[x].kr;
+        r.krc = hp_rep(A[x].hw);
         r.s = A[x].s;
-        r.score = A[x].H;
+        r.score = hp_val(A[x].hw);
         r.qid = (int32_t)(qbase + qi);
         out[off[qi] + x] = r;
     }

@@ -508,6 +508,10 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
 // extensions (rank-all pairs), index blocks they read, cells held summed
 // over the query positions, queries moved from LDS to device-memory tables.
 constexpr int64_t HAPL_SCRATCH = (int64_t)8 << 30;
+// A cell's scores travel packed with the reverse-complement start of their
+// representative string in the low HAPL_KRC_BITS bits: the index must hold
+// fewer than 2^HAPL_KRC_BITS symbols (and scores stay below 2^29).
+constexpr int HAPL_KRC_BITS = 35;
 struct RleView;
 int hapl_run(Ctx &c, const DevIndex &ix, const RleView *rle, const uint8_t *d_codes, const int64_t *qlens,
              int64_t nq, const rb3_hapl_opts &o, int64_t out_cap, rb3_hapl_t *d_out, int64_t *h_off,

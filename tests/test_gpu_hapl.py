@@ -81,6 +81,22 @@ def test_hapl_matches_oracle_banded(small, band, dev):
     assert st["extensions"] > 0
 
 
+@pytest.mark.parametrize("band", [12, 13, 32, 33])
+def test_hapl_kernel_boundaries(small, band):
+    # the LDS tables change at these bands: 12 is the last on 64 cells and
+    # 16 previous ones, 13 the first on 128 cells, 32 fills the 32 previous
+    # cells exactly, 33 the first on 256 cells (one query a wavefront);
+    # cheap gaps and mismatches fill the band at most positions
+    say(f"case: haplotype enumeration at band {band} (a boundary between LDS table sizes)")
+    w, idx, text, _ = small
+    qs = _reads(w, 60, 20, 90, sub=0.03, indel=0.005, stream=15000)
+    P = synth.pack(qs)
+    for scores in ((1, 4, 6, 1), (2, 1, 1, 1)):
+        m, x, o, e = scores
+        recs, off = idx.hapl(P.data, P.lens, match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
+        _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
+
+
 @pytest.mark.parametrize("dev", [False, True])
 def test_hapl_matches_oracle_unbanded(small, dev):
     say(f"case: haplotype enumeration without a band, reads 4-14 bp, device tables {dev}")
