@@ -249,7 +249,8 @@ typedef struct rb3_hapl_t {
  * results of the queries in flight (32 bytes each, at most the band's
  * number a query), and, for queries kept in device memory, about
  * 2 * max_cells * 48 + 12 * max_cells bytes each; queries run in chunks
- * of at most 8 GiB.
+ * whose device-memory tables would take at most 16 GiB (allocated only for
+ * the queries moved there).
  */
 int rb3_hapl(const rb3_index *idx, const rb3_hapl_opts *o, const uint8_t *q, const int64_t *qlens, int64_t n_q,
              int32_t mem, rb3_hapl_t *out, int64_t out_cap, int64_t *out_off);

@@ -24,6 +24,7 @@
 #include "views.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 namespace rb3 {
@@ -417,11 +418,11 @@ __global__ __launch_bounds__(64) void k_hapl(V ix, const uint8_t *__restrict__ Q
 // to device memory. Occupancy is set by LDS (allocated in 512-byte
 // granules) and registers:
 //   bands up to 12: two queries a wavefront, 64 cells and 16 previous ones
-//     each (8.4 KB a wavefront; registers for four wavefronts a SIMD, so
+//     each (7.8 KB a wavefront; registers for four wavefronts a SIMD, so
 //     32 queries a CU);
-//   bands up to 32: two queries, 128 cells and 32 previous ones (14.5 KB:
-//     10 wavefronts, 20 queries a CU);
-//   else one query, 256 and 256 (20.5 KB: 7 queries a CU).
+//   bands up to 32: two queries, 128 cells and 32 previous ones (13.3 KB:
+//     11 wavefronts, 22 queries a CU);
+//   else one query, 256 and 256 (21.0 KB: 7 queries a CU).
 constexpr int HW_CAP_PAIR = 64;
 constexpr int HW_PAIR_BAND = 12;
 constexpr int HW_PAIR_PREV = 16;
@@ -434,17 +435,23 @@ static_assert(HW_PAIR_PREV >= HW_PAIR_BAND, "the previous cells hold the band");
 // cell, four for the 64-cell tables, whose occupancy registers bound (the
 // shorter probe chains are free there; eight cost more to clear at every
 // position than they save).
+// A cell's E comes from one previous cell only (the one of its node), so E
+// is kept per previous cell (eW) and a cell names that cell (ci, index + 1;
+// 0: no insertion reached it) instead of an E word per cell.
 template <int CAP, int PCAP, int HB>
 struct HwLds {
     static constexpr int HS = (CAP <= HW_CAP_PAIR ? 4 : 2) * CAP;
+    using PIdx = typename std::conditional<(PCAP < 255), uint8_t, uint16_t>::type;
     int64_t ck[CAP], cs[CAP];  // current position's cells
-    uint64_t cH[CAP], cE[CAP], cF[CAP];  // packed scores with representatives
+    uint64_t cH[CAP], cF[CAP];  // packed scores with representatives
     int32_t slot[HS];  // cell index + 1, 0 = empty
     int64_t pk[PCAP], ps[PCAP];  // previous position's cells (at most the band)
     uint64_t pH[PCAP], pE[PCAP];
+    uint64_t eW[PCAP];  // packed E each previous cell passes to its node's cell
     int32_t hist[HB];  // positive scores mx - i, for the band's threshold
     int32_t nC, nP, flag, changed, tcount;
     uint8_t cd[CAP];  // dirty (deletion step), then kept among the tied cells
+    PIdx ci[CAP];
 };
 
 // Reductions over the HW lanes of one query (HW = 64 or 32).
@@ -489,9 +496,9 @@ __device__ int32_t hw_upsert(LDS &S, int32_t cap, int64_t k, int64_t s) {
                 S.ck[j] = k;
                 S.cs[j] = s;
                 S.cH[j] = 0;
-                S.cE[j] = 0;
                 S.cF[j] = 0;
                 S.cd[j] = 1;
+                S.ci[j] = 0;
             }
             int32_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(&S.slot[h], &expected, j + 1, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
@@ -656,7 +663,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
                     if (j < 0) {
                         bad = true;
                     } else {
-                        atomicMax((unsigned long long *)&S.cE[j], (unsigned long long)iw);
+                        // the only insertion into this node: plain stores
+                        S.eW[x] = iw;
+                        S.ci[j] = (typename LDS::PIdx)(x + 1);
                         atomicMax((unsigned long long *)&S.cH[j], (unsigned long long)iw);
                     }
                 }
@@ -808,7 +817,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_
                     S.pk[d] = S.ck[x];
                     S.ps[d] = S.cs[x];
                     S.pH[d] = S.cH[x];
-                    S.pE[d] = S.cE[x];
+                    S.pE[d] = S.ci[x] ? S.eW[S.ci[x] - 1] : 0;
                 }
             }
         }

@@ -507,7 +507,7 @@ int smem_run(Ctx &c, const DevIndex &ix, const uint8_t *d_q, const int64_t *qlen
 // position gives RB3_ELIMIT with its index in *h_bad. h_stats[0..3]:
 // extensions (rank-all pairs), index blocks they read, cells held summed
 // over the query positions, queries moved from LDS to device-memory tables.
-constexpr int64_t HAPL_SCRATCH = (int64_t)8 << 30;
+constexpr int64_t HAPL_SCRATCH = (int64_t)16 << 30;
 // A cell's scores travel packed with the reverse-complement start of their
 // representative string in the low HAPL_KRC_BITS bits: the index must hold
 // fewer than 2^HAPL_KRC_BITS symbols (and scores stay below 2^29).
