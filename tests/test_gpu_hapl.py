@@ -171,11 +171,12 @@ def test_hapl_band_tie_break_worked_case(band):
     idx.close()
 
 
-@pytest.mark.parametrize("band", [10, 25])
+@pytest.mark.parametrize("band", [10, 25, 40, 0])
 def test_hapl_run_length_index_and_output_retry(small, band):
     say(f"case: haplotype enumeration on the run-length index at band {band}; output sized by a retry")
     w, idx, text, _ = small
-    qs = _reads(w, 60, 20, 80, stream=12000)
+    # without a band, short reads (every cell is kept)
+    qs = _reads(w, 60, 20, 80, stream=12000) if band else _reads(w, 40, 4, 14, stream=12500)
     P = synth.pack(qs)
     r = rb3.rb3_rle_build(idx, 0)
     recs, off = r.hapl(P.data, P.lens, cap=1, band=band)
