@@ -97,14 +97,18 @@ def test_hapl_kernel_boundaries(small, band):
         _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
 
 
+@pytest.mark.parametrize("scores", [(1, 4, 6, 1), (2, 1, 1, 1)])
 @pytest.mark.parametrize("dev", [False, True])
-def test_hapl_matches_oracle_unbanded(small, dev):
-    say(f"case: haplotype enumeration without a band, reads 4-14 bp, device tables {dev}")
+def test_hapl_matches_oracle_unbanded(small, dev, scores):
+    m, x, o, e = scores
+    say(f"case: haplotype enumeration without a band, reads 4-14 bp, device tables {dev}, scores {scores}")
     w, idx, text, _ = small
-    qs = _reads(w, 80, 4, 14, stream=5000)
+    # cheap gaps keep many more cells without a band: fewer reads for the oracle
+    qs = _reads(w, 80 if scores == (1, 4, 6, 1) else 30, 4, 14, stream=5000)
     P = synth.pack(qs)
-    recs, off = idx.hapl(P.data, P.lens, band=0, max_cells=65535, device_tables=dev)
-    _compare(text, qs, recs, off, band=0)
+    recs, off = idx.hapl(P.data, P.lens, match=m, mismatch=x, gap_open=o, gap_ext=e, band=0, max_cells=65535,
+                         device_tables=dev)
+    _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=0)
 
 
 def test_hapl_queries_moved_to_device_tables(small):
