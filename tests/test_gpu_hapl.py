@@ -97,6 +97,18 @@ def test_hapl_kernel_boundaries(small, band):
         _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
 
 
+def test_hapl_repeatable(small):
+    # lanes race to create cells; no result may depend on which one wins
+    say("case: haplotype enumeration twice on the same reads (band 25, cheap gaps): equal records")
+    w, idx, _, _ = small
+    qs = _reads(w, 200, 20, 90, sub=0.03, indel=0.005, stream=16000)
+    P = synth.pack(qs)
+    kw = dict(match=2, mismatch=1, gap_open=1, gap_ext=1, band=25)
+    r1, o1 = idx.hapl(P.data, P.lens, **kw)
+    r2, o2 = idx.hapl(P.data, P.lens, **kw)
+    assert np.array_equal(o1, o2) and np.array_equal(r1, r2)
+
+
 @pytest.mark.parametrize("scores", [(1, 4, 6, 1), (2, 1, 1, 1)])
 @pytest.mark.parametrize("dev", [False, True])
 def test_hapl_matches_oracle_unbanded(small, dev, scores):
