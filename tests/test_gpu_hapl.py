@@ -97,6 +97,24 @@ def test_hapl_kernel_boundaries(small, band):
         _compare(text, qs, recs, off, match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
 
 
+def test_hapl_random_configurations(small):
+    # seeded draws of scores (match 1-3, mismatch 0-4, gap open 0-6, gap
+    # extension 1-3), bands across the LDS table sizes and both kernels
+    say("case: haplotype enumeration, 16 seeded configurations of scores, band and tables")
+    w, idx, text, _ = small
+    g = np.random.default_rng(2024)
+    for t in range(16):
+        m, x, o, e = int(g.integers(1, 4)), int(g.integers(0, 5)), int(g.integers(0, 7)), int(g.integers(1, 4))
+        band = int(g.choice([0, 1, 3, 7, 10, 12, 13, 16, 25, 31, 32, 33, 40]))
+        dev = bool(g.integers(0, 2))
+        qs = _reads(w, 16, 6, 14 if band == 0 else 70, sub=0.03, indel=0.005, stream=21000 + 100 * t)
+        P = synth.pack(qs)
+        kw = dict(match=m, mismatch=x, gap_open=o, gap_ext=e, band=band)
+        say(f"  {kw} device tables {dev}")
+        recs, off = idx.hapl(P.data, P.lens, device_tables=dev, max_cells=65535, **kw)
+        _compare(text, qs, recs, off, **kw)
+
+
 def test_hapl_repeatable(small):
     # lanes race to create cells; no result may depend on which one wins
     say("case: haplotype enumeration twice on the same reads (band 25, cheap gaps): equal records")
