@@ -292,6 +292,26 @@ def test_hapl_bench_shape_properties():
     idx.close()
 
 
+@pytest.mark.parametrize("scores", [(1, 4, 6, 1), (2, 1, 1, 1)])
+@pytest.mark.parametrize("band", [10, 25])
+def test_hapl_lds_and_device_tables_agree_at_scale(band, scores):
+    # the two kernels take the same steps independently (wavefronts with LDS
+    # tables, one thread per query with device-memory tables): every record
+    # equal on 3,000 reads of 125 bp against 32 haplotypes x 200 kb
+    m, x, o, e = scores
+    say(f"case: haplotype enumeration, LDS against device-memory tables, 3,000 reads of 125 bp, band {band}, "
+        f"scores {scores}")
+    w = synth.config_pangenome(genome_len=200_000, n_b1=32, n_new=4)
+    idx = rb3.rb3_build(w.b1.data, w.b1.lens)
+    qs = _reads(w, 3000, 125, 125, sub=0.01, indel=0.001, stream=40000)
+    P = synth.pack(qs)
+    kw = dict(match=m, mismatch=x, gap_open=o, gap_ext=e, band=band, max_cells=4096)
+    a, ao = idx.hapl(P.data, P.lens, **kw)
+    b, bo = idx.hapl(P.data, P.lens, device_tables=True, **kw)
+    assert np.array_equal(ao, bo) and np.array_equal(a, b)
+    idx.close()
+
+
 @pytest.mark.parametrize("band", [10, 25])
 def test_hapl_125bp_sample_against_oracle(band):
     say(f"case: haplotype enumeration of 125 bp reads on 32 haplotypes x 30 kb, band {band}: a sample against the "
